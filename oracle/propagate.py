@@ -1,0 +1,151 @@
+"""Layer-by-layer range analysis (AA) and uncertainty propagation (UP) of a
+box through a ReLU MLP, float64, by explicit coefficient tracking.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
+
+A form is a centre vector x0 [n] and a coefficient matrix F [n, N] whose
+column i multiplies symbol i (Eq. 1 for AA, eps_i in [-1, 1]; Eq. 6 for UP,
+Z_i zero-mean, unit-variance, independent).
+
+* Input form of a box with centre c and half-widths h (Sec. III-B for AA;
+  Sec. IV-C and Alg. 1 for UP): x0 = c, F = diag(h) for AA and
+  F = diag(h / sqrt 3) for UP (a uniform variable on [-h, h] has std h/sqrt 3).
+* Linear layer y = W x + b (Eq. 3 / Eq. 8, exact): x0 <- W x0 + b, F <- W F.
+* ReLU, per neuron j (Eq. 4 / Eq. 9): take (alpha_j, beta_j, gamma_j) from the
+  rule, then x0_j <- alpha_j x0_j + beta_j, row j of F <- alpha_j * row j, and
+  append one new symbol column whose only nonzero entry is gamma_j in row j.
+  The rule's input is (x0_j, r_j = sum_i |F_ji|) for AA (Eq. 2 hard range)
+  and (mu_j = x0_j, sigma_j = sqrt(sum_i F_ji^2)) for UP (Eq. 7, CLT).
+* Output read-off: AA range [x0 - r, x0 + r] (Eq. 2); UP N(x0, sum F^2)
+  (Eq. 7), whose soft bound is [mu - t sigma, mu + t sigma] (Alg. 1).
+
+Both return (centre, spread): AA (x0, r), UP (mu, sigma), so that the bound
+is centre -/+ k * spread with k = 1 for AA and k = t for UP.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from .mlp import as_f64_layers
+from .rules import relu_aa_rule, relu_up_rule
+
+AA = "aa"
+UP = "up"
+RAUA = "raua"  # AA propagation, uniform-assumption read-off (Sec. IV-A)
+
+
+def _chunk_for(layers, budget_bytes=2.0e8):
+    n_max = max(W.shape[0] for W, _ in layers)
+    d_max = 3 + sum(W.shape[0] for W, _ in layers[:-1])
+    return max(1, int(budget_bytes // (8 * n_max * d_max)))
+
+
+def _track(layers, centres, halves, method, keep_hidden=False):
+    """Coefficient tracking for one chunk of boxes; returns (centre, spread)
+    and optionally per-hidden-layer (pre-activation centre, row statistic)."""
+    C = centres.shape[0]
+    s = 1.0 if method in (AA, RAUA) else 1.0 / np.sqrt(3.0)
+    x0 = centres.copy()
+    F = np.zeros((C, 3, 3))
+    for i in range(3):
+        F[:, i, i] = halves[:, i] * s
+    hidden = []
+    last = len(layers) - 1
+    for li, (W, b) in enumerate(layers):
+        x0 = x0 @ W.T + b
+        F = np.matmul(W, F)
+        if li == last:
+            break
+        n = W.shape[0]
+        if method == UP:
+            stat = np.sqrt(np.einsum("cnd,cnd->cn", F, F))
+            alpha, beta, gamma2 = relu_up_rule(x0, stat)
+            gamma = np.sqrt(gamma2)
+        else:
+            stat = np.abs(F).sum(axis=2)
+            alpha, beta, gamma = relu_aa_rule(x0, stat)
+        if keep_hidden:
+            hidden.append((x0.copy(), stat.copy()))
+        x0 = alpha * x0 + beta
+        F = alpha[:, :, None] * F
+        G = np.zeros((C, n, n))
+        G[:, np.arange(n), np.arange(n)] = gamma
+        F = np.concatenate([F, G], axis=2)
+    row = F[:, 0, :]
+    if method == UP:
+        spread = np.sqrt(np.einsum("cd,cd->c", row, row))
+    elif method == AA:
+        spread = np.abs(row).sum(axis=1)
+    else:  # RA-UA: uniform variables on [-|x_i|, |x_i|] have variance x_i^2/3
+        spread = np.sqrt(np.einsum("cd,cd->c", row, row) / 3.0)
+    return x0[:, 0], spread, hidden
+
+
+def propagate(layers, centres, halves, method: str, chunk: int | None = None):
+    """Propagate boxes through the MLP.
+
+    centres, halves: [C, 3] (box centre and per-axis half-widths).
+    method: ``AA`` (range analysis), ``UP`` (uncertainty propagation) or
+    ``RAUA`` (range analysis with the uniform assumption read-off).
+    Returns float64 (centre [C], spread [C]).
+    """
+    layers = as_f64_layers(layers)
+    centres = np.asarray(centres, dtype=np.float64).reshape(-1, 3)
+    halves = np.asarray(halves, dtype=np.float64).reshape(-1, 3)
+    chunk = chunk or _chunk_for(layers)
+    cs, ss = [], []
+    for a in range(0, centres.shape[0], chunk):
+        c, s, _ = _track(layers, centres[a : a + chunk], halves[a : a + chunk], method)
+        cs.append(c)
+        ss.append(s)
+    if not cs:
+        return np.zeros(0), np.zeros(0)
+    return np.concatenate(cs), np.concatenate(ss)
+
+
+def propagate_hidden(layers, centres, halves, method: str):
+    """As ``propagate`` but also returns, per hidden layer, the pre-activation
+    centre [C, n] and row statistic [C, n] (sigma for UP, r for AA)."""
+    layers = as_f64_layers(layers)
+    centres = np.asarray(centres, dtype=np.float64).reshape(-1, 3)
+    halves = np.asarray(halves, dtype=np.float64).reshape(-1, 3)
+    return _track(layers, centres, halves, method, keep_hidden=True)
+
+
+def propagate_up_covariance(layers, centres, halves):
+    """UP written with the covariance of the symbols instead of the symbols.
+
+    Since the symbols are independent with unit variance, only
+    Sigma = F F^T enters sigma_j^2 = Sigma_jj (Eq. 7).  The rules become
+    Sigma <- W Sigma W^T (linear) and
+    Sigma <- D_alpha Sigma D_alpha + diag(gamma^2) (ReLU, Eq. 9).
+    Exactly equal to coefficient tracking; used as an internal cross-check.
+    """
+    layers = as_f64_layers(layers)
+    centres = np.asarray(centres, dtype=np.float64).reshape(-1, 3)
+    halves = np.asarray(halves, dtype=np.float64).reshape(-1, 3)
+    C = centres.shape[0]
+    x0 = centres.copy()
+    S = np.zeros((C, 3, 3))
+    for i in range(3):
+        S[:, i, i] = halves[:, i] ** 2 / 3.0
+    last = len(layers) - 1
+    for li, (W, b) in enumerate(layers):
+        x0 = x0 @ W.T + b
+        S = np.matmul(np.matmul(W, S), W.T)
+        if li == last:
+            break
+        n = W.shape[0]
+        sigma = np.sqrt(np.maximum(S[:, np.arange(n), np.arange(n)], 0.0))
+        alpha, beta, gamma2 = relu_up_rule(x0, sigma)
+        x0 = alpha * x0 + beta
+        S = alpha[:, :, None] * S * alpha[:, None, :]
+        S[:, np.arange(n), np.arange(n)] += gamma2
+    return x0[:, 0], np.sqrt(np.maximum(S[:, 0, 0], 0.0))
+
+
+def bounds(centre, spread, k):
+    """Bound read-off centre -/+ k * spread (AA: k = 1, Eq. 2; UP: k = t,
+    Alg. 1 soft bound)."""
+    return centre - k * spread, centre + k * spread
