@@ -1,0 +1,211 @@
+/*
+ * isx.h -- C ABI of libisx: hierarchical iso-surface extraction on ReLU
+ * coordinate MLPs (implicit neural representations) for AMD MI355X (gfx950).
+ *
+ * Method: Li & Shen, "Improving Efficiency of Iso-Surface Extraction on
+ * Implicit Neural Representations Using Uncertainty Propagation"
+ * (arXiv 2402.13861).
+ *
+ * The library propagates axis-aligned boxes through an MLP with either
+ *   - affine arithmetic (range analysis; Sec. III-A/B, Eq. 1-4), giving a hard
+ *     bound [x0 - r, x0 + r], or
+ *   - uncertainty propagation with probabilistic affine forms (Sec. IV-B/C,
+ *     Eq. 6-10, App. D ReLU row), giving a Gaussian N(mu, sigma^2) whose soft
+ *     bound is [mu - t sigma, mu + t sigma],
+ * classifies cells against iso-values (Alg. 1), searches an octree top-down
+ * keeping only active cells (Alg. 1 in 8-way form), evaluates the MLP at the
+ * corners of the active leaves and runs marching cubes there (Sec. IV-D).
+ *
+ * Conventions for every function:
+ *   - Returns ISX_OK (0) or a negative isx_status; never throws or aborts.
+ *     A human-readable message for the last failure on a context is returned
+ *     by isx_last_error().
+ *   - "d_" pointers are DEVICE pointers (e.g. torch tensor data_ptr()) owned
+ *     by the caller; "h_" pointers are host pointers owned by the caller.
+ *     The library never frees caller memory.
+ *   - Work is enqueued on the context's HIP stream.  Functions documented as
+ *     "asynchronous" return before the GPU work completes; the others
+ *     synchronise the stream before returning.
+ *   - Float layouts are C-contiguous, float32 unless stated otherwise.
+ *   - A context is not thread-safe; use one context per host thread.
+ */
+#ifndef ISX_H
+#define ISX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ISX_OK = 0,
+  ISX_EINVAL = -1,       /* bad argument (null pointer, unknown enum, k < 0 ...) */
+  ISX_ESHAPE = -2,       /* unsupported or inconsistent layer widths */
+  ISX_ENOMEM = -3,       /* device allocation failed */
+  ISX_ECAPACITY = -4,    /* a result exceeds a caller-set capacity (never truncated silently) */
+  ISX_EHIP = -5,         /* a HIP runtime call or kernel launch failed */
+  ISX_ENAN = -6,         /* NaN or Inf in weights, domain or iso-values */
+  ISX_EUNSUPPORTED = -7  /* valid request that this build does not implement */
+} isx_status;
+
+/* Range analysis by affine arithmetic ("RA-Full", Sec. III) or uncertainty
+ * propagation with probabilistic affine forms ("UP", Sec. IV-B). */
+typedef enum { ISX_AA = 0, ISX_UP = 1 } isx_method;
+
+/* Arithmetic of the propagation and evaluation kernels.
+ *   ISX_FP32: float32 everywhere; hidden-layer products on FP32 MFMA.
+ *   ISX_BF16: layer products with bfloat16 operands on MFMA, float32
+ *             accumulation, statistics and epilogues (centre column float32).
+ *   ISX_FP64: float64 everywhere (reference / re-check path). */
+typedef enum { ISX_FP32 = 0, ISX_BF16 = 1, ISX_FP64 = 2 } isx_precision;
+
+typedef struct isx_ctx isx_ctx;
+typedef struct isx_mesh isx_mesh;
+
+#define ISX_MAX_LINEAR 16 /* maximum number of linear layers */
+#define ISX_MAX_WIDTH 1024
+#define ISX_MAX_ISO 32    /* iso-values per MLP; cell masks are uint32 */
+
+/* Create a context on HIP device `device`, enqueuing on `hip_stream`
+ * (a hipStream_t; NULL = the device's null stream).  *out receives the
+ * context.  Errors: ISX_EINVAL (bad device / out == NULL), ISX_EHIP. */
+isx_status isx_create(int device, void* hip_stream, isx_ctx** out);
+
+/* Destroy a context and free all library-owned device memory of it
+ * (weights, work buffers).  Meshes must be freed separately. */
+isx_status isx_destroy(isx_ctx* ctx);
+
+/* Message of the last failed call on ctx ("" if none); owned by ctx, valid
+ * until the next call on ctx.  ctx == NULL gives the last create() error. */
+const char* isx_last_error(const isx_ctx* ctx);
+
+/* Load an MLP f: R^3 -> R (Sec. III-B).  n_linear linear layers,
+ * widths[0] = 3, widths[n_linear] = 1, 1 <= hidden widths <= ISX_MAX_WIDTH,
+ * 2 <= n_linear <= ISX_MAX_LINEAR.  h_W[l] is row-major
+ * [widths[l+1]][widths[l]] float32 and h_b[l] is [widths[l+1]], both HOST
+ * pointers; a ReLU follows every layer but the last.  Weights are copied to
+ * library-owned device memory (float32, float64 and bfloat16 copies, hidden
+ * widths zero-padded to a multiple of 32, which leaves every result
+ * unchanged), so the caller may free its copy on return.
+ * The domain defaults to [-1,1]^3 and the iso-value list to empty.
+ * Errors: ISX_EINVAL, ISX_ESHAPE, ISX_ENAN (non-finite weight), ISX_ENOMEM. */
+isx_status isx_load_mlp(isx_ctx* ctx, int32_t n_linear, const int32_t* widths,
+                        const float* const* h_W, const float* const* h_b, int32_t* mlp_id);
+
+/* Release an MLP's device memory. */
+isx_status isx_unload_mlp(isx_ctx* ctx, int32_t mlp_id);
+
+/* Axis-aligned domain [lo, hi] of the octree root (Alg. 1 inputs x_l, x_u).
+ * Errors: ISX_EINVAL (hi <= lo on an axis), ISX_ENAN. */
+isx_status isx_set_domain(isx_ctx* ctx, int32_t mlp_id, const float h_lo[3], const float h_hi[3]);
+
+/* Iso-values c_j (Alg. 1 input c), 0 <= n_iso <= ISX_MAX_ISO, host array.
+ * Bit j of every cell mask refers to h_iso[j].  Errors: ISX_EINVAL, ISX_ENAN. */
+isx_status isx_set_isovalues(isx_ctx* ctx, int32_t mlp_id, int32_t n_iso, const float* h_iso);
+
+/* Propagate n_cells boxes through the MLP (Alg. 1 lines 1-5 without the
+ * test).  d_centres [n][3] and d_halves [n][3] (per-axis half-widths, > 0)
+ * are device arrays.  d_out [n][2] receives (centre, spread) as float32:
+ * (x0, r) for ISX_AA, whose range is [x0 - r, x0 + r] (Eq. 2), and
+ * (mu, sigma) for ISX_UP (Eq. 7).  With ISX_FP64 the same pair is also
+ * written in float64 to d_out64 [n][2] if it is not NULL (it must be NULL
+ * for the other precisions).  Asynchronous.  n_cells == 0 is a no-op.
+ * Errors: ISX_EINVAL, ISX_ENOMEM, ISX_EHIP. */
+isx_status isx_propagate(isx_ctx* ctx, int32_t mlp_id, isx_method method, isx_precision precision,
+                         int64_t n_cells, const float* d_centres, const float* d_halves, float* d_out,
+                         double* d_out64);
+
+/* Classify and compact (Alg. 1 lines 6-7): cell i keeps iso bit j iff
+ * centre - k*spread <= c_j <= centre + k*spread (closed interval) and bit j is
+ * set in d_parent_mask[i] (NULL = all bits set); k is the paper's t for UP and
+ * must be 1 for the AA hard range.  The indices i of cells with a nonzero
+ * mask are written in increasing order to d_active_idx, their masks to
+ * d_active_mask, and the count to *d_n_active (device int64).  d_active_idx and
+ * d_active_mask must hold n_cells entries.  Asynchronous.
+ * Errors: ISX_EINVAL, ISX_EHIP. */
+isx_status isx_classify_compact(isx_ctx* ctx, int32_t mlp_id, float k, int64_t n_cells, const float* d_out,
+                                const uint32_t* d_parent_mask, uint32_t* d_active_idx,
+                                uint32_t* d_active_mask, int64_t* d_n_active);
+
+/* Plain MLP evaluation f(x) at n points (Sec. III-B; the reconstruction step
+ * of Sec. IV-D).  d_points [n][3], d_values [n], float32 device arrays;
+ * ISX_FP64 computes in float64 and rounds the result.  Asynchronous. */
+isx_status isx_eval_points(isx_ctx* ctx, int32_t mlp_id, isx_precision precision, int64_t n,
+                           const float* d_points, float* d_values);
+
+/* Parameters of a full extraction. */
+typedef struct {
+  isx_method method;       /* ISX_UP (soft bound) or ISX_AA (hard bound) */
+  isx_precision precision; /* arithmetic of propagation and corner evaluation */
+  float k;                 /* t of Alg. 1 for UP (ignored for AA, which uses 1) */
+  int32_t max_depth;       /* octree depth D: leaves are the (2^D)^3 grid cells, D <= 10 */
+  float fp64_band;         /* > 0: cells whose bound endpoint lies within
+                              fp64_band of an iso-value are re-propagated in
+                              float64 and that result decides (not with ISX_FP64) */
+  int64_t max_cells;       /* capacity of one level (0 = library default); a
+                              level above it fails with ISX_ECAPACITY */
+  int64_t chunk_cells;     /* cells propagated per batch (0 = automatic) */
+} isx_params;
+
+/* Full extraction (Alg. 1 followed by corner evaluation and marching cubes)
+ * of the MLP's iso-surfaces at all of its iso-values, from the root domain
+ * to depth params->max_depth.  *out receives a library-owned mesh.
+ * Synchronises the stream.  Errors: ISX_EINVAL, ISX_ECAPACITY, ISX_ENOMEM,
+ * ISX_EHIP. */
+isx_status isx_extract(isx_ctx* ctx, int32_t mlp_id, const isx_params* params, isx_mesh** out);
+
+/* Sizes of a mesh: triangles, active leaves, distinct leaf corners, and the
+ * number of octree levels recorded (max_depth + 1). */
+isx_status isx_mesh_info(const isx_mesh* mesh, int64_t* n_tris, int64_t* n_leaves, int64_t* n_corners,
+                         int32_t* n_levels);
+
+/* Per-level counts: cells propagated at that level and cells kept active
+ * (mask != 0), and the number of cells re-checked in float64. */
+isx_status isx_mesh_level(const isx_mesh* mesh, int32_t level, int64_t* n_cells, int64_t* n_active,
+                          int64_t* n_rechecked);
+
+/* Phase times in milliseconds measured with HIP events on the context
+ * stream: active-cell prediction (all levels), corner evaluation, marching
+ * cubes, total. */
+isx_status isx_mesh_times(const isx_mesh* mesh, float* ms_acp, float* ms_inr, float* ms_mc, float* ms_total);
+
+/* Copy the triangles to host arrays (each may be NULL to skip it):
+ *   h_pos  [n_tris][3][3] float32 vertex positions;
+ *   h_keys [n_tris][3]    uint64 vertex keys: (grid-point linear index * 3 +
+ *          axis) of the grid edge the vertex lies on, grid of (2^D+1)^3
+ *          points, linear index i + (2^D+1) (j + (2^D+1) k);
+ *   h_iso  [n_tris]       int32 iso-value index.
+ * Triangles are ordered by (active leaf in Morton order, iso index, case
+ * table order).  Synchronous. */
+isx_status isx_mesh_copy_tris(const isx_mesh* mesh, float* h_pos, uint64_t* h_keys, int32_t* h_iso);
+
+/* Copy the active leaves: Morton ids (x bit lowest, 3*D bits) and iso masks. */
+isx_status isx_mesh_copy_leaves(const isx_mesh* mesh, uint32_t* h_ids, uint32_t* h_masks);
+
+/* Copy one level's propagated cells: Morton ids, (centre, spread) and masks
+ * after the test.  Only available if the level's data was kept
+ * (ISX_KEEP_LEVELS in isx_set_option), else ISX_EUNSUPPORTED. */
+isx_status isx_mesh_copy_level(const isx_mesh* mesh, int32_t level, uint32_t* h_ids, float* h_out,
+                               uint32_t* h_masks);
+
+isx_status isx_mesh_free(isx_mesh* mesh);
+
+/* Copy the library's marching-cubes case table: h_count[256] triangles per
+ * case (case bit i set iff corner i < iso-value; corners (0,0,0) (1,0,0)
+ * (1,1,0) (0,1,0) (0,0,1) (1,0,1) (1,1,1) (0,1,1)), h_edges[256][15] edge
+ * indices, 3 per triangle, -1 padded.  Host only; needs no device. */
+isx_status isx_mc_case_table(uint8_t* h_count, int8_t* h_edges);
+
+/* Context options. */
+typedef enum {
+  ISX_KEEP_LEVELS = 1,     /* value 1: meshes keep every level's cells (for testing) */
+  ISX_HIDDEN_KERNEL = 2    /* 0 = automatic, 1 = force the SIMT kernels, 2 = force MFMA */
+} isx_option;
+isx_status isx_set_option(isx_ctx* ctx, isx_option option, int64_t value);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ISX_H */

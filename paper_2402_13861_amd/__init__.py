@@ -1,0 +1,243 @@
+"""paper_2402_13861_amd -- hierarchical iso-surface extraction on ReLU INRs
+for AMD MI355X (gfx950).
+
+A thin Python binding over the C ABI of ``libisx.so`` (``include/isx.h``):
+arguments are marshalled here, every step of the computation runs in the
+library's HIP kernels.  Device buffers are torch CUDA (HIP) tensors; torch
+provides device memory and streams only.
+
+Method: Li & Shen, arXiv 2402.13861 -- range analysis by affine arithmetic
+(Sec. III) and uncertainty propagation (Sec. IV), hierarchical extraction
+(Alg. 1), marching cubes on active leaves (Sec. IV-D).
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _lib
+from ._lib import AA, BF16, FP32, FP64, HIDDEN_KERNEL, KEEP_LEVELS, UP
+
+__all__ = ["Context", "Mesh", "IsxError", "AA", "UP", "FP32", "BF16", "FP64", "KEEP_LEVELS", "HIDDEN_KERNEL",
+           "mc_case_table"]
+
+
+class IsxError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        super().__init__(f"{_lib.STATUS_NAMES.get(status, status)}: {message}")
+
+
+def _ptr(t) -> Optional[int]:
+    """Device pointer of a torch tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensors passed to libisx must be contiguous")
+    return t.data_ptr()
+
+
+def _check_dev(t, dtype, name, shape_tail=None):
+    import torch
+
+    if t is None:
+        return
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape_tail is not None and tuple(t.shape[1:]) != tuple(shape_tail):
+        raise ValueError(f"{name} must have shape [n, {', '.join(map(str, shape_tail))}]")
+    del torch
+
+
+def mc_case_table():
+    """The library's marching-cubes table: (count[256] uint8, edges[256,15] int8)."""
+    cnt = np.zeros(256, dtype=np.uint8)
+    edg = np.zeros((256, 15), dtype=np.int8)
+    _lib.lib().isx_mc_case_table(cnt.ctypes.data, edg.ctypes.data)
+    return cnt, edg
+
+
+class Context:
+    """One library context on a HIP device and stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+
+        self._L = _lib.lib()
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        p = C.c_void_p()
+        st = self._L.isx_create(device, C.c_void_p(handle), C.byref(p))
+        if st != 0:
+            raise IsxError(st, self._L.isx_last_error(None).decode())
+        self._h = p
+        self.device = device
+
+    def _chk(self, st):
+        if st != 0:
+            raise IsxError(st, self._L.isx_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.isx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- weights / configuration
+    def load_mlp(self, Ws: Sequence[np.ndarray], bs: Sequence[np.ndarray]) -> int:
+        Ws = [np.ascontiguousarray(W, dtype=np.float32) for W in Ws]
+        bs = [np.ascontiguousarray(b, dtype=np.float32) for b in bs]
+        widths = [Ws[0].shape[1]] + [W.shape[0] for W in Ws]
+        n = len(Ws)
+        w_arr = (C.c_int32 * (n + 1))(*widths)
+        Wp = (C.c_void_p * n)(*[W.ctypes.data for W in Ws])
+        bp = (C.c_void_p * n)(*[b.ctypes.data for b in bs])
+        out = C.c_int32()
+        self._chk(self._L.isx_load_mlp(self._h, n, w_arr, Wp, bp, C.byref(out)))
+        return out.value
+
+    def load_weights(self, mlp) -> int:
+        """Load a ``workloads.MLPWeights``-like object (``Ws``, ``bs``)."""
+        return self.load_mlp(mlp.Ws, mlp.bs)
+
+    def unload_mlp(self, mlp_id: int):
+        self._chk(self._L.isx_unload_mlp(self._h, mlp_id))
+
+    def set_domain(self, mlp_id: int, lo, hi):
+        lo = (C.c_float * 3)(*map(float, lo))
+        hi = (C.c_float * 3)(*map(float, hi))
+        self._chk(self._L.isx_set_domain(self._h, mlp_id, lo, hi))
+
+    def set_isovalues(self, mlp_id: int, isos):
+        isos = [float(x) for x in np.atleast_1d(isos)]
+        arr = (C.c_float * max(1, len(isos)))(*isos)
+        self._chk(self._L.isx_set_isovalues(self._h, mlp_id, len(isos), arr))
+
+    def set_option(self, option: int, value: int):
+        self._chk(self._L.isx_set_option(self._h, option, int(value)))
+
+    # -- batched calls on device tensors (asynchronous on the context stream)
+    def propagate(self, mlp_id: int, method: int, precision: int, centres, halves, out, out64=None):
+        import torch
+
+        _check_dev(centres, torch.float32, "centres", (3,))
+        _check_dev(halves, torch.float32, "halves", (3,))
+        _check_dev(out, torch.float32, "out", (2,))
+        _check_dev(out64, torch.float64, "out64", (2,))
+        n = centres.shape[0]
+        if halves.shape[0] != n or out.shape[0] != n or (out64 is not None and out64.shape[0] != n):
+            raise ValueError("centres, halves and out must have the same length")
+        self._chk(self._L.isx_propagate(self._h, mlp_id, method, precision, n, _ptr(centres), _ptr(halves),
+                                        _ptr(out), _ptr(out64)))
+
+    def classify_compact(self, mlp_id: int, k: float, out, parent_mask=None):
+        """Returns (active_idx, active_mask, n_active) device tensors; the
+        first n_active entries are valid."""
+        import torch
+
+        _check_dev(out, torch.float32, "out", (2,))
+        n = out.shape[0]
+        if parent_mask is not None:
+            _check_dev(parent_mask, torch.int32, "parent_mask")
+        idx = torch.empty(max(n, 1), dtype=torch.int32, device=out.device)
+        msk = torch.empty(max(n, 1), dtype=torch.int32, device=out.device)
+        cnt = torch.zeros(1, dtype=torch.int64, device=out.device)
+        self._chk(self._L.isx_classify_compact(self._h, mlp_id, float(k), n, _ptr(out), _ptr(parent_mask),
+                                               _ptr(idx), _ptr(msk), _ptr(cnt)))
+        return idx, msk, cnt
+
+    def eval_points(self, mlp_id: int, precision: int, pts, vals):
+        import torch
+
+        _check_dev(pts, torch.float32, "pts", (3,))
+        _check_dev(vals, torch.float32, "vals")
+        self._chk(self._L.isx_eval_points(self._h, mlp_id, precision, pts.shape[0], _ptr(pts), _ptr(vals)))
+
+    # -- full extraction (synchronous)
+    def extract(self, mlp_id: int, method: int = UP, precision: int = FP32, k: float = 3.0, max_depth: int = 6,
+                fp64_band: float = 0.0, max_cells: int = 0, chunk_cells: int = 0) -> "Mesh":
+        p = _lib.Params(method, precision, float(k), int(max_depth), float(fp64_band), int(max_cells),
+                        int(chunk_cells))
+        h = C.c_void_p()
+        self._chk(self._L.isx_extract(self._h, mlp_id, C.byref(p), C.byref(h)))
+        return Mesh(self._L, h)
+
+
+class Mesh:
+    """Library-owned extraction result."""
+
+    def __init__(self, L, h):
+        self._L = L
+        self._h = h
+        nt, nl, nc, nlev = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int32()
+        L.isx_mesh_info(h, C.byref(nt), C.byref(nl), C.byref(nc), C.byref(nlev))
+        self.n_tris, self.n_leaves, self.n_corners, self.n_levels = nt.value, nl.value, nc.value, nlev.value
+
+    def free(self):
+        if self._h:
+            self._L.isx_mesh_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def levels(self):
+        out = []
+        for i in range(self.n_levels):
+            a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+            self._L.isx_mesh_level(self._h, i, C.byref(a), C.byref(b), C.byref(c))
+            out.append(dict(cells=a.value, active=b.value, rechecked=c.value))
+        return out
+
+    def times(self):
+        v = [C.c_float() for _ in range(4)]
+        self._L.isx_mesh_times(self._h, *[C.byref(x) for x in v])
+        return dict(acp_ms=v[0].value, inr_ms=v[1].value, mc_ms=v[2].value, total_ms=v[3].value)
+
+    def triangles(self):
+        pos = np.zeros((self.n_tris, 3, 3), dtype=np.float32)
+        keys = np.zeros((self.n_tris, 3), dtype=np.uint64)
+        iso = np.zeros(self.n_tris, dtype=np.int32)
+        st = self._L.isx_mesh_copy_tris(self._h, pos.ctypes.data, keys.ctypes.data, iso.ctypes.data)
+        if st != 0:
+            raise IsxError(st, "isx_mesh_copy_tris")
+        return pos, keys, iso
+
+    def leaves(self):
+        ids = np.zeros(self.n_leaves, dtype=np.uint32)
+        masks = np.zeros(self.n_leaves, dtype=np.uint32)
+        st = self._L.isx_mesh_copy_leaves(self._h, ids.ctypes.data, masks.ctypes.data)
+        if st != 0:
+            raise IsxError(st, "isx_mesh_copy_leaves")
+        return ids, masks
+
+    def level_cells(self, level: int):
+        n = self.levels()[level]["cells"]
+        ids = np.zeros(n, dtype=np.uint32)
+        out = np.zeros((n, 2), dtype=np.float32)
+        masks = np.zeros(n, dtype=np.uint32)
+        st = self._L.isx_mesh_copy_level(self._h, level, ids.ctypes.data, out.ctypes.data, masks.ctypes.data)
+        if st != 0:
+            raise IsxError(st, "isx_mesh_copy_level (set KEEP_LEVELS before extracting)")
+        return ids, out, masks

@@ -1,0 +1,87 @@
+"""ctypes declarations of the libisx C ABI (include/isx.h).
+
+Loading fails loudly: there is no fallback path.  Build the library with
+``python -m paper_2402_13861_amd.build`` first.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from pathlib import Path
+
+LIB_PATH = Path(__file__).resolve().parent / "libisx.so"
+
+OK, EINVAL, ESHAPE, ENOMEM, ECAPACITY, EHIP, ENAN, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+STATUS_NAMES = {
+    0: "ISX_OK", -1: "ISX_EINVAL", -2: "ISX_ESHAPE", -3: "ISX_ENOMEM", -4: "ISX_ECAPACITY",
+    -5: "ISX_EHIP", -6: "ISX_ENAN", -7: "ISX_EUNSUPPORTED",
+}
+AA, UP = 0, 1
+FP32, BF16, FP64 = 0, 1, 2
+KEEP_LEVELS, HIDDEN_KERNEL = 1, 2
+MAX_LINEAR, MAX_WIDTH, MAX_ISO = 16, 1024, 32
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("method", C.c_int),
+        ("precision", C.c_int),
+        ("k", C.c_float),
+        ("max_depth", C.c_int32),
+        ("fp64_band", C.c_float),
+        ("max_cells", C.c_int64),
+        ("chunk_cells", C.c_int64),
+    ]
+
+
+# (name, restype, argtypes)
+_SIGS = [
+    ("isx_create", C.c_int, [C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]),
+    ("isx_destroy", C.c_int, [C.c_void_p]),
+    ("isx_last_error", C.c_char_p, [C.c_void_p]),
+    ("isx_load_mlp", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_void_p),
+                               C.POINTER(C.c_void_p), C.POINTER(C.c_int32)]),
+    ("isx_unload_mlp", C.c_int, [C.c_void_p, C.c_int32]),
+    ("isx_set_domain", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
+    ("isx_set_isovalues", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_float)]),
+    ("isx_propagate", C.c_int, [C.c_void_p, C.c_int32, C.c_int, C.c_int, C.c_int64, C.c_void_p, C.c_void_p,
+                                C.c_void_p, C.c_void_p]),
+    ("isx_classify_compact", C.c_int, [C.c_void_p, C.c_int32, C.c_float, C.c_int64, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("isx_eval_points", C.c_int, [C.c_void_p, C.c_int32, C.c_int, C.c_int64, C.c_void_p, C.c_void_p]),
+    ("isx_extract", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Params), C.POINTER(C.c_void_p)]),
+    ("isx_mesh_info", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                C.POINTER(C.c_int32)]),
+    ("isx_mesh_level", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                 C.POINTER(C.c_int64)]),
+    ("isx_mesh_times", C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_float), C.POINTER(C.c_float),
+                                 C.POINTER(C.c_float)]),
+    ("isx_mesh_copy_tris", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("isx_mesh_copy_leaves", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("isx_mesh_copy_level", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("isx_mesh_free", C.c_int, [C.c_void_p]),
+    ("isx_mc_case_table", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("isx_set_option", C.c_int, [C.c_void_p, C.c_int, C.c_int64]),
+]
+
+EXPORTED = [name for name, _, _ in _SIGS]
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_2402_13861_amd.build` "
+                "(there is no non-HIP fallback)"
+            )
+        L = C.CDLL(str(LIB_PATH))
+        for name, res, args in _SIGS:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib

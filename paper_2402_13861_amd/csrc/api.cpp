@@ -1,0 +1,702 @@
+// C ABI of libisx (declared in include/isx.h): context, weights, batched
+// propagation, classification/compaction, and the full hierarchical
+// extraction of Alg. 1 followed by corner evaluation and marching cubes.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "isx_internal.h"
+
+using namespace isx;
+
+namespace {
+
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+std::string g_create_error;
+
+}  // namespace
+
+struct isx_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  std::vector<Model> models;
+  bool keep_levels = false;
+  int kernel_choice = 0;
+  size_t prop_budget = size_t(16) << 30;  // bytes of propagation scratch per chunk
+  // propagation scratch
+  Buf F32[2], vec32, F64[2], vec64;
+  // level scratch
+  Buf ids, pmask, centres, halves, out, mask, act_ids[2], act_mask[2], scan_tmp, count;
+  Buf rc_idx, rc_centres, rc_halves, rc_out32, rc_out64, rc_count;
+  // corner / mc scratch
+  Buf bitmap, word_prefix, corner_g, corner_pts, corner_vals, tri_off;
+  Buf cls_mask;
+  int64_t* h_count = nullptr;  // pinned
+};
+
+struct isx_mesh {
+  int depth = 0;
+  int64_t n_tris = 0, n_leaves = 0, n_corners = 0;
+  uint32_t* leaf_ids = nullptr;
+  uint32_t* leaf_masks = nullptr;
+  float* tri_pos = nullptr;
+  uint64_t* tri_keys = nullptr;
+  int32_t* tri_iso = nullptr;
+  std::vector<int64_t> lvl_cells, lvl_active, lvl_recheck;
+  std::vector<std::vector<uint32_t>> lvl_ids, lvl_masks;
+  std::vector<std::vector<float>> lvl_out;
+  bool kept = false;
+  float ms_acp = 0, ms_inr = 0, ms_mc = 0, ms_total = 0;
+};
+
+namespace {
+
+isx_status fail(isx_ctx* c, isx_status st, const std::string& msg) {
+  if (c) c->err = msg;
+  return st;
+}
+
+isx_status hip_fail(isx_ctx* c, hipError_t e, const char* where) {
+  return fail(c, e == hipErrorOutOfMemory ? ISX_ENOMEM : ISX_EHIP,
+              std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(expr)                                    \
+  do {                                                  \
+    hipError_t _e = (expr);                             \
+    if (_e != hipSuccess) return hip_fail(ctx, _e, #expr); \
+  } while (0)
+
+hipError_t ensure(Buf& b, size_t bytes) {
+  if (bytes == 0) bytes = 1;
+  if (b.bytes >= bytes) return hipSuccess;
+  if (b.p) {
+    hipError_t e = hipFree(b.p);
+    if (e != hipSuccess) return e;
+  }
+  b.p = nullptr;
+  b.bytes = 0;
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    return e;
+  }
+  b.bytes = bytes;
+  return hipSuccess;
+}
+
+void release(Buf& b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+void free_layer(Layer& l) {
+  void* ps[] = {l.W, l.Wt, l.b, l.Wd, l.Wtd, l.bd, l.Wbf};
+  for (void* p : ps)
+    if (p) (void)hipFree(p);
+  l = Layer{};
+}
+
+Model* get_model(isx_ctx* ctx, int32_t id) {
+  if (!ctx || id < 0 || id >= (int32_t)ctx->models.size() || !ctx->models[id].live) return nullptr;
+  return &ctx->models[id];
+}
+
+uint16_t f32_to_bf16_bits(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  // round to nearest even
+  const uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  return (uint16_t)(u >> 16);
+}
+
+template <typename T>
+hipError_t upload(T** dst, const std::vector<T>& src) {
+  hipError_t e = hipMalloc((void**)dst, src.size() * sizeof(T));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+// Scratch bytes per cell of the propagation at precision T.
+template <typename T>
+size_t per_cell_bytes(const Model& m) {
+  return (2 * prop_F_elems(m, 1) + prop_vec_elems(m, 1)) * sizeof(T);
+}
+
+template <typename T>
+int64_t chunk_for(isx_ctx* ctx, const Model& m, int64_t n, int64_t req) {
+  int64_t c = req > 0 ? req : (int64_t)(ctx->prop_budget / per_cell_bytes<T>(m));
+  c = std::max<int64_t>(1, std::min<int64_t>(c, n));
+  return c;
+}
+
+isx_status run_propagate(isx_ctx* ctx, const Model& m, isx_method method, isx_precision prec, int64_t n,
+                         const float* centres, const float* halves, float* out, double* out64, int64_t chunk_req) {
+  if (n <= 0) return ISX_OK;
+  if (prec == ISX_FP64) {
+    const int64_t chunk = chunk_for<double>(ctx, m, n, chunk_req);
+    PropWork<double> w;
+    HIPCHK(ensure(ctx->F64[0], prop_F_elems(m, chunk) * sizeof(double)));
+    HIPCHK(ensure(ctx->F64[1], prop_F_elems(m, chunk) * sizeof(double)));
+    HIPCHK(ensure(ctx->vec64, prop_vec_elems(m, chunk) * sizeof(double)));
+    w.F[0] = (double*)ctx->F64[0].p;
+    w.F[1] = (double*)ctx->F64[1].p;
+    w.vec = (double*)ctx->vec64.p;
+    for (int64_t s = 0; s < n; s += chunk) {
+      PropArgs a{&m, method, std::min(chunk, n - s), centres + 3 * s, halves + 3 * s, out + 2 * s,
+                 out64 ? out64 + 2 * s : nullptr, ctx->kernel_choice, ctx->stream};
+      HIPCHK(propagate_f64(a, w));
+    }
+    return ISX_OK;
+  }
+  if (prec == ISX_BF16) return fail(ctx, ISX_EUNSUPPORTED, "bf16 propagation is not built");
+  const int64_t chunk = chunk_for<float>(ctx, m, n, chunk_req);
+  PropWork<float> w;
+  HIPCHK(ensure(ctx->F32[0], prop_F_elems(m, chunk) * sizeof(float)));
+  HIPCHK(ensure(ctx->F32[1], prop_F_elems(m, chunk) * sizeof(float)));
+  HIPCHK(ensure(ctx->vec32, prop_vec_elems(m, chunk) * sizeof(float)));
+  w.F[0] = (float*)ctx->F32[0].p;
+  w.F[1] = (float*)ctx->F32[1].p;
+  w.vec = (float*)ctx->vec32.p;
+  for (int64_t s = 0; s < n; s += chunk) {
+    PropArgs a{&m, method, std::min(chunk, n - s), centres + 3 * s, halves + 3 * s, out + 2 * s, nullptr,
+               ctx->kernel_choice, ctx->stream};
+    HIPCHK(propagate_f32(a, w));
+  }
+  return ISX_OK;
+}
+
+IsoList iso_list(const Model& m) {
+  IsoList l;
+  l.n = m.n_iso;
+  for (int j = 0; j < ISX_MAX_ISO; ++j) l.c[j] = j < m.n_iso ? m.iso[j] : 0.f;
+  return l;
+}
+
+bool finite3(const float* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+}  // namespace
+
+// ---------------------------------------------------------------- recheck
+namespace isx {
+hipError_t launch_band_flags(int64_t n, const float* out, float k, const IsoList& iso, const uint32_t* mask_pre,
+                             float band, uint32_t* flags, hipStream_t s);
+hipError_t launch_gather_boxes(int64_t n, const uint32_t* idx, const float* centres, const float* halves,
+                               float* c_out, float* h_out, hipStream_t s);
+hipError_t launch_recheck_apply(int64_t n, const uint32_t* idx, const double* out64, double k, const IsoList& iso,
+                                const uint32_t* pmask, float* out, uint32_t* mask, hipStream_t s);
+}  // namespace isx
+
+extern "C" {
+
+isx_status isx_create(int device, void* hip_stream, isx_ctx** out) {
+  if (!out) return ISX_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || device < 0 || device >= n) {
+    g_create_error = "isx_create: no such HIP device";
+    return ISX_EINVAL;
+  }
+  e = hipSetDevice(device);
+  if (e != hipSuccess) {
+    g_create_error = std::string("hipSetDevice: ") + hipGetErrorString(e);
+    return ISX_EHIP;
+  }
+  e = upload_mc_table();
+  if (e != hipSuccess) {
+    g_create_error = std::string("upload_mc_table: ") + hipGetErrorString(e);
+    return ISX_EHIP;
+  }
+  isx_ctx* c = new isx_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  e = hipHostMalloc((void**)&c->h_count, 4 * sizeof(int64_t), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    delete c;
+    g_create_error = std::string("hipHostMalloc: ") + hipGetErrorString(e);
+    return ISX_EHIP;
+  }
+  *out = c;
+  return ISX_OK;
+}
+
+isx_status isx_destroy(isx_ctx* ctx) {
+  if (!ctx) return ISX_EINVAL;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (Model& m : ctx->models)
+    for (int l = 0; l < ISX_MAX_LINEAR; ++l) free_layer(m.L[l]);
+  Buf* bufs[] = {&ctx->F32[0], &ctx->F32[1], &ctx->vec32, &ctx->F64[0], &ctx->F64[1], &ctx->vec64,
+                 &ctx->ids, &ctx->pmask, &ctx->centres, &ctx->halves, &ctx->out, &ctx->mask,
+                 &ctx->act_ids[0], &ctx->act_ids[1], &ctx->act_mask[0], &ctx->act_mask[1], &ctx->scan_tmp,
+                 &ctx->count, &ctx->rc_idx, &ctx->rc_centres, &ctx->rc_halves, &ctx->rc_out32, &ctx->rc_out64,
+                 &ctx->rc_count, &ctx->bitmap, &ctx->word_prefix, &ctx->corner_g, &ctx->corner_pts,
+                 &ctx->corner_vals, &ctx->tri_off, &ctx->cls_mask};
+  for (Buf* b : bufs) release(*b);
+  if (ctx->h_count) (void)hipHostFree(ctx->h_count);
+  delete ctx;
+  return ISX_OK;
+}
+
+const char* isx_last_error(const isx_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
+
+isx_status isx_set_option(isx_ctx* ctx, isx_option option, int64_t value) {
+  if (!ctx) return ISX_EINVAL;
+  switch (option) {
+    case ISX_KEEP_LEVELS:
+      ctx->keep_levels = value != 0;
+      return ISX_OK;
+    case ISX_HIDDEN_KERNEL:
+      if (value < 0 || value > 2) return fail(ctx, ISX_EINVAL, "ISX_HIDDEN_KERNEL must be 0, 1 or 2");
+      ctx->kernel_choice = (int)value;
+      return ISX_OK;
+  }
+  return fail(ctx, ISX_EINVAL, "unknown option");
+}
+
+isx_status isx_mc_case_table(uint8_t* h_count, int8_t* h_edges) {
+  const McTable& t = mc_table();
+  if (h_count) std::memcpy(h_count, t.count, sizeof(t.count));
+  if (h_edges) std::memcpy(h_edges, t.edges, sizeof(t.edges));
+  return ISX_OK;
+}
+
+isx_status isx_load_mlp(isx_ctx* ctx, int32_t n_linear, const int32_t* widths, const float* const* h_W,
+                        const float* const* h_b, int32_t* mlp_id) {
+  if (!ctx || !widths || !h_W || !h_b || !mlp_id) return fail(ctx, ISX_EINVAL, "null argument");
+  if (n_linear < 2 || n_linear > ISX_MAX_LINEAR)
+    return fail(ctx, ISX_ESHAPE, "n_linear must be in [2, " + std::to_string(ISX_MAX_LINEAR) + "]");
+  if (widths[0] != 3 || widths[n_linear] != 1) return fail(ctx, ISX_ESHAPE, "widths[0] must be 3 and widths[L] 1");
+  for (int l = 1; l < n_linear; ++l)
+    if (widths[l] < 1 || widths[l] > ISX_MAX_WIDTH)
+      return fail(ctx, ISX_ESHAPE, "hidden width out of range at layer " + std::to_string(l));
+  for (int l = 0; l < n_linear; ++l) {
+    if (!h_W[l] || !h_b[l]) return fail(ctx, ISX_EINVAL, "null weight pointer");
+    const int64_t nw = (int64_t)widths[l] * widths[l + 1];
+    for (int64_t i = 0; i < nw; ++i)
+      if (!std::isfinite(h_W[l][i])) return fail(ctx, ISX_ENAN, "non-finite weight in layer " + std::to_string(l));
+    for (int i = 0; i < widths[l + 1]; ++i)
+      if (!std::isfinite(h_b[l][i])) return fail(ctx, ISX_ENAN, "non-finite bias in layer " + std::to_string(l));
+  }
+  (void)hipSetDevice(ctx->device);
+  Model m;
+  m.n_linear = n_linear;
+  for (int l = 0; l <= n_linear; ++l) {
+    m.widths[l] = widths[l];
+    m.pw[l] = (l == 0 || l == n_linear) ? widths[l] : (widths[l] + 31) / 32 * 32;
+  }
+  for (int l = 0; l < n_linear; ++l) {
+    const int ni = m.pw[l], no = m.pw[l + 1];
+    const int wi = widths[l], wo = widths[l + 1];
+    std::vector<float> W((size_t)no * ni, 0.f), Wt((size_t)ni * no, 0.f), b((size_t)no, 0.f);
+    std::vector<double> Wd((size_t)no * ni, 0.0), Wtd((size_t)ni * no, 0.0), bd((size_t)no, 0.0);
+    std::vector<uint16_t> Wbf((size_t)no * ni, 0);
+    for (int o = 0; o < wo; ++o) {
+      for (int i = 0; i < wi; ++i) {
+        const float w = h_W[l][(size_t)o * wi + i];
+        W[(size_t)o * ni + i] = w;
+        Wt[(size_t)i * no + o] = w;
+        Wd[(size_t)o * ni + i] = w;
+        Wtd[(size_t)i * no + o] = w;
+        Wbf[(size_t)o * ni + i] = f32_to_bf16_bits(w);
+      }
+      b[o] = h_b[l][o];
+      bd[o] = h_b[l][o];
+    }
+    Layer& L = m.L[l];
+    L.n_in = ni;
+    L.n_out = no;
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = upload(&L.W, W);
+    if (e == hipSuccess) e = upload(&L.Wt, Wt);
+    if (e == hipSuccess) e = upload(&L.b, b);
+    if (e == hipSuccess) e = upload(&L.Wd, Wd);
+    if (e == hipSuccess) e = upload(&L.Wtd, Wtd);
+    if (e == hipSuccess) e = upload(&L.bd, bd);
+    if (e == hipSuccess) e = upload(&L.Wbf, Wbf);
+    if (e != hipSuccess) {
+      for (int k = 0; k <= l; ++k) free_layer(m.L[k]);
+      return hip_fail(ctx, e, "isx_load_mlp upload");
+    }
+  }
+  m.live = true;
+  for (size_t i = 0; i < ctx->models.size(); ++i) {
+    if (!ctx->models[i].live) {
+      ctx->models[i] = m;
+      *mlp_id = (int32_t)i;
+      return ISX_OK;
+    }
+  }
+  ctx->models.push_back(m);
+  *mlp_id = (int32_t)ctx->models.size() - 1;
+  return ISX_OK;
+}
+
+isx_status isx_unload_mlp(isx_ctx* ctx, int32_t mlp_id) {
+  Model* m = get_model(ctx, mlp_id);
+  if (!m) return fail(ctx, ISX_EINVAL, "no such mlp");
+  (void)hipStreamSynchronize(ctx->stream);
+  for (int l = 0; l < ISX_MAX_LINEAR; ++l) free_layer(m->L[l]);
+  m->live = false;
+  return ISX_OK;
+}
+
+isx_status isx_set_domain(isx_ctx* ctx, int32_t mlp_id, const float h_lo[3], const float h_hi[3]) {
+  Model* m = get_model(ctx, mlp_id);
+  if (!m || !h_lo || !h_hi) return fail(ctx, ISX_EINVAL, "bad mlp id or null domain");
+  if (!finite3(h_lo) || !finite3(h_hi)) return fail(ctx, ISX_ENAN, "non-finite domain");
+  for (int a = 0; a < 3; ++a)
+    if (!(h_hi[a] > h_lo[a])) return fail(ctx, ISX_EINVAL, "domain hi must exceed lo on every axis");
+  for (int a = 0; a < 3; ++a) {
+    m->lo[a] = h_lo[a];
+    m->hi[a] = h_hi[a];
+  }
+  return ISX_OK;
+}
+
+isx_status isx_set_isovalues(isx_ctx* ctx, int32_t mlp_id, int32_t n_iso, const float* h_iso) {
+  Model* m = get_model(ctx, mlp_id);
+  if (!m) return fail(ctx, ISX_EINVAL, "bad mlp id");
+  if (n_iso < 0 || n_iso > ISX_MAX_ISO || (n_iso > 0 && !h_iso))
+    return fail(ctx, ISX_EINVAL, "n_iso must be in [0, " + std::to_string(ISX_MAX_ISO) + "]");
+  for (int j = 0; j < n_iso; ++j)
+    if (!std::isfinite(h_iso[j])) return fail(ctx, ISX_ENAN, "non-finite iso-value");
+  m->n_iso = n_iso;
+  for (int j = 0; j < ISX_MAX_ISO; ++j) m->iso[j] = j < n_iso ? h_iso[j] : 0.f;
+  return ISX_OK;
+}
+
+isx_status isx_propagate(isx_ctx* ctx, int32_t mlp_id, isx_method method, isx_precision precision, int64_t n_cells,
+                         const float* d_centres, const float* d_halves, float* d_out, double* d_out64) {
+  Model* m = get_model(ctx, mlp_id);
+  if (!m) return fail(ctx, ISX_EINVAL, "bad mlp id");
+  if (method != ISX_AA && method != ISX_UP) return fail(ctx, ISX_EINVAL, "unknown method");
+  if (precision != ISX_FP32 && precision != ISX_BF16 && precision != ISX_FP64)
+    return fail(ctx, ISX_EINVAL, "unknown precision");
+  if (n_cells < 0) return fail(ctx, ISX_EINVAL, "n_cells < 0");
+  if (n_cells == 0) return ISX_OK;
+  if (!d_centres || !d_halves || !d_out) return fail(ctx, ISX_EINVAL, "null buffer");
+  if (d_out64 && precision != ISX_FP64) return fail(ctx, ISX_EINVAL, "d_out64 is only written with ISX_FP64");
+  (void)hipSetDevice(ctx->device);
+  return run_propagate(ctx, *m, method, precision, n_cells, d_centres, d_halves, d_out, d_out64, 0);
+}
+
+isx_status isx_classify_compact(isx_ctx* ctx, int32_t mlp_id, float k, int64_t n_cells, const float* d_out,
+                                const uint32_t* d_parent_mask, uint32_t* d_active_idx, uint32_t* d_active_mask,
+                                int64_t* d_n_active) {
+  Model* m = get_model(ctx, mlp_id);
+  if (!m) return fail(ctx, ISX_EINVAL, "bad mlp id");
+  if (!(k >= 0.f) || !std::isfinite(k)) return fail(ctx, ISX_EINVAL, "k must be finite and >= 0");
+  if (n_cells < 0 || !d_n_active || (n_cells > 0 && (!d_out || !d_active_idx || !d_active_mask)))
+    return fail(ctx, ISX_EINVAL, "bad arguments");
+  if (n_cells > (int64_t)UINT32_MAX) return fail(ctx, ISX_ECAPACITY, "n_cells exceeds 2^32-1");
+  (void)hipSetDevice(ctx->device);
+  HIPCHK(ensure(ctx->cls_mask, (size_t)n_cells * sizeof(uint32_t)));
+  HIPCHK(ensure(ctx->scan_tmp, compact_tmp_bytes(n_cells)));
+  HIPCHK(launch_classify(n_cells, d_out, k, iso_list(*m), d_parent_mask, (uint32_t*)ctx->cls_mask.p, ctx->stream));
+  HIPCHK(launch_compact(n_cells, (const uint32_t*)ctx->cls_mask.p, nullptr, d_active_idx, d_active_mask, d_n_active,
+                        ctx->scan_tmp.p, ctx->stream));
+  return ISX_OK;
+}
+
+isx_status isx_eval_points(isx_ctx* ctx, int32_t mlp_id, isx_precision precision, int64_t n, const float* d_points,
+                           float* d_values) {
+  Model* m = get_model(ctx, mlp_id);
+  if (!m) return fail(ctx, ISX_EINVAL, "bad mlp id");
+  if (n < 0 || (n > 0 && (!d_points || !d_values))) return fail(ctx, ISX_EINVAL, "bad arguments");
+  (void)hipSetDevice(ctx->device);
+  if (precision == ISX_FP64) {
+    HIPCHK(eval_points_f64(*m, n, d_points, d_values, ctx->stream));
+  } else if (precision == ISX_FP32) {
+    HIPCHK(eval_points_f32(*m, n, d_points, d_values, ctx->stream));
+  } else if (precision == ISX_BF16) {
+    return fail(ctx, ISX_EUNSUPPORTED, "bf16 evaluation is not built");
+  } else {
+    return fail(ctx, ISX_EINVAL, "unknown precision");
+  }
+  return ISX_OK;
+}
+
+// ---------------------------------------------------------------- extract
+static isx_status read_count(isx_ctx* ctx, const int64_t* d, int64_t* h) {
+  HIPCHK(hipMemcpyAsync(ctx->h_count, d, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  *h = ctx->h_count[0];
+  return ISX_OK;
+}
+
+isx_status isx_extract(isx_ctx* ctx, int32_t mlp_id, const isx_params* p, isx_mesh** out) {
+  Model* mp = get_model(ctx, mlp_id);
+  if (!mp || !p || !out) return fail(ctx, ISX_EINVAL, "bad arguments");
+  *out = nullptr;
+  const Model& m = *mp;
+  if (p->method != ISX_AA && p->method != ISX_UP) return fail(ctx, ISX_EINVAL, "unknown method");
+  if (p->precision != ISX_FP32 && p->precision != ISX_BF16 && p->precision != ISX_FP64)
+    return fail(ctx, ISX_EINVAL, "unknown precision");
+  if (p->max_depth < 0 || p->max_depth > 10) return fail(ctx, ISX_EINVAL, "max_depth must be in [0, 10]");
+  if (!(p->k >= 0.f) || !std::isfinite(p->k)) return fail(ctx, ISX_EINVAL, "k must be finite and >= 0");
+  if (!(p->fp64_band >= 0.f)) return fail(ctx, ISX_EINVAL, "fp64_band must be >= 0");
+  if (m.n_iso < 1) return fail(ctx, ISX_EINVAL, "no iso-values set");
+  (void)hipSetDevice(ctx->device);
+  hipStream_t s = ctx->stream;
+  const float k = p->method == ISX_AA ? 1.f : p->k;
+  const int64_t cap = p->max_cells > 0 ? p->max_cells : (int64_t)1 << 28;
+  const IsoList iso = iso_list(m);
+  const uint32_t full = m.n_iso >= 32 ? 0xffffffffu : ((1u << m.n_iso) - 1u);
+  const bool recheck = p->fp64_band > 0.f && p->precision != ISX_FP64;
+
+  hipEvent_t ev[4];
+  for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+  HIPCHK(hipEventRecord(ev[0], s));
+
+  isx_mesh* mesh = new isx_mesh();
+  mesh->depth = p->max_depth;
+  mesh->kept = ctx->keep_levels;
+  auto bail = [&](isx_status st) {
+    isx_mesh_free(mesh);
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    return st;
+  };
+#define XCHK(expr)                                   \
+  do {                                               \
+    hipError_t _e = (expr);                          \
+    if (_e != hipSuccess) return bail(hip_fail(ctx, _e, #expr)); \
+  } while (0)
+
+  int64_t n_par = 0;
+  int cur = 0;  // parents in act_*[cur]
+  for (int L = 0; L <= p->max_depth; ++L) {
+    const int64_t n = L == 0 ? 1 : 8 * n_par;
+    if (n > cap)
+      return bail(fail(ctx, ISX_ECAPACITY, "level " + std::to_string(L) + " has " + std::to_string(n) +
+                                               " cells, above max_cells=" + std::to_string(cap)));
+    XCHK(ensure(ctx->ids, n * 4));
+    XCHK(ensure(ctx->pmask, n * 4));
+    XCHK(ensure(ctx->centres, n * 12));
+    XCHK(ensure(ctx->halves, n * 12));
+    XCHK(ensure(ctx->out, n * 8));
+    XCHK(ensure(ctx->mask, n * 4));
+    XCHK(ensure(ctx->act_ids[cur ^ 1], n * 4));
+    XCHK(ensure(ctx->act_mask[cur ^ 1], n * 4));
+    XCHK(ensure(ctx->scan_tmp, compact_tmp_bytes(n)));
+    XCHK(ensure(ctx->count, 2 * sizeof(int64_t)));
+    uint32_t* ids = (uint32_t*)ctx->ids.p;
+    uint32_t* pmask = (uint32_t*)ctx->pmask.p;
+    float* centres = (float*)ctx->centres.p;
+    float* halves = (float*)ctx->halves.p;
+    float* outb = (float*)ctx->out.p;
+    uint32_t* mask = (uint32_t*)ctx->mask.p;
+    if (L == 0) {
+      XCHK(launch_root(m, full, ids, pmask, centres, halves, s));
+    } else {
+      XCHK(launch_children(m, L, n_par, (const uint32_t*)ctx->act_ids[cur].p, (const uint32_t*)ctx->act_mask[cur].p,
+                           ids, pmask, centres, halves, s));
+    }
+    isx_status st = run_propagate(ctx, m, p->method, p->precision, n, centres, halves, outb, nullptr, p->chunk_cells);
+    if (st != ISX_OK) return bail(st);
+    XCHK(launch_classify(n, outb, k, iso, pmask, mask, s));
+    int64_t n_rc = 0;
+    if (recheck) {
+      XCHK(ensure(ctx->rc_idx, n * 4));
+      XCHK(ensure(ctx->rc_count, sizeof(int64_t)));
+      XCHK(launch_band_flags(n, outb, k, iso, pmask, p->fp64_band, (uint32_t*)ctx->rc_idx.p, s));
+      // compact flags -> indices (reuse act_mask[cur^1] as scratch for the flag masks)
+      XCHK(launch_compact(n, (const uint32_t*)ctx->rc_idx.p, nullptr, (uint32_t*)ctx->act_ids[cur ^ 1].p,
+                          (uint32_t*)ctx->act_mask[cur ^ 1].p, (int64_t*)ctx->rc_count.p, ctx->scan_tmp.p, s));
+      st = read_count(ctx, (const int64_t*)ctx->rc_count.p, &n_rc);
+      if (st != ISX_OK) return bail(st);
+      if (n_rc > 0) {
+        XCHK(ensure(ctx->rc_idx, n_rc * 4));
+        XCHK(ensure(ctx->rc_centres, n_rc * 12));
+        XCHK(ensure(ctx->rc_halves, n_rc * 12));
+        XCHK(ensure(ctx->rc_out32, n_rc * 8));
+        XCHK(ensure(ctx->rc_out64, n_rc * 16));
+        XCHK(hipMemcpyAsync(ctx->rc_idx.p, ctx->act_ids[cur ^ 1].p, n_rc * 4, hipMemcpyDeviceToDevice, s));
+        XCHK(launch_gather_boxes(n_rc, (const uint32_t*)ctx->rc_idx.p, centres, halves, (float*)ctx->rc_centres.p,
+                                 (float*)ctx->rc_halves.p, s));
+        st = run_propagate(ctx, m, p->method, ISX_FP64, n_rc, (const float*)ctx->rc_centres.p,
+                           (const float*)ctx->rc_halves.p, (float*)ctx->rc_out32.p, (double*)ctx->rc_out64.p,
+                           p->chunk_cells);
+        if (st != ISX_OK) return bail(st);
+        XCHK(launch_recheck_apply(n_rc, (const uint32_t*)ctx->rc_idx.p, (const double*)ctx->rc_out64.p, (double)k,
+                                  iso, pmask, outb, mask, s));
+      }
+    }
+    XCHK(launch_compact(n, mask, ids, (uint32_t*)ctx->act_ids[cur ^ 1].p, (uint32_t*)ctx->act_mask[cur ^ 1].p,
+                        (int64_t*)ctx->count.p, ctx->scan_tmp.p, s));
+    int64_t n_act = 0;
+    st = read_count(ctx, (const int64_t*)ctx->count.p, &n_act);
+    if (st != ISX_OK) return bail(st);
+    mesh->lvl_cells.push_back(n);
+    mesh->lvl_active.push_back(n_act);
+    mesh->lvl_recheck.push_back(n_rc);
+    if (ctx->keep_levels) {
+      std::vector<uint32_t> hi(n), hm(n);
+      std::vector<float> ho(2 * n);
+      XCHK(hipMemcpyAsync(hi.data(), ids, n * 4, hipMemcpyDeviceToHost, s));
+      XCHK(hipMemcpyAsync(hm.data(), mask, n * 4, hipMemcpyDeviceToHost, s));
+      XCHK(hipMemcpyAsync(ho.data(), outb, n * 8, hipMemcpyDeviceToHost, s));
+      XCHK(hipStreamSynchronize(s));
+      mesh->lvl_ids.push_back(std::move(hi));
+      mesh->lvl_masks.push_back(std::move(hm));
+      mesh->lvl_out.push_back(std::move(ho));
+    }
+    cur ^= 1;
+    n_par = n_act;
+  }
+  XCHK(hipEventRecord(ev[1], s));
+
+  // active leaves
+  const int D = p->max_depth;
+  const int64_t n_leaves = n_par;
+  mesh->n_leaves = n_leaves;
+  XCHK(hipMalloc((void**)&mesh->leaf_ids, std::max<int64_t>(1, n_leaves) * 4));
+  XCHK(hipMalloc((void**)&mesh->leaf_masks, std::max<int64_t>(1, n_leaves) * 4));
+  if (n_leaves > 0) {
+    XCHK(hipMemcpyAsync(mesh->leaf_ids, ctx->act_ids[cur].p, n_leaves * 4, hipMemcpyDeviceToDevice, s));
+    XCHK(hipMemcpyAsync(mesh->leaf_masks, ctx->act_mask[cur].p, n_leaves * 4, hipMemcpyDeviceToDevice, s));
+  }
+  // corners: bitmap, prefix, list, points, values
+  const uint64_t words = corner_bitmap_words(D);
+  XCHK(ensure(ctx->bitmap, words * 4));
+  XCHK(ensure(ctx->word_prefix, words * 4));
+  XCHK(ensure(ctx->scan_tmp, std::max(scan_tmp_bytes((int64_t)words), scan_tmp_bytes(n_leaves * m.n_iso))));
+  XCHK(launch_corner_mark(D, n_leaves, mesh->leaf_ids, (uint32_t*)ctx->bitmap.p, words, s));
+  XCHK(launch_corner_list(D, words, (const uint32_t*)ctx->bitmap.p, (uint32_t*)ctx->word_prefix.p,
+                          (int64_t*)ctx->count.p, ctx->scan_tmp.p, ctx->scan_tmp.bytes, nullptr, s));
+  int64_t n_corners = 0;
+  {
+    isx_status st = read_count(ctx, (const int64_t*)ctx->count.p, &n_corners);
+    if (st != ISX_OK) return bail(st);
+  }
+  mesh->n_corners = n_corners;
+  XCHK(ensure(ctx->corner_g, n_corners * 4));
+  XCHK(ensure(ctx->corner_pts, n_corners * 12));
+  XCHK(ensure(ctx->corner_vals, n_corners * 4));
+  XCHK(launch_corner_list(D, words, (const uint32_t*)ctx->bitmap.p, (uint32_t*)ctx->word_prefix.p,
+                          (int64_t*)ctx->count.p, ctx->scan_tmp.p, ctx->scan_tmp.bytes, (uint32_t*)ctx->corner_g.p,
+                          s));
+  XCHK(launch_corner_points(m, D, n_corners, (const uint32_t*)ctx->corner_g.p, (float*)ctx->corner_pts.p, s));
+  if (p->precision == ISX_FP64) {
+    XCHK(eval_points_f64(m, n_corners, (const float*)ctx->corner_pts.p, (float*)ctx->corner_vals.p, s));
+  } else {
+    XCHK(eval_points_f32(m, n_corners, (const float*)ctx->corner_pts.p, (float*)ctx->corner_vals.p, s));
+  }
+  XCHK(hipEventRecord(ev[2], s));
+  // marching cubes
+  const int64_t pairs = n_leaves * m.n_iso;
+  XCHK(ensure(ctx->tri_off, std::max<int64_t>(1, pairs) * 4));
+  XCHK(launch_mc_count(m, D, n_leaves, mesh->leaf_ids, mesh->leaf_masks, (const uint32_t*)ctx->bitmap.p,
+                       (const uint32_t*)ctx->word_prefix.p, (const float*)ctx->corner_vals.p, (uint32_t*)ctx->tri_off.p,
+                       (int64_t*)ctx->count.p, ctx->scan_tmp.p, ctx->scan_tmp.bytes, s));
+  int64_t n_tris = 0;
+  {
+    isx_status st = read_count(ctx, (const int64_t*)ctx->count.p, &n_tris);
+    if (st != ISX_OK) return bail(st);
+  }
+  mesh->n_tris = n_tris;
+  XCHK(hipMalloc((void**)&mesh->tri_pos, std::max<int64_t>(1, n_tris) * 36));
+  XCHK(hipMalloc((void**)&mesh->tri_keys, std::max<int64_t>(1, n_tris) * 24));
+  XCHK(hipMalloc((void**)&mesh->tri_iso, std::max<int64_t>(1, n_tris) * 4));
+  XCHK(launch_mc_emit(m, D, n_leaves, mesh->leaf_ids, mesh->leaf_masks, (const uint32_t*)ctx->bitmap.p,
+                      (const uint32_t*)ctx->word_prefix.p, (const float*)ctx->corner_vals.p,
+                      (const uint32_t*)ctx->tri_off.p, mesh->tri_pos, mesh->tri_keys, mesh->tri_iso, s));
+  XCHK(hipEventRecord(ev[3], s));
+  XCHK(hipEventSynchronize(ev[3]));
+  float t01 = 0, t12 = 0, t23 = 0, t03 = 0;
+  XCHK(hipEventElapsedTime(&t01, ev[0], ev[1]));
+  XCHK(hipEventElapsedTime(&t12, ev[1], ev[2]));
+  XCHK(hipEventElapsedTime(&t23, ev[2], ev[3]));
+  XCHK(hipEventElapsedTime(&t03, ev[0], ev[3]));
+  mesh->ms_acp = t01;
+  mesh->ms_inr = t12;
+  mesh->ms_mc = t23;
+  mesh->ms_total = t03;
+  for (auto& e : ev) (void)hipEventDestroy(e);
+#undef XCHK
+  *out = mesh;
+  return ISX_OK;
+}
+
+isx_status isx_mesh_info(const isx_mesh* mesh, int64_t* n_tris, int64_t* n_leaves, int64_t* n_corners,
+                         int32_t* n_levels) {
+  if (!mesh) return ISX_EINVAL;
+  if (n_tris) *n_tris = mesh->n_tris;
+  if (n_leaves) *n_leaves = mesh->n_leaves;
+  if (n_corners) *n_corners = mesh->n_corners;
+  if (n_levels) *n_levels = (int32_t)mesh->lvl_cells.size();
+  return ISX_OK;
+}
+
+isx_status isx_mesh_level(const isx_mesh* mesh, int32_t level, int64_t* n_cells, int64_t* n_active,
+                          int64_t* n_rechecked) {
+  if (!mesh || level < 0 || level >= (int32_t)mesh->lvl_cells.size()) return ISX_EINVAL;
+  if (n_cells) *n_cells = mesh->lvl_cells[level];
+  if (n_active) *n_active = mesh->lvl_active[level];
+  if (n_rechecked) *n_rechecked = mesh->lvl_recheck[level];
+  return ISX_OK;
+}
+
+isx_status isx_mesh_times(const isx_mesh* mesh, float* ms_acp, float* ms_inr, float* ms_mc, float* ms_total) {
+  if (!mesh) return ISX_EINVAL;
+  if (ms_acp) *ms_acp = mesh->ms_acp;
+  if (ms_inr) *ms_inr = mesh->ms_inr;
+  if (ms_mc) *ms_mc = mesh->ms_mc;
+  if (ms_total) *ms_total = mesh->ms_total;
+  return ISX_OK;
+}
+
+isx_status isx_mesh_copy_tris(const isx_mesh* mesh, float* h_pos, uint64_t* h_keys, int32_t* h_iso) {
+  if (!mesh) return ISX_EINVAL;
+  if (mesh->n_tris == 0) return ISX_OK;
+  if (h_pos && hipMemcpy(h_pos, mesh->tri_pos, mesh->n_tris * 36, hipMemcpyDeviceToHost) != hipSuccess) return ISX_EHIP;
+  if (h_keys && hipMemcpy(h_keys, mesh->tri_keys, mesh->n_tris * 24, hipMemcpyDeviceToHost) != hipSuccess)
+    return ISX_EHIP;
+  if (h_iso && hipMemcpy(h_iso, mesh->tri_iso, mesh->n_tris * 4, hipMemcpyDeviceToHost) != hipSuccess) return ISX_EHIP;
+  return ISX_OK;
+}
+
+isx_status isx_mesh_copy_leaves(const isx_mesh* mesh, uint32_t* h_ids, uint32_t* h_masks) {
+  if (!mesh) return ISX_EINVAL;
+  if (mesh->n_leaves == 0) return ISX_OK;
+  if (h_ids && hipMemcpy(h_ids, mesh->leaf_ids, mesh->n_leaves * 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return ISX_EHIP;
+  if (h_masks && hipMemcpy(h_masks, mesh->leaf_masks, mesh->n_leaves * 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return ISX_EHIP;
+  return ISX_OK;
+}
+
+isx_status isx_mesh_copy_level(const isx_mesh* mesh, int32_t level, uint32_t* h_ids, float* h_out,
+                               uint32_t* h_masks) {
+  if (!mesh || level < 0 || level >= (int32_t)mesh->lvl_cells.size()) return ISX_EINVAL;
+  if (!mesh->kept) return ISX_EUNSUPPORTED;
+  const size_t n = mesh->lvl_ids[level].size();
+  if (h_ids) std::memcpy(h_ids, mesh->lvl_ids[level].data(), n * 4);
+  if (h_masks) std::memcpy(h_masks, mesh->lvl_masks[level].data(), n * 4);
+  if (h_out) std::memcpy(h_out, mesh->lvl_out[level].data(), n * 8);
+  return ISX_OK;
+}
+
+isx_status isx_mesh_free(isx_mesh* mesh) {
+  if (!mesh) return ISX_EINVAL;
+  void* ps[] = {mesh->leaf_ids, mesh->leaf_masks, mesh->tri_pos, mesh->tri_keys, mesh->tri_iso};
+  for (void* q : ps)
+    if (q) (void)hipFree(q);
+  delete mesh;
+  return ISX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,148 @@
+// Internal declarations of libisx (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "isx.h"
+
+namespace isx {
+
+// Column layout of a cell's coefficient block at hidden layer h (1-based):
+// column 0 holds the centre, columns 1..3 the coefficients of the three input
+// symbols, columns 4..15 are zero, then one block of n_{i} columns for the
+// symbols introduced by the ReLUs of hidden layers i = 1..h-1.  Inside a
+// cell, a column's n_h coefficients are contiguous (column-major block).
+constexpr int kHeadCols = 16;
+
+// A loaded MLP.  Hidden widths are zero-padded to a multiple of 32: a padded
+// neuron has zero weights and bias, its pre-activation form is identically 0,
+// and the zero columns of the next layer's weights remove it from every
+// later value, so all results are unchanged.
+struct Layer {
+  int n_in = 0, n_out = 0;  // padded widths
+  float* W = nullptr;       // [n_out][n_in] row-major
+  float* Wt = nullptr;      // [n_in][n_out]
+  float* b = nullptr;       // [n_out]
+  double* Wd = nullptr;
+  double* Wtd = nullptr;
+  double* bd = nullptr;
+  uint16_t* Wbf = nullptr;  // bfloat16 bits, [n_out][n_in]
+};
+
+struct Model {
+  bool live = false;
+  int n_linear = 0;
+  int widths[ISX_MAX_LINEAR + 1] = {};  // as loaded
+  int pw[ISX_MAX_LINEAR + 1] = {};      // padded (pw[0] = 3, pw[L] = 1)
+  Layer L[ISX_MAX_LINEAR];
+  float lo[3] = {-1.f, -1.f, -1.f}, hi[3] = {1.f, 1.f, 1.f};
+  int n_iso = 0;
+  float iso[ISX_MAX_ISO] = {};
+  int hidden() const { return n_linear - 1; }
+  // columns of hidden layer h's coefficient block (h = 1..hidden())
+  int64_t cols(int h) const {
+    int64_t c = kHeadCols;
+    for (int i = 1; i < h; ++i) c += pw[i];
+    return c;
+  }
+};
+
+// Per-chunk working memory of the propagation (element type T).
+template <typename T>
+struct PropWork {
+  T* F[2] = {nullptr, nullptr};        // ping-pong coefficient blocks
+  size_t F_elems = 0;                  // capacity of each, in elements
+  T* vec = nullptr;                    // Y, A, B, G of every hidden layer
+  size_t vec_elems = 0;
+};
+
+// Device-side views passed by value to kernels.
+template <typename T>
+struct NetView {
+  int n_linear;
+  int n[ISX_MAX_LINEAR + 1];  // padded widths
+  const T* W[ISX_MAX_LINEAR];
+  const T* b[ISX_MAX_LINEAR];
+  // per hidden layer h = 1..n_linear-1, chunk-local [C][n_h]
+  const T* Y[ISX_MAX_LINEAR];
+  const T* A[ISX_MAX_LINEAR];
+  const T* B[ISX_MAX_LINEAR];
+  const T* G[ISX_MAX_LINEAR];
+};
+
+struct IsoList {
+  int n;
+  float c[ISX_MAX_ISO];
+};
+
+// ---- propagation launchers (kernels_prop.hip) ----
+// Propagate C boxes; writes (centre, spread) to out32 [C][2] and, if given,
+// out64 [C][2].  `work` must be sized by prop_work_need().
+struct PropArgs {
+  const Model* m;
+  isx_method method;
+  int64_t C;
+  const float* centres;
+  const float* halves;
+  float* out32;
+  double* out64;
+  int kernel_choice;  // 0 auto, 1 SIMT, 2 MFMA
+  hipStream_t stream;
+};
+size_t prop_F_elems(const Model& m, int64_t C);
+size_t prop_vec_elems(const Model& m, int64_t C);
+hipError_t propagate_f32(const PropArgs& a, PropWork<float>& w);
+hipError_t propagate_f64(const PropArgs& a, PropWork<double>& w);
+hipError_t propagate_bf16(const PropArgs& a, PropWork<float>& w, uint16_t* Fbf[2], size_t Fbf_elems);
+hipError_t eval_points_f32(const Model& m, int64_t n, const float* pts, float* vals, hipStream_t s);
+hipError_t eval_points_f64(const Model& m, int64_t n, const float* pts, float* vals, hipStream_t s);
+
+// ---- hierarchy / scan / marching cubes launchers (kernels_hier.hip) ----
+hipError_t launch_root(const Model& m, uint32_t full_mask, uint32_t* ids, uint32_t* pmask, float* centres,
+                       float* halves, hipStream_t s);
+hipError_t launch_children(const Model& m, int level, int64_t n_par, const uint32_t* par_ids,
+                           const uint32_t* par_masks, uint32_t* ids, uint32_t* pmask, float* centres,
+                           float* halves, hipStream_t s);
+hipError_t launch_classify(int64_t n, const float* out, float k, const IsoList& iso, const uint32_t* pmask,
+                           uint32_t* mask, hipStream_t s);
+// Stable compaction of the entries with mask != 0: writes (ids ? ids[i] : i)
+// and mask[i] in order, and the count to *d_count.  `tmp` needs
+// compact_tmp_bytes(n) bytes.
+size_t compact_tmp_bytes(int64_t n);
+hipError_t launch_compact(int64_t n, const uint32_t* mask, const uint32_t* ids, uint32_t* out_idx,
+                          uint32_t* out_mask, int64_t* d_count, void* tmp, hipStream_t s);
+// Corner set of the leaves: bitmap over the (2^D+1)^3 grid, its word prefix
+// sums, and the sorted list of corner grid indices.
+size_t corner_bitmap_words(int depth);
+hipError_t launch_corner_mark(int depth, int64_t n_leaves, const uint32_t* leaf_ids, uint32_t* bitmap,
+                              uint64_t words, hipStream_t s);
+hipError_t launch_corner_list(int depth, uint64_t words, const uint32_t* bitmap, uint32_t* word_prefix,
+                              int64_t* d_count, void* tmp, size_t tmp_bytes, uint32_t* corner_g,
+                              hipStream_t s);
+size_t scan_tmp_bytes(int64_t n);
+hipError_t launch_corner_points(const Model& m, int depth, int64_t n, const uint32_t* corner_g, float* pts,
+                                hipStream_t s);
+// Marching cubes on (leaf, iso) pairs.
+hipError_t upload_mc_table();
+hipError_t launch_mc_count(const Model& m, int depth, int64_t n_leaves, const uint32_t* leaf_ids,
+                           const uint32_t* leaf_masks, const uint32_t* bitmap, const uint32_t* word_prefix,
+                           const float* corner_vals, uint32_t* tri_offsets, int64_t* d_total, void* tmp,
+                           size_t tmp_bytes, hipStream_t s);
+hipError_t launch_mc_emit(const Model& m, int depth, int64_t n_leaves, const uint32_t* leaf_ids,
+                          const uint32_t* leaf_masks, const uint32_t* bitmap, const uint32_t* word_prefix,
+                          const float* corner_vals, const uint32_t* tri_offsets, float* tri_pos,
+                          uint64_t* tri_keys, int32_t* tri_iso, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
+
+// ---- marching-cubes case table (mc_table.cpp) ----
+struct McTable {
+  uint8_t count[256];       // triangles per case
+  int8_t edges[256][15];    // edge indices, 3 per triangle
+};
+const McTable& mc_table();
+
+}  // namespace isx

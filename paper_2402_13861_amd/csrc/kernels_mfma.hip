@@ -1,0 +1,289 @@
+// Hidden-layer coefficient products of the propagation on FP32 MFMA
+// (v_mfma_f32_32x32x2f32), with the ReLU rule fused into the epilogue.
+//
+// For one cell and one block of BM output neurons, the workgroup computes
+//   P = W[m0:m0+BM, :] * diag(alpha_{h-1}) * F_{h-1}   (all N = cols_in columns)
+// tile by tile (BN columns at a time, K streamed in chunks of KT through LDS;
+// alpha is applied, and beta added to the centre column, while the B tile is
+// staged), writes P as the next coefficient block (unless this is the last
+// hidden layer), accumulates each row's statistic (sum of squares for UP,
+// of absolute values for AA) over all columns, appends the new symbol block
+// W diag(gamma_{h-1}) with its statistic, and finally applies the ReLU rule
+// to each of its BM neurons.  The statistic is reduced in a fixed order
+// (lane butterflies, then waves in order), so results are deterministic.
+//
+// MFMA 32x32x2 f32 operand layout (lane l of a 64-wide wave): A element
+// (row l%32, k l/32), B element (k l/32, col l%32); accumulator register r
+// holds (row 8*(r/4) + 4*(l/32) + r%4, col l%32).
+//
+// Workgroups map to (cell, row block) so that the row blocks of one cell are
+// consecutive on the same XCD (blocks are dealt to the 8 XCDs round-robin),
+// letting the second row block find the cell's coefficients in that XCD's L2.
+#include "isx_internal.h"
+
+namespace isx {
+
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+template <int METHOD>
+__device__ __forceinline__ float mstat(float v) {
+  return METHOD == ISX_UP ? v * v : fabsf(v);
+}
+
+// same rule as the SIMT path (kept local to this translation unit)
+template <int METHOD>
+__device__ __forceinline__ void relu_rule_f32(float y, float stat, float& a, float& b, float& g) {
+  if (METHOD == ISX_UP) {
+    const float sigma = sqrtf(stat);
+    const float ay = fabsf(y);
+    if (!(sigma > 1e-30f * (ay > 1.f ? ay : 1.f))) {
+      a = y > 0.f ? 1.f : (y < 0.f ? 0.f : 0.5f);
+      b = 0.f;
+      g = 0.f;
+      return;
+    }
+    const float r = y / sigma;
+    const float Phi = 0.5f * erfcf(-r * 0.70710678118654752440f);
+    const float Q = 0.5f * erfcf(r * 0.70710678118654752440f);
+    const float phi = 0.39894228040143267794f * expf(-0.5f * r * r);
+    a = Phi;
+    b = sigma * phi;
+    const float g2 = sigma * sigma * ((r * r + 1.f) * Phi * Q + r * phi * (Q - Phi) - phi * phi);
+    g = g2 > 0.f ? sqrtf(g2) : 0.f;
+  } else {
+    const float l = y - stat, u = y + stat;
+    if (u <= 0.f) {
+      a = 0.f;
+      b = 0.f;
+      g = 0.f;
+    } else if (l >= 0.f) {
+      a = 1.f;
+      b = 0.f;
+      g = 0.f;
+    } else {
+      a = u / (u - l);
+      b = -a * l * 0.5f;
+      g = b;
+    }
+  }
+}
+
+template <int BM>
+struct Cfg {
+  static constexpr int NWAVES = 8;
+  static constexpr int THREADS = 64 * NWAVES;
+  static constexpr int WR = BM / 32;           // wave rows (32 neurons each)
+  static constexpr int WC = NWAVES / WR;       // wave columns
+  static constexpr int NB = BM == 128 ? 2 : 1; // 32-column MFMA blocks per wave
+  static constexpr int BN = 32 * NB * WC;      // columns per tile
+  static constexpr int KT = 32;                // K chunk
+  static constexpr int ASTR = BM;
+  static constexpr int BSTR = BN + 1;
+  static constexpr int G = THREADS / BM;       // thread groups in the generated-block pass
+};
+
+template <int METHOD, int BM>
+__global__ __launch_bounds__(512) void hidden_mfma_f32_kernel(
+    int64_t C, int n_in, int n_out, int64_t cols_in, int rb_count, const float* __restrict__ Wt,
+    const float* __restrict__ bias, const float* __restrict__ Fin, const float* __restrict__ Ain,
+    const float* __restrict__ Bin, const float* __restrict__ Gin, float* __restrict__ Fout, float* __restrict__ Y,
+    float* __restrict__ A, float* __restrict__ B, float* __restrict__ G) {
+  using K = Cfg<BM>;
+  __shared__ float As[K::KT * K::ASTR];
+  __shared__ float Bs[K::KT * K::BSTR];
+  __shared__ float s_alpha[ISX_MAX_WIDTH];
+  __shared__ float s_beta[ISX_MAX_WIDTH];
+  __shared__ float s_gamma[ISX_MAX_WIDTH];
+  __shared__ float s_y[BM];
+  __shared__ float s_stat[K::WC][BM];
+  __shared__ float s_gen[K::G][BM];
+
+  const int64_t blk = blockIdx.x;
+  const int xcd = (int)(blk & 7);
+  const int64_t q = blk >> 3;
+  const int rb = (int)(q % rb_count);
+  const int64_t cell = (q / rb_count) * 8 + xcd;
+  if (cell >= C) return;  // uniform for the whole workgroup
+  const int m0 = rb * BM;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wr = wave % K::WR, wc = wave / K::WR;
+  const int64_t cols_out = cols_in + n_in;
+  const float* fin = Fin + cell * cols_in * n_in;
+  float* fout = Fout ? Fout + cell * cols_out * n_out : nullptr;
+  for (int k = t; k < n_in; k += K::THREADS) {
+    s_alpha[k] = Ain[cell * n_in + k];
+    s_beta[k] = Bin[cell * n_in + k];
+    s_gamma[k] = Gin[cell * n_in + k];
+  }
+  __syncthreads();
+
+  float stat[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) stat[r] = 0.f;
+
+  const int64_t ntiles = (cols_in + K::BN - 1) / K::BN;
+  for (int64_t nt = 0; nt < ntiles; ++nt) {
+    const int64_t c0 = nt * K::BN;
+    const bool wave_active = c0 + wc * 32 * K::NB < cols_in;
+    v16f acc[K::NB];
+#pragma unroll
+    for (int nb = 0; nb < K::NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[nb][r] = 0.f;
+
+    for (int k0 = 0; k0 < n_in; k0 += K::KT) {
+      // stage A = W^T[k0:k0+KT, m0:m0+BM]
+      for (int idx = t; idx < K::KT * BM / 4; idx += K::THREADS) {
+        const int kk = idx / (BM / 4), mq = idx - kk * (BM / 4);
+        const float4 v = *reinterpret_cast<const float4*>(Wt + (int64_t)(k0 + kk) * n_out + m0 + 4 * mq);
+        *reinterpret_cast<float4*>(As + kk * K::ASTR + 4 * mq) = v;
+      }
+      // stage B = alpha . F[k0:k0+KT, c0:c0+BN] (+ beta on the centre column)
+      for (int idx = t; idx < K::KT * K::BN / 4; idx += K::THREADS) {
+        const int col = idx / (K::KT / 4), kq = idx - col * (K::KT / 4);
+        const int64_t gc = c0 + col;
+        const int k = k0 + 4 * kq;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (gc < cols_in) {
+          v = *reinterpret_cast<const float4*>(fin + gc * n_in + k);
+          v.x *= s_alpha[k];
+          v.y *= s_alpha[k + 1];
+          v.z *= s_alpha[k + 2];
+          v.w *= s_alpha[k + 3];
+          if (gc == 0) {
+            v.x += s_beta[k];
+            v.y += s_beta[k + 1];
+            v.z += s_beta[k + 2];
+            v.w += s_beta[k + 3];
+          }
+        }
+        Bs[(4 * kq + 0) * K::BSTR + col] = v.x;
+        Bs[(4 * kq + 1) * K::BSTR + col] = v.y;
+        Bs[(4 * kq + 2) * K::BSTR + col] = v.z;
+        Bs[(4 * kq + 3) * K::BSTR + col] = v.w;
+      }
+      __syncthreads();
+      if (wave_active) {
+#pragma unroll
+        for (int ks = 0; ks < K::KT / 2; ++ks) {
+          const int kr = 2 * ks + (lane >> 5);
+          const float a = As[kr * K::ASTR + wr * 32 + (lane & 31)];
+#pragma unroll
+          for (int nb = 0; nb < K::NB; ++nb) {
+            const float bv = Bs[kr * K::BSTR + wc * 32 * K::NB + nb * 32 + (lane & 31)];
+            acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bv, acc[nb], 0, 0, 0);
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (wave_active) {
+#pragma unroll
+      for (int nb = 0; nb < K::NB; ++nb) {
+        const int64_t col = c0 + wc * 32 * K::NB + nb * 32 + (lane & 31);
+        if (col < cols_in) {
+#pragma unroll
+          for (int q4 = 0; q4 < 4; ++q4) {
+            const int rl = wr * 32 + 8 * q4 + 4 * (lane >> 5);
+            float v0 = acc[nb][4 * q4 + 0], v1 = acc[nb][4 * q4 + 1];
+            float v2 = acc[nb][4 * q4 + 2], v3 = acc[nb][4 * q4 + 3];
+            if (col == 0) {
+              v0 += bias[m0 + rl + 0];
+              v1 += bias[m0 + rl + 1];
+              v2 += bias[m0 + rl + 2];
+              v3 += bias[m0 + rl + 3];
+              s_y[rl + 0] = v0;
+              s_y[rl + 1] = v1;
+              s_y[rl + 2] = v2;
+              s_y[rl + 3] = v3;
+            } else {
+              stat[4 * q4 + 0] += mstat<METHOD>(v0);
+              stat[4 * q4 + 1] += mstat<METHOD>(v1);
+              stat[4 * q4 + 2] += mstat<METHOD>(v2);
+              stat[4 * q4 + 3] += mstat<METHOD>(v3);
+            }
+            if (fout) *reinterpret_cast<float4*>(fout + col * n_out + m0 + rl) = make_float4(v0, v1, v2, v3);
+          }
+        }
+      }
+    }
+  }
+  // reduce each row's statistic over the 32 lanes holding its columns
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    float v = stat[r];
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 8);
+    v += __shfl_xor(v, 4);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 1);
+    stat[r] = v;
+  }
+  if ((lane & 31) == 0) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) s_stat[wc][wr * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)] = stat[r];
+  }
+  // new symbol block W diag(gamma_{h-1}) and its statistic
+  {
+    const int m = t % BM, g = t / BM;
+    float gs = 0.f;
+    for (int j = g; j < n_in; j += K::G) {
+      const float v = Wt[(int64_t)j * n_out + m0 + m] * s_gamma[j];
+      gs += mstat<METHOD>(v);
+      if (fout) fout[(cols_in + j) * n_out + m0 + m] = v;
+    }
+    s_gen[g][m] = gs;
+  }
+  __syncthreads();
+  if (t < BM) {
+    float tot = 0.f;
+#pragma unroll
+    for (int w = 0; w < K::WC; ++w) tot += s_stat[w][t];
+#pragma unroll
+    for (int g = 0; g < K::G; ++g) tot += s_gen[g][t];
+    float a, b, gg;
+    relu_rule_f32<METHOD>(s_y[t], tot, a, b, gg);
+    const int64_t o = cell * n_out + m0 + t;
+    Y[o] = s_y[t];
+    A[o] = a;
+    B[o] = b;
+    G[o] = gg;
+  }
+}
+
+bool mfma_supported(const Model& m) {
+  for (int h = 1; h < m.hidden(); ++h)
+    if (m.pw[h] % 32 != 0 || m.pw[h + 1] % 32 != 0 || m.pw[h] > ISX_MAX_WIDTH) return false;
+  return true;
+}
+
+template <int METHOD, int BM>
+static void launch_bm(int64_t C, int n_in, int n_out, int64_t cols_in, const float* Wt, const float* bias,
+                      const float* Fin, const float* Ain, const float* Bin, const float* Gin, float* Fout, float* Y,
+                      float* A, float* B, float* G, hipStream_t s) {
+  const int rb_count = n_out / BM;
+  const int64_t blocks = ((C + 7) / 8) * 8 * rb_count;
+  hipLaunchKernelGGL((hidden_mfma_f32_kernel<METHOD, BM>), dim3((unsigned)blocks), dim3(Cfg<BM>::THREADS), 0, s, C,
+                     n_in, n_out, cols_in, rb_count, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G);
+}
+
+hipError_t launch_hidden_mfma_f32(int method, int64_t C, int n_in, int n_out, int64_t cols_in, const float* Wt,
+                                  const float* bias, const float* Fin, const float* Ain, const float* Bin,
+                                  const float* Gin, float* Fout, float* Y, float* A, float* B, float* G,
+                                  hipStream_t s) {
+  if (C <= 0) return hipSuccess;
+  if (n_out % 32 != 0 || n_in % 32 != 0 || n_in > ISX_MAX_WIDTH) return hipErrorInvalidValue;
+  const int bm = n_out % 128 == 0 ? 128 : (n_out % 64 == 0 ? 64 : 32);
+  if (method == ISX_UP) {
+    if (bm == 128) launch_bm<ISX_UP, 128>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, s);
+    else if (bm == 64) launch_bm<ISX_UP, 64>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, s);
+    else launch_bm<ISX_UP, 32>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, s);
+  } else {
+    if (bm == 128) launch_bm<ISX_AA, 128>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, s);
+    else if (bm == 64) launch_bm<ISX_AA, 64>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, s);
+    else launch_bm<ISX_AA, 32>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, s);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace isx

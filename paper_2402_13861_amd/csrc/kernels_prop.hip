@@ -1,0 +1,515 @@
+// Propagation of boxes through a ReLU MLP: affine arithmetic (Sec. III,
+// Eq. 1-4) and uncertainty propagation with probabilistic affine forms
+// (Sec. IV-B/C, Eq. 6-10), plus plain MLP evaluation.
+//
+// Formulation (per cell).  The pre-activation form of hidden layer h is a
+// centre y_h [n_h] and a coefficient block F_h [n_h x N_h]; the linear rule
+// (Eq. 3 / Eq. 8) maps it exactly, and each ReLU (Eq. 4 / Eq. 9) replaces
+// neuron j by alpha_j x + beta_j plus a new symbol gamma_j Z_j.  So
+//   y_h   = W_h (alpha_{h-1} . y_{h-1} + beta_{h-1}) + b_h
+//   F_h   = [ W_h diag(alpha_{h-1}) F_{h-1} | W_h diag(gamma_{h-1}) ]
+// and the ReLU of layer h needs only the row statistic of F_h: the sum of
+// squares (UP: sigma^2, Eq. 7) or of absolute values (AA: r, Eq. 2).
+//   * alpha is applied when the next layer loads F (no extra pass);
+//   * the centre travels as column 0 of F (its B-load adds beta);
+//   * the last hidden layer only needs its row statistics, so its F is never
+//     written;
+//   * the output layer's coefficient of every symbol equals the product of
+//     the linearised layers above it (a row vector v propagated downward:
+//     v_L = w_out, v_{h-1} = (v_h . alpha_h) W_h), so the output spread is
+//     sum over layers and neurons of stat(v_h[j] gamma_h[j]) plus the input
+//     symbols' terms -- a few matrix-vector products per cell instead of
+//     another wide product.  Each symbol's output coefficient is the same
+//     number the forward tracking would give, so this is exact.
+#include "isx_internal.h"
+
+#include <algorithm>
+
+namespace isx {
+
+template <typename T>
+struct M;
+template <>
+struct M<float> {
+  static __device__ __forceinline__ float erfc_(float x) { return erfcf(x); }
+  static __device__ __forceinline__ float exp_(float x) { return expf(x); }
+  static __device__ __forceinline__ float sqrt_(float x) { return sqrtf(x); }
+  static __device__ __forceinline__ float abs_(float x) { return fabsf(x); }
+};
+template <>
+struct M<double> {
+  static __device__ __forceinline__ double erfc_(double x) { return erfc(x); }
+  static __device__ __forceinline__ double exp_(double x) { return exp(x); }
+  static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+  static __device__ __forceinline__ double abs_(double x) { return fabs(x); }
+};
+
+// ReLU linearisation from the pre-activation centre y and the row statistic
+// (UP: sum of squared coefficients; AA: sum of absolute coefficients).
+//  UP (Eq. 10, App. D ReLU row), r = y/sigma, Phi/phi standard normal cdf/pdf:
+//    alpha = Phi(r), beta = sigma phi(r),
+//    gamma^2 = sigma^2 [(r^2+1) Phi Q + r phi (Q - Phi) - phi^2], Q = 1 - Phi,
+//    with (1 - erf^2)/4 written as Phi*Q from erfc and the result clamped at 0;
+//    a zero-width input takes the exact limit (alpha = step(y), 1/2 at 0).
+//  AA (Eq. 4), hard range [l, u] = [y - r, y + r]: minimax line; for l < 0 < u
+//    alpha = u/(u-l), beta = gamma = -alpha l / 2; identity if l >= 0; 0 if u <= 0.
+template <typename T, int METHOD>
+__device__ __forceinline__ void relu_rule(T y, T stat, T& a, T& b, T& g) {
+  if (METHOD == ISX_UP) {
+    const T sigma = M<T>::sqrt_(stat);
+    const T ay = M<T>::abs_(y);
+    if (!(sigma > T(1e-30) * (ay > T(1) ? ay : T(1)))) {
+      a = y > T(0) ? T(1) : (y < T(0) ? T(0) : T(0.5));
+      b = T(0);
+      g = T(0);
+      return;
+    }
+    const T r = y / sigma;
+    const T Phi = T(0.5) * M<T>::erfc_(-r * T(0.70710678118654752440));
+    const T Q = T(0.5) * M<T>::erfc_(r * T(0.70710678118654752440));
+    const T phi = T(0.39894228040143267794) * M<T>::exp_(T(-0.5) * r * r);
+    a = Phi;
+    b = sigma * phi;
+    const T g2 = sigma * sigma * ((r * r + T(1)) * Phi * Q + r * phi * (Q - Phi) - phi * phi);
+    g = g2 > T(0) ? M<T>::sqrt_(g2) : T(0);
+  } else {
+    const T l = y - stat, u = y + stat;
+    if (u <= T(0)) {
+      a = T(0);
+      b = T(0);
+      g = T(0);
+    } else if (l >= T(0)) {
+      a = T(1);
+      b = T(0);
+      g = T(0);
+    } else {
+      a = u / (u - l);
+      b = -a * l * T(0.5);
+      g = b;
+    }
+  }
+}
+
+template <typename T, int METHOD>
+__device__ __forceinline__ T stat_term(T v) {
+  return METHOD == ISX_UP ? v * v : M<T>::abs_(v);
+}
+
+// ---------------------------------------------------------------- layer 1
+// Input form of a box (Sec. III-B / Sec. IV-C, Alg. 1 lines 1-3): centre c,
+// one symbol per axis with coefficient h_i (AA) or h_i/sqrt(3) (UP: a uniform
+// variable on [-h, h] has standard deviation h/sqrt 3).  One thread per
+// (cell, neuron).
+template <typename T, int METHOD>
+__global__ void layer1_kernel(int64_t C, int n, const float* __restrict__ centres,
+                              const float* __restrict__ halves, const T* __restrict__ W1,
+                              const T* __restrict__ b1, T* __restrict__ Fout, T* __restrict__ Y,
+                              T* __restrict__ A, T* __restrict__ B, T* __restrict__ G) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= C * n) return;
+  const int64_t cell = idx / n;
+  const int m = (int)(idx - cell * n);
+  const T s = METHOD == ISX_UP ? T(0.57735026918962576451) : T(1);
+  T f[3];
+  T y = b1[m];
+  T stat = T(0);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const T w = W1[m * 3 + i];
+    y += w * T(centres[cell * 3 + i]);
+    f[i] = w * (T(halves[cell * 3 + i]) * s);
+    stat += stat_term<T, METHOD>(f[i]);
+  }
+  T a, b, g;
+  relu_rule<T, METHOD>(y, stat, a, b, g);
+  Y[idx] = y;
+  A[idx] = a;
+  B[idx] = b;
+  G[idx] = g;
+  if (Fout) {
+    T* col = Fout + cell * (int64_t)kHeadCols * n + m;
+    col[0] = y;
+    col[(int64_t)1 * n] = f[0];
+    col[(int64_t)2 * n] = f[1];
+    col[(int64_t)3 * n] = f[2];
+#pragma unroll
+    for (int c = 4; c < kHeadCols; ++c) col[(int64_t)c * n] = T(0);
+  }
+}
+
+// ----------------------------------------------------- hidden layer (SIMT)
+// Reference kernel: one workgroup per cell, one thread per output neuron m;
+// the cell's columns stream through LDS in tiles of CT (alpha-scaled on load,
+// beta added to the centre column); thread m accumulates its full row
+// statistic, appends the new symbol block W diag(gamma_{h-1}), and applies
+// the ReLU rule.
+template <typename T, int METHOD, int CT>
+__global__ void hidden_simt_kernel(int64_t C, int n_in, int n_out, int64_t cols_in,
+                                   const T* __restrict__ Wt, const T* __restrict__ bias,
+                                   const T* __restrict__ Fin, const T* __restrict__ Ain,
+                                   const T* __restrict__ Bin, const T* __restrict__ Gin,
+                                   T* __restrict__ Fout, T* __restrict__ Y, T* __restrict__ A,
+                                   T* __restrict__ B, T* __restrict__ G) {
+  extern __shared__ unsigned char smem_raw[];
+  T* Bs = reinterpret_cast<T*>(smem_raw);  // [n_in][CT]
+  const int64_t cell = blockIdx.x;
+  const int m = threadIdx.x;
+  const bool act = m < n_out;
+  const int64_t cols_out = cols_in + n_in;
+  const T* fin = Fin + cell * cols_in * n_in;
+  T* fout = Fout ? Fout + cell * cols_out * n_out : nullptr;
+  const T* ain = Ain + cell * n_in;
+  const T* bin = Bin + cell * n_in;
+  const T* gin = Gin + cell * n_in;
+  const T bm = act ? bias[m] : T(0);
+  T y = T(0), stat = T(0);
+  for (int64_t c0 = 0; c0 < cols_in; c0 += CT) {
+    const int nc = (int)((cols_in - c0) < CT ? (cols_in - c0) : CT);
+    for (int i = threadIdx.x; i < CT * n_in; i += blockDim.x) {
+      const int col = i / n_in;
+      const int k = i - col * n_in;
+      T v = T(0);
+      if (col < nc) {
+        v = ain[k] * fin[(c0 + col) * n_in + k];
+        if (c0 + col == 0) v += bin[k];
+      }
+      Bs[k * CT + col] = v;
+    }
+    __syncthreads();
+    if (act) {
+      T acc[CT];
+#pragma unroll
+      for (int c = 0; c < CT; ++c) acc[c] = T(0);
+      for (int k = 0; k < n_in; ++k) {
+        const T w = Wt[(int64_t)k * n_out + m];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[c] += w * Bs[k * CT + c];
+      }
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        if (c < nc) {
+          const int64_t col = c0 + c;
+          T v = acc[c];
+          if (col == 0) {
+            v += bm;
+            y = v;
+          } else {
+            stat += stat_term<T, METHOD>(v);
+          }
+          if (fout) fout[col * n_out + m] = v;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (act) {
+    for (int j = 0; j < n_in; ++j) {
+      const T v = Wt[(int64_t)j * n_out + m] * gin[j];
+      stat += stat_term<T, METHOD>(v);
+      if (fout) fout[(cols_in + j) * n_out + m] = v;
+    }
+    T a, b, g;
+    relu_rule<T, METHOD>(y, stat, a, b, g);
+    const int64_t o = cell * n_out + m;
+    Y[o] = y;
+    A[o] = a;
+    B[o] = b;
+    G[o] = g;
+  }
+}
+
+// ------------------------------------------------------------ output layer
+// Output read-off (Eq. 2 for AA, Eq. 7 for UP) by the downward row vector
+// described at the top of this file.  One workgroup (256 threads) per cell.
+template <typename T, int METHOD>
+__global__ void output_kernel(int64_t C, NetView<T> net, const float* __restrict__ halves,
+                              float* __restrict__ out32, double* __restrict__ out64) {
+  __shared__ T v[ISX_MAX_WIDTH];
+  __shared__ T u[ISX_MAX_WIDTH];
+  __shared__ T red[2][256 / 64];
+  const int64_t cell = blockIdx.x;
+  const int t = threadIdx.x;
+  const int L = net.n_linear;
+  const int Lh = L - 1;
+  const int nL = net.n[Lh];
+  const T* wout = net.W[L - 1];
+  T mu_p = T(0), acc_p = T(0);
+  {
+    const T* Yh = net.Y[Lh] + cell * nL;
+    const T* Ah = net.A[Lh] + cell * nL;
+    const T* Bh = net.B[Lh] + cell * nL;
+    const T* Gh = net.G[Lh] + cell * nL;
+    for (int j = t; j < nL; j += blockDim.x) {
+      const T w = wout[j];
+      mu_p += w * (Ah[j] * Yh[j] + Bh[j]);
+      acc_p += stat_term<T, METHOD>(w * Gh[j]);
+      v[j] = w;
+    }
+  }
+  __syncthreads();
+  for (int h = Lh; h >= 2; --h) {
+    const int nh = net.n[h], np = net.n[h - 1];
+    const T* Ah = net.A[h] + cell * nh;
+    for (int j = t; j < nh; j += blockDim.x) u[j] = v[j] * Ah[j];
+    __syncthreads();
+    const T* Wl = net.W[h - 1];  // [nh][np]
+    const T* Gp = net.G[h - 1] + cell * np;
+    for (int i = t; i < np; i += blockDim.x) {
+      T s = T(0);
+      for (int j = 0; j < nh; ++j) s += u[j] * Wl[(int64_t)j * np + i];
+      v[i] = s;
+      acc_p += stat_term<T, METHOD>(s * Gp[i]);
+    }
+    __syncthreads();
+  }
+  {
+    const int n1 = net.n[1];
+    const T* A1 = net.A[1] + cell * n1;
+    for (int j = t; j < n1; j += blockDim.x) u[j] = v[j] * A1[j];
+    __syncthreads();
+    if (t < 3) {
+      const T* W0 = net.W[0];  // [n1][3]
+      T s = T(0);
+      for (int j = 0; j < n1; ++j) s += u[j] * W0[j * 3 + t];
+      const T sc = METHOD == ISX_UP ? T(0.57735026918962576451) : T(1);
+      acc_p += stat_term<T, METHOD>(s * (T(halves[cell * 3 + t]) * sc));
+    }
+  }
+  // block reduction of (mu_p, acc_p)
+  for (int off = 32; off > 0; off >>= 1) {
+    mu_p += __shfl_xor(mu_p, off);
+    acc_p += __shfl_xor(acc_p, off);
+  }
+  const int wave = t >> 6;
+  if ((t & 63) == 0) {
+    red[0][wave] = mu_p;
+    red[1][wave] = acc_p;
+  }
+  __syncthreads();
+  if (t == 0) {
+    T mu = T(0), acc = T(0);
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      mu += red[0][w];
+      acc += red[1][w];
+    }
+    mu += net.b[L - 1][0];
+    const T spread = METHOD == ISX_UP ? M<T>::sqrt_(acc) : acc;
+    out32[cell * 2 + 0] = (float)mu;
+    out32[cell * 2 + 1] = (float)spread;
+    if (out64) {
+      out64[cell * 2 + 0] = (double)mu;
+      out64[cell * 2 + 1] = (double)spread;
+    }
+  }
+}
+
+// ------------------------------------------------------- MLP evaluation
+// Plain forward pass (Sec. III-B) on tiles of PT points; one thread per
+// neuron, activations of the tile in LDS.
+template <typename T, int PT>
+__global__ void mlp_eval_kernel(int64_t n, NetView<T> net, int n_max, const float* __restrict__ pts,
+                                float* __restrict__ vals) {
+  extern __shared__ unsigned char smem_raw[];
+  T* h0 = reinterpret_cast<T*>(smem_raw);  // [n_max][PT]
+  T* h1 = h0 + (size_t)n_max * PT;
+  const int64_t p0 = (int64_t)blockIdx.x * PT;
+  const int t = threadIdx.x;
+  for (int i = t; i < 3 * PT; i += blockDim.x) {
+    const int p = i / 3, a = i - p * 3;
+    h0[a * PT + p] = (p0 + p < n) ? T(pts[(p0 + p) * 3 + a]) : T(0);
+  }
+  __syncthreads();
+  T* hin = h0;
+  T* hout = h1;
+  for (int l = 0; l < net.n_linear; ++l) {
+    const int ni = net.n[l], no = net.n[l + 1];
+    const T* W = net.W[l];
+    for (int m = t; m < no; m += blockDim.x) {
+      T acc[PT];
+      const T bm = net.b[l][m];
+#pragma unroll
+      for (int p = 0; p < PT; ++p) acc[p] = bm;
+      for (int k = 0; k < ni; ++k) {
+        const T w = W[(int64_t)m * ni + k];
+#pragma unroll
+        for (int p = 0; p < PT; ++p) acc[p] += w * hin[k * PT + p];
+      }
+      const bool relu = l + 1 < net.n_linear;
+#pragma unroll
+      for (int p = 0; p < PT; ++p) hout[m * PT + p] = relu ? (acc[p] > T(0) ? acc[p] : T(0)) : acc[p];
+    }
+    __syncthreads();
+    T* tmp = hin;
+    hin = hout;
+    hout = tmp;
+  }
+  if (t < PT && p0 + t < n) vals[p0 + t] = (float)hin[t];
+}
+
+// ================================================================ host side
+size_t prop_F_elems(const Model& m, int64_t C) {
+  size_t best = 1;
+  for (int h = 1; h < m.hidden(); ++h) best = std::max(best, (size_t)(m.cols(h) * m.pw[h]));
+  return best * (size_t)C;
+}
+
+size_t prop_vec_elems(const Model& m, int64_t C) {
+  size_t s = 0;
+  for (int h = 1; h <= m.hidden(); ++h) s += 4 * (size_t)m.pw[h];
+  return s * (size_t)C;
+}
+
+template <typename T>
+static void layer_ptrs(const Model& m, int64_t C, T* vec, T** Y, T** A, T** B, T** G) {
+  size_t off = 0;
+  for (int h = 1; h <= m.hidden(); ++h) {
+    const size_t n = (size_t)m.pw[h] * C;
+    Y[h] = vec + off;
+    A[h] = vec + off + n;
+    B[h] = vec + off + 2 * n;
+    G[h] = vec + off + 3 * n;
+    off += 4 * n;
+  }
+}
+
+template <typename T>
+static const T* wptr(const Layer& l);
+template <>
+const float* wptr<float>(const Layer& l) {
+  return l.W;
+}
+template <>
+const double* wptr<double>(const Layer& l) {
+  return l.Wd;
+}
+template <typename T>
+static const T* wtptr(const Layer& l);
+template <>
+const float* wtptr<float>(const Layer& l) {
+  return l.Wt;
+}
+template <>
+const double* wtptr<double>(const Layer& l) {
+  return l.Wtd;
+}
+template <typename T>
+static const T* bptr(const Layer& l);
+template <>
+const float* bptr<float>(const Layer& l) {
+  return l.b;
+}
+template <>
+const double* bptr<double>(const Layer& l) {
+  return l.bd;
+}
+
+template <typename T>
+static NetView<T> make_view(const Model& m) {
+  NetView<T> v{};
+  v.n_linear = m.n_linear;
+  for (int i = 0; i <= m.n_linear; ++i) v.n[i] = m.pw[i];
+  for (int l = 0; l < m.n_linear; ++l) {
+    v.W[l] = wptr<T>(m.L[l]);
+    v.b[l] = bptr<T>(m.L[l]);
+  }
+  return v;
+}
+
+hipError_t launch_hidden_mfma_f32(int method, int64_t C, int n_in, int n_out, int64_t cols_in, const float* Wt,
+                                  const float* bias, const float* Fin, const float* Ain, const float* Bin,
+                                  const float* Gin, float* Fout, float* Y, float* A, float* B, float* G,
+                                  hipStream_t s);
+bool mfma_supported(const Model& m);
+
+template <typename T>
+static hipError_t hidden_mfma(int, int64_t, int, int, int64_t, const T*, const T*, const T*, const T*, const T*,
+                              const T*, T*, T*, T*, T*, T*, hipStream_t) {
+  return hipErrorNotSupported;
+}
+template <>
+hipError_t hidden_mfma<float>(int method, int64_t C, int n_in, int n_out, int64_t cols_in, const float* Wt,
+                              const float* bias, const float* Fin, const float* Ain, const float* Bin,
+                              const float* Gin, float* Fout, float* Y, float* A, float* B, float* G, hipStream_t s) {
+  return launch_hidden_mfma_f32(method, C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, s);
+}
+
+template <typename T, int METHOD>
+static hipError_t propagate_impl(const PropArgs& a, PropWork<T>& w, bool use_mfma) {
+  const Model& m = *a.m;
+  const int Lh = m.hidden();
+  const int64_t C = a.C;
+  T *Y[ISX_MAX_LINEAR] = {}, *A[ISX_MAX_LINEAR] = {}, *B[ISX_MAX_LINEAR] = {}, *G[ISX_MAX_LINEAR] = {};
+  layer_ptrs<T>(m, C, w.vec, Y, A, B, G);
+  int cur = 0;
+  {
+    const int n1 = m.pw[1];
+    const int64_t threads = C * n1;
+    const int bs = 256;
+    hipLaunchKernelGGL((layer1_kernel<T, METHOD>), dim3((unsigned)((threads + bs - 1) / bs)), dim3(bs), 0,
+                       a.stream, C, n1, a.centres, a.halves, wptr<T>(m.L[0]), bptr<T>(m.L[0]),
+                       Lh >= 2 ? w.F[cur] : (T*)nullptr, Y[1], A[1], B[1], G[1]);
+  }
+  for (int h = 2; h <= Lh; ++h) {
+    const int n_in = m.pw[h - 1], n_out = m.pw[h];
+    const int64_t cols_in = m.cols(h - 1);
+    T* Fout = h < Lh ? w.F[cur ^ 1] : nullptr;
+    if (use_mfma) {
+      hipError_t e = hidden_mfma<T>(METHOD, C, n_in, n_out, cols_in, wtptr<T>(m.L[h - 1]), bptr<T>(m.L[h - 1]),
+                                    w.F[cur], A[h - 1], B[h - 1], G[h - 1], Fout, Y[h], A[h], B[h], G[h], a.stream);
+      if (e != hipSuccess) return e;
+    } else {
+      constexpr int CT = sizeof(T) == 8 ? 8 : 16;
+      const int bs = std::max(64, (n_out + 63) / 64 * 64);
+      const size_t lds = (size_t)CT * n_in * sizeof(T);
+      hipLaunchKernelGGL((hidden_simt_kernel<T, METHOD, CT>), dim3((unsigned)C), dim3(bs), lds, a.stream, C, n_in,
+                         n_out, cols_in, wtptr<T>(m.L[h - 1]), bptr<T>(m.L[h - 1]), w.F[cur], A[h - 1], B[h - 1],
+                         G[h - 1], Fout, Y[h], A[h], B[h], G[h]);
+    }
+    cur ^= 1;
+  }
+  NetView<T> view = make_view<T>(m);
+  for (int h = 1; h <= Lh; ++h) {
+    view.Y[h] = Y[h];
+    view.A[h] = A[h];
+    view.B[h] = B[h];
+    view.G[h] = G[h];
+  }
+  hipLaunchKernelGGL((output_kernel<T, METHOD>), dim3((unsigned)C), dim3(256), 0, a.stream, C, view, a.halves,
+                     a.out32, a.out64);
+  return hipGetLastError();
+}
+
+hipError_t propagate_f32(const PropArgs& a, PropWork<float>& w) {
+  if (a.C <= 0) return hipSuccess;
+  const bool use_mfma = a.kernel_choice != 1 && mfma_supported(*a.m);
+  return a.method == ISX_UP ? propagate_impl<float, ISX_UP>(a, w, use_mfma)
+                            : propagate_impl<float, ISX_AA>(a, w, use_mfma);
+}
+
+hipError_t propagate_f64(const PropArgs& a, PropWork<double>& w) {
+  if (a.C <= 0) return hipSuccess;
+  return a.method == ISX_UP ? propagate_impl<double, ISX_UP>(a, w, false)
+                            : propagate_impl<double, ISX_AA>(a, w, false);
+}
+
+template <typename T, int PT>
+static hipError_t eval_points_t(const Model& m, int64_t n, const float* pts, float* vals, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int n_max = 3;
+  for (int i = 0; i <= m.n_linear; ++i) n_max = std::max(n_max, m.pw[i]);
+  const int bs = std::min(1024, std::max(64, (n_max + 63) / 64 * 64));
+  const size_t lds = 2 * (size_t)n_max * PT * sizeof(T);
+  NetView<T> view = make_view<T>(m);
+  hipLaunchKernelGGL((mlp_eval_kernel<T, PT>), dim3((unsigned)((n + PT - 1) / PT)), dim3(bs), lds, s, n, view,
+                     n_max, pts, vals);
+  return hipGetLastError();
+}
+
+hipError_t eval_points_f32(const Model& m, int64_t n, const float* pts, float* vals, hipStream_t s) {
+  return eval_points_t<float, 8>(m, n, pts, vals, s);
+}
+hipError_t eval_points_f64(const Model& m, int64_t n, const float* pts, float* vals, hipStream_t s) {
+  return eval_points_t<double, 4>(m, n, pts, vals, s);
+}
+
+}  // namespace isx

@@ -1,0 +1,283 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Tolerances: float32 bounds (centre and centre -/+ k spread) within 1e-5
+relative to max(|o|, S), S the output scale, with the spread itself within
+1e-4 relative; float64 results within 1e-10 (1e-9 on the spread); integer
+results (classification masks, compaction order, active sets) exact, except
+active-set differences in cells that are -- or descend from -- cells whose
+oracle bound endpoint lies within 1e-4 S of an iso-value; triangle vertices
+within 1e-4 on shared grid edges.
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import mc
+from oracle.mlp import mlp_forward
+from oracle.octree import extract_active
+from oracle.propagate import AA, UP, propagate
+from workloads import he_normal_mlp, random_boxes, uniform_points
+
+from _parity import assert_pair_close, close_sets, leaf_ijk, output_scale, unexcused_level_diffs
+
+pytestmark = pytest.mark.gpu
+
+METHODS = {"up": (UP, 1), "aa": (AA, 0)}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2402_13861_amd as isx
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    c = isx.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def _dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+def _gpu_prop(ctx, mid, method, precision, c, h, kernel=None):
+    import paper_2402_13861_amd as isx
+
+    if kernel is not None:
+        ctx.set_option(isx.HIDDEN_KERNEL, kernel)
+    n = c.shape[0]
+    out = torch.full((n, 2), float("nan"), dtype=torch.float32, device="cuda")
+    out64 = torch.full((n, 2), float("nan"), dtype=torch.float64, device="cuda") if precision == isx.FP64 else None
+    ctx.propagate(mid, method, precision, _dev(c), _dev(h), out, out64)
+    torch.cuda.synchronize()
+    if kernel is not None:
+        ctx.set_option(isx.HIDDEN_KERNEL, 0)
+    return out.cpu().numpy(), (out64.cpu().numpy() if out64 is not None else None)
+
+
+WIDTHS = [
+    [3, 64, 64, 64, 1],  # 3->64x3->1 ReLU with He-normal weights (seed 0)
+    [3, 32, 32, 1],
+    [3, 48, 40, 1],  # hidden widths not multiples of 32 (padding path)
+    [3, 128, 128, 128, 128, 1],
+    [3, 256, 256, 256, 1],
+]
+
+
+@pytest.mark.parametrize("widths", WIDTHS, ids=lambda w: "x".join(map(str, w)))
+@pytest.mark.parametrize("mname", ["up", "aa"])
+def test_propagate_fp32_and_fp64_match_oracle(ctx, widths, mname):
+    import paper_2402_13861_amd as isx
+
+    method, gm = METHODS[mname]
+    mlp = he_normal_mlp(widths, seed=0)
+    mid = ctx.load_weights(mlp)
+    try:
+        c, h, _ = random_boxes(257, range(0, 10), seed=11)
+        ref = propagate(mlp, c, h, method)
+        S = output_scale(mlp)
+        k = 3.0 if mname == "up" else 1.0
+        g32, _ = _gpu_prop(ctx, mid, gm, isx.FP32, c, h)
+        assert_pair_close(g32, ref, S, 1e-5, f"fp32 {mname} {widths}", k=k)
+        _, g64 = _gpu_prop(ctx, mid, gm, isx.FP64, c, h)
+        assert_pair_close(g64, ref, S, 1e-10, f"fp64 {mname} {widths}", k=k)
+        g32s, _ = _gpu_prop(ctx, mid, gm, isx.FP32, c, h, kernel=1)
+        assert_pair_close(g32s, ref, S, 1e-5, f"fp32 simt {mname} {widths}", k=k)
+    finally:
+        ctx.unload_mlp(mid)
+
+
+def test_propagate_edge_cases(ctx):
+    import paper_2402_13861_amd as isx
+
+    mlp = he_normal_mlp([3, 64, 64, 1], seed=3)
+    mid = ctx.load_weights(mlp)
+    try:
+        # empty batch is a no-op
+        ctx.propagate(mid, isx.UP, isx.FP32, torch.zeros((0, 3), device="cuda"), torch.zeros((0, 3), device="cuda"),
+                      torch.zeros((0, 2), device="cuda"))
+        # a single box, a huge box, tiny boxes, anisotropic boxes
+        c = np.array([[0.1, 0.2, -0.3], [0.0, 0.0, 0.0], [0.5, -0.5, 0.25], [-0.2, 0.3, 0.9]], dtype=np.float32)
+        h = np.array([[0.5, 0.5, 0.5], [4.0, 4.0, 4.0], [1e-6, 1e-6, 1e-6], [0.01, 0.3, 0.002]], dtype=np.float32)
+        S = output_scale(mlp)
+        for mname in ("up", "aa"):
+            method, gm = METHODS[mname]
+            ref = propagate(mlp, c, h, method)
+            g, _ = _gpu_prop(ctx, mid, gm, isx.FP32, c, h)
+            assert_pair_close(g, ref, S, 1e-5, f"edge {mname}", k=3.0 if mname == "up" else 1.0)
+        # chunked launch: a batch much larger than one chunk gives the same answers
+        c2, h2, _ = random_boxes(3000, range(0, 9), seed=4)
+        a, _ = _gpu_prop(ctx, mid, isx.UP, isx.FP32, c2, h2)
+        b, _ = _gpu_prop(ctx, mid, isx.UP, isx.FP32, c2[1000:2000], h2[1000:2000])
+        np.testing.assert_array_equal(a[1000:2000], b)
+    finally:
+        ctx.unload_mlp(mid)
+
+
+def test_propagate_is_deterministic(ctx):
+    import paper_2402_13861_amd as isx
+
+    mlp = he_normal_mlp([3, 128, 128, 128, 1], seed=5)
+    mid = ctx.load_weights(mlp)
+    try:
+        c, h, _ = random_boxes(500, range(0, 10), seed=6)
+        a, _ = _gpu_prop(ctx, mid, isx.UP, isx.FP32, c, h)
+        b, _ = _gpu_prop(ctx, mid, isx.UP, isx.FP32, c, h)
+        np.testing.assert_array_equal(a, b)
+    finally:
+        ctx.unload_mlp(mid)
+
+
+def test_eval_points_match_oracle(ctx):
+    import paper_2402_13861_amd as isx
+
+    mlp = he_normal_mlp([3, 256, 256, 256, 1], seed=7)
+    mid = ctx.load_weights(mlp)
+    try:
+        x = uniform_points(5003, seed=8).astype(np.float32)
+        ref = mlp_forward(mlp, x.astype(np.float64))
+        S = float(ref.std())
+        for prec, tol in ((isx.FP32, 1e-5), (isx.FP64, 1e-12)):
+            v = torch.empty(x.shape[0], dtype=torch.float32, device="cuda")
+            ctx.eval_points(mid, prec, _dev(x), v)
+            torch.cuda.synchronize()
+            err = np.abs(v.cpu().numpy() - ref) / np.maximum(np.abs(ref), S)
+            print(f"eval prec={prec} max rel err {err.max():.3e}", flush=True)
+            # float64 eval is rounded to float32 on output
+            assert err.max() <= max(tol, 6e-8 if prec == isx.FP64 else tol)
+    finally:
+        ctx.unload_mlp(mid)
+
+
+def test_classify_compact_bit_exact(ctx):
+    rng = np.random.default_rng(9)
+    n = 20_011  # several scan tiles and a ragged tail
+    out = np.stack([rng.normal(0, 1, n), np.abs(rng.normal(0, 0.5, n))], 1).astype(np.float32)
+    out[::97, 1] = 0.0  # zero spread
+    isos = np.array([-0.5, 0.0, 0.7], dtype=np.float32)
+    # put some bounds exactly on an iso-value (closed interval keeps them)
+    out[5, 0], out[5, 1] = np.float32(0.2), np.float32(0.5)
+    pmask = rng.integers(0, 8, n).astype(np.uint32)
+    mlp = he_normal_mlp([3, 32, 32, 1], seed=0)
+    mid = ctx.load_weights(mlp)
+    try:
+        ctx.set_isovalues(mid, isos)
+        for k in (1.0, 3.0):
+            idx, msk, cnt = ctx.classify_compact(mid, k, _dev(out), _dev(pmask.view(np.int32), torch.int32))
+            torch.cuda.synchronize()
+            c32, s32, k32 = out[:, 0], out[:, 1], np.float32(k)
+            ks = (k32 * s32).astype(np.float32)
+            lo = (c32 - ks).astype(np.float32)
+            hi = (c32 + ks).astype(np.float32)
+            bits = np.zeros(n, dtype=np.uint32)
+            for j, cj in enumerate(isos):
+                bits |= ((lo <= cj) & (cj <= hi)).astype(np.uint32) << np.uint32(j)
+            bits &= pmask
+            want_idx = np.nonzero(bits)[0]
+            m = int(cnt.item())
+            assert m == want_idx.size
+            np.testing.assert_array_equal(idx[:m].cpu().numpy().astype(np.int64), want_idx)
+            np.testing.assert_array_equal(msk[:m].cpu().numpy().view(np.uint32), bits[want_idx])
+        # empty input
+        idx, msk, cnt = ctx.classify_compact(mid, 3.0, torch.zeros((0, 2), device="cuda"))
+        torch.cuda.synchronize()
+        assert int(cnt.item()) == 0
+    finally:
+        ctx.unload_mlp(mid)
+
+
+def _gpu_levels(mesh):
+    return [mesh.level_cells(L) for L in range(mesh.n_levels)]
+
+
+@pytest.mark.parametrize("mname,prec_name", [("up", "fp32"), ("aa", "fp32"), ("up", "fp64")])
+def test_extract_matches_oracle_cfg1(ctx, mname, prec_name):
+    """3->64x3->1 He-normal (seed 0), iso = median over 10^4 points, depth 5/6."""
+    import paper_2402_13861_amd as isx
+
+    method, gm = METHODS[mname]
+    prec = {"fp32": isx.FP32, "fp64": isx.FP64}[prec_name]
+    depth = 6 if (mname == "up" and prec_name == "fp32") else 5
+    mlp = he_normal_mlp([3, 64, 64, 64, 1], seed=0)
+    vals = mlp_forward(mlp, uniform_points(10_000, seed=1))
+    iso = [float(np.float32(np.median(vals)))]
+    S = float(vals.std())
+    mid = ctx.load_weights(mlp)
+    try:
+        ctx.set_isovalues(mid, iso)
+        ctx.set_option(isx.KEEP_LEVELS, 1)
+        mesh = ctx.extract(mid, gm, prec, k=3.0, max_depth=depth)
+        ctx.set_option(isx.KEEP_LEVELS, 0)
+        gl = _gpu_levels(mesh)
+        ol = extract_active(mlp, method, iso, depth, k=3.0)
+        close = close_sets(ol, method, 3.0, iso, S)
+        bad = unexcused_level_diffs(gl, ol, close)
+        print("levels gpu", [l["active"] for l in mesh.levels()], "oracle",
+              [int((l["mask"] != 0).sum()) for l in ol], flush=True)
+        assert not bad, bad
+        # leaves
+        g_ids, g_masks = mesh.leaves()
+        o_leaf = ol[-1]["ids"][ol[-1]["mask"] != 0]
+        common = np.intersect1d(g_ids.astype(np.uint64), o_leaf)
+        # triangles on the common leaves: compare vertices per edge key
+        pos, keys, tiso = mesh.triangles()
+        ijk = leaf_ijk(o_leaf)
+        ov = mc.corner_values(lambda p: mlp_forward(mlp, p), ijk, depth)
+        ot = mc.march(ijk, ov, iso[0], depth)
+        gmap = {}
+        for t in range(keys.shape[0]):
+            for q in range(3):
+                gmap[int(keys[t, q])] = pos[t, q]
+        omap = {}
+        for t in range(ot["keys"].shape[0]):
+            for q in range(3):
+                omap[int(ot["keys"][t, q])] = ot["pos"][t, q]
+        shared = set(gmap) & set(omap)
+        assert len(shared) > 0.95 * min(len(gmap), len(omap))
+        dv = max(float(np.abs(gmap[e] - omap[e]).max()) for e in shared)
+        print(f"triangles gpu {pos.shape[0]} oracle {ot['keys'].shape[0]}; leaves gpu {g_ids.size} oracle "
+              f"{o_leaf.size} common {common.size}; max vertex diff {dv:.2e}", flush=True)
+        assert dv <= 1e-4
+    finally:
+        ctx.unload_mlp(mid)
+
+
+def test_extract_aa_surface_equals_dense_oracle(ctx):
+    """AA is sound: the hierarchical surface equals the brute-force dense
+    surface (same triangles on the same grid edges)."""
+    import paper_2402_13861_amd as isx
+
+    mlp = he_normal_mlp([3, 32, 32, 1], seed=3)
+    depth = 5
+    vals = mlp_forward(mlp, uniform_points(4000, seed=1))
+    iso = float(np.float32(np.median(vals)))
+    mid = ctx.load_weights(mlp)
+    try:
+        ctx.set_isovalues(mid, [iso])
+        mesh = ctx.extract(mid, isx.AA, isx.FP64, k=1.0, max_depth=depth)
+        pos, keys, _ = mesh.triangles()
+        grid = mc.dense_grid(lambda p: mlp_forward(mlp, p), depth)
+        ijk, cv = mc.dense_cells(grid)
+        act = mc.iso_voxels(cv, iso)
+        dense = mc.march(ijk[act], cv[act], iso, depth)
+        gk = sorted(tuple(sorted(map(int, t))) for t in keys)
+        dk = sorted(tuple(sorted(map(int, t))) for t in dense["keys"])
+        assert gk == dk
+    finally:
+        ctx.unload_mlp(mid)
+
+
+def test_extract_capacity_error(ctx):
+    import paper_2402_13861_amd as isx
+
+    mlp = he_normal_mlp([3, 32, 32, 1], seed=3)
+    mid = ctx.load_weights(mlp)
+    try:
+        ctx.set_isovalues(mid, [0.0])
+        with pytest.raises(isx.IsxError) as e:
+            ctx.extract(mid, isx.AA, isx.FP32, k=1.0, max_depth=6, max_cells=16)
+        assert e.value.status == -4
+    finally:
+        ctx.unload_mlp(mid)
