@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Benchmark of hierarchical iso-surface extraction on one MI355X.
+
+Workload (default): ReLU MLP 3->256x5->1 fitted to a synthetic Fourier field
+(k^-5/3 spectrum), octree to depth 9 (512^3 effective resolution), iso-values
+at the 25/50/75 % output quantiles, uncertainty propagation with t = 3 and a
+float64 re-check band of 1e-3 S.  One step = one full extraction (every octree
+level: propagation, classification, compaction; then leaf-corner evaluation
+and marching cubes), with the weights resident and nothing cached between
+steps.
+
+Prints one JSON line (stdout).  Progress goes to stderr.
+
+    python bench.py [--steps K] [--warmup W] [--precision fp32|bf16]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+from pathlib import Path
+
+ROOT = Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+METRIC = "iso-surface ms @512³, cells/s; plain vs BF16+surrogate at ≥99.9% cell recall"
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp64": 78.6}
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    src = ROOT / "paper_2402_13861_amd" / "csrc" / "kernels_mfma.hip"
+    return hashlib.sha256(src.read_bytes()).hexdigest()[:16]
+
+
+def traffic_from_profiles(precision: str, flops_per_launch: float):
+    """HBM bytes per launch of the dominant kernel from committed rocprofv3
+    counter summaries, if they were taken on the current kernel source."""
+    f = ROOT / "profiles" / f"hidden_layer_{precision}_traffic.json"
+    if not f.exists():
+        return None
+    t = json.loads(f.read_text())
+    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(mlp, levels, budget_s: float):
+    """The float64 oracle on a bounded sample: random cells drawn level by
+    level in proportion to the GPU run's propagated cells, timed on the host;
+    the extraction time is extrapolated from that rate."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle.propagate import UP, propagate
+    from workloads import random_boxes
+
+    counts = np.array([l["cells"] for l in levels], dtype=np.float64)
+    total = counts.sum()
+    p = counts / total
+    rng = np.random.default_rng(0)
+    done, t_used = 0, 0.0
+    batch = 16
+    while t_used < budget_s:
+        lv = int(rng.choice(len(p), p=p))
+        c, h, _ = random_boxes(batch, [lv], seed=int(rng.integers(1 << 30)))
+        t0 = time.perf_counter()
+        propagate(mlp, c, h, UP)
+        t_used += time.perf_counter() - t0
+        done += batch
+    rate = done / t_used
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    return rate, done, t_used, threads, total
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--workload", default="relu256x5_fourier")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--depth", type=int, default=None)
+    ap.add_argument("--cpu-baseline-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    a = ap.parse_args(argv)
+
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2402_13861_amd as isx
+    from workloads.configs import WORKLOADS, isovalues, load_mlp
+
+    w = WORKLOADS[a.workload]
+    depth = a.depth if a.depth is not None else w["depth"]
+    mlp = load_mlp(a.workload)
+    isos, S = isovalues(a.workload)
+    prec = {"fp32": isx.FP32, "bf16": isx.BF16}[a.precision]
+    band = w.get("band_rel", 0.0) * S
+    log(f"bench: {a.workload} widths {mlp.widths} depth {depth} isos {isos} precision {a.precision} band {band:.3g}")
+
+    ctx = isx.Context(0)
+    ctx.set_option(isx.SCRATCH_BYTES, 48 << 30)
+    ctx.set_option(isx.VERBOSE, 1)
+    mid = ctx.load_weights(mlp)
+    ctx.set_isovalues(mid, isos)
+    kw = dict(method=isx.UP, precision=prec, k=w["k"], max_depth=depth, fp64_band=band)
+
+    for i in range(a.warmup):
+        t0 = time.perf_counter()
+        m = ctx.extract(mid, **kw)
+        log(f"warmup {i}: {1e3 * (time.perf_counter() - t0):.1f} ms, {m.n_leaves} leaves, {m.n_tris} triangles")
+        m.free()
+
+    ctx.set_option(isx.PROFILE, 1)
+    ctx.profile(reset=True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    runs = []
+    for i in range(a.steps):
+        t0 = time.perf_counter()
+        m = ctx.extract(mid, **kw)
+        dt = time.perf_counter() - t0
+        runs.append(dict(wall_s=dt, levels=m.levels(), times=m.times(), leaves=m.n_leaves, tris=m.n_tris,
+                         corners=m.n_corners))
+        log(f"step {i}: {1e3 * dt:.1f} ms, leaves {m.n_leaves}, triangles {m.n_tris}, corners {m.n_corners}, "
+            f"phases {m.times()}")
+        m.free()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    prof = ctx.profile(reset=True)
+    ctx.set_option(isx.PROFILE, 0)
+
+    K = a.steps
+    eff_cells = float((1 << depth) ** 3)
+    ms_per_step = 1e3 * elapsed / K
+    value = eff_cells * K / elapsed
+    levels = runs[-1]["levels"]
+    propagated = sum(l["cells"] for l in levels)
+    acp_s = np.mean([r["times"]["acp_ms"] for r in runs]) / 1e3
+    log("levels:", [(l["cells"], l["active"], l["rechecked"]) for l in levels])
+
+    launches = max(prof["launches"], 1)
+    avg_ms = prof["ms"] / launches
+    flops_per_launch = prof["flops"] / launches
+    achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+    peak = PEAK_TFLOPS[a.precision]
+    traffic = traffic_from_profiles(a.precision, flops_per_launch)
+    roofline = {
+        "bound": "mfma",
+        "kernel": "hidden_mfma_f32_kernel" if a.precision == "fp32" else "hidden_mfma_bf16_kernel",
+        "achieved": round(achieved, 3),
+        "peak": peak,
+        "unit": "TFLOP/s",
+        "frac": round(achieved / peak, 4),
+        "traffic": traffic,
+        "launches": prof["launches"],
+        "avg_launch_ms": round(avg_ms, 4),
+        "flops_per_launch": flops_per_launch,
+        "alg_bytes_per_launch": prof["bytes"] / launches,
+        "alg_hbm_GBps": round(prof["bytes"] / launches / (avg_ms * 1e-3) / 1e9, 1) if avg_ms > 0 else 0.0,
+    }
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        rate, done, t_used, threads, total = cpu_baseline(mlp, levels, a.cpu_baseline_seconds)
+        est_s = total / rate
+        cpu = {
+            "value": eff_cells / est_s,
+            "unit": "cells/s",
+            "cores": threads,
+            "kind": "oracle",
+            "sample": (f"float64 oracle propagation of {done} random cells drawn over octree levels in proportion "
+                       f"to the GPU run's {int(total)} propagated cells ({t_used:.1f} s, {rate:.1f} cells/s); "
+                       f"extraction time extrapolated from propagation alone ({est_s:.0f} s)"),
+        }
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": a.precision,
+        "data": "synthetic",
+        "config": {
+            "workload": f"{a.workload}: ReLU MLP {'x'.join(map(str, mlp.widths))}, octree depth {depth} "
+                        f"({1 << depth}^3), {len(isos)} iso-values, UP t={w['k']}, fp64 band {w.get('band_rel', 0)} S",
+            "method": "up",
+            "precision": a.precision,
+            "surrogate": False,
+        },
+        "propagated_cells": propagated,
+        "propagated_cells_per_s": propagated / acp_s if acp_s > 0 else None,
+        "active_leaves": runs[-1]["leaves"],
+        "triangles": runs[-1]["tris"],
+        "phase_ms": {k: round(np.mean([r["times"][k] for r in runs]), 2) for k in runs[-1]["times"]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -200,9 +200,22 @@ isx_status isx_mc_case_table(uint8_t* h_count, int8_t* h_edges);
 /* Context options. */
 typedef enum {
   ISX_KEEP_LEVELS = 1,     /* value 1: meshes keep every level's cells (for testing) */
-  ISX_HIDDEN_KERNEL = 2    /* 0 = automatic, 1 = force the SIMT kernels, 2 = force MFMA */
+  ISX_HIDDEN_KERNEL = 2,   /* 0 = automatic, 1 = force the SIMT kernels, 2 = force MFMA */
+  ISX_PROFILE = 3,         /* value 1: time every hidden-layer launch with HIP events */
+  ISX_SCRATCH_BYTES = 4,   /* bytes of propagation scratch per batch (default 16 GiB) */
+  ISX_VERBOSE = 5          /* value 1: isx_extract prints one line per octree level to stderr */
 } isx_option;
 isx_status isx_set_option(isx_ctx* ctx, isx_option option, int64_t value);
+
+/* Accumulated hidden-layer kernel statistics since the last reset (ISX_PROFILE
+ * on): launches, summed device time in ms (HIP events on the context stream),
+ * algorithmic flops (2 * n_out * n_in * real columns per cell; the real
+ * columns of hidden layer h are 1 centre + 3 input symbols + the true widths
+ * of layers 1..h-2) and algorithmic bytes (the coefficient block read, plus
+ * the block written unless it is the last hidden layer, at the storage
+ * precision).  Synchronises the stream.  reset != 0 clears the counters. */
+isx_status isx_get_profile(isx_ctx* ctx, int64_t* launches, double* ms, double* flops, double* bytes,
+                           int32_t reset);
 
 #ifdef __cplusplus
 }

@@ -20,10 +20,10 @@ from typing import Optional, Sequence
 import numpy as np
 
 from . import _lib
-from ._lib import AA, BF16, FP32, FP64, HIDDEN_KERNEL, KEEP_LEVELS, UP
+from ._lib import AA, BF16, FP32, FP64, HIDDEN_KERNEL, KEEP_LEVELS, PROFILE, SCRATCH_BYTES, UP, VERBOSE
 
 __all__ = ["Context", "Mesh", "IsxError", "AA", "UP", "FP32", "BF16", "FP64", "KEEP_LEVELS", "HIDDEN_KERNEL",
-           "mc_case_table"]
+           "PROFILE", "SCRATCH_BYTES", "VERBOSE", "mc_case_table"]
 
 
 class IsxError(RuntimeError):
@@ -133,6 +133,13 @@ class Context:
 
     def set_option(self, option: int, value: int):
         self._chk(self._L.isx_set_option(self._h, option, int(value)))
+
+    def profile(self, reset: bool = True):
+        """Hidden-layer kernel statistics (ISX_PROFILE on): dict of launches,
+        ms, flops, bytes."""
+        n, ms, fl, by = C.c_int64(), C.c_double(), C.c_double(), C.c_double()
+        self._chk(self._L.isx_get_profile(self._h, C.byref(n), C.byref(ms), C.byref(fl), C.byref(by), int(reset)))
+        return dict(launches=n.value, ms=ms.value, flops=fl.value, bytes=by.value)
 
     # -- batched calls on device tensors (asynchronous on the context stream)
     def propagate(self, mlp_id: int, method: int, precision: int, centres, halves, out, out64=None):

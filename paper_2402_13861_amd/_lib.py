@@ -18,7 +18,7 @@ STATUS_NAMES = {
 }
 AA, UP = 0, 1
 FP32, BF16, FP64 = 0, 1, 2
-KEEP_LEVELS, HIDDEN_KERNEL = 1, 2
+KEEP_LEVELS, HIDDEN_KERNEL, PROFILE, SCRATCH_BYTES, VERBOSE = 1, 2, 3, 4, 5
 MAX_LINEAR, MAX_WIDTH, MAX_ISO = 16, 1024, 32
 
 
@@ -62,6 +62,8 @@ _SIGS = [
     ("isx_mesh_free", C.c_int, [C.c_void_p]),
     ("isx_mc_case_table", C.c_int, [C.c_void_p, C.c_void_p]),
     ("isx_set_option", C.c_int, [C.c_void_p, C.c_int, C.c_int64]),
+    ("isx_get_profile", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                  C.POINTER(C.c_double), C.c_int32]),
 ]
 
 EXPORTED = [name for name, _, _ in _SIGS]

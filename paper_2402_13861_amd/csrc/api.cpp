@@ -31,6 +31,7 @@ struct isx_ctx {
   std::string err;
   std::vector<Model> models;
   bool keep_levels = false;
+  bool verbose = false;
   int kernel_choice = 0;
   size_t prop_budget = size_t(16) << 30;  // bytes of propagation scratch per chunk
   // propagation scratch
@@ -42,6 +43,7 @@ struct isx_ctx {
   Buf bitmap, word_prefix, corner_g, corner_pts, corner_vals, tri_off;
   Buf cls_mask;
   int64_t* h_count = nullptr;  // pinned
+  Profiler prof;
 };
 
 struct isx_mesh {
@@ -156,8 +158,9 @@ isx_status run_propagate(isx_ctx* ctx, const Model& m, isx_method method, isx_pr
     w.vec = (double*)ctx->vec64.p;
     for (int64_t s = 0; s < n; s += chunk) {
       PropArgs a{&m, method, std::min(chunk, n - s), centres + 3 * s, halves + 3 * s, out + 2 * s,
-                 out64 ? out64 + 2 * s : nullptr, ctx->kernel_choice, ctx->stream};
+                 out64 ? out64 + 2 * s : nullptr, ctx->kernel_choice, ctx->stream, &ctx->prof};
       HIPCHK(propagate_f64(a, w));
+      if (ctx->prof.pending.size() > 4096) ctx->prof.harvest();
     }
     return ISX_OK;
   }
@@ -172,8 +175,9 @@ isx_status run_propagate(isx_ctx* ctx, const Model& m, isx_method method, isx_pr
   w.vec = (float*)ctx->vec32.p;
   for (int64_t s = 0; s < n; s += chunk) {
     PropArgs a{&m, method, std::min(chunk, n - s), centres + 3 * s, halves + 3 * s, out + 2 * s, nullptr,
-               ctx->kernel_choice, ctx->stream};
+               ctx->kernel_choice, ctx->stream, &ctx->prof};
     HIPCHK(propagate_f32(a, w));
+    if (ctx->prof.pending.size() > 4096) ctx->prof.harvest();
   }
   return ISX_OK;
 }
@@ -263,8 +267,34 @@ isx_status isx_set_option(isx_ctx* ctx, isx_option option, int64_t value) {
       if (value < 0 || value > 2) return fail(ctx, ISX_EINVAL, "ISX_HIDDEN_KERNEL must be 0, 1 or 2");
       ctx->kernel_choice = (int)value;
       return ISX_OK;
+    case ISX_PROFILE:
+      ctx->prof.on = value != 0;
+      return ISX_OK;
+    case ISX_VERBOSE:
+      ctx->verbose = value != 0;
+      return ISX_OK;
+    case ISX_SCRATCH_BYTES:
+      if (value < (int64_t)(1 << 20)) return fail(ctx, ISX_EINVAL, "ISX_SCRATCH_BYTES must be >= 1 MiB");
+      ctx->prop_budget = (size_t)value;
+      return ISX_OK;
   }
   return fail(ctx, ISX_EINVAL, "unknown option");
+}
+
+isx_status isx_get_profile(isx_ctx* ctx, int64_t* launches, double* ms, double* flops, double* bytes,
+                           int32_t reset) {
+  if (!ctx) return ISX_EINVAL;
+  (void)hipSetDevice(ctx->device);
+  ctx->prof.harvest();
+  if (launches) *launches = ctx->prof.launches;
+  if (ms) *ms = ctx->prof.ms;
+  if (flops) *flops = ctx->prof.flops;
+  if (bytes) *bytes = ctx->prof.bytes;
+  if (reset) {
+    ctx->prof.launches = 0;
+    ctx->prof.ms = ctx->prof.flops = ctx->prof.bytes = 0;
+  }
+  return ISX_OK;
 }
 
 isx_status isx_mc_case_table(uint8_t* h_count, int8_t* h_edges) {
@@ -543,6 +573,11 @@ isx_status isx_extract(isx_ctx* ctx, int32_t mlp_id, const isx_params* p, isx_me
     mesh->lvl_cells.push_back(n);
     mesh->lvl_active.push_back(n_act);
     mesh->lvl_recheck.push_back(n_rc);
+    if (ctx->verbose) {
+      std::fprintf(stderr, "isx: level %d: %lld cells, %lld active, %lld re-checked\n", L, (long long)n,
+                   (long long)n_act, (long long)n_rc);
+      std::fflush(stderr);
+    }
     if (ctx->keep_levels) {
       std::vector<uint32_t> hi(n), hm(n);
       std::vector<float> ho(2 * n);

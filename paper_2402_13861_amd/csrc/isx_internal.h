@@ -79,6 +79,51 @@ struct IsoList {
   float c[ISX_MAX_ISO];
 };
 
+// Optional timing of hidden-layer launches (HIP events on the stream).
+struct Profiler {
+  bool on = false;
+  struct Rec {
+    hipEvent_t a, b;
+    double flops, bytes;
+  };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  int64_t launches = 0;
+  double ms = 0, flops = 0, bytes = 0;
+  hipEvent_t take() {
+    hipEvent_t e = nullptr;
+    if (!pool.empty()) {
+      e = pool.back();
+      pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+    }
+    return e;
+  }
+  // fold completed records into the totals (blocks on the last one)
+  void harvest() {
+    for (Rec& r : pending) {
+      float t = 0.f;
+      if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+        ms += t;
+        flops += r.flops;
+        bytes += r.bytes;
+        ++launches;
+      }
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    pending.clear();
+  }
+  ~Profiler() {
+    for (Rec& r : pending) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+
 // ---- propagation launchers (kernels_prop.hip) ----
 // Propagate C boxes; writes (centre, spread) to out32 [C][2] and, if given,
 // out64 [C][2].  `work` must be sized by prop_work_need().
@@ -92,6 +137,7 @@ struct PropArgs {
   double* out64;
   int kernel_choice;  // 0 auto, 1 SIMT, 2 MFMA
   hipStream_t stream;
+  Profiler* prof;     // may be null
 };
 size_t prop_F_elems(const Model& m, int64_t C);
 size_t prop_vec_elems(const Model& m, int64_t C);

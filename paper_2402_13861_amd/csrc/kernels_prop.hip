@@ -453,6 +453,18 @@ static hipError_t propagate_impl(const PropArgs& a, PropWork<T>& w, bool use_mfm
     const int n_in = m.pw[h - 1], n_out = m.pw[h];
     const int64_t cols_in = m.cols(h - 1);
     T* Fout = h < Lh ? w.F[cur ^ 1] : nullptr;
+    Profiler::Rec rec{};
+    const bool prof = a.prof && a.prof->on;
+    if (prof) {
+      int64_t real_cols = 4;
+      for (int i = 1; i <= h - 2; ++i) real_cols += m.widths[i];
+      rec.a = a.prof->take();
+      rec.b = a.prof->take();
+      rec.flops = 2.0 * m.widths[h] * m.widths[h - 1] * (double)real_cols * (double)C;
+      rec.bytes = (double)sizeof(T) * C *
+                  ((double)real_cols * m.widths[h - 1] + (h < Lh ? (double)(real_cols + m.widths[h - 1]) * m.widths[h] : 0.0));
+      if (rec.a) (void)hipEventRecord(rec.a, a.stream);
+    }
     if (use_mfma) {
       hipError_t e = hidden_mfma<T>(METHOD, C, n_in, n_out, cols_in, wtptr<T>(m.L[h - 1]), bptr<T>(m.L[h - 1]),
                                     w.F[cur], A[h - 1], B[h - 1], G[h - 1], Fout, Y[h], A[h], B[h], G[h], a.stream);
@@ -464,6 +476,10 @@ static hipError_t propagate_impl(const PropArgs& a, PropWork<T>& w, bool use_mfm
       hipLaunchKernelGGL((hidden_simt_kernel<T, METHOD, CT>), dim3((unsigned)C), dim3(bs), lds, a.stream, C, n_in,
                          n_out, cols_in, wtptr<T>(m.L[h - 1]), bptr<T>(m.L[h - 1]), w.F[cur], A[h - 1], B[h - 1],
                          G[h - 1], Fout, Y[h], A[h], B[h], G[h]);
+    }
+    if (prof && rec.a && rec.b) {
+      (void)hipEventRecord(rec.b, a.stream);
+      a.prof->pending.push_back(rec);
     }
     cur ^= 1;
   }

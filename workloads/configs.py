@@ -1,0 +1,48 @@
+"""The synthetic workloads: MLP shapes, weight sources, iso-value protocol and
+octree depth.  Inputs only; no method arithmetic here.
+
+* ``relu64x3_he``: ReLU MLP 3->64->64->64->1, He-normal weights and biases
+  (seed 0) on [-1,1]^3, octree depth 6 (64^3 leaves), iso = median of the MLP
+  over 10^4 uniform points, t = 3.
+* ``relu256x5_fourier``: ReLU MLP 3->256x5->1 fitted (2000 Adam steps, batch
+  65536, lr 1e-3, He-normal init seed 0) to a standardised sum of 512 random
+  Fourier modes with a k^(-5/3) amplitude spectrum, |k| <= 16, sampled on
+  256^3 points (field seed 2); octree depth 9 (512^3 effective resolution);
+  iso-values at the 25/50/75 % output quantiles; t = 3; float64 re-check band
+  1e-3 S.
+"""
+
+from __future__ import annotations
+
+import json
+from pathlib import Path
+
+from .weights import he_normal_mlp, read_weights
+
+DATA = Path(__file__).resolve().parent / "data"
+ISO_JSON = Path(__file__).resolve().parent / "isovalues.json"
+
+WORKLOADS = {
+    "relu64x3_he": dict(
+        widths=[3, 64, 64, 64, 1], weight_seed=0, weights=None, depth=6, k=3.0, iso_quantiles="median",
+    ),
+    "relu256x5_fourier": dict(
+        widths=[3, 256, 256, 256, 256, 256, 1], weight_seed=0, weights="relu_256x5_fourier.isxw", depth=9, k=3.0,
+        iso_quantiles=[0.25, 0.5, 0.75], band_rel=1e-3,
+    ),
+}
+
+
+def load_mlp(name: str):
+    w = WORKLOADS[name]
+    if w["weights"] is None:
+        return he_normal_mlp(w["widths"], w["weight_seed"])
+    mlp = read_weights(DATA / w["weights"])
+    assert mlp.widths == w["widths"], (mlp.widths, w["widths"])
+    return mlp
+
+
+def isovalues(name: str):
+    """(iso list, output scale S) as written by make_isovalues."""
+    t = json.loads(ISO_JSON.read_text())[name]
+    return t["iso"], t["scale"]
