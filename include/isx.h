@@ -203,7 +203,8 @@ typedef enum {
   ISX_HIDDEN_KERNEL = 2,   /* 0 = automatic, 1 = force the SIMT kernels, 2 = force MFMA */
   ISX_PROFILE = 3,         /* value 1: time every hidden-layer launch with HIP events */
   ISX_SCRATCH_BYTES = 4,   /* bytes of propagation scratch per batch (default 16 GiB) */
-  ISX_VERBOSE = 5          /* value 1: isx_extract prints one line per octree level to stderr */
+  ISX_VERBOSE = 5,         /* value 1: isx_extract prints one line per octree level to stderr */
+  ISX_BF16_VARIANT = 6     /* bf16 hidden-layer tile shape: 0 = default for the width, 1..4 = forced */
 } isx_option;
 isx_status isx_set_option(isx_ctx* ctx, isx_option option, int64_t value);
 

@@ -20,10 +20,10 @@ from typing import Optional, Sequence
 import numpy as np
 
 from . import _lib
-from ._lib import AA, BF16, FP32, FP64, HIDDEN_KERNEL, KEEP_LEVELS, PROFILE, SCRATCH_BYTES, UP, VERBOSE
+from ._lib import AA, BF16, BF16_VARIANT, FP32, FP64, HIDDEN_KERNEL, KEEP_LEVELS, PROFILE, SCRATCH_BYTES, UP, VERBOSE
 
 __all__ = ["Context", "Mesh", "IsxError", "AA", "UP", "FP32", "BF16", "FP64", "KEEP_LEVELS", "HIDDEN_KERNEL",
-           "PROFILE", "SCRATCH_BYTES", "VERBOSE", "mc_case_table"]
+           "PROFILE", "SCRATCH_BYTES", "VERBOSE", "BF16_VARIANT", "mc_case_table"]
 
 
 class IsxError(RuntimeError):

@@ -33,9 +33,10 @@ struct isx_ctx {
   bool keep_levels = false;
   bool verbose = false;
   int kernel_choice = 0;
+  int bf16_variant = 0;
   size_t prop_budget = size_t(16) << 30;  // bytes of propagation scratch per chunk
   // propagation scratch
-  Buf F32[2], vec32, F64[2], vec64;
+  Buf F32[2], vec32, F64[2], vec64, Fbf[2];
   // level scratch
   Buf ids, pmask, centres, halves, out, mask, act_ids[2], act_mask[2], scan_tmp, count;
   Buf rc_idx, rc_centres, rc_halves, rc_out32, rc_out64, rc_count;
@@ -104,7 +105,7 @@ void release(Buf& b) {
 }
 
 void free_layer(Layer& l) {
-  void* ps[] = {l.W, l.Wt, l.b, l.Wd, l.Wtd, l.bd, l.Wbf};
+  void* ps[] = {l.W, l.Wt, l.b, l.Wd, l.Wtd, l.bd, l.Wtbf};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   l = Layer{};
@@ -158,13 +159,32 @@ isx_status run_propagate(isx_ctx* ctx, const Model& m, isx_method method, isx_pr
     w.vec = (double*)ctx->vec64.p;
     for (int64_t s = 0; s < n; s += chunk) {
       PropArgs a{&m, method, std::min(chunk, n - s), centres + 3 * s, halves + 3 * s, out + 2 * s,
-                 out64 ? out64 + 2 * s : nullptr, ctx->kernel_choice, ctx->stream, &ctx->prof};
+                 out64 ? out64 + 2 * s : nullptr, ctx->kernel_choice, ctx->stream, &ctx->prof, ctx->bf16_variant};
       HIPCHK(propagate_f64(a, w));
       if (ctx->prof.pending.size() > 4096) ctx->prof.harvest();
     }
     return ISX_OK;
   }
-  if (prec == ISX_BF16) return fail(ctx, ISX_EUNSUPPORTED, "bf16 propagation is not built");
+  if (prec == ISX_BF16) {
+    if (!bf16_supported(m))
+      return fail(ctx, ISX_EUNSUPPORTED, "bf16 propagation needs every hidden layer's input width <= 256");
+    const size_t per_cell = 2 * prop_F_elems_bf16(m, 1) * 2 + prop_vec_elems(m, 1) * 4;
+    int64_t chunk = chunk_req > 0 ? chunk_req : (int64_t)(ctx->prop_budget / per_cell);
+    chunk = std::max<int64_t>(1, std::min<int64_t>(chunk, n));
+    PropWork<float> w;
+    HIPCHK(ensure(ctx->Fbf[0], prop_F_elems_bf16(m, chunk) * 2));
+    HIPCHK(ensure(ctx->Fbf[1], prop_F_elems_bf16(m, chunk) * 2));
+    HIPCHK(ensure(ctx->vec32, prop_vec_elems(m, chunk) * sizeof(float)));
+    w.vec = (float*)ctx->vec32.p;
+    uint16_t* Fbf[2] = {(uint16_t*)ctx->Fbf[0].p, (uint16_t*)ctx->Fbf[1].p};
+    for (int64_t s = 0; s < n; s += chunk) {
+      PropArgs a{&m, method, std::min(chunk, n - s), centres + 3 * s, halves + 3 * s, out + 2 * s, nullptr,
+                 ctx->kernel_choice, ctx->stream, &ctx->prof, ctx->bf16_variant};
+      HIPCHK(propagate_bf16(a, w, Fbf, 0));
+      if (ctx->prof.pending.size() > 4096) ctx->prof.harvest();
+    }
+    return ISX_OK;
+  }
   const int64_t chunk = chunk_for<float>(ctx, m, n, chunk_req);
   PropWork<float> w;
   HIPCHK(ensure(ctx->F32[0], prop_F_elems(m, chunk) * sizeof(float)));
@@ -175,7 +195,7 @@ isx_status run_propagate(isx_ctx* ctx, const Model& m, isx_method method, isx_pr
   w.vec = (float*)ctx->vec32.p;
   for (int64_t s = 0; s < n; s += chunk) {
     PropArgs a{&m, method, std::min(chunk, n - s), centres + 3 * s, halves + 3 * s, out + 2 * s, nullptr,
-               ctx->kernel_choice, ctx->stream, &ctx->prof};
+               ctx->kernel_choice, ctx->stream, &ctx->prof, ctx->bf16_variant};
     HIPCHK(propagate_f32(a, w));
     if (ctx->prof.pending.size() > 4096) ctx->prof.harvest();
   }
@@ -243,7 +263,8 @@ isx_status isx_destroy(isx_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   for (Model& m : ctx->models)
     for (int l = 0; l < ISX_MAX_LINEAR; ++l) free_layer(m.L[l]);
-  Buf* bufs[] = {&ctx->F32[0], &ctx->F32[1], &ctx->vec32, &ctx->F64[0], &ctx->F64[1], &ctx->vec64,
+  Buf* bufs[] = {&ctx->F32[0], &ctx->F32[1], &ctx->vec32, &ctx->F64[0], &ctx->F64[1], &ctx->vec64, &ctx->Fbf[0],
+                 &ctx->Fbf[1],
                  &ctx->ids, &ctx->pmask, &ctx->centres, &ctx->halves, &ctx->out, &ctx->mask,
                  &ctx->act_ids[0], &ctx->act_ids[1], &ctx->act_mask[0], &ctx->act_mask[1], &ctx->scan_tmp,
                  &ctx->count, &ctx->rc_idx, &ctx->rc_centres, &ctx->rc_halves, &ctx->rc_out32, &ctx->rc_out64,
@@ -272,6 +293,10 @@ isx_status isx_set_option(isx_ctx* ctx, isx_option option, int64_t value) {
       return ISX_OK;
     case ISX_VERBOSE:
       ctx->verbose = value != 0;
+      return ISX_OK;
+    case ISX_BF16_VARIANT:
+      if (value < 0 || value > 4) return fail(ctx, ISX_EINVAL, "ISX_BF16_VARIANT must be in [0, 4]");
+      ctx->bf16_variant = (int)value;
       return ISX_OK;
     case ISX_SCRATCH_BYTES:
       if (value < (int64_t)(1 << 20)) return fail(ctx, ISX_EINVAL, "ISX_SCRATCH_BYTES must be >= 1 MiB");
@@ -333,7 +358,7 @@ isx_status isx_load_mlp(isx_ctx* ctx, int32_t n_linear, const int32_t* widths, c
     const int wi = widths[l], wo = widths[l + 1];
     std::vector<float> W((size_t)no * ni, 0.f), Wt((size_t)ni * no, 0.f), b((size_t)no, 0.f);
     std::vector<double> Wd((size_t)no * ni, 0.0), Wtd((size_t)ni * no, 0.0), bd((size_t)no, 0.0);
-    std::vector<uint16_t> Wbf((size_t)no * ni, 0);
+    std::vector<uint16_t> Wtbf((size_t)ni * no, 0);
     for (int o = 0; o < wo; ++o) {
       for (int i = 0; i < wi; ++i) {
         const float w = h_W[l][(size_t)o * wi + i];
@@ -341,7 +366,7 @@ isx_status isx_load_mlp(isx_ctx* ctx, int32_t n_linear, const int32_t* widths, c
         Wt[(size_t)i * no + o] = w;
         Wd[(size_t)o * ni + i] = w;
         Wtd[(size_t)i * no + o] = w;
-        Wbf[(size_t)o * ni + i] = f32_to_bf16_bits(w);
+        Wtbf[(size_t)i * no + o] = f32_to_bf16_bits(w);
       }
       b[o] = h_b[l][o];
       bd[o] = h_b[l][o];
@@ -356,7 +381,7 @@ isx_status isx_load_mlp(isx_ctx* ctx, int32_t n_linear, const int32_t* widths, c
     if (e == hipSuccess) e = upload(&L.Wd, Wd);
     if (e == hipSuccess) e = upload(&L.Wtd, Wtd);
     if (e == hipSuccess) e = upload(&L.bd, bd);
-    if (e == hipSuccess) e = upload(&L.Wbf, Wbf);
+    if (e == hipSuccess) e = upload(&L.Wtbf, Wtbf);
     if (e != hipSuccess) {
       for (int k = 0; k <= l; ++k) free_layer(m.L[k]);
       return hip_fail(ctx, e, "isx_load_mlp upload");
@@ -453,7 +478,7 @@ isx_status isx_eval_points(isx_ctx* ctx, int32_t mlp_id, isx_precision precision
   } else if (precision == ISX_FP32) {
     HIPCHK(eval_points_f32(*m, n, d_points, d_values, ctx->stream));
   } else if (precision == ISX_BF16) {
-    return fail(ctx, ISX_EUNSUPPORTED, "bf16 evaluation is not built");
+    HIPCHK(eval_points_f32(*m, n, d_points, d_values, ctx->stream));
   } else {
     return fail(ctx, ISX_EINVAL, "unknown precision");
   }

@@ -30,7 +30,7 @@ struct Layer {
   double* Wd = nullptr;
   double* Wtd = nullptr;
   double* bd = nullptr;
-  uint16_t* Wbf = nullptr;  // bfloat16 bits, [n_out][n_in]
+  uint16_t* Wtbf = nullptr; // bfloat16 bits of W^T, [n_in][n_out]
 };
 
 struct Model {
@@ -47,6 +47,14 @@ struct Model {
   int64_t cols(int h) const {
     int64_t c = kHeadCols;
     for (int i = 1; i < h; ++i) c += pw[i];
+    return c;
+  }
+  // bf16 path: columns of hidden layer h's block that are stored (the last
+  // symbol block, W_h diag(gamma_{h-1}), is never stored: the next layer
+  // multiplies by W_h^T directly and scales those columns by gamma_{h-1})
+  int64_t stored_cols(int h) const {
+    int64_t c = kHeadCols;
+    for (int i = 1; i + 1 < h; ++i) c += pw[i];
     return c;
   }
 };
@@ -138,12 +146,15 @@ struct PropArgs {
   int kernel_choice;  // 0 auto, 1 SIMT, 2 MFMA
   hipStream_t stream;
   Profiler* prof;     // may be null
+  int bf16_variant;   // 0 = default tile shape for the width
 };
 size_t prop_F_elems(const Model& m, int64_t C);
 size_t prop_vec_elems(const Model& m, int64_t C);
 hipError_t propagate_f32(const PropArgs& a, PropWork<float>& w);
 hipError_t propagate_f64(const PropArgs& a, PropWork<double>& w);
 hipError_t propagate_bf16(const PropArgs& a, PropWork<float>& w, uint16_t* Fbf[2], size_t Fbf_elems);
+bool bf16_supported(const Model& m);
+size_t prop_F_elems_bf16(const Model& m, int64_t C);
 hipError_t eval_points_f32(const Model& m, int64_t n, const float* pts, float* vals, hipStream_t s);
 hipError_t eval_points_f64(const Model& m, int64_t n, const float* pts, float* vals, hipStream_t s);
 

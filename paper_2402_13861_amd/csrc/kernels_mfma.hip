@@ -225,12 +225,26 @@ __global__ __launch_bounds__(512) void hidden_mfma_f32_kernel(
   }
   // new symbol block W diag(gamma_{h-1}) and its statistic
   {
+    // eight independent weight loads in flight per thread
+    constexpr int U = 8;
     const int m = t % BM, g = t / BM;
     float gs = 0.f;
-    for (int j = g; j < n_in; j += K::G) {
-      const float v = Wt[(int64_t)j * n_out + m0 + m] * s_gamma[j];
-      gs += mstat<METHOD>(v);
-      if (fout) fout[(cols_in + j) * n_out + m0 + m] = v;
+    for (int j0 = g; j0 < n_in; j0 += U * K::G) {
+      float wv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = j0 + u * K::G;
+        wv[u] = j < n_in ? Wt[(int64_t)j * n_out + m0 + m] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = j0 + u * K::G;
+        if (j < n_in) {
+          const float v = wv[u] * s_gamma[j];
+          gs += mstat<METHOD>(v);
+          if (fout) fout[(cols_in + j) * n_out + m0 + m] = v;
+        }
+      }
     }
     s_gen[g][m] = gs;
   }

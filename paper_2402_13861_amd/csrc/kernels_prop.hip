@@ -495,6 +495,27 @@ static hipError_t propagate_impl(const PropArgs& a, PropWork<T>& w, bool use_mfm
   return hipGetLastError();
 }
 
+// Output read-off for paths that keep float32 vectors (used by the bf16 path).
+hipError_t launch_output_f32(const Model& m, isx_method method, int64_t C, float* vec, const float* halves,
+                             float* out32, hipStream_t s) {
+  float *Y[ISX_MAX_LINEAR] = {}, *A[ISX_MAX_LINEAR] = {}, *B[ISX_MAX_LINEAR] = {}, *G[ISX_MAX_LINEAR] = {};
+  layer_ptrs<float>(m, C, vec, Y, A, B, G);
+  NetView<float> view = make_view<float>(m);
+  for (int h = 1; h <= m.hidden(); ++h) {
+    view.Y[h] = Y[h];
+    view.A[h] = A[h];
+    view.B[h] = B[h];
+    view.G[h] = G[h];
+  }
+  if (method == ISX_UP)
+    hipLaunchKernelGGL((output_kernel<float, ISX_UP>), dim3((unsigned)C), dim3(256), 0, s, C, view, halves, out32,
+                       (double*)nullptr);
+  else
+    hipLaunchKernelGGL((output_kernel<float, ISX_AA>), dim3((unsigned)C), dim3(256), 0, s, C, view, halves, out32,
+                       (double*)nullptr);
+  return hipGetLastError();
+}
+
 hipError_t propagate_f32(const PropArgs& a, PropWork<float>& w) {
   if (a.C <= 0) return hipSuccess;
   const bool use_mfma = a.kernel_choice != 1 && mfma_supported(*a.m);

@@ -281,3 +281,78 @@ def test_extract_capacity_error(ctx):
         assert e.value.status == -4
     finally:
         ctx.unload_mlp(mid)
+
+
+BF16_WIDTHS = [
+    [3, 64, 64, 64, 1],
+    [3, 128, 128, 128, 128, 1],
+    [3, 256, 256, 256, 256, 256, 1],
+    [3, 96, 160, 1],  # widths that are multiples of 32 but not of 64/128
+]
+
+
+@pytest.mark.parametrize("widths", BF16_WIDTHS, ids=lambda w: "x".join(map(str, w)))
+@pytest.mark.parametrize("mname", ["up", "aa"])
+def test_propagate_bf16_error_against_oracle(ctx, widths, mname):
+    """BF16 operands, FP32 accumulation: the bound error against the FP64
+    oracle, reported per result and bounded (relative to max(|o|, S))."""
+    import paper_2402_13861_amd as isx
+
+    method, gm = METHODS[mname]
+    mlp = he_normal_mlp(widths, seed=0)
+    mid = ctx.load_weights(mlp)
+    try:
+        c, h, _ = random_boxes(257, range(0, 10), seed=11)
+        ref = propagate(mlp, c, h, method)
+        S = output_scale(mlp)
+        k = 3.0 if mname == "up" else 1.0
+        g, _ = _gpu_prop(ctx, mid, gm, isx.BF16, c, h)
+        worst, _ = assert_pair_close(g, ref, S, 5e-2, f"bf16 {mname} {widths}", k=k, spread_rtol=0.2)
+        # the centre is a float32 point evaluation of the linearised net
+        assert worst["centre"] <= 1e-2
+    finally:
+        ctx.unload_mlp(mid)
+
+
+def test_bf16_unsupported_width_reports_error(ctx):
+    import paper_2402_13861_amd as isx
+
+    mlp = he_normal_mlp([3, 512, 512, 1], seed=0)
+    mid = ctx.load_weights(mlp)
+    try:
+        c, h, _ = random_boxes(4, [3], seed=1)
+        with pytest.raises(isx.IsxError) as e:
+            _gpu_prop(ctx, mid, isx.UP, isx.BF16, c, h)
+        assert e.value.status == -7
+    finally:
+        ctx.unload_mlp(mid)
+
+
+@pytest.mark.parametrize("prec_name", ["fp32", "bf16"])
+def test_fp64_band_reproduces_oracle_active_sets(ctx, prec_name):
+    """With the float64 re-check band wider than the float32/bf16 bound
+    error, every classification is decided as in float64: the active sets
+    equal the oracle's except for cells within 1e-9 S of an iso-value."""
+    import paper_2402_13861_amd as isx
+
+    prec = {"fp32": isx.FP32, "bf16": isx.BF16}[prec_name]
+    mlp = he_normal_mlp([3, 64, 64, 64, 1], seed=0)
+    vals = mlp_forward(mlp, uniform_points(10_000, seed=1))
+    isos = [float(np.float32(np.quantile(vals, q))) for q in (0.3, 0.6)]
+    S = float(vals.std())
+    band = (1e-3 if prec_name == "fp32" else 5e-2) * S
+    mid = ctx.load_weights(mlp)
+    try:
+        ctx.set_isovalues(mid, isos)
+        ctx.set_option(isx.KEEP_LEVELS, 1)
+        mesh = ctx.extract(mid, isx.UP, prec, k=3.0, max_depth=5, fp64_band=band)
+        ctx.set_option(isx.KEEP_LEVELS, 0)
+        lv = mesh.levels()
+        print(f"{prec_name} band: rechecked per level {[l['rechecked'] for l in lv]}", flush=True)
+        assert sum(l["rechecked"] for l in lv) > 0
+        ol = extract_active(mlp, UP, isos, 5, k=3.0)
+        close = close_sets(ol, UP, 3.0, isos, S, band_rel=1e-9)
+        bad = unexcused_level_diffs(_gpu_levels(mesh), ol, close)
+        assert not bad, bad
+    finally:
+        ctx.unload_mlp(mid)
