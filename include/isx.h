@@ -146,6 +146,9 @@ typedef struct {
   int64_t max_cells;       /* capacity of one level (0 = library default); a
                               level above it fails with ISX_ECAPACITY */
   int64_t chunk_cells;     /* cells propagated per batch (0 = automatic) */
+  int32_t use_surrogate;   /* 1: decide cells with the surrogate attached to
+                              the MLP where it is confident (see
+                              isx_surrogate_attach), propagate the rest */
 } isx_params;
 
 /* Full extraction (Alg. 1 followed by corner evaluation and marching cubes)
@@ -160,10 +163,11 @@ isx_status isx_extract(isx_ctx* ctx, int32_t mlp_id, const isx_params* params, i
 isx_status isx_mesh_info(const isx_mesh* mesh, int64_t* n_tris, int64_t* n_leaves, int64_t* n_corners,
                          int32_t* n_levels);
 
-/* Per-level counts: cells propagated at that level and cells kept active
- * (mask != 0), and the number of cells re-checked in float64. */
+/* Per-level counts: cells examined at that level, cells kept active
+ * (mask != 0), cells re-checked in float64, and cells actually propagated
+ * (all examined cells unless the surrogate decided some). */
 isx_status isx_mesh_level(const isx_mesh* mesh, int32_t level, int64_t* n_cells, int64_t* n_active,
-                          int64_t* n_rechecked);
+                          int64_t* n_rechecked, int64_t* n_propagated);
 
 /* Phase times in milliseconds measured with HIP events on the context
  * stream: active-cell prediction (all levels), corner evaluation, marching
@@ -190,6 +194,57 @@ isx_status isx_mesh_copy_level(const isx_mesh* mesh, int32_t level, uint32_t* h_
                                uint32_t* h_masks);
 
 isx_status isx_mesh_free(isx_mesh* mesh);
+
+/* ---- Learned surrogate ----------------------------------------------
+ * A small ReLU MLP g: (c_x, c_y, c_z, a*log2(cell size)+b) -> standardised
+ * ((mu - mu_bar)/S, ln sigma), predicting the propagation's output for a cell
+ * at a fraction of its cost.  Trained on the GPU (bf16 MFMA products, float32
+ * accumulation and master weights, Adam with beta1 = 0.9, beta2 = 0.999,
+ * eps = 1e-8) on (cell, propagated mu/sigma) pairs the caller provides.
+ *
+ * isx_surrogate_load: n_linear layers, widths[0] = 4, widths[n_linear] = 2,
+ *   row-major float32 host weights (copied); Adam state starts at zero.
+ * isx_surrogate_get: copy the current weights into host arrays of the same
+ *   shapes.
+ * isx_surrogate_set_norm: mu_bar, S (> 0) of the targets and a, b of the
+ *   size feature.
+ * isx_surrogate_train: `steps` Adam steps on mini-batches of `batch` rows
+ *   taken in order from row `first_row` of the n pairs (wrapping around):
+ *   d_centres/d_halves [n][3] and d_targets [n][2] = propagated (mu, sigma),
+ *   device arrays.  d_loss [steps] (device, may be NULL) receives each step's
+ *   loss.  Asynchronous.
+ * isx_surrogate_predict: d_out [n][2] = predicted (mu, sigma) in the INR's
+ *   units.  Asynchronous.
+ * isx_surrogate_attach: use surrogate sur_id in isx_extract of mlp_id (when
+ *   params.use_surrogate).  h_err_mu[L], h_err_logsig[L] (L < n_levels) are
+ *   the standard deviations of the surrogate's error at octree level L (field
+ *   units and log-sigma units).  A cell is decided without propagation when
+ *   for every iso-value c it still carries either
+ *     |mu_hat - c| - z err_mu > t sigma_hat exp(+z err_logsig)  (outside), or
+ *     |mu_hat - c| + z err_mu < t sigma_hat exp(-z err_logsig)  (inside);
+ *   otherwise it is propagated.  Leaves are always propagated unless
+ *   accept_leaves.  sur_id = -1 detaches.
+ * Errors: ISX_EINVAL, ISX_ESHAPE, ISX_ENAN, ISX_ENOMEM, ISX_EHIP. */
+isx_status isx_surrogate_load(isx_ctx* ctx, int32_t n_linear, const int32_t* widths, const float* const* h_W,
+                              const float* const* h_b, int32_t* sur_id);
+isx_status isx_surrogate_get(isx_ctx* ctx, int32_t sur_id, float* const* h_W, float* const* h_b);
+isx_status isx_surrogate_set_norm(isx_ctx* ctx, int32_t sur_id, float mu_bar, float scale, float size_a,
+                                  float size_b);
+isx_status isx_surrogate_train(isx_ctx* ctx, int32_t sur_id, int64_t n, const float* d_centres,
+                               const float* d_halves, const float* d_targets, int64_t first_row, int32_t steps,
+                               int32_t batch, float lr, float* d_loss);
+/* Gradients of the loss on one mini-batch (rows first_row.. of the n pairs,
+ * as in isx_surrogate_train) without updating the weights; copied to host
+ * arrays shaped like the weights, and the batch loss to *h_loss (may be
+ * NULL).  Synchronous. */
+isx_status isx_surrogate_grad(isx_ctx* ctx, int32_t sur_id, int64_t n, const float* d_centres,
+                              const float* d_halves, const float* d_targets, int64_t first_row, int32_t batch,
+                              float* const* h_gW, float* const* h_gb, float* h_loss);
+isx_status isx_surrogate_predict(isx_ctx* ctx, int32_t sur_id, int64_t n, const float* d_centres,
+                                 const float* d_halves, float* d_out);
+isx_status isx_surrogate_attach(isx_ctx* ctx, int32_t mlp_id, int32_t sur_id, int32_t n_levels,
+                                const float* h_err_mu, const float* h_err_logsig, float z, int32_t accept_leaves);
+isx_status isx_surrogate_free(isx_ctx* ctx, int32_t sur_id);
 
 /* Copy the library's marching-cubes case table: h_count[256] triangles per
  * case (case bit i set iff corner i < iso-value; corners (0,0,0) (1,0,0)

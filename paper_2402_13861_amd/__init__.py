@@ -171,6 +171,75 @@ class Context:
                                                _ptr(idx), _ptr(msk), _ptr(cnt)))
         return idx, msk, cnt
 
+    # -- learned surrogate
+    def surrogate_load(self, Ws, bs) -> int:
+        Ws = [np.ascontiguousarray(W, dtype=np.float32) for W in Ws]
+        bs = [np.ascontiguousarray(b, dtype=np.float32) for b in bs]
+        widths = [Ws[0].shape[1]] + [W.shape[0] for W in Ws]
+        n = len(Ws)
+        out = C.c_int32()
+        self._chk(self._L.isx_surrogate_load(self._h, n, (C.c_int32 * (n + 1))(*widths),
+                                             (C.c_void_p * n)(*[W.ctypes.data for W in Ws]),
+                                             (C.c_void_p * n)(*[b.ctypes.data for b in bs]), C.byref(out)))
+        self._sur_shapes = getattr(self, "_sur_shapes", {})
+        self._sur_shapes[out.value] = [W.shape for W in Ws]
+        return out.value
+
+    def surrogate_weights(self, sid: int):
+        shapes = self._sur_shapes[sid]
+        Ws = [np.zeros(s, dtype=np.float32) for s in shapes]
+        bs = [np.zeros(s[0], dtype=np.float32) for s in shapes]
+        n = len(Ws)
+        self._chk(self._L.isx_surrogate_get(self._h, sid, (C.c_void_p * n)(*[W.ctypes.data for W in Ws]),
+                                            (C.c_void_p * n)(*[b.ctypes.data for b in bs])))
+        return Ws, bs
+
+    def surrogate_set_norm(self, sid: int, mu_bar: float, scale: float, size_a: float, size_b: float):
+        self._chk(self._L.isx_surrogate_set_norm(self._h, sid, float(mu_bar), float(scale), float(size_a),
+                                                 float(size_b)))
+
+    def surrogate_train(self, sid: int, centres, halves, targets, steps: int, batch: int, lr: float,
+                        first_row: int = 0, loss=None):
+        import torch
+
+        _check_dev(centres, torch.float32, "centres", (3,))
+        _check_dev(halves, torch.float32, "halves", (3,))
+        _check_dev(targets, torch.float32, "targets", (2,))
+        _check_dev(loss, torch.float32, "loss")
+        self._chk(self._L.isx_surrogate_train(self._h, sid, centres.shape[0], _ptr(centres), _ptr(halves),
+                                              _ptr(targets), int(first_row), int(steps), int(batch), float(lr),
+                                              _ptr(loss)))
+
+    def surrogate_grad(self, sid: int, centres, halves, targets, batch: int, first_row: int = 0):
+        shapes = self._sur_shapes[sid]
+        gW = [np.zeros(s, dtype=np.float32) for s in shapes]
+        gb = [np.zeros(s[0], dtype=np.float32) for s in shapes]
+        n = len(gW)
+        loss = C.c_float()
+        self._chk(self._L.isx_surrogate_grad(self._h, sid, centres.shape[0], _ptr(centres), _ptr(halves),
+                                             _ptr(targets), int(first_row), int(batch),
+                                             (C.c_void_p * n)(*[g.ctypes.data for g in gW]),
+                                             (C.c_void_p * n)(*[g.ctypes.data for g in gb]), C.byref(loss)))
+        return gW, gb, loss.value
+
+    def surrogate_predict(self, sid: int, centres, halves, out):
+        import torch
+
+        _check_dev(out, torch.float32, "out", (2,))
+        self._chk(self._L.isx_surrogate_predict(self._h, sid, centres.shape[0], _ptr(centres), _ptr(halves),
+                                                _ptr(out)))
+
+    def surrogate_attach(self, mlp_id: int, sid: int, err_mu, err_logsig, z: float = 2.0,
+                         accept_leaves: bool = False):
+        err_mu = [float(x) for x in err_mu]
+        err_ls = [float(x) for x in err_logsig]
+        n = len(err_mu)
+        self._chk(self._L.isx_surrogate_attach(self._h, mlp_id, sid, n, (C.c_float * n)(*err_mu),
+                                               (C.c_float * n)(*err_ls), float(z), int(bool(accept_leaves))))
+
+    def surrogate_free(self, sid: int):
+        self._chk(self._L.isx_surrogate_free(self._h, sid))
+
     def eval_points(self, mlp_id: int, precision: int, pts, vals):
         import torch
 
@@ -180,9 +249,10 @@ class Context:
 
     # -- full extraction (synchronous)
     def extract(self, mlp_id: int, method: int = UP, precision: int = FP32, k: float = 3.0, max_depth: int = 6,
-                fp64_band: float = 0.0, max_cells: int = 0, chunk_cells: int = 0) -> "Mesh":
+                fp64_band: float = 0.0, max_cells: int = 0, chunk_cells: int = 0,
+                use_surrogate: bool = False) -> "Mesh":
         p = _lib.Params(method, precision, float(k), int(max_depth), float(fp64_band), int(max_cells),
-                        int(chunk_cells))
+                        int(chunk_cells), int(bool(use_surrogate)))
         h = C.c_void_p()
         self._chk(self._L.isx_extract(self._h, mlp_id, C.byref(p), C.byref(h)))
         return Mesh(self._L, h)
@@ -212,9 +282,9 @@ class Mesh:
     def levels(self):
         out = []
         for i in range(self.n_levels):
-            a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
-            self._L.isx_mesh_level(self._h, i, C.byref(a), C.byref(b), C.byref(c))
-            out.append(dict(cells=a.value, active=b.value, rechecked=c.value))
+            a, b, c, d = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+            self._L.isx_mesh_level(self._h, i, C.byref(a), C.byref(b), C.byref(c), C.byref(d))
+            out.append(dict(cells=a.value, active=b.value, rechecked=c.value, propagated=d.value))
         return out
 
     def times(self):

@@ -31,6 +31,7 @@ class Params(C.Structure):
         ("fp64_band", C.c_float),
         ("max_cells", C.c_int64),
         ("chunk_cells", C.c_int64),
+        ("use_surrogate", C.c_int32),
     ]
 
 
@@ -53,7 +54,7 @@ _SIGS = [
     ("isx_mesh_info", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                 C.POINTER(C.c_int32)]),
     ("isx_mesh_level", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
-                                 C.POINTER(C.c_int64)]),
+                                 C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     ("isx_mesh_times", C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_float), C.POINTER(C.c_float),
                                  C.POINTER(C.c_float)]),
     ("isx_mesh_copy_tris", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -62,6 +63,19 @@ _SIGS = [
     ("isx_mesh_free", C.c_int, [C.c_void_p]),
     ("isx_mc_case_table", C.c_int, [C.c_void_p, C.c_void_p]),
     ("isx_set_option", C.c_int, [C.c_void_p, C.c_int, C.c_int64]),
+    ("isx_surrogate_load", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_void_p),
+                                     C.POINTER(C.c_void_p), C.POINTER(C.c_int32)]),
+    ("isx_surrogate_get", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]),
+    ("isx_surrogate_set_norm", C.c_int, [C.c_void_p, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float]),
+    ("isx_surrogate_train", C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_int64, C.c_int32, C.c_int32, C.c_float, C.c_void_p]),
+    ("isx_surrogate_grad", C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_int64, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                     C.POINTER(C.c_float)]),
+    ("isx_surrogate_predict", C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("isx_surrogate_attach", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_float),
+                                       C.POINTER(C.c_float), C.c_float, C.c_int32]),
+    ("isx_surrogate_free", C.c_int, [C.c_void_p, C.c_int32]),
     ("isx_get_profile", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double),
                                   C.POINTER(C.c_double), C.c_int32]),
 ]

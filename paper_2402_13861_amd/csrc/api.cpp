@@ -25,6 +25,18 @@ std::string g_create_error;
 
 }  // namespace
 
+// Surrogate state: float32 master weights, Adam moments, gradients.
+struct Sur {
+  bool live = false;
+  int L = 0;
+  int w[ISX_MAX_LINEAR + 1] = {};
+  float *W[ISX_MAX_LINEAR] = {}, *b[ISX_MAX_LINEAR] = {};
+  float *mW[ISX_MAX_LINEAR] = {}, *vW[ISX_MAX_LINEAR] = {}, *mb[ISX_MAX_LINEAR] = {}, *vb[ISX_MAX_LINEAR] = {};
+  float *gW[ISX_MAX_LINEAR] = {}, *gb[ISX_MAX_LINEAR] = {};
+  int64_t t = 0;
+  float mu_bar = 0.f, scale = 1.f, size_a = 1.f, size_b = 0.f;
+};
+
 struct isx_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -43,6 +55,11 @@ struct isx_ctx {
   // corner / mc scratch
   Buf bitmap, word_prefix, corner_g, corner_pts, corner_vals, tri_off;
   Buf cls_mask;
+  // surrogate: models, training/inference activations, extraction scratch
+  std::vector<Sur> surs;
+  Buf sur_act[ISX_MAX_LINEAR + 1], sur_out, sur_T, sur_d[2];
+  Buf sp_pred, sp_fb, sp_idx, sp_pm, sp_c, sp_h, sp_out, sp_mask, sp_cnt, sp_tmp;
+  Buf rc_flags, rc_fidx, rc_fmask;
   int64_t* h_count = nullptr;  // pinned
   Profiler prof;
 };
@@ -55,7 +72,7 @@ struct isx_mesh {
   float* tri_pos = nullptr;
   uint64_t* tri_keys = nullptr;
   int32_t* tri_iso = nullptr;
-  std::vector<int64_t> lvl_cells, lvl_active, lvl_recheck;
+  std::vector<int64_t> lvl_cells, lvl_active, lvl_recheck, lvl_prop;
   std::vector<std::vector<uint32_t>> lvl_ids, lvl_masks;
   std::vector<std::vector<float>> lvl_out;
   bool kept = false;
@@ -271,6 +288,12 @@ isx_status isx_destroy(isx_ctx* ctx) {
                  &ctx->rc_count, &ctx->bitmap, &ctx->word_prefix, &ctx->corner_g, &ctx->corner_pts,
                  &ctx->corner_vals, &ctx->tri_off, &ctx->cls_mask};
   for (Buf* b : bufs) release(*b);
+  Buf* sbufs[] = {&ctx->sur_out, &ctx->sur_T, &ctx->sur_d[0], &ctx->sur_d[1], &ctx->sp_pred, &ctx->sp_fb,
+                  &ctx->sp_idx, &ctx->sp_pm, &ctx->sp_c, &ctx->sp_h, &ctx->sp_out, &ctx->sp_mask, &ctx->sp_cnt,
+                  &ctx->sp_tmp, &ctx->rc_flags, &ctx->rc_fidx, &ctx->rc_fmask};
+  for (Buf* b : sbufs) release(*b);
+  for (Buf& b : ctx->sur_act) release(b);
+  for (int i = 0; i < (int)ctx->surs.size(); ++i) isx_surrogate_free(ctx, i);
   if (ctx->h_count) (void)hipHostFree(ctx->h_count);
   delete ctx;
   return ISX_OK;
@@ -493,6 +516,72 @@ static isx_status read_count(isx_ctx* ctx, const int64_t* d, int64_t* h) {
   return ISX_OK;
 }
 
+// Propagate n cells, classify them (closed soft/hard bound, parent masks) and
+// re-check in float64 the cells within the band.  Writes out[n][2], mask[n].
+static isx_status prop_classify(isx_ctx* ctx, const Model& m, const isx_params* p, float k, const IsoList& iso,
+                                int64_t n, const float* centres, const float* halves, const uint32_t* pmask,
+                                float* out, uint32_t* mask, int64_t* n_rc_out) {
+  hipStream_t s = ctx->stream;
+  *n_rc_out = 0;
+  if (n <= 0) return ISX_OK;
+  isx_status st = run_propagate(ctx, m, p->method, p->precision, n, centres, halves, out, nullptr, p->chunk_cells);
+  if (st != ISX_OK) return st;
+  HIPCHK(launch_classify(n, out, k, iso, pmask, mask, s));
+  if (!(p->fp64_band > 0.f) || p->precision == ISX_FP64) return ISX_OK;
+  HIPCHK(ensure(ctx->rc_flags, n * 4));
+  HIPCHK(ensure(ctx->rc_fidx, n * 4));
+  HIPCHK(ensure(ctx->rc_count, sizeof(int64_t)));
+  HIPCHK(ensure(ctx->scan_tmp, compact_tmp_bytes(n)));
+  HIPCHK(launch_band_flags(n, out, k, iso, pmask, p->fp64_band, (uint32_t*)ctx->rc_flags.p, s));
+  HIPCHK(launch_compact(n, (const uint32_t*)ctx->rc_flags.p, nullptr, (uint32_t*)ctx->rc_fidx.p, nullptr,
+                        (int64_t*)ctx->rc_count.p, ctx->scan_tmp.p, s));
+  int64_t n_rc = 0;
+  st = read_count(ctx, (const int64_t*)ctx->rc_count.p, &n_rc);
+  if (st != ISX_OK) return st;
+  if (n_rc > 0) {
+    HIPCHK(ensure(ctx->rc_centres, n_rc * 12));
+    HIPCHK(ensure(ctx->rc_halves, n_rc * 12));
+    HIPCHK(ensure(ctx->rc_out32, n_rc * 8));
+    HIPCHK(ensure(ctx->rc_out64, n_rc * 16));
+    HIPCHK(launch_gather_boxes(n_rc, (const uint32_t*)ctx->rc_fidx.p, centres, halves, (float*)ctx->rc_centres.p,
+                               (float*)ctx->rc_halves.p, s));
+    st = run_propagate(ctx, m, p->method, ISX_FP64, n_rc, (const float*)ctx->rc_centres.p,
+                       (const float*)ctx->rc_halves.p, (float*)ctx->rc_out32.p, (double*)ctx->rc_out64.p,
+                       p->chunk_cells);
+    if (st != ISX_OK) return st;
+    HIPCHK(launch_recheck_apply(n_rc, (const uint32_t*)ctx->rc_fidx.p, (const double*)ctx->rc_out64.p, (double)k, iso,
+                                pmask, out, mask, s));
+  }
+  *n_rc_out = n_rc;
+  return ISX_OK;
+}
+
+static Sur* get_sur(isx_ctx* ctx, int32_t id) {
+  if (!ctx || id < 0 || id >= (int32_t)ctx->surs.size() || !ctx->surs[id].live) return nullptr;
+  return &ctx->surs[id];
+}
+
+// Surrogate forward pass over n cells, (mu_hat, sigma_hat) in field units.
+static isx_status sur_predict_n(isx_ctx* ctx, Sur& S, int64_t n, const float* centres, const float* halves,
+                                float* out) {
+  hipStream_t s = ctx->stream;
+  const int64_t chunk = std::min<int64_t>(n, (int64_t)1 << 20);
+  for (int l = 0; l < S.L; ++l) HIPCHK(ensure(ctx->sur_act[l], (size_t)chunk * S.w[l] * 4));
+  HIPCHK(ensure(ctx->sur_out, (size_t)chunk * 8));
+  for (int64_t r0 = 0; r0 < n; r0 += chunk) {
+    const int B = (int)std::min<int64_t>(chunk, n - r0);
+    HIPCHK(sur_features(n, r0, B, centres, halves, S.size_a, S.size_b, (float*)ctx->sur_act[0].p, nullptr, 0.f, 1.f,
+                        nullptr, s));
+    for (int l = 0; l < S.L; ++l) {
+      float* C = l + 1 < S.L ? (float*)ctx->sur_act[l + 1].p : (float*)ctx->sur_out.p;
+      HIPCHK(sur_gemm(B, S.w[l + 1], S.w[l], (const float*)ctx->sur_act[l].p, S.w[l], false, S.W[l], S.w[l], true, C,
+                      S.w[l + 1], S.b[l], l + 1 < S.L, nullptr, 0, s));
+    }
+    HIPCHK(sur_unstd(B, (const float*)ctx->sur_out.p, S.mu_bar, S.scale, out + 2 * r0, s));
+  }
+  return ISX_OK;
+}
+
 isx_status isx_extract(isx_ctx* ctx, int32_t mlp_id, const isx_params* p, isx_mesh** out) {
   Model* mp = get_model(ctx, mlp_id);
   if (!mp || !p || !out) return fail(ctx, ISX_EINVAL, "bad arguments");
@@ -511,7 +600,6 @@ isx_status isx_extract(isx_ctx* ctx, int32_t mlp_id, const isx_params* p, isx_me
   const int64_t cap = p->max_cells > 0 ? p->max_cells : (int64_t)1 << 28;
   const IsoList iso = iso_list(m);
   const uint32_t full = m.n_iso >= 32 ? 0xffffffffu : ((1u << m.n_iso) - 1u);
-  const bool recheck = p->fp64_band > 0.f && p->precision != ISX_FP64;
 
   hipEvent_t ev[4];
   for (auto& e : ev) HIPCHK(hipEventCreate(&e));
@@ -560,35 +648,46 @@ isx_status isx_extract(isx_ctx* ctx, int32_t mlp_id, const isx_params* p, isx_me
       XCHK(launch_children(m, L, n_par, (const uint32_t*)ctx->act_ids[cur].p, (const uint32_t*)ctx->act_mask[cur].p,
                            ids, pmask, centres, halves, s));
     }
-    isx_status st = run_propagate(ctx, m, p->method, p->precision, n, centres, halves, outb, nullptr, p->chunk_cells);
-    if (st != ISX_OK) return bail(st);
-    XCHK(launch_classify(n, outb, k, iso, pmask, mask, s));
-    int64_t n_rc = 0;
-    if (recheck) {
-      XCHK(ensure(ctx->rc_idx, n * 4));
-      XCHK(ensure(ctx->rc_count, sizeof(int64_t)));
-      XCHK(launch_band_flags(n, outb, k, iso, pmask, p->fp64_band, (uint32_t*)ctx->rc_idx.p, s));
-      // compact flags -> indices (reuse act_mask[cur^1] as scratch for the flag masks)
-      XCHK(launch_compact(n, (const uint32_t*)ctx->rc_idx.p, nullptr, (uint32_t*)ctx->act_ids[cur ^ 1].p,
-                          (uint32_t*)ctx->act_mask[cur ^ 1].p, (int64_t*)ctx->rc_count.p, ctx->scan_tmp.p, s));
-      st = read_count(ctx, (const int64_t*)ctx->rc_count.p, &n_rc);
+    int64_t n_rc = 0, n_prop = n;
+    isx_status st = ISX_OK;
+    Sur* S = p->use_surrogate ? get_sur(ctx, m.sur_id) : nullptr;
+    if (p->use_surrogate && !S) return bail(fail(ctx, ISX_EINVAL, "use_surrogate set but no surrogate attached"));
+    if (!S) {
+      st = prop_classify(ctx, m, p, k, iso, n, centres, halves, pmask, outb, mask, &n_rc);
       if (st != ISX_OK) return bail(st);
-      if (n_rc > 0) {
-        XCHK(ensure(ctx->rc_idx, n_rc * 4));
-        XCHK(ensure(ctx->rc_centres, n_rc * 12));
-        XCHK(ensure(ctx->rc_halves, n_rc * 12));
-        XCHK(ensure(ctx->rc_out32, n_rc * 8));
-        XCHK(ensure(ctx->rc_out64, n_rc * 16));
-        XCHK(hipMemcpyAsync(ctx->rc_idx.p, ctx->act_ids[cur ^ 1].p, n_rc * 4, hipMemcpyDeviceToDevice, s));
-        XCHK(launch_gather_boxes(n_rc, (const uint32_t*)ctx->rc_idx.p, centres, halves, (float*)ctx->rc_centres.p,
-                                 (float*)ctx->rc_halves.p, s));
-        st = run_propagate(ctx, m, p->method, ISX_FP64, n_rc, (const float*)ctx->rc_centres.p,
-                           (const float*)ctx->rc_halves.p, (float*)ctx->rc_out32.p, (double*)ctx->rc_out64.p,
-                           p->chunk_cells);
+    } else {
+      // surrogate decides the confident cells, the others are propagated
+      XCHK(ensure(ctx->sp_pred, n * 8));
+      XCHK(ensure(ctx->sp_fb, n * 4));
+      XCHK(ensure(ctx->sp_idx, n * 4));
+      XCHK(ensure(ctx->sp_cnt, sizeof(int64_t)));
+      st = sur_predict_n(ctx, *S, n, centres, halves, (float*)ctx->sp_pred.p);
+      if (st != ISX_OK) return bail(st);
+      const int Ls = std::min(L, std::max(0, m.sur_levels - 1));
+      XCHK(sur_partition(n, (const float*)ctx->sp_pred.p, k, iso, pmask, m.sur_err_mu[Ls], m.sur_err_ls[Ls], m.sur_z,
+                         L == p->max_depth ? 1 : 0, m.sur_accept_leaves, mask, (uint32_t*)ctx->sp_fb.p, s));
+      XCHK(hipMemcpyAsync(outb, ctx->sp_pred.p, n * 8, hipMemcpyDeviceToDevice, s));
+      XCHK(launch_compact(n, (const uint32_t*)ctx->sp_fb.p, nullptr, (uint32_t*)ctx->sp_idx.p, nullptr,
+                          (int64_t*)ctx->sp_cnt.p, ctx->scan_tmp.p, s));
+      int64_t n_fb = 0;
+      st = read_count(ctx, (const int64_t*)ctx->sp_cnt.p, &n_fb);
+      if (st != ISX_OK) return bail(st);
+      if (n_fb > 0) {
+        XCHK(ensure(ctx->sp_c, n_fb * 12));
+        XCHK(ensure(ctx->sp_h, n_fb * 12));
+        XCHK(ensure(ctx->sp_pm, n_fb * 4));
+        XCHK(ensure(ctx->sp_out, n_fb * 8));
+        XCHK(ensure(ctx->sp_mask, n_fb * 4));
+        const uint32_t* fidx = (const uint32_t*)ctx->sp_idx.p;
+        XCHK(launch_gather_boxes(n_fb, fidx, centres, halves, (float*)ctx->sp_c.p, (float*)ctx->sp_h.p, s));
+        XCHK(gather_u32(n_fb, fidx, pmask, (uint32_t*)ctx->sp_pm.p, s));
+        st = prop_classify(ctx, m, p, k, iso, n_fb, (const float*)ctx->sp_c.p, (const float*)ctx->sp_h.p,
+                           (const uint32_t*)ctx->sp_pm.p, (float*)ctx->sp_out.p, (uint32_t*)ctx->sp_mask.p, &n_rc);
         if (st != ISX_OK) return bail(st);
-        XCHK(launch_recheck_apply(n_rc, (const uint32_t*)ctx->rc_idx.p, (const double*)ctx->rc_out64.p, (double)k,
-                                  iso, pmask, outb, mask, s));
+        XCHK(scatter_u32(n_fb, fidx, (const uint32_t*)ctx->sp_mask.p, mask, s));
+        XCHK(scatter_u64(n_fb, fidx, (const uint64_t*)ctx->sp_out.p, (uint64_t*)outb, s));
       }
+      n_prop = n_fb;
     }
     XCHK(launch_compact(n, mask, ids, (uint32_t*)ctx->act_ids[cur ^ 1].p, (uint32_t*)ctx->act_mask[cur ^ 1].p,
                         (int64_t*)ctx->count.p, ctx->scan_tmp.p, s));
@@ -598,9 +697,10 @@ isx_status isx_extract(isx_ctx* ctx, int32_t mlp_id, const isx_params* p, isx_me
     mesh->lvl_cells.push_back(n);
     mesh->lvl_active.push_back(n_act);
     mesh->lvl_recheck.push_back(n_rc);
+    mesh->lvl_prop.push_back(n_prop);
     if (ctx->verbose) {
-      std::fprintf(stderr, "isx: level %d: %lld cells, %lld active, %lld re-checked\n", L, (long long)n,
-                   (long long)n_act, (long long)n_rc);
+      std::fprintf(stderr, "isx: level %d: %lld cells, %lld active, %lld propagated, %lld re-checked\n", L,
+                   (long long)n, (long long)n_act, (long long)n_prop, (long long)n_rc);
       std::fflush(stderr);
     }
     if (ctx->keep_levels) {
@@ -702,11 +802,12 @@ isx_status isx_mesh_info(const isx_mesh* mesh, int64_t* n_tris, int64_t* n_leave
 }
 
 isx_status isx_mesh_level(const isx_mesh* mesh, int32_t level, int64_t* n_cells, int64_t* n_active,
-                          int64_t* n_rechecked) {
+                          int64_t* n_rechecked, int64_t* n_propagated) {
   if (!mesh || level < 0 || level >= (int32_t)mesh->lvl_cells.size()) return ISX_EINVAL;
   if (n_cells) *n_cells = mesh->lvl_cells[level];
   if (n_active) *n_active = mesh->lvl_active[level];
   if (n_rechecked) *n_rechecked = mesh->lvl_recheck[level];
+  if (n_propagated) *n_propagated = mesh->lvl_prop[level];
   return ISX_OK;
 }
 
@@ -756,6 +857,203 @@ isx_status isx_mesh_free(isx_mesh* mesh) {
   for (void* q : ps)
     if (q) (void)hipFree(q);
   delete mesh;
+  return ISX_OK;
+}
+
+isx_status isx_surrogate_load(isx_ctx* ctx, int32_t n_linear, const int32_t* widths, const float* const* h_W,
+                              const float* const* h_b, int32_t* sur_id) {
+  if (!ctx || !widths || !h_W || !h_b || !sur_id) return fail(ctx, ISX_EINVAL, "null argument");
+  if (n_linear < 1 || n_linear > ISX_MAX_LINEAR) return fail(ctx, ISX_ESHAPE, "bad surrogate depth");
+  if (widths[0] != 4 || widths[n_linear] != 2) return fail(ctx, ISX_ESHAPE, "surrogate widths must be 4 -> ... -> 2");
+  for (int l = 1; l < n_linear; ++l)
+    if (widths[l] < 1 || widths[l] > ISX_MAX_WIDTH) return fail(ctx, ISX_ESHAPE, "bad surrogate hidden width");
+  for (int l = 0; l < n_linear; ++l) {
+    if (!h_W[l] || !h_b[l]) return fail(ctx, ISX_EINVAL, "null weight pointer");
+    for (int64_t i = 0; i < (int64_t)widths[l] * widths[l + 1]; ++i)
+      if (!std::isfinite(h_W[l][i])) return fail(ctx, ISX_ENAN, "non-finite surrogate weight");
+    for (int i = 0; i < widths[l + 1]; ++i)
+      if (!std::isfinite(h_b[l][i])) return fail(ctx, ISX_ENAN, "non-finite surrogate bias");
+  }
+  (void)hipSetDevice(ctx->device);
+  Sur S;
+  S.L = n_linear;
+  for (int l = 0; l <= n_linear; ++l) S.w[l] = widths[l];
+  for (int l = 0; l < n_linear; ++l) {
+    const size_t nw = (size_t)widths[l] * widths[l + 1], nb = (size_t)widths[l + 1];
+    std::vector<float> W(h_W[l], h_W[l] + nw), b(h_b[l], h_b[l] + nb), zw(nw, 0.f), zb(nb, 0.f);
+    hipError_t e = upload(&S.W[l], W);
+    if (e == hipSuccess) e = upload(&S.b[l], b);
+    if (e == hipSuccess) e = upload(&S.mW[l], zw);
+    if (e == hipSuccess) e = upload(&S.vW[l], zw);
+    if (e == hipSuccess) e = upload(&S.gW[l], zw);
+    if (e == hipSuccess) e = upload(&S.mb[l], zb);
+    if (e == hipSuccess) e = upload(&S.vb[l], zb);
+    if (e == hipSuccess) e = upload(&S.gb[l], zb);
+    if (e != hipSuccess) return hip_fail(ctx, e, "isx_surrogate_load upload");
+  }
+  S.live = true;
+  ctx->surs.push_back(S);
+  *sur_id = (int32_t)ctx->surs.size() - 1;
+  return ISX_OK;
+}
+
+isx_status isx_surrogate_free(isx_ctx* ctx, int32_t sur_id) {
+  Sur* S = get_sur(ctx, sur_id);
+  if (!S) return fail(ctx, ISX_EINVAL, "no such surrogate");
+  (void)hipStreamSynchronize(ctx->stream);
+  for (int l = 0; l < S->L; ++l) {
+    float* ps[] = {S->W[l], S->b[l], S->mW[l], S->vW[l], S->mb[l], S->vb[l], S->gW[l], S->gb[l]};
+    for (float* q : ps)
+      if (q) (void)hipFree(q);
+  }
+  *S = Sur{};
+  for (Model& m : ctx->models)
+    if (m.sur_id == sur_id) m.sur_id = -1;
+  return ISX_OK;
+}
+
+isx_status isx_surrogate_get(isx_ctx* ctx, int32_t sur_id, float* const* h_W, float* const* h_b) {
+  Sur* S = get_sur(ctx, sur_id);
+  if (!S || !h_W || !h_b) return fail(ctx, ISX_EINVAL, "bad arguments");
+  (void)hipSetDevice(ctx->device);
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  for (int l = 0; l < S->L; ++l) {
+    HIPCHK(hipMemcpy(h_W[l], S->W[l], (size_t)S->w[l] * S->w[l + 1] * 4, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(h_b[l], S->b[l], (size_t)S->w[l + 1] * 4, hipMemcpyDeviceToHost));
+  }
+  return ISX_OK;
+}
+
+isx_status isx_surrogate_set_norm(isx_ctx* ctx, int32_t sur_id, float mu_bar, float scale, float size_a,
+                                  float size_b) {
+  Sur* S = get_sur(ctx, sur_id);
+  if (!S) return fail(ctx, ISX_EINVAL, "no such surrogate");
+  if (!std::isfinite(mu_bar) || !(scale > 0.f) || !std::isfinite(scale) || !std::isfinite(size_a) ||
+      !std::isfinite(size_b))
+    return fail(ctx, ISX_EINVAL, "bad normalisation");
+  S->mu_bar = mu_bar;
+  S->scale = scale;
+  S->size_a = size_a;
+  S->size_b = size_b;
+  return ISX_OK;
+}
+
+// One forward and backward pass on rows [r0, r0 + batch) (wrapping) of the
+// training set; leaves the gradients in S.gW / S.gb.
+static isx_status sur_fwd_bwd(isx_ctx* ctx, Sur& S, int64_t n, const float* d_centres, const float* d_halves,
+                              const float* d_targets, int64_t r0, int batch, float* d_loss) {
+  hipStream_t s = ctx->stream;
+  int wmax = 2;
+  for (int l = 0; l <= S.L; ++l) wmax = std::max(wmax, S.w[l]);
+  for (int l = 0; l < S.L; ++l) HIPCHK(ensure(ctx->sur_act[l], (size_t)batch * S.w[l] * 4));
+  HIPCHK(ensure(ctx->sur_out, (size_t)batch * 8));
+  HIPCHK(ensure(ctx->sur_T, (size_t)batch * 8));
+  HIPCHK(ensure(ctx->sur_d[0], (size_t)batch * wmax * 4));
+  HIPCHK(ensure(ctx->sur_d[1], (size_t)batch * wmax * 4));
+  HIPCHK(sur_features(n, r0, batch, d_centres, d_halves, S.size_a, S.size_b, (float*)ctx->sur_act[0].p, d_targets,
+                      S.mu_bar, S.scale, (float*)ctx->sur_T.p, s));
+  for (int l = 0; l < S.L; ++l) {
+    float* C = l + 1 < S.L ? (float*)ctx->sur_act[l + 1].p : (float*)ctx->sur_out.p;
+    HIPCHK(sur_gemm(batch, S.w[l + 1], S.w[l], (const float*)ctx->sur_act[l].p, S.w[l], false, S.W[l], S.w[l], true, C,
+                    S.w[l + 1], S.b[l], l + 1 < S.L, nullptr, 0, s));
+  }
+  int cur = 0;
+  HIPCHK(sur_loss(batch, (const float*)ctx->sur_out.p, (const float*)ctx->sur_T.p, (float*)ctx->sur_d[cur].p, d_loss,
+                  s));
+  for (int l = S.L - 1; l >= 0; --l) {
+    const float* dY = (const float*)ctx->sur_d[cur].p;
+    // dW = dY^T H_l,  db = column sums of dY,  dH_l = (dY W_l) . [H_l > 0]
+    HIPCHK(sur_gemm(S.w[l + 1], S.w[l], batch, dY, S.w[l + 1], true, (const float*)ctx->sur_act[l].p, S.w[l], false,
+                    S.gW[l], S.w[l], nullptr, false, nullptr, 0, s));
+    HIPCHK(sur_colsum(batch, S.w[l + 1], dY, S.gb[l], s));
+    if (l > 0) {
+      HIPCHK(sur_gemm(batch, S.w[l], S.w[l + 1], dY, S.w[l + 1], false, S.W[l], S.w[l], false,
+                      (float*)ctx->sur_d[cur ^ 1].p, S.w[l], nullptr, false, (const float*)ctx->sur_act[l].p, S.w[l],
+                      s));
+      cur ^= 1;
+    }
+  }
+  return ISX_OK;
+}
+
+isx_status isx_surrogate_grad(isx_ctx* ctx, int32_t sur_id, int64_t n, const float* d_centres, const float* d_halves,
+                              const float* d_targets, int64_t first_row, int32_t batch, float* const* h_gW,
+                              float* const* h_gb, float* h_loss) {
+  Sur* Sp = get_sur(ctx, sur_id);
+  if (!Sp) return fail(ctx, ISX_EINVAL, "no such surrogate");
+  if (n <= 0 || !d_centres || !d_halves || !d_targets || batch < 1 || first_row < 0 || !h_gW || !h_gb)
+    return fail(ctx, ISX_EINVAL, "bad arguments");
+  (void)hipSetDevice(ctx->device);
+  Sur& S = *Sp;
+  HIPCHK(ensure(ctx->sp_cnt, sizeof(float) * 2));
+  isx_status e = sur_fwd_bwd(ctx, S, n, d_centres, d_halves, d_targets, first_row % n, batch, (float*)ctx->sp_cnt.p);
+  if (e != ISX_OK) return e;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  for (int l = 0; l < S.L; ++l) {
+    HIPCHK(hipMemcpy(h_gW[l], S.gW[l], (size_t)S.w[l] * S.w[l + 1] * 4, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(h_gb[l], S.gb[l], (size_t)S.w[l + 1] * 4, hipMemcpyDeviceToHost));
+  }
+  if (h_loss) HIPCHK(hipMemcpy(h_loss, ctx->sp_cnt.p, sizeof(float), hipMemcpyDeviceToHost));
+  return ISX_OK;
+}
+
+isx_status isx_surrogate_train(isx_ctx* ctx, int32_t sur_id, int64_t n, const float* d_centres, const float* d_halves,
+                               const float* d_targets, int64_t first_row, int32_t steps, int32_t batch, float lr,
+                               float* d_loss) {
+  Sur* Sp = get_sur(ctx, sur_id);
+  if (!Sp) return fail(ctx, ISX_EINVAL, "no such surrogate");
+  Sur& S = *Sp;
+  if (n <= 0 || !d_centres || !d_halves || !d_targets || steps < 0 || batch < 1 || first_row < 0 ||
+      !(lr > 0.f))
+    return fail(ctx, ISX_EINVAL, "bad training arguments");
+  (void)hipSetDevice(ctx->device);
+  hipStream_t s = ctx->stream;
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  for (int st = 0; st < steps; ++st) {
+    const int64_t r0 = (first_row + (int64_t)st * batch) % n;
+    isx_status e = sur_fwd_bwd(ctx, S, n, d_centres, d_halves, d_targets, r0, batch, d_loss ? d_loss + st : nullptr);
+    if (e != ISX_OK) return e;
+    S.t += 1;
+    const float c1 = 1.f - std::pow(b1, (float)S.t), c2 = 1.f - std::pow(b2, (float)S.t);
+    for (int l = 0; l < S.L; ++l) {
+      HIPCHK(sur_adam(S.w[l] * S.w[l + 1], S.W[l], S.gW[l], S.mW[l], S.vW[l], lr, b1, b2, eps, c1, c2, s));
+      HIPCHK(sur_adam(S.w[l + 1], S.b[l], S.gb[l], S.mb[l], S.vb[l], lr, b1, b2, eps, c1, c2, s));
+    }
+  }
+  return ISX_OK;
+}
+
+isx_status isx_surrogate_predict(isx_ctx* ctx, int32_t sur_id, int64_t n, const float* d_centres,
+                                 const float* d_halves, float* d_out) {
+  Sur* S = get_sur(ctx, sur_id);
+  if (!S) return fail(ctx, ISX_EINVAL, "no such surrogate");
+  if (n < 0 || (n > 0 && (!d_centres || !d_halves || !d_out))) return fail(ctx, ISX_EINVAL, "bad arguments");
+  if (n == 0) return ISX_OK;
+  (void)hipSetDevice(ctx->device);
+  return sur_predict_n(ctx, *S, n, d_centres, d_halves, d_out);
+}
+
+isx_status isx_surrogate_attach(isx_ctx* ctx, int32_t mlp_id, int32_t sur_id, int32_t n_levels,
+                                const float* h_err_mu, const float* h_err_logsig, float z, int32_t accept_leaves) {
+  Model* m = get_model(ctx, mlp_id);
+  if (!m) return fail(ctx, ISX_EINVAL, "bad mlp id");
+  if (sur_id == -1) {
+    m->sur_id = -1;
+    return ISX_OK;
+  }
+  if (!get_sur(ctx, sur_id)) return fail(ctx, ISX_EINVAL, "no such surrogate");
+  if (n_levels < 1 || n_levels > 16 || !h_err_mu || !h_err_logsig || !(z >= 0.f))
+    return fail(ctx, ISX_EINVAL, "bad surrogate band");
+  for (int i = 0; i < n_levels; ++i)
+    if (!(h_err_mu[i] >= 0.f) || !(h_err_logsig[i] >= 0.f)) return fail(ctx, ISX_EINVAL, "bad error scales");
+  m->sur_id = sur_id;
+  m->sur_levels = n_levels;
+  for (int i = 0; i < 16; ++i) {
+    m->sur_err_mu[i] = i < n_levels ? h_err_mu[i] : h_err_mu[n_levels - 1];
+    m->sur_err_ls[i] = i < n_levels ? h_err_logsig[i] : h_err_logsig[n_levels - 1];
+  }
+  m->sur_z = z;
+  m->sur_accept_leaves = accept_leaves ? 1 : 0;
   return ISX_OK;
 }
 

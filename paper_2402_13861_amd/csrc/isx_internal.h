@@ -42,6 +42,12 @@ struct Model {
   float lo[3] = {-1.f, -1.f, -1.f}, hi[3] = {1.f, 1.f, 1.f};
   int n_iso = 0;
   float iso[ISX_MAX_ISO] = {};
+  // surrogate attached for extraction (-1 = none)
+  int sur_id = -1;
+  int sur_levels = 0;
+  float sur_err_mu[16] = {}, sur_err_ls[16] = {};
+  float sur_z = 2.f;
+  int sur_accept_leaves = 0;
   int hidden() const { return n_linear - 1; }
   // columns of hidden layer h's coefficient block (h = 1..hidden())
   int64_t cols(int h) const {
@@ -194,6 +200,23 @@ hipError_t launch_mc_emit(const Model& m, int depth, int64_t n_leaves, const uin
                           const float* corner_vals, const uint32_t* tri_offsets, float* tri_pos,
                           uint64_t* tri_keys, int32_t* tri_iso, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
+
+// ---- surrogate kernels (kernels_sur.hip) ----
+hipError_t sur_gemm(int M, int N, int K, const float* A, int lda, bool ta, const float* B, int ldb, bool tb, float* C,
+                    int ldc, const float* bias, bool relu, const float* mask, int ldm, hipStream_t s);
+hipError_t sur_features(int64_t n, int64_t r0, int B, const float* centres, const float* halves, float a, float b,
+                        float* X, const float* mu_sigma, float mu_bar, float scale, float* T, hipStream_t s);
+hipError_t sur_loss(int B, const float* out, const float* T, float* dout, float* loss_out, hipStream_t s);
+hipError_t sur_colsum(int M, int N, const float* dY, float* db, hipStream_t s);
+hipError_t sur_adam(int n, float* p, const float* g, float* m, float* v, float lr, float b1, float b2, float eps,
+                    float c1, float c2, hipStream_t s);
+hipError_t sur_unstd(int64_t n, const float* o, float mu_bar, float scale, float* out, hipStream_t s);
+hipError_t sur_partition(int64_t n, const float* pred, float k, const IsoList& iso, const uint32_t* pmask,
+                         float err_mu, float err_ls, float z, int leaf, int accept_leaves, uint32_t* mask,
+                         uint32_t* fallback, hipStream_t s);
+hipError_t gather_u32(int64_t n, const uint32_t* idx, const uint32_t* src, uint32_t* dst, hipStream_t s);
+hipError_t scatter_u32(int64_t n, const uint32_t* idx, const uint32_t* src, uint32_t* dst, hipStream_t s);
+hipError_t scatter_u64(int64_t n, const uint32_t* idx, const uint64_t* src, uint64_t* dst, hipStream_t s);
 
 // ---- marching-cubes case table (mc_table.cpp) ----
 struct McTable {

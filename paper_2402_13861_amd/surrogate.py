@@ -1,0 +1,202 @@
+"""Training pipeline of the learned surrogate (orchestration only; every
+propagation, forward/backward pass and optimiser step runs in the library's
+HIP kernels).
+
+The surrogate is a ReLU MLP 4 -> 128 -> 128 -> 128 -> 2 that maps a cell
+(centre, log2 size) to the propagation's predicted (mean, sigma).  It is
+trained on (cell, propagated mean/sigma) pairs produced by the method itself:
+half are uniform random cells at octree levels 3..D, half are cells visited
+by a plain extraction.  Its error is calibrated per octree level on held-out
+pairs; during extraction a cell is decided by the surrogate only when every
+iso-value it carries lies outside (or inside) the predicted soft bound by
+more than z = 2 standard deviations of that error, and is propagated
+otherwise.
+"""
+
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+from . import _lib
+
+SIZE_A = 0.25  # size feature: a * log2(cell size) + b (maps levels 0..10 into [-1.5, 1])
+SIZE_B = 1.0
+
+
+def _morton_decode(ids):
+    ids = np.asarray(ids, dtype=np.uint64)
+    out = []
+    for axis in range(3):
+        v = np.zeros(ids.shape, dtype=np.int64)
+        for t in range(11):
+            v |= (((ids >> np.uint64(3 * t + axis)) & np.uint64(1)).astype(np.int64)) << t
+        out.append(v)
+    return np.stack(out, axis=1)
+
+
+def level_boxes(level: int, ids, lo=(-1.0,) * 3, hi=(1.0,) * 3):
+    """Centres and half-widths (float32) of Morton cells at a level."""
+    ijk = _morton_decode(ids).astype(np.float64)
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    step = (hi - lo) / (2.0 ** (level + 1))
+    c = lo[None, :] + (2 * ijk + 1) * step[None, :]
+    h = np.broadcast_to(step, c.shape)
+    return c.astype(np.float32), np.ascontiguousarray(h, dtype=np.float32)
+
+
+def random_level_cells(n: int, levels, rng, lo=(-1.0,) * 3, hi=(1.0,) * 3):
+    L = rng.choice(np.asarray(list(levels)), size=n)
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    ijk = np.floor(rng.random((n, 3)) * (2.0 ** L)[:, None])
+    step = (hi - lo)[None, :] / (2.0 ** (L + 1))[:, None]
+    c = lo[None, :] + (2 * ijk + 1) * step
+    return c.astype(np.float32), step.astype(np.float32), L
+
+
+@dataclass
+class SurrogateInfo:
+    sid: int
+    n_pairs: int
+    steps: int
+    train_seconds: float
+    final_loss: float
+    err_mu: List[float] = field(default_factory=list)
+    err_logsig: List[float] = field(default_factory=list)
+    losses: Optional[np.ndarray] = None
+    z: float = 2.0
+
+
+def miss_rate(pred, true, levels, err_mu, err_ls, isos, k, z):
+    """Fraction of held-out cells that the plain test keeps for some iso-value
+    but the surrogate rule at band z would drop for that iso-value."""
+    mu_h, sg_h = pred[:, 0], pred[:, 1]
+    mu, sg = true[:, 0], true[:, 1]
+    em = np.asarray(err_mu)[levels]
+    el = np.asarray(err_ls)[levels]
+    hi_s = k * sg_h * np.exp(z * el)
+    miss = np.zeros(len(mu), dtype=bool)
+    kept = np.zeros(len(mu), dtype=bool)
+    for c in isos:
+        plain_keep = np.abs(mu - c) <= k * sg
+        drop = np.abs(mu_h - c) - z * em > hi_s
+        kept |= plain_keep
+        miss |= plain_keep & drop
+    return miss.sum() / max(kept.sum(), 1)
+
+
+def train_surrogate(ctx, mlp_id: int, depth: int, mu_bar: float, scale: float, visited=None,
+                    n_pairs: int = 5_000_000, steps: int = 2000, batch: int = 4096, lr: float = 1e-3,
+                    hidden=(128, 128, 128), seed: int = 0, holdout: int = 200_000, z: Optional[float] = None,
+                    isos=None, k: float = 3.0, miss_target: float = 1e-4, accept_leaves: bool = False,
+                    lo=(-1.0,) * 3, hi=(1.0,) * 3, log=None) -> SurrogateInfo:
+    """Train a surrogate for ``mlp_id`` and attach it for extraction.
+
+    visited: optional list, per octree level, of Morton ids of cells a plain
+    extraction propagated; half of the training pairs are drawn from them.
+    Targets are the float32 uncertainty propagation of each training cell.
+    The safety band is z standard deviations of the surrogate's per-level
+    error; with z None it is the smallest of a ladder of values whose miss
+    rate on the held-out cells (against the iso-values ``isos`` and the
+    bound multiplier k) is at most ``miss_target``.
+    """
+    import torch
+
+    log = log or (lambda *a: None)
+    rng = np.random.default_rng(seed)
+    n_train = n_pairs
+    n_total = n_train + holdout
+    # --- training cells: half random levels 3..depth, half visited cells
+    n_vis = n_total // 2 if visited else 0
+    parts_c, parts_h, parts_L = [], [], []
+    if n_vis:
+        sizes = np.array([len(v) for v in visited], dtype=np.float64)
+        p = sizes / sizes.sum()
+        counts = rng.multinomial(n_vis, p)
+        for L, (ids, cnt) in enumerate(zip(visited, counts)):
+            if cnt == 0 or len(ids) == 0:
+                continue
+            pick = np.asarray(ids)[rng.integers(0, len(ids), cnt)]
+            c, h = level_boxes(L, pick, lo, hi)
+            parts_c.append(c)
+            parts_h.append(h)
+            parts_L.append(np.full(cnt, L))
+    c, h, L = random_level_cells(n_total - n_vis, range(min(3, depth), depth + 1), rng, lo, hi)
+    parts_c.append(c)
+    parts_h.append(h)
+    parts_L.append(L)
+    centres = np.concatenate(parts_c)
+    halves = np.concatenate(parts_h)
+    levels = np.concatenate(parts_L)
+    perm = rng.permutation(n_total)
+    centres, halves, levels = centres[perm], halves[perm], levels[perm]
+
+    dev = torch.device("cuda", ctx.device)
+    C = torch.from_numpy(np.ascontiguousarray(centres)).to(dev)
+    H = torch.from_numpy(np.ascontiguousarray(halves)).to(dev)
+    T = torch.empty((n_total, 2), dtype=torch.float32, device=dev)
+    t0 = time.perf_counter()
+    ctx.propagate(mlp_id, _lib.UP, _lib.FP32, C, H, T)
+    torch.cuda.synchronize(dev)
+    log(f"surrogate: {n_total} training cells propagated in {time.perf_counter() - t0:.1f} s")
+
+    # --- model: He-normal weights N(0, 2/fan_in), small random biases
+    widths = [4, *hidden, 2]
+    Ws, bs = [], []
+    for fi, fo in zip(widths[:-1], widths[1:]):
+        std = np.sqrt(2.0 / fi)
+        Ws.append((rng.standard_normal((fo, fi)) * std).astype(np.float32))
+        bs.append((rng.standard_normal(fo) * std * 0.1).astype(np.float32))
+    sid = ctx.surrogate_load(Ws, bs)
+    ctx.surrogate_set_norm(sid, mu_bar, scale, SIZE_A, SIZE_B)
+
+    Ct, Ht, Tt = C[:n_train], H[:n_train], T[:n_train]
+    losses = torch.empty(steps, dtype=torch.float32, device=dev)
+    t0 = time.perf_counter()
+    ctx.surrogate_train(sid, Ct, Ht, Tt, steps=steps, batch=batch, lr=lr, loss=losses)
+    torch.cuda.synchronize(dev)
+    train_s = time.perf_counter() - t0
+    losses = losses.cpu().numpy()
+    log(f"surrogate: {steps} steps of batch {batch} in {train_s:.2f} s, loss {losses[0]:.4f} -> "
+        f"{losses[-20:].mean():.4f}")
+
+    # --- calibration on held-out cells: error std per level
+    Cv, Hv, Tv = C[n_train:], H[n_train:], T[n_train:]
+    P = torch.empty((holdout, 2), dtype=torch.float32, device=dev)
+    ctx.surrogate_predict(sid, Cv, Hv, P)
+    torch.cuda.synchronize(dev)
+    p = P.cpu().numpy().astype(np.float64)
+    tv = Tv.cpu().numpy().astype(np.float64)
+    lv = levels[n_train:]
+    err_mu, err_ls = [], []
+    for L in range(depth + 1):
+        sel = lv == L
+        if sel.sum() < 50:
+            err_mu.append(err_mu[-1] if err_mu else scale)
+            err_ls.append(err_ls[-1] if err_ls else 1.0)
+            continue
+        dmu = p[sel, 0] - tv[sel, 0]
+        dls = np.log(np.maximum(p[sel, 1], 1e-30)) - np.log(np.maximum(tv[sel, 1], 1e-30))
+        err_mu.append(float(np.sqrt(np.mean(dmu ** 2))))
+        err_ls.append(float(np.sqrt(np.mean(dls ** 2))))
+    log("surrogate: per-level error (mu, log sigma): " +
+        ", ".join(f"L{L} {a:.3g}/{b:.3g}" for L, (a, b) in enumerate(zip(err_mu, err_ls))))
+    if z is None:
+        if isos is None:
+            raise ValueError("z=None calibrates the band and needs the iso-values")
+        rates = {}
+        for zc in (2.0, 2.5, 3.0, 3.5, 4.0, 5.0, 6.0, 8.0, 12.0):
+            rates[zc] = miss_rate(p, tv, lv, err_mu, err_ls, isos, k, zc)
+            if rates[zc] <= miss_target:
+                break
+        z = zc
+        log("surrogate: held-out miss rate by band: " + ", ".join(f"z={a}: {b:.2e}" for a, b in rates.items()))
+    ctx.surrogate_attach(mlp_id, sid, err_mu, err_ls, z=z, accept_leaves=accept_leaves)
+    info = SurrogateInfo(sid, n_train, steps, train_s, float(losses[-20:].mean()), err_mu, err_ls, losses)
+    info.z = z
+    return info

@@ -1,0 +1,112 @@
+"""GPU tests of the learned surrogate: forward pass and gradients against
+the float64 oracle (bf16 operand tolerances), training progress, and the
+surrogate-assisted extraction's recall against the plain method."""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import surrogate as osg
+from oracle.mlp import mlp_forward
+from workloads import he_normal_mlp, random_boxes, uniform_points
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2402_13861_amd as isx
+
+    assert torch.cuda.is_available()
+    c = isx.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def _dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+def _sur_weights(seed=0):
+    m = he_normal_mlp([4, 128, 128, 128, 2], seed=seed)
+    return m.Ws, m.bs
+
+
+def test_surrogate_forward_matches_oracle(ctx):
+    Ws, bs = _sur_weights(1)
+    sid = ctx.surrogate_load(Ws, bs)
+    try:
+        ctx.surrogate_set_norm(sid, 0.3, 2.0, 0.25, 1.0)
+        c, h, _ = random_boxes(3001, range(0, 10), seed=2)
+        out = torch.empty((c.shape[0], 2), device="cuda")
+        ctx.surrogate_predict(sid, _dev(c), _dev(h), out)
+        torch.cuda.synchronize()
+        o, _ = osg.forward(Ws, bs, osg.features(c, h, 0.25, 1.0))
+        g = out.cpu().numpy().astype(np.float64)
+        std_g = np.stack([(g[:, 0] - 0.3) / 2.0, np.log(g[:, 1])], 1)
+        err = np.abs(std_g - o)
+        scale = np.abs(o).max(axis=0)
+        print("surrogate forward max abs err", err.max(axis=0), "output scale", scale, flush=True)
+        assert np.all(err.max(axis=0) <= 2e-2 * np.maximum(scale, 1.0))
+    finally:
+        ctx.surrogate_free(sid)
+
+
+def test_surrogate_gradients_match_oracle(ctx):
+    Ws, bs = _sur_weights(3)
+    sid = ctx.surrogate_load(Ws, bs)
+    try:
+        ctx.surrogate_set_norm(sid, 0.0, 1.0, 0.25, 1.0)
+        n = 512
+        c, h, _ = random_boxes(n, range(0, 10), seed=4)
+        rng = np.random.default_rng(5)
+        tgt = np.stack([rng.normal(0, 1, n), np.exp(rng.normal(-2, 1, n))], 1).astype(np.float32)
+        gW, gb, loss = ctx.surrogate_grad(sid, _dev(c), _dev(h), _dev(tgt), batch=n)
+        X = osg.features(c, h, 0.25, 1.0)
+        T = osg.targets(tgt[:, 0], tgt[:, 1], 0.0, 1.0)
+        out, acts = osg.forward(Ws, bs, X)
+        rW, rb = osg.backward(Ws, acts, out, T)
+        assert loss == pytest.approx(osg.loss(out, T), rel=2e-2)
+        for li in range(4):
+            for g, r in ((gW[li], rW[li]), (gb[li], rb[li])):
+                g = g.astype(np.float64).ravel()
+                r = r.ravel()
+                rel = np.linalg.norm(g - r) / max(np.linalg.norm(r), 1e-30)
+                cos = g @ r / max(np.linalg.norm(g) * np.linalg.norm(r), 1e-30)
+                print(f"layer {li}: rel L2 {rel:.3e} cosine {cos:.6f}", flush=True)
+                assert rel <= 2e-2 and cos >= 0.999
+    finally:
+        ctx.surrogate_free(sid)
+
+
+def test_extraction_with_surrogate_recall(ctx):
+    """Plain UP leaves vs surrogate-assisted leaves (3->64x3->1, depth 6)."""
+    import paper_2402_13861_amd as isx
+    from paper_2402_13861_amd.surrogate import train_surrogate
+
+    mlp = he_normal_mlp([3, 64, 64, 64, 1], seed=0)
+    vals = mlp_forward(mlp, uniform_points(10_000, seed=1))
+    isos = [float(np.float32(np.quantile(vals, q))) for q in (0.25, 0.5, 0.75)]
+    S = float(vals.std())
+    mid = ctx.load_weights(mlp)
+    try:
+        ctx.set_isovalues(mid, isos)
+        ctx.set_option(isx.KEEP_LEVELS, 1)
+        plain = ctx.extract(mid, isx.UP, isx.FP32, k=3.0, max_depth=6)
+        ctx.set_option(isx.KEEP_LEVELS, 0)
+        visited = [plain.level_cells(L)[0] for L in range(plain.n_levels)]
+        info = train_surrogate(ctx, mid, 6, float(vals.mean()), S, visited=visited, n_pairs=200_000, steps=800,
+                               batch=2048, holdout=20_000, seed=0, isos=isos, k=3.0, log=print)
+        assert info.losses[-50:].mean() < 0.3 * info.losses[:10].mean()
+        sur = ctx.extract(mid, isx.UP, isx.FP32, k=3.0, max_depth=6, use_surrogate=True)
+        p_ids, _ = plain.leaves()
+        s_ids, _ = sur.leaves()
+        recall = np.intersect1d(p_ids, s_ids).size / max(p_ids.size, 1)
+        lv = sur.levels()
+        print("recall", recall, "levels", [(l["cells"], l["propagated"], l["active"]) for l in lv], flush=True)
+        assert recall >= 0.999
+        assert sum(l["propagated"] for l in lv) < sum(l["cells"] for l in lv)
+    finally:
+        ctx.unload_mlp(mid)
