@@ -84,10 +84,16 @@ def cpu_baseline(mlp, levels, budget_s: float):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="relu256x5_fourier")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16"])
+    ap.add_argument("--no-surrogate", action="store_true", help="headline path without the learned surrogate")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 reference run")
+    ap.add_argument("--accept-leaves", type=int, default=1,
+                    help="let the surrogate accept leaves it is confident about (recall is unaffected)")
+    ap.add_argument("--sur-pairs", type=int, default=5_000_000)
+    ap.add_argument("--sur-steps", type=int, default=2000)
     ap.add_argument("--depth", type=int, default=None)
     ap.add_argument("--cpu-baseline-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -101,23 +107,58 @@ def main(argv=None):
     import torch
 
     import paper_2402_13861_amd as isx
+    from paper_2402_13861_amd.surrogate import train_surrogate
     from workloads.configs import WORKLOADS, isovalues, load_mlp
 
     w = WORKLOADS[a.workload]
     depth = a.depth if a.depth is not None else w["depth"]
     mlp = load_mlp(a.workload)
     isos, S = isovalues(a.workload)
+    import json as _json
+
+    mu_bar = _json.loads((ROOT / "workloads" / "isovalues.json").read_text())[a.workload]["mean"]
     prec = {"fp32": isx.FP32, "bf16": isx.BF16}[a.precision]
     band = w.get("band_rel", 0.0) * S
-    log(f"bench: {a.workload} widths {mlp.widths} depth {depth} isos {isos} precision {a.precision} band {band:.3g}")
+    use_sur = not a.no_surrogate
+    log(f"bench: {a.workload} widths {mlp.widths} depth {depth} isos {isos} precision {a.precision} "
+        f"surrogate {use_sur} band {band:.3g}")
 
     ctx = isx.Context(0)
     ctx.set_option(isx.SCRATCH_BYTES, 48 << 30)
     ctx.set_option(isx.VERBOSE, 1)
     mid = ctx.load_weights(mlp)
     ctx.set_isovalues(mid, isos)
-    kw = dict(method=isx.UP, precision=prec, k=w["k"], max_depth=depth, fp64_band=band)
+    base = dict(method=isx.UP, k=w["k"], max_depth=depth, fp64_band=band)
 
+    # 1. plain FP32 reference: the speedup baseline, the recall reference and
+    #    the source of visited cells for the surrogate's training set
+    plain = None
+    if not a.no_plain or use_sur:
+        ctx.set_option(isx.KEEP_LEVELS, 1 if use_sur else 0)
+        t0 = time.perf_counter()
+        m = ctx.extract(mid, precision=isx.FP32, **base)
+        plain_s = time.perf_counter() - t0
+        ctx.set_option(isx.KEEP_LEVELS, 0)
+        plain_ids, _ = m.leaves()
+        visited = [m.level_cells(L)[0] for L in range(m.n_levels)] if use_sur else None
+        plain = dict(ms=1e3 * plain_s, leaves=int(m.n_leaves), tris=int(m.n_tris),
+                     propagated=sum(l["cells"] for l in m.levels()), phases=m.times())
+        log(f"plain fp32: {1e3 * plain_s:.1f} ms, {m.n_leaves} leaves")
+        m.free()
+
+    # 2. surrogate training (once per INR, not part of the timed extraction)
+    sur_info = None
+    if use_sur:
+        t0 = time.perf_counter()
+        info = train_surrogate(ctx, mid, depth, mu_bar, S, visited=visited, n_pairs=a.sur_pairs, steps=a.sur_steps,
+                               isos=isos, k=w["k"], accept_leaves=bool(a.accept_leaves), log=log)
+        sur_info = dict(train_total_s=round(time.perf_counter() - t0, 2), train_kernel_s=round(info.train_seconds, 3),
+                        pairs=info.n_pairs, steps=info.steps, final_loss=info.final_loss, z=info.z,
+                        accept_leaves=bool(a.accept_leaves),
+                        err_mu=[round(x, 5) for x in info.err_mu], err_logsig=[round(x, 4) for x in info.err_logsig])
+        del visited
+
+    kw = dict(base, precision=prec, use_surrogate=use_sur)
     for i in range(a.warmup):
         t0 = time.perf_counter()
         m = ctx.extract(mid, **kw)
@@ -129,6 +170,7 @@ def main(argv=None):
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     runs = []
+    last_ids = None
     for i in range(a.steps):
         t0 = time.perf_counter()
         m = ctx.extract(mid, **kw)
@@ -137,6 +179,8 @@ def main(argv=None):
                          corners=m.n_corners))
         log(f"step {i}: {1e3 * dt:.1f} ms, leaves {m.n_leaves}, triangles {m.n_tris}, corners {m.n_corners}, "
             f"phases {m.times()}")
+        if i == a.steps - 1:
+            last_ids, _ = m.leaves()
         m.free()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
@@ -148,9 +192,19 @@ def main(argv=None):
     ms_per_step = 1e3 * elapsed / K
     value = eff_cells * K / elapsed
     levels = runs[-1]["levels"]
-    propagated = sum(l["cells"] for l in levels)
+    examined = sum(l["cells"] for l in levels)
+    propagated = sum(l["propagated"] for l in levels)
     acp_s = np.mean([r["times"]["acp_ms"] for r in runs]) / 1e3
-    log("levels:", [(l["cells"], l["active"], l["rechecked"]) for l in levels])
+    log("levels (cells, propagated, active, re-checked):",
+        [(l["cells"], l["propagated"], l["active"], l["rechecked"]) for l in levels])
+
+    quality = None
+    if plain is not None:
+        common = np.intersect1d(plain_ids, last_ids).size
+        quality = dict(recall_vs_plain=common / max(plain_ids.size, 1),
+                       false_active_vs_plain=(last_ids.size - common) / max(last_ids.size, 1),
+                       plain_leaves=int(plain_ids.size), leaves=int(last_ids.size))
+        log("quality:", quality)
 
     launches = max(prof["launches"], 1)
     avg_ms = prof["ms"] / launches
@@ -176,17 +230,20 @@ def main(argv=None):
     cpu = None
     if not a.no_cpu_baseline:
         rate, done, t_used, threads, total = cpu_baseline(mlp, levels, a.cpu_baseline_seconds)
-        est_s = total / rate
+        total_plain = plain["propagated"] if plain is not None else total
+        est_s = total_plain / rate
         cpu = {
             "value": eff_cells / est_s,
             "unit": "cells/s",
             "cores": threads,
             "kind": "oracle",
             "sample": (f"float64 oracle propagation of {done} random cells drawn over octree levels in proportion "
-                       f"to the GPU run's {int(total)} propagated cells ({t_used:.1f} s, {rate:.1f} cells/s); "
-                       f"extraction time extrapolated from propagation alone ({est_s:.0f} s)"),
+                       f"to the extraction's cells ({t_used:.1f} s, {rate:.1f} cells/s); plain-method extraction "
+                       f"time extrapolated from propagation of its {int(total_plain)} cells alone ({est_s:.0f} s)"),
         }
 
+    name = ("bf16+surrogate" if use_sur else "bf16") if a.precision == "bf16" else ("fp32+surrogate" if use_sur
+                                                                                     else "fp32")
     out = {
         "metric": METRIC,
         "value": value,
@@ -202,16 +259,21 @@ def main(argv=None):
         "data": "synthetic",
         "config": {
             "workload": f"{a.workload}: ReLU MLP {'x'.join(map(str, mlp.widths))}, octree depth {depth} "
-                        f"({1 << depth}^3), {len(isos)} iso-values, UP t={w['k']}, fp64 band {w.get('band_rel', 0)} S",
-            "method": "up",
-            "precision": a.precision,
-            "surrogate": False,
+                        f"({1 << depth}^3 effective cells), {len(isos)} iso-values, UP t={w['k']}, "
+                        f"fp64 band {w.get('band_rel', 0)} S",
+            "path": name,
         },
+        "value_definition": "effective cells (2^depth)^3 per second of full extraction",
+        "plain_fp32": plain and {k: v for k, v in plain.items() if k != "phases"},
+        "speedup_vs_plain_fp32": (plain["ms"] / ms_per_step) if plain else None,
+        "quality": quality,
+        "surrogate": sur_info,
+        "examined_cells": examined,
         "propagated_cells": propagated,
         "propagated_cells_per_s": propagated / acp_s if acp_s > 0 else None,
         "active_leaves": runs[-1]["leaves"],
         "triangles": runs[-1]["tris"],
-        "phase_ms": {k: round(np.mean([r["times"][k] for r in runs]), 2) for k in runs[-1]["times"]},
+        "phase_ms": {k: round(float(np.mean([r["times"][k] for r in runs])), 2) for k in runs[-1]["times"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
