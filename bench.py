@@ -36,8 +36,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
-    src = ROOT / "paper_2402_13861_amd" / "csrc" / "kernels_mfma.hip"
+KERNEL_SOURCE = {"fp32": "kernels_mfma.hip", "bf16": "kernels_bf16.hip"}
+
+
+def kernel_source_hash(precision: str) -> str:
+    src = ROOT / "paper_2402_13861_amd" / "csrc" / KERNEL_SOURCE[precision]
     return hashlib.sha256(src.read_bytes()).hexdigest()[:16]
 
 
@@ -48,7 +51,7 @@ def traffic_from_profiles(precision: str, flops_per_launch: float):
     if not f.exists():
         return None
     t = json.loads(f.read_text())
-    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+    if t.get("kernel_source_sha256_16") != kernel_source_hash(precision):
         return None
     return t.get("hbm_bytes_per_launch")
 
@@ -81,6 +84,24 @@ def cpu_baseline(mlp, levels, budget_s: float):
     return rate, done, t_used, threads, total
 
 
+def copy_probe(nbytes: int, reps: int = 5):
+    """A plain device-to-device copy of known size: the reference that scales
+    the HBM byte counters (FETCH_SIZE, WRITE_SIZE) read for the kernels."""
+    import torch
+
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").uniform_()
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_bytes": nbytes, "reps": reps, "ms": 1e3 * dt,
+                      "GBps_read_plus_write": 2 * nbytes / dt / 1e9}), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,16 +113,23 @@ def main(argv=None):
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 reference run")
     ap.add_argument("--accept-leaves", type=int, default=1,
                     help="let the surrogate accept leaves it is confident about (recall is unaffected)")
+    ap.add_argument("--sur-base", type=int, default=1,
+                    help="1: the surrogate predicts corrections to the INR's centre linearisation; "
+                         "0: standardised (mean, log sigma) targets")
     ap.add_argument("--sur-pairs", type=int, default=5_000_000)
     ap.add_argument("--sur-steps", type=int, default=2000)
     ap.add_argument("--depth", type=int, default=None)
     ap.add_argument("--cpu-baseline-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-bytes", type=int, default=0,
+                    help="only run a plain copy of this many bytes (counter calibration) and exit")
     a = ap.parse_args(argv)
 
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         return 2
+    if a.copy_probe_bytes:
+        return copy_probe(a.copy_probe_bytes)
 
     import numpy as np
     import torch
@@ -151,10 +179,13 @@ def main(argv=None):
     if use_sur:
         t0 = time.perf_counter()
         info = train_surrogate(ctx, mid, depth, mu_bar, S, visited=visited, n_pairs=a.sur_pairs, steps=a.sur_steps,
-                               isos=isos, k=w["k"], accept_leaves=bool(a.accept_leaves), log=log)
+                               isos=isos, k=w["k"], accept_leaves=bool(a.accept_leaves), base=bool(a.sur_base),
+                               log=log)
         sur_info = dict(train_total_s=round(time.perf_counter() - t0, 2), train_kernel_s=round(info.train_seconds, 3),
                         pairs=info.n_pairs, steps=info.steps, final_loss=info.final_loss, z=info.z,
-                        accept_leaves=bool(a.accept_leaves),
+                        z_accept=info.z_accept, holdout_miss=info.holdout_miss,
+                        holdout_false_accept=info.holdout_false_accept,
+                        accept_leaves=bool(a.accept_leaves), base=bool(a.sur_base),
                         err_mu=[round(x, 5) for x in info.err_mu], err_logsig=[round(x, 4) for x in info.err_logsig])
         del visited
 
@@ -206,9 +237,11 @@ def main(argv=None):
                        plain_leaves=int(plain_ids.size), leaves=int(last_ids.size))
         log("quality:", quality)
 
-    launches = max(prof["launches"], 1)
-    avg_ms = prof["ms"] / launches
-    flops_per_launch = prof["flops"] / launches
+    kind = "hidden_fp32" if a.precision == "fp32" else "hidden_bf16"
+    kp = prof[kind]
+    launches = max(kp["launches"], 1)
+    avg_ms = kp["ms"] / launches
+    flops_per_launch = kp["flops"] / launches
     achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
     peak = PEAK_TFLOPS[a.precision]
     traffic = traffic_from_profiles(a.precision, flops_per_launch)
@@ -220,12 +253,18 @@ def main(argv=None):
         "unit": "TFLOP/s",
         "frac": round(achieved / peak, 4),
         "traffic": traffic,
-        "launches": prof["launches"],
+        "launches": kp["launches"],
         "avg_launch_ms": round(avg_ms, 4),
         "flops_per_launch": flops_per_launch,
-        "alg_bytes_per_launch": prof["bytes"] / launches,
-        "alg_hbm_GBps": round(prof["bytes"] / launches / (avg_ms * 1e-3) / 1e9, 1) if avg_ms > 0 else 0.0,
+        "alg_bytes_per_launch": kp["bytes"] / launches,
+        "alg_hbm_GBps": round(kp["bytes"] / launches / (avg_ms * 1e-3) / 1e9, 1) if avg_ms > 0 else 0.0,
     }
+    kernels = {}
+    for name, v in prof.items():
+        if v["launches"]:
+            kernels[name] = {"ms_per_step": round(v["ms"] / K, 2), "launches_per_step": v["launches"] / K,
+                             "TFLOPs": round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 2) if v["ms"] > 0 else None}
+    log("kernel time per step:", kernels)
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -275,6 +314,7 @@ def main(argv=None):
         "triangles": runs[-1]["tris"],
         "phase_ms": {k: round(float(np.mean([r["times"][k] for r in runs])), 2) for k in runs[-1]["times"]},
         "roofline": roofline,
+        "kernels": kernels,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

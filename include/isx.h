@@ -104,7 +104,7 @@ isx_status isx_set_domain(isx_ctx* ctx, int32_t mlp_id, const float h_lo[3], con
  * Bit j of every cell mask refers to h_iso[j].  Errors: ISX_EINVAL, ISX_ENAN. */
 isx_status isx_set_isovalues(isx_ctx* ctx, int32_t mlp_id, int32_t n_iso, const float* h_iso);
 
-/* Propagate n_cells boxes through the MLP (Alg. 1 lines 1-5 without the
+/* Propagate n_cells boxes through the MLP (the bound computation of Alg. 1, without the
  * test).  d_centres [n][3] and d_halves [n][3] (per-axis half-widths, > 0)
  * are device arrays.  d_out [n][2] receives (centre, spread) as float32:
  * (x0, r) for ISX_AA, whose range is [x0 - r, x0 + r] (Eq. 2), and
@@ -116,7 +116,7 @@ isx_status isx_propagate(isx_ctx* ctx, int32_t mlp_id, isx_method method, isx_pr
                          int64_t n_cells, const float* d_centres, const float* d_halves, float* d_out,
                          double* d_out64);
 
-/* Classify and compact (Alg. 1 lines 6-7): cell i keeps iso bit j iff
+/* Classify and compact (the pruning test of Alg. 1): cell i keeps iso bit j iff
  * centre - k*spread <= c_j <= centre + k*spread (closed interval) and bit j is
  * set in d_parent_mask[i] (NULL = all bits set); k is the paper's t for UP and
  * must be 1 for the AA hard range.  The indices i of cells with a nonzero
@@ -133,6 +133,16 @@ isx_status isx_classify_compact(isx_ctx* ctx, int32_t mlp_id, float k, int64_t n
  * ISX_FP64 computes in float64 and rounds the result.  Asynchronous. */
 isx_status isx_eval_points(isx_ctx* ctx, int32_t mlp_id, isx_precision precision, int64_t n,
                            const float* d_points, float* d_values);
+
+/* Centre linearisation of n cells: the limit of the uncertainty propagation
+ * (Sec. IV-C input form, Eq. 6-8) when no ReLU changes sign inside the cell.
+ * d_out [n][2] receives (f(c), s) with s = |J(c) diag(h)|_2 / sqrt(3), J the
+ * gradient of the MLP at the centre (a ReLU's derivative at 0 taken as 0).
+ * d_centres, d_halves [n][3] as in isx_propagate.  float32 (MFMA products),
+ * asynchronous; hidden widths up to ISX_MAX_WIDTH.
+ * Errors: ISX_EINVAL, ISX_EHIP. */
+isx_status isx_linearize(isx_ctx* ctx, int32_t mlp_id, int64_t n, const float* d_centres,
+                         const float* d_halves, float* d_out);
 
 /* Parameters of a full extraction. */
 typedef struct {
@@ -208,6 +218,13 @@ isx_status isx_mesh_free(isx_mesh* mesh);
  *   shapes.
  * isx_surrogate_set_norm: mu_bar, S (> 0) of the targets and a, b of the
  *   size feature.
+ * isx_surrogate_set_base: make the two outputs corrections to the centre
+ *   linearisation (f, s) of MLP mlp_id (isx_linearize): the network is then
+ *   trained on ((mu - f)/s_b, ln(sigma / s_b)) and predicts
+ *   mu_hat = f + s_b o_0, sigma_hat = s_b exp(o_1), with s_b = max(s, s_floor)
+ *   (s_floor > 0, field units), and the band's err_mu is in units of s_b.
+ *   mlp_id = -1 returns to the standardised targets.  The MLP must stay
+ *   loaded while the surrogate is used.
  * isx_surrogate_train: `steps` Adam steps on mini-batches of `batch` rows
  *   taken in order from row `first_row` of the n pairs (wrapping around):
  *   d_centres/d_halves [n][3] and d_targets [n][2] = propagated (mu, sigma),
@@ -218,11 +235,14 @@ isx_status isx_mesh_free(isx_mesh* mesh);
  * isx_surrogate_attach: use surrogate sur_id in isx_extract of mlp_id (when
  *   params.use_surrogate).  h_err_mu[L], h_err_logsig[L] (L < n_levels) are
  *   the standard deviations of the surrogate's error at octree level L (field
- *   units and log-sigma units).  A cell is decided without propagation when
+ *   units, or units of s_b with a base; and log-sigma units).  A cell is decided without propagation when
  *   for every iso-value c it still carries either
  *     |mu_hat - c| - z err_mu > t sigma_hat exp(+z err_logsig)  (outside), or
- *     |mu_hat - c| + z err_mu < t sigma_hat exp(-z err_logsig)  (inside);
- *   otherwise it is propagated.  Leaves are always propagated unless
+ *     |mu_hat - c| + z_accept err_mu < t sigma_hat exp(-z_accept err_logsig)
+ *                                                              (inside);
+ *   otherwise it is propagated.  A wrongly pruned cell loses surface, a
+ *   wrongly accepted one only costs work (its children are classified in
+ *   turn; at the leaves it is an extra leaf), so the two bands may differ.  Leaves are always propagated unless
  *   accept_leaves.  sur_id = -1 detaches.
  * Errors: ISX_EINVAL, ISX_ESHAPE, ISX_ENAN, ISX_ENOMEM, ISX_EHIP. */
 isx_status isx_surrogate_load(isx_ctx* ctx, int32_t n_linear, const int32_t* widths, const float* const* h_W,
@@ -230,6 +250,7 @@ isx_status isx_surrogate_load(isx_ctx* ctx, int32_t n_linear, const int32_t* wid
 isx_status isx_surrogate_get(isx_ctx* ctx, int32_t sur_id, float* const* h_W, float* const* h_b);
 isx_status isx_surrogate_set_norm(isx_ctx* ctx, int32_t sur_id, float mu_bar, float scale, float size_a,
                                   float size_b);
+isx_status isx_surrogate_set_base(isx_ctx* ctx, int32_t sur_id, int32_t mlp_id, float s_floor);
 isx_status isx_surrogate_train(isx_ctx* ctx, int32_t sur_id, int64_t n, const float* d_centres,
                                const float* d_halves, const float* d_targets, int64_t first_row, int32_t steps,
                                int32_t batch, float lr, float* d_loss);
@@ -243,7 +264,8 @@ isx_status isx_surrogate_grad(isx_ctx* ctx, int32_t sur_id, int64_t n, const flo
 isx_status isx_surrogate_predict(isx_ctx* ctx, int32_t sur_id, int64_t n, const float* d_centres,
                                  const float* d_halves, float* d_out);
 isx_status isx_surrogate_attach(isx_ctx* ctx, int32_t mlp_id, int32_t sur_id, int32_t n_levels,
-                                const float* h_err_mu, const float* h_err_logsig, float z, int32_t accept_leaves);
+                                const float* h_err_mu, const float* h_err_logsig, float z, float z_accept,
+                                int32_t accept_leaves);
 isx_status isx_surrogate_free(isx_ctx* ctx, int32_t sur_id);
 
 /* Copy the library's marching-cubes case table: h_count[256] triangles per
@@ -263,15 +285,27 @@ typedef enum {
 } isx_option;
 isx_status isx_set_option(isx_ctx* ctx, isx_option option, int64_t value);
 
-/* Accumulated hidden-layer kernel statistics since the last reset (ISX_PROFILE
- * on): launches, summed device time in ms (HIP events on the context stream),
- * algorithmic flops (2 * n_out * n_in * real columns per cell; the real
- * columns of hidden layer h are 1 centre + 3 input symbols + the true widths
- * of layers 1..h-2) and algorithmic bytes (the coefficient block read, plus
- * the block written unless it is the last hidden layer, at the storage
- * precision).  Synchronises the stream.  reset != 0 clears the counters. */
-isx_status isx_get_profile(isx_ctx* ctx, int64_t* launches, double* ms, double* flops, double* bytes,
-                           int32_t reset);
+/* Kernel kinds timed by ISX_PROFILE. */
+typedef enum {
+  ISX_KERNEL_HIDDEN_FP32 = 0,      /* hidden-layer product, FP32 MFMA */
+  ISX_KERNEL_HIDDEN_BF16 = 1,      /* hidden-layer product, BF16 MFMA */
+  ISX_KERNEL_HIDDEN_SIMT_FP32 = 2, /* hidden-layer product, float32 vector ALUs */
+  ISX_KERNEL_HIDDEN_FP64 = 3,      /* hidden-layer product, float64 (re-check band, ISX_FP64) */
+  ISX_KERNEL_DENSE = 4,            /* dense forward passes (corner evaluation, linearisation) */
+  ISX_KERNEL_OUTPUT = 5            /* output read-off (spread of the last layer) */
+} isx_kernel_kind;
+
+/* Accumulated statistics of one kernel kind since the last reset (ISX_PROFILE
+ * on): launches, summed device time in ms (HIP events recorded around each
+ * launch on the context stream), algorithmic flops and algorithmic bytes.
+ * For the hidden-layer kinds: flops = 2 * n_out * n_in * real columns per
+ * cell (the real columns of hidden layer h are the 3 input symbols (+1
+ * centre in the float32/float64 layouts) and the true widths of layers
+ * 1..h-2); bytes = the coefficient block read plus the block written unless
+ * it is the last hidden layer, at the storage precision.  Synchronises the
+ * stream.  reset != 0 clears the counters of every kind. */
+isx_status isx_get_profile(isx_ctx* ctx, int32_t kernel, int64_t* launches, double* ms, double* flops,
+                           double* bytes, int32_t reset);
 
 #ifdef __cplusplus
 }

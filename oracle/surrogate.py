@@ -4,7 +4,8 @@ and one Adam step.
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 
 The surrogate maps a cell (centre c, per-axis half-width h) to a predicted
-(mean, sigma) of the INR output over the cell.  Features: x = (c_x, c_y, c_z,
+(mean, sigma) of the INR output over the cell, either directly or as a
+correction to a base (f, s) per cell (the centre linearisation).  Features: x = (c_x, c_y, c_z,
 a * log2(2 h_x) + b) (cell size normalised by a fixed affine map); a ReLU MLP
 4 -> 128 -> 128 -> 128 -> 2 outputs standardised targets
 t = ((mu - mu_bar) / S, ln sigma).  Loss: half the sum of the two mean squared
@@ -25,6 +26,20 @@ def features(centres, halves, a, b):
 
 def targets(mu, sigma, mu_bar, scale):
     return np.stack([(np.asarray(mu, np.float64) - mu_bar) / scale, np.log(np.asarray(sigma, np.float64))], axis=1)
+
+
+def base_targets(mu, sigma, f, s, s_floor):
+    """Targets relative to a base (f, s) per cell, the centre linearisation:
+    ((mu - f) / s_b, ln(sigma / s_b)) with s_b = max(s, s_floor)."""
+    sb = np.maximum(np.asarray(s, np.float64), s_floor)
+    return np.stack([(np.asarray(mu, np.float64) - np.asarray(f, np.float64)) / sb,
+                     np.log(np.asarray(sigma, np.float64) / sb)], axis=1)
+
+
+def base_prediction(out, f, s, s_floor):
+    """(mu_hat, sigma_hat) from the network outputs and the base."""
+    sb = np.maximum(np.asarray(s, np.float64), s_floor)
+    return np.stack([np.asarray(f, np.float64) + sb * out[:, 0], sb * np.exp(out[:, 1])], axis=1)
 
 
 def forward(Ws, bs, X):

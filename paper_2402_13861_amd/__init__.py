@@ -22,6 +22,8 @@ import numpy as np
 from . import _lib
 from ._lib import AA, BF16, BF16_VARIANT, FP32, FP64, HIDDEN_KERNEL, KEEP_LEVELS, PROFILE, SCRATCH_BYTES, UP, VERBOSE
 
+KERNEL_KINDS = ("hidden_fp32", "hidden_bf16", "hidden_simt_fp32", "hidden_fp64", "dense", "output")
+
 __all__ = ["Context", "Mesh", "IsxError", "AA", "UP", "FP32", "BF16", "FP64", "KEEP_LEVELS", "HIDDEN_KERNEL",
            "PROFILE", "SCRATCH_BYTES", "VERBOSE", "BF16_VARIANT", "mc_case_table"]
 
@@ -135,11 +137,16 @@ class Context:
         self._chk(self._L.isx_set_option(self._h, option, int(value)))
 
     def profile(self, reset: bool = True):
-        """Hidden-layer kernel statistics (ISX_PROFILE on): dict of launches,
-        ms, flops, bytes."""
-        n, ms, fl, by = C.c_int64(), C.c_double(), C.c_double(), C.c_double()
-        self._chk(self._L.isx_get_profile(self._h, C.byref(n), C.byref(ms), C.byref(fl), C.byref(by), int(reset)))
-        return dict(launches=n.value, ms=ms.value, flops=fl.value, bytes=by.value)
+        """Kernel statistics per kind (ISX_PROFILE on): {kind name: dict of
+        launches, ms, flops, bytes}; reset clears them afterwards."""
+        out = {}
+        for kind, name in enumerate(KERNEL_KINDS):
+            n, ms, fl, by = C.c_int64(), C.c_double(), C.c_double(), C.c_double()
+            self._chk(self._L.isx_get_profile(self._h, kind, C.byref(n), C.byref(ms), C.byref(fl), C.byref(by), 0))
+            out[name] = dict(launches=n.value, ms=ms.value, flops=fl.value, bytes=by.value)
+        if reset:
+            self._chk(self._L.isx_get_profile(self._h, 0, None, None, None, None, 1))
+        return out
 
     # -- batched calls on device tensors (asynchronous on the context stream)
     def propagate(self, mlp_id: int, method: int, precision: int, centres, halves, out, out64=None):
@@ -198,6 +205,11 @@ class Context:
         self._chk(self._L.isx_surrogate_set_norm(self._h, sid, float(mu_bar), float(scale), float(size_a),
                                                  float(size_b)))
 
+    def surrogate_set_base(self, sid: int, mlp_id: int, s_floor: float = 0.0):
+        """Outputs become corrections to ``mlp_id``'s centre linearisation
+        (mlp_id = -1: standardised targets)."""
+        self._chk(self._L.isx_surrogate_set_base(self._h, sid, int(mlp_id), float(s_floor)))
+
     def surrogate_train(self, sid: int, centres, halves, targets, steps: int, batch: int, lr: float,
                         first_row: int = 0, loss=None):
         import torch
@@ -230,12 +242,14 @@ class Context:
                                                 _ptr(out)))
 
     def surrogate_attach(self, mlp_id: int, sid: int, err_mu, err_logsig, z: float = 2.0,
-                         accept_leaves: bool = False):
+                         accept_leaves: bool = False, z_accept: Optional[float] = None):
+        """z: band for pruning; z_accept: band for accepting (default z)."""
         err_mu = [float(x) for x in err_mu]
         err_ls = [float(x) for x in err_logsig]
         n = len(err_mu)
+        za = float(z if z_accept is None else z_accept)
         self._chk(self._L.isx_surrogate_attach(self._h, mlp_id, sid, n, (C.c_float * n)(*err_mu),
-                                               (C.c_float * n)(*err_ls), float(z), int(bool(accept_leaves))))
+                                               (C.c_float * n)(*err_ls), float(z), za, int(bool(accept_leaves))))
 
     def surrogate_free(self, sid: int):
         self._chk(self._L.isx_surrogate_free(self._h, sid))
@@ -246,6 +260,18 @@ class Context:
         _check_dev(pts, torch.float32, "pts", (3,))
         _check_dev(vals, torch.float32, "vals")
         self._chk(self._L.isx_eval_points(self._h, mlp_id, precision, pts.shape[0], _ptr(pts), _ptr(vals)))
+
+    def linearize(self, mlp_id: int, centres, halves, out):
+        """(f(c), |J(c) diag(h)| / sqrt 3) per cell into ``out [n, 2]``."""
+        import torch
+
+        _check_dev(centres, torch.float32, "centres", (3,))
+        _check_dev(halves, torch.float32, "halves", (3,))
+        _check_dev(out, torch.float32, "out", (2,))
+        n = centres.shape[0]
+        if halves.shape[0] != n or out.shape[0] != n:
+            raise ValueError("centres, halves and out must have the same length")
+        self._chk(self._L.isx_linearize(self._h, mlp_id, n, _ptr(centres), _ptr(halves), _ptr(out)))
 
     # -- full extraction (synchronous)
     def extract(self, mlp_id: int, method: int = UP, precision: int = FP32, k: float = 3.0, max_depth: int = 6,

@@ -20,6 +20,8 @@ AA, UP = 0, 1
 FP32, BF16, FP64 = 0, 1, 2
 KEEP_LEVELS, HIDDEN_KERNEL, PROFILE, SCRATCH_BYTES, VERBOSE, BF16_VARIANT = 1, 2, 3, 4, 5, 6
 MAX_LINEAR, MAX_WIDTH, MAX_ISO = 16, 1024, 32
+(KERNEL_HIDDEN_FP32, KERNEL_HIDDEN_BF16, KERNEL_HIDDEN_SIMT_FP32, KERNEL_HIDDEN_FP64, KERNEL_DENSE,
+ KERNEL_OUTPUT) = range(6)
 
 
 class Params(C.Structure):
@@ -50,6 +52,7 @@ _SIGS = [
     ("isx_classify_compact", C.c_int, [C.c_void_p, C.c_int32, C.c_float, C.c_int64, C.c_void_p, C.c_void_p,
                                        C.c_void_p, C.c_void_p, C.c_void_p]),
     ("isx_eval_points", C.c_int, [C.c_void_p, C.c_int32, C.c_int, C.c_int64, C.c_void_p, C.c_void_p]),
+    ("isx_linearize", C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("isx_extract", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Params), C.POINTER(C.c_void_p)]),
     ("isx_mesh_info", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                 C.POINTER(C.c_int32)]),
@@ -67,6 +70,7 @@ _SIGS = [
                                      C.POINTER(C.c_void_p), C.POINTER(C.c_int32)]),
     ("isx_surrogate_get", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]),
     ("isx_surrogate_set_norm", C.c_int, [C.c_void_p, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float]),
+    ("isx_surrogate_set_base", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_float]),
     ("isx_surrogate_train", C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_int64, C.c_int32, C.c_int32, C.c_float, C.c_void_p]),
     ("isx_surrogate_grad", C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -74,10 +78,10 @@ _SIGS = [
                                      C.POINTER(C.c_float)]),
     ("isx_surrogate_predict", C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("isx_surrogate_attach", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_float),
-                                       C.POINTER(C.c_float), C.c_float, C.c_int32]),
+                                       C.POINTER(C.c_float), C.c_float, C.c_float, C.c_int32]),
     ("isx_surrogate_free", C.c_int, [C.c_void_p, C.c_int32]),
-    ("isx_get_profile", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double),
-                                  C.POINTER(C.c_double), C.c_int32]),
+    ("isx_get_profile", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                  C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int32]),
 ]
 
 EXPORTED = [name for name, _, _ in _SIGS]

@@ -35,6 +35,9 @@ struct Sur {
   float *gW[ISX_MAX_LINEAR] = {}, *gb[ISX_MAX_LINEAR] = {};
   int64_t t = 0;
   float mu_bar = 0.f, scale = 1.f, size_a = 1.f, size_b = 0.f;
+  // outputs are corrections to this MLP's centre linearisation (-1: plain)
+  int32_t base_mlp = -1;
+  float s_floor = 0.f;
 };
 
 struct isx_ctx {
@@ -57,7 +60,7 @@ struct isx_ctx {
   Buf cls_mask;
   // surrogate: models, training/inference activations, extraction scratch
   std::vector<Sur> surs;
-  Buf sur_act[ISX_MAX_LINEAR + 1], sur_out, sur_T, sur_d[2];
+  Buf sur_act[ISX_MAX_LINEAR + 1], sur_out, sur_T, sur_d[2], sur_base, sp_base, sp_scale;
   Buf sp_pred, sp_fb, sp_idx, sp_pm, sp_c, sp_h, sp_out, sp_mask, sp_cnt, sp_tmp;
   Buf rc_flags, rc_fidx, rc_fmask;
   int64_t* h_count = nullptr;  // pinned
@@ -178,7 +181,6 @@ isx_status run_propagate(isx_ctx* ctx, const Model& m, isx_method method, isx_pr
       PropArgs a{&m, method, std::min(chunk, n - s), centres + 3 * s, halves + 3 * s, out + 2 * s,
                  out64 ? out64 + 2 * s : nullptr, ctx->kernel_choice, ctx->stream, &ctx->prof, ctx->bf16_variant};
       HIPCHK(propagate_f64(a, w));
-      if (ctx->prof.pending.size() > 4096) ctx->prof.harvest();
     }
     return ISX_OK;
   }
@@ -198,7 +200,6 @@ isx_status run_propagate(isx_ctx* ctx, const Model& m, isx_method method, isx_pr
       PropArgs a{&m, method, std::min(chunk, n - s), centres + 3 * s, halves + 3 * s, out + 2 * s, nullptr,
                  ctx->kernel_choice, ctx->stream, &ctx->prof, ctx->bf16_variant};
       HIPCHK(propagate_bf16(a, w, Fbf, 0));
-      if (ctx->prof.pending.size() > 4096) ctx->prof.harvest();
     }
     return ISX_OK;
   }
@@ -214,7 +215,6 @@ isx_status run_propagate(isx_ctx* ctx, const Model& m, isx_method method, isx_pr
     PropArgs a{&m, method, std::min(chunk, n - s), centres + 3 * s, halves + 3 * s, out + 2 * s, nullptr,
                ctx->kernel_choice, ctx->stream, &ctx->prof, ctx->bf16_variant};
     HIPCHK(propagate_f32(a, w));
-    if (ctx->prof.pending.size() > 4096) ctx->prof.harvest();
   }
   return ISX_OK;
 }
@@ -288,7 +288,8 @@ isx_status isx_destroy(isx_ctx* ctx) {
                  &ctx->rc_count, &ctx->bitmap, &ctx->word_prefix, &ctx->corner_g, &ctx->corner_pts,
                  &ctx->corner_vals, &ctx->tri_off, &ctx->cls_mask};
   for (Buf* b : bufs) release(*b);
-  Buf* sbufs[] = {&ctx->sur_out, &ctx->sur_T, &ctx->sur_d[0], &ctx->sur_d[1], &ctx->sp_pred, &ctx->sp_fb,
+  Buf* sbufs[] = {&ctx->sur_out, &ctx->sur_T, &ctx->sur_d[0], &ctx->sur_d[1], &ctx->sur_base, &ctx->sp_base,
+                  &ctx->sp_scale, &ctx->sp_pred, &ctx->sp_fb,
                   &ctx->sp_idx, &ctx->sp_pm, &ctx->sp_c, &ctx->sp_h, &ctx->sp_out, &ctx->sp_mask, &ctx->sp_cnt,
                   &ctx->sp_tmp, &ctx->rc_flags, &ctx->rc_fidx, &ctx->rc_fmask};
   for (Buf* b : sbufs) release(*b);
@@ -329,19 +330,19 @@ isx_status isx_set_option(isx_ctx* ctx, isx_option option, int64_t value) {
   return fail(ctx, ISX_EINVAL, "unknown option");
 }
 
-isx_status isx_get_profile(isx_ctx* ctx, int64_t* launches, double* ms, double* flops, double* bytes,
-                           int32_t reset) {
+isx_status isx_get_profile(isx_ctx* ctx, int32_t kernel, int64_t* launches, double* ms, double* flops,
+                           double* bytes, int32_t reset) {
   if (!ctx) return ISX_EINVAL;
+  if (kernel < 0 || kernel >= Profiler::kKinds) return fail(ctx, ISX_EINVAL, "unknown kernel kind");
   (void)hipSetDevice(ctx->device);
   ctx->prof.harvest();
-  if (launches) *launches = ctx->prof.launches;
-  if (ms) *ms = ctx->prof.ms;
-  if (flops) *flops = ctx->prof.flops;
-  if (bytes) *bytes = ctx->prof.bytes;
-  if (reset) {
-    ctx->prof.launches = 0;
-    ctx->prof.ms = ctx->prof.flops = ctx->prof.bytes = 0;
-  }
+  const Profiler::Tot& T = ctx->prof.tot[kernel];
+  if (launches) *launches = T.launches;
+  if (ms) *ms = T.ms;
+  if (flops) *flops = T.flops;
+  if (bytes) *bytes = T.bytes;
+  if (reset)
+    for (Profiler::Tot& t : ctx->prof.tot) t = Profiler::Tot{};
   return ISX_OK;
 }
 
@@ -490,6 +491,18 @@ isx_status isx_classify_compact(isx_ctx* ctx, int32_t mlp_id, float k, int64_t n
   return ISX_OK;
 }
 
+// float32 point evaluation: FP32 MFMA, or the SIMT kernel when forced
+static hipError_t eval_f32(isx_ctx* ctx, const Model& m, int64_t n, const float* pts, float* vals, hipStream_t s) {
+  if (ctx->kernel_choice == 1) return eval_points_f32(m, n, pts, vals, s);
+  double flops = 6.0 * m.widths[1] + 2.0 * m.widths[m.n_linear - 1];
+  for (int h = 2; h < m.n_linear; ++h) flops += 2.0 * m.widths[h] * m.widths[h - 1];
+  Profiler::Rec rec{};
+  const bool prof = ctx->prof.begin(rec, ISX_KERNEL_DENSE, flops * (double)n, 16.0 * n, s);
+  hipError_t e = eval_points_mfma(m, n, pts, vals, s);
+  if (prof) ctx->prof.end(rec, s);
+  return e;
+}
+
 isx_status isx_eval_points(isx_ctx* ctx, int32_t mlp_id, isx_precision precision, int64_t n, const float* d_points,
                            float* d_values) {
   Model* m = get_model(ctx, mlp_id);
@@ -498,13 +511,22 @@ isx_status isx_eval_points(isx_ctx* ctx, int32_t mlp_id, isx_precision precision
   (void)hipSetDevice(ctx->device);
   if (precision == ISX_FP64) {
     HIPCHK(eval_points_f64(*m, n, d_points, d_values, ctx->stream));
-  } else if (precision == ISX_FP32) {
-    HIPCHK(eval_points_f32(*m, n, d_points, d_values, ctx->stream));
-  } else if (precision == ISX_BF16) {
-    HIPCHK(eval_points_f32(*m, n, d_points, d_values, ctx->stream));
+  } else if (precision == ISX_FP32 || precision == ISX_BF16) {
+    HIPCHK(eval_f32(ctx, *m, n, d_points, d_values, ctx->stream));
   } else {
     return fail(ctx, ISX_EINVAL, "unknown precision");
   }
+  return ISX_OK;
+}
+
+isx_status isx_linearize(isx_ctx* ctx, int32_t mlp_id, int64_t n, const float* d_centres, const float* d_halves,
+                         float* d_out) {
+  Model* m = get_model(ctx, mlp_id);
+  if (!m) return fail(ctx, ISX_EINVAL, "bad mlp id");
+  if (n < 0 || (n > 0 && (!d_centres || !d_halves || !d_out))) return fail(ctx, ISX_EINVAL, "bad arguments");
+  if (n == 0) return ISX_OK;
+  (void)hipSetDevice(ctx->device);
+  HIPCHK(linearize_mfma(*m, n, d_centres, d_halves, d_out, ctx->stream));
   return ISX_OK;
 }
 
@@ -561,23 +583,32 @@ static Sur* get_sur(isx_ctx* ctx, int32_t id) {
   return &ctx->surs[id];
 }
 
-// Surrogate forward pass over n cells, (mu_hat, sigma_hat) in field units.
+// Surrogate forward pass over n cells, (mu_hat, sigma_hat) in field units;
+// with a base MLP also the per-cell base scale s_b into sb_out (if given).
 static isx_status sur_predict_n(isx_ctx* ctx, Sur& S, int64_t n, const float* centres, const float* halves,
-                                float* out) {
+                                float* out, float* sb_out) {
   hipStream_t s = ctx->stream;
+  const Model* base = nullptr;
+  if (S.base_mlp >= 0) {
+    base = get_model(ctx, S.base_mlp);
+    if (!base) return fail(ctx, ISX_EINVAL, "the surrogate's base MLP was unloaded");
+  }
   const int64_t chunk = std::min<int64_t>(n, (int64_t)1 << 20);
   for (int l = 0; l < S.L; ++l) HIPCHK(ensure(ctx->sur_act[l], (size_t)chunk * S.w[l] * 4));
   HIPCHK(ensure(ctx->sur_out, (size_t)chunk * 8));
+  if (base) HIPCHK(ensure(ctx->sp_base, (size_t)chunk * 8));
   for (int64_t r0 = 0; r0 < n; r0 += chunk) {
     const int B = (int)std::min<int64_t>(chunk, n - r0);
     HIPCHK(sur_features(n, r0, B, centres, halves, S.size_a, S.size_b, (float*)ctx->sur_act[0].p, nullptr, 0.f, 1.f,
-                        nullptr, s));
+                        nullptr, 0.f, nullptr, s));
     for (int l = 0; l < S.L; ++l) {
       float* C = l + 1 < S.L ? (float*)ctx->sur_act[l + 1].p : (float*)ctx->sur_out.p;
       HIPCHK(sur_gemm(B, S.w[l + 1], S.w[l], (const float*)ctx->sur_act[l].p, S.w[l], false, S.W[l], S.w[l], true, C,
                       S.w[l + 1], S.b[l], l + 1 < S.L, nullptr, 0, s));
     }
-    HIPCHK(sur_unstd(B, (const float*)ctx->sur_out.p, S.mu_bar, S.scale, out + 2 * r0, s));
+    if (base) HIPCHK(linearize_mfma(*base, B, centres + 3 * r0, halves + 3 * r0, (float*)ctx->sp_base.p, s));
+    HIPCHK(sur_unstd(B, (const float*)ctx->sur_out.p, S.mu_bar, S.scale, base ? (const float*)ctx->sp_base.p : nullptr,
+                     S.s_floor, out + 2 * r0, sb_out ? sb_out + r0 : nullptr, s));
   }
   return ISX_OK;
 }
@@ -661,10 +692,13 @@ isx_status isx_extract(isx_ctx* ctx, int32_t mlp_id, const isx_params* p, isx_me
       XCHK(ensure(ctx->sp_fb, n * 4));
       XCHK(ensure(ctx->sp_idx, n * 4));
       XCHK(ensure(ctx->sp_cnt, sizeof(int64_t)));
-      st = sur_predict_n(ctx, *S, n, centres, halves, (float*)ctx->sp_pred.p);
+      const bool based = S->base_mlp >= 0;
+      if (based) XCHK(ensure(ctx->sp_scale, n * 4));
+      float* unit = based ? (float*)ctx->sp_scale.p : nullptr;
+      st = sur_predict_n(ctx, *S, n, centres, halves, (float*)ctx->sp_pred.p, unit);
       if (st != ISX_OK) return bail(st);
       const int Ls = std::min(L, std::max(0, m.sur_levels - 1));
-      XCHK(sur_partition(n, (const float*)ctx->sp_pred.p, k, iso, pmask, m.sur_err_mu[Ls], m.sur_err_ls[Ls], m.sur_z,
+      XCHK(sur_partition(n, (const float*)ctx->sp_pred.p, unit, k, iso, pmask, m.sur_err_mu[Ls], m.sur_err_ls[Ls], m.sur_z, m.sur_z_acc,
                          L == p->max_depth ? 1 : 0, m.sur_accept_leaves, mask, (uint32_t*)ctx->sp_fb.p, s));
       XCHK(hipMemcpyAsync(outb, ctx->sp_pred.p, n * 8, hipMemcpyDeviceToDevice, s));
       XCHK(launch_compact(n, (const uint32_t*)ctx->sp_fb.p, nullptr, (uint32_t*)ctx->sp_idx.p, nullptr,
@@ -753,7 +787,7 @@ isx_status isx_extract(isx_ctx* ctx, int32_t mlp_id, const isx_params* p, isx_me
   if (p->precision == ISX_FP64) {
     XCHK(eval_points_f64(m, n_corners, (const float*)ctx->corner_pts.p, (float*)ctx->corner_vals.p, s));
   } else {
-    XCHK(eval_points_f32(m, n_corners, (const float*)ctx->corner_pts.p, (float*)ctx->corner_vals.p, s));
+    XCHK(eval_f32(ctx, m, n_corners, (const float*)ctx->corner_pts.p, (float*)ctx->corner_vals.p, s));
   }
   XCHK(hipEventRecord(ev[2], s));
   // marching cubes
@@ -941,7 +975,7 @@ isx_status isx_surrogate_set_norm(isx_ctx* ctx, int32_t sur_id, float mu_bar, fl
 // One forward and backward pass on rows [r0, r0 + batch) (wrapping) of the
 // training set; leaves the gradients in S.gW / S.gb.
 static isx_status sur_fwd_bwd(isx_ctx* ctx, Sur& S, int64_t n, const float* d_centres, const float* d_halves,
-                              const float* d_targets, int64_t r0, int batch, float* d_loss) {
+                              const float* d_targets, const float* d_base, int64_t r0, int batch, float* d_loss) {
   hipStream_t s = ctx->stream;
   int wmax = 2;
   for (int l = 0; l <= S.L; ++l) wmax = std::max(wmax, S.w[l]);
@@ -951,7 +985,7 @@ static isx_status sur_fwd_bwd(isx_ctx* ctx, Sur& S, int64_t n, const float* d_ce
   HIPCHK(ensure(ctx->sur_d[0], (size_t)batch * wmax * 4));
   HIPCHK(ensure(ctx->sur_d[1], (size_t)batch * wmax * 4));
   HIPCHK(sur_features(n, r0, batch, d_centres, d_halves, S.size_a, S.size_b, (float*)ctx->sur_act[0].p, d_targets,
-                      S.mu_bar, S.scale, (float*)ctx->sur_T.p, s));
+                      S.mu_bar, S.scale, d_base, S.s_floor, (float*)ctx->sur_T.p, s));
   for (int l = 0; l < S.L; ++l) {
     float* C = l + 1 < S.L ? (float*)ctx->sur_act[l + 1].p : (float*)ctx->sur_out.p;
     HIPCHK(sur_gemm(batch, S.w[l + 1], S.w[l], (const float*)ctx->sur_act[l].p, S.w[l], false, S.W[l], S.w[l], true, C,
@@ -976,6 +1010,19 @@ static isx_status sur_fwd_bwd(isx_ctx* ctx, Sur& S, int64_t n, const float* d_ce
   return ISX_OK;
 }
 
+// Base (f, s) of all n training cells when the surrogate has a base MLP.
+static isx_status sur_train_base(isx_ctx* ctx, const Sur& S, int64_t n, const float* d_centres,
+                                 const float* d_halves, const float** d_base) {
+  *d_base = nullptr;
+  if (S.base_mlp < 0) return ISX_OK;
+  const Model* base = get_model(ctx, S.base_mlp);
+  if (!base) return fail(ctx, ISX_EINVAL, "the surrogate's base MLP was unloaded");
+  HIPCHK(ensure(ctx->sur_base, (size_t)n * 8));
+  HIPCHK(linearize_mfma(*base, n, d_centres, d_halves, (float*)ctx->sur_base.p, ctx->stream));
+  *d_base = (const float*)ctx->sur_base.p;
+  return ISX_OK;
+}
+
 isx_status isx_surrogate_grad(isx_ctx* ctx, int32_t sur_id, int64_t n, const float* d_centres, const float* d_halves,
                               const float* d_targets, int64_t first_row, int32_t batch, float* const* h_gW,
                               float* const* h_gb, float* h_loss) {
@@ -986,7 +1033,10 @@ isx_status isx_surrogate_grad(isx_ctx* ctx, int32_t sur_id, int64_t n, const flo
   (void)hipSetDevice(ctx->device);
   Sur& S = *Sp;
   HIPCHK(ensure(ctx->sp_cnt, sizeof(float) * 2));
-  isx_status e = sur_fwd_bwd(ctx, S, n, d_centres, d_halves, d_targets, first_row % n, batch, (float*)ctx->sp_cnt.p);
+  const float* d_base = nullptr;
+  isx_status e = sur_train_base(ctx, S, n, d_centres, d_halves, &d_base);
+  if (e != ISX_OK) return e;
+  e = sur_fwd_bwd(ctx, S, n, d_centres, d_halves, d_targets, d_base, first_row % n, batch, (float*)ctx->sp_cnt.p);
   if (e != ISX_OK) return e;
   HIPCHK(hipStreamSynchronize(ctx->stream));
   for (int l = 0; l < S.L; ++l) {
@@ -1009,9 +1059,15 @@ isx_status isx_surrogate_train(isx_ctx* ctx, int32_t sur_id, int64_t n, const fl
   (void)hipSetDevice(ctx->device);
   hipStream_t s = ctx->stream;
   const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const float* d_base = nullptr;
+  {
+    isx_status e = sur_train_base(ctx, S, n, d_centres, d_halves, &d_base);
+    if (e != ISX_OK) return e;
+  }
   for (int st = 0; st < steps; ++st) {
     const int64_t r0 = (first_row + (int64_t)st * batch) % n;
-    isx_status e = sur_fwd_bwd(ctx, S, n, d_centres, d_halves, d_targets, r0, batch, d_loss ? d_loss + st : nullptr);
+    isx_status e = sur_fwd_bwd(ctx, S, n, d_centres, d_halves, d_targets, d_base, r0, batch,
+                               d_loss ? d_loss + st : nullptr);
     if (e != ISX_OK) return e;
     S.t += 1;
     const float c1 = 1.f - std::pow(b1, (float)S.t), c2 = 1.f - std::pow(b2, (float)S.t);
@@ -1030,11 +1086,27 @@ isx_status isx_surrogate_predict(isx_ctx* ctx, int32_t sur_id, int64_t n, const 
   if (n < 0 || (n > 0 && (!d_centres || !d_halves || !d_out))) return fail(ctx, ISX_EINVAL, "bad arguments");
   if (n == 0) return ISX_OK;
   (void)hipSetDevice(ctx->device);
-  return sur_predict_n(ctx, *S, n, d_centres, d_halves, d_out);
+  return sur_predict_n(ctx, *S, n, d_centres, d_halves, d_out, nullptr);
+}
+
+isx_status isx_surrogate_set_base(isx_ctx* ctx, int32_t sur_id, int32_t mlp_id, float s_floor) {
+  Sur* S = get_sur(ctx, sur_id);
+  if (!S) return fail(ctx, ISX_EINVAL, "no such surrogate");
+  if (mlp_id == -1) {
+    S->base_mlp = -1;
+    return ISX_OK;
+  }
+  const Model* m = get_model(ctx, mlp_id);
+  if (!m) return fail(ctx, ISX_EINVAL, "bad mlp id");
+  if (!(s_floor > 0.f) || !std::isfinite(s_floor)) return fail(ctx, ISX_EINVAL, "s_floor must be finite and > 0");
+  S->base_mlp = mlp_id;
+  S->s_floor = s_floor;
+  return ISX_OK;
 }
 
 isx_status isx_surrogate_attach(isx_ctx* ctx, int32_t mlp_id, int32_t sur_id, int32_t n_levels,
-                                const float* h_err_mu, const float* h_err_logsig, float z, int32_t accept_leaves) {
+                                const float* h_err_mu, const float* h_err_logsig, float z, float z_accept,
+                                int32_t accept_leaves) {
   Model* m = get_model(ctx, mlp_id);
   if (!m) return fail(ctx, ISX_EINVAL, "bad mlp id");
   if (sur_id == -1) {
@@ -1042,7 +1114,7 @@ isx_status isx_surrogate_attach(isx_ctx* ctx, int32_t mlp_id, int32_t sur_id, in
     return ISX_OK;
   }
   if (!get_sur(ctx, sur_id)) return fail(ctx, ISX_EINVAL, "no such surrogate");
-  if (n_levels < 1 || n_levels > 16 || !h_err_mu || !h_err_logsig || !(z >= 0.f))
+  if (n_levels < 1 || n_levels > 16 || !h_err_mu || !h_err_logsig || !(z >= 0.f) || !(z_accept >= 0.f))
     return fail(ctx, ISX_EINVAL, "bad surrogate band");
   for (int i = 0; i < n_levels; ++i)
     if (!(h_err_mu[i] >= 0.f) || !(h_err_logsig[i] >= 0.f)) return fail(ctx, ISX_EINVAL, "bad error scales");
@@ -1053,6 +1125,7 @@ isx_status isx_surrogate_attach(isx_ctx* ctx, int32_t mlp_id, int32_t sur_id, in
     m->sur_err_ls[i] = i < n_levels ? h_err_logsig[i] : h_err_logsig[n_levels - 1];
   }
   m->sur_z = z;
+  m->sur_z_acc = z_accept;
   m->sur_accept_leaves = accept_leaves ? 1 : 0;
   return ISX_OK;
 }

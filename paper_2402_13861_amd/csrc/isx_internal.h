@@ -46,7 +46,7 @@ struct Model {
   int sur_id = -1;
   int sur_levels = 0;
   float sur_err_mu[16] = {}, sur_err_ls[16] = {};
-  float sur_z = 2.f;
+  float sur_z = 2.f, sur_z_acc = 2.f;
   int sur_accept_leaves = 0;
   int hidden() const { return n_linear - 1; }
   // columns of hidden layer h's coefficient block (h = 1..hidden())
@@ -93,17 +93,23 @@ struct IsoList {
   float c[ISX_MAX_ISO];
 };
 
-// Optional timing of hidden-layer launches (HIP events on the stream).
+// Optional timing of kernel launches (HIP events on the stream), kept per
+// kernel kind (isx_kernel_kind).
 struct Profiler {
+  static constexpr int kKinds = 8;
   bool on = false;
   struct Rec {
     hipEvent_t a, b;
     double flops, bytes;
+    int kind;
+  };
+  struct Tot {
+    int64_t launches = 0;
+    double ms = 0, flops = 0, bytes = 0;
   };
   std::vector<Rec> pending;
   std::vector<hipEvent_t> pool;
-  int64_t launches = 0;
-  double ms = 0, flops = 0, bytes = 0;
+  Tot tot[kKinds];
   hipEvent_t take() {
     hipEvent_t e = nullptr;
     if (!pool.empty()) {
@@ -114,15 +120,34 @@ struct Profiler {
     }
     return e;
   }
+  // start a record of `kind` (returns false when off or out of events)
+  bool begin(Rec& r, int kind, double flops, double bytes, hipStream_t s) {
+    if (!on) return false;
+    r.a = take();
+    r.b = take();
+    r.kind = kind;
+    r.flops = flops;
+    r.bytes = bytes;
+    if (!r.a || !r.b) return false;
+    (void)hipEventRecord(r.a, s);
+    return true;
+  }
+  void end(Rec& r, hipStream_t s) {
+    (void)hipEventRecord(r.b, s);
+    pending.push_back(r);
+    if (pending.size() > 4096) harvest();
+  }
   // fold completed records into the totals (blocks on the last one)
   void harvest() {
     for (Rec& r : pending) {
       float t = 0.f;
-      if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
-        ms += t;
-        flops += r.flops;
-        bytes += r.bytes;
-        ++launches;
+      if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess &&
+          r.kind >= 0 && r.kind < kKinds) {
+        Tot& T = tot[r.kind];
+        T.ms += t;
+        T.flops += r.flops;
+        T.bytes += r.bytes;
+        ++T.launches;
       }
       pool.push_back(r.a);
       pool.push_back(r.b);
@@ -163,6 +188,17 @@ bool bf16_supported(const Model& m);
 size_t prop_F_elems_bf16(const Model& m, int64_t C);
 hipError_t eval_points_f32(const Model& m, int64_t n, const float* pts, float* vals, hipStream_t s);
 hipError_t eval_points_f64(const Model& m, int64_t n, const float* pts, float* vals, hipStream_t s);
+// ---- dense FP32-MFMA forward passes (kernels_dense.hip) ----
+hipError_t eval_points_mfma(const Model& m, int64_t n, const float* pts, float* vals, hipStream_t s);
+// (f(c), |J(c) diag(h)| / sqrt(3)) per cell, out [n][2]
+hipError_t linearize_mfma(const Model& m, int64_t n, const float* centres, const float* halves, float* out,
+                          hipStream_t s);
+// output read-off of C cells from the hidden layers' Y, A, B, G vectors
+// (indexed by hidden layer 1..n_linear-1, each [C][padded width])
+hipError_t launch_output_mfma(const Model& m, isx_method method, int64_t C, float* const* Y, float* const* A,
+                              float* const* B, float* const* G, const float* halves, float* out, hipStream_t s);
+// algorithmic flops of the output read-off per cell
+double output_flops_per_cell(const Model& m);
 
 // ---- hierarchy / scan / marching cubes launchers (kernels_hier.hip) ----
 hipError_t launch_root(const Model& m, uint32_t full_mask, uint32_t* ids, uint32_t* pmask, float* centres,
@@ -205,15 +241,17 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
 hipError_t sur_gemm(int M, int N, int K, const float* A, int lda, bool ta, const float* B, int ldb, bool tb, float* C,
                     int ldc, const float* bias, bool relu, const float* mask, int ldm, hipStream_t s);
 hipError_t sur_features(int64_t n, int64_t r0, int B, const float* centres, const float* halves, float a, float b,
-                        float* X, const float* mu_sigma, float mu_bar, float scale, float* T, hipStream_t s);
+                        float* X, const float* mu_sigma, float mu_bar, float scale, const float* base,
+                        float s_floor, float* T, hipStream_t s);
 hipError_t sur_loss(int B, const float* out, const float* T, float* dout, float* loss_out, hipStream_t s);
 hipError_t sur_colsum(int M, int N, const float* dY, float* db, hipStream_t s);
 hipError_t sur_adam(int n, float* p, const float* g, float* m, float* v, float lr, float b1, float b2, float eps,
                     float c1, float c2, hipStream_t s);
-hipError_t sur_unstd(int64_t n, const float* o, float mu_bar, float scale, float* out, hipStream_t s);
-hipError_t sur_partition(int64_t n, const float* pred, float k, const IsoList& iso, const uint32_t* pmask,
-                         float err_mu, float err_ls, float z, int leaf, int accept_leaves, uint32_t* mask,
-                         uint32_t* fallback, hipStream_t s);
+hipError_t sur_unstd(int64_t n, const float* o, float mu_bar, float scale, const float* base, float s_floor,
+                     float* out, float* sb_out, hipStream_t s);
+hipError_t sur_partition(int64_t n, const float* pred, const float* mu_unit, float k, const IsoList& iso,
+                         const uint32_t* pmask, float err_mu, float err_ls, float z, float z_acc, int leaf,
+                         int accept_leaves, uint32_t* mask, uint32_t* fallback, hipStream_t s);
 hipError_t gather_u32(int64_t n, const uint32_t* idx, const uint32_t* src, uint32_t* dst, hipStream_t s);
 hipError_t scatter_u32(int64_t n, const uint32_t* idx, const uint32_t* src, uint32_t* dst, hipStream_t s);
 hipError_t scatter_u64(int64_t n, const uint32_t* idx, const uint64_t* src, uint64_t* dst, hipStream_t s);

@@ -463,17 +463,15 @@ hipError_t propagate_bf16(const PropArgs& a, PropWork<float>& w, uint16_t* Fbf_r
     const int g_in = h >= 3 ? m.pw[h - 2] : 0;
     __bf16* Fout = h < Lh ? Fbf[cur ^ 1] : nullptr;
     Profiler::Rec rec{};
-    const bool prof = a.prof && a.prof->on;
-    if (prof) {
+    bool prof = false;
+    if (a.prof && a.prof->on) {
       int64_t real_cols = 3;  // symbol columns (the centre is not part of the bf16 product)
       for (int i = 1; i <= h - 2; ++i) real_cols += m.widths[i];
-      rec.a = a.prof->take();
-      rec.b = a.prof->take();
-      rec.flops = 2.0 * m.widths[h] * m.widths[h - 1] * (double)real_cols * (double)C;
+      const double flops = 2.0 * m.widths[h] * m.widths[h - 1] * (double)real_cols * (double)C;
       // HBM: the stored part of the input block is read, the output block written
       const double stored_in = (double)(real_cols - (h >= 3 ? m.widths[h - 2] : 0));
-      rec.bytes = 2.0 * C * (stored_in * m.widths[h - 1] + (h < Lh ? (double)real_cols * m.widths[h] : 0.0));
-      if (rec.a) (void)hipEventRecord(rec.a, a.stream);
+      const double bytes = 2.0 * C * (stored_in * m.widths[h - 1] + (h < Lh ? (double)real_cols * m.widths[h] : 0.0));
+      prof = a.prof->begin(rec, ISX_KERNEL_HIDDEN_BF16, flops, bytes, a.stream);
     }
     const Layer& L = m.L[h - 1];
     const __bf16* WtPrev = reinterpret_cast<const __bf16*>(m.L[h - 2].Wtbf);
@@ -484,13 +482,16 @@ hipError_t propagate_bf16(const PropArgs& a, PropWork<float>& w, uint16_t* Fbf_r
                        : launch_bf16_m<ISX_AA>(a.bf16_variant, C, n_in, n_out, s_in, g_in, L.W, L.b, WtPrev, Gp2, Fbf[cur], Y[h - 1],
                                                A[h - 1], B[h - 1], G[h - 1], Fout, Y[h], A[h], B[h], G[h], a.stream);
     if (e != hipSuccess) return e;
-    if (prof && rec.a && rec.b) {
-      (void)hipEventRecord(rec.b, a.stream);
-      a.prof->pending.push_back(rec);
-    }
+    if (prof) a.prof->end(rec, a.stream);
     cur ^= 1;
   }
-  return launch_output_f32(m, a.method, C, w.vec, a.halves, a.out32, a.stream);
+  Profiler::Rec rec{};
+  const bool prof = a.prof && a.prof->begin(rec, ISX_KERNEL_OUTPUT, output_flops_per_cell(m) * (double)C,
+                                            4.0 * C * 4.0 * (double)m.pw[1] * Lh, a.stream);
+  hipError_t e = a.kernel_choice == 1 ? launch_output_f32(m, a.method, C, w.vec, a.halves, a.out32, a.stream)
+                                      : launch_output_mfma(m, a.method, C, Y, A, B, G, a.halves, a.out32, a.stream);
+  if (prof) a.prof->end(rec, a.stream);
+  return e;
 }
 
 }  // namespace isx

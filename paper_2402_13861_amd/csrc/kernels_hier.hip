@@ -37,7 +37,7 @@ static Domain make_domain(const Model& m, int level) {
 }
 
 // Box of cell (i, j, k) at the level: centre lo + (2i+1) step, half-width step
-// (Alg. 1 lines 1-2), computed in float64 and rounded once to float32.
+// (the box of Alg. 1), computed in float64 and rounded once to float32.
 __device__ __forceinline__ void cell_box(uint32_t id, const Domain& d, float* c, float* h) {
   const uint32_t ijk[3] = {unspread3(id), unspread3(id >> 1), unspread3(id >> 2)};
 #pragma unroll
@@ -91,7 +91,7 @@ hipError_t launch_children(const Model& m, int level, int64_t n_par, const uint3
   return hipGetLastError();
 }
 
-// Soft/hard bound test of Alg. 1 line 6 for every iso-value; the interval is
+// Soft/hard bound test of Alg. 1 for every iso-value; the interval is
 // closed (a bound touching c keeps the cell).
 __global__ void classify_kernel(int64_t n, const float* __restrict__ out, float k, IsoList iso,
                                 const uint32_t* __restrict__ pmask, uint32_t* __restrict__ mask) {

@@ -96,7 +96,7 @@ __device__ __forceinline__ T stat_term(T v) {
 }
 
 // ---------------------------------------------------------------- layer 1
-// Input form of a box (Sec. III-B / Sec. IV-C, Alg. 1 lines 1-3): centre c,
+// Input form of a box (Sec. III-B / Sec. IV-C; the input box of Alg. 1): centre c,
 // one symbol per axis with coefficient h_i (AA) or h_i/sqrt(3) (UP: a uniform
 // variable on [-h, h] has standard deviation h/sqrt 3).  One thread per
 // (cell, neuron).
@@ -454,16 +454,17 @@ static hipError_t propagate_impl(const PropArgs& a, PropWork<T>& w, bool use_mfm
     const int64_t cols_in = m.cols(h - 1);
     T* Fout = h < Lh ? w.F[cur ^ 1] : nullptr;
     Profiler::Rec rec{};
-    const bool prof = a.prof && a.prof->on;
-    if (prof) {
+    bool prof = false;
+    if (a.prof && a.prof->on) {
       int64_t real_cols = 4;
       for (int i = 1; i <= h - 2; ++i) real_cols += m.widths[i];
-      rec.a = a.prof->take();
-      rec.b = a.prof->take();
-      rec.flops = 2.0 * m.widths[h] * m.widths[h - 1] * (double)real_cols * (double)C;
-      rec.bytes = (double)sizeof(T) * C *
-                  ((double)real_cols * m.widths[h - 1] + (h < Lh ? (double)(real_cols + m.widths[h - 1]) * m.widths[h] : 0.0));
-      if (rec.a) (void)hipEventRecord(rec.a, a.stream);
+      const double flops = 2.0 * m.widths[h] * m.widths[h - 1] * (double)real_cols * (double)C;
+      const double bytes = (double)sizeof(T) * C *
+                           ((double)real_cols * m.widths[h - 1] +
+                            (h < Lh ? (double)(real_cols + m.widths[h - 1]) * m.widths[h] : 0.0));
+      const int kind = use_mfma ? ISX_KERNEL_HIDDEN_FP32 : (sizeof(T) == 8 ? ISX_KERNEL_HIDDEN_FP64
+                                                                           : ISX_KERNEL_HIDDEN_SIMT_FP32);
+      prof = a.prof->begin(rec, kind, flops, bytes, a.stream);
     }
     if (use_mfma) {
       hipError_t e = hidden_mfma<T>(METHOD, C, n_in, n_out, cols_in, wtptr<T>(m.L[h - 1]), bptr<T>(m.L[h - 1]),
@@ -477,21 +478,29 @@ static hipError_t propagate_impl(const PropArgs& a, PropWork<T>& w, bool use_mfm
                          n_out, cols_in, wtptr<T>(m.L[h - 1]), bptr<T>(m.L[h - 1]), w.F[cur], A[h - 1], B[h - 1],
                          G[h - 1], Fout, Y[h], A[h], B[h], G[h]);
     }
-    if (prof && rec.a && rec.b) {
-      (void)hipEventRecord(rec.b, a.stream);
-      a.prof->pending.push_back(rec);
-    }
+    if (prof) a.prof->end(rec, a.stream);
     cur ^= 1;
   }
-  NetView<T> view = make_view<T>(m);
-  for (int h = 1; h <= Lh; ++h) {
-    view.Y[h] = Y[h];
-    view.A[h] = A[h];
-    view.B[h] = B[h];
-    view.G[h] = G[h];
+  Profiler::Rec rec{};
+  const bool prof = a.prof && a.prof->begin(rec, ISX_KERNEL_OUTPUT, output_flops_per_cell(m) * (double)C,
+                                            (double)sizeof(T) * C * 4.0 * (double)m.pw[1] * Lh, a.stream);
+  if (use_mfma && sizeof(T) == 4 && a.out64 == nullptr) {
+    hipError_t e = launch_output_mfma(m, (isx_method)METHOD, C, reinterpret_cast<float* const*>(Y),
+                                      reinterpret_cast<float* const*>(A), reinterpret_cast<float* const*>(B),
+                                      reinterpret_cast<float* const*>(G), a.halves, a.out32, a.stream);
+    if (e != hipSuccess) return e;
+  } else {
+    NetView<T> view = make_view<T>(m);
+    for (int h = 1; h <= Lh; ++h) {
+      view.Y[h] = Y[h];
+      view.A[h] = A[h];
+      view.B[h] = B[h];
+      view.G[h] = G[h];
+    }
+    hipLaunchKernelGGL((output_kernel<T, METHOD>), dim3((unsigned)C), dim3(256), 0, a.stream, C, view, a.halves,
+                       a.out32, a.out64);
   }
-  hipLaunchKernelGGL((output_kernel<T, METHOD>), dim3((unsigned)C), dim3(256), 0, a.stream, C, view, a.halves,
-                     a.out32, a.out64);
+  if (prof) a.prof->end(rec, a.stream);
   return hipGetLastError();
 }
 

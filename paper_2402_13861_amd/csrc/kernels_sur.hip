@@ -99,12 +99,14 @@ hipError_t sur_gemm(int M, int N, int K, const float* A, int lda, bool ta, const
 
 // ---------------------------------------------------------- elementwise
 // Features x = (c_x, c_y, c_z, a * log2(2 h_x) + b) of rows [r0, r0+B) of a
-// data set of n cells (wrapping around), and optionally the standardised
-// targets ((mu - mu_bar)/S, ln sigma).
+// data set of n cells (wrapping around), and optionally the targets: the
+// standardised ((mu - mu_bar)/S, ln sigma) or, with a base (f, s) per cell,
+// the corrections to that base ((mu - f)/s_b, ln(sigma/s_b)), s_b =
+// max(s, s_floor).
 __global__ void sur_features_kernel(int64_t n, int64_t r0, int B, const float* __restrict__ centres,
                                     const float* __restrict__ halves, float a, float b, float* __restrict__ X,
                                     const float* __restrict__ mu_sigma, float mu_bar, float scale,
-                                    float* __restrict__ T) {
+                                    const float* __restrict__ base, float s_floor, float* __restrict__ T) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= B) return;
   const int64_t row = (r0 + i) % n;
@@ -115,16 +117,23 @@ __global__ void sur_features_kernel(int64_t n, int64_t r0, int B, const float* _
   if (T) {
     const float mu = mu_sigma[row * 2 + 0];
     const float sg = fmaxf(mu_sigma[row * 2 + 1], 1e-12f * scale);
-    T[i * 2 + 0] = (mu - mu_bar) / scale;
-    T[i * 2 + 1] = logf(sg);
+    if (base) {
+      const float sb = fmaxf(base[row * 2 + 1], s_floor);
+      T[i * 2 + 0] = (mu - base[row * 2 + 0]) / sb;
+      T[i * 2 + 1] = logf(sg / sb);
+    } else {
+      T[i * 2 + 0] = (mu - mu_bar) / scale;
+      T[i * 2 + 1] = logf(sg);
+    }
   }
 }
 
 hipError_t sur_features(int64_t n, int64_t r0, int B, const float* centres, const float* halves, float a, float b,
-                        float* X, const float* mu_sigma, float mu_bar, float scale, float* T, hipStream_t s) {
+                        float* X, const float* mu_sigma, float mu_bar, float scale, const float* base,
+                        float s_floor, float* T, hipStream_t s) {
   if (B <= 0) return hipSuccess;
   hipLaunchKernelGGL(sur_features_kernel, dim3((B + 255) / 256), dim3(256), 0, s, n, r0, B, centres, halves, a, b, X,
-                     mu_sigma, mu_bar, scale, T);
+                     mu_sigma, mu_bar, scale, base, s_floor, T);
   return hipGetLastError();
 }
 
@@ -194,39 +203,54 @@ hipError_t sur_adam(int n, float* p, const float* g, float* m, float* v, float l
   return hipGetLastError();
 }
 
-// Standardised outputs -> (mu_hat, sigma_hat) in field units.
+// Network outputs -> (mu_hat, sigma_hat) in field units: standardised
+// outputs, or corrections to a base (f, s) per cell (then the base scale s_b
+// is also written to sb_out if given).
 __global__ void sur_unstd_kernel(int64_t n, const float* __restrict__ o, float mu_bar, float scale,
-                                 float* __restrict__ out) {
+                                 const float* __restrict__ base, float s_floor, float* __restrict__ out,
+                                 float* __restrict__ sb_out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  out[i * 2 + 0] = mu_bar + scale * o[i * 2 + 0];
-  out[i * 2 + 1] = expf(o[i * 2 + 1]);
+  if (base) {
+    const float sb = fmaxf(base[i * 2 + 1], s_floor);
+    out[i * 2 + 0] = base[i * 2 + 0] + sb * o[i * 2 + 0];
+    out[i * 2 + 1] = sb * expf(o[i * 2 + 1]);
+    if (sb_out) sb_out[i] = sb;
+  } else {
+    out[i * 2 + 0] = mu_bar + scale * o[i * 2 + 0];
+    out[i * 2 + 1] = expf(o[i * 2 + 1]);
+  }
 }
 
-hipError_t sur_unstd(int64_t n, const float* o, float mu_bar, float scale, float* out, hipStream_t s) {
+hipError_t sur_unstd(int64_t n, const float* o, float mu_bar, float scale, const float* base, float s_floor,
+                     float* out, float* sb_out, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(sur_unstd_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, o, mu_bar, scale, out);
+  hipLaunchKernelGGL(sur_unstd_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, o, mu_bar, scale, base,
+                     s_floor, out, sb_out);
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------ partition
 // Decide a cell from the surrogate when every iso-value it still carries is
 // confidently inside or outside the soft bound, allowing z standard deviations
-// of the surrogate's own per-level error (err_mu in field units, err_ls in
-// log-sigma units):
-//   prune bit j   if |mu_hat - c_j| - z err_mu > t sigma_hat e^{+z err_ls}
-//   accept bit j  if |mu_hat - c_j| + z err_mu < t sigma_hat e^{-z err_ls}
+// of the surrogate's own per-level error (err_mu in field units, or in units
+// of the per-cell base scale mu_unit[i] when given; err_ls in log-sigma
+// units), z_p for pruning and z_a for accepting:
+//   prune bit j   if |mu_hat - c_j| - z_p err_mu > t sigma_hat e^{+z_p err_ls}
+//   accept bit j  if |mu_hat - c_j| + z_a err_mu < t sigma_hat e^{-z_a err_ls}
 // and fall back to propagation otherwise (always at the leaf level unless
 // accept_leaves).  Writes mask (decided cells) and fallback flags.
-__global__ void sur_partition_kernel(int64_t n, const float* __restrict__ pred, float k, IsoList iso,
-                                     const uint32_t* __restrict__ pmask, float err_mu, float err_ls, float z,
+__global__ void sur_partition_kernel(int64_t n, const float* __restrict__ pred, const float* __restrict__ mu_unit,
+                                     float k, IsoList iso, const uint32_t* __restrict__ pmask, float err_mu,
+                                     float err_ls, float z, float z_acc,
                                      int leaf, int accept_leaves, uint32_t* __restrict__ mask,
                                      uint32_t* __restrict__ fallback) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float mu = pred[2 * i], sg = pred[2 * i + 1];
-  const float hi_s = k * sg * expf(z * err_ls), lo_s = k * sg * expf(-z * err_ls);
-  const float e = z * err_mu;
+  const float hi_s = k * sg * expf(z * err_ls), lo_s = k * sg * expf(-z_acc * err_ls);
+  const float unit = err_mu * (mu_unit ? mu_unit[i] : 1.f);
+  const float e = z * unit, ea = z_acc * unit;
   const uint32_t pm = pmask[i];
   uint32_t acc_bits = 0;
   bool unsure = false;
@@ -234,7 +258,7 @@ __global__ void sur_partition_kernel(int64_t n, const float* __restrict__ pred, 
     if (!((pm >> j) & 1u)) continue;
     const float d = fabsf(mu - iso.c[j]);
     if (d - e > hi_s) continue;                 // confidently outside
-    if (d + e < lo_s) acc_bits |= 1u << j;      // confidently inside
+    if (d + ea < lo_s) acc_bits |= 1u << j;     // confidently inside
     else unsure = true;
   }
   if (!(mu == mu) || !(sg == sg)) unsure = true;  // NaN predictions fall back
@@ -243,12 +267,12 @@ __global__ void sur_partition_kernel(int64_t n, const float* __restrict__ pred, 
   mask[i] = fb ? 0u : acc_bits;
 }
 
-hipError_t sur_partition(int64_t n, const float* pred, float k, const IsoList& iso, const uint32_t* pmask,
-                         float err_mu, float err_ls, float z, int leaf, int accept_leaves, uint32_t* mask,
-                         uint32_t* fallback, hipStream_t s) {
+hipError_t sur_partition(int64_t n, const float* pred, const float* mu_unit, float k, const IsoList& iso,
+                         const uint32_t* pmask, float err_mu, float err_ls, float z, float z_acc, int leaf,
+                         int accept_leaves, uint32_t* mask, uint32_t* fallback, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(sur_partition_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, pred, k, iso,
-                     pmask, err_mu, err_ls, z, leaf, accept_leaves, mask, fallback);
+  hipLaunchKernelGGL(sur_partition_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, pred, mu_unit, k, iso,
+                     pmask, err_mu, err_ls, z, z_acc, leaf, accept_leaves, mask, fallback);
   return hipGetLastError();
 }
 

@@ -6,11 +6,14 @@ The surrogate is a ReLU MLP 4 -> 128 -> 128 -> 128 -> 2 that maps a cell
 (centre, log2 size) to the propagation's predicted (mean, sigma).  It is
 trained on (cell, propagated mean/sigma) pairs produced by the method itself:
 half are uniform random cells at octree levels 3..D, half are cells visited
-by a plain extraction.  Its error is calibrated per octree level on held-out
-pairs; during extraction a cell is decided by the surrogate only when every
-iso-value it carries lies outside (or inside) the predicted soft bound by
-more than z = 2 standard deviations of that error, and is propagated
-otherwise.
+by a plain extraction.  Its two outputs are either standardised targets
+((mu - mu_bar)/S, ln sigma), or, with ``base=True``, corrections to the
+centre linearisation (f(c), s) of the INR, which the library computes
+alongside: ((mu - f)/s_b, ln(sigma/s_b)).  Its error is calibrated per octree
+level on held-out pairs; during extraction a cell is decided by the
+surrogate only when every iso-value it carries lies outside (or inside) the
+predicted soft bound by more than z standard deviations of that error, and
+is propagated otherwise.
 """
 
 from __future__ import annotations
@@ -70,14 +73,18 @@ class SurrogateInfo:
     err_logsig: List[float] = field(default_factory=list)
     losses: Optional[np.ndarray] = None
     z: float = 2.0
+    z_accept: float = 2.0
+    holdout_miss: float = 0.0
+    holdout_false_accept: float = 0.0
 
 
-def miss_rate(pred, true, levels, err_mu, err_ls, isos, k, z):
+def miss_rate(pred, true, levels, err_mu, err_ls, isos, k, z, unit=None):
     """Fraction of held-out cells that the plain test keeps for some iso-value
-    but the surrogate rule at band z would drop for that iso-value."""
+    but the surrogate rule at band z would drop for that iso-value (err_mu in
+    units of ``unit`` per cell when given)."""
     mu_h, sg_h = pred[:, 0], pred[:, 1]
     mu, sg = true[:, 0], true[:, 1]
-    em = np.asarray(err_mu)[levels]
+    em = np.asarray(err_mu)[levels] * (1.0 if unit is None else unit)
     el = np.asarray(err_ls)[levels]
     hi_s = k * sg_h * np.exp(z * el)
     miss = np.zeros(len(mu), dtype=bool)
@@ -90,20 +97,47 @@ def miss_rate(pred, true, levels, err_mu, err_ls, isos, k, z):
     return miss.sum() / max(kept.sum(), 1)
 
 
+def false_accept_rate(pred, true, levels, err_mu, err_ls, isos, k, z, unit=None):
+    """Held-out cells that the surrogate rule at accept band z would accept
+    for an iso-value the plain test rejects, per cell the plain test keeps."""
+    mu_h, sg_h = pred[:, 0], pred[:, 1]
+    mu, sg = true[:, 0], true[:, 1]
+    em = np.asarray(err_mu)[levels] * (1.0 if unit is None else unit)
+    el = np.asarray(err_ls)[levels]
+    lo_s = k * sg_h * np.exp(-z * el)
+    bad = np.zeros(len(mu), dtype=bool)
+    kept = np.zeros(len(mu), dtype=bool)
+    for c in isos:
+        plain_keep = np.abs(mu - c) <= k * sg
+        accept = np.abs(mu_h - c) + z * em < lo_s
+        kept |= plain_keep
+        bad |= accept & ~plain_keep
+    return bad.sum() / max(kept.sum(), 1)
+
+
+Z_LADDER = (0.0, 0.5, 1.0, 1.5, 2.0, 2.5, 3.0, 3.5, 4.0, 5.0, 6.0, 8.0, 12.0)
+
+
 def train_surrogate(ctx, mlp_id: int, depth: int, mu_bar: float, scale: float, visited=None,
                     n_pairs: int = 5_000_000, steps: int = 2000, batch: int = 4096, lr: float = 1e-3,
                     hidden=(128, 128, 128), seed: int = 0, holdout: int = 200_000, z: Optional[float] = None,
-                    isos=None, k: float = 3.0, miss_target: float = 1e-4, accept_leaves: bool = False,
+                    isos=None, k: float = 3.0, miss_target: float = 1e-4, accept_target: float = 1e-3,
+                    z_accept: Optional[float] = None, accept_leaves: bool = False, base: bool = False,
                     lo=(-1.0,) * 3, hi=(1.0,) * 3, log=None) -> SurrogateInfo:
     """Train a surrogate for ``mlp_id`` and attach it for extraction.
 
     visited: optional list, per octree level, of Morton ids of cells a plain
     extraction propagated; half of the training pairs are drawn from them.
-    Targets are the float32 uncertainty propagation of each training cell.
+    Targets are the float32 uncertainty propagation of each training cell;
+    with ``base`` the network learns corrections to the INR's centre
+    linearisation (s_b floored at 1e-6 S) and err_mu is in units of s_b.
     The safety band is z standard deviations of the surrogate's per-level
     error; with z None it is the smallest of a ladder of values whose miss
     rate on the held-out cells (against the iso-values ``isos`` and the
-    bound multiplier k) is at most ``miss_target``.
+    bound multiplier k) is at most ``miss_target``.  A wrong accept only
+    costs work, so the accept band z_accept is calibrated on its own: with
+    None, the smallest ladder value whose held-out false-accept rate is at
+    most ``accept_target``.
     """
     import torch
 
@@ -154,6 +188,9 @@ def train_surrogate(ctx, mlp_id: int, depth: int, mu_bar: float, scale: float, v
         bs.append((rng.standard_normal(fo) * std * 0.1).astype(np.float32))
     sid = ctx.surrogate_load(Ws, bs)
     ctx.surrogate_set_norm(sid, mu_bar, scale, SIZE_A, SIZE_B)
+    s_floor = 1e-6 * scale
+    if base:
+        ctx.surrogate_set_base(sid, mlp_id, s_floor)
 
     Ct, Ht, Tt = C[:n_train], H[:n_train], T[:n_train]
     losses = torch.empty(steps, dtype=torch.float32, device=dev)
@@ -173,6 +210,12 @@ def train_surrogate(ctx, mlp_id: int, depth: int, mu_bar: float, scale: float, v
     p = P.cpu().numpy().astype(np.float64)
     tv = Tv.cpu().numpy().astype(np.float64)
     lv = levels[n_train:]
+    unit = None
+    if base:
+        Bv = torch.empty((holdout, 2), dtype=torch.float32, device=dev)
+        ctx.linearize(mlp_id, Cv, Hv, Bv)
+        torch.cuda.synchronize(dev)
+        unit = np.maximum(Bv.cpu().numpy()[:, 1].astype(np.float64), s_floor)
     err_mu, err_ls = [], []
     for L in range(depth + 1):
         sel = lv == L
@@ -181,22 +224,37 @@ def train_surrogate(ctx, mlp_id: int, depth: int, mu_bar: float, scale: float, v
             err_ls.append(err_ls[-1] if err_ls else 1.0)
             continue
         dmu = p[sel, 0] - tv[sel, 0]
+        if unit is not None:
+            dmu = dmu / unit[sel]
         dls = np.log(np.maximum(p[sel, 1], 1e-30)) - np.log(np.maximum(tv[sel, 1], 1e-30))
         err_mu.append(float(np.sqrt(np.mean(dmu ** 2))))
         err_ls.append(float(np.sqrt(np.mean(dls ** 2))))
     log("surrogate: per-level error (mu, log sigma): " +
         ", ".join(f"L{L} {a:.3g}/{b:.3g}" for L, (a, b) in enumerate(zip(err_mu, err_ls))))
+    if (z is None or z_accept is None) and isos is None:
+        raise ValueError("calibrating a band needs the iso-values")
     if z is None:
-        if isos is None:
-            raise ValueError("z=None calibrates the band and needs the iso-values")
         rates = {}
-        for zc in (2.0, 2.5, 3.0, 3.5, 4.0, 5.0, 6.0, 8.0, 12.0):
-            rates[zc] = miss_rate(p, tv, lv, err_mu, err_ls, isos, k, zc)
+        for zc in Z_LADDER[4:]:
+            rates[zc] = miss_rate(p, tv, lv, err_mu, err_ls, isos, k, zc, unit)
             if rates[zc] <= miss_target:
                 break
         z = zc
-        log("surrogate: held-out miss rate by band: " + ", ".join(f"z={a}: {b:.2e}" for a, b in rates.items()))
-    ctx.surrogate_attach(mlp_id, sid, err_mu, err_ls, z=z, accept_leaves=accept_leaves)
+        log("surrogate: held-out miss rate by prune band: " + ", ".join(f"z={a}: {b:.2e}" for a, b in rates.items()))
+    if z_accept is None:
+        rates = {}
+        for zc in Z_LADDER:
+            rates[zc] = false_accept_rate(p, tv, lv, err_mu, err_ls, isos, k, zc, unit)
+            if rates[zc] <= accept_target:
+                break
+        z_accept = zc
+        log("surrogate: held-out false-accept rate by accept band: " +
+            ", ".join(f"z={a}: {b:.2e}" for a, b in rates.items()))
+    ctx.surrogate_attach(mlp_id, sid, err_mu, err_ls, z=z, accept_leaves=accept_leaves, z_accept=z_accept)
     info = SurrogateInfo(sid, n_train, steps, train_s, float(losses[-20:].mean()), err_mu, err_ls, losses)
     info.z = z
+    info.z_accept = z_accept
+    if isos is not None:
+        info.holdout_miss = float(miss_rate(p, tv, lv, err_mu, err_ls, isos, k, z, unit))
+        info.holdout_false_accept = float(false_accept_rate(p, tv, lv, err_mu, err_ls, isos, k, z_accept, unit))
     return info

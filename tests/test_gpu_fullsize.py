@@ -1,0 +1,128 @@
+"""Parity at the full benchmark shape, on sampled outputs.
+
+Workload: the 3->256x5->1 ReLU INR fitted to the synthetic Fourier field,
+octree to depth 9 (512^3 effective cells), iso-values at the 25/50/75 %
+output quantiles, uncertainty propagation with t = 3, BF16 products with the
+float64 re-check band of 1e-3 S: the launch configuration the benchmark
+times.  The float64 oracle cannot run the whole extraction, so it checks
+cells sampled at several levels (bounds and masks, the mask given the
+parent's mask the GPU computed) and triangles of sampled leaves (vertices on
+shared grid edges).
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import mc
+from oracle.metrics import margin
+from oracle.octree import cell_boxes, classify
+from oracle.mlp import mlp_forward
+from oracle.propagate import UP, propagate
+
+from _parity import leaf_ijk
+
+pytestmark = pytest.mark.gpu
+
+WORKLOAD = "relu256x5_fourier"
+
+
+@pytest.fixture(scope="module")
+def run():
+    import paper_2402_13861_amd as isx
+    from workloads.configs import WORKLOADS, isovalues, load_mlp
+
+    assert torch.cuda.is_available()
+    w = WORKLOADS[WORKLOAD]
+    mlp = load_mlp(WORKLOAD)
+    isos, S = isovalues(WORKLOAD)
+    ctx = isx.Context(0)
+    mid = ctx.load_weights(mlp)
+    ctx.set_isovalues(mid, isos)
+    ctx.set_option(isx.KEEP_LEVELS, 1)
+    print(f"extracting {WORKLOAD} depth {w['depth']} bf16 band {w['band_rel']} S", flush=True)
+    mesh = ctx.extract(mid, isx.UP, isx.BF16, k=w["k"], max_depth=w["depth"], fp64_band=w["band_rel"] * S)
+    ctx.set_option(isx.KEEP_LEVELS, 0)
+    print("levels", [(l["cells"], l["active"], l["rechecked"]) for l in mesh.levels()], flush=True)
+    yield dict(ctx=ctx, mid=mid, mesh=mesh, mlp=mlp, isos=np.asarray(isos, np.float64), S=S, k=w["k"],
+               depth=w["depth"])
+    mesh.free()
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def test_sampled_cells_match_oracle(run):
+    mesh, mlp, isos, S, k = run["mesh"], run["mlp"], run["isos"], run["S"], run["k"]
+    rng = np.random.default_rng(0)
+    worst = 0.0
+    for L in (3, 5, 7, 8, 9):
+        ids, out, masks = mesh.level_cells(L)
+        pids, _, pmasks = mesh.level_cells(L - 1)
+        pick = np.sort(rng.choice(ids.size, size=min(48, ids.size), replace=False))
+        cid = ids[pick].astype(np.uint64)
+        c, h = cell_boxes(L, cid)
+        mu, sg = propagate(mlp, c, h, UP)
+        # bounds: the bf16 parity tolerance (5e-2 of max(|o|, S))
+        g = out[pick].astype(np.float64)
+        for sgn in (-1.0, 1.0):
+            o = mu + sgn * k * sg
+            e = np.abs(g[:, 0] + sgn * k * g[:, 1] - o) / np.maximum(np.abs(o), S)
+            worst = max(worst, float(e.max()))
+        # masks: parent mask from the GPU's previous level (Morton ids sorted)
+        par = (cid >> np.uint64(3)).astype(np.uint32)
+        pos = np.searchsorted(pids, par)
+        assert np.all(pids[pos] == par)
+        want = classify(mu, sg, k, isos, pmasks[pos])
+        m = margin(mu, sg, k, isos)
+        excused = m <= 1e-4 * S
+        diff = (want != masks[pick]) & ~excused
+        print(f"level {L}: {pick.size} sampled cells, {int((want != masks[pick]).sum())} mask differences "
+              f"({int(diff.sum())} unexcused)", flush=True)
+        assert not diff.any(), (L, cid[diff][:5])
+    print(f"max bound error over samples {worst:.3e}", flush=True)
+    assert worst <= 5e-2
+
+
+def test_sampled_leaf_triangles_match_oracle(run):
+    mesh, mlp, isos, S, depth = run["mesh"], run["mlp"], run["isos"], run["S"], run["depth"]
+    leaf_ids, leaf_masks = mesh.leaves()
+    rng = np.random.default_rng(1)
+    pick = np.sort(rng.choice(leaf_ids.size, size=400, replace=False))
+    ids, lm = leaf_ids[pick].astype(np.uint64), leaf_masks[pick]
+    ijk = leaf_ijk(ids)
+    vals = mc.corner_values(lambda p: mlp_forward(mlp, p), ijk, depth)
+    pos, keys, tiso = mesh.triangles()
+    flat_keys = keys.reshape(-1)
+    flat_pos = pos.reshape(-1, 3)
+    flat_iso = np.repeat(tiso, 3)
+    n_checked = 0
+    worst = 0.0
+    for j, c in enumerate(isos):
+        rows = np.nonzero((lm >> np.uint32(j)) & 1)[0]
+        if rows.size == 0:
+            continue
+        ot = mc.march(ijk[rows], vals[rows], c, depth)
+        if ot["keys"].size == 0:
+            continue
+        sel = flat_iso == j
+        gk = flat_keys[sel]
+        gp = flat_pos[sel]
+        order = np.argsort(gk, kind="stable")
+        gk, gp = gk[order], gp[order]
+        ok_ = ot["keys"].reshape(-1)
+        op = ot["pos"].reshape(-1, 3)
+        at = np.searchsorted(gk, ok_)
+        at = np.minimum(at, gk.size - 1)
+        found = gk[at] == ok_
+        # a leaf with a corner within 1e-4 S of the iso-value may have a
+        # different case on the GPU; every other oracle vertex must exist
+        near = np.abs(vals[rows] - c).min(axis=1) <= 1e-4 * S
+        tri_near = np.repeat(near[ot["cell"]], 3)
+        assert np.all(found | tri_near), int((~found & ~tri_near).sum())
+        d = np.abs(gp[at[found]] - op[found]).max()
+        worst = max(worst, float(d))
+        n_checked += int(found.sum())
+    print(f"{n_checked} sampled vertices, max vertex difference {worst:.2e}", flush=True)
+    assert n_checked > 100
+    assert worst <= 1e-4

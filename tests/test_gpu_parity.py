@@ -151,6 +151,55 @@ def test_eval_points_match_oracle(ctx):
         ctx.unload_mlp(mid)
 
 
+DENSE_WIDTHS = WIDTHS + [
+    [3, 96, 1],  # one hidden layer: no MFMA layer, output straight from layer 1
+    [3, 512, 512, 1],  # 64-column tiles
+    [3, 1024, 64, 1],  # 32-column tiles, fewer output tiles than waves
+    [3, 256, 256, 256, 256, 256, 1],  # the 3->256x5->1 shape
+]
+
+
+@pytest.mark.parametrize("widths", DENSE_WIDTHS, ids=lambda w: "x".join(map(str, w)))
+def test_dense_eval_and_linearize_match_oracle(ctx, widths):
+    """FP32-MFMA point evaluation and centre linearisation against the
+    float64 oracle, on ragged batch sizes; the SIMT evaluation agrees too."""
+    import paper_2402_13861_amd as isx
+    from oracle.linearize import linearize
+
+    mlp = he_normal_mlp(widths, seed=13)
+    S = output_scale(mlp)
+    mid = ctx.load_weights(mlp)
+    try:
+        for n in (1, 129, 4133):
+            x = uniform_points(n, seed=n).astype(np.float32)
+            ref = mlp_forward(mlp, x.astype(np.float64))
+            for kern in (0, 1):  # MFMA, SIMT
+                ctx.set_option(isx.HIDDEN_KERNEL, kern)
+                v = torch.full((n,), float("nan"), dtype=torch.float32, device="cuda")
+                ctx.eval_points(mid, isx.FP32, _dev(x), v)
+                torch.cuda.synchronize()
+                err = np.abs(v.cpu().numpy() - ref) / np.maximum(np.abs(ref), S)
+                assert err.max() <= 1e-5, (n, kern, err.max())
+            ctx.set_option(isx.HIDDEN_KERNEL, 0)
+            c, h, _ = random_boxes(n, range(0, 10), seed=n + 1)
+            f, s, margin = linearize(mlp, c.astype(np.float64), h.astype(np.float64), return_margin=True)
+            out = torch.full((n, 2), float("nan"), dtype=torch.float32, device="cuda")
+            ctx.linearize(mid, _dev(c), _dev(h), out)
+            torch.cuda.synchronize()
+            g = out.cpu().numpy().astype(np.float64)
+            ef = np.abs(g[:, 0] - f) / np.maximum(np.abs(f), S)
+            es = np.abs(g[:, 1] - s) / np.maximum(s, 1e-3 * S)
+            # a centre within float32 rounding of a kink may take the other side
+            ok = margin > 1e-4
+            print(f"n={n}: eval ok; linearise max rel err f {ef.max():.3e} s {es[ok].max() if ok.any() else 0:.3e} "
+                  f"({(~ok).sum()} cells near a kink)", flush=True)
+            assert ef.max() <= 1e-5
+            assert (es[ok] <= 1e-4).all()
+    finally:
+        ctx.set_option(isx.HIDDEN_KERNEL, 0)
+        ctx.unload_mlp(mid)
+
+
 def test_classify_compact_bit_exact(ctx):
     rng = np.random.default_rng(9)
     n = 20_011  # several scan tiles and a ragged tail

@@ -75,3 +75,19 @@ def test_training_reduces_loss_on_a_smooth_target():
         sg.adam_step(params, dWs + dbs, m, v, t, 3e-3)
     l1 = sg.loss(sg.forward(Ws, bs, X)[0], T)
     assert l1 < 0.2 * l0
+
+
+def test_base_targets_invert_base_prediction():
+    rng = np.random.default_rng(9)
+    f = rng.normal(0, 1, 50)
+    s = np.exp(rng.normal(-3, 1, 50))
+    s[:5] = 0.0  # below the floor
+    mu = f + s * rng.normal(0, 0.1, 50)
+    sigma = np.maximum(s, 1e-6) * np.exp(rng.normal(0, 0.05, 50))
+    T = sg.base_targets(mu, sigma, f, s, 1e-6)
+    back = sg.base_prediction(T, f, s, 1e-6)
+    np.testing.assert_allclose(back[:, 0], mu, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(back[:, 1], sigma, rtol=1e-12)
+    # a perfect linearisation gives zero targets
+    Z = sg.base_targets(f[5:], s[5:], f[5:], s[5:], 1e-6)
+    np.testing.assert_allclose(Z, 0.0, atol=1e-12)
