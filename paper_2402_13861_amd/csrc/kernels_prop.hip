@@ -419,6 +419,10 @@ hipError_t launch_hidden_mfma_f32(int method, int64_t C, int n_in, int n_out, in
                                   const float* bias, const float* Fin, const float* Ain, const float* Bin,
                                   const float* Gin, float* Fout, float* Y, float* A, float* B, float* G,
                                   hipStream_t s);
+hipError_t launch_hidden_mfma_f64(int method, int64_t C, int n_in, int n_out, int64_t cols_in, const double* Wt,
+                                  const double* bias, const double* Fin, const double* Ain, const double* Bin,
+                                  const double* Gin, double* Fout, double* Y, double* A, double* B, double* G,
+                                  hipStream_t s);
 bool mfma_supported(const Model& m);
 
 template <typename T>
@@ -431,6 +435,13 @@ hipError_t hidden_mfma<float>(int method, int64_t C, int n_in, int n_out, int64_
                               const float* bias, const float* Fin, const float* Ain, const float* Bin,
                               const float* Gin, float* Fout, float* Y, float* A, float* B, float* G, hipStream_t s) {
   return launch_hidden_mfma_f32(method, C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, s);
+}
+template <>
+hipError_t hidden_mfma<double>(int method, int64_t C, int n_in, int n_out, int64_t cols_in, const double* Wt,
+                               const double* bias, const double* Fin, const double* Ain, const double* Bin,
+                               const double* Gin, double* Fout, double* Y, double* A, double* B, double* G,
+                               hipStream_t s) {
+  return launch_hidden_mfma_f64(method, C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, s);
 }
 
 template <typename T, int METHOD>
@@ -462,8 +473,8 @@ static hipError_t propagate_impl(const PropArgs& a, PropWork<T>& w, bool use_mfm
       const double bytes = (double)sizeof(T) * C *
                            ((double)real_cols * m.widths[h - 1] +
                             (h < Lh ? (double)(real_cols + m.widths[h - 1]) * m.widths[h] : 0.0));
-      const int kind = use_mfma ? ISX_KERNEL_HIDDEN_FP32 : (sizeof(T) == 8 ? ISX_KERNEL_HIDDEN_FP64
-                                                                           : ISX_KERNEL_HIDDEN_SIMT_FP32);
+      const int kind = sizeof(T) == 8 ? ISX_KERNEL_HIDDEN_FP64
+                                      : (use_mfma ? ISX_KERNEL_HIDDEN_FP32 : ISX_KERNEL_HIDDEN_SIMT_FP32);
       prof = a.prof->begin(rec, kind, flops, bytes, a.stream);
     }
     if (use_mfma) {
@@ -534,8 +545,9 @@ hipError_t propagate_f32(const PropArgs& a, PropWork<float>& w) {
 
 hipError_t propagate_f64(const PropArgs& a, PropWork<double>& w) {
   if (a.C <= 0) return hipSuccess;
-  return a.method == ISX_UP ? propagate_impl<double, ISX_UP>(a, w, false)
-                            : propagate_impl<double, ISX_AA>(a, w, false);
+  const bool use_mfma = a.kernel_choice != 1 && mfma_supported(*a.m);
+  return a.method == ISX_UP ? propagate_impl<double, ISX_UP>(a, w, use_mfma)
+                            : propagate_impl<double, ISX_AA>(a, w, use_mfma);
 }
 
 template <typename T, int PT>

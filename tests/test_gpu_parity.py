@@ -85,6 +85,8 @@ def test_propagate_fp32_and_fp64_match_oracle(ctx, widths, mname):
         assert_pair_close(g64, ref, S, 1e-10, f"fp64 {mname} {widths}", k=k)
         g32s, _ = _gpu_prop(ctx, mid, gm, isx.FP32, c, h, kernel=1)
         assert_pair_close(g32s, ref, S, 1e-5, f"fp32 simt {mname} {widths}", k=k)
+        _, g64s = _gpu_prop(ctx, mid, gm, isx.FP64, c, h, kernel=1)
+        assert_pair_close(g64s, ref, S, 1e-10, f"fp64 simt {mname} {widths}", k=k)
     finally:
         ctx.unload_mlp(mid)
 
