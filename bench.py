@@ -44,16 +44,18 @@ def kernel_source_hash(precision: str) -> str:
     return hashlib.sha256(src.read_bytes()).hexdigest()[:16]
 
 
-def traffic_from_profiles(precision: str, flops_per_launch: float):
-    """HBM bytes per launch of the dominant kernel from committed rocprofv3
-    counter summaries, if they were taken on the current kernel source."""
+def traffic_from_profiles(precision: str, cells_per_launch: float):
+    """HBM bytes per launch of the dominant kernel: the committed rocprofv3
+    counter summary's bytes per propagated cell (all hidden-layer launches of
+    a cell; taken on the current kernel source, else None) times the
+    propagated cells per launch of this run (propagated cells / launches)."""
     f = ROOT / "profiles" / f"hidden_layer_{precision}_traffic.json"
     if not f.exists():
         return None
     t = json.loads(f.read_text())
     if t.get("kernel_source_sha256_16") != kernel_source_hash(precision):
         return None
-    return t.get("hbm_bytes_per_launch")
+    return t["hbm_bytes_per_cell"] * cells_per_launch
 
 
 def cpu_baseline(mlp, levels, budget_s: float):
@@ -244,7 +246,8 @@ def main(argv=None):
     flops_per_launch = kp["flops"] / launches
     achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
     peak = PEAK_TFLOPS[a.precision]
-    traffic = traffic_from_profiles(a.precision, flops_per_launch)
+    cells_per_launch = propagated / (kp["launches"] / K) if kp["launches"] else 0.0
+    traffic = traffic_from_profiles(a.precision, cells_per_launch)
     roofline = {
         "bound": "mfma",
         "kernel": "hidden_mfma_f32_kernel" if a.precision == "fp32" else "hidden_mfma_bf16_kernel",
