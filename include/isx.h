@@ -281,7 +281,10 @@ typedef enum {
   ISX_PROFILE = 3,         /* value 1: time every hidden-layer launch with HIP events */
   ISX_SCRATCH_BYTES = 4,   /* bytes of propagation scratch per batch (default 16 GiB) */
   ISX_VERBOSE = 5,         /* value 1: isx_extract prints one line per octree level to stderr */
-  ISX_BF16_VARIANT = 6     /* bf16 hidden-layer tile shape: 0 = default for the width, 1..4 = forced */
+  ISX_BF16_VARIANT = 6,    /* bf16 hidden-layer tile shape: 0 = default for the width, 1..4 = forced */
+  ISX_UP_FORM = 7          /* bf16 uncertainty propagation: 0 = covariance form (exact alternative to
+                              coefficient tracking: C_h = W_h (D C_{h-1} D + diag(gamma^2)) W_h^T, one
+                              fused launch per batch, hidden widths <= 256), 1 = coefficient form */
 } isx_option;
 isx_status isx_set_option(isx_ctx* ctx, isx_option option, int64_t value);
 

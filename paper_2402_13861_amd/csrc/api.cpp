@@ -49,6 +49,7 @@ struct isx_ctx {
   bool verbose = false;
   int kernel_choice = 0;
   int bf16_variant = 0;
+  int up_form = 0;
   size_t prop_budget = size_t(16) << 30;  // bytes of propagation scratch per chunk
   // propagation scratch
   Buf F32[2], vec32, F64[2], vec64, Fbf[2];
@@ -124,8 +125,13 @@ void release(Buf& b) {
   b.bytes = 0;
 }
 
+void free_model_table(Model& m) {
+  if (m.dev_layers) (void)hipFree(m.dev_layers);
+  m.dev_layers = nullptr;
+}
+
 void free_layer(Layer& l) {
-  void* ps[] = {l.W, l.Wt, l.b, l.Wd, l.Wtd, l.bd, l.Wtbf};
+  void* ps[] = {l.W, l.Wt, l.b, l.Wd, l.Wtd, l.bd, l.Wtbf, l.Wbf};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   l = Layer{};
@@ -187,18 +193,22 @@ isx_status run_propagate(isx_ctx* ctx, const Model& m, isx_method method, isx_pr
   if (prec == ISX_BF16) {
     if (!bf16_supported(m))
       return fail(ctx, ISX_EUNSUPPORTED, "bf16 propagation needs every hidden layer's input width <= 256");
-    const size_t per_cell = 2 * prop_F_elems_bf16(m, 1) * 2 + prop_vec_elems(m, 1) * 4;
+    // the covariance form (UP) keeps each cell on chip: no coefficient blocks
+    const bool cov = method == ISX_UP && ctx->up_form == 0 && cov_supported(m);
+    const size_t per_cell = (cov ? 0 : 2 * prop_F_elems_bf16(m, 1) * 2) + prop_vec_elems(m, 1) * 4;
     int64_t chunk = chunk_req > 0 ? chunk_req : (int64_t)(ctx->prop_budget / per_cell);
     chunk = std::max<int64_t>(1, std::min<int64_t>(chunk, n));
     PropWork<float> w;
-    HIPCHK(ensure(ctx->Fbf[0], prop_F_elems_bf16(m, chunk) * 2));
-    HIPCHK(ensure(ctx->Fbf[1], prop_F_elems_bf16(m, chunk) * 2));
+    if (!cov) {
+      HIPCHK(ensure(ctx->Fbf[0], prop_F_elems_bf16(m, chunk) * 2));
+      HIPCHK(ensure(ctx->Fbf[1], prop_F_elems_bf16(m, chunk) * 2));
+    }
     HIPCHK(ensure(ctx->vec32, prop_vec_elems(m, chunk) * sizeof(float)));
     w.vec = (float*)ctx->vec32.p;
     uint16_t* Fbf[2] = {(uint16_t*)ctx->Fbf[0].p, (uint16_t*)ctx->Fbf[1].p};
     for (int64_t s = 0; s < n; s += chunk) {
       PropArgs a{&m, method, std::min(chunk, n - s), centres + 3 * s, halves + 3 * s, out + 2 * s, nullptr,
-                 ctx->kernel_choice, ctx->stream, &ctx->prof, ctx->bf16_variant};
+                 ctx->kernel_choice, ctx->stream, &ctx->prof, ctx->bf16_variant, ctx->up_form};
       HIPCHK(propagate_bf16(a, w, Fbf, 0));
     }
     return ISX_OK;
@@ -278,8 +288,10 @@ isx_status isx_destroy(isx_ctx* ctx) {
   if (!ctx) return ISX_EINVAL;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
-  for (Model& m : ctx->models)
+  for (Model& m : ctx->models) {
     for (int l = 0; l < ISX_MAX_LINEAR; ++l) free_layer(m.L[l]);
+    free_model_table(m);
+  }
   Buf* bufs[] = {&ctx->F32[0], &ctx->F32[1], &ctx->vec32, &ctx->F64[0], &ctx->F64[1], &ctx->vec64, &ctx->Fbf[0],
                  &ctx->Fbf[1],
                  &ctx->ids, &ctx->pmask, &ctx->centres, &ctx->halves, &ctx->out, &ctx->mask,
@@ -317,6 +329,10 @@ isx_status isx_set_option(isx_ctx* ctx, isx_option option, int64_t value) {
       return ISX_OK;
     case ISX_VERBOSE:
       ctx->verbose = value != 0;
+      return ISX_OK;
+    case ISX_UP_FORM:
+      if (value < 0 || value > 1) return fail(ctx, ISX_EINVAL, "ISX_UP_FORM must be 0 or 1");
+      ctx->up_form = (int)value;
       return ISX_OK;
     case ISX_BF16_VARIANT:
       if (value < 0 || value > 4) return fail(ctx, ISX_EINVAL, "ISX_BF16_VARIANT must be in [0, 4]");
@@ -382,7 +398,7 @@ isx_status isx_load_mlp(isx_ctx* ctx, int32_t n_linear, const int32_t* widths, c
     const int wi = widths[l], wo = widths[l + 1];
     std::vector<float> W((size_t)no * ni, 0.f), Wt((size_t)ni * no, 0.f), b((size_t)no, 0.f);
     std::vector<double> Wd((size_t)no * ni, 0.0), Wtd((size_t)ni * no, 0.0), bd((size_t)no, 0.0);
-    std::vector<uint16_t> Wtbf((size_t)ni * no, 0);
+    std::vector<uint16_t> Wtbf((size_t)ni * no, 0), Wbf((size_t)no * ni, 0);
     for (int o = 0; o < wo; ++o) {
       for (int i = 0; i < wi; ++i) {
         const float w = h_W[l][(size_t)o * wi + i];
@@ -391,6 +407,7 @@ isx_status isx_load_mlp(isx_ctx* ctx, int32_t n_linear, const int32_t* widths, c
         Wd[(size_t)o * ni + i] = w;
         Wtd[(size_t)i * no + o] = w;
         Wtbf[(size_t)i * no + o] = f32_to_bf16_bits(w);
+        Wbf[(size_t)o * ni + i] = f32_to_bf16_bits(w);
       }
       b[o] = h_b[l][o];
       bd[o] = h_b[l][o];
@@ -406,8 +423,20 @@ isx_status isx_load_mlp(isx_ctx* ctx, int32_t n_linear, const int32_t* widths, c
     if (e == hipSuccess) e = upload(&L.Wtd, Wtd);
     if (e == hipSuccess) e = upload(&L.bd, bd);
     if (e == hipSuccess) e = upload(&L.Wtbf, Wtbf);
+    if (e == hipSuccess) e = upload(&L.Wbf, Wbf);
     if (e != hipSuccess) {
       for (int k = 0; k <= l; ++k) free_layer(m.L[k]);
+      return hip_fail(ctx, e, "isx_load_mlp upload");
+    }
+  }
+  {
+    std::vector<DevLayer> table(n_linear);
+    for (int l = 0; l < n_linear; ++l)
+      table[l] = DevLayer{m.L[l].W, m.L[l].Wbf, m.L[l].b, m.L[l].n_in, m.L[l].n_out};
+    hipError_t e = upload(&m.dev_layers, table);
+    if (e != hipSuccess) {
+      for (int k = 0; k < n_linear; ++k) free_layer(m.L[k]);
+      free_model_table(m);
       return hip_fail(ctx, e, "isx_load_mlp upload");
     }
   }
@@ -429,6 +458,7 @@ isx_status isx_unload_mlp(isx_ctx* ctx, int32_t mlp_id) {
   if (!m) return fail(ctx, ISX_EINVAL, "no such mlp");
   (void)hipStreamSynchronize(ctx->stream);
   for (int l = 0; l < ISX_MAX_LINEAR; ++l) free_layer(m->L[l]);
+  free_model_table(*m);
   m->live = false;
   return ISX_OK;
 }

@@ -31,6 +31,17 @@ struct Layer {
   double* Wtd = nullptr;
   double* bd = nullptr;
   uint16_t* Wtbf = nullptr; // bfloat16 bits of W^T, [n_in][n_out]
+  uint16_t* Wbf = nullptr;  // bfloat16 bits of W, [n_out][n_in]
+};
+
+// Per-layer pointers in device memory, for kernels that walk the layers with a
+// runtime index (one scalar load per layer instead of whole pointer arrays in
+// kernel arguments).
+struct DevLayer {
+  const float* W;         // [n_out][n_in]
+  const uint16_t* Wbf;    // bfloat16 bits of W, [n_out][n_in]
+  const float* b;         // [n_out]
+  int n_in, n_out;        // padded widths
 };
 
 struct Model {
@@ -39,6 +50,7 @@ struct Model {
   int widths[ISX_MAX_LINEAR + 1] = {};  // as loaded
   int pw[ISX_MAX_LINEAR + 1] = {};      // padded (pw[0] = 3, pw[L] = 1)
   Layer L[ISX_MAX_LINEAR];
+  DevLayer* dev_layers = nullptr;  // device copy of the per-layer pointers
   float lo[3] = {-1.f, -1.f, -1.f}, hi[3] = {1.f, 1.f, 1.f};
   int n_iso = 0;
   float iso[ISX_MAX_ISO] = {};
@@ -178,6 +190,7 @@ struct PropArgs {
   hipStream_t stream;
   Profiler* prof;     // may be null
   int bf16_variant;   // 0 = default tile shape for the width
+  int up_form = 0;    // bf16 UP: 0 = covariance form when supported, 1 = coefficient form
 };
 size_t prop_F_elems(const Model& m, int64_t C);
 size_t prop_vec_elems(const Model& m, int64_t C);
@@ -185,6 +198,12 @@ hipError_t propagate_f32(const PropArgs& a, PropWork<float>& w);
 hipError_t propagate_f64(const PropArgs& a, PropWork<double>& w);
 hipError_t propagate_bf16(const PropArgs& a, PropWork<float>& w, uint16_t* Fbf[2], size_t Fbf_elems);
 bool bf16_supported(const Model& m);
+// covariance-form UP on BF16 MFMA (kernels_cov.hip)
+bool cov_supported(const Model& m);
+double cov_flops_per_cell(const Model& m);
+// vec: the Y, A, B, G vectors of hidden layers 1..L-1, each [C][padded width], in that order per layer
+hipError_t launch_up_cov_bf16(const Model& m, int64_t C, const float* centres, const float* halves, float* vec,
+                              hipStream_t s);
 size_t prop_F_elems_bf16(const Model& m, int64_t C);
 hipError_t eval_points_f32(const Model& m, int64_t n, const float* pts, float* vals, hipStream_t s);
 hipError_t eval_points_f64(const Model& m, int64_t n, const float* pts, float* vals, hipStream_t s);

@@ -1,0 +1,392 @@
+// Uncertainty propagation in covariance form on BF16 MFMA
+// (v_mfma_f32_32x32x16_bf16, float32 accumulation).
+//
+// The Gaussian rule of a hidden layer only needs each neuron's variance, the
+// diagonal of C_h = P_h P_h^T, where P_h is the layer's coefficient matrix
+// (Eq. 8).  Since P_h = W_h [D_{h-1} P_{h-1} | diag(gamma_{h-1})] (Eq. 9, the
+// rule scales the rows of the previous form and appends one new symbol per
+// neuron), the covariances follow exactly from
+//   C_1 = W_1 diag(h^2 / 3) W_1^T,
+//   C_h = W_h X_{h-1} W_h^T,  X_{h-1} = D_{h-1} C_{h-1} D_{h-1} + diag(gamma_{h-1}^2),
+// with D = diag(alpha): the same result as tracking the coefficients, without
+// the growing symbol blocks.  For hidden widths up to 256 a cell's X fits in
+// one CU's LDS as bfloat16, so one workgroup carries a cell through every
+// hidden layer without touching HBM between layers; the only global traffic
+// is the weights (L2-resident) and each layer's (y, alpha, beta, gamma)
+// vectors for the output read-off.  Affine arithmetic has no such form (its
+// statistic is a sum of magnitudes) and keeps the coefficient kernel.
+//
+// Per layer h (8 waves, 512 threads):
+//   2. T = W_h X_{h-1}: each wave computes a tile of RPW x CPW blocks of
+//      32 x 32, with A = bfloat16 fragments of its weight rows streamed from
+//      the L2-resident bf16 copy of W a few k-steps ahead, and B = rows of X
+//      from LDS (X is symmetric, so its rows serve as B columns).  A weight
+//      fragment serves CPW products and an LDS fragment RPW.
+//   3. T replaces X in LDS (row-major).
+//   4. Per neuron (a thread pair), in one pass over its float32 weight row:
+//      the centre y = W z + b with z = alpha . y_{h-1} + beta, the variance
+//      C_h[j][j] = sum_k T[j][k] W[j][k], and the ReLU rule, which gives
+//      (alpha, beta, gamma).
+//   5. C_h = T W_h^T on the wave's tile (A = rows of T from LDS, B = weight
+//      fragments, whose lane layout is the B layout of the transposed
+//      product).  The last hidden layer needs only step 4.
+//   6. X_h = D C_h D + diag(gamma^2) goes to LDS as bfloat16 for layer h+1
+//      (C_h is symmetric, so the tile's columns are written as rows).
+// MFMA 32x32x16 bf16 layout (lane l): A (row l%32, k 8(l/32)+e), B (k
+// 8(l/32)+e, column l%32), e = 0..7; accumulator register r holds (row
+// 8(r/4) + 4(l/32) + r%4, column l%32).
+#include "isx_internal.h"
+
+#include <algorithm>
+
+namespace isx {
+
+typedef __bf16 cbf16x8 __attribute__((ext_vector_type(8)));
+typedef __attribute__((address_space(1))) const cbf16x8 gbf16x8;  // in global memory
+typedef float cv16f __attribute__((ext_vector_type(16)));
+
+constexpr int kCovThreads = 512;  // 8 waves
+constexpr int kCovNMax = 256;     // largest padded hidden width
+
+template <int N>
+struct CovShape {
+  static constexpr int STR = N + 8;  // LDS row stride in bfloat16 (16-byte shifted rows)
+  static constexpr int KS = N / 16;  // k-steps of one product
+  static constexpr int NB = N / 32;  // 32-row (and 32-column) blocks
+  // Each wave computes RPW x CPW blocks of 32 x 32: RPW blocks whose operand
+  // is weight rows (global memory) and CPW blocks whose operand comes from
+  // LDS; a weight fragment serves CPW products and an LDS fragment RPW.
+  static constexpr int RPW = NB >= 5 ? 2 : 1;
+  static constexpr int CPW = NB <= 2 ? 1 : (NB <= 4 ? 2 : (NB <= 6 ? 3 : 4));
+  static constexpr int RG = (NB + RPW - 1) / RPW;  // wave groups along the weight rows
+  static constexpr int CG = (NB + CPW - 1) / CPW;  // wave groups along the LDS operand
+  static constexpr int PF = 4;                     // weight fragments loaded this many k-steps ahead
+  static constexpr size_t LDS = (size_t)N * STR * 2 + 8 * N * sizeof(float);
+  static_assert(RG * CG <= 8, "more tiles than waves");
+};
+
+// acc[r][c] += W[wrow[r] rows] * L[lrow[c] rows]^T over all N k values, as
+// MFMA products D[i][j] = sum_k A[i][k] B[k][j]: with WA the weight rows are
+// the A operand (rows of D) and the LDS rows the B operand (columns of D);
+// otherwise the roles swap.  wfrag[r] points at this lane's 8-element chunk
+// of weight row wrow[r] (k = 8 hi), lfrag[c] at its chunk of LDS row lrow[c].
+template <int N, bool WA>
+__device__ __forceinline__ void cov_tile_gemm(gbf16x8* const (&wfrag)[CovShape<N>::RPW],
+                                              const __bf16* const (&lfrag)[CovShape<N>::CPW], bool tile_ok,
+                                              cv16f (&acc)[CovShape<N>::RPW][CovShape<N>::CPW]) {
+  using S = CovShape<N>;
+  constexpr int KS = S::KS, RPW = S::RPW, CPW = S::CPW, PF = S::PF < S::KS ? S::PF : S::KS;
+  // fragments are loaded unconditionally (invalid blocks point at block 0)
+  cbf16x8 wf[KS][RPW];
+#pragma unroll
+  for (int ks = 0; ks < PF; ++ks)
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) wf[ks][r] = wfrag[r][2 * ks];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    if (ks + PF < KS) {
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) wf[ks + PF][r] = wfrag[r][2 * (ks + PF)];
+    }
+    cbf16x8 lf[CPW];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) lf[c] = *reinterpret_cast<const cbf16x8*>(lfrag[c] + 16 * ks);
+    if (tile_ok) {
+#pragma unroll
+      for (int r = 0; r < RPW; ++r)
+#pragma unroll
+        for (int c = 0; c < CPW; ++c)
+          acc[r][c] = WA ? __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[ks][r], lf[c], acc[r][c], 0, 0, 0)
+                         : __builtin_amdgcn_mfma_f32_32x32x16_bf16(lf[c], wf[ks][r], acc[r][c], 0, 0, 0);
+    }
+  }
+}
+
+// Y, A, B, G of one hidden layer (n neurons) inside the vector buffer, which
+// holds them for layers 1..L-1 in order, each [C][n]
+__device__ __forceinline__ void cov_store_vec(float* v, int64_t C, int n, int64_t cell, int j, float y, float a,
+                                              float b, float g) {
+  const int64_t NC = (int64_t)n * C;
+  const int64_t o = cell * n + j;
+  v[o] = y;
+  v[NC + o] = a;
+  v[2 * NC + o] = b;
+  v[3 * NC + o] = g;
+}
+
+// Gaussian least-squares ReLU rule (App. D ReLU row, erfc form, clamped).
+__device__ __forceinline__ void cov_relu_rule(float y, float var, float& a, float& b, float& g) {
+  const float sigma = sqrtf(fmaxf(var, 0.f));
+  const float ay = fabsf(y);
+  if (!(sigma > 1e-30f * (ay > 1.f ? ay : 1.f))) {
+    a = y > 0.f ? 1.f : (y < 0.f ? 0.f : 0.5f);
+    b = 0.f;
+    g = 0.f;
+    return;
+  }
+  const float r = y / sigma;
+  const float Phi = 0.5f * erfcf(-r * 0.70710678118654752440f);
+  const float Q = 0.5f * erfcf(r * 0.70710678118654752440f);
+  const float phi = 0.39894228040143267794f * expf(-0.5f * r * r);
+  a = Phi;
+  b = sigma * phi;
+  const float g2 = sigma * sigma * ((r * r + 1.f) * Phi * Q + r * phi * (Q - Phi) - phi * phi);
+  g = g2 > 0.f ? sqrtf(g2) : 0.f;
+}
+
+// All hidden layers have padded width N (the input layer is 3 wide).
+template <int N>
+__global__ __launch_bounds__(kCovThreads) void up_cov_bf16_kernel(int64_t C, int n_linear,
+                                                                  const DevLayer* __restrict__ layers,
+                                                                  float* __restrict__ vec,
+                                                                  const float* __restrict__ centres,
+                                                                  const float* __restrict__ halves) {
+  using S = CovShape<N>;
+  constexpr int STR = S::STR, KS = S::KS, NB = S::NB;
+  extern __shared__ float4 cov_smem4[];
+  __bf16* X = reinterpret_cast<__bf16*>(cov_smem4);  // [N][STR]: X, then T
+  float* s_alpha = reinterpret_cast<float*>(X + (size_t)N * STR);
+  float* s_zbuf = s_alpha + N;  // two buffers of z = alpha . y + beta (previous layer, this layer)
+  float* s_gamma = s_zbuf + 2 * N;
+  float* s_var = s_gamma + N;
+  float* s_F = s_var + N;       // layer 1: F = W_1 diag(h / sqrt 3), [N][3]
+
+  const int64_t cell = blockIdx.x;
+  if (cell >= C) return;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int l32 = lane & 31, hi = lane >> 5;
+  constexpr int RPW = S::RPW, CPW = S::CPW, RG = S::RG, CG = S::CG;
+  // this wave's tile: weight-row blocks rg*RPW.., LDS-row blocks cg*CPW..
+  const int rg = wave % RG, cg = wave / RG;
+  const bool tile = cg < CG;
+  const int Lh = n_linear - 1;
+  float* vh = vec;  // this hidden layer's Y, A, B, G
+
+  // ---- layer 1: centre, variances, rule, X_1
+  {
+    const DevLayer L1 = layers[0];
+    const float* W1 = L1.W;
+    const float sc = 0.57735026918962576451f;
+    const float hx = halves[cell * 3 + 0] * sc, hy = halves[cell * 3 + 1] * sc, hz = halves[cell * 3 + 2] * sc;
+    float* s_z = s_zbuf + N;  // read by layer 2
+    for (int j = t; j < N; j += kCovThreads) {
+      const float w0 = W1[j * 3 + 0], w1 = W1[j * 3 + 1], w2 = W1[j * 3 + 2];
+      const float y = L1.b[j] + w0 * centres[cell * 3 + 0] + w1 * centres[cell * 3 + 1] + w2 * centres[cell * 3 + 2];
+      const float f0 = w0 * hx, f1 = w1 * hy, f2 = w2 * hz;
+      float a, b, g;
+      cov_relu_rule(y, f0 * f0 + f1 * f1 + f2 * f2, a, b, g);
+      s_alpha[j] = a;
+      s_z[j] = a * y + b;
+      s_gamma[j] = g;
+      s_F[3 * j + 0] = f0;
+      s_F[3 * j + 1] = f1;
+      s_F[3 * j + 2] = f2;
+      cov_store_vec(vh, C, N, cell, j, y, a, b, g);
+    }
+    __syncthreads();
+    if (Lh >= 2) {
+      // X_1[i][j] = alpha_i alpha_j F_i . F_j + delta_ij gamma_j^2, eight
+      // consecutive j per thread and store
+      for (int e = t; e < N * N / 8; e += kCovThreads) {
+        const int i = e / (N / 8), j0 = 8 * (e - i * (N / 8));
+        const float ai = s_alpha[i], fi0 = s_F[3 * i], fi1 = s_F[3 * i + 1], fi2 = s_F[3 * i + 2];
+        cbf16x8 v8;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int j = j0 + u;
+          float v = ai * s_alpha[j] * (fi0 * s_F[3 * j] + fi1 * s_F[3 * j + 1] + fi2 * s_F[3 * j + 2]);
+          if (i == j) v += s_gamma[j] * s_gamma[j];
+          v8[u] = (__bf16)v;
+        }
+        *reinterpret_cast<cbf16x8*>(X + (size_t)i * STR + j0) = v8;
+      }
+    }
+    __syncthreads();
+    vh += 4 * (int64_t)N * C;
+  }
+
+  for (int h = 2; h <= Lh; ++h) {
+    const DevLayer Lw = layers[h - 1];
+    const bool last = h == Lh;
+    const __bf16* Wb = reinterpret_cast<const __bf16*>(Lw.Wbf);
+    gbf16x8* wfrag[RPW];
+    bool wok[RPW];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      const int blk = rg * RPW + r;
+      wok[r] = tile && blk < NB;
+      wfrag[r] = (gbf16x8*)(Wb + (int64_t)((wok[r] ? blk : 0) * 32 + l32) * N + 8 * hi);
+    }
+    const __bf16* lfrag[CPW];
+    bool lok[CPW];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const int blk = cg * CPW + c;
+      lok[c] = tile && blk < NB;
+      lfrag[c] = X + (size_t)((lok[c] ? blk : 0) * 32 + l32) * STR + 8 * hi;
+    }
+
+    const float* s_zin = s_zbuf + (h - 1 & 1) * N;  // z of layer h-1
+    float* s_zout = s_zbuf + (h & 1) * N;           // z of layer h
+    // 2. T = W X on the wave's tile (rows: weight blocks, columns: X blocks,
+    //    X symmetric); 3. T -> LDS row-major once every wave has read X
+    {
+      cv16f acc[RPW][CPW];
+#pragma unroll
+      for (int r = 0; r < RPW; ++r)
+#pragma unroll
+        for (int c = 0; c < CPW; ++c)
+#pragma unroll
+          for (int e = 0; e < 16; ++e) acc[r][c][e] = 0.f;
+      cov_tile_gemm<N, true>(wfrag, lfrag, tile, acc);
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < RPW; ++r)
+#pragma unroll
+        for (int c = 0; c < CPW; ++c)
+          if (wok[r] && lok[c]) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+              const int row = (rg * RPW + r) * 32 + 8 * (e >> 2) + 4 * hi + (e & 3);
+              X[(size_t)row * STR + (cg * CPW + c) * 32 + l32] = (__bf16)acc[r][c][e];
+            }
+          }
+    }
+    __syncthreads();
+
+    // 4. per neuron j (a thread pair): the float32 centre y_j = W[j] z + b_j,
+    //    the variance C_h[j][j] = sum_k T[j][k] W[j][k], and the ReLU rule
+    for (int j = t >> 1; j < N; j += kCovThreads / 2) {
+      const int part = t & 1;
+      const float* wrow = Lw.W + (int64_t)j * N;
+      const __bf16* trow = X + (size_t)j * STR;
+      float v = 0.f, yc = 0.f;
+#pragma unroll 2
+      for (int k = 8 * part; k < N; k += 16) {
+        const cbf16x8 tv = *reinterpret_cast<const cbf16x8*>(trow + k);
+        const float4 w0 = *reinterpret_cast<const float4*>(wrow + k);
+        const float4 w1 = *reinterpret_cast<const float4*>(wrow + k + 4);
+        const float4 z0 = *reinterpret_cast<const float4*>(s_zin + k);
+        const float4 z1 = *reinterpret_cast<const float4*>(s_zin + k + 4);
+        v += w0.x * (float)tv[0] + w0.y * (float)tv[1] + w0.z * (float)tv[2] + w0.w * (float)tv[3] +
+             w1.x * (float)tv[4] + w1.y * (float)tv[5] + w1.z * (float)tv[6] + w1.w * (float)tv[7];
+        yc += w0.x * z0.x + w0.y * z0.y + w0.z * z0.z + w0.w * z0.w + w1.x * z1.x + w1.y * z1.y + w1.z * z1.z +
+              w1.w * z1.w;
+      }
+      v += __shfl_xor(v, 1);
+      yc += __shfl_xor(yc, 1);
+      if (part == 0) {
+        float a, b, g;
+        const float y = yc + Lw.b[j];
+        cov_relu_rule(y, v, a, b, g);
+        s_var[j] = v;
+        s_alpha[j] = a;
+        s_zout[j] = a * y + b;
+        s_gamma[j] = g;
+        cov_store_vec(vh, C, N, cell, j, y, a, b, g);
+      }
+    }
+    if (last) break;
+    vh += 4 * (int64_t)N * C;
+    // 5. C_h on the wave's tile, C[i][j] = sum_k T[i][k] W[j][k] (rows i:
+    //    T blocks from LDS, columns j: weight blocks)
+    cv16f cacc[RPW][CPW];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r)
+#pragma unroll
+      for (int c = 0; c < CPW; ++c)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) cacc[r][c][e] = 0.f;
+    cov_tile_gemm<N, false>(wfrag, lfrag, tile, cacc);
+    __syncthreads();  // every wave has read T; the new slopes are in LDS
+    // 6. X_h = D C D + diag(gamma^2); C is symmetric, so the tile's columns j
+    //    are written as rows of X.  The lane that wrote a diagonal entry
+    //    rewrites it from the variance the rule used.
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      if (!wok[r]) continue;
+      const int j = (rg * RPW + r) * 32 + l32;
+      const float aj = s_alpha[j];
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        if (!lok[c]) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i0 = (cg * CPW + c) * 32 + 8 * q + 4 * hi;
+          // keep the slope loads next to their use (hoisting them all would
+          // cost registers)
+          __asm__ volatile("" ::: "memory");
+          const float4 ai = *reinterpret_cast<const float4*>(s_alpha + i0);
+          __bf16 v4[4];
+          v4[0] = (__bf16)(ai.x * aj * cacc[r][c][4 * q + 0]);
+          v4[1] = (__bf16)(ai.y * aj * cacc[r][c][4 * q + 1]);
+          v4[2] = (__bf16)(ai.z * aj * cacc[r][c][4 * q + 2]);
+          v4[3] = (__bf16)(ai.w * aj * cacc[r][c][4 * q + 3]);
+          *reinterpret_cast<uint2*>(X + (size_t)j * STR + i0) = *reinterpret_cast<const uint2*>(v4);
+        }
+        if (cg * CPW + c == rg * RPW + r && ((l32 >> 2) & 1) == hi)
+          X[(size_t)j * STR + j] = (__bf16)(aj * aj * s_var[j] + s_gamma[j] * s_gamma[j]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Padded width shared by every hidden layer, or 0 if they differ or exceed
+// the LDS tile.
+static int cov_width(const Model& m) {
+  if (m.n_linear < 2) return 0;
+  const int n = m.pw[1];
+  for (int h = 1; h < m.n_linear; ++h)
+    if (m.pw[h] != n) return 0;
+  return (n % 32 == 0 && n <= kCovNMax) ? n : 0;
+}
+
+bool cov_supported(const Model& m) { return cov_width(m) != 0; }
+
+template <int N>
+static hipError_t launch_cov_n(const Model& m, int64_t C, const float* centres, const float* halves, float* vec,
+                               hipStream_t s) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&up_cov_bf16_kernel<N>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)CovShape<N>::LDS);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((up_cov_bf16_kernel<N>), dim3((unsigned)C), dim3(kCovThreads), CovShape<N>::LDS, s, C,
+                     m.n_linear, m.dev_layers, vec, centres, halves);
+  return hipGetLastError();
+}
+
+hipError_t launch_up_cov_bf16(const Model& m, int64_t C, const float* centres, const float* halves, float* vec,
+                              hipStream_t s) {
+  if (C <= 0) return hipSuccess;
+  switch (cov_width(m)) {
+    case 32: return launch_cov_n<32>(m, C, centres, halves, vec, s);
+    case 64: return launch_cov_n<64>(m, C, centres, halves, vec, s);
+    case 96: return launch_cov_n<96>(m, C, centres, halves, vec, s);
+    case 128: return launch_cov_n<128>(m, C, centres, halves, vec, s);
+    case 160: return launch_cov_n<160>(m, C, centres, halves, vec, s);
+    case 192: return launch_cov_n<192>(m, C, centres, halves, vec, s);
+    case 224: return launch_cov_n<224>(m, C, centres, halves, vec, s);
+    case 256: return launch_cov_n<256>(m, C, centres, halves, vec, s);
+    default: return hipErrorNotSupported;
+  }
+}
+
+// Algorithmic flops per cell of the covariance form (true widths): per hidden
+// layer h >= 2, T = W X (2 n_h n_{h-1}^2) and C = T W^T (2 n_h^2 n_{h-1}; the
+// last hidden layer only its diagonal 32x32 blocks).
+double cov_flops_per_cell(const Model& m) {
+  double f = 0.0;
+  const int Lh = m.n_linear - 1;
+  for (int h = 2; h <= Lh; ++h) {
+    const double a = m.widths[h], b = m.widths[h - 1];
+    f += 2.0 * a * b * b;
+    f += h < Lh ? 2.0 * a * a * b : 2.0 * a * 32.0 * b;
+  }
+  return f;
+}
+
+}  // namespace isx

@@ -338,7 +338,9 @@ BF16_WIDTHS = [
     [3, 64, 64, 64, 1],
     [3, 128, 128, 128, 128, 1],
     [3, 256, 256, 256, 256, 256, 1],
-    [3, 96, 160, 1],  # widths that are multiples of 32 but not of 64/128
+    [3, 96, 160, 1],  # widths that are multiples of 32 but not of 64/128 (coefficient form only)
+    [3, 96, 96, 96, 1],
+    [3, 40, 40, 40, 1],  # padded to 64
 ]
 
 
@@ -357,11 +359,17 @@ def test_propagate_bf16_error_against_oracle(ctx, widths, mname):
         ref = propagate(mlp, c, h, method)
         S = output_scale(mlp)
         k = 3.0 if mname == "up" else 1.0
-        g, _ = _gpu_prop(ctx, mid, gm, isx.BF16, c, h)
-        worst, _ = assert_pair_close(g, ref, S, 5e-2, f"bf16 {mname} {widths}", k=k, spread_rtol=0.2)
-        # the centre is a float32 point evaluation of the linearised net
-        assert worst["centre"] <= 1e-2
+        # UP: the covariance form (default where the widths allow) and the
+        # coefficient form; AA: the coefficient form
+        for form in ((0, 1) if mname == "up" else (0,)):
+            ctx.set_option(isx.UP_FORM, form)
+            g, _ = _gpu_prop(ctx, mid, gm, isx.BF16, c, h)
+            worst, _ = assert_pair_close(g, ref, S, 5e-2, f"bf16 {mname} form {form} {widths}", k=k,
+                                         spread_rtol=0.2)
+            # the centre is a float32 point evaluation of the linearised net
+            assert worst["centre"] <= 1e-2
     finally:
+        ctx.set_option(isx.UP_FORM, 0)
         ctx.unload_mlp(mid)
 
 
