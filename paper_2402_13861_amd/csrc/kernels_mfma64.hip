@@ -138,32 +138,75 @@ __global__ __launch_bounds__(512) void hidden_mfma_f64_kernel(
 #pragma unroll
         for (int i = 0; i < 4; ++i) acc[rs][cs][i] = 0.0;
 
+    // K chunks: the next chunk's operands are loaded into registers while
+    // the current one is multiplied, then stored to LDS
+    constexpr int TA = K::KT * BM / 2, TB = K::KT * K::BN / 2;  // double2 per chunk
+    constexpr int NA = (TA + K::THREADS - 1) / K::THREADS;      // per thread
+    constexpr int NBL = (TB + K::THREADS - 1) / K::THREADS;
+    static_assert(NA <= 2 && NBL <= 4, "prefetch registers");
+    // named registers (not arrays) keep the prefetch out of memory
+    double2 ra0 = make_double2(0.0, 0.0), ra1 = ra0, rb0 = ra0, rb1 = ra0, rb2 = ra0, rb3 = ra0;
+// loads are unconditional (indices clamped to valid addresses, values
+// masked afterwards), so they stay in flight while the products run
+#define ISX_F64_LOAD_A(U, DST, K0)                                                                   \
+  {                                                                                                  \
+    const int idx = min(t + (U) * K::THREADS, TA - 1);                                               \
+    const int kk = idx / (BM / 2), mp = idx - kk * (BM / 2);                                         \
+    DST = *reinterpret_cast<const double2*>(Wt + (int64_t)((K0) + kk) * n_out + m0 + 2 * mp);        \
+  }
+#define ISX_F64_LOAD_B(U, DST, K0)                                                                   \
+  {                                                                                                  \
+    const int idx = min(t + (U) * K::THREADS, TB - 1);                                               \
+    const int col = idx / (K::KT / 2), kp = idx - col * (K::KT / 2);                                 \
+    const int64_t gc = c0 + col;                                                                     \
+    const int64_t gcc = gc < cols_in ? gc : cols_in - 1;                                             \
+    const double2 v = *reinterpret_cast<const double2*>(fin + gcc * n_in + (K0) + 2 * kp);           \
+    DST = gc < cols_in ? v : make_double2(0.0, 0.0);                                                 \
+  }
+#define ISX_F64_LOAD_CHUNK(K0)                                  \
+  {                                                             \
+    ISX_F64_LOAD_A(0, ra0, K0);                                 \
+    if constexpr (NA > 1) ISX_F64_LOAD_A(1, ra1, K0);           \
+    ISX_F64_LOAD_B(0, rb0, K0);                                 \
+    if constexpr (NBL > 1) ISX_F64_LOAD_B(1, rb1, K0);          \
+    if constexpr (NBL > 2) ISX_F64_LOAD_B(2, rb2, K0);          \
+    if constexpr (NBL > 3) ISX_F64_LOAD_B(3, rb3, K0);          \
+  }
+#define ISX_F64_STORE_A(U, SRC)                                                     \
+  {                                                                                 \
+    const int idx = t + (U) * K::THREADS;                                           \
+    const int kk = idx / (BM / 2), mp = idx - kk * (BM / 2);                        \
+    if (idx < TA) *reinterpret_cast<double2*>(As + kk * K::ASTR + 2 * mp) = SRC;    \
+  }
+#define ISX_F64_STORE_B(U, SRC)                                                     \
+  {                                                                                 \
+    const int idx = t + (U) * K::THREADS;                                           \
+    const int col = idx / (K::KT / 2), kp = idx - col * (K::KT / 2);                \
+    if (idx < TB) {                                                                 \
+      const int k = k0 + 2 * kp;                                                    \
+      double2 v = SRC;                                                              \
+      v.x *= s_alpha[k];                                                            \
+      v.y *= s_alpha[k + 1];                                                        \
+      if (c0 + col == 0) {                                                          \
+        v.x += s_beta[k];                                                           \
+        v.y += s_beta[k + 1];                                                       \
+      }                                                                             \
+      Bs[(2 * kp + 0) * K::BSTR + col] = v.x;                                       \
+      Bs[(2 * kp + 1) * K::BSTR + col] = v.y;                                       \
+    }                                                                               \
+  }
+    ISX_F64_LOAD_CHUNK(0);
     for (int k0 = 0; k0 < n_in; k0 += K::KT) {
-      // stage A = W^T[k0:k0+KT, m0:m0+BM]
-      for (int idx = t; idx < K::KT * BM / 2; idx += K::THREADS) {
-        const int kk = idx / (BM / 2), mp = idx - kk * (BM / 2);
-        const double2 v = *reinterpret_cast<const double2*>(Wt + (int64_t)(k0 + kk) * n_out + m0 + 2 * mp);
-        *reinterpret_cast<double2*>(As + kk * K::ASTR + 2 * mp) = v;
-      }
-      // stage B = alpha . F[k0:k0+KT, c0:c0+BN] (+ beta on the centre column)
-      for (int idx = t; idx < K::KT * K::BN / 2; idx += K::THREADS) {
-        const int col = idx / (K::KT / 2), kp = idx - col * (K::KT / 2);
-        const int64_t gc = c0 + col;
-        const int k = k0 + 2 * kp;
-        double2 v = make_double2(0.0, 0.0);
-        if (gc < cols_in) {
-          v = *reinterpret_cast<const double2*>(fin + gc * n_in + k);
-          v.x *= s_alpha[k];
-          v.y *= s_alpha[k + 1];
-          if (gc == 0) {
-            v.x += s_beta[k];
-            v.y += s_beta[k + 1];
-          }
-        }
-        Bs[(2 * kp + 0) * K::BSTR + col] = v.x;
-        Bs[(2 * kp + 1) * K::BSTR + col] = v.y;
-      }
+      __syncthreads();  // the previous chunk's products are done with LDS
+      ISX_F64_STORE_A(0, ra0);
+      if constexpr (NA > 1) ISX_F64_STORE_A(1, ra1);
+      // B = alpha . F (+ beta on the centre column)
+      ISX_F64_STORE_B(0, rb0);
+      if constexpr (NBL > 1) ISX_F64_STORE_B(1, rb1);
+      if constexpr (NBL > 2) ISX_F64_STORE_B(2, rb2);
+      if constexpr (NBL > 3) ISX_F64_STORE_B(3, rb3);
       __syncthreads();
+      if (k0 + K::KT < n_in) ISX_F64_LOAD_CHUNK(k0 + K::KT);
       if (wave_active) {
 #pragma unroll
         for (int ks = 0; ks < K::KT / 4; ++ks) {
@@ -180,8 +223,13 @@ __global__ __launch_bounds__(512) void hidden_mfma_f64_kernel(
           }
         }
       }
-      __syncthreads();
     }
+#undef ISX_F64_LOAD_CHUNK
+#undef ISX_F64_LOAD_A
+#undef ISX_F64_LOAD_B
+#undef ISX_F64_STORE_A
+#undef ISX_F64_STORE_B
+    __syncthreads();
     if (wave_active) {
 #pragma unroll
       for (int cs = 0; cs < 2 * K::NB; ++cs) {
