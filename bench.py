@@ -119,6 +119,8 @@ def main(argv=None):
                     help="1: the surrogate predicts corrections to the INR's centre linearisation; "
                          "0: standardised (mean, log sigma) targets")
     ap.add_argument("--sur-pairs", type=int, default=5_000_000)
+    ap.add_argument("--sur-holdout", type=int, default=1_000_000,
+                    help="held-out (cell, propagated) pairs for the error and band calibration")
     ap.add_argument("--sur-steps", type=int, default=2000)
     ap.add_argument("--depth", type=int, default=None)
     ap.add_argument("--cpu-baseline-seconds", type=float, default=15.0)
@@ -181,11 +183,13 @@ def main(argv=None):
     if use_sur:
         t0 = time.perf_counter()
         info = train_surrogate(ctx, mid, depth, mu_bar, S, visited=visited, n_pairs=a.sur_pairs, steps=a.sur_steps,
+                               holdout=a.sur_holdout,
                                isos=isos, k=w["k"], accept_leaves=bool(a.accept_leaves), base=bool(a.sur_base),
                                log=log)
         sur_info = dict(train_total_s=round(time.perf_counter() - t0, 2), train_kernel_s=round(info.train_seconds, 3),
                         pairs=info.n_pairs, steps=info.steps, final_loss=info.final_loss, z=info.z,
-                        z_accept=info.z_accept, holdout_miss=info.holdout_miss,
+                        z_accept=info.z_accept, z_levels=info.z_levels, z_accept_levels=info.z_accept_levels,
+                        holdout_miss=info.holdout_miss,
                         holdout_false_accept=info.holdout_false_accept,
                         accept_leaves=bool(a.accept_leaves), base=bool(a.sur_base),
                         err_mu=[round(x, 5) for x in info.err_mu], err_logsig=[round(x, 4) for x in info.err_logsig])

@@ -235,8 +235,10 @@ isx_status isx_mesh_free(isx_mesh* mesh);
  * isx_surrogate_attach: use surrogate sur_id in isx_extract of mlp_id (when
  *   params.use_surrogate).  h_err_mu[L], h_err_logsig[L] (L < n_levels) are
  *   the standard deviations of the surrogate's error at octree level L (field
- *   units, or units of s_b with a base; and log-sigma units).  A cell is decided without propagation when
- *   for every iso-value c it still carries either
+ *   units, or units of s_b with a base; and log-sigma units), h_z[L] and
+ *   h_z_accept[L] the level's prune and accept bands in those units (levels
+ *   beyond n_levels use the last entry).  A cell at level L is decided
+ *   without propagation when for every iso-value c it still carries either
  *     |mu_hat - c| - z err_mu > t sigma_hat exp(+z err_logsig)  (outside), or
  *     |mu_hat - c| + z_accept err_mu < t sigma_hat exp(-z_accept err_logsig)
  *                                                              (inside);
@@ -264,8 +266,8 @@ isx_status isx_surrogate_grad(isx_ctx* ctx, int32_t sur_id, int64_t n, const flo
 isx_status isx_surrogate_predict(isx_ctx* ctx, int32_t sur_id, int64_t n, const float* d_centres,
                                  const float* d_halves, float* d_out);
 isx_status isx_surrogate_attach(isx_ctx* ctx, int32_t mlp_id, int32_t sur_id, int32_t n_levels,
-                                const float* h_err_mu, const float* h_err_logsig, float z, float z_accept,
-                                int32_t accept_leaves);
+                                const float* h_err_mu, const float* h_err_logsig, const float* h_z,
+                                const float* h_z_accept, int32_t accept_leaves);
 isx_status isx_surrogate_free(isx_ctx* ctx, int32_t sur_id);
 
 /* Copy the library's marching-cubes case table: h_count[256] triangles per

@@ -242,15 +242,25 @@ class Context:
         self._chk(self._L.isx_surrogate_predict(self._h, sid, centres.shape[0], _ptr(centres), _ptr(halves),
                                                 _ptr(out)))
 
-    def surrogate_attach(self, mlp_id: int, sid: int, err_mu, err_logsig, z: float = 2.0,
-                         accept_leaves: bool = False, z_accept: Optional[float] = None):
-        """z: band for pruning; z_accept: band for accepting (default z)."""
+    def surrogate_attach(self, mlp_id: int, sid: int, err_mu, err_logsig, z=2.0, accept_leaves: bool = False,
+                         z_accept=None):
+        """z: band for pruning; z_accept: band for accepting (default z);
+        each a scalar or one value per level."""
         err_mu = [float(x) for x in err_mu]
         err_ls = [float(x) for x in err_logsig]
         n = len(err_mu)
-        za = float(z if z_accept is None else z_accept)
+
+        def per_level(v):
+            v = [float(v)] * n if np.isscalar(v) else [float(x) for x in v]
+            if len(v) != n:
+                raise ValueError("band arrays need one value per level")
+            return v
+
+        zp = per_level(z)
+        za = per_level(z if z_accept is None else z_accept)
         self._chk(self._L.isx_surrogate_attach(self._h, mlp_id, sid, n, (C.c_float * n)(*err_mu),
-                                               (C.c_float * n)(*err_ls), float(z), za, int(bool(accept_leaves))))
+                                               (C.c_float * n)(*err_ls), (C.c_float * n)(*zp),
+                                               (C.c_float * n)(*za), int(bool(accept_leaves))))
 
     def surrogate_free(self, sid: int):
         self._chk(self._L.isx_surrogate_free(self._h, sid))

@@ -728,7 +728,7 @@ isx_status isx_extract(isx_ctx* ctx, int32_t mlp_id, const isx_params* p, isx_me
       st = sur_predict_n(ctx, *S, n, centres, halves, (float*)ctx->sp_pred.p, unit);
       if (st != ISX_OK) return bail(st);
       const int Ls = std::min(L, std::max(0, m.sur_levels - 1));
-      XCHK(sur_partition(n, (const float*)ctx->sp_pred.p, unit, k, iso, pmask, m.sur_err_mu[Ls], m.sur_err_ls[Ls], m.sur_z, m.sur_z_acc,
+      XCHK(sur_partition(n, (const float*)ctx->sp_pred.p, unit, k, iso, pmask, m.sur_err_mu[Ls], m.sur_err_ls[Ls], m.sur_z[Ls], m.sur_z_acc[Ls],
                          L == p->max_depth ? 1 : 0, m.sur_accept_leaves, mask, (uint32_t*)ctx->sp_fb.p, s));
       XCHK(hipMemcpyAsync(outb, ctx->sp_pred.p, n * 8, hipMemcpyDeviceToDevice, s));
       XCHK(launch_compact(n, (const uint32_t*)ctx->sp_fb.p, nullptr, (uint32_t*)ctx->sp_idx.p, nullptr,
@@ -1135,8 +1135,8 @@ isx_status isx_surrogate_set_base(isx_ctx* ctx, int32_t sur_id, int32_t mlp_id, 
 }
 
 isx_status isx_surrogate_attach(isx_ctx* ctx, int32_t mlp_id, int32_t sur_id, int32_t n_levels,
-                                const float* h_err_mu, const float* h_err_logsig, float z, float z_accept,
-                                int32_t accept_leaves) {
+                                const float* h_err_mu, const float* h_err_logsig, const float* h_z,
+                                const float* h_z_accept, int32_t accept_leaves) {
   Model* m = get_model(ctx, mlp_id);
   if (!m) return fail(ctx, ISX_EINVAL, "bad mlp id");
   if (sur_id == -1) {
@@ -1144,18 +1144,21 @@ isx_status isx_surrogate_attach(isx_ctx* ctx, int32_t mlp_id, int32_t sur_id, in
     return ISX_OK;
   }
   if (!get_sur(ctx, sur_id)) return fail(ctx, ISX_EINVAL, "no such surrogate");
-  if (n_levels < 1 || n_levels > 16 || !h_err_mu || !h_err_logsig || !(z >= 0.f) || !(z_accept >= 0.f))
+  if (n_levels < 1 || n_levels > 16 || !h_err_mu || !h_err_logsig || !h_z || !h_z_accept)
     return fail(ctx, ISX_EINVAL, "bad surrogate band");
   for (int i = 0; i < n_levels; ++i)
-    if (!(h_err_mu[i] >= 0.f) || !(h_err_logsig[i] >= 0.f)) return fail(ctx, ISX_EINVAL, "bad error scales");
+    if (!(h_err_mu[i] >= 0.f) || !(h_err_logsig[i] >= 0.f) || !(h_z[i] >= 0.f) || !(h_z_accept[i] >= 0.f) ||
+        !std::isfinite(h_err_mu[i]) || !std::isfinite(h_err_logsig[i]) || !std::isfinite(h_z[i]) ||
+        !std::isfinite(h_z_accept[i]))
+      return fail(ctx, ISX_EINVAL, "bad error scales or bands");
   m->sur_id = sur_id;
   m->sur_levels = n_levels;
   for (int i = 0; i < 16; ++i) {
     m->sur_err_mu[i] = i < n_levels ? h_err_mu[i] : h_err_mu[n_levels - 1];
     m->sur_err_ls[i] = i < n_levels ? h_err_logsig[i] : h_err_logsig[n_levels - 1];
+    m->sur_z[i] = i < n_levels ? h_z[i] : h_z[n_levels - 1];
+    m->sur_z_acc[i] = i < n_levels ? h_z_accept[i] : h_z_accept[n_levels - 1];
   }
-  m->sur_z = z;
-  m->sur_z_acc = z_accept;
   m->sur_accept_leaves = accept_leaves ? 1 : 0;
   return ISX_OK;
 }

@@ -58,7 +58,7 @@ struct Model {
   int sur_id = -1;
   int sur_levels = 0;
   float sur_err_mu[16] = {}, sur_err_ls[16] = {};
-  float sur_z = 2.f, sur_z_acc = 2.f;
+  float sur_z[16] = {}, sur_z_acc[16] = {};  // per-level prune / accept bands
   int sur_accept_leaves = 0;
   int hidden() const { return n_linear - 1; }
   // columns of hidden layer h's coefficient block (h = 1..hidden())

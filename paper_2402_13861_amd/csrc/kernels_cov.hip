@@ -91,6 +91,9 @@ __device__ __forceinline__ void cov_tile_gemm(gbf16x8* const (&wfrag)[CovShape<N
     cbf16x8 lf[CPW];
 #pragma unroll
     for (int c = 0; c < CPW; ++c) lf[c] = *reinterpret_cast<const cbf16x8*>(lfrag[c] + 16 * ks);
+    // keep the loads above the products: without this the scheduler sinks
+    // the weight loads next to their use and every step waits on L2
+    __builtin_amdgcn_sched_barrier(0);
     if (tile_ok) {
 #pragma unroll
       for (int r = 0; r < RPW; ++r)

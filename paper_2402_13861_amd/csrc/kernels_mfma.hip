@@ -131,38 +131,81 @@ __global__ __launch_bounds__(512) void hidden_mfma_f32_kernel(
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[nb][r] = 0.f;
 
+    // K chunks: the next chunk's operands are loaded into registers while
+    // the current one is multiplied, then stored to LDS
+    constexpr int TA = K::KT * BM / 4, TB = K::KT * K::BN / 4;  // float4 per chunk
+    constexpr int NA = (TA + K::THREADS - 1) / K::THREADS;      // per thread
+    constexpr int NBL = (TB + K::THREADS - 1) / K::THREADS;
+    static_assert(NA <= 2 && NBL <= 4, "prefetch registers");
+    // named registers (not arrays) keep the prefetch out of memory
+    float4 ra0 = make_float4(0.f, 0.f, 0.f, 0.f), ra1 = ra0, rb0 = ra0, rb1 = ra0, rb2 = ra0, rb3 = ra0;
+// loads are unconditional (indices clamped to valid addresses, values
+// masked afterwards), so they stay in flight while the products run
+#define ISX_F32_LOAD_A(U, DST, K0)                                                                 \
+  {                                                                                                \
+    const int idx = min(t + (U) * K::THREADS, TA - 1);                                             \
+    const int kk = idx / (BM / 4), mq = idx - kk * (BM / 4);                                       \
+    DST = *reinterpret_cast<const float4*>(Wt + (int64_t)((K0) + kk) * n_out + m0 + 4 * mq);       \
+  }
+#define ISX_F32_LOAD_B(U, DST, K0)                                                                 \
+  {                                                                                                \
+    const int idx = min(t + (U) * K::THREADS, TB - 1);                                             \
+    const int col = idx / (K::KT / 4), kq = idx - col * (K::KT / 4);                               \
+    const int64_t gc = c0 + col;                                                                   \
+    const int64_t gcc = gc < cols_in ? gc : cols_in - 1;                                           \
+    const float4 v = *reinterpret_cast<const float4*>(fin + gcc * n_in + (K0) + 4 * kq);           \
+    DST = gc < cols_in ? v : make_float4(0.f, 0.f, 0.f, 0.f);                                      \
+  }
+#define ISX_F32_LOAD_CHUNK(K0)                         \
+  {                                                    \
+    ISX_F32_LOAD_A(0, ra0, K0);                        \
+    if constexpr (NA > 1) ISX_F32_LOAD_A(1, ra1, K0);  \
+    ISX_F32_LOAD_B(0, rb0, K0);                        \
+    if constexpr (NBL > 1) ISX_F32_LOAD_B(1, rb1, K0); \
+    if constexpr (NBL > 2) ISX_F32_LOAD_B(2, rb2, K0); \
+    if constexpr (NBL > 3) ISX_F32_LOAD_B(3, rb3, K0); \
+  }
+#define ISX_F32_STORE_A(U, SRC)                                                  \
+  {                                                                              \
+    const int idx = t + (U) * K::THREADS;                                        \
+    const int kk = idx / (BM / 4), mq = idx - kk * (BM / 4);                     \
+    if (idx < TA) *reinterpret_cast<float4*>(As + kk * K::ASTR + 4 * mq) = SRC;  \
+  }
+#define ISX_F32_STORE_B(U, SRC)                                    \
+  {                                                                \
+    const int idx = t + (U) * K::THREADS;                          \
+    const int col = idx / (K::KT / 4), kq = idx - col * (K::KT / 4); \
+    if (idx < TB) {                                                \
+      const int k = k0 + 4 * kq;                                   \
+      float4 v = SRC;                                              \
+      v.x *= s_alpha[k];                                           \
+      v.y *= s_alpha[k + 1];                                       \
+      v.z *= s_alpha[k + 2];                                       \
+      v.w *= s_alpha[k + 3];                                       \
+      if (c0 + col == 0) {                                         \
+        v.x += s_beta[k];                                          \
+        v.y += s_beta[k + 1];                                      \
+        v.z += s_beta[k + 2];                                      \
+        v.w += s_beta[k + 3];                                      \
+      }                                                            \
+      Bs[(4 * kq + 0) * K::BSTR + col] = v.x;                      \
+      Bs[(4 * kq + 1) * K::BSTR + col] = v.y;                      \
+      Bs[(4 * kq + 2) * K::BSTR + col] = v.z;                      \
+      Bs[(4 * kq + 3) * K::BSTR + col] = v.w;                      \
+    }                                                              \
+  }
+    ISX_F32_LOAD_CHUNK(0);
     for (int k0 = 0; k0 < n_in; k0 += K::KT) {
-      // stage A = W^T[k0:k0+KT, m0:m0+BM]
-      for (int idx = t; idx < K::KT * BM / 4; idx += K::THREADS) {
-        const int kk = idx / (BM / 4), mq = idx - kk * (BM / 4);
-        const float4 v = *reinterpret_cast<const float4*>(Wt + (int64_t)(k0 + kk) * n_out + m0 + 4 * mq);
-        *reinterpret_cast<float4*>(As + kk * K::ASTR + 4 * mq) = v;
-      }
-      // stage B = alpha . F[k0:k0+KT, c0:c0+BN] (+ beta on the centre column)
-      for (int idx = t; idx < K::KT * K::BN / 4; idx += K::THREADS) {
-        const int col = idx / (K::KT / 4), kq = idx - col * (K::KT / 4);
-        const int64_t gc = c0 + col;
-        const int k = k0 + 4 * kq;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (gc < cols_in) {
-          v = *reinterpret_cast<const float4*>(fin + gc * n_in + k);
-          v.x *= s_alpha[k];
-          v.y *= s_alpha[k + 1];
-          v.z *= s_alpha[k + 2];
-          v.w *= s_alpha[k + 3];
-          if (gc == 0) {
-            v.x += s_beta[k];
-            v.y += s_beta[k + 1];
-            v.z += s_beta[k + 2];
-            v.w += s_beta[k + 3];
-          }
-        }
-        Bs[(4 * kq + 0) * K::BSTR + col] = v.x;
-        Bs[(4 * kq + 1) * K::BSTR + col] = v.y;
-        Bs[(4 * kq + 2) * K::BSTR + col] = v.z;
-        Bs[(4 * kq + 3) * K::BSTR + col] = v.w;
-      }
+      __syncthreads();  // the previous chunk's products are done with LDS
+      ISX_F32_STORE_A(0, ra0);
+      if constexpr (NA > 1) ISX_F32_STORE_A(1, ra1);
+      // B = alpha . F (+ beta on the centre column)
+      ISX_F32_STORE_B(0, rb0);
+      if constexpr (NBL > 1) ISX_F32_STORE_B(1, rb1);
+      if constexpr (NBL > 2) ISX_F32_STORE_B(2, rb2);
+      if constexpr (NBL > 3) ISX_F32_STORE_B(3, rb3);
       __syncthreads();
+      if (k0 + K::KT < n_in) ISX_F32_LOAD_CHUNK(k0 + K::KT);
       if (wave_active) {
 #pragma unroll
         for (int ks = 0; ks < K::KT / 2; ++ks) {
@@ -175,8 +218,13 @@ __global__ __launch_bounds__(512) void hidden_mfma_f32_kernel(
           }
         }
       }
-      __syncthreads();
     }
+#undef ISX_F32_LOAD_CHUNK
+#undef ISX_F32_LOAD_A
+#undef ISX_F32_LOAD_B
+#undef ISX_F32_STORE_A
+#undef ISX_F32_STORE_B
+    __syncthreads();
     if (wave_active) {
 #pragma unroll
       for (int nb = 0; nb < K::NB; ++nb) {

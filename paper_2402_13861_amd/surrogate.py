@@ -74,6 +74,8 @@ class SurrogateInfo:
     losses: Optional[np.ndarray] = None
     z: float = 2.0
     z_accept: float = 2.0
+    z_levels: List[float] = field(default_factory=list)
+    z_accept_levels: List[float] = field(default_factory=list)
     holdout_miss: float = 0.0
     holdout_false_accept: float = 0.0
 
@@ -123,6 +125,7 @@ def train_surrogate(ctx, mlp_id: int, depth: int, mu_bar: float, scale: float, v
                     hidden=(128, 128, 128), seed: int = 0, holdout: int = 200_000, z: Optional[float] = None,
                     isos=None, k: float = 3.0, miss_target: float = 1e-4, accept_target: float = 1e-3,
                     z_accept: Optional[float] = None, accept_leaves: bool = False, base: bool = False,
+                    per_level: bool = True, min_level_kept: int = 20000,
                     lo=(-1.0,) * 3, hi=(1.0,) * 3, log=None) -> SurrogateInfo:
     """Train a surrogate for ``mlp_id`` and attach it for extraction.
 
@@ -137,7 +140,10 @@ def train_surrogate(ctx, mlp_id: int, depth: int, mu_bar: float, scale: float, v
     bound multiplier k) is at most ``miss_target``.  A wrong accept only
     costs work, so the accept band z_accept is calibrated on its own: with
     None, the smallest ladder value whose held-out false-accept rate is at
-    most ``accept_target``.
+    most ``accept_target``.  With ``per_level``, each octree level whose
+    held-out set has at least ``min_level_kept`` cells that the plain test
+    keeps gets its own bands by the same rules (the others use the global
+    ones).
     """
     import torch
 
@@ -250,11 +256,34 @@ def train_surrogate(ctx, mlp_id: int, depth: int, mu_bar: float, scale: float, v
         z_accept = zc
         log("surrogate: held-out false-accept rate by accept band: " +
             ", ".join(f"z={a}: {b:.2e}" for a, b in rates.items()))
-    ctx.surrogate_attach(mlp_id, sid, err_mu, err_ls, z=z, accept_leaves=accept_leaves, z_accept=z_accept)
+    z_lv = [float(z)] * (depth + 1)
+    za_lv = [float(z_accept)] * (depth + 1)
+    if per_level and isos is not None:
+        for L in range(depth + 1):
+            sel = lv == L
+            if not sel.any():
+                continue
+            mu_t, sg_t = tv[sel, 0], tv[sel, 1]
+            kept = np.zeros(sel.sum(), dtype=bool)
+            for c in isos:
+                kept |= np.abs(mu_t - c) <= k * sg_t
+            if kept.sum() < min_level_kept:
+                continue
+            u = None if unit is None else unit[sel]
+            args = (p[sel], tv[sel], lv[sel], err_mu, err_ls, isos, k)
+            z_lv[L] = next((zc for zc in Z_LADDER[4:] if miss_rate(*args, zc, u) <= miss_target), Z_LADDER[-1])
+            za_lv[L] = next((zc for zc in Z_LADDER if false_accept_rate(*args, zc, u) <= accept_target),
+                            Z_LADDER[-1])
+        log("surrogate: per-level bands (prune/accept): " +
+            ", ".join(f"L{L} {a}/{b}" for L, (a, b) in enumerate(zip(z_lv, za_lv))))
+    ctx.surrogate_attach(mlp_id, sid, err_mu, err_ls, z=z_lv, accept_leaves=accept_leaves, z_accept=za_lv)
     info = SurrogateInfo(sid, n_train, steps, train_s, float(losses[-20:].mean()), err_mu, err_ls, losses)
     info.z = z
     info.z_accept = z_accept
+    info.z_levels = z_lv
+    info.z_accept_levels = za_lv
     if isos is not None:
-        info.holdout_miss = float(miss_rate(p, tv, lv, err_mu, err_ls, isos, k, z, unit))
-        info.holdout_false_accept = float(false_accept_rate(p, tv, lv, err_mu, err_ls, isos, k, z_accept, unit))
+        zl, zal = np.asarray(z_lv)[lv], np.asarray(za_lv)[lv]
+        info.holdout_miss = float(miss_rate(p, tv, lv, err_mu, err_ls, isos, k, zl, unit))
+        info.holdout_false_accept = float(false_accept_rate(p, tv, lv, err_mu, err_ls, isos, k, zal, unit))
     return info
