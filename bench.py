@@ -36,24 +36,29 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCE = {"fp32": "kernels_mfma.hip", "bf16": "kernels_bf16.hip"}
+# hidden-layer kernel kinds: (kernel name, source file, MFMA dtype)
+HIDDEN_KINDS = {
+    "hidden_fp32": ("hidden_mfma_f32_kernel", "kernels_mfma.hip", "fp32"),
+    "hidden_bf16": ("hidden_mfma_bf16_kernel", "kernels_bf16.hip", "bf16"),
+    "hidden_cov_bf16": ("up_cov_bf16_kernel", "kernels_cov.hip", "bf16"),
+}
 
 
-def kernel_source_hash(precision: str) -> str:
-    src = ROOT / "paper_2402_13861_amd" / "csrc" / KERNEL_SOURCE[precision]
+def kernel_source_hash(kind: str) -> str:
+    src = ROOT / "paper_2402_13861_amd" / "csrc" / HIDDEN_KINDS[kind][1]
     return hashlib.sha256(src.read_bytes()).hexdigest()[:16]
 
 
-def traffic_from_profiles(precision: str, cells_per_launch: float):
+def traffic_from_profiles(kind: str, cells_per_launch: float):
     """HBM bytes per launch of the dominant kernel: the committed rocprofv3
     counter summary's bytes per propagated cell (all hidden-layer launches of
     a cell; taken on the current kernel source, else None) times the
     propagated cells per launch of this run (propagated cells / launches)."""
-    f = ROOT / "profiles" / f"hidden_layer_{precision}_traffic.json"
+    f = ROOT / "profiles" / f"{kind}_traffic.json"
     if not f.exists():
         return None
     t = json.loads(f.read_text())
-    if t.get("kernel_source_sha256_16") != kernel_source_hash(precision):
+    if t.get("kernel_source_sha256_16") != kernel_source_hash(kind):
         return None
     return t["hbm_bytes_per_cell"] * cells_per_launch
 
@@ -243,18 +248,19 @@ def main(argv=None):
                        plain_leaves=int(plain_ids.size), leaves=int(last_ids.size))
         log("quality:", quality)
 
-    kind = "hidden_fp32" if a.precision == "fp32" else "hidden_bf16"
+    # the dominant hidden-layer kernel: the kind with the most device time
+    kind = max(HIDDEN_KINDS, key=lambda k_: prof[k_]["ms"])
     kp = prof[kind]
     launches = max(kp["launches"], 1)
     avg_ms = kp["ms"] / launches
     flops_per_launch = kp["flops"] / launches
     achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
-    peak = PEAK_TFLOPS[a.precision]
+    peak = PEAK_TFLOPS[HIDDEN_KINDS[kind][2]]
     cells_per_launch = propagated / (kp["launches"] / K) if kp["launches"] else 0.0
-    traffic = traffic_from_profiles(a.precision, cells_per_launch)
+    traffic = traffic_from_profiles(kind, cells_per_launch)
     roofline = {
         "bound": "mfma",
-        "kernel": "hidden_mfma_f32_kernel" if a.precision == "fp32" else "hidden_mfma_bf16_kernel",
+        "kernel": HIDDEN_KINDS[kind][0],
         "achieved": round(achieved, 3),
         "peak": peak,
         "unit": "TFLOP/s",

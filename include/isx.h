@@ -297,7 +297,9 @@ typedef enum {
   ISX_KERNEL_HIDDEN_SIMT_FP32 = 2, /* hidden-layer product, float32 vector ALUs */
   ISX_KERNEL_HIDDEN_FP64 = 3,      /* hidden-layer product, float64 (re-check band, ISX_FP64) */
   ISX_KERNEL_DENSE = 4,            /* dense forward passes (corner evaluation, linearisation) */
-  ISX_KERNEL_OUTPUT = 5            /* output read-off (spread of the last layer) */
+  ISX_KERNEL_OUTPUT = 5,           /* output read-off (spread of the last layer) */
+  ISX_KERNEL_HIDDEN_COV_BF16 = 6   /* every hidden layer of uncertainty propagation in covariance form,
+                                      BF16 MFMA (ISX_UP_FORM 0) */
 } isx_kernel_kind;
 
 /* Accumulated statistics of one kernel kind since the last reset (ISX_PROFILE
@@ -307,7 +309,12 @@ typedef enum {
  * cell (the real columns of hidden layer h are the 3 input symbols (+1
  * centre in the float32/float64 layouts) and the true widths of layers
  * 1..h-2); bytes = the coefficient block read plus the block written unless
- * it is the last hidden layer, at the storage precision.  Synchronises the
+ * it is the last hidden layer, at the storage precision.  For the covariance
+ * kind: flops = per hidden layer h >= 2, 2 n_h n_{h-1}^2 for T = W_h X_{h-1}
+ * and 2 n_h^2 n_{h-1} for C_h = T W_h^T (the last hidden layer: 2 n_h n_{h-1}
+ * for the diagonal of C_h alone); bytes = the cell's centre and half-sizes
+ * read plus the four per-neuron float32 vectors written per hidden layer.
+ * Synchronises the
  * stream.  reset != 0 clears the counters of every kind. */
 isx_status isx_get_profile(isx_ctx* ctx, int32_t kernel, int64_t* launches, double* ms, double* flops,
                            double* bytes, int32_t reset);

@@ -379,15 +379,15 @@ hipError_t launch_up_cov_bf16(const Model& m, int64_t C, const float* centres, c
 }
 
 // Algorithmic flops per cell of the covariance form (true widths): per hidden
-// layer h >= 2, T = W X (2 n_h n_{h-1}^2) and C = T W^T (2 n_h^2 n_{h-1}; the
-// last hidden layer only its diagonal 32x32 blocks).
+// layer h >= 2, T = W X (2 n_h n_{h-1}^2) and C = T W^T (2 n_h^2 n_{h-1}); the
+// last hidden layer needs only the diagonal of C (2 n_h n_{h-1}).
 double cov_flops_per_cell(const Model& m) {
   double f = 0.0;
   const int Lh = m.n_linear - 1;
   for (int h = 2; h <= Lh; ++h) {
     const double a = m.widths[h], b = m.widths[h - 1];
     f += 2.0 * a * b * b;
-    f += h < Lh ? 2.0 * a * a * b : 2.0 * a * 32.0 * b;
+    f += h < Lh ? 2.0 * a * a * b : 2.0 * a * b;
   }
   return f;
 }
