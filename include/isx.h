@@ -310,9 +310,11 @@ typedef enum {
  * centre in the float32/float64 layouts) and the true widths of layers
  * 1..h-2); bytes = the coefficient block read plus the block written unless
  * it is the last hidden layer, at the storage precision.  For the covariance
- * kind: flops = per hidden layer h >= 2, 2 n_h n_{h-1}^2 for T = W_h X_{h-1}
- * and 2 n_h^2 n_{h-1} for C_h = T W_h^T (the last hidden layer: 2 n_h n_{h-1}
- * for the diagonal of C_h alone); bytes = the cell's centre and half-sizes
+ * kind: flops = for layer 2, 14 n_2 n_1 (T_2 from the rank-3 factor of X_1
+ * and the variances) plus 2 n_2^2 n_1 for C_2 = T_2 W_2^T; for each later
+ * hidden layer h, 2 n_h n_{h-1}^2 for T = W_h X_{h-1} and 2 n_h^2 n_{h-1} for
+ * C_h = T W_h^T (the last hidden layer: 2 n_h n_{h-1} for the diagonal of C_h
+ * alone); bytes = the cell's centre and half-sizes
  * read plus the four per-neuron float32 vectors written per hidden layer.
  * Synchronises the
  * stream.  reset != 0 clears the counters of every kind. */

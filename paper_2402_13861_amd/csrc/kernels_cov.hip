@@ -16,7 +16,11 @@
 // vectors for the output read-off.  Affine arithmetic has no such form (its
 // statistic is a sum of magnitudes) and keeps the coefficient kernel.
 //
-// Per layer h (8 waves, 512 threads):
+// Layer 1: X_1 = G G^T + diag(gamma_1^2) with G = D_1 W_1 diag(h / sqrt 3)
+// (N x 3) has rank 3, so layer 2 needs no product for T: with P = W_2 G,
+// T = W_2 X_1 = P G^T + W_2 diag(gamma_1^2) is written element by element,
+// and the variances of layer 2 are |P_j|^2 + sum_k W_2[j][k]^2 gamma_1k^2.
+// Per layer h >= 3 (8 waves, 512 threads):
 //   2. T = W_h X_{h-1}: each wave computes a tile of RPW x CPW blocks of
 //      32 x 32, with A = bfloat16 fragments of its weight rows streamed from
 //      the L2-resident bf16 copy of W a few k-steps ahead, and B = rows of X
@@ -26,7 +30,9 @@
 //   4. Per neuron (a thread pair), in one pass over its float32 weight row:
 //      the centre y = W z + b with z = alpha . y_{h-1} + beta, the variance
 //      C_h[j][j] = sum_k T[j][k] W[j][k], and the ReLU rule, which gives
-//      (alpha, beta, gamma).
+//      (alpha, beta, gamma).  The pair's two lanes read 8-element chunks of
+//      the row 64 elements apart, so that the rows of neighbouring pairs fall
+//      in different LDS banks.
 //   5. C_h = T W_h^T on the wave's tile (A = rows of T from LDS, B = weight
 //      fragments, whose lane layout is the B layout of the transposed
 //      product).  The last hidden layer needs only step 4.
@@ -43,6 +49,9 @@ namespace isx {
 
 typedef __bf16 cbf16x8 __attribute__((ext_vector_type(8)));
 typedef __attribute__((address_space(1))) const cbf16x8 gbf16x8;  // in global memory
+typedef __attribute__((address_space(1))) const float gfloat;
+typedef float cv4f __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const cv4f gfloat4;
 typedef float cv16f __attribute__((ext_vector_type(16)));
 
 constexpr int kCovThreads = 512;  // 8 waves
@@ -61,7 +70,7 @@ struct CovShape {
   static constexpr int RG = (NB + RPW - 1) / RPW;  // wave groups along the weight rows
   static constexpr int CG = (NB + CPW - 1) / CPW;  // wave groups along the LDS operand
   static constexpr int PF = 4;                     // weight fragments loaded this many k-steps ahead
-  static constexpr size_t LDS = (size_t)N * STR * 2 + 8 * N * sizeof(float);
+  static constexpr size_t LDS = (size_t)N * STR * 2 + 14 * N * sizeof(float);
   static_assert(RG * CG <= 8, "more tiles than waves");
 };
 
@@ -137,6 +146,14 @@ __device__ __forceinline__ void cov_relu_rule(float y, float var, float& a, floa
   g = g2 > 0.f ? sqrtf(g2) : 0.f;
 }
 
+// Start of the i-th 8-element chunk (i < N/16) that lane `part` of a thread
+// pair reads of an N-element row: for N a multiple of 128 the two lanes read
+// chunks 8 apart (128 bytes of bfloat16), else adjacent chunks.
+template <int N>
+__device__ __forceinline__ int cov_chunk(int i, int part) {
+  return N % 128 == 0 ? 8 * ((i & 7) + 16 * (i >> 3) + 8 * part) : 8 * (2 * i + part);
+}
+
 // All hidden layers have padded width N (the input layer is 3 wide).
 template <int N>
 __global__ __launch_bounds__(kCovThreads) void up_cov_bf16_kernel(int64_t C, int n_linear,
@@ -152,7 +169,8 @@ __global__ __launch_bounds__(kCovThreads) void up_cov_bf16_kernel(int64_t C, int
   float* s_zbuf = s_alpha + N;  // two buffers of z = alpha . y + beta (previous layer, this layer)
   float* s_gamma = s_zbuf + 2 * N;
   float* s_var = s_gamma + N;
-  float* s_F = s_var + N;       // layer 1: F = W_1 diag(h / sqrt 3), [N][3]
+  float4* s_G = reinterpret_cast<float4*>(s_var + N);  // layer 1: (G_j, gamma_1j^2), G = D_1 W_1 diag(h / sqrt 3)
+  float4* s_P = s_G + N;                               // layer 2: (P_j, 0), P = W_2 G
 
   const int64_t cell = blockIdx.x;
   if (cell >= C) return;
@@ -165,44 +183,25 @@ __global__ __launch_bounds__(kCovThreads) void up_cov_bf16_kernel(int64_t C, int
   const int Lh = n_linear - 1;
   float* vh = vec;  // this hidden layer's Y, A, B, G
 
-  // ---- layer 1: centre, variances, rule, X_1
+  // ---- layer 1: centre, variances, rule, G
   {
     const DevLayer L1 = layers[0];
-    const float* W1 = L1.W;
+    gfloat* W1 = (gfloat*)L1.W;
+    gfloat* b1 = (gfloat*)L1.b;
     const float sc = 0.57735026918962576451f;
     const float hx = halves[cell * 3 + 0] * sc, hy = halves[cell * 3 + 1] * sc, hz = halves[cell * 3 + 2] * sc;
     float* s_z = s_zbuf + N;  // read by layer 2
     for (int j = t; j < N; j += kCovThreads) {
       const float w0 = W1[j * 3 + 0], w1 = W1[j * 3 + 1], w2 = W1[j * 3 + 2];
-      const float y = L1.b[j] + w0 * centres[cell * 3 + 0] + w1 * centres[cell * 3 + 1] + w2 * centres[cell * 3 + 2];
+      const float y = b1[j] + w0 * centres[cell * 3 + 0] + w1 * centres[cell * 3 + 1] + w2 * centres[cell * 3 + 2];
       const float f0 = w0 * hx, f1 = w1 * hy, f2 = w2 * hz;
       float a, b, g;
       cov_relu_rule(y, f0 * f0 + f1 * f1 + f2 * f2, a, b, g);
       s_alpha[j] = a;
       s_z[j] = a * y + b;
       s_gamma[j] = g;
-      s_F[3 * j + 0] = f0;
-      s_F[3 * j + 1] = f1;
-      s_F[3 * j + 2] = f2;
+      s_G[j] = make_float4(a * f0, a * f1, a * f2, g * g);
       cov_store_vec(vh, C, N, cell, j, y, a, b, g);
-    }
-    __syncthreads();
-    if (Lh >= 2) {
-      // X_1[i][j] = alpha_i alpha_j F_i . F_j + delta_ij gamma_j^2, eight
-      // consecutive j per thread and store
-      for (int e = t; e < N * N / 8; e += kCovThreads) {
-        const int i = e / (N / 8), j0 = 8 * (e - i * (N / 8));
-        const float ai = s_alpha[i], fi0 = s_F[3 * i], fi1 = s_F[3 * i + 1], fi2 = s_F[3 * i + 2];
-        cbf16x8 v8;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int j = j0 + u;
-          float v = ai * s_alpha[j] * (fi0 * s_F[3 * j] + fi1 * s_F[3 * j + 1] + fi2 * s_F[3 * j + 2]);
-          if (i == j) v += s_gamma[j] * s_gamma[j];
-          v8[u] = (__bf16)v;
-        }
-        *reinterpret_cast<cbf16x8*>(X + (size_t)i * STR + j0) = v8;
-      }
     }
     __syncthreads();
     vh += 4 * (int64_t)N * C;
@@ -231,65 +230,136 @@ __global__ __launch_bounds__(kCovThreads) void up_cov_bf16_kernel(int64_t C, int
 
     const float* s_zin = s_zbuf + (h - 1 & 1) * N;  // z of layer h-1
     float* s_zout = s_zbuf + (h & 1) * N;           // z of layer h
-    // 2. T = W X on the wave's tile (rows: weight blocks, columns: X blocks,
-    //    X symmetric); 3. T -> LDS row-major once every wave has read X
-    {
-      cv16f acc[RPW][CPW];
-#pragma unroll
-      for (int r = 0; r < RPW; ++r)
-#pragma unroll
-        for (int c = 0; c < CPW; ++c)
-#pragma unroll
-          for (int e = 0; e < 16; ++e) acc[r][c][e] = 0.f;
-      cov_tile_gemm<N, true>(wfrag, lfrag, tile, acc);
-      __syncthreads();
-#pragma unroll
-      for (int r = 0; r < RPW; ++r)
-#pragma unroll
-        for (int c = 0; c < CPW; ++c)
-          if (wok[r] && lok[c]) {
-#pragma unroll
-            for (int e = 0; e < 16; ++e) {
-              const int row = (rg * RPW + r) * 32 + 8 * (e >> 2) + 4 * hi + (e & 3);
-              X[(size_t)row * STR + (cg * CPW + c) * 32 + l32] = (__bf16)acc[r][c][e];
-            }
-          }
-    }
-    __syncthreads();
-
-    // 4. per neuron j (a thread pair): the float32 centre y_j = W[j] z + b_j,
-    //    the variance C_h[j][j] = sum_k T[j][k] W[j][k], and the ReLU rule
-    for (int j = t >> 1; j < N; j += kCovThreads / 2) {
-      const int part = t & 1;
-      const float* wrow = Lw.W + (int64_t)j * N;
-      const __bf16* trow = X + (size_t)j * STR;
-      float v = 0.f, yc = 0.f;
+    if (h == 2) {
+      // 4. per neuron j (a thread pair), one pass over the float32 weight
+      //    row: y_j = W[j] z + b_j, P_j = W[j] G and the variance
+      //    |P_j|^2 + sum_k W[j][k]^2 gamma_1k^2, then the ReLU rule
+      for (int j = t >> 1; j < N; j += kCovThreads / 2) {
+        const int part = t & 1;
+        gfloat* wrow = (gfloat*)Lw.W + (int64_t)j * N;
+        float yc = 0.f, p0 = 0.f, p1 = 0.f, p2 = 0.f, q = 0.f;
 #pragma unroll 2
-      for (int k = 8 * part; k < N; k += 16) {
-        const cbf16x8 tv = *reinterpret_cast<const cbf16x8*>(trow + k);
-        const float4 w0 = *reinterpret_cast<const float4*>(wrow + k);
-        const float4 w1 = *reinterpret_cast<const float4*>(wrow + k + 4);
-        const float4 z0 = *reinterpret_cast<const float4*>(s_zin + k);
-        const float4 z1 = *reinterpret_cast<const float4*>(s_zin + k + 4);
-        v += w0.x * (float)tv[0] + w0.y * (float)tv[1] + w0.z * (float)tv[2] + w0.w * (float)tv[3] +
-             w1.x * (float)tv[4] + w1.y * (float)tv[5] + w1.z * (float)tv[6] + w1.w * (float)tv[7];
-        yc += w0.x * z0.x + w0.y * z0.y + w0.z * z0.z + w0.w * z0.w + w1.x * z1.x + w1.y * z1.y + w1.z * z1.z +
-              w1.w * z1.w;
+        for (int i = 0; i < N / 16; ++i) {
+          const int k = cov_chunk<N>(i, part);
+          const cv4f w0 = *reinterpret_cast<gfloat4*>(wrow + k);
+          const cv4f w1 = *reinterpret_cast<gfloat4*>(wrow + k + 4);
+          const float4 z0 = *reinterpret_cast<const float4*>(s_zin + k);
+          const float4 z1 = *reinterpret_cast<const float4*>(s_zin + k + 4);
+          yc += w0.x * z0.x + w0.y * z0.y + w0.z * z0.z + w0.w * z0.w + w1.x * z1.x + w1.y * z1.y + w1.z * z1.z +
+                w1.w * z1.w;
+          const float wv[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const float4 g4 = s_G[k + u];
+            p0 += wv[u] * g4.x;
+            p1 += wv[u] * g4.y;
+            p2 += wv[u] * g4.z;
+            q += wv[u] * wv[u] * g4.w;
+          }
+        }
+        yc += __shfl_xor(yc, 1);
+        p0 += __shfl_xor(p0, 1);
+        p1 += __shfl_xor(p1, 1);
+        p2 += __shfl_xor(p2, 1);
+        q += __shfl_xor(q, 1);
+        if (part == 0) {
+          float a, b, g;
+          const float y = yc + ((gfloat*)Lw.b)[j];
+          const float v = p0 * p0 + p1 * p1 + p2 * p2 + q;
+          cov_relu_rule(y, v, a, b, g);
+          s_var[j] = v;
+          s_alpha[j] = a;
+          s_zout[j] = a * y + b;
+          s_gamma[j] = g;
+          s_P[j] = make_float4(p0, p1, p2, 0.f);
+          cov_store_vec(vh, C, N, cell, j, y, a, b, g);
+        }
       }
-      v += __shfl_xor(v, 1);
-      yc += __shfl_xor(yc, 1);
-      if (part == 0) {
-        float a, b, g;
-        const float y = yc + Lw.b[j];
-        cov_relu_rule(y, v, a, b, g);
-        s_var[j] = v;
-        s_alpha[j] = a;
-        s_zout[j] = a * y + b;
-        s_gamma[j] = g;
-        cov_store_vec(vh, C, N, cell, j, y, a, b, g);
+      if (last) break;
+      __syncthreads();
+      // 3. T = P G^T + W diag(gamma_1^2) -> LDS row-major; each thread keeps
+      //    one 8-column chunk of G and walks rows
+      constexpr int NCH = N / 8, TR = kCovThreads / NCH;
+      if (t < NCH * TR) {
+        const int k0 = 8 * (t % NCH);
+        float4 gk[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) gk[u] = s_G[k0 + u];
+        for (int i = t / NCH; i < N; i += TR) {
+          const float4 p = s_P[i];
+          gfloat* wrow = (gfloat*)Lw.W + (int64_t)i * N + k0;
+          const cv4f w0 = *reinterpret_cast<gfloat4*>(wrow);
+          const cv4f w1 = *reinterpret_cast<gfloat4*>(wrow + 4);
+          const float wv[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+          cbf16x8 v8;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) v8[u] = (__bf16)(p.x * gk[u].x + p.y * gk[u].y + p.z * gk[u].z + wv[u] * gk[u].w);
+          *reinterpret_cast<cbf16x8*>(X + (size_t)i * STR + k0) = v8;
+        }
       }
+      __syncthreads();
+    } else {
+      // 2. T = W X on the wave's tile (rows: weight blocks, columns: X blocks,
+      //    X symmetric); 3. T -> LDS row-major once every wave has read X
+      {
+        cv16f acc[RPW][CPW];
+#pragma unroll
+        for (int r = 0; r < RPW; ++r)
+#pragma unroll
+          for (int c = 0; c < CPW; ++c)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[r][c][e] = 0.f;
+        cov_tile_gemm<N, true>(wfrag, lfrag, tile, acc);
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < RPW; ++r)
+#pragma unroll
+          for (int c = 0; c < CPW; ++c)
+            if (wok[r] && lok[c]) {
+#pragma unroll
+              for (int e = 0; e < 16; ++e) {
+                const int row = (rg * RPW + r) * 32 + 8 * (e >> 2) + 4 * hi + (e & 3);
+                X[(size_t)row * STR + (cg * CPW + c) * 32 + l32] = (__bf16)acc[r][c][e];
+              }
+            }
+      }
+      __syncthreads();
+
+      // 4. per neuron j (a thread pair): the float32 centre y_j = W[j] z + b_j,
+      //    the variance C_h[j][j] = sum_k T[j][k] W[j][k], and the ReLU rule
+      for (int j = t >> 1; j < N; j += kCovThreads / 2) {
+        const int part = t & 1;
+        gfloat* wrow = (gfloat*)Lw.W + (int64_t)j * N;
+        const __bf16* trow = X + (size_t)j * STR;
+        float v = 0.f, yc = 0.f;
+#pragma unroll 2
+        for (int i = 0; i < N / 16; ++i) {
+          const int k = cov_chunk<N>(i, part);
+          const cbf16x8 tv = *reinterpret_cast<const cbf16x8*>(trow + k);
+          const cv4f w0 = *reinterpret_cast<gfloat4*>(wrow + k);
+          const cv4f w1 = *reinterpret_cast<gfloat4*>(wrow + k + 4);
+          const float4 z0 = *reinterpret_cast<const float4*>(s_zin + k);
+          const float4 z1 = *reinterpret_cast<const float4*>(s_zin + k + 4);
+          v += w0.x * (float)tv[0] + w0.y * (float)tv[1] + w0.z * (float)tv[2] + w0.w * (float)tv[3] +
+               w1.x * (float)tv[4] + w1.y * (float)tv[5] + w1.z * (float)tv[6] + w1.w * (float)tv[7];
+          yc += w0.x * z0.x + w0.y * z0.y + w0.z * z0.z + w0.w * z0.w + w1.x * z1.x + w1.y * z1.y + w1.z * z1.z +
+                w1.w * z1.w;
+        }
+        v += __shfl_xor(v, 1);
+        yc += __shfl_xor(yc, 1);
+        if (part == 0) {
+          float a, b, g;
+          const float y = yc + ((gfloat*)Lw.b)[j];
+          cov_relu_rule(y, v, a, b, g);
+          s_var[j] = v;
+          s_alpha[j] = a;
+          s_zout[j] = a * y + b;
+          s_gamma[j] = g;
+          cov_store_vec(vh, C, N, cell, j, y, a, b, g);
+        }
+      }
+      if (last) break;
     }
-    if (last) break;
     vh += 4 * (int64_t)N * C;
     // 5. C_h on the wave's tile, C[i][j] = sum_k T[i][k] W[j][k] (rows i:
     //    T blocks from LDS, columns j: weight blocks)
@@ -378,16 +448,19 @@ hipError_t launch_up_cov_bf16(const Model& m, int64_t C, const float* centres, c
   }
 }
 
-// Algorithmic flops per cell of the covariance form (true widths): per hidden
-// layer h >= 2, T = W X (2 n_h n_{h-1}^2) and C = T W^T (2 n_h^2 n_{h-1}); the
-// last hidden layer needs only the diagonal of C (2 n_h n_{h-1}).
+// Algorithmic flops per cell of the covariance form (true widths): layer 2
+// builds T from the rank-3 factor (P = W G, T = P G^T + W diag(gamma^2) and
+// the variances: 14 n_2 n_1) and multiplies C = T W^T (2 n_2^2 n_1); every
+// later layer h multiplies T = W X (2 n_h n_{h-1}^2) and C = T W^T
+// (2 n_h^2 n_{h-1}); the last hidden layer needs only the diagonal of C
+// (2 n_h n_{h-1}).
 double cov_flops_per_cell(const Model& m) {
   double f = 0.0;
   const int Lh = m.n_linear - 1;
   for (int h = 2; h <= Lh; ++h) {
     const double a = m.widths[h], b = m.widths[h - 1];
-    f += 2.0 * a * b * b;
-    f += h < Lh ? 2.0 * a * a * b : 2.0 * a * b;
+    f += h == 2 ? 14.0 * a * b : 2.0 * a * b * b;
+    f += h < Lh ? 2.0 * a * a * b : (h == 2 ? 0.0 : 2.0 * a * b);
   }
   return f;
 }
