@@ -32,7 +32,38 @@ struct Layer {
   double* bd = nullptr;
   uint16_t* Wtbf = nullptr; // bfloat16 bits of W^T, [n_in][n_out]
   uint16_t* Wbf = nullptr;  // bfloat16 bits of W, [n_out][n_in]
+  // square hidden layers of width <= kCovNMax only (else null):
+  uint16_t* Wfr = nullptr;  // bfloat16 bits of W in MFMA fragment order (cov_frag_index)
+  float* Wv = nullptr;      // W with each row's chunks in row-pass order (cov_row_pos)
 };
+
+// Covariance-form layouts of a square N x N layer (N a multiple of 32, at
+// most kCovNMax).
+constexpr int kCovNMax = 256;
+
+// Position of W[row][k] in the fragment-order copy: for each 32-row block and
+// each 16-wide k-step, the 64 lanes' 8-element A fragments of the
+// 32x32x16 bf16 product (lane 32 (k%16 >= 8) + row%32) lie in one 1 KiB run.
+__host__ __device__ inline int64_t cov_frag_index(int N, int row, int k) {
+  const int blk = row >> 5, l32 = row & 31, ks = k >> 4, hi = (k >> 3) & 1, e = k & 7;
+  return ((int64_t)(blk * (N >> 4) + ks) * 64 + hi * 32 + l32) * 8 + e;
+}
+
+// The row passes give each row 4 lanes (q = 0..3); at step m (m < N/32)
+// lane q reads the row's 8-element chunk cov_row_chunk(N, q, m).  For N a
+// multiple of 128 the four chunks of a step lie 32 elements apart, so the
+// bfloat16 rows of 4 neighbouring rows (LDS row stride = 4 dwords mod 16)
+// fall in distinct LDS banks.
+__host__ __device__ inline int cov_row_chunk(int N, int q, int m) {
+  return N % 128 == 0 ? 4 * q + (m & 3) + 16 * (m >> 2) : q * (N >> 5) + m;
+}
+
+// Position of W[row][8 c + e] in the row-pass copy, c = cov_row_chunk(N, q, m):
+// the four lanes' chunks of one step are adjacent (32 floats, one 128-byte
+// line).
+__host__ __device__ inline int64_t cov_row_pos(int N, int row, int q, int m, int e) {
+  return (int64_t)row * N + (4 * m + q) * 8 + e;
+}
 
 // Per-layer pointers in device memory, for kernels that walk the layers with a
 // runtime index (one scalar load per layer instead of whole pointer arrays in
@@ -40,6 +71,8 @@ struct Layer {
 struct DevLayer {
   const float* W;         // [n_out][n_in]
   const uint16_t* Wbf;    // bfloat16 bits of W, [n_out][n_in]
+  const uint16_t* Wfr;    // fragment order (square layers <= kCovNMax, else null)
+  const float* Wv;        // row-pass order (square layers <= kCovNMax, else null)
   const float* b;         // [n_out]
   int n_in, n_out;        // padded widths
 };

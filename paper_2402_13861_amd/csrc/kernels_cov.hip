@@ -23,16 +23,18 @@
 // Per layer h >= 3 (8 waves, 512 threads):
 //   2. T = W_h X_{h-1}: each wave computes a tile of RPW x CPW blocks of
 //      32 x 32, with A = bfloat16 fragments of its weight rows streamed from
-//      the L2-resident bf16 copy of W a few k-steps ahead, and B = rows of X
-//      from LDS (X is symmetric, so its rows serve as B columns).  A weight
-//      fragment serves CPW products and an LDS fragment RPW.
+//      the L2-resident fragment-order copy of W a few k-steps ahead (a wave's
+//      fragment load is one 1 KiB run), and B = rows of X from LDS (X is
+//      symmetric, so its rows serve as B columns).  A weight fragment serves
+//      CPW products and an LDS fragment RPW.
 //   3. T replaces X in LDS (row-major).
-//   4. Per neuron (a thread pair), in one pass over its float32 weight row:
-//      the centre y = W z + b with z = alpha . y_{h-1} + beta, the variance
-//      C_h[j][j] = sum_k T[j][k] W[j][k], and the ReLU rule, which gives
-//      (alpha, beta, gamma).  The pair's two lanes read 8-element chunks of
-//      the row 64 elements apart, so that the rows of neighbouring pairs fall
-//      in different LDS banks.
+//   4. Per neuron (a quad of lanes), in one pass over its float32 weight
+//      row: the centre y = W z + b with z = alpha . y_{h-1} + beta, the
+//      variance C_h[j][j] = sum_k T[j][k] W[j][k], and the ReLU rule, which
+//      gives (alpha, beta, gamma).  The quad's lanes read chunks of T that
+//      fall in distinct LDS banks for 4 neighbouring rows, and the weights
+//      come from a copy whose rows are permuted so that the same lanes read
+//      one 128-byte line per row and step.
 //   5. C_h = T W_h^T on the wave's tile (A = rows of T from LDS, B = weight
 //      fragments, whose lane layout is the B layout of the transposed
 //      product).  The last hidden layer needs only step 4.
@@ -55,7 +57,6 @@ typedef __attribute__((address_space(1))) const cv4f gfloat4;
 typedef float cv16f __attribute__((ext_vector_type(16)));
 
 constexpr int kCovThreads = 512;  // 8 waves
-constexpr int kCovNMax = 256;     // largest padded hidden width
 
 template <int N>
 struct CovShape {
@@ -77,8 +78,10 @@ struct CovShape {
 // acc[r][c] += W[wrow[r] rows] * L[lrow[c] rows]^T over all N k values, as
 // MFMA products D[i][j] = sum_k A[i][k] B[k][j]: with WA the weight rows are
 // the A operand (rows of D) and the LDS rows the B operand (columns of D);
-// otherwise the roles swap.  wfrag[r] points at this lane's 8-element chunk
-// of weight row wrow[r] (k = 8 hi), lfrag[c] at its chunk of LDS row lrow[c].
+// otherwise the roles swap.  wfrag[r] points at this lane's A fragment of
+// k-step 0 of weight block r in the fragment-order copy (the next k-step's
+// fragment lies 64 fragments on), lfrag[c] at its 8-element chunk of LDS row
+// lrow[c].
 template <int N, bool WA>
 __device__ __forceinline__ void cov_tile_gemm(gbf16x8* const (&wfrag)[CovShape<N>::RPW],
                                               const __bf16* const (&lfrag)[CovShape<N>::CPW], bool tile_ok,
@@ -90,12 +93,12 @@ __device__ __forceinline__ void cov_tile_gemm(gbf16x8* const (&wfrag)[CovShape<N
 #pragma unroll
   for (int ks = 0; ks < PF; ++ks)
 #pragma unroll
-    for (int r = 0; r < RPW; ++r) wf[ks][r] = wfrag[r][2 * ks];
+    for (int r = 0; r < RPW; ++r) wf[ks][r] = wfrag[r][64 * ks];
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks) {
     if (ks + PF < KS) {
 #pragma unroll
-      for (int r = 0; r < RPW; ++r) wf[ks + PF][r] = wfrag[r][2 * (ks + PF)];
+      for (int r = 0; r < RPW; ++r) wf[ks + PF][r] = wfrag[r][64 * (ks + PF)];
     }
     cbf16x8 lf[CPW];
 #pragma unroll
@@ -146,12 +149,11 @@ __device__ __forceinline__ void cov_relu_rule(float y, float var, float& a, floa
   g = g2 > 0.f ? sqrtf(g2) : 0.f;
 }
 
-// Start of the i-th 8-element chunk (i < N/16) that lane `part` of a thread
-// pair reads of an N-element row: for N a multiple of 128 the two lanes read
-// chunks 8 apart (128 bytes of bfloat16), else adjacent chunks.
-template <int N>
-__device__ __forceinline__ int cov_chunk(int i, int part) {
-  return N % 128 == 0 ? 8 * ((i & 7) + 16 * (i >> 3) + 8 * part) : 8 * (2 * i + part);
+// Sum over the 4 lanes of a quad (all four active), via DPP quad permutes.
+__device__ __forceinline__ float quad_sum(float x) {
+  x += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, false));  // lane ^ 1
+  x += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x4E, 0xF, 0xF, false));  // lane ^ 2
+  return x;
 }
 
 // All hidden layers have padded width N (the input layer is 3 wide).
@@ -177,6 +179,10 @@ __global__ __launch_bounds__(kCovThreads) void up_cov_bf16_kernel(int64_t C, int
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int l32 = lane & 31, hi = lane >> 5;
   constexpr int RPW = S::RPW, CPW = S::CPW, RG = S::RG, CG = S::CG;
+  // row passes: 16-row groups, a quad of lanes per row (lane q of row rq)
+  constexpr int NG = N / 16, GPW = (NG + 7) / 8;
+  static_assert(GPW <= 4, "one rule lane per group");
+  const int q = lane & 3, rq = lane >> 2;
   // this wave's tile: weight-row blocks rg*RPW.., LDS-row blocks cg*CPW..
   const int rg = wave % RG, cg = wave / RG;
   const bool tile = cg < CG;
@@ -210,14 +216,14 @@ __global__ __launch_bounds__(kCovThreads) void up_cov_bf16_kernel(int64_t C, int
   for (int h = 2; h <= Lh; ++h) {
     const DevLayer Lw = layers[h - 1];
     const bool last = h == Lh;
-    const __bf16* Wb = reinterpret_cast<const __bf16*>(Lw.Wbf);
+    const __bf16* Wb = reinterpret_cast<const __bf16*>(Lw.Wfr);
     gbf16x8* wfrag[RPW];
     bool wok[RPW];
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
       const int blk = rg * RPW + r;
       wok[r] = tile && blk < NB;
-      wfrag[r] = (gbf16x8*)(Wb + (int64_t)((wok[r] ? blk : 0) * 32 + l32) * N + 8 * hi);
+      wfrag[r] = (gbf16x8*)(Wb + ((int64_t)(wok[r] ? blk : 0) * KS * 64 + lane) * 8);
     }
     const __bf16* lfrag[CPW];
     bool lok[CPW];
@@ -231,47 +237,65 @@ __global__ __launch_bounds__(kCovThreads) void up_cov_bf16_kernel(int64_t C, int
     const float* s_zin = s_zbuf + (h - 1 & 1) * N;  // z of layer h-1
     float* s_zout = s_zbuf + (h & 1) * N;           // z of layer h
     if (h == 2) {
-      // 4. per neuron j (a thread pair), one pass over the float32 weight
-      //    row: y_j = W[j] z + b_j, P_j = W[j] G and the variance
+      // 4. per neuron j (a lane quad), one pass over the row-pass copy of its
+      //    weight row: y_j = W[j] z + b_j, P_j = W[j] G and the variance
       //    |P_j|^2 + sum_k W[j][k]^2 gamma_1k^2, then the ReLU rule
-      for (int j = t >> 1; j < N; j += kCovThreads / 2) {
-        const int part = t & 1;
-        gfloat* wrow = (gfloat*)Lw.W + (int64_t)j * N;
-        float yc = 0.f, p0 = 0.f, p1 = 0.f, p2 = 0.f, q = 0.f;
-#pragma unroll 2
-        for (int i = 0; i < N / 16; ++i) {
-          const int k = cov_chunk<N>(i, part);
-          const cv4f w0 = *reinterpret_cast<gfloat4*>(wrow + k);
-          const cv4f w1 = *reinterpret_cast<gfloat4*>(wrow + k + 4);
-          const float4 z0 = *reinterpret_cast<const float4*>(s_zin + k);
-          const float4 z1 = *reinterpret_cast<const float4*>(s_zin + k + 4);
-          yc += w0.x * z0.x + w0.y * z0.y + w0.z * z0.z + w0.w * z0.w + w1.x * z1.x + w1.y * z1.y + w1.z * z1.z +
-                w1.w * z1.w;
-          const float wv[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+      {
+        float r5[GPW][5];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const float4 g4 = s_G[k + u];
-            p0 += wv[u] * g4.x;
-            p1 += wv[u] * g4.y;
-            p2 += wv[u] * g4.z;
-            q += wv[u] * wv[u] * g4.w;
+        for (int gi = 0; gi < GPW; ++gi) {
+#pragma unroll
+          for (int u = 0; u < 5; ++u) r5[gi][u] = 0.f;
+          if (wave + 8 * gi < NG) {
+            const int j = 16 * (wave + 8 * gi) + rq;
+            gfloat* wv = (gfloat*)Lw.Wv + (int64_t)j * N + 8 * q;
+            float yc = 0.f, p0 = 0.f, p1 = 0.f, p2 = 0.f, qv = 0.f;
+#pragma unroll 2
+            for (int m = 0; m < N / 32; ++m) {
+              const int k = 8 * cov_row_chunk(N, q, m);
+              const cv4f w0 = *reinterpret_cast<gfloat4*>(wv + 32 * m);
+              const cv4f w1 = *reinterpret_cast<gfloat4*>(wv + 32 * m + 4);
+              const float4 z0 = *reinterpret_cast<const float4*>(s_zin + k);
+              const float4 z1 = *reinterpret_cast<const float4*>(s_zin + k + 4);
+              yc += w0.x * z0.x + w0.y * z0.y + w0.z * z0.z + w0.w * z0.w + w1.x * z1.x + w1.y * z1.y +
+                    w1.z * z1.z + w1.w * z1.w;
+              const float wk[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+#pragma unroll
+              for (int u = 0; u < 8; ++u) {
+                const float4 g4 = s_G[k + u];
+                p0 += wk[u] * g4.x;
+                p1 += wk[u] * g4.y;
+                p2 += wk[u] * g4.z;
+                qv += wk[u] * wk[u] * g4.w;
+              }
+            }
+            r5[gi][0] = quad_sum(yc);
+            r5[gi][1] = quad_sum(p0);
+            r5[gi][2] = quad_sum(p1);
+            r5[gi][3] = quad_sum(p2);
+            r5[gi][4] = quad_sum(qv);
           }
         }
-        yc += __shfl_xor(yc, 1);
-        p0 += __shfl_xor(p0, 1);
-        p1 += __shfl_xor(p1, 1);
-        p2 += __shfl_xor(p2, 1);
-        q += __shfl_xor(q, 1);
-        if (part == 0) {
+        // lane q of the quad applies the rule to the row of group q
+        int j = -1;
+        float sel[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int gi = 0; gi < GPW; ++gi)
+          if (q == gi && wave + 8 * gi < NG) {
+            j = 16 * (wave + 8 * gi) + rq;
+#pragma unroll
+            for (int u = 0; u < 5; ++u) sel[u] = r5[gi][u];
+          }
+        if (j >= 0) {
           float a, b, g;
-          const float y = yc + ((gfloat*)Lw.b)[j];
-          const float v = p0 * p0 + p1 * p1 + p2 * p2 + q;
+          const float y = sel[0] + ((gfloat*)Lw.b)[j];
+          const float v = sel[1] * sel[1] + sel[2] * sel[2] + sel[3] * sel[3] + sel[4];
           cov_relu_rule(y, v, a, b, g);
           s_var[j] = v;
           s_alpha[j] = a;
           s_zout[j] = a * y + b;
           s_gamma[j] = g;
-          s_P[j] = make_float4(p0, p1, p2, 0.f);
+          s_P[j] = make_float4(sel[1], sel[2], sel[3], 0.f);
           cov_store_vec(vh, C, N, cell, j, y, a, b, g);
         }
       }
@@ -325,29 +349,46 @@ __global__ __launch_bounds__(kCovThreads) void up_cov_bf16_kernel(int64_t C, int
       }
       __syncthreads();
 
-      // 4. per neuron j (a thread pair): the float32 centre y_j = W[j] z + b_j,
-      //    the variance C_h[j][j] = sum_k T[j][k] W[j][k], and the ReLU rule
-      for (int j = t >> 1; j < N; j += kCovThreads / 2) {
-        const int part = t & 1;
-        gfloat* wrow = (gfloat*)Lw.W + (int64_t)j * N;
-        const __bf16* trow = X + (size_t)j * STR;
-        float v = 0.f, yc = 0.f;
+      // 4. per neuron j (a lane quad), one pass over the row-pass copy of
+      //    its weight row: the float32 centre y_j = W[j] z + b_j, the
+      //    variance C_h[j][j] = sum_k T[j][k] W[j][k], and the ReLU rule
+      {
+        float r2[GPW][2];
+#pragma unroll
+        for (int gi = 0; gi < GPW; ++gi) {
+          r2[gi][0] = r2[gi][1] = 0.f;
+          if (wave + 8 * gi < NG) {
+            const int j = 16 * (wave + 8 * gi) + rq;
+            gfloat* wv = (gfloat*)Lw.Wv + (int64_t)j * N + 8 * q;
+            const __bf16* trow = X + (size_t)j * STR;
+            float v = 0.f, yc = 0.f;
 #pragma unroll 2
-        for (int i = 0; i < N / 16; ++i) {
-          const int k = cov_chunk<N>(i, part);
-          const cbf16x8 tv = *reinterpret_cast<const cbf16x8*>(trow + k);
-          const cv4f w0 = *reinterpret_cast<gfloat4*>(wrow + k);
-          const cv4f w1 = *reinterpret_cast<gfloat4*>(wrow + k + 4);
-          const float4 z0 = *reinterpret_cast<const float4*>(s_zin + k);
-          const float4 z1 = *reinterpret_cast<const float4*>(s_zin + k + 4);
-          v += w0.x * (float)tv[0] + w0.y * (float)tv[1] + w0.z * (float)tv[2] + w0.w * (float)tv[3] +
-               w1.x * (float)tv[4] + w1.y * (float)tv[5] + w1.z * (float)tv[6] + w1.w * (float)tv[7];
-          yc += w0.x * z0.x + w0.y * z0.y + w0.z * z0.z + w0.w * z0.w + w1.x * z1.x + w1.y * z1.y + w1.z * z1.z +
-                w1.w * z1.w;
+            for (int m = 0; m < N / 32; ++m) {
+              const int k = 8 * cov_row_chunk(N, q, m);
+              const cbf16x8 tv = *reinterpret_cast<const cbf16x8*>(trow + k);
+              const cv4f w0 = *reinterpret_cast<gfloat4*>(wv + 32 * m);
+              const cv4f w1 = *reinterpret_cast<gfloat4*>(wv + 32 * m + 4);
+              const float4 z0 = *reinterpret_cast<const float4*>(s_zin + k);
+              const float4 z1 = *reinterpret_cast<const float4*>(s_zin + k + 4);
+              v += w0.x * (float)tv[0] + w0.y * (float)tv[1] + w0.z * (float)tv[2] + w0.w * (float)tv[3] +
+                   w1.x * (float)tv[4] + w1.y * (float)tv[5] + w1.z * (float)tv[6] + w1.w * (float)tv[7];
+              yc += w0.x * z0.x + w0.y * z0.y + w0.z * z0.z + w0.w * z0.w + w1.x * z1.x + w1.y * z1.y +
+                    w1.z * z1.z + w1.w * z1.w;
+            }
+            r2[gi][0] = quad_sum(yc);
+            r2[gi][1] = quad_sum(v);
+          }
         }
-        v += __shfl_xor(v, 1);
-        yc += __shfl_xor(yc, 1);
-        if (part == 0) {
+        int j = -1;
+        float yc = 0.f, v = 0.f;
+#pragma unroll
+        for (int gi = 0; gi < GPW; ++gi)
+          if (q == gi && wave + 8 * gi < NG) {
+            j = 16 * (wave + 8 * gi) + rq;
+            yc = r2[gi][0];
+            v = r2[gi][1];
+          }
+        if (j >= 0) {
           float a, b, g;
           const float y = yc + ((gfloat*)Lw.b)[j];
           cov_relu_rule(y, v, a, b, g);
