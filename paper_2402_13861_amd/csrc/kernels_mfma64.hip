@@ -216,6 +216,8 @@ __global__ __launch_bounds__(512) void hidden_mfma_f64_kernel(
           for (int rs = 0; rs < 2; ++rs) a[rs] = As[kr * K::ASTR + wr * 32 + rs * 16 + l16];
 #pragma unroll
           for (int cs = 0; cs < 2 * K::NB; ++cs) {
+            // 16-column sub-tiles past the last real column are skipped
+            if (c0 + wc * 32 * K::NB + cs * 16 >= cols_in) continue;
             const double bv = Bs[kr * K::BSTR + wc * 32 * K::NB + cs * 16 + l16];
 #pragma unroll
             for (int rs = 0; rs < 2; ++rs)
@@ -336,7 +338,10 @@ hipError_t launch_hidden_mfma_f64(int method, int64_t C, int n_in, int n_out, in
                                   hipStream_t s) {
   if (C <= 0) return hipSuccess;
   if (n_out % 32 != 0 || n_in % 32 != 0 || n_in > ISX_MAX_WIDTH) return hipErrorInvalidValue;
-  const int bm = n_out % 128 == 0 ? 128 : (n_out % 64 == 0 ? 64 : 32);
+  // 64-row blocks run two workgroups per CU (the 128-row tile needs more
+  // registers than that allows); wider layers keep 128 so that each cell's
+  // coefficient block is streamed fewer times
+  const int bm = (n_out % 64 == 0 && n_out <= 256) ? 64 : (n_out % 128 == 0 ? 128 : (n_out % 64 == 0 ? 64 : 32));
 #define ISX_F64_ARGS C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, s
   if (method == ISX_UP) {
     if (bm == 128) launch64_bm<ISX_UP, 128>(ISX_F64_ARGS);
