@@ -17,9 +17,11 @@
 // statistic is a sum of magnitudes) and keeps the coefficient kernel.
 //
 // Layer 1: X_1 = G G^T + diag(gamma_1^2) with G = D_1 W_1 diag(h / sqrt 3)
-// (N x 3) has rank 3, so layer 2 needs no product for T: with P = W_2 G,
-// T = W_2 X_1 = P G^T + W_2 diag(gamma_1^2) is written element by element,
-// and the variances of layer 2 are |P_j|^2 + sum_k W_2[j][k]^2 gamma_1k^2.
+// (N x 3) has rank 3, so with P = W_2 G (N x 3),
+//   C_2 = W_2 X_1 W_2^T = P P^T + T' W_2^T,  T' = W_2 diag(gamma_1^2):
+// layer 2 writes T' element by element in its per-neuron pass (which also
+// gives P and the variances |P_j|^2 + sum_k W_2[j][k]^2 gamma_1k^2) and makes
+// one product, whose accumulators start from P_i . P_j.
 // Per layer h >= 3 (8 waves, 512 threads):
 //   2. T = W_h X_{h-1}: each wave computes a tile of RPW x CPW blocks of
 //      32 x 32, with A = bfloat16 fragments of its weight rows streamed from
@@ -237,51 +239,66 @@ __global__ __launch_bounds__(kCovThreads) void up_cov_bf16_kernel(int64_t C, int
     const float* s_zin = s_zbuf + (h - 1 & 1) * N;  // z of layer h-1
     float* s_zout = s_zbuf + (h & 1) * N;           // z of layer h
     if (h == 2) {
-      // 4. per neuron j (a lane quad), one pass over the row-pass copy of its
-      //    weight row: y_j = W[j] z + b_j, P_j = W[j] G and the variance
-      //    |P_j|^2 + sum_k W[j][k]^2 gamma_1k^2, then the ReLU rule
+      // 3./4. per neuron j (a lane quad), one pass over the row-pass copy of
+      //    its weight row, both row groups of the wave together (G and z
+      //    are read once for both): y_j = W[j] z + b_j, P_j = W[j] G, the
+      //    variance |P_j|^2 + sum_k W[j][k]^2 gamma_1k^2 and the ReLU rule,
+      //    and row j of T' = W diag(gamma_1^2) into LDS
       {
         float r5[GPW][5];
+        gfloat* wv[GPW];
+        bool gok[GPW];
 #pragma unroll
         for (int gi = 0; gi < GPW; ++gi) {
 #pragma unroll
           for (int u = 0; u < 5; ++u) r5[gi][u] = 0.f;
-          if (wave + 8 * gi < NG) {
-            const int j = 16 * (wave + 8 * gi) + rq;
-            gfloat* wv = (gfloat*)Lw.Wv + (int64_t)j * N + 8 * q;
-            float yc = 0.f, p0 = 0.f, p1 = 0.f, p2 = 0.f, qv = 0.f;
+          gok[gi] = wave + 8 * gi < NG;  // wave-uniform
+          const int j = 16 * (gok[gi] ? wave + 8 * gi : 0) + rq;
+          wv[gi] = (gfloat*)Lw.Wv + (int64_t)j * N + 8 * q;
+        }
 #pragma unroll 2
-            for (int m = 0; m < N / 32; ++m) {
-              const int k = 8 * cov_row_chunk(N, q, m);
-              const cv4f w0 = *reinterpret_cast<gfloat4*>(wv + 32 * m);
-              const cv4f w1 = *reinterpret_cast<gfloat4*>(wv + 32 * m + 4);
-              const float4 z0 = *reinterpret_cast<const float4*>(s_zin + k);
-              const float4 z1 = *reinterpret_cast<const float4*>(s_zin + k + 4);
-              yc += w0.x * z0.x + w0.y * z0.y + w0.z * z0.z + w0.w * z0.w + w1.x * z1.x + w1.y * z1.y +
-                    w1.z * z1.z + w1.w * z1.w;
-              const float wk[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+        for (int m = 0; m < N / 32; ++m) {
+          const int k = 8 * cov_row_chunk(N, q, m);
+          cv4f w0[GPW], w1[GPW];
 #pragma unroll
-              for (int u = 0; u < 8; ++u) {
-                const float4 g4 = s_G[k + u];
-                p0 += wk[u] * g4.x;
-                p1 += wk[u] * g4.y;
-                p2 += wk[u] * g4.z;
-                qv += wk[u] * wk[u] * g4.w;
-              }
+          for (int gi = 0; gi < GPW; ++gi) {
+            w0[gi] = *reinterpret_cast<gfloat4*>(wv[gi] + 32 * m);
+            w1[gi] = *reinterpret_cast<gfloat4*>(wv[gi] + 32 * m + 4);
+          }
+          const float4 z0 = *reinterpret_cast<const float4*>(s_zin + k);
+          const float4 z1 = *reinterpret_cast<const float4*>(s_zin + k + 4);
+          float4 g4[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) g4[u] = s_G[k + u];
+#pragma unroll
+          for (int gi = 0; gi < GPW; ++gi) {
+            if (!gok[gi]) continue;
+            const float wk[8] = {w0[gi].x, w0[gi].y, w0[gi].z, w0[gi].w, w1[gi].x, w1[gi].y, w1[gi].z, w1[gi].w};
+            r5[gi][0] += wk[0] * z0.x + wk[1] * z0.y + wk[2] * z0.z + wk[3] * z0.w + wk[4] * z1.x + wk[5] * z1.y +
+                         wk[6] * z1.z + wk[7] * z1.w;
+            cbf16x8 t8;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              r5[gi][1] += wk[u] * g4[u].x;
+              r5[gi][2] += wk[u] * g4[u].y;
+              r5[gi][3] += wk[u] * g4[u].z;
+              const float wg = wk[u] * g4[u].w;
+              r5[gi][4] += wk[u] * wg;
+              t8[u] = (__bf16)wg;
             }
-            r5[gi][0] = quad_sum(yc);
-            r5[gi][1] = quad_sum(p0);
-            r5[gi][2] = quad_sum(p1);
-            r5[gi][3] = quad_sum(p2);
-            r5[gi][4] = quad_sum(qv);
+            *reinterpret_cast<cbf16x8*>(X + (size_t)(16 * (wave + 8 * gi) + rq) * STR + k) = t8;
           }
         }
+#pragma unroll
+        for (int gi = 0; gi < GPW; ++gi)
+#pragma unroll
+          for (int u = 0; u < 5; ++u) r5[gi][u] = quad_sum(r5[gi][u]);
         // lane q of the quad applies the rule to the row of group q
         int j = -1;
         float sel[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int gi = 0; gi < GPW; ++gi)
-          if (q == gi && wave + 8 * gi < NG) {
+          if (q == gi && gok[gi]) {
             j = 16 * (wave + 8 * gi) + rq;
 #pragma unroll
             for (int u = 0; u < 5; ++u) sel[u] = r5[gi][u];
@@ -300,27 +317,6 @@ __global__ __launch_bounds__(kCovThreads) void up_cov_bf16_kernel(int64_t C, int
         }
       }
       if (last) break;
-      __syncthreads();
-      // 3. T = P G^T + W diag(gamma_1^2) -> LDS row-major; each thread keeps
-      //    one 8-column chunk of G and walks rows
-      constexpr int NCH = N / 8, TR = kCovThreads / NCH;
-      if (t < NCH * TR) {
-        const int k0 = 8 * (t % NCH);
-        float4 gk[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) gk[u] = s_G[k0 + u];
-        for (int i = t / NCH; i < N; i += TR) {
-          const float4 p = s_P[i];
-          gfloat* wrow = (gfloat*)Lw.W + (int64_t)i * N + k0;
-          const cv4f w0 = *reinterpret_cast<gfloat4*>(wrow);
-          const cv4f w1 = *reinterpret_cast<gfloat4*>(wrow + 4);
-          const float wv[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
-          cbf16x8 v8;
-#pragma unroll
-          for (int u = 0; u < 8; ++u) v8[u] = (__bf16)(p.x * gk[u].x + p.y * gk[u].y + p.z * gk[u].z + wv[u] * gk[u].w);
-          *reinterpret_cast<cbf16x8*>(X + (size_t)i * STR + k0) = v8;
-        }
-      }
       __syncthreads();
     } else {
       // 2. T = W X on the wave's tile (rows: weight blocks, columns: X blocks,
@@ -404,13 +400,24 @@ __global__ __launch_bounds__(kCovThreads) void up_cov_bf16_kernel(int64_t C, int
     vh += 4 * (int64_t)N * C;
     // 5. C_h on the wave's tile, C[i][j] = sum_k T[i][k] W[j][k] (rows i:
     //    T blocks from LDS, columns j: weight blocks)
+    //    (at layer 2 the accumulators start from the rank-3 part P_i . P_j)
     cv16f cacc[RPW][CPW];
 #pragma unroll
     for (int r = 0; r < RPW; ++r)
 #pragma unroll
-      for (int c = 0; c < CPW; ++c)
+      for (int c = 0; c < CPW; ++c) {
+        if (h == 2 && wok[r] && lok[c]) {
+          const float4 pj = s_P[(rg * RPW + r) * 32 + l32];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) cacc[r][c][e] = 0.f;
+          for (int e = 0; e < 16; ++e) {
+            const float4 pi = s_P[(cg * CPW + c) * 32 + 8 * (e >> 2) + 4 * hi + (e & 3)];
+            cacc[r][c][e] = pi.x * pj.x + pi.y * pj.y + pi.z * pj.z;
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < 16; ++e) cacc[r][c][e] = 0.f;
+        }
+      }
     cov_tile_gemm<N, false>(wfrag, lfrag, tile, cacc);
     __syncthreads();  // every wave has read T; the new slopes are in LDS
     // 6. X_h = D C D + diag(gamma^2); C is symmetric, so the tile's columns j
@@ -425,17 +432,17 @@ __global__ __launch_bounds__(kCovThreads) void up_cov_bf16_kernel(int64_t C, int
       for (int c = 0; c < CPW; ++c) {
         if (!lok[c]) continue;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int i0 = (cg * CPW + c) * 32 + 8 * q + 4 * hi;
+        for (int q4 = 0; q4 < 4; ++q4) {
+          const int i0 = (cg * CPW + c) * 32 + 8 * q4 + 4 * hi;
           // keep the slope loads next to their use (hoisting them all would
           // cost registers)
           __asm__ volatile("" ::: "memory");
           const float4 ai = *reinterpret_cast<const float4*>(s_alpha + i0);
           __bf16 v4[4];
-          v4[0] = (__bf16)(ai.x * aj * cacc[r][c][4 * q + 0]);
-          v4[1] = (__bf16)(ai.y * aj * cacc[r][c][4 * q + 1]);
-          v4[2] = (__bf16)(ai.z * aj * cacc[r][c][4 * q + 2]);
-          v4[3] = (__bf16)(ai.w * aj * cacc[r][c][4 * q + 3]);
+          v4[0] = (__bf16)(ai.x * aj * cacc[r][c][4 * q4 + 0]);
+          v4[1] = (__bf16)(ai.y * aj * cacc[r][c][4 * q4 + 1]);
+          v4[2] = (__bf16)(ai.z * aj * cacc[r][c][4 * q4 + 2]);
+          v4[3] = (__bf16)(ai.w * aj * cacc[r][c][4 * q4 + 3]);
           *reinterpret_cast<uint2*>(X + (size_t)j * STR + i0) = *reinterpret_cast<const uint2*>(v4);
         }
         if (cg * CPW + c == rg * RPW + r && ((l32 >> 2) & 1) == hi)

@@ -341,6 +341,9 @@ BF16_WIDTHS = [
     [3, 96, 160, 1],  # widths that are multiples of 32 but not of 64/128 (coefficient form only)
     [3, 96, 96, 96, 1],
     [3, 40, 40, 40, 1],  # padded to 64
+    [3, 64, 64, 1],  # one hidden product (layer 2 is the last hidden layer)
+    [3, 32, 32, 32, 32, 32, 32, 32, 1],  # deep and narrow
+    [3, 224, 224, 224, 1],  # two row groups per wave, width not a multiple of 128
 ]
 
 
