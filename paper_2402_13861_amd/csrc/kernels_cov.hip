@@ -400,24 +400,40 @@ __global__ __launch_bounds__(kCovThreads) void up_cov_bf16_kernel(int64_t C, int
     vh += 4 * (int64_t)N * C;
     // 5. C_h on the wave's tile, C[i][j] = sum_k T[i][k] W[j][k] (rows i:
     //    T blocks from LDS, columns j: weight blocks)
-    //    (at layer 2 the accumulators start from the rank-3 part P_i . P_j)
+    //    (at layer 2 the accumulators start from the rank-3 part P_i . P_j:
+    //    two float32 products with k = 2, over P's components (0, 1) and
+    //    (2, 3), the fourth being zero)
     cv16f cacc[RPW][CPW];
 #pragma unroll
     for (int r = 0; r < RPW; ++r)
 #pragma unroll
+      for (int c = 0; c < CPW; ++c)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) cacc[r][c][e] = 0.f;
+    if (h == 2) {
+      float pa[CPW][2], pb[RPW][2];
+#pragma unroll
       for (int c = 0; c < CPW; ++c) {
-        if (h == 2 && wok[r] && lok[c]) {
-          const float4 pj = s_P[(rg * RPW + r) * 32 + l32];
-#pragma unroll
-          for (int e = 0; e < 16; ++e) {
-            const float4 pi = s_P[(cg * CPW + c) * 32 + 8 * (e >> 2) + 4 * hi + (e & 3)];
-            cacc[r][c][e] = pi.x * pj.x + pi.y * pj.y + pi.z * pj.z;
-          }
-        } else {
-#pragma unroll
-          for (int e = 0; e < 16; ++e) cacc[r][c][e] = 0.f;
-        }
+        const float4 p = s_P[(lok[c] ? cg * CPW + c : 0) * 32 + l32];
+        pa[c][0] = hi ? p.y : p.x;
+        pa[c][1] = hi ? p.w : p.z;
       }
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) {
+        const float4 p = s_P[(wok[r] ? rg * RPW + r : 0) * 32 + l32];
+        pb[r][0] = hi ? p.y : p.x;
+        pb[r][1] = hi ? p.w : p.z;
+      }
+      if (tile) {
+#pragma unroll
+        for (int r = 0; r < RPW; ++r)
+#pragma unroll
+          for (int c = 0; c < CPW; ++c) {
+            cacc[r][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(pa[c][0], pb[r][0], cacc[r][c], 0, 0, 0);
+            cacc[r][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(pa[c][1], pb[r][1], cacc[r][c], 0, 0, 0);
+          }
+      }
+    }
     cov_tile_gemm<N, false>(wfrag, lfrag, tile, cacc);
     __syncthreads();  // every wave has read T; the new slopes are in LDS
     // 6. X_h = D C D + diag(gamma^2); C is symmetric, so the tile's columns j
@@ -431,13 +447,17 @@ __global__ __launch_bounds__(kCovThreads) void up_cov_bf16_kernel(int64_t C, int
 #pragma unroll
       for (int c = 0; c < CPW; ++c) {
         if (!lok[c]) continue;
+        // the block's 16 slopes in one round trip (kept next to their use:
+        // hoisting every block's would cost registers)
+        __asm__ volatile("" ::: "memory");
+        float4 ab[4];
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4)
+          ab[q4] = *reinterpret_cast<const float4*>(s_alpha + (cg * CPW + c) * 32 + 8 * q4 + 4 * hi);
 #pragma unroll
         for (int q4 = 0; q4 < 4; ++q4) {
           const int i0 = (cg * CPW + c) * 32 + 8 * q4 + 4 * hi;
-          // keep the slope loads next to their use (hoisting them all would
-          // cost registers)
-          __asm__ volatile("" ::: "memory");
-          const float4 ai = *reinterpret_cast<const float4*>(s_alpha + i0);
+          const float4 ai = ab[q4];
           __bf16 v4[4];
           v4[0] = (__bf16)(ai.x * aj * cacc[r][c][4 * q4 + 0]);
           v4[1] = (__bf16)(ai.y * aj * cacc[r][c][4 * q4 + 1]);
