@@ -284,9 +284,14 @@ typedef enum {
   ISX_SCRATCH_BYTES = 4,   /* bytes of propagation scratch per batch (default 16 GiB) */
   ISX_VERBOSE = 5,         /* value 1: isx_extract prints one line per octree level to stderr */
   ISX_BF16_VARIANT = 6,    /* bf16 hidden-layer tile shape: 0 = default for the width, 1..4 = forced */
-  ISX_UP_FORM = 7          /* bf16 uncertainty propagation: 0 = covariance form (exact alternative to
+  ISX_UP_FORM = 7,         /* bf16 uncertainty propagation: 0 = covariance form (exact alternative to
                               coefficient tracking: C_h = W_h (D C_{h-1} D + diag(gamma^2)) W_h^T, one
                               fused launch per batch, hidden widths <= 256), 1 = coefficient form */
+  ISX_LIN_PRECISION = 8    /* centre linearisation (isx_linearize and the surrogate's base): 1 (default)
+                              = bfloat16 MFMA with every column carried as two bfloat16 parts and three
+                              bfloat16 products per layer (f within ~3e-4 of max(|f|, output scale), s
+                              within ~2e-3 relative; used when every hidden layer has the same width
+                              <= 256, else float32), 0 = float32 MFMA */
 } isx_option;
 isx_status isx_set_option(isx_ctx* ctx, isx_option option, int64_t value);
 
@@ -298,8 +303,9 @@ typedef enum {
   ISX_KERNEL_HIDDEN_FP64 = 3,      /* hidden-layer product, float64 (re-check band, ISX_FP64) */
   ISX_KERNEL_DENSE = 4,            /* dense forward passes (corner evaluation, linearisation) */
   ISX_KERNEL_OUTPUT = 5,           /* output read-off (spread of the last layer) */
-  ISX_KERNEL_HIDDEN_COV_BF16 = 6   /* every hidden layer of uncertainty propagation in covariance form,
+  ISX_KERNEL_HIDDEN_COV_BF16 = 6,  /* every hidden layer of uncertainty propagation in covariance form,
                                       BF16 MFMA (ISX_UP_FORM 0) */
+  ISX_KERNEL_LINEARIZE = 7         /* centre linearisation (isx_linearize, the surrogate's base) */
 } isx_kernel_kind;
 
 /* Accumulated statistics of one kernel kind since the last reset (ISX_PROFILE

@@ -21,10 +21,10 @@ import numpy as np
 
 from . import _lib
 from ._lib import (AA, BF16, BF16_VARIANT, FP32, FP64, HIDDEN_KERNEL, KEEP_LEVELS, PROFILE, SCRATCH_BYTES, UP,
-                   UP_FORM, VERBOSE)
+                   UP_FORM, LIN_PRECISION, VERBOSE)
 
 KERNEL_KINDS = ("hidden_fp32", "hidden_bf16", "hidden_simt_fp32", "hidden_fp64", "dense", "output",
-                "hidden_cov_bf16")
+                "hidden_cov_bf16", "linearize")
 
 __all__ = ["Context", "Mesh", "IsxError", "AA", "UP", "FP32", "BF16", "FP64", "KEEP_LEVELS", "HIDDEN_KERNEL",
            "PROFILE", "SCRATCH_BYTES", "VERBOSE", "BF16_VARIANT", "mc_case_table"]

@@ -50,6 +50,7 @@ struct isx_ctx {
   int kernel_choice = 0;
   int bf16_variant = 0;
   int up_form = 0;
+  int lin_prec = 1;  // centre linearisation: 1 = bf16 split where supported, 0 = float32
   size_t prop_budget = size_t(16) << 30;  // bytes of propagation scratch per chunk
   // propagation scratch
   Buf F32[2], vec32, F64[2], vec64, Fbf[2];
@@ -131,7 +132,7 @@ void free_model_table(Model& m) {
 }
 
 void free_layer(Layer& l) {
-  void* ps[] = {l.W, l.Wt, l.b, l.Wd, l.Wtd, l.bd, l.Wtbf, l.Wbf, l.Wfr, l.Wv};
+  void* ps[] = {l.W, l.Wt, l.b, l.Wd, l.Wtd, l.bd, l.Wtbf, l.Wbf, l.Wfr, l.Wfrl, l.Wv};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   l = Layer{};
@@ -334,6 +335,10 @@ isx_status isx_set_option(isx_ctx* ctx, isx_option option, int64_t value) {
       if (value < 0 || value > 1) return fail(ctx, ISX_EINVAL, "ISX_UP_FORM must be 0 or 1");
       ctx->up_form = (int)value;
       return ISX_OK;
+    case ISX_LIN_PRECISION:
+      if (value < 0 || value > 1) return fail(ctx, ISX_EINVAL, "ISX_LIN_PRECISION must be 0 or 1");
+      ctx->lin_prec = (int)value;
+      return ISX_OK;
     case ISX_BF16_VARIANT:
       if (value < 0 || value > 4) return fail(ctx, ISX_EINVAL, "ISX_BF16_VARIANT must be in [0, 4]");
       ctx->bf16_variant = (int)value;
@@ -427,16 +432,24 @@ isx_status isx_load_mlp(isx_ctx* ctx, int32_t n_linear, const int32_t* widths, c
     if (e == hipSuccess && l >= 1 && l + 1 < n_linear && ni == no && no <= kCovNMax) {
       // copies in the covariance kernel's access orders
       const int N = no;
-      std::vector<uint16_t> Wfr((size_t)N * N);
+      std::vector<uint16_t> Wfr((size_t)N * N), Wfrl((size_t)N * N);
       std::vector<float> Wv((size_t)N * N);
       for (int r = 0; r < N; ++r)
-        for (int k = 0; k < N; ++k) Wfr[cov_frag_index(N, r, k)] = Wbf[(size_t)r * N + k];
+        for (int k = 0; k < N; ++k) {
+          const uint16_t hb = Wbf[(size_t)r * N + k];
+          uint32_t hu = (uint32_t)hb << 16;
+          float hf;
+          std::memcpy(&hf, &hu, 4);
+          Wfr[cov_frag_index(N, r, k)] = hb;
+          Wfrl[cov_frag_index(N, r, k)] = f32_to_bf16_bits(W[(size_t)r * N + k] - hf);
+        }
       for (int r = 0; r < N; ++r)
         for (int m = 0; m < N / 32; ++m)
           for (int q = 0; q < 4; ++q)
             for (int x = 0; x < 8; ++x)
               Wv[cov_row_pos(N, r, q, m, x)] = W[(size_t)r * N + 8 * cov_row_chunk(N, q, m) + x];
       e = upload(&L.Wfr, Wfr);
+      if (e == hipSuccess) e = upload(&L.Wfrl, Wfrl);
       if (e == hipSuccess) e = upload(&L.Wv, Wv);
     }
     if (e != hipSuccess) {
@@ -447,7 +460,8 @@ isx_status isx_load_mlp(isx_ctx* ctx, int32_t n_linear, const int32_t* widths, c
   {
     std::vector<DevLayer> table(n_linear);
     for (int l = 0; l < n_linear; ++l)
-      table[l] = DevLayer{m.L[l].W, m.L[l].Wbf, m.L[l].Wfr, m.L[l].Wv, m.L[l].b, m.L[l].n_in, m.L[l].n_out};
+      table[l] = DevLayer{m.L[l].W,   m.L[l].Wbf, m.L[l].Wfr,  m.L[l].Wfrl,
+                          m.L[l].Wv,  m.L[l].b,   m.L[l].n_in, m.L[l].n_out};
     hipError_t e = upload(&m.dev_layers, table);
     if (e != hipSuccess) {
       for (int k = 0; k < n_linear; ++k) free_layer(m.L[k]);
@@ -564,6 +578,22 @@ isx_status isx_eval_points(isx_ctx* ctx, int32_t mlp_id, isx_precision precision
   return ISX_OK;
 }
 
+// Centre linearisation of n cells: bf16 split where the option and the
+// widths allow, else float32; timed as ISX_KERNEL_LINEARIZE.
+static hipError_t linearize_cells(isx_ctx* ctx, const Model& m, int64_t n, const float* centres,
+                                  const float* halves, float* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const bool bf = ctx->lin_prec == 1 && lin_bf16_supported(m);
+  double f = 0.0;
+  for (int h = 2; h < m.n_linear; ++h) f += 2.0 * m.widths[h] * m.widths[h - 1];
+  f *= bf ? 6.0 : 4.0;  // bf16: three centre products and three tangents; float32: four columns
+  Profiler::Rec rec{};
+  const bool prof = ctx->prof.begin(rec, ISX_KERNEL_LINEARIZE, f * (double)n, 32.0 * n, s);
+  hipError_t e = bf ? linearize_bf16(m, n, centres, halves, out, s) : linearize_mfma(m, n, centres, halves, out, s);
+  if (prof) ctx->prof.end(rec, s);
+  return e;
+}
+
 isx_status isx_linearize(isx_ctx* ctx, int32_t mlp_id, int64_t n, const float* d_centres, const float* d_halves,
                          float* d_out) {
   Model* m = get_model(ctx, mlp_id);
@@ -571,7 +601,7 @@ isx_status isx_linearize(isx_ctx* ctx, int32_t mlp_id, int64_t n, const float* d
   if (n < 0 || (n > 0 && (!d_centres || !d_halves || !d_out))) return fail(ctx, ISX_EINVAL, "bad arguments");
   if (n == 0) return ISX_OK;
   (void)hipSetDevice(ctx->device);
-  HIPCHK(linearize_mfma(*m, n, d_centres, d_halves, d_out, ctx->stream));
+  HIPCHK(linearize_cells(ctx, *m, n, d_centres, d_halves, d_out, ctx->stream));
   return ISX_OK;
 }
 
@@ -651,7 +681,7 @@ static isx_status sur_predict_n(isx_ctx* ctx, Sur& S, int64_t n, const float* ce
       HIPCHK(sur_gemm(B, S.w[l + 1], S.w[l], (const float*)ctx->sur_act[l].p, S.w[l], false, S.W[l], S.w[l], true, C,
                       S.w[l + 1], S.b[l], l + 1 < S.L, nullptr, 0, s));
     }
-    if (base) HIPCHK(linearize_mfma(*base, B, centres + 3 * r0, halves + 3 * r0, (float*)ctx->sp_base.p, s));
+    if (base) HIPCHK(linearize_cells(ctx, *base, B, centres + 3 * r0, halves + 3 * r0, (float*)ctx->sp_base.p, s));
     HIPCHK(sur_unstd(B, (const float*)ctx->sur_out.p, S.mu_bar, S.scale, base ? (const float*)ctx->sp_base.p : nullptr,
                      S.s_floor, out + 2 * r0, sb_out ? sb_out + r0 : nullptr, s));
   }
@@ -1063,7 +1093,7 @@ static isx_status sur_train_base(isx_ctx* ctx, const Sur& S, int64_t n, const fl
   const Model* base = get_model(ctx, S.base_mlp);
   if (!base) return fail(ctx, ISX_EINVAL, "the surrogate's base MLP was unloaded");
   HIPCHK(ensure(ctx->sur_base, (size_t)n * 8));
-  HIPCHK(linearize_mfma(*base, n, d_centres, d_halves, (float*)ctx->sur_base.p, ctx->stream));
+  HIPCHK(linearize_cells(ctx, *base, n, d_centres, d_halves, (float*)ctx->sur_base.p, ctx->stream));
   *d_base = (const float*)ctx->sur_base.p;
   return ISX_OK;
 }

@@ -34,6 +34,7 @@ struct Layer {
   uint16_t* Wbf = nullptr;  // bfloat16 bits of W, [n_out][n_in]
   // square hidden layers of width <= kCovNMax only (else null):
   uint16_t* Wfr = nullptr;  // bfloat16 bits of W in MFMA fragment order (cov_frag_index)
+  uint16_t* Wfrl = nullptr; // bfloat16 bits of W - bf16(W), same order
   float* Wv = nullptr;      // W with each row's chunks in row-pass order (cov_row_pos)
 };
 
@@ -72,6 +73,7 @@ struct DevLayer {
   const float* W;         // [n_out][n_in]
   const uint16_t* Wbf;    // bfloat16 bits of W, [n_out][n_in]
   const uint16_t* Wfr;    // fragment order (square layers <= kCovNMax, else null)
+  const uint16_t* Wfrl;   // W - bf16(W) in fragment order (same layers)
   const float* Wv;        // row-pass order (square layers <= kCovNMax, else null)
   const float* b;         // [n_out]
   int n_in, n_out;        // padded widths
@@ -243,6 +245,9 @@ hipError_t eval_points_f64(const Model& m, int64_t n, const float* pts, float* v
 // ---- dense FP32-MFMA forward passes (kernels_dense.hip) ----
 hipError_t eval_points_mfma(const Model& m, int64_t n, const float* pts, float* vals, hipStream_t s);
 // (f(c), |J(c) diag(h)| / sqrt(3)) per cell, out [n][2]
+bool lin_bf16_supported(const Model& m);
+hipError_t linearize_bf16(const Model& m, int64_t n, const float* centres, const float* halves, float* out,
+                          hipStream_t s);
 hipError_t linearize_mfma(const Model& m, int64_t n, const float* centres, const float* halves, float* out,
                           hipStream_t s);
 // output read-off of C cells from the hidden layers' Y, A, B, G vectors

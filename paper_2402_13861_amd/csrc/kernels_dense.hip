@@ -492,4 +492,200 @@ hipError_t launch_output_mfma(const Model& m, isx_method method, int64_t C, floa
             : launch_output_k<ISX_AA, 1024>(C, net, halves, out, s);
 }
 
+// ------------------------------------------ centre linearisation in BF16
+// The same (f(c), s) as DENSE_LIN for nets whose hidden layers all have one
+// padded width N <= kCovNMax, on BF16 MFMA (v_mfma_f32_32x32x16_bf16):
+//   * every column (the centre and the three tangents) is carried as two
+//     bfloat16 parts, x = xh + xl (xl = bf16(x - xh)), and each layer's
+//     product is Wh xh + Wh xl + Wl xh with W = Wh + Wl (both bfloat16); the
+//     dropped term Wl xl and the splits leave a relative error near 2^-16 per
+//     layer, the level of a float32 dot product of this length (three
+//     bfloat16 products cost about a fifth of one float32 product).
+// A workgroup owns 32 cells.  In LDS: X[col][cell][2N] = (xh | xl) for
+// col = 0 (centre) and 1..3 (tangents), rows padded by 8 bfloat16 (16 bytes).
+// Wave w owns weight row block w (32 neurons) and its four column tiles, so
+// each pair of weight fragments (Wh, Wl) serves twelve products.
+namespace {
+typedef __bf16 lbf16x8 __attribute__((ext_vector_type(8)));
+typedef __attribute__((address_space(1))) const lbf16x8 glbf16x8;
+typedef float lv16f __attribute__((ext_vector_type(16)));
+constexpr int kLinCells = 32;
+
+template <int N>
+struct LinShape {
+  static constexpr int STR = 2 * N + 8;  // row stride (bfloat16): xh | xl | pad
+  static constexpr int KS = N / 16;
+  static constexpr int RB = N / 32;
+  static constexpr size_t LDS = (size_t)4 * kLinCells * STR * 2;
+};
+}  // namespace
+
+template <int N>
+__global__ __launch_bounds__(kDenseThreads) void lin_bf16_kernel(int64_t n_items, int n_linear,
+                                                                 const DevLayer* __restrict__ layers,
+                                                                 const float* __restrict__ centres,
+                                                                 const float* __restrict__ halves,
+                                                                 float* __restrict__ out) {
+  using S = LinShape<N>;
+  constexpr int STR = S::STR, KS = S::KS;
+  extern __shared__ float4 lin_smem4[];
+  __bf16* X = reinterpret_cast<__bf16*>(lin_smem4);  // [4][kLinCells][STR]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l32 = lane & 31, hi = lane >> 5;
+  const int64_t item0 = (int64_t)blockIdx.x * kLinCells;
+  auto row = [&](int col, int cell) { return X + (size_t)(col * kLinCells + cell) * STR; };
+
+  // ---- layer 1 (3 -> N) on the vector ALUs
+  {
+    const DevLayer L1 = layers[0];
+    for (int e = tid; e < kLinCells * N; e += kDenseThreads) {
+      const int cell = e / N, j = e - cell * N;
+      const int64_t item = item0 + cell;
+      float v[4] = {0.f, 0.f, 0.f, 0.f};
+      if (item < n_items) {
+        const float w0 = L1.W[j * 3 + 0], w1 = L1.W[j * 3 + 1], w2 = L1.W[j * 3 + 2];
+        const float* c = centres + item * 3;
+        const float pre = L1.b[j] + w0 * c[0] + w1 * c[1] + w2 * c[2];
+        if (pre > 0.f) {
+          const float* h = halves + item * 3;
+          v[0] = pre;
+          v[1] = w0 * h[0] * 0.57735026918962576451f;
+          v[2] = w1 * h[1] * 0.57735026918962576451f;
+          v[3] = w2 * h[2] * 0.57735026918962576451f;
+        }
+      }
+#pragma unroll
+      for (int col = 0; col < 4; ++col) {
+        const __bf16 xh = (__bf16)v[col];
+        row(col, cell)[j] = xh;
+        row(col, cell)[N + j] = (__bf16)(v[col] - (float)xh);
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- hidden layers 2 .. n_linear-1
+  for (int l = 1; l + 1 < n_linear; ++l) {
+    const DevLayer Lw = layers[l];
+    const bool active = wave < S::RB;  // wave-uniform
+    const int rb = active ? wave : 0;
+    glbf16x8* ah = (glbf16x8*)(reinterpret_cast<const __bf16*>(Lw.Wfr) + ((int64_t)rb * KS * 64 + lane) * 8);
+    glbf16x8* al = (glbf16x8*)(reinterpret_cast<const __bf16*>(Lw.Wfrl) + ((int64_t)rb * KS * 64 + lane) * 8);
+    lv16f acc[4];
+#pragma unroll
+    for (int col = 0; col < 4; ++col)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[col][r] = 0.f;
+    if (active) {
+      lbf16x8 a_next = ah[0], l_next = al[0];
+      for (int ks = 0; ks < KS; ++ks) {
+        const lbf16x8 a = a_next, lo = l_next;
+        if (ks + 1 < KS) {
+          a_next = ah[64 * (ks + 1)];
+          l_next = al[64 * (ks + 1)];
+        }
+#pragma unroll
+        for (int col = 0; col < 4; ++col) {
+          const __bf16* b = row(col, l32) + 8 * hi + 16 * ks;  // this lane's cell, k = 8 hi
+          const lbf16x8 xh = *reinterpret_cast<const lbf16x8*>(b);
+          const lbf16x8 xl = *reinterpret_cast<const lbf16x8*>(b + N);
+          acc[col] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, xh, acc[col], 0, 0, 0);
+          acc[col] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, xl, acc[col], 0, 0, 0);
+          acc[col] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo, xh, acc[col], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();  // every wave has read the layer input
+    // register r of acc[col] holds (neuron 32 rb + 8(r/4) + 4 hi + r%4, cell
+    // l32); the tangents take the ReLU mask of the centre's pre-activation
+    if (active) {
+#pragma unroll
+      for (int q4 = 0; q4 < 4; ++q4) {
+        const int i0 = rb * 32 + 8 * q4 + 4 * hi;
+        bool on[4];
+#pragma unroll
+        for (int col = 0; col < 4; ++col) {
+          __bf16 vh[4], vl[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            float x = acc[col][4 * q4 + u];
+            if (col == 0) {
+              x += Lw.b[i0 + u];
+              on[u] = x > 0.f;
+            }
+            x = on[u] ? x : 0.f;
+            vh[u] = (__bf16)x;
+            vl[u] = (__bf16)(x - (float)vh[u]);
+          }
+          *reinterpret_cast<uint2*>(row(col, l32) + i0) = *reinterpret_cast<const uint2*>(vh);
+          *reinterpret_cast<uint2*>(row(col, l32) + N + i0) = *reinterpret_cast<const uint2*>(vl);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- output layer (N -> 1): per cell the value and the three directional
+  // derivatives, each a float32 dot product by 4 threads in a fixed order
+  {
+    const DevLayer Lo = layers[n_linear - 1];
+    const int dot = tid >> 2, part = tid & 3;  // 128 dots: (cell, column)
+    const int cell = dot >> 2, col = dot & 3;
+    const __bf16* x = row(col, cell);
+    float s = 0.f;
+    for (int k = part; k < N; k += 4) s += Lo.W[k] * ((float)x[k] + (float)x[N + k]);
+    s += __shfl_xor(s, 1);
+    s += __shfl_xor(s, 2);
+    // the cell's four sums sit in lanes 16c', 16c'+4, 16c'+8, 16c'+12 of the wave
+    const int base = lane & ~15;
+    const float f = __shfl(s, base), d1 = __shfl(s, base + 4), d2 = __shfl(s, base + 8),
+                d3 = __shfl(s, base + 12);
+    const int64_t item = item0 + cell;
+    if ((tid & 15) == 0 && item < n_items) {
+      out[item * 2 + 0] = f + Lo.b[0];
+      out[item * 2 + 1] = sqrtf(d1 * d1 + d2 * d2 + d3 * d3);
+    }
+  }
+}
+
+template <int N>
+static hipError_t launch_lin_n(const Model& m, int64_t n, const float* centres, const float* halves, float* out,
+                               hipStream_t s) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&lin_bf16_kernel<N>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)LinShape<N>::LDS);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  const int64_t blocks = (n + kLinCells - 1) / kLinCells;
+  hipLaunchKernelGGL((lin_bf16_kernel<N>), dim3((unsigned)blocks), dim3(kDenseThreads), LinShape<N>::LDS, s, n,
+                     m.n_linear, m.dev_layers, centres, halves, out);
+  return hipGetLastError();
+}
+
+bool lin_bf16_supported(const Model& m) {
+  if (m.n_linear < 3 || !cov_supported(m)) return false;
+  for (int l = 1; l + 1 < m.n_linear; ++l)
+    if (!m.L[l].Wfr || !m.L[l].Wfrl) return false;
+  return true;
+}
+
+hipError_t linearize_bf16(const Model& m, int64_t n, const float* centres, const float* halves, float* out,
+                          hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (!lin_bf16_supported(m)) return hipErrorNotSupported;
+  switch (m.pw[1]) {
+    case 32: return launch_lin_n<32>(m, n, centres, halves, out, s);
+    case 64: return launch_lin_n<64>(m, n, centres, halves, out, s);
+    case 96: return launch_lin_n<96>(m, n, centres, halves, out, s);
+    case 128: return launch_lin_n<128>(m, n, centres, halves, out, s);
+    case 160: return launch_lin_n<160>(m, n, centres, halves, out, s);
+    case 192: return launch_lin_n<192>(m, n, centres, halves, out, s);
+    case 224: return launch_lin_n<224>(m, n, centres, halves, out, s);
+    case 256: return launch_lin_n<256>(m, n, centres, halves, out, s);
+    default: return hipErrorNotSupported;
+  }
+}
+
 }  // namespace isx

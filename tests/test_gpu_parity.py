@@ -164,7 +164,12 @@ DENSE_WIDTHS = WIDTHS + [
 @pytest.mark.parametrize("widths", DENSE_WIDTHS, ids=lambda w: "x".join(map(str, w)))
 def test_dense_eval_and_linearize_match_oracle(ctx, widths):
     """FP32-MFMA point evaluation and centre linearisation against the
-    float64 oracle, on ragged batch sizes; the SIMT evaluation agrees too."""
+    float64 oracle, on ragged batch sizes; the SIMT evaluation agrees too.
+    The BF16 linearisation (every column carried as two bfloat16 parts, three
+    bfloat16 products per layer: relative rounding near 2^-17 per product) is
+    held to 3e-4 of max(|f|, S) on f (about 1.3e-4 at worst on 4133 cells of
+    the 3->256x5->1 net, a hundredth of a depth-9 cell's sigma) and 2e-3 on
+    s."""
     import paper_2402_13861_amd as isx
     from oracle.linearize import linearize
 
@@ -185,19 +190,22 @@ def test_dense_eval_and_linearize_match_oracle(ctx, widths):
             ctx.set_option(isx.HIDDEN_KERNEL, 0)
             c, h, _ = random_boxes(n, range(0, 10), seed=n + 1)
             f, s, margin = linearize(mlp, c.astype(np.float64), h.astype(np.float64), return_margin=True)
-            out = torch.full((n, 2), float("nan"), dtype=torch.float32, device="cuda")
-            ctx.linearize(mid, _dev(c), _dev(h), out)
-            torch.cuda.synchronize()
-            g = out.cpu().numpy().astype(np.float64)
-            ef = np.abs(g[:, 0] - f) / np.maximum(np.abs(f), S)
-            es = np.abs(g[:, 1] - s) / np.maximum(s, 1e-3 * S)
-            # a centre within float32 rounding of a kink may take the other side
-            ok = margin > 1e-4
-            print(f"n={n}: eval ok; linearise max rel err f {ef.max():.3e} s {es[ok].max() if ok.any() else 0:.3e} "
-                  f"({(~ok).sum()} cells near a kink)", flush=True)
-            assert ef.max() <= 1e-5
-            assert (es[ok] <= 1e-4).all()
+            for prec, tol_f, tol_s in ((0, 1e-5, 1e-4), (1, 3e-4, 2e-3)):
+                ctx.set_option(isx.LIN_PRECISION, prec)
+                out = torch.full((n, 2), float("nan"), dtype=torch.float32, device="cuda")
+                ctx.linearize(mid, _dev(c), _dev(h), out)
+                torch.cuda.synchronize()
+                g = out.cpu().numpy().astype(np.float64)
+                ef = np.abs(g[:, 0] - f) / np.maximum(np.abs(f), S)
+                es = np.abs(g[:, 1] - s) / np.maximum(s, 1e-3 * S)
+                # a centre within rounding of a kink may take the other side
+                ok = margin > 1e-4
+                print(f"n={n} lin precision {prec}: max rel err f {ef.max():.3e} "
+                      f"s {es[ok].max() if ok.any() else 0:.3e} ({(~ok).sum()} cells near a kink)", flush=True)
+                assert ef.max() <= tol_f
+                assert (es[ok] <= tol_s).all()
     finally:
+        ctx.set_option(isx.LIN_PRECISION, 1)
         ctx.set_option(isx.HIDDEN_KERNEL, 0)
         ctx.unload_mlp(mid)
 
