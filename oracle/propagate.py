@@ -21,6 +21,23 @@ Z_i zero-mean, unit-variance, independent).
 
 Both return (centre, spread): AA (x0, r), UP (mu, sigma), so that the bound
 is centre -/+ k * spread with k = 1 for AA and k = t for UP.
+
+Rounding margin for AA (``margin=True``; the paper assumes exact arithmetic,
+this is the reading that keeps float bounds sound).  A linear layer computed
+in floating point with unit roundoff u (and operands rounded with u_b) lands
+within m_j = c (sum_k |W_jk| (rho_k + |x0_k|) + |b_j|) of the exact form,
+with c = 2 u_b + u_b^2 + g_{K+1} (1 + u_b)^2 and g_n = n u / (1 - n u)
+(K = layer input width, rho_k = sum_i |F_ki|).  That error is one more
+independent symbol per neuron:
+* the radius entering the ReLU rule is r_j (1 + 2 g_D) + m_j (the first
+  factor covers the rounding of the D-term sum r_j itself);
+* after the rule the error symbol is scaled by alpha_j and merged into the
+  new symbol, gamma_j + alpha_j m_j, plus a slack of 8 u (alpha_j (|x0_j| +
+  r_j) + |beta_j|) for the rounding of the rule, the centre update and the
+  row scaling;
+* the output radius gets the same widening, plus 4 u_32 (|x0| + r) so that a
+  float32 read-off x0 -/+ r still contains the range.
+The oracle applies it with float64 arithmetic (u = 2^-53, u_b = 0).
 """
 
 from __future__ import annotations
@@ -41,7 +58,21 @@ def _chunk_for(layers, budget_bytes=2.0e8):
     return max(1, int(budget_bytes // (8 * n_max * d_max)))
 
 
-def _track(layers, centres, halves, method, keep_hidden=False):
+U64 = 2.0 ** -53
+U32 = 2.0 ** -24
+
+
+def gamma_n(n, u):
+    """n u / (1 - n u): the relative error bound of an n-term float sum."""
+    return n * u / (1.0 - n * u)
+
+
+def margin_const(K, u, u_b=0.0):
+    """c of the AA rounding margin for a length-K product (bias included)."""
+    return 2.0 * u_b + u_b * u_b + gamma_n(K + 1, u) * (1.0 + u_b) ** 2
+
+
+def _track(layers, centres, halves, method, keep_hidden=False, margin=False):
     """Coefficient tracking for one chunk of boxes; returns (centre, spread)
     and optionally per-hidden-layer (pre-activation centre, row statistic)."""
     C = centres.shape[0]
@@ -53,6 +84,10 @@ def _track(layers, centres, halves, method, keep_hidden=False):
     hidden = []
     last = len(layers) - 1
     for li, (W, b) in enumerate(layers):
+        m = None
+        if margin:
+            rho = np.abs(F).sum(axis=2)
+            m = margin_const(W.shape[1], U64) * ((rho + np.abs(x0)) @ np.abs(W).T + np.abs(b))
         x0 = x0 @ W.T + b
         F = np.matmul(W, F)
         if li == last:
@@ -64,7 +99,11 @@ def _track(layers, centres, halves, method, keep_hidden=False):
             gamma = np.sqrt(gamma2)
         else:
             stat = np.abs(F).sum(axis=2)
+            if margin:
+                stat = stat * (1.0 + 2.0 * gamma_n(F.shape[2], U64)) + m
             alpha, beta, gamma = relu_aa_rule(x0, stat)
+            if margin:
+                gamma = gamma + alpha * m + 8.0 * U64 * (alpha * (np.abs(x0) + stat) + np.abs(beta))
         if keep_hidden:
             hidden.append((x0.copy(), stat.copy()))
         x0 = alpha * x0 + beta
@@ -77,26 +116,32 @@ def _track(layers, centres, halves, method, keep_hidden=False):
         spread = np.sqrt(np.einsum("cd,cd->c", row, row))
     elif method == AA:
         spread = np.abs(row).sum(axis=1)
+        if margin:
+            spread = spread * (1.0 + 2.0 * gamma_n(row.shape[1], U64)) + m[:, 0]
+            spread = spread + 4.0 * U32 * (np.abs(x0[:, 0]) + spread)
     else:  # RA-UA: uniform variables on [-|x_i|, |x_i|] have variance x_i^2/3
         spread = np.sqrt(np.einsum("cd,cd->c", row, row) / 3.0)
     return x0[:, 0], spread, hidden
 
 
-def propagate(layers, centres, halves, method: str, chunk: int | None = None):
+def propagate(layers, centres, halves, method: str, chunk: int | None = None, margin: bool = False):
     """Propagate boxes through the MLP.
 
     centres, halves: [C, 3] (box centre and per-axis half-widths).
     method: ``AA`` (range analysis), ``UP`` (uncertainty propagation) or
     ``RAUA`` (range analysis with the uniform assumption read-off).
+    margin: AA only, apply the rounding margin (module docstring).
     Returns float64 (centre [C], spread [C]).
     """
+    if margin and method != AA:
+        raise ValueError("the rounding margin applies to AA")
     layers = as_f64_layers(layers)
     centres = np.asarray(centres, dtype=np.float64).reshape(-1, 3)
     halves = np.asarray(halves, dtype=np.float64).reshape(-1, 3)
     chunk = chunk or _chunk_for(layers)
     cs, ss = [], []
     for a in range(0, centres.shape[0], chunk):
-        c, s, _ = _track(layers, centres[a : a + chunk], halves[a : a + chunk], method)
+        c, s, _ = _track(layers, centres[a : a + chunk], halves[a : a + chunk], method, margin=margin)
         cs.append(c)
         ss.append(s)
     if not cs:

@@ -243,3 +243,76 @@ def test_hidden_statistics_shapes_and_first_layer_closed_form():
     W1 = mlp.Ws[0].astype(float)
     np.testing.assert_allclose(y1, c @ W1.T + mlp.bs[0], rtol=1e-12)
     np.testing.assert_allclose(s1, np.sqrt((W1[None] * h[:, None, :] ** 2 * W1[None]).sum(-1) / 3), rtol=1e-12)
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_aa_margin_widens_by_a_tiny_amount(seed):
+    """The rounding margin (float64 arithmetic, float32 read-off slack)
+    contains the unwidened AA range and moves it by about 1e-7 relative."""
+    mlp = he_normal_mlp([3, 32, 32, 32, 1], seed=seed)
+    c, h, _ = random_boxes(60, range(0, 8), seed=300 + seed)
+    x0, r = propagate(mlp, c, h, AA)
+    x0m, rm = propagate(mlp, c, h, AA, margin=True)
+    scale = np.abs(x0) + r
+    # a wider ReLU range gives a slightly different line, so the centre moves
+    # too; the widened range contains the plain one
+    assert (x0m - rm <= x0 - r).all() and (x0m + rm >= x0 + r).all()
+    assert (np.abs(x0m - x0) + np.abs(rm - r) <= 1e-6 * scale).all()
+
+
+def test_aa_margin_keeps_tight_ranges_sound_in_float32():
+    """On boxes where the net is affine (every neuron active), AA is exact
+    and its range is attained at box corners.  The same arithmetic in float32
+    then misses corner values by a rounding error, which the margin covers."""
+    from oracle.mlp import as_f64_layers
+
+    rng = np.random.default_rng(11)
+    widths = [3, 24, 24, 24, 1]
+    layers = []
+    for a, b in zip(widths[:-1], widths[1:]):
+        W = rng.uniform(0.0, 1.0, (b, a)) / a
+        layers.append((W, rng.uniform(0.5, 1.0, b)))
+    layers = as_f64_layers(layers)
+    c = rng.uniform(-0.5, 0.5, (40, 3))
+    h = np.full((40, 3), 0.25)
+    x0, r = propagate(layers, c, h, AA)
+    x0m, rm = propagate(layers, c, h, AA, margin=True)
+    corners = np.array([[sx, sy, sz] for sx in (-1, 1) for sy in (-1, 1) for sz in (-1, 1)], dtype=float)
+    for i in range(c.shape[0]):
+        v = mlp_forward(layers, c[i] + corners * h[i])
+        # exact: the range is attained
+        assert abs(v.max() - (x0[i] + r[i])) <= 1e-12 * (abs(x0[i]) + r[i])
+        assert abs(v.min() - (x0[i] - r[i])) <= 1e-12 * (abs(x0[i]) + r[i])
+        # the widened float64 range contains it with room for float32 read-off
+        lo32, hi32 = np.float32(x0m[i]) - np.float32(rm[i]), np.float32(x0m[i]) + np.float32(rm[i])
+        assert lo32 <= v.min() and v.max() <= hi32
+
+
+def _bf16(x):
+    """Round float32 values to bfloat16 (nearest even), returned as float64."""
+    b = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    b = ((b + 0x7FFF + ((b >> 16) & 1)) >> 16) << 16
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("K", [3, 64, 256, 1027])
+def test_aa_margin_constant_bounds_float32_and_bf16_products(K):
+    """c of the margin bounds the error of a float32 dot product (sequential
+    float32 sum, optional bfloat16 operands) against the exact product of the
+    unrounded operands: |fl(w.x + b) - (w.x + b)| <= c (sum |w||x| + |b|)."""
+    from oracle.propagate import U32, margin_const
+
+    rng = np.random.default_rng(K)
+    for trial in range(200):
+        w = rng.standard_normal(K).astype(np.float32)
+        x = (rng.standard_normal(K) * rng.uniform(0.1, 10)).astype(np.float32)
+        b = np.float32(rng.standard_normal())
+        exact = float(np.dot(w.astype(np.float64), x.astype(np.float64))) + float(b)
+        scale = float(np.abs(w.astype(np.float64)) @ np.abs(x.astype(np.float64))) + abs(float(b))
+        for u_b in (0.0, 2.0 ** -8):
+            wr, xr = (w, x) if u_b == 0 else (_bf16(w).astype(np.float32), _bf16(x).astype(np.float32))
+            acc = np.float32(0)
+            for k in range(K):  # float32 products and sums, in order
+                acc = np.float32(acc + np.float32(wr[k] * xr[k]))
+            acc = np.float32(acc + b)
+            assert abs(float(acc) - exact) <= margin_const(K, U32, u_b) * scale, (trial, u_b)
