@@ -287,11 +287,16 @@ typedef enum {
   ISX_UP_FORM = 7,         /* bf16 uncertainty propagation: 0 = covariance form (exact alternative to
                               coefficient tracking: C_h = W_h (D C_{h-1} D + diag(gamma^2)) W_h^T, one
                               fused launch per batch, hidden widths <= 256), 1 = coefficient form */
-  ISX_LIN_PRECISION = 8    /* centre linearisation (isx_linearize and the surrogate's base): 1 (default)
+  ISX_LIN_PRECISION = 8,   /* centre linearisation (isx_linearize and the surrogate's base): 1 (default)
                               = bfloat16 MFMA with every column carried as two bfloat16 parts and three
                               bfloat16 products per layer (f within ~3e-4 of max(|f|, output scale), s
                               within ~2e-3 relative; used when every hidden layer has the same width
                               <= 256, else float32), 0 = float32 MFMA */
+  ISX_AA_MARGIN = 9        /* affine arithmetic: 1 = widen every layer by the rounding margin of its
+                              floating-point evaluation (operand rounding 2^-8 for bfloat16 products,
+                              accumulation 2^-24 float32 / 2^-53 float64), so that the returned range
+                              contains the exact range of the network over the box; 0 (default) = the
+                              paper's rule (exact arithmetic assumed) evaluated in floating point */
 } isx_option;
 isx_status isx_set_option(isx_ctx* ctx, isx_option option, int64_t value);
 

@@ -21,7 +21,7 @@ import numpy as np
 
 from . import _lib
 from ._lib import (AA, BF16, BF16_VARIANT, FP32, FP64, HIDDEN_KERNEL, KEEP_LEVELS, PROFILE, SCRATCH_BYTES, UP,
-                   UP_FORM, LIN_PRECISION, VERBOSE)
+                   UP_FORM, LIN_PRECISION, AA_MARGIN, VERBOSE)
 
 KERNEL_KINDS = ("hidden_fp32", "hidden_bf16", "hidden_simt_fp32", "hidden_fp64", "dense", "output",
                 "hidden_cov_bf16", "linearize")

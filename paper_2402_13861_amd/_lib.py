@@ -18,7 +18,8 @@ STATUS_NAMES = {
 }
 AA, UP = 0, 1
 FP32, BF16, FP64 = 0, 1, 2
-KEEP_LEVELS, HIDDEN_KERNEL, PROFILE, SCRATCH_BYTES, VERBOSE, BF16_VARIANT, UP_FORM, LIN_PRECISION = 1, 2, 3, 4, 5, 6, 7, 8
+(KEEP_LEVELS, HIDDEN_KERNEL, PROFILE, SCRATCH_BYTES, VERBOSE, BF16_VARIANT, UP_FORM, LIN_PRECISION,
+ AA_MARGIN) = 1, 2, 3, 4, 5, 6, 7, 8, 9
 MAX_LINEAR, MAX_WIDTH, MAX_ISO = 16, 1024, 32
 (KERNEL_HIDDEN_FP32, KERNEL_HIDDEN_BF16, KERNEL_HIDDEN_SIMT_FP32, KERNEL_HIDDEN_FP64, KERNEL_DENSE,
  KERNEL_OUTPUT, KERNEL_HIDDEN_COV_BF16, KERNEL_LINEARIZE) = range(8)

@@ -51,6 +51,7 @@ struct isx_ctx {
   int bf16_variant = 0;
   int up_form = 0;
   int lin_prec = 1;  // centre linearisation: 1 = bf16 split where supported, 0 = float32
+  int aa_margin = 0; // AA: widen by the rounding margin
   size_t prop_budget = size_t(16) << 30;  // bytes of propagation scratch per chunk
   // propagation scratch
   Buf F32[2], vec32, F64[2], vec64, Fbf[2];
@@ -162,7 +163,7 @@ hipError_t upload(T** dst, const std::vector<T>& src) {
 // Scratch bytes per cell of the propagation at precision T.
 template <typename T>
 size_t per_cell_bytes(const Model& m) {
-  return (2 * prop_F_elems(m, 1) + prop_vec_elems(m, 1)) * sizeof(T);
+  return (2 * prop_F_elems(m, 1) + prop_vec_elems(m, 1, true)) * sizeof(T);
 }
 
 template <typename T>
@@ -175,18 +176,20 @@ int64_t chunk_for(isx_ctx* ctx, const Model& m, int64_t n, int64_t req) {
 isx_status run_propagate(isx_ctx* ctx, const Model& m, isx_method method, isx_precision prec, int64_t n,
                          const float* centres, const float* halves, float* out, double* out64, int64_t chunk_req) {
   if (n <= 0) return ISX_OK;
+  const bool marg = method == ISX_AA && ctx->aa_margin != 0;
   if (prec == ISX_FP64) {
     const int64_t chunk = chunk_for<double>(ctx, m, n, chunk_req);
     PropWork<double> w;
     HIPCHK(ensure(ctx->F64[0], prop_F_elems(m, chunk) * sizeof(double)));
     HIPCHK(ensure(ctx->F64[1], prop_F_elems(m, chunk) * sizeof(double)));
-    HIPCHK(ensure(ctx->vec64, prop_vec_elems(m, chunk) * sizeof(double)));
+    HIPCHK(ensure(ctx->vec64, prop_vec_elems(m, chunk, marg) * sizeof(double)));
     w.F[0] = (double*)ctx->F64[0].p;
     w.F[1] = (double*)ctx->F64[1].p;
     w.vec = (double*)ctx->vec64.p;
     for (int64_t s = 0; s < n; s += chunk) {
       PropArgs a{&m, method, std::min(chunk, n - s), centres + 3 * s, halves + 3 * s, out + 2 * s,
                  out64 ? out64 + 2 * s : nullptr, ctx->kernel_choice, ctx->stream, &ctx->prof, ctx->bf16_variant};
+      a.aa_margin = marg;
       HIPCHK(propagate_f64(a, w));
     }
     return ISX_OK;
@@ -196,7 +199,7 @@ isx_status run_propagate(isx_ctx* ctx, const Model& m, isx_method method, isx_pr
       return fail(ctx, ISX_EUNSUPPORTED, "bf16 propagation needs every hidden layer's input width <= 256");
     // the covariance form (UP) keeps each cell on chip: no coefficient blocks
     const bool cov = method == ISX_UP && ctx->up_form == 0 && cov_supported(m);
-    const size_t per_cell = (cov ? 0 : 2 * prop_F_elems_bf16(m, 1) * 2) + prop_vec_elems(m, 1) * 4;
+    const size_t per_cell = (cov ? 0 : 2 * prop_F_elems_bf16(m, 1) * 2) + prop_vec_elems(m, 1, marg) * 4;
     int64_t chunk = chunk_req > 0 ? chunk_req : (int64_t)(ctx->prop_budget / per_cell);
     chunk = std::max<int64_t>(1, std::min<int64_t>(chunk, n));
     PropWork<float> w;
@@ -204,12 +207,13 @@ isx_status run_propagate(isx_ctx* ctx, const Model& m, isx_method method, isx_pr
       HIPCHK(ensure(ctx->Fbf[0], prop_F_elems_bf16(m, chunk) * 2));
       HIPCHK(ensure(ctx->Fbf[1], prop_F_elems_bf16(m, chunk) * 2));
     }
-    HIPCHK(ensure(ctx->vec32, prop_vec_elems(m, chunk) * sizeof(float)));
+    HIPCHK(ensure(ctx->vec32, prop_vec_elems(m, chunk, marg) * sizeof(float)));
     w.vec = (float*)ctx->vec32.p;
     uint16_t* Fbf[2] = {(uint16_t*)ctx->Fbf[0].p, (uint16_t*)ctx->Fbf[1].p};
     for (int64_t s = 0; s < n; s += chunk) {
       PropArgs a{&m, method, std::min(chunk, n - s), centres + 3 * s, halves + 3 * s, out + 2 * s, nullptr,
                  ctx->kernel_choice, ctx->stream, &ctx->prof, ctx->bf16_variant, ctx->up_form};
+      a.aa_margin = marg;
       HIPCHK(propagate_bf16(a, w, Fbf, 0));
     }
     return ISX_OK;
@@ -218,13 +222,14 @@ isx_status run_propagate(isx_ctx* ctx, const Model& m, isx_method method, isx_pr
   PropWork<float> w;
   HIPCHK(ensure(ctx->F32[0], prop_F_elems(m, chunk) * sizeof(float)));
   HIPCHK(ensure(ctx->F32[1], prop_F_elems(m, chunk) * sizeof(float)));
-  HIPCHK(ensure(ctx->vec32, prop_vec_elems(m, chunk) * sizeof(float)));
+  HIPCHK(ensure(ctx->vec32, prop_vec_elems(m, chunk, marg) * sizeof(float)));
   w.F[0] = (float*)ctx->F32[0].p;
   w.F[1] = (float*)ctx->F32[1].p;
   w.vec = (float*)ctx->vec32.p;
   for (int64_t s = 0; s < n; s += chunk) {
     PropArgs a{&m, method, std::min(chunk, n - s), centres + 3 * s, halves + 3 * s, out + 2 * s, nullptr,
                ctx->kernel_choice, ctx->stream, &ctx->prof, ctx->bf16_variant};
+    a.aa_margin = marg;
     HIPCHK(propagate_f32(a, w));
   }
   return ISX_OK;
@@ -334,6 +339,10 @@ isx_status isx_set_option(isx_ctx* ctx, isx_option option, int64_t value) {
     case ISX_UP_FORM:
       if (value < 0 || value > 1) return fail(ctx, ISX_EINVAL, "ISX_UP_FORM must be 0 or 1");
       ctx->up_form = (int)value;
+      return ISX_OK;
+    case ISX_AA_MARGIN:
+      if (value < 0 || value > 1) return fail(ctx, ISX_EINVAL, "ISX_AA_MARGIN must be 0 or 1");
+      ctx->aa_margin = (int)value;
       return ISX_OK;
     case ISX_LIN_PRECISION:
       if (value < 0 || value > 1) return fail(ctx, ISX_EINVAL, "ISX_LIN_PRECISION must be 0 or 1");

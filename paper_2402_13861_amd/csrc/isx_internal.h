@@ -226,9 +226,29 @@ struct PropArgs {
   Profiler* prof;     // may be null
   int bf16_variant;   // 0 = default tile shape for the width
   int up_form = 0;    // bf16 UP: 0 = covariance form when supported, 1 = coefficient form
+  int aa_margin = 0;  // AA: widen by the rounding margin (kernels_margin.hip)
 };
+
+// Constants of the affine-arithmetic rounding margin of one layer
+// (kernels_margin.hip): c, the inflation of the margin's own sums, of the
+// row statistic, and the rule's slack.
+template <typename T>
+struct AaMargin {
+  T c, infl_m, infl_s, slack;
+};
+template <typename T>
+AaMargin<T> aa_margin_consts(double u, double u_b, int K, int64_t D);
+template <typename T>
+hipError_t launch_aa_margin_hidden(int64_t C, int n_in, int n_out, const T* Wt, const T* bias, const T* Yp,
+                                   const T* Ap, const T* Bp, const T* Rp, const float* centres, const float* halves,
+                                   const T* Y, const T* S, T* A, T* B, T* G, T* R, const AaMargin<T>& k,
+                                   hipStream_t s);
+template <typename T>
+hipError_t launch_aa_margin_output(int64_t C, int n_in, const T* Wt, const T* bias, const T* Yp, const T* Ap,
+                                   const T* Bp, const T* Rp, const float* centres, const float* halves, float* out32,
+                                   double* out64, const AaMargin<T>& k, hipStream_t s);
 size_t prop_F_elems(const Model& m, int64_t C);
-size_t prop_vec_elems(const Model& m, int64_t C);
+size_t prop_vec_elems(const Model& m, int64_t C, bool with_margin = false);
 hipError_t propagate_f32(const PropArgs& a, PropWork<float>& w);
 hipError_t propagate_f64(const PropArgs& a, PropWork<double>& w);
 hipError_t propagate_bf16(const PropArgs& a, PropWork<float>& w, uint16_t* Fbf[2], size_t Fbf_elems);

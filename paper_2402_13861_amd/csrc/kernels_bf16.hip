@@ -81,7 +81,8 @@ template <int METHOD>
 __global__ void layer1_bf16_kernel(int64_t C, int n, const float* __restrict__ centres,
                                    const float* __restrict__ halves, const float* __restrict__ W1,
                                    const float* __restrict__ b1, __bf16* __restrict__ Fout, float* __restrict__ Y,
-                                   float* __restrict__ A, float* __restrict__ B, float* __restrict__ G) {
+                                   float* __restrict__ A, float* __restrict__ B, float* __restrict__ G,
+                                   float* __restrict__ S) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= C * n) return;
   const int64_t cell = idx / n;
@@ -102,6 +103,7 @@ __global__ void layer1_bf16_kernel(int64_t C, int n, const float* __restrict__ c
   A[idx] = a;
   B[idx] = b;
   G[idx] = g;
+  if (S) S[idx] = stat;
   if (Fout) {
     __bf16* col = Fout + cell * (int64_t)kHeadCols * n + m;
     col[0] = (__bf16)0.f;
@@ -129,7 +131,7 @@ __global__ __launch_bounds__(64 * NW) void hidden_mfma_bf16_kernel(
     const float* __restrict__ bias, const __bf16* __restrict__ WtPrev, const float* __restrict__ Gprev2,
     const __bf16* __restrict__ Fin, const float* __restrict__ Yin, const float* __restrict__ Ain,
     const float* __restrict__ Bin, const float* __restrict__ Gin, __bf16* __restrict__ Fout, float* __restrict__ Y,
-    float* __restrict__ A, float* __restrict__ B, float* __restrict__ G) {
+    float* __restrict__ A, float* __restrict__ B, float* __restrict__ G, float* __restrict__ S) {
   constexpr int THREADS = 64 * NW;
   constexpr int BN = 32 * NB;                  // columns per tile
   constexpr int BM = 32 * RB * NW;             // output neurons per workgroup
@@ -352,6 +354,7 @@ __global__ __launch_bounds__(64 * NW) void hidden_mfma_bf16_kernel(
     A[o] = a;
     B[o] = b;
     G[o] = gg;
+    if (S) S[o] = tot;
   }
 }
 
@@ -365,7 +368,7 @@ template <int METHOD, int NW, int RB, int NB, int KMAXT>
 static hipError_t launch_bf16_k(int64_t C, int n_in, int n_out, int64_t s_in, int g_in, const float* W,
                                 const float* bias, const __bf16* WtPrev, const float* Gprev2, const __bf16* Fin,
                                 const float* Yin, const float* Ain, const float* Bin, const float* Gin, __bf16* Fout,
-                                float* Y, float* A, float* B, float* G, hipStream_t s) {
+                                float* Y, float* A, float* B, float* G, float* S, hipStream_t s) {
   constexpr int BM = 32 * RB * NW;
   constexpr int BN = 32 * NB;
   const int rb_count = n_out / BM;
@@ -380,7 +383,7 @@ static hipError_t launch_bf16_k(int64_t C, int n_in, int n_out, int64_t s_in, in
   }
   hipLaunchKernelGGL((hidden_mfma_bf16_kernel<METHOD, NW, RB, NB, KMAXT>), dim3((unsigned)blocks), dim3(64 * NW), lds, s, C,
                      n_in, n_out, s_in, g_in, rb_count, W, bias, WtPrev, Gprev2, Fin, Yin, Ain, Bin, Gin, Fout, Y, A,
-                     B, G);
+                     B, G, S);
   return hipGetLastError();
 }
 
@@ -391,8 +394,8 @@ template <int METHOD, int NW, int RB, int NB>
 static hipError_t launch_bf16_v(int64_t C, int n_in, int n_out, int64_t s_in, int g_in, const float* W,
                                 const float* bias, const __bf16* WtPrev, const float* Gprev2, const __bf16* Fin,
                                 const float* Yin, const float* Ain, const float* Bin, const float* Gin, __bf16* Fout,
-                                float* Y, float* A, float* B, float* G, hipStream_t s) {
-#define ISX_BF16_KARGS C, n_in, n_out, s_in, g_in, W, bias, WtPrev, Gprev2, Fin, Yin, Ain, Bin, Gin, Fout, Y, A, B, G, s
+                                float* Y, float* A, float* B, float* G, float* S, hipStream_t s) {
+#define ISX_BF16_KARGS C, n_in, n_out, s_in, g_in, W, bias, WtPrev, Gprev2, Fin, Yin, Ain, Bin, Gin, Fout, Y, A, B, G, S, s
   if (n_in <= 64) return launch_bf16_k<METHOD, NW, RB, NB, 64>(ISX_BF16_KARGS);
   if (n_in <= 128) return launch_bf16_k<METHOD, NW, RB, NB, 128>(ISX_BF16_KARGS);
   return launch_bf16_k<METHOD, NW, RB, NB, 256>(ISX_BF16_KARGS);
@@ -403,8 +406,8 @@ template <int METHOD>
 static hipError_t launch_bf16_m(int variant, int64_t C, int n_in, int n_out, int64_t s_in, int g_in, const float* W,
                                 const float* bias, const __bf16* WtPrev, const float* Gprev2, const __bf16* Fin,
                                 const float* Yin, const float* Ain, const float* Bin, const float* Gin, __bf16* Fout,
-                                float* Y, float* A, float* B, float* G, hipStream_t s) {
-#define ISX_BF16_ARGS C, n_in, n_out, s_in, g_in, W, bias, WtPrev, Gprev2, Fin, Yin, Ain, Bin, Gin, Fout, Y, A, B, G, s
+                                float* Y, float* A, float* B, float* G, float* S, hipStream_t s) {
+#define ISX_BF16_ARGS C, n_in, n_out, s_in, g_in, W, bias, WtPrev, Gprev2, Fin, Yin, Ain, Bin, Gin, Fout, Y, A, B, G, S, s
   if (variant == 1 && n_out % 256 == 0) return launch_bf16_v<METHOD, 4, 2, 2>(ISX_BF16_ARGS);
   if (variant == 3 && n_out % 128 == 0) return launch_bf16_v<METHOD, 4, 1, 2>(ISX_BF16_ARGS);
   if (variant == 4 && n_out % 64 == 0) return launch_bf16_v<METHOD, 2, 1, 2>(ISX_BF16_ARGS);
@@ -461,6 +464,22 @@ hipError_t propagate_bf16(const PropArgs& a, PropWork<float>& w, uint16_t* Fbf_r
     if (prof2) a.prof->end(rec2, a.stream);
     return e;
   }
+  // AA rounding margin (kernels_margin.hip): bfloat16 operands from layer 2
+  // on (u_b = 2^-8), float32 accumulation; the row statistics S and radii R
+  // follow the four vectors of every layer in the vector buffer
+  const bool marg = a.method == ISX_AA && a.aa_margin;
+  float *S[ISX_MAX_LINEAR] = {}, *R[ISX_MAX_LINEAR] = {};
+  if (marg) {
+    size_t tot = 0;
+    for (int h = 1; h <= Lh; ++h) tot += (size_t)m.pw[h] * C;
+    size_t off = 4 * tot;
+    for (int h = 1; h <= Lh; ++h) {
+      S[h] = w.vec + off;
+      R[h] = w.vec + off + tot;
+      off += (size_t)m.pw[h] * C;
+    }
+  }
+  int64_t D = 3;  // symbol columns summed by the row statistic of the layer
   int cur = 0;
   {
     const int n1 = m.pw[1];
@@ -468,11 +487,17 @@ hipError_t propagate_bf16(const PropArgs& a, PropWork<float>& w, uint16_t* Fbf_r
     if (a.method == ISX_UP)
       hipLaunchKernelGGL(layer1_bf16_kernel<ISX_UP>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, a.stream,
                          C, n1, a.centres, a.halves, m.L[0].W, m.L[0].b, Lh >= 2 ? Fbf[cur] : nullptr, Y[1], A[1], B[1],
-                         G[1]);
+                         G[1], (float*)nullptr);
     else
       hipLaunchKernelGGL(layer1_bf16_kernel<ISX_AA>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, a.stream,
                          C, n1, a.centres, a.halves, m.L[0].W, m.L[0].b, Lh >= 2 ? Fbf[cur] : nullptr, Y[1], A[1], B[1],
-                         G[1]);
+                         G[1], S[1]);
+    if (marg) {
+      hipError_t e = launch_aa_margin_hidden<float>(C, 3, n1, m.L[0].Wt, m.L[0].b, nullptr, nullptr, nullptr, nullptr,
+                                                    a.centres, a.halves, Y[1], S[1], A[1], B[1], G[1], R[1],
+                                                    aa_margin_consts<float>(0x1p-24, 0.0, 3, D), a.stream);
+      if (e != hipSuccess) return e;
+    }
   }
   for (int h = 2; h <= Lh; ++h) {
     const int n_in = m.pw[h - 1], n_out = m.pw[h];
@@ -494,12 +519,21 @@ hipError_t propagate_bf16(const PropArgs& a, PropWork<float>& w, uint16_t* Fbf_r
     const __bf16* WtPrev = reinterpret_cast<const __bf16*>(m.L[h - 2].Wtbf);
     const float* Gp2 = h >= 3 ? G[h - 2] : nullptr;
     hipError_t e = a.method == ISX_UP
-                       ? launch_bf16_m<ISX_UP>(a.bf16_variant, C, n_in, n_out, s_in, g_in, L.W, L.b, WtPrev, Gp2, Fbf[cur], Y[h - 1],
-                                               A[h - 1], B[h - 1], G[h - 1], Fout, Y[h], A[h], B[h], G[h], a.stream)
-                       : launch_bf16_m<ISX_AA>(a.bf16_variant, C, n_in, n_out, s_in, g_in, L.W, L.b, WtPrev, Gp2, Fbf[cur], Y[h - 1],
-                                               A[h - 1], B[h - 1], G[h - 1], Fout, Y[h], A[h], B[h], G[h], a.stream);
+                       ? launch_bf16_m<ISX_UP>(a.bf16_variant, C, n_in, n_out, s_in, g_in, L.W, L.b, WtPrev, Gp2,
+                                               Fbf[cur], Y[h - 1], A[h - 1], B[h - 1], G[h - 1], Fout, Y[h], A[h], B[h],
+                                               G[h], (float*)nullptr, a.stream)
+                       : launch_bf16_m<ISX_AA>(a.bf16_variant, C, n_in, n_out, s_in, g_in, L.W, L.b, WtPrev, Gp2,
+                                               Fbf[cur], Y[h - 1], A[h - 1], B[h - 1], G[h - 1], Fout, Y[h], A[h], B[h],
+                                               G[h], S[h], a.stream);
     if (e != hipSuccess) return e;
     if (prof) a.prof->end(rec, a.stream);
+    D += n_in;
+    if (marg) {
+      e = launch_aa_margin_hidden<float>(C, n_in, n_out, L.Wt, L.b, Y[h - 1], A[h - 1], B[h - 1], R[h - 1], a.centres,
+                                         a.halves, Y[h], S[h], A[h], B[h], G[h], R[h],
+                                         aa_margin_consts<float>(0x1p-24, 0x1p-8, n_in, D), a.stream);
+      if (e != hipSuccess) return e;
+    }
     cur ^= 1;
   }
   Profiler::Rec rec{};
@@ -508,6 +542,16 @@ hipError_t propagate_bf16(const PropArgs& a, PropWork<float>& w, uint16_t* Fbf_r
   hipError_t e = a.kernel_choice == 1 ? launch_output_f32(m, a.method, C, w.vec, a.halves, a.out32, a.stream)
                                       : launch_output_mfma(m, a.method, C, Y, A, B, G, a.halves, a.out32, a.stream);
   if (prof) a.prof->end(rec, a.stream);
+  if (e == hipSuccess && marg) {
+    // the read-off runs on float32 vectors and weights (u_b = 0)
+    int kmax = 3;
+    for (int h = 1; h <= Lh; ++h) kmax = std::max(kmax, m.pw[h]);
+    AaMargin<float> k = aa_margin_consts<float>(0x1p-24, 0.0, m.pw[Lh], D + m.pw[Lh]);
+    const double u = 0x1p-24;
+    k.c = (float)((m.n_linear + 1) * ((kmax + 1) * u / (1.0 - (kmax + 1) * u)));
+    e = launch_aa_margin_output<float>(C, m.pw[Lh], m.L[Lh].Wt, m.L[Lh].b, Y[Lh], A[Lh], B[Lh], R[Lh], a.centres,
+                                       a.halves, a.out32, nullptr, k, a.stream);
+  }
   return e;
 }
 

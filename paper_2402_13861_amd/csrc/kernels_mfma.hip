@@ -87,7 +87,7 @@ __global__ __launch_bounds__(512) void hidden_mfma_f32_kernel(
     int64_t C, int n_in, int n_out, int64_t cols_in, int rb_count, const float* __restrict__ Wt,
     const float* __restrict__ bias, const float* __restrict__ Fin, const float* __restrict__ Ain,
     const float* __restrict__ Bin, const float* __restrict__ Gin, float* __restrict__ Fout, float* __restrict__ Y,
-    float* __restrict__ A, float* __restrict__ B, float* __restrict__ G) {
+    float* __restrict__ A, float* __restrict__ B, float* __restrict__ G, float* __restrict__ S) {
   using K = Cfg<BM>;
   __shared__ float As[K::KT * K::ASTR];
   __shared__ float Bs[K::KT * K::BSTR];
@@ -310,6 +310,7 @@ __global__ __launch_bounds__(512) void hidden_mfma_f32_kernel(
     A[o] = a;
     B[o] = b;
     G[o] = gg;
+    if (S) S[o] = tot;
   }
 }
 
@@ -322,28 +323,28 @@ bool mfma_supported(const Model& m) {
 template <int METHOD, int BM>
 static void launch_bm(int64_t C, int n_in, int n_out, int64_t cols_in, const float* Wt, const float* bias,
                       const float* Fin, const float* Ain, const float* Bin, const float* Gin, float* Fout, float* Y,
-                      float* A, float* B, float* G, hipStream_t s) {
+                      float* A, float* B, float* G, float* S, hipStream_t s) {
   const int rb_count = n_out / BM;
   const int64_t blocks = ((C + 7) / 8) * 8 * rb_count;
   hipLaunchKernelGGL((hidden_mfma_f32_kernel<METHOD, BM>), dim3((unsigned)blocks), dim3(Cfg<BM>::THREADS), 0, s, C,
-                     n_in, n_out, cols_in, rb_count, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G);
+                     n_in, n_out, cols_in, rb_count, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S);
 }
 
 hipError_t launch_hidden_mfma_f32(int method, int64_t C, int n_in, int n_out, int64_t cols_in, const float* Wt,
                                   const float* bias, const float* Fin, const float* Ain, const float* Bin,
-                                  const float* Gin, float* Fout, float* Y, float* A, float* B, float* G,
+                                  const float* Gin, float* Fout, float* Y, float* A, float* B, float* G, float* S,
                                   hipStream_t s) {
   if (C <= 0) return hipSuccess;
   if (n_out % 32 != 0 || n_in % 32 != 0 || n_in > ISX_MAX_WIDTH) return hipErrorInvalidValue;
   const int bm = n_out % 128 == 0 ? 128 : (n_out % 64 == 0 ? 64 : 32);
   if (method == ISX_UP) {
-    if (bm == 128) launch_bm<ISX_UP, 128>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, s);
-    else if (bm == 64) launch_bm<ISX_UP, 64>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, s);
-    else launch_bm<ISX_UP, 32>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, s);
+    if (bm == 128) launch_bm<ISX_UP, 128>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, s);
+    else if (bm == 64) launch_bm<ISX_UP, 64>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, s);
+    else launch_bm<ISX_UP, 32>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, s);
   } else {
-    if (bm == 128) launch_bm<ISX_AA, 128>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, s);
-    else if (bm == 64) launch_bm<ISX_AA, 64>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, s);
-    else launch_bm<ISX_AA, 32>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, s);
+    if (bm == 128) launch_bm<ISX_AA, 128>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, s);
+    else if (bm == 64) launch_bm<ISX_AA, 64>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, s);
+    else launch_bm<ISX_AA, 32>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, s);
   }
   return hipGetLastError();
 }

@@ -87,7 +87,8 @@ __global__ __launch_bounds__(512) void hidden_mfma_f64_kernel(
     int64_t C, int n_in, int n_out, int64_t cols_in, int rb_count, const double* __restrict__ Wt,
     const double* __restrict__ bias, const double* __restrict__ Fin, const double* __restrict__ Ain,
     const double* __restrict__ Bin, const double* __restrict__ Gin, double* __restrict__ Fout,
-    double* __restrict__ Y, double* __restrict__ A, double* __restrict__ B, double* __restrict__ G) {
+    double* __restrict__ Y, double* __restrict__ A, double* __restrict__ B, double* __restrict__ G,
+    double* __restrict__ S) {
   using K = Cfg64<BM>;
   __shared__ double As[K::KT * K::ASTR];
   __shared__ double Bs[K::KT * K::BSTR];
@@ -319,30 +320,31 @@ __global__ __launch_bounds__(512) void hidden_mfma_f64_kernel(
     A[o] = a;
     B[o] = b;
     G[o] = gg;
+    if (S) S[o] = tot;
   }
 }
 
 template <int METHOD, int BM>
 static void launch64_bm(int64_t C, int n_in, int n_out, int64_t cols_in, const double* Wt, const double* bias,
                         const double* Fin, const double* Ain, const double* Bin, const double* Gin, double* Fout,
-                        double* Y, double* A, double* B, double* G, hipStream_t s) {
+                        double* Y, double* A, double* B, double* G, double* S, hipStream_t s) {
   const int rb_count = n_out / BM;
   const int64_t blocks = ((C + 7) / 8) * 8 * rb_count;
   hipLaunchKernelGGL((hidden_mfma_f64_kernel<METHOD, BM>), dim3((unsigned)blocks), dim3(Cfg64<BM>::THREADS), 0, s,
-                     C, n_in, n_out, cols_in, rb_count, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G);
+                     C, n_in, n_out, cols_in, rb_count, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S);
 }
 
 hipError_t launch_hidden_mfma_f64(int method, int64_t C, int n_in, int n_out, int64_t cols_in, const double* Wt,
                                   const double* bias, const double* Fin, const double* Ain, const double* Bin,
                                   const double* Gin, double* Fout, double* Y, double* A, double* B, double* G,
-                                  hipStream_t s) {
+                                  double* S, hipStream_t s) {
   if (C <= 0) return hipSuccess;
   if (n_out % 32 != 0 || n_in % 32 != 0 || n_in > ISX_MAX_WIDTH) return hipErrorInvalidValue;
   // 64-row blocks run two workgroups per CU (the 128-row tile needs more
   // registers than that allows); wider layers keep 128 so that each cell's
   // coefficient block is streamed fewer times
   const int bm = (n_out % 64 == 0 && n_out <= 256) ? 64 : (n_out % 128 == 0 ? 128 : (n_out % 64 == 0 ? 64 : 32));
-#define ISX_F64_ARGS C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, s
+#define ISX_F64_ARGS C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, s
   if (method == ISX_UP) {
     if (bm == 128) launch64_bm<ISX_UP, 128>(ISX_F64_ARGS);
     else if (bm == 64) launch64_bm<ISX_UP, 64>(ISX_F64_ARGS);

@@ -104,7 +104,7 @@ template <typename T, int METHOD>
 __global__ void layer1_kernel(int64_t C, int n, const float* __restrict__ centres,
                               const float* __restrict__ halves, const T* __restrict__ W1,
                               const T* __restrict__ b1, T* __restrict__ Fout, T* __restrict__ Y,
-                              T* __restrict__ A, T* __restrict__ B, T* __restrict__ G) {
+                              T* __restrict__ A, T* __restrict__ B, T* __restrict__ G, T* __restrict__ S) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= C * n) return;
   const int64_t cell = idx / n;
@@ -126,6 +126,7 @@ __global__ void layer1_kernel(int64_t C, int n, const float* __restrict__ centre
   A[idx] = a;
   B[idx] = b;
   G[idx] = g;
+  if (S) S[idx] = stat;
   if (Fout) {
     T* col = Fout + cell * (int64_t)kHeadCols * n + m;
     col[0] = y;
@@ -149,7 +150,7 @@ __global__ void hidden_simt_kernel(int64_t C, int n_in, int n_out, int64_t cols_
                                    const T* __restrict__ Fin, const T* __restrict__ Ain,
                                    const T* __restrict__ Bin, const T* __restrict__ Gin,
                                    T* __restrict__ Fout, T* __restrict__ Y, T* __restrict__ A,
-                                   T* __restrict__ B, T* __restrict__ G) {
+                                   T* __restrict__ B, T* __restrict__ G, T* __restrict__ S) {
   extern __shared__ unsigned char smem_raw[];
   T* Bs = reinterpret_cast<T*>(smem_raw);  // [n_in][CT]
   const int64_t cell = blockIdx.x;
@@ -215,6 +216,7 @@ __global__ void hidden_simt_kernel(int64_t C, int n_in, int n_out, int64_t cols_
     A[o] = a;
     B[o] = b;
     G[o] = g;
+    if (S) S[o] = stat;
   }
 }
 
@@ -353,10 +355,26 @@ size_t prop_F_elems(const Model& m, int64_t C) {
   return best * (size_t)C;
 }
 
-size_t prop_vec_elems(const Model& m, int64_t C) {
+// Per hidden layer h: Y, A, B, G (each [C][n_h]) in layer order, then (with
+// the AA rounding margin) the row statistics S and the absolute radii R of
+// every layer.
+size_t prop_vec_elems(const Model& m, int64_t C, bool with_margin) {
   size_t s = 0;
-  for (int h = 1; h <= m.hidden(); ++h) s += 4 * (size_t)m.pw[h];
+  for (int h = 1; h <= m.hidden(); ++h) s += (with_margin ? 6 : 4) * (size_t)m.pw[h];
   return s * (size_t)C;
+}
+
+template <typename T>
+static void margin_ptrs(const Model& m, int64_t C, T* vec, T** S, T** R) {
+  size_t tot = 0;
+  for (int h = 1; h <= m.hidden(); ++h) tot += (size_t)m.pw[h] * C;
+  size_t off = 4 * tot;
+  for (int h = 1; h <= m.hidden(); ++h) {
+    const size_t n = (size_t)m.pw[h] * C;
+    S[h] = vec + off;
+    R[h] = vec + off + tot;
+    off += n;
+  }
 }
 
 template <typename T>
@@ -417,31 +435,32 @@ static NetView<T> make_view(const Model& m) {
 
 hipError_t launch_hidden_mfma_f32(int method, int64_t C, int n_in, int n_out, int64_t cols_in, const float* Wt,
                                   const float* bias, const float* Fin, const float* Ain, const float* Bin,
-                                  const float* Gin, float* Fout, float* Y, float* A, float* B, float* G,
+                                  const float* Gin, float* Fout, float* Y, float* A, float* B, float* G, float* S,
                                   hipStream_t s);
 hipError_t launch_hidden_mfma_f64(int method, int64_t C, int n_in, int n_out, int64_t cols_in, const double* Wt,
                                   const double* bias, const double* Fin, const double* Ain, const double* Bin,
                                   const double* Gin, double* Fout, double* Y, double* A, double* B, double* G,
-                                  hipStream_t s);
+                                  double* S, hipStream_t s);
 bool mfma_supported(const Model& m);
 
 template <typename T>
 static hipError_t hidden_mfma(int, int64_t, int, int, int64_t, const T*, const T*, const T*, const T*, const T*,
-                              const T*, T*, T*, T*, T*, T*, hipStream_t) {
+                              const T*, T*, T*, T*, T*, T*, T*, hipStream_t) {
   return hipErrorNotSupported;
 }
 template <>
 hipError_t hidden_mfma<float>(int method, int64_t C, int n_in, int n_out, int64_t cols_in, const float* Wt,
                               const float* bias, const float* Fin, const float* Ain, const float* Bin,
-                              const float* Gin, float* Fout, float* Y, float* A, float* B, float* G, hipStream_t s) {
-  return launch_hidden_mfma_f32(method, C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, s);
+                              const float* Gin, float* Fout, float* Y, float* A, float* B, float* G, float* S,
+                              hipStream_t s) {
+  return launch_hidden_mfma_f32(method, C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, s);
 }
 template <>
 hipError_t hidden_mfma<double>(int method, int64_t C, int n_in, int n_out, int64_t cols_in, const double* Wt,
                                const double* bias, const double* Fin, const double* Ain, const double* Bin,
                                const double* Gin, double* Fout, double* Y, double* A, double* B, double* G,
-                               hipStream_t s) {
-  return launch_hidden_mfma_f64(method, C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, s);
+                               double* S, hipStream_t s) {
+  return launch_hidden_mfma_f64(method, C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, s);
 }
 
 template <typename T, int METHOD>
@@ -450,7 +469,14 @@ static hipError_t propagate_impl(const PropArgs& a, PropWork<T>& w, bool use_mfm
   const int Lh = m.hidden();
   const int64_t C = a.C;
   T *Y[ISX_MAX_LINEAR] = {}, *A[ISX_MAX_LINEAR] = {}, *B[ISX_MAX_LINEAR] = {}, *G[ISX_MAX_LINEAR] = {};
+  T *S[ISX_MAX_LINEAR] = {}, *R[ISX_MAX_LINEAR] = {};
   layer_ptrs<T>(m, C, w.vec, Y, A, B, G);
+  // AA rounding margin: the kernels also write their row statistics, and a
+  // pass after each layer re-applies the rule to the widened radius
+  const bool marg = METHOD == ISX_AA && a.aa_margin;
+  const double u = sizeof(T) == 8 ? 0x1p-53 : 0x1p-24;
+  if (marg) margin_ptrs<T>(m, C, w.vec, S, R);
+  int64_t D = 3;  // symbol columns summed by the row statistic of the layer
   int cur = 0;
   {
     const int n1 = m.pw[1];
@@ -458,7 +484,13 @@ static hipError_t propagate_impl(const PropArgs& a, PropWork<T>& w, bool use_mfm
     const int bs = 256;
     hipLaunchKernelGGL((layer1_kernel<T, METHOD>), dim3((unsigned)((threads + bs - 1) / bs)), dim3(bs), 0,
                        a.stream, C, n1, a.centres, a.halves, wptr<T>(m.L[0]), bptr<T>(m.L[0]),
-                       Lh >= 2 ? w.F[cur] : (T*)nullptr, Y[1], A[1], B[1], G[1]);
+                       Lh >= 2 ? w.F[cur] : (T*)nullptr, Y[1], A[1], B[1], G[1], S[1]);
+    if (marg) {
+      hipError_t e = launch_aa_margin_hidden<T>(C, 3, n1, wtptr<T>(m.L[0]), bptr<T>(m.L[0]), nullptr, nullptr, nullptr,
+                                                nullptr, a.centres, a.halves, Y[1], S[1], A[1], B[1], G[1], R[1],
+                                                aa_margin_consts<T>(u, 0.0, 3, D), a.stream);
+      if (e != hipSuccess) return e;
+    }
   }
   for (int h = 2; h <= Lh; ++h) {
     const int n_in = m.pw[h - 1], n_out = m.pw[h];
@@ -479,7 +511,8 @@ static hipError_t propagate_impl(const PropArgs& a, PropWork<T>& w, bool use_mfm
     }
     if (use_mfma) {
       hipError_t e = hidden_mfma<T>(METHOD, C, n_in, n_out, cols_in, wtptr<T>(m.L[h - 1]), bptr<T>(m.L[h - 1]),
-                                    w.F[cur], A[h - 1], B[h - 1], G[h - 1], Fout, Y[h], A[h], B[h], G[h], a.stream);
+                                    w.F[cur], A[h - 1], B[h - 1], G[h - 1], Fout, Y[h], A[h], B[h], G[h], S[h],
+                                    a.stream);
       if (e != hipSuccess) return e;
     } else {
       constexpr int CT = sizeof(T) == 8 ? 8 : 16;
@@ -487,9 +520,16 @@ static hipError_t propagate_impl(const PropArgs& a, PropWork<T>& w, bool use_mfm
       const size_t lds = (size_t)CT * n_in * sizeof(T);
       hipLaunchKernelGGL((hidden_simt_kernel<T, METHOD, CT>), dim3((unsigned)C), dim3(bs), lds, a.stream, C, n_in,
                          n_out, cols_in, wtptr<T>(m.L[h - 1]), bptr<T>(m.L[h - 1]), w.F[cur], A[h - 1], B[h - 1],
-                         G[h - 1], Fout, Y[h], A[h], B[h], G[h]);
+                         G[h - 1], Fout, Y[h], A[h], B[h], G[h], S[h]);
     }
     if (prof) a.prof->end(rec, a.stream);
+    D += n_in;
+    if (marg) {
+      hipError_t e = launch_aa_margin_hidden<T>(C, n_in, n_out, wtptr<T>(m.L[h - 1]), bptr<T>(m.L[h - 1]), Y[h - 1],
+                                                A[h - 1], B[h - 1], R[h - 1], a.centres, a.halves, Y[h], S[h], A[h],
+                                                B[h], G[h], R[h], aa_margin_consts<T>(u, 0.0, n_in, D), a.stream);
+      if (e != hipSuccess) return e;
+    }
     cur ^= 1;
   }
   Profiler::Rec rec{};
@@ -512,6 +552,16 @@ static hipError_t propagate_impl(const PropArgs& a, PropWork<T>& w, bool use_mfm
                        a.out32, a.out64);
   }
   if (prof) a.prof->end(rec, a.stream);
+  if (marg) {
+    int kmax = 3;
+    for (int h = 1; h <= Lh; ++h) kmax = std::max(kmax, m.pw[h]);
+    AaMargin<T> k = aa_margin_consts<T>(u, 0.0, m.pw[Lh], D + m.pw[Lh]);
+    // the downward read-off: (layers + 1) products of length <= kmax
+    k.c = (T)((m.n_linear + 1) * ((kmax + 1) * u / (1.0 - (kmax + 1) * u)));
+    hipError_t e = launch_aa_margin_output<T>(C, m.pw[Lh], wtptr<T>(m.L[Lh]), bptr<T>(m.L[Lh]), Y[Lh], A[Lh], B[Lh],
+                                              R[Lh], a.centres, a.halves, a.out32, a.out64, k, a.stream);
+    if (e != hipSuccess) return e;
+  }
   return hipGetLastError();
 }
 

@@ -426,3 +426,86 @@ def test_fp64_band_reproduces_oracle_active_sets(ctx, prec_name):
         assert not bad, bad
     finally:
         ctx.unload_mlp(mid)
+
+
+MARGIN_CASES = [
+    ("fp32-mfma", [3, 64, 64, 64, 1], 0),
+    ("fp32-simt", [3, 48, 40, 1], 1),
+    ("bf16", [3, 128, 128, 128, 1], 0),
+    ("fp64", [3, 64, 64, 64, 1], 0),
+]
+
+
+@pytest.mark.parametrize("name,widths,kernel", MARGIN_CASES, ids=[c[0] for c in MARGIN_CASES])
+def test_aa_margin_contains_sampled_and_oracle_ranges(ctx, name, widths, kernel):
+    """ISX_AA_MARGIN: the widened AA range of every box contains the float64
+    values of the network at a 9^3 grid, 500 random points and the corners
+    of the box, and contains the float64 oracle's AA range; without the
+    margin the float32 ranges stay within 1e-5 of the oracle."""
+    import paper_2402_13861_amd as isx
+
+    prec = {"fp32-mfma": isx.FP32, "fp32-simt": isx.FP32, "bf16": isx.BF16, "fp64": isx.FP64}[name]
+    mlp = he_normal_mlp(widths, seed=21)
+    S = output_scale(mlp)
+    mid = ctx.load_weights(mlp)
+    try:
+        c, h, _ = random_boxes(300, range(0, 9), seed=22)
+        x0o, ro = propagate(mlp, c, h, AA)
+        ctx.set_option(isx.AA_MARGIN, 1)
+        g, g64 = _gpu_prop(ctx, mid, isx.AA, prec, c, h, kernel=kernel)
+        ctx.set_option(isx.AA_MARGIN, 0)
+        if g64 is not None:
+            g = g64
+        lo, hi = g[:, 0].astype(np.float64) - g[:, 1], g[:, 0].astype(np.float64) + g[:, 1]
+        # the oracle's exact-arithmetic range is inside
+        assert (lo <= x0o - ro).all() and (hi >= x0o + ro).all(), name
+        g1 = np.linspace(-1, 1, 9)
+        unit = np.concatenate([np.stack(np.meshgrid(g1, g1, g1, indexing="ij"), -1).reshape(-1, 3),
+                               np.random.default_rng(23).uniform(-1, 1, (500, 3))])
+        for i in range(c.shape[0]):
+            v = mlp_forward(mlp, c[i].astype(np.float64) + unit * h[i].astype(np.float64))
+            assert lo[i] <= v.min() and v.max() <= hi[i], (name, i)
+        widen = (g[:, 1] - ro) / np.maximum(np.abs(x0o) + ro, S)
+        print(f"{name}: widened spread minus oracle spread, relative: median {np.median(widen):.2e} "
+              f"max {widen.max():.2e}", flush=True)
+    finally:
+        ctx.set_option(isx.AA_MARGIN, 0)
+        ctx.unload_mlp(mid)
+
+
+@pytest.mark.parametrize("prec_name", ["fp32", "bf16"])
+def test_aa_margin_keeps_exact_affine_ranges_sound(ctx, prec_name):
+    """On boxes where every neuron is active the network is affine there, AA
+    is exact and the range is attained at box corners.  With the margin the
+    float32 / bfloat16 range contains every corner value (float64); the
+    count of boxes whose plain float range misses a corner is reported."""
+    import paper_2402_13861_amd as isx
+    from workloads.weights import MLPWeights
+
+    prec = isx.FP32 if prec_name == "fp32" else isx.BF16
+    rng = np.random.default_rng(31)
+    widths = [3, 64, 64, 64, 1]
+    Ws, bs = [], []
+    for a, b in zip(widths[:-1], widths[1:]):
+        Ws.append((rng.uniform(0.0, 1.0, (b, a)) / a).astype(np.float32))
+        bs.append(rng.uniform(0.5, 1.0, b).astype(np.float32))
+    mlp = MLPWeights(Ws=Ws, bs=bs)
+    mid = ctx.load_weights(mlp)
+    try:
+        c = rng.uniform(-0.5, 0.5, (200, 3)).astype(np.float32)
+        h = np.full((200, 3), 0.25, dtype=np.float32)
+        corners = np.array([[sx, sy, sz] for sx in (-1, 1) for sy in (-1, 1) for sz in (-1, 1)], dtype=float)
+        vals = np.stack([mlp_forward(mlp, c[i].astype(float) + corners * h[i].astype(float)) for i in range(200)])
+        missed = {}
+        for marg in (0, 1):
+            ctx.set_option(isx.AA_MARGIN, marg)
+            g, _ = _gpu_prop(ctx, mid, isx.AA, prec, c, h)
+            lo = g[:, 0].astype(np.float64) - g[:, 1]
+            hi = g[:, 0].astype(np.float64) + g[:, 1]
+            missed[marg] = int(((vals.min(axis=1) < lo) | (vals.max(axis=1) > hi)).sum())
+        print(f"{prec_name}: boxes whose range misses a corner value: plain {missed[0]}, with margin {missed[1]}",
+              flush=True)
+        assert missed[1] == 0
+    finally:
+        ctx.set_option(isx.AA_MARGIN, 0)
+        ctx.unload_mlp(mid)
