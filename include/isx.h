@@ -168,6 +168,17 @@ typedef struct {
  * ISX_EHIP. */
 isx_status isx_extract(isx_ctx* ctx, int32_t mlp_id, const isx_params* params, isx_mesh** out);
 
+/* isx_extract_batch: isx_extract of n INRs (mlp_ids[i], each with its own
+ * iso-values and attached surrogate) with the same params; out[i] receives
+ * INR i's mesh.  The INRs are dealt to up to ISX_BATCH_WORKERS worker
+ * contexts, each with its own stream and scratch and one host thread, so
+ * that the level loops of different INRs overlap on the device; each mesh is
+ * identical to the one isx_extract returns.  Waits for the caller's stream
+ * first; synchronous.  On an error every mesh of the call is freed, out[i]
+ * is NULL and isx_last_error names the INR. */
+isx_status isx_extract_batch(isx_ctx* ctx, int32_t n, const int32_t* mlp_ids, const isx_params* params,
+                             isx_mesh** out);
+
 /* Sizes of a mesh: triangles, active leaves, distinct leaf corners, and the
  * number of octree levels recorded (max_depth + 1). */
 isx_status isx_mesh_info(const isx_mesh* mesh, int64_t* n_tris, int64_t* n_leaves, int64_t* n_corners,
@@ -292,11 +303,13 @@ typedef enum {
                               bfloat16 products per layer (f within ~3e-4 of max(|f|, output scale), s
                               within ~2e-3 relative; used when every hidden layer has the same width
                               <= 256, else float32), 0 = float32 MFMA */
-  ISX_AA_MARGIN = 9        /* affine arithmetic: 1 = widen every layer by the rounding margin of its
+  ISX_AA_MARGIN = 9,       /* affine arithmetic: 1 = widen every layer by the rounding margin of its
                               floating-point evaluation (operand rounding 2^-8 for bfloat16 products,
                               accumulation 2^-24 float32 / 2^-53 float64), so that the returned range
                               contains the exact range of the network over the box; 0 (default) = the
                               paper's rule (exact arithmetic assumed) evaluated in floating point */
+  ISX_BATCH_WORKERS = 10   /* isx_extract_batch: worker contexts (streams) that run INRs at once, 1..16
+                              (default 4) */
 } isx_option;
 isx_status isx_set_option(isx_ctx* ctx, isx_option option, int64_t value);
 

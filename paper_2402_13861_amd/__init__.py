@@ -21,7 +21,7 @@ import numpy as np
 
 from . import _lib
 from ._lib import (AA, BF16, BF16_VARIANT, FP32, FP64, HIDDEN_KERNEL, KEEP_LEVELS, PROFILE, SCRATCH_BYTES, UP,
-                   UP_FORM, LIN_PRECISION, AA_MARGIN, VERBOSE)
+                   UP_FORM, LIN_PRECISION, AA_MARGIN, BATCH_WORKERS, VERBOSE)
 
 KERNEL_KINDS = ("hidden_fp32", "hidden_bf16", "hidden_simt_fp32", "hidden_fp64", "dense", "output",
                 "hidden_cov_bf16", "linearize")
@@ -294,6 +294,18 @@ class Context:
         h = C.c_void_p()
         self._chk(self._L.isx_extract(self._h, mlp_id, C.byref(p), C.byref(h)))
         return Mesh(self._L, h)
+
+    def extract_batch(self, mlp_ids, method: int = UP, precision: int = FP32, k: float = 3.0, max_depth: int = 6,
+                      fp64_band: float = 0.0, max_cells: int = 0, chunk_cells: int = 0,
+                      use_surrogate: bool = False) -> list:
+        """isx_extract of several INRs with the same parameters, run on
+        ISX_BATCH_WORKERS streams at once; returns one Mesh per INR."""
+        p = _lib.Params(method, precision, float(k), int(max_depth), float(fp64_band), int(max_cells),
+                        int(chunk_cells), int(bool(use_surrogate)))
+        ids = (C.c_int32 * len(mlp_ids))(*[int(i) for i in mlp_ids])
+        hs = (C.c_void_p * len(mlp_ids))()
+        self._chk(self._L.isx_extract_batch(self._h, len(mlp_ids), ids, C.byref(p), hs))
+        return [Mesh(self._L, C.c_void_p(h)) for h in hs]
 
 
 class Mesh:

@@ -7,6 +7,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
+#include <thread>
 #include <string>
 #include <vector>
 
@@ -68,6 +70,12 @@ struct isx_ctx {
   Buf rc_flags, rc_fidx, rc_fmask;
   int64_t* h_count = nullptr;  // pinned
   Profiler prof;
+  // batched extraction: worker contexts with their own stream and scratch;
+  // a worker borrows its parent's models and surrogates (never frees them)
+  std::vector<isx_ctx*> workers;
+  bool borrowed = false;
+  bool own_stream = false;
+  int batch_workers = 4;
 };
 
 struct isx_mesh {
@@ -293,7 +301,13 @@ isx_status isx_create(int device, void* hip_stream, isx_ctx** out) {
 isx_status isx_destroy(isx_ctx* ctx) {
   if (!ctx) return ISX_EINVAL;
   (void)hipSetDevice(ctx->device);
+  for (isx_ctx* w : ctx->workers) (void)isx_destroy(w);
+  ctx->workers.clear();
   (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->borrowed) {
+    ctx->models.clear();
+    ctx->surs.clear();
+  }
   for (Model& m : ctx->models) {
     for (int l = 0; l < ISX_MAX_LINEAR; ++l) free_layer(m.L[l]);
     free_model_table(m);
@@ -314,6 +328,7 @@ isx_status isx_destroy(isx_ctx* ctx) {
   for (Buf& b : ctx->sur_act) release(b);
   for (int i = 0; i < (int)ctx->surs.size(); ++i) isx_surrogate_free(ctx, i);
   if (ctx->h_count) (void)hipHostFree(ctx->h_count);
+  if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return ISX_OK;
 }
@@ -339,6 +354,10 @@ isx_status isx_set_option(isx_ctx* ctx, isx_option option, int64_t value) {
     case ISX_UP_FORM:
       if (value < 0 || value > 1) return fail(ctx, ISX_EINVAL, "ISX_UP_FORM must be 0 or 1");
       ctx->up_form = (int)value;
+      return ISX_OK;
+    case ISX_BATCH_WORKERS:
+      if (value < 1 || value > 16) return fail(ctx, ISX_EINVAL, "ISX_BATCH_WORKERS must be in [1, 16]");
+      ctx->batch_workers = (int)value;
       return ISX_OK;
     case ISX_AA_MARGIN:
       if (value < 0 || value > 1) return fail(ctx, ISX_EINVAL, "ISX_AA_MARGIN must be 0 or 1");
@@ -906,6 +925,89 @@ isx_status isx_extract(isx_ctx* ctx, int32_t mlp_id, const isx_params* p, isx_me
   for (auto& e : ev) (void)hipEventDestroy(e);
 #undef XCHK
   *out = mesh;
+  return ISX_OK;
+}
+
+// Batched extraction: the INRs are dealt to up to ISX_BATCH_WORKERS worker
+// contexts, each with its own stream and level scratch, driven by one host
+// thread each, so that the level loops of different INRs (small launches and
+// host reads of level counts) overlap on the device.
+static isx_status make_worker(isx_ctx* ctx, isx_ctx** out) {
+  isx_ctx* w = new isx_ctx();
+  w->device = ctx->device;
+  w->borrowed = true;
+  w->own_stream = true;
+  hipError_t e = hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&w->h_count, 4 * sizeof(int64_t), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    if (w->stream) (void)hipStreamDestroy(w->stream);
+    delete w;
+    return hip_fail(ctx, e, "batch worker");
+  }
+  *out = w;
+  return ISX_OK;
+}
+
+isx_status isx_extract_batch(isx_ctx* ctx, int32_t n, const int32_t* mlp_ids, const isx_params* p,
+                             isx_mesh** out) {
+  if (!ctx || n < 0 || (n > 0 && (!mlp_ids || !p || !out))) return fail(ctx, ISX_EINVAL, "bad arguments");
+  for (int32_t i = 0; i < n; ++i) {
+    out[i] = nullptr;
+    if (!get_model(ctx, mlp_ids[i])) return fail(ctx, ISX_EINVAL, "bad mlp id at " + std::to_string(i));
+  }
+  if (n == 0) return ISX_OK;
+  (void)hipSetDevice(ctx->device);
+  // the caller's stream may hold work the INRs depend on
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  const int nw = std::min<int>(ctx->batch_workers, n);
+  while ((int)ctx->workers.size() < nw) {
+    isx_ctx* w = nullptr;
+    const isx_status st = make_worker(ctx, &w);
+    if (st != ISX_OK) return st;
+    ctx->workers.push_back(w);
+  }
+  for (int i = 0; i < nw; ++i) {
+    isx_ctx* w = ctx->workers[i];
+    w->models = ctx->models;
+    w->surs = ctx->surs;
+    w->kernel_choice = ctx->kernel_choice;
+    w->bf16_variant = ctx->bf16_variant;
+    w->up_form = ctx->up_form;
+    w->lin_prec = ctx->lin_prec;
+    w->aa_margin = ctx->aa_margin;
+    w->keep_levels = ctx->keep_levels;
+    w->verbose = false;
+    w->prop_budget = std::max<size_t>(size_t(1) << 28, ctx->prop_budget / nw);
+  }
+  std::atomic<int32_t> next{0};
+  std::vector<isx_status> st(nw, ISX_OK);
+  std::vector<std::string> err(nw);
+  auto run = [&](int wi) {
+    isx_ctx* w = ctx->workers[wi];
+    (void)hipSetDevice(w->device);
+    for (int32_t i = next.fetch_add(1); i < n; i = next.fetch_add(1)) {
+      const isx_status s = isx_extract(w, mlp_ids[i], p, &out[i]);
+      if (s != ISX_OK) {
+        st[wi] = s;
+        err[wi] = "INR " + std::to_string(i) + ": " + w->err;
+        next.store(n);
+        return;
+      }
+    }
+  };
+  std::vector<std::thread> threads;
+  for (int wi = 1; wi < nw; ++wi) threads.emplace_back(run, wi);
+  run(0);
+  for (std::thread& t : threads) t.join();
+  for (int wi = 0; wi < nw; ++wi) {
+    if (st[wi] != ISX_OK) {
+      for (int32_t i = 0; i < n; ++i) {
+        if (out[i]) isx_mesh_free(out[i]);
+        out[i] = nullptr;
+      }
+      return fail(ctx, st[wi], err[wi]);
+    }
+  }
   return ISX_OK;
 }
 
