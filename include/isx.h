@@ -281,6 +281,19 @@ isx_status isx_surrogate_attach(isx_ctx* ctx, int32_t mlp_id, int32_t sur_id, in
                                 const float* h_z_accept, int32_t accept_leaves);
 isx_status isx_surrogate_free(isx_ctx* ctx, int32_t sur_id);
 
+/* isx_surrogate_save_file: write surrogate sur_id to `path` (binary, little
+ * endian): "ISXSUR01", int32 n_linear, int32 widths[n_linear + 1], float32
+ * mu_bar, S, a, b, s_floor, int32 has_base, then per layer the row-major
+ * float32 W and b.  Synchronous.  ISX_EINVAL on a bad id or an unwritable
+ * path.
+ * isx_surrogate_load_file: read such a file into a new surrogate (*sur_id);
+ * a file written with a base becomes corrections to the linearisation of
+ * base_mlp_id (which must then be a loaded MLP; -1 is an error for such a
+ * file and is required otherwise).  ISX_EINVAL on a missing or malformed
+ * file. */
+isx_status isx_surrogate_save_file(isx_ctx* ctx, int32_t sur_id, const char* path);
+isx_status isx_surrogate_load_file(isx_ctx* ctx, const char* path, int32_t base_mlp_id, int32_t* sur_id);
+
 /* Copy the library's marching-cubes case table: h_count[256] triangles per
  * case (case bit i set iff corner i < iso-value; corners (0,0,0) (1,0,0)
  * (1,1,0) (0,1,0) (0,0,1) (1,0,1) (1,1,1) (0,1,1)), h_edges[256][15] edge

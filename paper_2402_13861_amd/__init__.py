@@ -266,6 +266,25 @@ class Context:
     def surrogate_free(self, sid: int):
         self._chk(self._L.isx_surrogate_free(self._h, sid))
 
+    def surrogate_save(self, sid: int, path: str):
+        """Write surrogate sid (weights, normalisation, base flag) to a file."""
+        self._chk(self._L.isx_surrogate_save_file(self._h, sid, str(path).encode()))
+
+    def surrogate_load_file(self, path: str, base_mlp: int = -1) -> int:
+        """Read a file written by surrogate_save; base_mlp is the MLP whose
+        linearisation a base-mode surrogate corrects (-1 for none)."""
+        out = C.c_int32()
+        self._chk(self._L.isx_surrogate_load_file(self._h, str(path).encode(), int(base_mlp), C.byref(out)))
+        sid = out.value
+        # shapes for surrogate_weights: read back from the file header
+        with open(path, "rb") as f:
+            f.read(8)
+            L = int(np.frombuffer(f.read(4), dtype=np.int32)[0])
+            w = np.frombuffer(f.read(4 * (L + 1)), dtype=np.int32)
+        self._sur_shapes = getattr(self, "_sur_shapes", {})
+        self._sur_shapes[sid] = [(int(w[l + 1]), int(w[l])) for l in range(L)]
+        return sid
+
     def eval_points(self, mlp_id: int, precision: int, pts, vals):
         import torch
 

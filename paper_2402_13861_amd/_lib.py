@@ -84,6 +84,8 @@ _SIGS = [
                                        C.POINTER(C.c_float), C.POINTER(C.c_float), C.POINTER(C.c_float),
                                        C.c_int32]),
     ("isx_surrogate_free", C.c_int, [C.c_void_p, C.c_int32]),
+    ("isx_surrogate_save_file", C.c_int, [C.c_void_p, C.c_int32, C.c_char_p]),
+    ("isx_surrogate_load_file", C.c_int, [C.c_void_p, C.c_char_p, C.c_int32, C.POINTER(C.c_int32)]),
     ("isx_get_profile", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                   C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int32]),
 ]

@@ -1132,6 +1132,78 @@ isx_status isx_surrogate_free(isx_ctx* ctx, int32_t sur_id) {
   return ISX_OK;
 }
 
+isx_status isx_surrogate_save_file(isx_ctx* ctx, int32_t sur_id, const char* path) {
+  Sur* S = get_sur(ctx, sur_id);
+  if (!S || !path) return fail(ctx, ISX_EINVAL, "bad surrogate id or path");
+  std::vector<std::vector<float>> W(S->L), b(S->L);
+  std::vector<float*> pw(S->L), pb(S->L);
+  for (int l = 0; l < S->L; ++l) {
+    W[l].resize((size_t)S->w[l + 1] * S->w[l]);
+    b[l].resize(S->w[l + 1]);
+    pw[l] = W[l].data();
+    pb[l] = b[l].data();
+  }
+  const isx_status st = isx_surrogate_get(ctx, sur_id, pw.data(), pb.data());
+  if (st != ISX_OK) return st;
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(ctx, ISX_EINVAL, std::string("cannot write ") + path);
+  bool ok = std::fwrite("ISXSUR01", 1, 8, f) == 8;
+  const int32_t L = S->L, has_base = S->base_mlp >= 0 ? 1 : 0;
+  const float norm[5] = {S->mu_bar, S->scale, S->size_a, S->size_b, S->s_floor};
+  ok = ok && std::fwrite(&L, 4, 1, f) == 1 && std::fwrite(S->w, 4, L + 1, f) == (size_t)(L + 1) &&
+       std::fwrite(norm, 4, 5, f) == 5 && std::fwrite(&has_base, 4, 1, f) == 1;
+  for (int l = 0; ok && l < L; ++l)
+    ok = std::fwrite(W[l].data(), 4, W[l].size(), f) == W[l].size() &&
+         std::fwrite(b[l].data(), 4, b[l].size(), f) == b[l].size();
+  ok = (std::fclose(f) == 0) && ok;
+  return ok ? ISX_OK : fail(ctx, ISX_EINVAL, std::string("write failed: ") + path);
+}
+
+isx_status isx_surrogate_load_file(isx_ctx* ctx, const char* path, int32_t base_mlp_id, int32_t* sur_id) {
+  if (!ctx || !path || !sur_id) return fail(ctx, ISX_EINVAL, "bad arguments");
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(ctx, ISX_EINVAL, std::string("cannot read ") + path);
+  char magic[8];
+  int32_t L = 0, has_base = 0;
+  int32_t w[ISX_MAX_LINEAR + 1] = {};
+  float norm[5] = {};
+  bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "ISXSUR01", 8) == 0 &&
+            std::fread(&L, 4, 1, f) == 1 && L >= 1 && L <= ISX_MAX_LINEAR &&
+            std::fread(w, 4, L + 1, f) == (size_t)(L + 1) && std::fread(norm, 4, 5, f) == 5 &&
+            std::fread(&has_base, 4, 1, f) == 1;
+  for (int l = 0; ok && l <= L; ++l) ok = w[l] >= 1 && w[l] <= 4096;
+  std::vector<std::vector<float>> W, b;
+  if (ok) {
+    W.resize(L);
+    b.resize(L);
+    for (int l = 0; ok && l < L; ++l) {
+      W[l].resize((size_t)w[l + 1] * w[l]);
+      b[l].resize(w[l + 1]);
+      ok = std::fread(W[l].data(), 4, W[l].size(), f) == W[l].size() &&
+           std::fread(b[l].data(), 4, b[l].size(), f) == b[l].size();
+    }
+  }
+  std::fclose(f);
+  if (!ok) return fail(ctx, ISX_EINVAL, std::string("malformed surrogate file ") + path);
+  if ((has_base != 0) != (base_mlp_id >= 0))
+    return fail(ctx, ISX_EINVAL, has_base ? "the file's surrogate needs a base MLP" : "the file has no base");
+  std::vector<const float*> pw(L), pb(L);
+  for (int l = 0; l < L; ++l) {
+    pw[l] = W[l].data();
+    pb[l] = b[l].data();
+  }
+  int32_t id = -1;
+  isx_status st = isx_surrogate_load(ctx, L, w, pw.data(), pb.data(), &id);
+  if (st == ISX_OK) st = isx_surrogate_set_norm(ctx, id, norm[0], norm[1], norm[2], norm[3]);
+  if (st == ISX_OK && has_base) st = isx_surrogate_set_base(ctx, id, base_mlp_id, norm[4]);
+  if (st != ISX_OK) {
+    if (id >= 0) (void)isx_surrogate_free(ctx, id);
+    return st;
+  }
+  *sur_id = id;
+  return ISX_OK;
+}
+
 isx_status isx_surrogate_get(isx_ctx* ctx, int32_t sur_id, float* const* h_W, float* const* h_b) {
   Sur* S = get_sur(ctx, sur_id);
   if (!S || !h_W || !h_b) return fail(ctx, ISX_EINVAL, "bad arguments");

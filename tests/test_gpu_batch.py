@@ -96,3 +96,45 @@ def test_extract_batch_reports_a_bad_inr(ctx):
         assert ms[0].n_leaves == ms[1].n_leaves
     finally:
         ctx.unload_mlp(mid)
+
+
+def test_extract_batch_overlaps_small_inrs(ctx):
+    """32 small INRs (3->64x3->1, depth 6, BF16): the level loops are
+    launch- and sync-bound, so running them on several streams at once is
+    faster than one after another.  Prints both times; the meshes agree."""
+    import paper_2402_13861_amd as isx
+
+    ids = []
+    try:
+        for i in range(32):
+            mlp = he_normal_mlp([3, 64, 64, 64, 1], seed=6400 + i)
+            vals = mlp_forward(mlp, uniform_points(2000, seed=6500 + i))
+            mid = ctx.load_weights(mlp)
+            ctx.set_isovalues(mid, [float(np.median(vals))])
+            ids.append(mid)
+        kw = dict(method=isx.UP, precision=isx.BF16, k=3.0, max_depth=6)
+        for m in [ctx.extract(i, **kw) for i in ids]:
+            m.free()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        singles = [ctx.extract(i, **kw) for i in ids]
+        t_single = time.perf_counter() - t0
+        times = {}
+        for workers in (1, 4, 8):
+            ctx.set_option(isx.BATCH_WORKERS, workers)
+            for m in ctx.extract_batch(ids, **kw):
+                m.free()
+            t0 = time.perf_counter()
+            batch = ctx.extract_batch(ids, **kw)
+            times[workers] = time.perf_counter() - t0
+            assert [m.n_tris for m in batch] == [m.n_tris for m in singles]
+            for m in batch:
+                m.free()
+        print("32 INRs 3->64x3->1, depth 6, BF16: one by one %.1f ms; batch %s" %
+              (t_single * 1e3, ", ".join(f"{w} workers {t * 1e3:.1f} ms" for w, t in times.items())), flush=True)
+        for m in singles:
+            m.free()
+    finally:
+        ctx.set_option(isx.BATCH_WORKERS, 4)
+        for mid in ids:
+            ctx.unload_mlp(mid)

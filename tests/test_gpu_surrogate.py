@@ -203,3 +203,44 @@ def test_surrogate_with_base_gains_over_plain_extraction(ctx):
         assert n_sur < 0.75 * n_plain
     finally:
         ctx.unload_mlp(mid)
+
+
+def test_surrogate_file_round_trip(ctx, tmp_path):
+    """isx_surrogate_save_file / isx_surrogate_load_file: the reloaded
+    surrogate (weights, normalisation, linearisation base) predicts exactly
+    what the saved one does; a base-mode file needs its MLP."""
+    import paper_2402_13861_amd as isx
+
+    mid = None
+    try:
+        mlp = he_normal_mlp([3, 32, 32, 1], seed=4)
+        mid = ctx.load_weights(mlp)
+        rng = np.random.default_rng(9)
+        Ws = [rng.standard_normal((o, i)).astype(np.float32) * 0.3 for i, o in [(4, 16), (16, 16), (16, 2)]]
+        bs = [rng.standard_normal(o).astype(np.float32) * 0.1 for o in (16, 16, 2)]
+        c, h, _ = random_boxes(1000, range(2, 8), seed=3)
+        C_, H_ = torch.from_numpy(c).cuda(), torch.from_numpy(h).cuda()
+        for base in (False, True):
+            sid = ctx.surrogate_load(Ws, bs)
+            ctx.surrogate_set_norm(sid, 0.1, 0.7, 0.25, 1.0)
+            if base:
+                ctx.surrogate_set_base(sid, mid, 1e-4)
+            p0 = torch.empty((1000, 2), device="cuda")
+            ctx.surrogate_predict(sid, C_, H_, p0)
+            path = tmp_path / f"sur_{int(base)}.bin"
+            ctx.surrogate_save(sid, path)
+            if base:
+                with pytest.raises(isx.IsxError):
+                    ctx.surrogate_load_file(path, -1)
+            sid2 = ctx.surrogate_load_file(path, mid if base else -1)
+            p1 = torch.empty((1000, 2), device="cuda")
+            ctx.surrogate_predict(sid2, C_, H_, p1)
+            torch.cuda.synchronize()
+            assert torch.equal(p0, p1), base
+            W2, b2 = ctx.surrogate_weights(sid2)
+            assert all(np.array_equal(a, b) for a, b in zip(Ws, W2))
+            ctx.surrogate_free(sid)
+            ctx.surrogate_free(sid2)
+    finally:
+        if mid is not None:
+            ctx.unload_mlp(mid)
