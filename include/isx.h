@@ -155,7 +155,7 @@ typedef struct {
                               float64 and that result decides (not with ISX_FP64) */
   int64_t max_cells;       /* capacity of one level (0 = library default); a
                               level above it fails with ISX_ECAPACITY */
-  int64_t chunk_cells;     /* cells propagated per batch (0 = automatic) */
+  int64_t chunk_cells;     /* cells propagated per batch (0 = automatic; at most 2^22) */
   int32_t use_surrogate;   /* 1: decide cells with the surrogate attached to
                               the MLP where it is confident (see
                               isx_surrogate_attach), propagate the rest */

@@ -174,10 +174,14 @@ size_t per_cell_bytes(const Model& m) {
   return (2 * prop_F_elems(m, 1) + prop_vec_elems(m, 1, true)) * sizeof(T);
 }
 
+// Cells per propagation chunk at most: kernels that give a cell a whole
+// workgroup keep a launch's work-items below 2^32 with it.
+constexpr int64_t kMaxPropChunk = int64_t(1) << 22;
+
 template <typename T>
 int64_t chunk_for(isx_ctx* ctx, const Model& m, int64_t n, int64_t req) {
   int64_t c = req > 0 ? req : (int64_t)(ctx->prop_budget / per_cell_bytes<T>(m));
-  c = std::max<int64_t>(1, std::min<int64_t>(c, n));
+  c = std::max<int64_t>(1, std::min<int64_t>({c, n, kMaxPropChunk}));
   return c;
 }
 
@@ -209,7 +213,7 @@ isx_status run_propagate(isx_ctx* ctx, const Model& m, isx_method method, isx_pr
     const bool cov = method == ISX_UP && ctx->up_form == 0 && cov_supported(m);
     const size_t per_cell = (cov ? 0 : 2 * prop_F_elems_bf16(m, 1) * 2) + prop_vec_elems(m, 1, marg) * 4;
     int64_t chunk = chunk_req > 0 ? chunk_req : (int64_t)(ctx->prop_budget / per_cell);
-    chunk = std::max<int64_t>(1, std::min<int64_t>(chunk, n));
+    chunk = std::max<int64_t>(1, std::min<int64_t>({chunk, n, kMaxPropChunk}));
     PropWork<float> w;
     if (!cov) {
       HIPCHK(ensure(ctx->Fbf[0], prop_F_elems_bf16(m, chunk) * 2));

@@ -23,13 +23,14 @@
 // gives P and the variances |P_j|^2 + sum_k W_2[j][k]^2 gamma_1k^2) and makes
 // one product, whose accumulators start from P_i . P_j.
 // Per layer h >= 3 (8 waves, 512 threads):
-//   2. T = W_h X_{h-1}: each wave computes a tile of RPW x CPW blocks of
-//      32 x 32, with A = bfloat16 fragments of its weight rows streamed from
-//      the L2-resident fragment-order copy of W a few k-steps ahead (a wave's
-//      fragment load is one 1 KiB run), and B = rows of X from LDS (X is
-//      symmetric, so its rows serve as B columns).  A weight fragment serves
-//      CPW products and an LDS fragment RPW.
-//   3. T replaces X in LDS (row-major).
+//   2. T = W_h X_{h-1}, computed as T^T = X W_h^T: each wave computes a tile
+//      of RPW x CPW blocks of 32 x 32, with A = rows of X from LDS and B =
+//      bfloat16 fragments of its weight rows streamed from the L2-resident
+//      fragment-order copy of W a few k-steps ahead (a wave's fragment load
+//      is one 1 KiB run).  A weight fragment serves CPW products and an LDS
+//      fragment RPW.
+//   3. T replaces X in LDS (row-major); in the transposed product a lane's
+//      register quad holds four consecutive entries of one row of T.
 //   4. Per neuron (a quad of lanes), in one pass over its float32 weight
 //      row: the centre y = W z + b with z = alpha . y_{h-1} + beta, the
 //      variance C_h[j][j] = sum_k T[j][k] W[j][k], and the ReLU rule, which
@@ -319,8 +320,8 @@ __global__ __launch_bounds__(kCovThreads) void up_cov_bf16_kernel(int64_t C, int
       if (last) break;
       __syncthreads();
     } else {
-      // 2. T = W X on the wave's tile (rows: weight blocks, columns: X blocks,
-      //    X symmetric); 3. T -> LDS row-major once every wave has read X
+      // 2. T^T = X W^T on the wave's tile (X symmetric); 3. T -> LDS
+      //    row-major once every wave has read X
       {
         cv16f acc[RPW][CPW];
 #pragma unroll
@@ -329,19 +330,28 @@ __global__ __launch_bounds__(kCovThreads) void up_cov_bf16_kernel(int64_t C, int
           for (int c = 0; c < CPW; ++c)
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[r][c][e] = 0.f;
-        cov_tile_gemm<N, true>(wfrag, lfrag, tile, acc);
+        // as T^T = X W^T (rows: X blocks, columns: weight rows), so that a
+        // lane holds four consecutive entries of a row of T per register
+        // quad and writes them with one 8-byte store
+        cov_tile_gemm<N, false>(wfrag, lfrag, tile, acc);
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < RPW; ++r)
+        for (int r = 0; r < RPW; ++r) {
+          if (!wok[r]) continue;
+          const int j = (rg * RPW + r) * 32 + l32;
 #pragma unroll
-          for (int c = 0; c < CPW; ++c)
-            if (wok[r] && lok[c]) {
+          for (int c = 0; c < CPW; ++c) {
+            if (!lok[c]) continue;
 #pragma unroll
-              for (int e = 0; e < 16; ++e) {
-                const int row = (rg * RPW + r) * 32 + 8 * (e >> 2) + 4 * hi + (e & 3);
-                X[(size_t)row * STR + (cg * CPW + c) * 32 + l32] = (__bf16)acc[r][c][e];
-              }
+            for (int q4 = 0; q4 < 4; ++q4) {
+              const int i0 = (cg * CPW + c) * 32 + 8 * q4 + 4 * hi;
+              __bf16 v4[4];
+#pragma unroll
+              for (int e = 0; e < 4; ++e) v4[e] = (__bf16)acc[r][c][4 * q4 + e];
+              *reinterpret_cast<uint2*>(X + (size_t)j * STR + i0) = *reinterpret_cast<const uint2*>(v4);
             }
+          }
+        }
       }
       __syncthreads();
 
@@ -495,6 +505,8 @@ static hipError_t launch_cov_n(const Model& m, int64_t C, const float* centres, 
     if (e != hipSuccess) return e;
     attr_set = true;
   }
+  // one workgroup per cell: a launch's work-items must stay below 2^32
+  if (C > (int64_t(1) << 22)) return hipErrorInvalidValue;
   hipLaunchKernelGGL((up_cov_bf16_kernel<N>), dim3((unsigned)C), dim3(kCovThreads), CovShape<N>::LDS, s, C,
                      m.n_linear, m.dev_layers, vec, centres, halves);
   return hipGetLastError();

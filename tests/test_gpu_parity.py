@@ -350,6 +350,7 @@ BF16_WIDTHS = [
     [3, 96, 96, 96, 1],
     [3, 40, 40, 40, 1],  # padded to 64
     [3, 64, 64, 1],  # one hidden product (layer 2 is the last hidden layer)
+    [3, 64, 1],  # one hidden layer: no hidden product, the read-off alone
     [3, 32, 32, 32, 32, 32, 32, 32, 1],  # deep and narrow
     [3, 224, 224, 224, 1],  # two row groups per wave, width not a multiple of 128
 ]
@@ -381,6 +382,26 @@ def test_propagate_bf16_error_against_oracle(ctx, widths, mname):
             assert worst["centre"] <= 1e-2
     finally:
         ctx.set_option(isx.UP_FORM, 0)
+        ctx.unload_mlp(mid)
+
+
+def test_cov_propagate_past_one_grid(ctx):
+    """More cells than one launch grid takes (2^22 workgroups): the
+    covariance form splits the launch, and cells on both sides of the split
+    and at the end match the oracle."""
+    import paper_2402_13861_amd as isx
+
+    mlp = he_normal_mlp([3, 32, 32, 1], seed=3)
+    mid = ctx.load_weights(mlp)
+    try:
+        n = (1 << 22) + 777
+        c, h, _ = random_boxes(n, range(2, 10), seed=5)
+        g, _ = _gpu_prop(ctx, mid, isx.UP, isx.BF16, c, h)
+        assert np.isfinite(g).all()
+        pick = np.r_[0:16, (1 << 22) - 16:(1 << 22) + 16, n - 16:n]
+        ref = propagate(mlp, c[pick], h[pick], UP)
+        assert_pair_close(g[pick], ref, output_scale(mlp), 5e-2, "bf16 up past one grid", k=3.0, spread_rtol=0.2)
+    finally:
         ctx.unload_mlp(mid)
 
 
