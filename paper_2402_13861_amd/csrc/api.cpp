@@ -141,7 +141,7 @@ void free_model_table(Model& m) {
 }
 
 void free_layer(Layer& l) {
-  void* ps[] = {l.W, l.Wt, l.b, l.Wd, l.Wtd, l.bd, l.Wtbf, l.Wbf, l.Wfr, l.Wfrl, l.Wv};
+  void* ps[] = {l.W, l.Wt, l.b, l.Wd, l.Wtd, l.bd, l.Wtbf, l.Wbf, l.Wfr, l.Wfrl, l.Wv, l.Wq};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   l = Layer{};
@@ -465,7 +465,7 @@ isx_status isx_load_mlp(isx_ctx* ctx, int32_t n_linear, const int32_t* widths, c
       // copies in the covariance kernel's access orders
       const int N = no;
       std::vector<uint16_t> Wfr((size_t)N * N), Wfrl((size_t)N * N);
-      std::vector<float> Wv((size_t)N * N);
+      std::vector<float> Wv((size_t)N * N), Wq((size_t)N * N);
       for (int r = 0; r < N; ++r)
         for (int k = 0; k < N; ++k) {
           const uint16_t hb = Wbf[(size_t)r * N + k];
@@ -480,9 +480,12 @@ isx_status isx_load_mlp(isx_ctx* ctx, int32_t n_linear, const int32_t* widths, c
           for (int q = 0; q < 4; ++q)
             for (int x = 0; x < 8; ++x)
               Wv[cov_row_pos(N, r, q, m, x)] = W[(size_t)r * N + 8 * cov_row_chunk(N, q, m) + x];
+      for (int r = 0; r < N; ++r)
+        for (int k = 0; k < N; ++k) Wq[cov_quad_pos(N, r, k)] = W[(size_t)r * N + k];
       e = upload(&L.Wfr, Wfr);
       if (e == hipSuccess) e = upload(&L.Wfrl, Wfrl);
       if (e == hipSuccess) e = upload(&L.Wv, Wv);
+      if (e == hipSuccess) e = upload(&L.Wq, Wq);
     }
     if (e != hipSuccess) {
       for (int k = 0; k <= l; ++k) free_layer(m.L[k]);
@@ -493,7 +496,7 @@ isx_status isx_load_mlp(isx_ctx* ctx, int32_t n_linear, const int32_t* widths, c
     std::vector<DevLayer> table(n_linear);
     for (int l = 0; l < n_linear; ++l)
       table[l] = DevLayer{m.L[l].W,   m.L[l].Wbf, m.L[l].Wfr,  m.L[l].Wfrl,
-                          m.L[l].Wv,  m.L[l].b,   m.L[l].n_in, m.L[l].n_out};
+                          m.L[l].Wv,  m.L[l].Wq,  m.L[l].b,    m.L[l].n_in, m.L[l].n_out};
     hipError_t e = upload(&m.dev_layers, table);
     if (e != hipSuccess) {
       for (int k = 0; k < n_linear; ++k) free_layer(m.L[k]);

@@ -36,6 +36,7 @@ struct Layer {
   uint16_t* Wfr = nullptr;  // bfloat16 bits of W in MFMA fragment order (cov_frag_index)
   uint16_t* Wfrl = nullptr; // bfloat16 bits of W - bf16(W), same order
   float* Wv = nullptr;      // W with each row's chunks in row-pass order (cov_row_pos)
+  float* Wq = nullptr;      // W in accumulator-quad order (cov_quad_pos)
 };
 
 // Covariance-form layouts of a square N x N layer (N a multiple of 32, at
@@ -66,6 +67,16 @@ __host__ __device__ inline int64_t cov_row_pos(int N, int row, int q, int m, int
   return (int64_t)row * N + (4 * m + q) * 8 + e;
 }
 
+// Position of W[row][k] in the accumulator-quad copy.  In the transposed
+// product T^T = X W^T a lane (l32, hi) of the wave that owns row block rb and
+// column block cb holds, in register quad q4, T[rb 32 + l32][cb 32 + 8 q4 +
+// 4 hi + e], e = 0..3; the matching four weights are one float4, and the 64
+// lanes' float4s of one (rb, cb, q4) are adjacent (1 KiB).
+__host__ __device__ inline int64_t cov_quad_pos(int N, int row, int k) {
+  const int rb = row >> 5, l32 = row & 31, cb = k >> 5, q4 = (k >> 3) & 3, hi = (k >> 2) & 1, e = k & 3;
+  return ((((int64_t)(rb * (N >> 5) + cb) * 4 + q4) * 64) + hi * 32 + l32) * 4 + e;
+}
+
 // Per-layer pointers in device memory, for kernels that walk the layers with a
 // runtime index (one scalar load per layer instead of whole pointer arrays in
 // kernel arguments).
@@ -75,6 +86,7 @@ struct DevLayer {
   const uint16_t* Wfr;    // fragment order (square layers <= kCovNMax, else null)
   const uint16_t* Wfrl;   // W - bf16(W) in fragment order (same layers)
   const float* Wv;        // row-pass order (square layers <= kCovNMax, else null)
+  const float* Wq;        // accumulator-quad order (same layers)
   const float* b;         // [n_out]
   int n_in, n_out;        // padded widths
 };

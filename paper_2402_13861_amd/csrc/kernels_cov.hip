@@ -29,18 +29,17 @@
 //      fragment-order copy of W a few k-steps ahead (a wave's fragment load
 //      is one 1 KiB run).  A weight fragment serves CPW products and an LDS
 //      fragment RPW.
-//   3. T replaces X in LDS (row-major); in the transposed product a lane's
-//      register quad holds four consecutive entries of one row of T.
-//   4. Per neuron (a quad of lanes), in one pass over its float32 weight
-//      row: the centre y = W z + b with z = alpha . y_{h-1} + beta, the
-//      variance C_h[j][j] = sum_k T[j][k] W[j][k], and the ReLU rule, which
-//      gives (alpha, beta, gamma).  The quad's lanes read chunks of T that
-//      fall in distinct LDS banks for 4 neighbouring rows, and the weights
-//      come from a copy whose rows are permuted so that the same lanes read
-//      one 128-byte line per row and step.
+//   3. From the float32 accumulators (a lane's register quad holds four
+//      consecutive entries of one row j of T): T replaces X in LDS
+//      (row-major), and each lane sums its columns' share of the variance
+//      C_h[j][j] = sum_i T[j][i] W[j][i] and of the centre W[j] z, with z =
+//      alpha . y_{h-1} + beta, from a float32 copy of W in the accumulators'
+//      order (one 1 KiB run per wave and register quad).
+//   4. Per neuron, the column groups' partial sums, y = W z + b, and the
+//      ReLU rule, which gives (alpha, beta, gamma).
 //   5. C_h = T W_h^T on the wave's tile (A = rows of T from LDS, B = weight
 //      fragments, whose lane layout is the B layout of the transposed
-//      product).  The last hidden layer needs only step 4.
+//      product).  The last hidden layer stops after step 4 (and keeps no T).
 //   6. X_h = D C_h D + diag(gamma^2) goes to LDS as bfloat16 for layer h+1
 //      (C_h is symmetric, so the tile's columns are written as rows).
 // MFMA 32x32x16 bf16 layout (lane l): A (row l%32, k 8(l/32)+e), B (k
@@ -320,81 +319,91 @@ __global__ __launch_bounds__(kCovThreads) void up_cov_bf16_kernel(int64_t C, int
       if (last) break;
       __syncthreads();
     } else {
-      // 2. T^T = X W^T on the wave's tile (X symmetric); 3. T -> LDS
-      //    row-major once every wave has read X
+      // 2. T^T = X W^T on the wave's tile (X symmetric)
+      cv16f acc[RPW][CPW];
+#pragma unroll
+      for (int r = 0; r < RPW; ++r)
+#pragma unroll
+        for (int c = 0; c < CPW; ++c)
+#pragma unroll
+          for (int e = 0; e < 16; ++e) acc[r][c][e] = 0.f;
+      cov_tile_gemm<N, false>(wfrag, lfrag, tile, acc);
+      // 3. from the float32 accumulators: T -> LDS row-major (not needed
+      //    after the last hidden layer), and per weight row j the partial
+      //    sums of the variance C_h[j][j] = sum_i T[j][i] W[j][i] and of the
+      //    centre W[j] z over the tile's columns i, with the float32 weights
+      //    in accumulator order (one 1 KiB run per wave and register quad).
+      //    A lane's register quad holds four consecutive entries of row j;
+      //    the other half of the wave holds the next four.  The column
+      //    groups' partial sums meet in LDS that is free from layer 3 on
+      //    (G, P).  Blocks go in the order bi = r CPW + c; their weights
+      //    are loaded two blocks ahead, the first two before the barrier
+      //    (blocks outside the matrix read block 0 and are not used).
+      gfloat4* wq = (gfloat4*)Lw.Wq;
+      constexpr int NBL = RPW * CPW;
+      auto wq_at = [&](int bi, int q4) -> cv4f {
+        const int r = bi / CPW, c = bi % CPW;
+        const int rb = wok[r] ? rg * RPW + r : 0, cb = lok[c] ? cg * CPW + c : 0;
+        return wq[((int64_t)(rb * NB + cb) * 4 + q4) * 64 + lane];
+      };
+      cv4f wb[3][4];
+#pragma unroll
+      for (int bi = 0; bi < 2 && bi < NBL; ++bi)
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4) wb[bi][q4] = wq_at(bi, q4);
+      __syncthreads();  // every wave has read X
       {
-        cv16f acc[RPW][CPW];
+        float2* s_part = reinterpret_cast<float2*>(s_G);  // [CG][N]
+        float pv[RPW], py[RPW];
 #pragma unroll
-        for (int r = 0; r < RPW; ++r)
+        for (int r = 0; r < RPW; ++r) pv[r] = py[r] = 0.f;
 #pragma unroll
-          for (int c = 0; c < CPW; ++c)
+        for (int bi = 0; bi < NBL; ++bi) {
+          const int r = bi / CPW, c = bi % CPW;
+          if (bi + 2 < NBL) {
 #pragma unroll
-            for (int e = 0; e < 16; ++e) acc[r][c][e] = 0.f;
-        // as T^T = X W^T (rows: X blocks, columns: weight rows), so that a
-        // lane holds four consecutive entries of a row of T per register
-        // quad and writes them with one 8-byte store
-        cov_tile_gemm<N, false>(wfrag, lfrag, tile, acc);
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < RPW; ++r) {
-          if (!wok[r]) continue;
-          const int j = (rg * RPW + r) * 32 + l32;
-#pragma unroll
-          for (int c = 0; c < CPW; ++c) {
-            if (!lok[c]) continue;
+            for (int q4 = 0; q4 < 4; ++q4) wb[(bi + 2) % 3][q4] = wq_at(bi + 2, q4);
+          }
+          // keeps later blocks' loads from being hoisted here (registers)
+          __asm__ volatile("" ::: "memory");
+          if (wok[r] && lok[c]) {
+            const int j = (rg * RPW + r) * 32 + l32;
 #pragma unroll
             for (int q4 = 0; q4 < 4; ++q4) {
               const int i0 = (cg * CPW + c) * 32 + 8 * q4 + 4 * hi;
-              __bf16 v4[4];
-#pragma unroll
-              for (int e = 0; e < 4; ++e) v4[e] = (__bf16)acc[r][c][4 * q4 + e];
-              *reinterpret_cast<uint2*>(X + (size_t)j * STR + i0) = *reinterpret_cast<const uint2*>(v4);
+              const cv4f w4 = wb[bi % 3][q4];
+              const float4 z4 = *reinterpret_cast<const float4*>(s_zin + i0);
+              const float t0 = acc[r][c][4 * q4 + 0], t1 = acc[r][c][4 * q4 + 1];
+              const float t2 = acc[r][c][4 * q4 + 2], t3 = acc[r][c][4 * q4 + 3];
+              pv[r] += w4.x * t0 + w4.y * t1 + w4.z * t2 + w4.w * t3;
+              py[r] += w4.x * z4.x + w4.y * z4.y + w4.z * z4.z + w4.w * z4.w;
+              if (!last) {
+                __bf16 v4[4] = {(__bf16)t0, (__bf16)t1, (__bf16)t2, (__bf16)t3};
+                *reinterpret_cast<uint2*>(X + (size_t)j * STR + i0) = *reinterpret_cast<const uint2*>(v4);
+              }
             }
           }
+        }
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+          const float v = pv[r] + __shfl_xor(pv[r], 32);
+          const float y = py[r] + __shfl_xor(py[r], 32);
+          if (wok[r] && hi == 0) s_part[cg * N + (rg * RPW + r) * 32 + l32] = make_float2(v, y);
         }
       }
       __syncthreads();
-
-      // 4. per neuron j (a lane quad), one pass over the row-pass copy of
-      //    its weight row: the float32 centre y_j = W[j] z + b_j, the
-      //    variance C_h[j][j] = sum_k T[j][k] W[j][k], and the ReLU rule
+      // 4. per neuron: the column groups' sums in a fixed order, the centre
+      //    y = W z + b with z = alpha . y_{h-1} + beta, and the ReLU rule
       {
-        float r2[GPW][2];
+        const float2* s_part = reinterpret_cast<const float2*>(s_G);
+        for (int j = t; j < N; j += kCovThreads) {
+          float v = 0.f, yc = 0.f;
 #pragma unroll
-        for (int gi = 0; gi < GPW; ++gi) {
-          r2[gi][0] = r2[gi][1] = 0.f;
-          if (wave + 8 * gi < NG) {
-            const int j = 16 * (wave + 8 * gi) + rq;
-            gfloat* wv = (gfloat*)Lw.Wv + (int64_t)j * N + 8 * q;
-            const __bf16* trow = X + (size_t)j * STR;
-            float v = 0.f, yc = 0.f;
-#pragma unroll 2
-            for (int m = 0; m < N / 32; ++m) {
-              const int k = 8 * cov_row_chunk(N, q, m);
-              const cbf16x8 tv = *reinterpret_cast<const cbf16x8*>(trow + k);
-              const cv4f w0 = *reinterpret_cast<gfloat4*>(wv + 32 * m);
-              const cv4f w1 = *reinterpret_cast<gfloat4*>(wv + 32 * m + 4);
-              const float4 z0 = *reinterpret_cast<const float4*>(s_zin + k);
-              const float4 z1 = *reinterpret_cast<const float4*>(s_zin + k + 4);
-              v += w0.x * (float)tv[0] + w0.y * (float)tv[1] + w0.z * (float)tv[2] + w0.w * (float)tv[3] +
-                   w1.x * (float)tv[4] + w1.y * (float)tv[5] + w1.z * (float)tv[6] + w1.w * (float)tv[7];
-              yc += w0.x * z0.x + w0.y * z0.y + w0.z * z0.z + w0.w * z0.w + w1.x * z1.x + w1.y * z1.y +
-                    w1.z * z1.z + w1.w * z1.w;
-            }
-            r2[gi][0] = quad_sum(yc);
-            r2[gi][1] = quad_sum(v);
+          for (int g = 0; g < CG; ++g) {
+            const float2 p = s_part[g * N + j];
+            v += p.x;
+            yc += p.y;
           }
-        }
-        int j = -1;
-        float yc = 0.f, v = 0.f;
-#pragma unroll
-        for (int gi = 0; gi < GPW; ++gi)
-          if (q == gi && wave + 8 * gi < NG) {
-            j = 16 * (wave + 8 * gi) + rq;
-            yc = r2[gi][0];
-            v = r2[gi][1];
-          }
-        if (j >= 0) {
           float a, b, g;
           const float y = yc + ((gfloat*)Lw.b)[j];
           cov_relu_rule(y, v, a, b, g);
