@@ -161,7 +161,7 @@ __global__ __launch_bounds__(64 * NW) void hidden_mfma_bf16_kernel(
   const int64_t cell = (q / rb_count) * 8 + xcd;
   if (cell >= C) return;
   const int m0 = rb * BM;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int t = threadIdx.x, lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);  // wave-uniform
   const int nch = n_in / 8;
   const int64_t cin = s_in + g_in;
   const __bf16* fin = Fin + cell * s_in * n_in;

@@ -178,7 +178,9 @@ __global__ __launch_bounds__(kCovThreads) void up_cov_bf16_kernel(int64_t C, int
 
   const int64_t cell = blockIdx.x;
   if (cell >= C) return;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  // the wave index is uniform across a wave: kept in a scalar register,
+  // everything derived from it (tile, row groups) is too
+  const int t = threadIdx.x, lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
   const int l32 = lane & 31, hi = lane >> 5;
   constexpr int RPW = S::RPW, CPW = S::CPW, RG = S::RG, CG = S::CG;
   // row passes: 16-row groups, a quad of lanes per row (lane q of row rq)

@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_mfma_kernel(int64_t n_ite
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
   const int q = lane >> 5;
   const int l32 = lane & 31;
   const int64_t item0 = (int64_t)blockIdx.x * (BN / PER);
@@ -330,7 +330,7 @@ __global__ __launch_bounds__(kDenseThreads) void output_mfma_kernel(int64_t C, O
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
   const int q = lane >> 5;
   const int l32 = lane & 31;
   const int64_t cell0 = (int64_t)blockIdx.x * BN;

@@ -105,7 +105,7 @@ __global__ __launch_bounds__(512) void hidden_mfma_f32_kernel(
   const int64_t cell = (q / rb_count) * 8 + xcd;
   if (cell >= C) return;  // uniform for the whole workgroup
   const int m0 = rb * BM;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int t = threadIdx.x, lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);  // wave-uniform
   const int wr = wave % K::WR, wc = wave / K::WR;
   const int64_t cols_out = cols_in + n_in;
   const float* fin = Fin + cell * cols_in * n_in;

@@ -108,7 +108,7 @@ __global__ __launch_bounds__(512) void hidden_mfma_f64_kernel(
   const int64_t cell = (qq / rb_count) * 8 + xcd;
   if (cell >= C) return;  // uniform for the whole workgroup
   const int m0 = rb * BM;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int t = threadIdx.x, lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);  // wave-uniform
   const int wr = wave % K::WR, wc = wave / K::WR;
   const int l16 = lane & 15, q4 = lane >> 4;
   const int64_t cols_out = cols_in + n_in;

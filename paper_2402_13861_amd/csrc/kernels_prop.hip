@@ -282,7 +282,7 @@ __global__ void output_kernel(int64_t C, NetView<T> net, const float* __restrict
     mu_p += __shfl_xor(mu_p, off);
     acc_p += __shfl_xor(acc_p, off);
   }
-  const int wave = t >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);  // wave-uniform
   if ((t & 63) == 0) {
     red[0][wave] = mu_p;
     red[1][wave] = acc_p;

@@ -27,7 +27,7 @@ __global__ __launch_bounds__(256) void sur_gemm_kernel(int M, int N, int K, cons
                                                        int relu, const float* __restrict__ mask, int ldm) {
   __shared__ __bf16 As[GT * GKP];
   __shared__ __bf16 Bs[GT * GKP];
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int t = threadIdx.x, lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);  // wave-uniform
   const int wr = wave & 1, wc = wave >> 1;
   const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
   sv16f acc;
