@@ -460,34 +460,38 @@ __global__ __launch_bounds__(kCovThreads) void up_cov_bf16_kernel(int64_t C, int
     // 6. X_h = D C D + diag(gamma^2); C is symmetric, so the tile's columns j
     //    are written as rows of X.  The lane that wrote a diagonal entry
     //    rewrites it from the variance the rule used.
+    //    Column blocks outermost: a block's 16 column slopes are read once
+    //    for the RPW row blocks.
+    float aj[RPW];
 #pragma unroll
-    for (int r = 0; r < RPW; ++r) {
-      if (!wok[r]) continue;
-      const int j = (rg * RPW + r) * 32 + l32;
-      const float aj = s_alpha[j];
+    for (int r = 0; r < RPW; ++r) aj[r] = s_alpha[(wok[r] ? rg * RPW + r : 0) * 32 + l32];
 #pragma unroll
-      for (int c = 0; c < CPW; ++c) {
-        if (!lok[c]) continue;
-        // the block's 16 slopes in one round trip (kept next to their use:
-        // hoisting every block's would cost registers)
-        __asm__ volatile("" ::: "memory");
-        float4 ab[4];
+    for (int c = 0; c < CPW; ++c) {
+      if (!lok[c]) continue;
+      // (kept next to their use: hoisting every block's slopes would cost
+      // registers)
+      __asm__ volatile("" ::: "memory");
+      float4 ab[4];
 #pragma unroll
-        for (int q4 = 0; q4 < 4; ++q4)
-          ab[q4] = *reinterpret_cast<const float4*>(s_alpha + (cg * CPW + c) * 32 + 8 * q4 + 4 * hi);
+      for (int q4 = 0; q4 < 4; ++q4)
+        ab[q4] = *reinterpret_cast<const float4*>(s_alpha + (cg * CPW + c) * 32 + 8 * q4 + 4 * hi);
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) {
+        if (!wok[r]) continue;
+        const int j = (rg * RPW + r) * 32 + l32;
 #pragma unroll
         for (int q4 = 0; q4 < 4; ++q4) {
           const int i0 = (cg * CPW + c) * 32 + 8 * q4 + 4 * hi;
           const float4 ai = ab[q4];
           __bf16 v4[4];
-          v4[0] = (__bf16)(ai.x * aj * cacc[r][c][4 * q4 + 0]);
-          v4[1] = (__bf16)(ai.y * aj * cacc[r][c][4 * q4 + 1]);
-          v4[2] = (__bf16)(ai.z * aj * cacc[r][c][4 * q4 + 2]);
-          v4[3] = (__bf16)(ai.w * aj * cacc[r][c][4 * q4 + 3]);
+          v4[0] = (__bf16)(ai.x * aj[r] * cacc[r][c][4 * q4 + 0]);
+          v4[1] = (__bf16)(ai.y * aj[r] * cacc[r][c][4 * q4 + 1]);
+          v4[2] = (__bf16)(ai.z * aj[r] * cacc[r][c][4 * q4 + 2]);
+          v4[3] = (__bf16)(ai.w * aj[r] * cacc[r][c][4 * q4 + 3]);
           *reinterpret_cast<uint2*>(X + (size_t)j * STR + i0) = *reinterpret_cast<const uint2*>(v4);
         }
         if (cg * CPW + c == rg * RPW + r && ((l32 >> 2) & 1) == hi)
-          X[(size_t)j * STR + j] = (__bf16)(aj * aj * s_var[j] + s_gamma[j] * s_gamma[j]);
+          X[(size_t)j * STR + j] = (__bf16)(aj[r] * aj[r] * s_var[j] + s_gamma[j] * s_gamma[j]);
       }
     }
     __syncthreads();
