@@ -142,8 +142,11 @@ __device__ __forceinline__ void cov_relu_rule(float y, float var, float& a, floa
     return;
   }
   const float r = y / sigma;
-  const float Phi = 0.5f * erfcf(-r * 0.70710678118654752440f);
-  const float Q = 0.5f * erfcf(r * 0.70710678118654752440f);
+  // one tail: the smaller of Phi(r) and Q(r) = 1 - Phi(r) from erfc, the
+  // larger as its complement
+  const float tail = 0.5f * erfcf(fabsf(r) * 0.70710678118654752440f);
+  const float Phi = r >= 0.f ? 1.f - tail : tail;
+  const float Q = r >= 0.f ? tail : 1.f - tail;
   const float phi = 0.39894228040143267794f * expf(-0.5f * r * r);
   a = Phi;
   b = sigma * phi;
