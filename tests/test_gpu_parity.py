@@ -118,6 +118,35 @@ def test_propagate_edge_cases(ctx):
         ctx.unload_mlp(mid)
 
 
+@pytest.mark.parametrize("prec_name", ["fp32", "bf16", "fp64"])
+def test_propagate_small_chunks_match_one_chunk(ctx, prec_name):
+    """A 1 MiB scratch budget splits a batch into many chunks (a few cells
+    each for float64); every result equals the one-chunk result bit for bit,
+    for both methods and, in BF16 UP, both forms."""
+    import paper_2402_13861_amd as isx
+
+    prec = {"fp32": isx.FP32, "bf16": isx.BF16, "fp64": isx.FP64}[prec_name]
+    mlp = he_normal_mlp([3, 64, 64, 64, 1], seed=8)
+    mid = ctx.load_weights(mlp)
+    c, h, _ = random_boxes(3000, range(0, 10), seed=9)
+    try:
+        for method in (isx.UP, isx.AA):
+            forms = (0, 1) if (prec == isx.BF16 and method == isx.UP) else (0,)
+            for form in forms:
+                ctx.set_option(isx.UP_FORM, form)
+                ctx.set_option(isx.SCRATCH_BYTES, 16 << 30)
+                a32, a64 = _gpu_prop(ctx, mid, method, prec, c, h)
+                ctx.set_option(isx.SCRATCH_BYTES, 1 << 20)
+                b32, b64 = _gpu_prop(ctx, mid, method, prec, c, h)
+                np.testing.assert_array_equal(a32, b32)
+                if a64 is not None:
+                    np.testing.assert_array_equal(a64, b64)
+    finally:
+        ctx.set_option(isx.SCRATCH_BYTES, 16 << 30)
+        ctx.set_option(isx.UP_FORM, 0)
+        ctx.unload_mlp(mid)
+
+
 def test_propagate_is_deterministic(ctx):
     import paper_2402_13861_amd as isx
 
