@@ -141,7 +141,7 @@ void free_model_table(Model& m) {
 }
 
 void free_layer(Layer& l) {
-  void* ps[] = {l.W, l.Wt, l.b, l.Wd, l.Wtd, l.bd, l.Wtbf, l.Wbf, l.Wfr, l.Wfrl, l.Wv, l.Wq};
+  void* ps[] = {l.W, l.Wt, l.b, l.Wd, l.Wtd, l.bd, l.Wtbf, l.Wbf, l.Wfr, l.Wfrl, l.Wv, l.Wq, l.WTfr, l.WTfrl};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   l = Layer{};
@@ -464,7 +464,7 @@ isx_status isx_load_mlp(isx_ctx* ctx, int32_t n_linear, const int32_t* widths, c
     if (e == hipSuccess && l >= 1 && l + 1 < n_linear && ni == no && no <= kCovNMax) {
       // copies in the covariance kernel's access orders
       const int N = no;
-      std::vector<uint16_t> Wfr((size_t)N * N), Wfrl((size_t)N * N);
+      std::vector<uint16_t> Wfr((size_t)N * N), Wfrl((size_t)N * N), WTfr((size_t)N * N), WTfrl((size_t)N * N);
       std::vector<float> Wv((size_t)N * N), Wq((size_t)N * N);
       for (int r = 0; r < N; ++r)
         for (int k = 0; k < N; ++k) {
@@ -474,6 +474,9 @@ isx_status isx_load_mlp(isx_ctx* ctx, int32_t n_linear, const int32_t* widths, c
           std::memcpy(&hf, &hu, 4);
           Wfr[cov_frag_index(N, r, k)] = hb;
           Wfrl[cov_frag_index(N, r, k)] = f32_to_bf16_bits(W[(size_t)r * N + k] - hf);
+          // W^T: row k of W^T is column k of W
+          WTfr[cov_frag_index(N, k, r)] = hb;
+          WTfrl[cov_frag_index(N, k, r)] = f32_to_bf16_bits(W[(size_t)r * N + k] - hf);
         }
       for (int r = 0; r < N; ++r)
         for (int m = 0; m < N / 32; ++m)
@@ -486,6 +489,8 @@ isx_status isx_load_mlp(isx_ctx* ctx, int32_t n_linear, const int32_t* widths, c
       if (e == hipSuccess) e = upload(&L.Wfrl, Wfrl);
       if (e == hipSuccess) e = upload(&L.Wv, Wv);
       if (e == hipSuccess) e = upload(&L.Wq, Wq);
+      if (e == hipSuccess) e = upload(&L.WTfr, WTfr);
+      if (e == hipSuccess) e = upload(&L.WTfrl, WTfrl);
     }
     if (e != hipSuccess) {
       for (int k = 0; k <= l; ++k) free_layer(m.L[k]);
@@ -496,7 +501,8 @@ isx_status isx_load_mlp(isx_ctx* ctx, int32_t n_linear, const int32_t* widths, c
     std::vector<DevLayer> table(n_linear);
     for (int l = 0; l < n_linear; ++l)
       table[l] = DevLayer{m.L[l].W,   m.L[l].Wbf, m.L[l].Wfr,  m.L[l].Wfrl,
-                          m.L[l].Wv,  m.L[l].Wq,  m.L[l].b,    m.L[l].n_in, m.L[l].n_out};
+                          m.L[l].Wv,  m.L[l].Wq,  m.L[l].WTfr, m.L[l].WTfrl,
+                          m.L[l].b,   m.L[l].n_in, m.L[l].n_out};
     hipError_t e = upload(&m.dev_layers, table);
     if (e != hipSuccess) {
       for (int k = 0; k < n_linear; ++k) free_layer(m.L[k]);

@@ -37,6 +37,8 @@ struct Layer {
   uint16_t* Wfrl = nullptr; // bfloat16 bits of W - bf16(W), same order
   float* Wv = nullptr;      // W with each row's chunks in row-pass order (cov_row_pos)
   float* Wq = nullptr;      // W in accumulator-quad order (cov_quad_pos)
+  uint16_t* WTfr = nullptr;  // bfloat16 bits of W^T in fragment order (rows: W's columns)
+  uint16_t* WTfrl = nullptr; // bfloat16 bits of W^T - bf16(W^T), same order
 };
 
 // Covariance-form layouts of a square N x N layer (N a multiple of 32, at
@@ -87,6 +89,8 @@ struct DevLayer {
   const uint16_t* Wfrl;   // W - bf16(W) in fragment order (same layers)
   const float* Wv;        // row-pass order (square layers <= kCovNMax, else null)
   const float* Wq;        // accumulator-quad order (same layers)
+  const uint16_t* WTfr;   // W^T hi / lo in fragment order (same layers)
+  const uint16_t* WTfrl;
   const float* b;         // [n_out]
   int n_in, n_out;        // padded widths
 };
@@ -284,6 +288,11 @@ hipError_t linearize_mfma(const Model& m, int64_t n, const float* centres, const
                           hipStream_t s);
 // output read-off of C cells from the hidden layers' Y, A, B, G vectors
 // (indexed by hidden layer 1..n_linear-1, each [C][padded width])
+// UP read-off on BF16 MFMA with hi/lo splits (nets with one padded hidden
+// width <= kCovNMax; kernels_dense.hip)
+bool output_bf16_supported(const Model& m);
+hipError_t launch_output_bf16(const Model& m, int64_t C, float* const* Y, float* const* A, float* const* B,
+                              float* const* G, const float* halves, float* out, hipStream_t s);
 hipError_t launch_output_mfma(const Model& m, isx_method method, int64_t C, float* const* Y, float* const* A,
                               float* const* B, float* const* G, const float* halves, float* out, hipStream_t s);
 // algorithmic flops of the output read-off per cell

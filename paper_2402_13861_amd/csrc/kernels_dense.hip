@@ -688,4 +688,229 @@ hipError_t linearize_bf16(const Model& m, int64_t n, const float* centres, const
   }
 }
 
+
+// ------------------------------------------ output read-off in BF16 (UP)
+// The read-off's downward chain U_{h-1} = (U_h W_h) . A_{h-1} (rows: cells)
+// for the BF16 path's nets with one padded hidden width N <= kCovNMax, on
+// BF16 MFMA: U in LDS as bfloat16 hi/lo parts ([cell][neuron], rows padded
+// by 8), W_h^T in fragment order as hi/lo copies, and each product
+// Wh Uh + Wh Ul + Wl Uh in float32 (the dropped Wl Ul and the splits leave a
+// relative error near 2^-16 per layer; the spread is a sum of squares, so it
+// does not cancel).  Only for UP: the AA rounding margin assumes a float32
+// read-off.  A workgroup owns 64 cells; wave w owns neuron block w of
+// U_{h-1} and both cell blocks.
+namespace {
+constexpr int kOutCells = 64;
+
+template <int N>
+struct OutShape {
+  static constexpr int STR = N + 8;
+  static constexpr int KS = N / 16;
+  static constexpr int RB = N / 32;
+  static constexpr int CB = kOutCells / 32;
+  static constexpr size_t LDS = (size_t)2 * kOutCells * STR * 2 + (size_t)kOutCells * (RB + 2) * sizeof(float);
+};
+
+__device__ __forceinline__ void split_store4(__bf16* h, __bf16* l, float v0, float v1, float v2, float v3) {
+  __bf16 a[4], b[4];
+  const float v[4] = {v0, v1, v2, v3};
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    a[e] = (__bf16)v[e];
+    b[e] = (__bf16)(v[e] - (float)a[e]);
+  }
+  *reinterpret_cast<uint2*>(h) = *reinterpret_cast<const uint2*>(a);
+  *reinterpret_cast<uint2*>(l) = *reinterpret_cast<const uint2*>(b);
+}
+}  // namespace
+
+template <int N>
+__global__ __launch_bounds__(kDenseThreads) void output_bf16_kernel(int64_t C, OutNet net,
+                                                                    const DevLayer* __restrict__ layers,
+                                                                    const float* __restrict__ halves,
+                                                                    float* __restrict__ out) {
+  using S = OutShape<N>;
+  constexpr int STR = S::STR, KS = S::KS, RB = S::RB, CB = S::CB;
+  extern __shared__ float4 ob_smem4[];
+  __bf16* Uh = reinterpret_cast<__bf16*>(ob_smem4);  // [kOutCells][STR]
+  __bf16* Ul = Uh + kOutCells * STR;
+  float* slots = reinterpret_cast<float*>(Ul + kOutCells * STR);  // [kOutCells][RB] spread partials
+  float* cmu = slots + kOutCells * RB;                            // [kOutCells]
+  float* cacc = cmu + kOutCells;                                  // [kOutCells]
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int l32 = lane & 31, hi = lane >> 5;
+  const int64_t cell0 = (int64_t)blockIdx.x * kOutCells;
+  const int Lh = net.n_linear - 1;
+
+  for (int i = tid; i < kOutCells * RB; i += kDenseThreads) slots[i] = 0.f;
+  // last hidden layer: 8 lanes per cell, 4 neurons each per step (one
+  // 128-byte line per cell and array): the mean, the layer's own symbols and
+  // U_L = w_out . A_L
+  {
+    const int cl = tid >> 3, part = tid & 7;
+    const int64_t cell = cell0 + cl;
+    const float* Yh = net.Y[Lh];
+    const float* Ah = net.A[Lh];
+    const float* Bh = net.B[Lh];
+    const float* Gh = net.G[Lh];
+    float mu = 0.f, ac = 0.f;
+    for (int j = 4 * part; j < N; j += 32) {
+      float4 y4 = make_float4(0.f, 0.f, 0.f, 0.f), a4 = y4, b4 = y4, g4 = y4;
+      if (cell < C) {
+        const int64_t e = cell * N + j;
+        y4 = *reinterpret_cast<const float4*>(Yh + e);
+        a4 = *reinterpret_cast<const float4*>(Ah + e);
+        b4 = *reinterpret_cast<const float4*>(Bh + e);
+        g4 = *reinterpret_cast<const float4*>(Gh + e);
+      }
+      const float4 w4 = *reinterpret_cast<const float4*>(net.wout + j);
+      mu += w4.x * (a4.x * y4.x + b4.x) + w4.y * (a4.y * y4.y + b4.y) + w4.z * (a4.z * y4.z + b4.z) +
+            w4.w * (a4.w * y4.w + b4.w);
+      const float q0 = w4.x * g4.x, q1 = w4.y * g4.y, q2 = w4.z * g4.z, q3 = w4.w * g4.w;
+      ac += q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3;
+      split_store4(Uh + cl * STR + j, Ul + cl * STR + j, w4.x * a4.x, w4.y * a4.y, w4.z * a4.z, w4.w * a4.w);
+    }
+#pragma unroll
+    for (int o = 1; o < 8; o <<= 1) {
+      mu += __shfl_xor(mu, o);
+      ac += __shfl_xor(ac, o);
+    }
+    if (part == 0) {
+      cmu[cl] = mu;
+      cacc[cl] = ac;
+    }
+  }
+  __syncthreads();
+
+  for (int h = Lh; h >= 2; --h) {
+    const DevLayer Lw = layers[h - 1];  // W_h, [N][N]
+    lv16f acc[CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[cb][e] = 0.f;
+    if (wave < RB) {
+      const int64_t fo = ((int64_t)wave * KS * 64 + lane) * 8;
+      glbf16x8* ah_p = (glbf16x8*)(reinterpret_cast<const __bf16*>(Lw.WTfr) + fo);
+      glbf16x8* al_p = (glbf16x8*)(reinterpret_cast<const __bf16*>(Lw.WTfrl) + fo);
+#pragma unroll 4
+      for (int ks = 0; ks < KS; ++ks) {
+        const lbf16x8 ah = ah_p[64 * ks], al = al_p[64 * ks];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+          const size_t o = (size_t)(cb * 32 + l32) * STR + 16 * ks + 8 * hi;
+          const lbf16x8 bh = *reinterpret_cast<const lbf16x8*>(Uh + o);
+          const lbf16x8 bl = *reinterpret_cast<const lbf16x8*>(Ul + o);
+          acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[cb], 0, 0, 0);
+          acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[cb], 0, 0, 0);
+          acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[cb], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();  // every wave has read U_h
+    if (wave < RB) {
+      const float* Gp = net.G[h - 1];
+      const float* Ap = net.A[h - 1];
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        const int col = cb * 32 + l32;
+        const int64_t cell = cell0 + col;
+        float sp = 0.f;
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4) {
+          const int i0 = wave * 32 + 8 * q4 + 4 * hi;  // accumulator rows i0..i0+3
+          float4 g4 = make_float4(0.f, 0.f, 0.f, 0.f), a4 = g4;
+          if (cell < C) {
+            g4 = *reinterpret_cast<const float4*>(Gp + cell * N + i0);
+            a4 = *reinterpret_cast<const float4*>(Ap + cell * N + i0);
+          }
+          const float v0 = acc[cb][4 * q4 + 0], v1 = acc[cb][4 * q4 + 1];
+          const float v2 = acc[cb][4 * q4 + 2], v3 = acc[cb][4 * q4 + 3];
+          const float r0 = v0 * g4.x, r1 = v1 * g4.y, r2 = v2 * g4.z, r3 = v3 * g4.w;
+          sp += r0 * r0 + r1 * r1 + r2 * r2 + r3 * r3;
+          split_store4(Uh + col * STR + i0, Ul + col * STR + i0, v0 * a4.x, v1 * a4.y, v2 * a4.z, v3 * a4.w);
+        }
+        sp += __shfl_xor(sp, 32);
+        if (hi == 0) slots[col * RB + wave] += sp;
+      }
+    }
+    __syncthreads();
+  }
+
+  // input symbols: ((v_1 . A_1) W_1)[a] times the input scale h_a / sqrt 3
+  {
+    const int cl = tid >> 3, part = tid & 7;
+    const int64_t cell = cell0 + cl;
+    float t = 0.f;
+    if (part < 3 && cell < C) {
+      float sa = 0.f;
+      for (int j = 0; j < N; ++j)
+        sa += ((float)Uh[cl * STR + j] + (float)Ul[cl * STR + j]) * net.W0[j * 3 + part];
+      const float v = sa * (halves[cell * 3 + part] * 0.57735026918962576451f);
+      t = v * v;
+    }
+#pragma unroll
+    for (int o = 1; o < 8; o <<= 1) t += __shfl_xor(t, o);
+    if (part == 0 && cell < C) {
+      float a = cacc[cl] + t;
+      for (int r = 0; r < RB; ++r) a += slots[cl * RB + r];
+      out[cell * 2 + 0] = cmu[cl] + net.bout[0];
+      out[cell * 2 + 1] = sqrtf(a);
+    }
+  }
+}
+
+template <int N>
+static hipError_t launch_out_bf16_n(int64_t C, const OutNet& net, const Model& m, const float* halves, float* out,
+                                    hipStream_t s) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&output_bf16_kernel<N>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)OutShape<N>::LDS);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  const int64_t blocks = (C + kOutCells - 1) / kOutCells;
+  hipLaunchKernelGGL((output_bf16_kernel<N>), dim3((unsigned)blocks), dim3(kDenseThreads), OutShape<N>::LDS, s, C,
+                     net, m.dev_layers, halves, out);
+  return hipGetLastError();
+}
+
+bool output_bf16_supported(const Model& m) {
+  if (m.n_linear < 2 || !cov_supported(m)) return false;
+  for (int l = 1; l + 1 < m.n_linear; ++l)
+    if (!m.L[l].WTfr || !m.L[l].WTfrl) return false;
+  return true;
+}
+
+hipError_t launch_output_bf16(const Model& m, int64_t C, float* const* Y, float* const* A, float* const* B,
+                              float* const* G, const float* halves, float* out, hipStream_t s) {
+  if (C <= 0) return hipSuccess;
+  if (!output_bf16_supported(m)) return hipErrorNotSupported;
+  OutNet net{};
+  net.n_linear = m.n_linear;
+  for (int i = 0; i <= m.n_linear; ++i) net.n[i] = m.pw[i];
+  for (int l = 0; l < m.n_linear; ++l) net.Wt[l] = m.L[l].Wt;
+  net.W0 = m.L[0].W;
+  net.wout = m.L[m.n_linear - 1].W;
+  net.bout = m.L[m.n_linear - 1].b;
+  for (int h = 1; h < m.n_linear; ++h) {
+    net.Y[h] = Y[h];
+    net.A[h] = A[h];
+    net.B[h] = B[h];
+    net.G[h] = G[h];
+  }
+  switch (m.pw[1]) {
+    case 32: return launch_out_bf16_n<32>(C, net, m, halves, out, s);
+    case 64: return launch_out_bf16_n<64>(C, net, m, halves, out, s);
+    case 96: return launch_out_bf16_n<96>(C, net, m, halves, out, s);
+    case 128: return launch_out_bf16_n<128>(C, net, m, halves, out, s);
+    case 160: return launch_out_bf16_n<160>(C, net, m, halves, out, s);
+    case 192: return launch_out_bf16_n<192>(C, net, m, halves, out, s);
+    case 224: return launch_out_bf16_n<224>(C, net, m, halves, out, s);
+    case 256: return launch_out_bf16_n<256>(C, net, m, halves, out, s);
+    default: return hipErrorNotSupported;
+  }
+}
+
 }  // namespace isx
