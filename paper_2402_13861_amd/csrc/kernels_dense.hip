@@ -789,6 +789,24 @@ __global__ __launch_bounds__(kDenseThreads) void output_bf16_kernel(int64_t C, O
     for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc[cb][e] = 0.f;
+    // the epilogue's G and A of layer h-1 are loaded before the products
+    // (they do not depend on them), so their latency overlaps the MFMAs
+    float4 gpre[CB][4], apre[CB][4];
+    if (wave < RB) {
+      const float* Gp = net.G[h - 1];
+      const float* Ap = net.A[h - 1];
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        const int64_t cell = cell0 + cb * 32 + l32;
+        const int64_t cc = cell < C ? cell : C - 1;  // (rows past the end read a valid cell, unused)
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4) {
+          const int i0 = wave * 32 + 8 * q4 + 4 * hi;
+          gpre[cb][q4] = *reinterpret_cast<const float4*>(Gp + cc * N + i0);
+          apre[cb][q4] = *reinterpret_cast<const float4*>(Ap + cc * N + i0);
+        }
+      }
+    }
     if (wave < RB) {
       const int64_t fo = ((int64_t)wave * KS * 64 + lane) * 8;
       glbf16x8* ah_p = (glbf16x8*)(reinterpret_cast<const __bf16*>(Lw.WTfr) + fo);
@@ -809,21 +827,14 @@ __global__ __launch_bounds__(kDenseThreads) void output_bf16_kernel(int64_t C, O
     }
     __syncthreads();  // every wave has read U_h
     if (wave < RB) {
-      const float* Gp = net.G[h - 1];
-      const float* Ap = net.A[h - 1];
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb) {
         const int col = cb * 32 + l32;
-        const int64_t cell = cell0 + col;
         float sp = 0.f;
 #pragma unroll
         for (int q4 = 0; q4 < 4; ++q4) {
           const int i0 = wave * 32 + 8 * q4 + 4 * hi;  // accumulator rows i0..i0+3
-          float4 g4 = make_float4(0.f, 0.f, 0.f, 0.f), a4 = g4;
-          if (cell < C) {
-            g4 = *reinterpret_cast<const float4*>(Gp + cell * N + i0);
-            a4 = *reinterpret_cast<const float4*>(Ap + cell * N + i0);
-          }
+          const float4 g4 = gpre[cb][q4], a4 = apre[cb][q4];
           const float v0 = acc[cb][4 * q4 + 0], v1 = acc[cb][4 * q4 + 1];
           const float v2 = acc[cb][4 * q4 + 2], v3 = acc[cb][4 * q4 + 3];
           const float r0 = v0 * g4.x, r1 = v1 * g4.y, r2 = v2 * g4.z, r3 = v3 * g4.w;

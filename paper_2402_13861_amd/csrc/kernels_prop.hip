@@ -222,80 +222,114 @@ __global__ void hidden_simt_kernel(int64_t C, int n_in, int n_out, int64_t cols_
 
 // ------------------------------------------------------------ output layer
 // Output read-off (Eq. 2 for AA, Eq. 7 for UP) by the downward row vector
-// described at the top of this file.  One workgroup (256 threads) per cell.
-template <typename T, int METHOD>
-__global__ void output_kernel(int64_t C, NetView<T> net, const float* __restrict__ halves,
-                              float* __restrict__ out32, double* __restrict__ out64) {
-  __shared__ T v[ISX_MAX_WIDTH];
-  __shared__ T u[ISX_MAX_WIDTH];
-  __shared__ T red[2][256 / 64];
-  const int64_t cell = blockIdx.x;
+// described at the top of this file.  One workgroup (256 threads) handles
+// CPB cells: each weight of the chain is loaded once for all of them (the
+// chain's weights are the read-off's main traffic).  Every cell's sums run in
+// the same order for any CPB.  LDS: v and u of the CPB cells, [CPB][nmax]
+// each (nmax = the widest hidden layer).
+template <typename T, int METHOD, int CPB>
+__global__ __launch_bounds__(256) void output_kernel(int64_t C, NetView<T> net, int nmax,
+                                                     const float* __restrict__ halves, float* __restrict__ out32,
+                                                     double* __restrict__ out64) {
+  extern __shared__ float4 outk_smem4[];
+  T* v = reinterpret_cast<T*>(outk_smem4);  // [CPB][nmax]
+  T* u = v + CPB * nmax;                    // [CPB][nmax]
+  __shared__ T red[2][CPB][256 / 64];
+  const int64_t cell0 = (int64_t)blockIdx.x * CPB;
   const int t = threadIdx.x;
   const int L = net.n_linear;
   const int Lh = L - 1;
   const int nL = net.n[Lh];
   const T* wout = net.W[L - 1];
-  T mu_p = T(0), acc_p = T(0);
-  {
-    const T* Yh = net.Y[Lh] + cell * nL;
-    const T* Ah = net.A[Lh] + cell * nL;
-    const T* Bh = net.B[Lh] + cell * nL;
-    const T* Gh = net.G[Lh] + cell * nL;
+  int64_t cl[CPB];  // the cell, clamped to a valid one for cells past the end
+#pragma unroll
+  for (int c = 0; c < CPB; ++c) cl[c] = cell0 + c < C ? cell0 + c : C - 1;
+  T mu_p[CPB], acc_p[CPB];
+#pragma unroll
+  for (int c = 0; c < CPB; ++c) mu_p[c] = acc_p[c] = T(0);
+#pragma unroll
+  for (int c = 0; c < CPB; ++c) {
+    const T* Yh = net.Y[Lh] + cl[c] * nL;
+    const T* Ah = net.A[Lh] + cl[c] * nL;
+    const T* Bh = net.B[Lh] + cl[c] * nL;
+    const T* Gh = net.G[Lh] + cl[c] * nL;
     for (int j = t; j < nL; j += blockDim.x) {
       const T w = wout[j];
-      mu_p += w * (Ah[j] * Yh[j] + Bh[j]);
-      acc_p += stat_term<T, METHOD>(w * Gh[j]);
-      v[j] = w;
+      mu_p[c] += w * (Ah[j] * Yh[j] + Bh[j]);
+      acc_p[c] += stat_term<T, METHOD>(w * Gh[j]);
+      v[c * nmax + j] = w;
     }
   }
   __syncthreads();
   for (int h = Lh; h >= 2; --h) {
     const int nh = net.n[h], np = net.n[h - 1];
-    const T* Ah = net.A[h] + cell * nh;
-    for (int j = t; j < nh; j += blockDim.x) u[j] = v[j] * Ah[j];
+#pragma unroll
+    for (int c = 0; c < CPB; ++c) {
+      const T* Ah = net.A[h] + cl[c] * nh;
+      for (int j = t; j < nh; j += blockDim.x) u[c * nmax + j] = v[c * nmax + j] * Ah[j];
+    }
     __syncthreads();
     const T* Wl = net.W[h - 1];  // [nh][np]
-    const T* Gp = net.G[h - 1] + cell * np;
     for (int i = t; i < np; i += blockDim.x) {
-      T s = T(0);
-      for (int j = 0; j < nh; ++j) s += u[j] * Wl[(int64_t)j * np + i];
-      v[i] = s;
-      acc_p += stat_term<T, METHOD>(s * Gp[i]);
+      T sv[CPB];
+#pragma unroll
+      for (int c = 0; c < CPB; ++c) sv[c] = T(0);
+      for (int j = 0; j < nh; ++j) {
+        const T w = Wl[(int64_t)j * np + i];
+#pragma unroll
+        for (int c = 0; c < CPB; ++c) sv[c] += u[c * nmax + j] * w;
+      }
+#pragma unroll
+      for (int c = 0; c < CPB; ++c) {
+        v[c * nmax + i] = sv[c];
+        acc_p[c] += stat_term<T, METHOD>(sv[c] * net.G[h - 1][cl[c] * np + i]);
+      }
     }
     __syncthreads();
   }
   {
     const int n1 = net.n[1];
-    const T* A1 = net.A[1] + cell * n1;
-    for (int j = t; j < n1; j += blockDim.x) u[j] = v[j] * A1[j];
+#pragma unroll
+    for (int c = 0; c < CPB; ++c) {
+      const T* A1 = net.A[1] + cl[c] * n1;
+      for (int j = t; j < n1; j += blockDim.x) u[c * nmax + j] = v[c * nmax + j] * A1[j];
+    }
     __syncthreads();
     if (t < 3) {
       const T* W0 = net.W[0];  // [n1][3]
-      T s = T(0);
-      for (int j = 0; j < n1; ++j) s += u[j] * W0[j * 3 + t];
       const T sc = METHOD == ISX_UP ? T(0.57735026918962576451) : T(1);
-      acc_p += stat_term<T, METHOD>(s * (T(halves[cell * 3 + t]) * sc));
+#pragma unroll
+      for (int c = 0; c < CPB; ++c) {
+        T s = T(0);
+        for (int j = 0; j < n1; ++j) s += u[c * nmax + j] * W0[j * 3 + t];
+        acc_p[c] += stat_term<T, METHOD>(s * (T(halves[cl[c] * 3 + t]) * sc));
+      }
     }
   }
-  // block reduction of (mu_p, acc_p)
-  for (int off = 32; off > 0; off >>= 1) {
-    mu_p += __shfl_xor(mu_p, off);
-    acc_p += __shfl_xor(acc_p, off);
-  }
+  // block reductions of (mu_p, acc_p)
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);  // wave-uniform
-  if ((t & 63) == 0) {
-    red[0][wave] = mu_p;
-    red[1][wave] = acc_p;
+#pragma unroll
+  for (int c = 0; c < CPB; ++c) {
+    for (int off = 32; off > 0; off >>= 1) {
+      mu_p[c] += __shfl_xor(mu_p[c], off);
+      acc_p[c] += __shfl_xor(acc_p[c], off);
+    }
+    if ((t & 63) == 0) {
+      red[0][c][wave] = mu_p[c];
+      red[1][c][wave] = acc_p[c];
+    }
   }
   __syncthreads();
-  if (t == 0) {
+  if (t < CPB && cell0 + t < C) {
+    const int c = t;
     T mu = T(0), acc = T(0);
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-      mu += red[0][w];
-      acc += red[1][w];
+      mu += red[0][c][w];
+      acc += red[1][c][w];
     }
     mu += net.b[L - 1][0];
     const T spread = METHOD == ISX_UP ? M<T>::sqrt_(acc) : acc;
+    const int64_t cell = cell0 + c;
     out32[cell * 2 + 0] = (float)mu;
     out32[cell * 2 + 1] = (float)spread;
     if (out64) {
@@ -303,6 +337,26 @@ __global__ void output_kernel(int64_t C, NetView<T> net, const float* __restrict
       out64[cell * 2 + 1] = (double)spread;
     }
   }
+}
+
+// Launch of the read-off with CPB cells per workgroup.
+template <typename T, int METHOD, int CPB>
+static hipError_t launch_output_simt(const Model& m, int64_t C, const NetView<T>& view, const float* halves,
+                                     float* out32, double* out64, hipStream_t s) {
+  int nmax = 3;
+  for (int h = 1; h < m.n_linear; ++h) nmax = std::max(nmax, m.pw[h]);
+  const size_t lds = (size_t)2 * CPB * nmax * sizeof(T);
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&output_kernel<T, METHOD, CPB>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(2 * CPB * ISX_MAX_WIDTH * sizeof(T)));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((output_kernel<T, METHOD, CPB>), dim3((unsigned)((C + CPB - 1) / CPB)), dim3(256), lds, s, C,
+                     view, nmax, halves, out32, out64);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------- MLP evaluation
@@ -548,8 +602,10 @@ static hipError_t propagate_impl(const PropArgs& a, PropWork<T>& w, bool use_mfm
       view.B[h] = B[h];
       view.G[h] = G[h];
     }
-    hipLaunchKernelGGL((output_kernel<T, METHOD>), dim3((unsigned)C), dim3(256), 0, a.stream, C, view, a.halves,
-                       a.out32, a.out64);
+    // float64 (the re-check band) batches 4 cells per workgroup
+    hipError_t e = sizeof(T) == 8 ? launch_output_simt<T, METHOD, 4>(m, C, view, a.halves, a.out32, a.out64, a.stream)
+                                  : launch_output_simt<T, METHOD, 1>(m, C, view, a.halves, a.out32, a.out64, a.stream);
+    if (e != hipSuccess) return e;
   }
   if (prof) a.prof->end(rec, a.stream);
   if (marg) {
@@ -577,13 +633,8 @@ hipError_t launch_output_f32(const Model& m, isx_method method, int64_t C, float
     view.B[h] = B[h];
     view.G[h] = G[h];
   }
-  if (method == ISX_UP)
-    hipLaunchKernelGGL((output_kernel<float, ISX_UP>), dim3((unsigned)C), dim3(256), 0, s, C, view, halves, out32,
-                       (double*)nullptr);
-  else
-    hipLaunchKernelGGL((output_kernel<float, ISX_AA>), dim3((unsigned)C), dim3(256), 0, s, C, view, halves, out32,
-                       (double*)nullptr);
-  return hipGetLastError();
+  return method == ISX_UP ? launch_output_simt<float, ISX_UP, 1>(m, C, view, halves, out32, nullptr, s)
+                          : launch_output_simt<float, ISX_AA, 1>(m, C, view, halves, out32, nullptr, s);
 }
 
 hipError_t propagate_f32(const PropArgs& a, PropWork<float>& w) {
