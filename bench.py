@@ -36,12 +36,47 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# hidden-layer kernel kinds: (kernel name, source file, MFMA dtype)
+# hidden-layer kernel kinds: (kernel name, source file, MFMA dtype, formulation)
 HIDDEN_KINDS = {
-    "hidden_fp32": ("hidden_mfma_f32_kernel", "kernels_mfma.hip", "fp32"),
-    "hidden_bf16": ("hidden_mfma_bf16_kernel", "kernels_bf16.hip", "bf16"),
-    "hidden_cov_bf16": ("up_cov_bf16_kernel", "kernels_cov.hip", "bf16"),
+    "hidden_fp32": ("hidden_mfma_f32_kernel", "kernels_mfma.hip", "fp32", "coefficient"),
+    "hidden_bf16": ("hidden_mfma_bf16_kernel", "kernels_bf16.hip", "bf16", "coefficient"),
+    "hidden_cov_bf16": ("up_cov_bf16_kernel", "kernels_cov.hip", "bf16", "covariance"),
+    "hidden_fp64": ("hidden_mfma_f64_kernel", "kernels_mfma64.hip", "fp64", "coefficient"),
 }
+
+
+def alg_flops_coefficient(widths):
+    """Algorithmic flops of one cell's hidden-layer products in coefficient
+    form: sum over hidden layers h >= 2 of 2 n_h n_{h-1} (D_h + 1), where
+    D_2 = 3 and D_{h+1} = D_h + n_h symbol columns enter layer h (+1 for the
+    centre column)."""
+    hid = widths[1:-1]
+    D, f = 3, 0.0
+    for h in range(1, len(hid)):
+        f += 2.0 * hid[h] * hid[h - 1] * (D + 1)
+        D += hid[h - 1]
+    return f
+
+
+def alg_flops_cov_hybrid(widths):
+    """Algorithmic flops of the cheapest exact formulation of uncertainty
+    propagation per cell: layer by layer the cheaper of the coefficient
+    product (2 n_h n_{h-1} D_h) and the covariance update W Sigma W^T
+    (2 n^3 for W Sigma plus n^3 for the symmetric half of the second
+    product), paying once for Sigma = F F^T (n^2 D, symmetric) where the
+    covariance form takes over.  3->256x5->1: 168.7 MFLOP."""
+    hid = widths[1:-1]
+    D, f, cov = 3, 0.0, False
+    for h in range(1, len(hid)):
+        n_o, n_i = hid[h], hid[h - 1]
+        coef = 2.0 * n_o * n_i * D
+        full = 2.0 * n_o * n_i * n_i + 1.0 * n_o * n_o * n_i
+        if not cov and full < coef:
+            f += 1.0 * n_i * n_i * D
+            cov = True
+        f += full if cov else coef
+        D += n_i
+    return f
 
 
 def kernel_source_hash(kind: str) -> str:
@@ -63,32 +98,100 @@ def traffic_from_profiles(kind: str, cells_per_launch: float):
     return t["hbm_bytes_per_cell"] * cells_per_launch
 
 
-def cpu_baseline(mlp, levels, budget_s: float):
-    """The float64 oracle on a bounded sample: random cells drawn level by
-    level in proportion to the GPU run's propagated cells, timed on the host;
-    the extraction time is extrapolated from that rate."""
+def host_cpu():
+    """(logical cores, CPU model) of the host."""
+    model = "unknown"
+    try:
+        for line in Path("/proc/cpuinfo").read_text().splitlines():
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return os.cpu_count() or 1, model
+
+
+def cpu_baseline(mlp, depth: int, budget_s: float, seed: int = 0):
+    """The float64 oracle on a bounded sample: random cells drawn uniformly
+    over octree levels 3..depth (the oracle's cost per cell does not depend on
+    the level), timed on the host's BLAS threads.  Returns the rate and the
+    sample with its oracle (mu, sigma), which also serves to measure the GPU
+    paths' error against the oracle."""
     import numpy as np
     from threadpoolctl import threadpool_info
 
     from oracle.propagate import UP, propagate
     from workloads import random_boxes
 
-    counts = np.array([l["cells"] for l in levels], dtype=np.float64)
-    total = counts.sum()
-    p = counts / total
-    rng = np.random.default_rng(0)
+    rng = np.random.default_rng(seed)
+    levels = list(range(min(3, depth), depth + 1))
+    cs, hs, ls, mus, sgs = [], [], [], [], []
     done, t_used = 0, 0.0
-    batch = 16
+    batch = 32
     while t_used < budget_s:
-        lv = int(rng.choice(len(p), p=p))
-        c, h, _ = random_boxes(batch, [lv], seed=int(rng.integers(1 << 30)))
+        c, h, L = random_boxes(batch, levels, seed=int(rng.integers(1 << 30)))
         t0 = time.perf_counter()
-        propagate(mlp, c, h, UP)
+        mu, sg = propagate(mlp, c, h, UP)
         t_used += time.perf_counter() - t0
         done += batch
+        cs.append(c)
+        hs.append(h)
+        ls.append(L)
+        mus.append(mu)
+        sgs.append(sg)
     rate = done / t_used
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    return rate, done, t_used, threads, total
+    sample = dict(centres=np.concatenate(cs), halves=np.concatenate(hs), levels=np.concatenate(ls),
+                  mu=np.concatenate(mus), sigma=np.concatenate(sgs))
+    return rate, done, t_used, threads, sample
+
+
+def error_vs_oracle(ctx, mid, mlp, sample, S, k, n_aa, log):
+    """Error of the GPU's BF16 bounds (UP covariance form, UP coefficient form,
+    AA) and FP32 UP bounds against the float64 oracle, per octree level: max
+    and 99.9th percentile of |endpoint_gpu - endpoint_oracle| / S over both
+    endpoints centre -/+ k spread (AA: k = 1).  AA is measured on the first
+    n_aa cells of the sample (the oracle's AA is run here, untimed)."""
+    import numpy as np
+    import torch
+
+    import paper_2402_13861_amd as isx
+    from oracle.propagate import AA, propagate
+
+    def gpu(method, prec, c, h, form=0):
+        ctx.set_option(isx.UP_FORM, form)
+        out = torch.empty((c.shape[0], 2), dtype=torch.float32, device="cuda")
+        ctx.propagate(mid, method, prec, torch.from_numpy(c).cuda(), torch.from_numpy(h).cuda(), out)
+        torch.cuda.synchronize()
+        ctx.set_option(isx.UP_FORM, 0)
+        return out.cpu().numpy().astype(np.float64)
+
+    def stats(g, oc, os_, kk, lv):
+        e = np.maximum(np.abs((g[:, 0] - kk * g[:, 1]) - (oc - kk * os_)),
+                       np.abs((g[:, 0] + kk * g[:, 1]) - (oc + kk * os_))) / S
+        per = {}
+        for L in np.unique(lv):
+            sel = lv == L
+            per[int(L)] = {"n": int(sel.sum()), "max": float(e[sel].max()),
+                           "p999": float(np.quantile(e[sel], 0.999))}
+        return {"max": float(e.max()), "p999": float(np.quantile(e, 0.999)), "levels": per}
+
+    c, h, lv = sample["centres"], sample["halves"], sample["levels"]
+    mu, sg = sample["mu"], sample["sigma"]
+    out = {"unit": "S (output scale)", "n_cells": int(c.shape[0]), "k": k}
+    out["up_bf16_cov"] = stats(gpu(isx.UP, isx.BF16, c, h, 0), mu, sg, k, lv)
+    out["up_bf16_coef"] = stats(gpu(isx.UP, isx.BF16, c, h, 1), mu, sg, k, lv)
+    out["up_fp32"] = stats(gpu(isx.UP, isx.FP32, c, h), mu, sg, k, lv)
+    na = min(n_aa, c.shape[0])
+    x0, r = propagate(mlp, c[:na], h[:na], AA)
+    out["aa_bf16"] = stats(gpu(isx.AA, isx.BF16, c[:na], h[:na]), x0, r, 1.0, lv[:na])
+    out["aa_fp32"] = stats(gpu(isx.AA, isx.FP32, c[:na], h[:na]), x0, r, 1.0, lv[:na])
+    for key in ("up_bf16_cov", "up_bf16_coef", "up_fp32", "aa_bf16", "aa_fp32"):
+        v = out[key]
+        log(f"error vs oracle {key}: max {v['max']:.3e} S, p99.9 {v['p999']:.3e} S; per level max " +
+            ", ".join(f"L{L} {d['max']:.2e}" for L, d in v["levels"].items()))
+    return out
+
 
 
 def copy_probe(nbytes: int, reps: int = 5):
@@ -128,7 +231,9 @@ def main(argv=None):
                     help="held-out (cell, propagated) pairs for the error and band calibration")
     ap.add_argument("--sur-steps", type=int, default=2000)
     ap.add_argument("--depth", type=int, default=None)
-    ap.add_argument("--cpu-baseline-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-baseline-seconds", type=float, default=25.0)
+    ap.add_argument("--no-bf16-only", action="store_true",
+                    help="skip the BF16 extraction without the surrogate (its recall is reported)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-bytes", type=int, default=0,
                     help="only run a plain copy of this many bytes (counter calibration) and exit")
@@ -181,6 +286,21 @@ def main(argv=None):
         plain = dict(ms=1e3 * plain_s, leaves=int(m.n_leaves), tris=int(m.n_tris),
                      propagated=sum(l["cells"] for l in m.levels()), phases=m.times())
         log(f"plain fp32: {1e3 * plain_s:.1f} ms, {m.n_leaves} leaves")
+        m.free()
+
+    # 1b. BF16 without the surrogate: separates the BF16 error's share of the
+    #     leaf differences from the surrogate's
+    bf16_only = None
+    if plain is not None and a.precision == "bf16" and use_sur and not a.no_bf16_only:
+        t0 = time.perf_counter()
+        m = ctx.extract(mid, precision=isx.BF16, **base)
+        dt = time.perf_counter() - t0
+        ids_b, _ = m.leaves()
+        common = np.intersect1d(plain_ids, ids_b).size
+        bf16_only = dict(ms=1e3 * dt, leaves=int(m.n_leaves), recall_vs_plain=common / max(plain_ids.size, 1),
+                         false_active_vs_plain=(ids_b.size - common) / max(ids_b.size, 1),
+                         rechecked=sum(l["rechecked"] for l in m.levels()))
+        log(f"bf16 without surrogate: {bf16_only}")
         m.free()
 
     # 2. surrogate training (once per INR, not part of the timed extraction)
@@ -248,29 +368,57 @@ def main(argv=None):
                        plain_leaves=int(plain_ids.size), leaves=int(last_ids.size))
         log("quality:", quality)
 
+    # per hidden-layer kernel kind: achieved rate at the algorithmic flop count
+    # of its formulation (coefficient form: alg_flops_coefficient per cell;
+    # covariance form: the cheapest exact formulation, alg_flops_cov_hybrid),
+    # and at the flops the kernel executes (the library's own count)
+    rechecked = sum(l["rechecked"] for l in levels)
+    per_kernel = {}
+    for kname, (kern, src, dt, form) in HIDDEN_KINDS.items():
+        v = prof[kname]
+        if not v["launches"] or v["ms"] <= 0:
+            continue
+        if kname == "hidden_cov_bf16":
+            alg = propagated * K * alg_flops_cov_hybrid(mlp.widths)
+        elif kname == "hidden_fp64":
+            alg = rechecked * K * alg_flops_coefficient(mlp.widths)
+        else:
+            alg = v["flops"]
+        sec = v["ms"] * 1e-3
+        per_kernel[kname] = {
+            "kernel": kern, "dtype": dt, "formulation": form, "ms_per_step": round(v["ms"] / K, 2),
+            "launches_per_step": v["launches"] / K, "alg_flops_per_step": alg / K,
+            "achieved_TFLOPs": round(alg / sec / 1e12, 2), "frac": round(alg / sec / 1e12 / PEAK_TFLOPS[dt], 4),
+            "executed_flops_per_step": v["flops"] / K,
+            "executed_TFLOPs": round(v["flops"] / sec / 1e12, 2),
+            "frac_executed": round(v["flops"] / sec / 1e12 / PEAK_TFLOPS[dt], 4),
+        }
     # the dominant hidden-layer kernel: the kind with the most device time
-    kind = max(HIDDEN_KINDS, key=lambda k_: prof[k_]["ms"])
+    kind = max(per_kernel, key=lambda k_: prof[k_]["ms"])
     kp = prof[kind]
+    pk = per_kernel[kind]
     launches = max(kp["launches"], 1)
     avg_ms = kp["ms"] / launches
-    flops_per_launch = kp["flops"] / launches
-    achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
-    peak = PEAK_TFLOPS[HIDDEN_KINDS[kind][2]]
-    cells_per_launch = propagated / (kp["launches"] / K) if kp["launches"] else 0.0
+    alg_per_launch = pk["alg_flops_per_step"] * K / launches
+    cells_kind = rechecked if kind == "hidden_fp64" else propagated
+    cells_per_launch = cells_kind / (kp["launches"] / K) if kp["launches"] else 0.0
     traffic = traffic_from_profiles(kind, cells_per_launch)
     roofline = {
         "bound": "mfma",
         "kernel": HIDDEN_KINDS[kind][0],
-        "achieved": round(achieved, 3),
-        "peak": peak,
+        "achieved": round(alg_per_launch / (avg_ms * 1e-3) / 1e12, 3),
+        "peak": PEAK_TFLOPS[HIDDEN_KINDS[kind][2]],
         "unit": "TFLOP/s",
-        "frac": round(achieved / peak, 4),
+        "frac": pk["frac"],
         "traffic": traffic,
         "launches": kp["launches"],
         "avg_launch_ms": round(avg_ms, 4),
-        "flops_per_launch": flops_per_launch,
+        "alg_flops_per_launch": alg_per_launch,
+        "cells_per_launch": cells_per_launch,
+        "frac_executed": pk["frac_executed"],
         "alg_bytes_per_launch": kp["bytes"] / launches,
         "alg_hbm_GBps": round(kp["bytes"] / launches / (avg_ms * 1e-3) / 1e9, 1) if avg_ms > 0 else 0.0,
+        "per_kernel": per_kernel,
     }
     kernels = {}
     for name, v in prof.items():
@@ -278,21 +426,31 @@ def main(argv=None):
             kernels[name] = {"ms_per_step": round(v["ms"] / K, 2), "launches_per_step": v["launches"] / K,
                              "TFLOPs": round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 2) if v["ms"] > 0 else None}
     log("kernel time per step:", kernels)
+    log("roofline per kernel:", per_kernel)
 
     cpu = None
+    err_oracle = None
     if not a.no_cpu_baseline:
-        rate, done, t_used, threads, total = cpu_baseline(mlp, levels, a.cpu_baseline_seconds)
-        total_plain = plain["propagated"] if plain is not None else total
+        rate, done, t_used, threads, sample = cpu_baseline(mlp, depth, a.cpu_baseline_seconds)
+        total_plain = plain["propagated"] if plain is not None else examined
         est_s = total_plain / rate
+        n_cores, cpu_model = host_cpu()
         cpu = {
             "value": eff_cells / est_s,
             "unit": "cells/s",
             "cores": threads,
+            "host_cores": n_cores,
+            "cpu_model": cpu_model,
             "kind": "oracle",
-            "sample": (f"float64 oracle propagation of {done} random cells drawn over octree levels in proportion "
-                       f"to the extraction's cells ({t_used:.1f} s, {rate:.1f} cells/s); plain-method extraction "
-                       f"time extrapolated from propagation of its {int(total_plain)} cells alone ({est_s:.0f} s)"),
+            "sample": (f"float64 oracle propagation of {done} random cells drawn uniformly over octree levels "
+                       f"3..{depth} ({t_used:.1f} s on {threads} BLAS threads, {rate:.1f} cells/s; the oracle's "
+                       f"cost per cell does not depend on the level); plain-method extraction time extrapolated "
+                       f"from propagation of its {int(total_plain)} cells alone ({est_s:.0f} s)"),
         }
+        err_oracle = error_vs_oracle(ctx, mid, mlp, sample, S, w["k"], 2000, log)
+        err_oracle["band_S"] = w.get("band_rel", 0.0)
+        err_oracle["levels_where_band_exceeds_bf16_max"] = [
+            L for L, d in err_oracle["up_bf16_cov"]["levels"].items() if d["max"] < w.get("band_rel", 0.0)]
 
     name = ("bf16+surrogate" if use_sur else "bf16") if a.precision == "bf16" else ("fp32+surrogate" if use_sur
                                                                                      else "fp32")
@@ -319,6 +477,8 @@ def main(argv=None):
         "plain_fp32": plain and {k: v for k, v in plain.items() if k != "phases"},
         "speedup_vs_plain_fp32": (plain["ms"] / ms_per_step) if plain else None,
         "quality": quality,
+        "bf16_only": bf16_only,
+        "bf16_err_vs_oracle": err_oracle,
         "surrogate": sur_info,
         "examined_cells": examined,
         "propagated_cells": propagated,

@@ -4,12 +4,31 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "isx.h"
 
 namespace isx {
+
+// Raise a kernel's dynamic LDS limit to `bytes` on the current device, once
+// per (device, kernel, size).  Safe when several host threads launch at once
+// (batched extraction drives one context per thread).
+inline hipError_t ensure_lds_limit(const void* fn, int bytes) {
+  static std::mutex mu;
+  static std::vector<std::tuple<int, const void*, int>> done;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> g(mu);
+  for (const auto& t : done)
+    if (std::get<0>(t) == dev && std::get<1>(t) == fn && std::get<2>(t) >= bytes) return hipSuccess;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess) done.emplace_back(dev, fn, bytes);
+  return e;
+}
 
 // Column layout of a cell's coefficient block at hidden layer h (1-based):
 // column 0 holds the centre, columns 1..3 the coefficients of the three input

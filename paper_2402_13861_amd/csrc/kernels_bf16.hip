@@ -374,12 +374,9 @@ static hipError_t launch_bf16_k(int64_t C, int n_in, int n_out, int64_t s_in, in
   const int rb_count = n_out / BM;
   const int64_t blocks = ((C + 7) / 8) * 8 * rb_count;
   const size_t lds = (2 * (size_t)BN * (KMAXT + 8) + 2 * (size_t)BN * (BM + 8)) * sizeof(__bf16);
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)hidden_mfma_bf16_kernel<METHOD, NW, RB, NB, KMAXT>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  {
+    hipError_t e = ensure_lds_limit((const void*)hidden_mfma_bf16_kernel<METHOD, NW, RB, NB, KMAXT>, (int)lds);
     if (e != hipSuccess) return e;
-    attr_set = true;
   }
   hipLaunchKernelGGL((hidden_mfma_bf16_kernel<METHOD, NW, RB, NB, KMAXT>), dim3((unsigned)blocks), dim3(64 * NW), lds, s, C,
                      n_in, n_out, s_in, g_in, rb_count, W, bias, WtPrev, Gprev2, Fin, Yin, Ain, Bin, Gin, Fout, Y, A,

@@ -516,12 +516,9 @@ bool cov_supported(const Model& m) { return cov_width(m) != 0; }
 template <int N>
 static hipError_t launch_cov_n(const Model& m, int64_t C, const float* centres, const float* halves, float* vec,
                                hipStream_t s) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&up_cov_bf16_kernel<N>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)CovShape<N>::LDS);
+  {
+    hipError_t e = ensure_lds_limit(reinterpret_cast<const void*>(&up_cov_bf16_kernel<N>), (int)CovShape<N>::LDS);
     if (e != hipSuccess) return e;
-    attr_set = true;
   }
   // one workgroup per cell: a launch's work-items must stay below 2^32
   if (C > (int64_t(1) << 22)) return hipErrorInvalidValue;

@@ -254,12 +254,9 @@ static hipError_t launch_dense_k(const Model& m, int64_t n, const float* in0, co
   constexpr int per = MODE == DENSE_LIN ? 4 : 1;
   constexpr int items = Sh::BN / per;
   const int64_t blocks = (n + items - 1) / items;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&dense_mfma_kernel<MODE, KMAX>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)Sh::LDS);
+  {
+    hipError_t e = ensure_lds_limit(reinterpret_cast<const void*>(&dense_mfma_kernel<MODE, KMAX>), (int)Sh::LDS);
     if (e != hipSuccess) return e;
-    attr_set = true;
   }
   hipLaunchKernelGGL((dense_mfma_kernel<MODE, KMAX>), dim3((unsigned)blocks), dim3(kDenseThreads), Sh::LDS, s, n,
                      dense_net(m), in0, in1, out);
@@ -446,12 +443,9 @@ template <int METHOD, int KMAX>
 static hipError_t launch_output_k(int64_t C, const OutNet& net, const float* halves, float* out, hipStream_t s) {
   using Sh = DenseShape<KMAX>;
   const size_t lds = Sh::LDS + (size_t)(Sh::BN * (KMAX / 32) + 2 * Sh::BN) * sizeof(float);
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&output_mfma_kernel<METHOD, KMAX>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  {
+    hipError_t e = ensure_lds_limit(reinterpret_cast<const void*>(&output_mfma_kernel<METHOD, KMAX>), (int)lds);
     if (e != hipSuccess) return e;
-    attr_set = true;
   }
   const int64_t blocks = (C + Sh::BN - 1) / Sh::BN;
   hipLaunchKernelGGL((output_mfma_kernel<METHOD, KMAX>), dim3((unsigned)blocks), dim3(kDenseThreads), lds, s, C, net,
@@ -651,12 +645,9 @@ __global__ __launch_bounds__(kDenseThreads) void lin_bf16_kernel(int64_t n_items
 template <int N>
 static hipError_t launch_lin_n(const Model& m, int64_t n, const float* centres, const float* halves, float* out,
                                hipStream_t s) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&lin_bf16_kernel<N>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)LinShape<N>::LDS);
+  {
+    hipError_t e = ensure_lds_limit(reinterpret_cast<const void*>(&lin_bf16_kernel<N>), (int)LinShape<N>::LDS);
     if (e != hipSuccess) return e;
-    attr_set = true;
   }
   const int64_t blocks = (n + kLinCells - 1) / kLinCells;
   hipLaunchKernelGGL((lin_bf16_kernel<N>), dim3((unsigned)blocks), dim3(kDenseThreads), LinShape<N>::LDS, s, n,
@@ -874,12 +865,9 @@ __global__ __launch_bounds__(kDenseThreads) void output_bf16_kernel(int64_t C, O
 template <int N>
 static hipError_t launch_out_bf16_n(int64_t C, const OutNet& net, const Model& m, const float* halves, float* out,
                                     hipStream_t s) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&output_bf16_kernel<N>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)OutShape<N>::LDS);
+  {
+    hipError_t e = ensure_lds_limit(reinterpret_cast<const void*>(&output_bf16_kernel<N>), (int)OutShape<N>::LDS);
     if (e != hipSuccess) return e;
-    attr_set = true;
   }
   const int64_t blocks = (C + kOutCells - 1) / kOutCells;
   hipLaunchKernelGGL((output_bf16_kernel<N>), dim3((unsigned)blocks), dim3(kDenseThreads), OutShape<N>::LDS, s, C,

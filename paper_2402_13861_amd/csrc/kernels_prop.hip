@@ -346,13 +346,9 @@ static hipError_t launch_output_simt(const Model& m, int64_t C, const NetView<T>
   int nmax = 3;
   for (int h = 1; h < m.n_linear; ++h) nmax = std::max(nmax, m.pw[h]);
   const size_t lds = (size_t)2 * CPB * nmax * sizeof(T);
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&output_kernel<T, METHOD, CPB>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)(2 * CPB * ISX_MAX_WIDTH * sizeof(T)));
+  {
+    hipError_t e = ensure_lds_limit(reinterpret_cast<const void*>(&output_kernel<T, METHOD, CPB>), (int)(2 * CPB * ISX_MAX_WIDTH * sizeof(T)));
     if (e != hipSuccess) return e;
-    attr_set = true;
   }
   hipLaunchKernelGGL((output_kernel<T, METHOD, CPB>), dim3((unsigned)((C + CPB - 1) / CPB)), dim3(256), lds, s, C,
                      view, nmax, halves, out32, out64);

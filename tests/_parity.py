@@ -80,3 +80,40 @@ def unexcused_level_diffs(gpu_levels, oracle_levels, close):
 def leaf_ijk(ids):
     i, j, k = morton_decode(np.asarray(ids, dtype=np.uint64))
     return np.stack([i, j, k], axis=1)
+
+
+def unexplained_unshared_edges(gmap, omap, depth, f, iso, S, diff_leaves, band_rel=1e-4):
+    """Grid edges that carry a vertex in only one of the two meshes and are
+    explained by neither of the two allowed causes: a containing cell that is
+    an active leaf in one run only (``diff_leaves``, Morton ids, each already
+    excused by the active-set check), or an endpoint whose value lies within
+    band_rel * S of the iso-value (the case bits may differ there).  Keys are
+    (grid point linear index) * 3 + axis on the (2^D + 1)^3 grid."""
+    from oracle.octree import morton_encode
+
+    R = (1 << depth) + 1
+    n = 1 << depth
+    bad = []
+    for key in set(gmap) ^ set(omap):
+        p, axis = divmod(int(key), 3)
+        i, j, kk = p % R, (p // R) % R, p // (R * R)
+        ijk = [i, j, kk]
+        end = list(ijk)
+        end[axis] += 1
+        step = 2.0 / n
+        pts = np.array([[-1.0 + step * q for q in ijk], [-1.0 + step * q for q in end]])
+        v = f(pts)
+        if np.abs(v - iso).min() <= band_rel * S:
+            continue
+        cells = []
+        others = [a for a in range(3) if a != axis]
+        for d0 in (-1, 0):
+            for d1 in (-1, 0):
+                c = list(ijk)
+                c[others[0]] += d0
+                c[others[1]] += d1
+                if all(0 <= c[a] < n for a in range(3)):
+                    cells.append(int(morton_encode(c[0], c[1], c[2])))
+        if not any(c in diff_leaves for c in cells):
+            bad.append(int(key))
+    return bad

@@ -1,0 +1,183 @@
+"""GPU parity at the benchmark's network shape, against the float64 oracle.
+
+Nets: the 3->256x5->1 ReLU INR fitted to the synthetic Fourier field (the
+benchmark's INR) and a He-normal 3->256x5->1 (seed 0).  Checked here:
+* float32 (MFMA and vector-ALU kernels) and float64 propagation, both
+  methods, at 1e-5 / 1e-10 of max(|o|, S) on the bounds (spread: 1e-4 / 1e-9
+  relative), on dyadic cells of every octree level 0..9;
+* the BF16 paths' bound error against the oracle per octree level, in units
+  of S, with the float64 re-check band shown to exceed it where the band is
+  meant to protect the classification (levels >= 6);
+* extraction at depth 7 with the three iso-values: the float32 + band and
+  the BF16 + band leaf sets against the float64 extraction (the plain-UP set
+  the recall target refers to).
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle.propagate import AA, UP, propagate
+from workloads import he_normal_mlp, random_boxes
+
+from _parity import assert_pair_close, output_scale
+
+pytestmark = pytest.mark.gpu
+
+METHODS = {"up": (UP, 1), "aa": (AA, 0)}
+INR = "relu256x5_fourier"
+
+# Largest BF16 endpoint error against the oracle, in units of S, over levels
+# 0..9 of the 3->256x5->1 INR (about twice the largest value measured on the
+# device, rounded up): UP covariance form, UP coefficient form, AA.
+BF16_ENDPOINT_TOL = {"up-cov": 2e-2, "up-coef": 2e-2, "aa": 2e-2}
+BAND_REL = 1e-3  # the float64 re-check band of the benchmark, in units of S
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2402_13861_amd as isx
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    c = isx.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def _net(name):
+    from workloads.configs import load_mlp
+
+    if name == "fourier-inr":
+        return load_mlp(INR)
+    return he_normal_mlp([3, 256, 256, 256, 256, 256, 1], seed=0)
+
+
+def _gpu_prop(ctx, mid, method, precision, c, h, kernel=0, form=0):
+    import paper_2402_13861_amd as isx
+
+    ctx.set_option(isx.HIDDEN_KERNEL, kernel)
+    ctx.set_option(isx.UP_FORM, form)
+    n = c.shape[0]
+    out = torch.full((n, 2), float("nan"), dtype=torch.float32, device="cuda")
+    out64 = torch.full((n, 2), float("nan"), dtype=torch.float64, device="cuda") if precision == isx.FP64 else None
+    try:
+        ctx.propagate(mid, method, precision, torch.from_numpy(c).cuda(), torch.from_numpy(h).cuda(), out, out64)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_option(isx.HIDDEN_KERNEL, 0)
+        ctx.set_option(isx.UP_FORM, 0)
+    return out.cpu().numpy(), (out64.cpu().numpy() if out64 is not None else None)
+
+
+@pytest.mark.parametrize("net", ["fourier-inr", "he-normal"])
+@pytest.mark.parametrize("mname", ["up", "aa"])
+def test_propagate_256x5_fp32_and_fp64_match_oracle(ctx, net, mname):
+    import paper_2402_13861_amd as isx
+
+    method, gm = METHODS[mname]
+    mlp = _net(net)
+    S = output_scale(mlp)
+    k = 3.0 if mname == "up" else 1.0
+    c, h, _ = random_boxes(200, range(0, 10), seed=41)
+    print(f"oracle {mname} on {net}: 200 cells, levels 0..9", flush=True)
+    ref = propagate(mlp, c, h, method)
+    mid = ctx.load_weights(mlp)
+    try:
+        for kern, kname in ((0, "mfma"), (1, "simt")):
+            g32, _ = _gpu_prop(ctx, mid, gm, isx.FP32, c, h, kernel=kern)
+            assert_pair_close(g32, ref, S, 1e-5, f"fp32 {kname} {mname} {net}", k=k)
+            _, g64 = _gpu_prop(ctx, mid, gm, isx.FP64, c, h, kernel=kern)
+            assert_pair_close(g64, ref, S, 1e-10, f"fp64 {kname} {mname} {net}", k=k)
+    finally:
+        ctx.unload_mlp(mid)
+
+
+def _endpoint_err(g, oc, os_, k, S):
+    g = np.asarray(g, np.float64)
+    lo = np.abs((g[:, 0] - k * g[:, 1]) - (oc - k * os_))
+    hi = np.abs((g[:, 0] + k * g[:, 1]) - (oc + k * os_))
+    return np.maximum(lo, hi) / S
+
+
+def test_bf16_error_per_level_on_the_benchmark_inr(ctx):
+    """BF16 bound error against the oracle on 80 cells per octree level
+    0..9 (800 cells), per level max and 99.9th percentile in units of S.
+    Both UP forms and AA stay within BF16_ENDPOINT_TOL; for UP (the
+    benchmark's method) the band 1e-3 S exceeds the largest error at every
+    level from 6 on, so that a cell classified differently in BF16 and in
+    float64 there is always inside the band and re-decided in float64."""
+    import paper_2402_13861_amd as isx
+    from workloads.configs import isovalues
+
+    mlp = _net("fourier-inr")
+    _, S = isovalues(INR)
+    rng_levels = np.repeat(np.arange(10), 80)
+    cs, hs = [], []
+    for L in range(10):
+        c, h, _ = random_boxes(80, [L], seed=100 + L)
+        cs.append(c)
+        hs.append(h)
+    c, h = np.concatenate(cs), np.concatenate(hs)
+    print("oracle UP and AA on 800 cells of the 3->256x5->1 INR", flush=True)
+    mu, sg = propagate(mlp, c, h, UP)
+    x0, r = propagate(mlp, c, h, AA)
+    mid = ctx.load_weights(mlp)
+    try:
+        results = {
+            "up-cov": _endpoint_err(_gpu_prop(ctx, mid, isx.UP, isx.BF16, c, h, form=0)[0], mu, sg, 3.0, S),
+            "up-coef": _endpoint_err(_gpu_prop(ctx, mid, isx.UP, isx.BF16, c, h, form=1)[0], mu, sg, 3.0, S),
+            "aa": _endpoint_err(_gpu_prop(ctx, mid, isx.AA, isx.BF16, c, h)[0], x0, r, 1.0, S),
+            "up-fp32": _endpoint_err(_gpu_prop(ctx, mid, isx.UP, isx.FP32, c, h)[0], mu, sg, 3.0, S),
+        }
+    finally:
+        ctx.unload_mlp(mid)
+    for name, e in results.items():
+        per = [(L, float(e[rng_levels == L].max()), float(np.quantile(e[rng_levels == L], 0.999)))
+               for L in range(10)]
+        print(f"bf16 error vs oracle [{name}] (units of S): max {e.max():.3e} p99.9 {np.quantile(e, 0.999):.3e}; "
+              + ", ".join(f"L{L} {m:.2e}/{q:.2e}" for L, m, q in per), flush=True)
+    for name, tol in BF16_ENDPOINT_TOL.items():
+        assert results[name].max() <= tol, (name, float(results[name].max()))
+    for name in ("up-cov", "up-coef"):
+        deep = results[name][rng_levels >= 6]
+        assert deep.max() < BAND_REL, (name, float(deep.max()))
+    assert results["up-fp32"].max() < 1e-2 * BAND_REL
+
+
+def test_band_leaf_sets_equal_fp64_extraction_depth7(ctx):
+    """Depth 7 (128^3), 3 iso-values, t = 3 on the benchmark INR: the float32
+    and the BF16 extractions with the 1e-3 S float64 re-check band give the
+    float64 extraction's leaves (the plain-UP set the recall target refers
+    to).  float32: exactly, since its bound error (1e-5 of max(|o|, S)) is far
+    inside the band and band cells are decided by the same float64 kernels.
+    BF16: recall and precision at least 99.99 %, every difference counted."""
+    import paper_2402_13861_amd as isx
+    from workloads.configs import isovalues
+
+    mlp = _net("fourier-inr")
+    isos, S = isovalues(INR)
+    mid = ctx.load_weights(mlp)
+    try:
+        ctx.set_isovalues(mid, isos)
+        kw = dict(k=3.0, max_depth=7)
+        m64 = ctx.extract(mid, isx.UP, isx.FP64, **kw)
+        ids64, masks64 = m64.leaves()
+        m64.free()
+        m32 = ctx.extract(mid, isx.UP, isx.FP32, fp64_band=BAND_REL * S, **kw)
+        ids32, masks32 = m32.leaves()
+        m32.free()
+        mbf = ctx.extract(mid, isx.UP, isx.BF16, fp64_band=BAND_REL * S, **kw)
+        idsbf, _ = mbf.leaves()
+        rc = sum(l["rechecked"] for l in mbf.levels())
+        mbf.free()
+    finally:
+        ctx.unload_mlp(mid)
+    common = np.intersect1d(idsbf, ids64).size
+    print(f"depth 7 leaves: fp64 {ids64.size}, fp32+band {ids32.size}, bf16+band {idsbf.size} "
+          f"(common with fp64 {common}, bf16 re-checked {rc})", flush=True)
+    np.testing.assert_array_equal(ids32, ids64)
+    np.testing.assert_array_equal(masks32, masks64)
+    assert common >= 0.9999 * ids64.size
+    assert common >= 0.9999 * idsbf.size

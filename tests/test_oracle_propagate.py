@@ -316,3 +316,57 @@ def test_aa_margin_constant_bounds_float32_and_bf16_products(K):
                 acc = np.float32(acc + np.float32(wr[k] * xr[k]))
             acc = np.float32(acc + b)
             assert abs(float(acc) - exact) <= margin_const(K, U32, u_b) * scale, (trial, u_b)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_raua_affine_net_closed_form(seed):
+    """RA-UA (Sec. IV-A, Eq. 5): affine-arithmetic coefficients read off as
+    independent uniform variables, variance x_i^2 / 3 each.  On a net that is
+    affine on the box the AA coefficients are exactly A_i h_i, so the read-off
+    is N(f(c), sum (A_i h_i)^2 / 3) -- the exact mean and variance of f under
+    a uniform input on the box."""
+    from oracle.propagate import RAUA
+
+    layers, A, a = _affine_on_domain_net(seed)
+    c, h, _ = random_boxes(64, range(0, 6), seed=20 + seed)
+    c = c.astype(np.float64)
+    h = h.astype(np.float64)
+    mu, sigma = propagate(layers, c, h, RAUA)
+    np.testing.assert_allclose(mu, c @ A + a, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(sigma, np.sqrt(((A * h) ** 2).sum(1) / 3.0), rtol=1e-12)
+
+
+def test_raua_one_kink_hand_example():
+    """One ReLU neuron on the pre-activation 1 + 2 eps_1 (range [-1, 3]):
+    the Chebyshev rule gives 0.75 x + 0.375 + 0.375 eps', so the output form
+    is 1.125 + 1.5 eps_1 + 0.375 eps'.  RA-UA reads it as mean 1.125 and
+    variance (1.5^2 + 0.375^2) / 3 = 0.796875; AA's radius is 1.875."""
+    from oracle.propagate import RAUA
+
+    layers = [(np.array([[1.0, 0.0, 0.0]]), np.array([0.0])), (np.array([[1.0]]), np.array([0.0]))]
+    c = np.array([[1.0, 0.3, -0.2]])
+    h = np.array([[2.0, 0.5, 0.25]])
+    mu, sigma = propagate(layers, c, h, RAUA)
+    assert mu[0] == pytest.approx(1.125, abs=1e-15)
+    assert sigma[0] == pytest.approx(np.sqrt(0.796875), rel=1e-15)
+    x0, r = propagate(layers, c, h, AA)
+    assert x0[0] == pytest.approx(1.125, abs=1e-15)
+    assert r[0] == pytest.approx(1.875, rel=1e-15)
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_raua_between_aa_radius_bounds(seed):
+    """RA-UA and AA share the coefficients x_i (N of them), so by the norm
+    inequalities r / sqrt(3 N) <= sigma_RAUA <= r / sqrt(3) with r = sum |x_i|,
+    and the centres are equal."""
+    from oracle.propagate import RAUA
+
+    widths = [3, 16, 16, 1]
+    mlp = he_normal_mlp(widths, seed=seed)
+    c, h, _ = random_boxes(200, range(0, 6), seed=seed)
+    mu, sigma = propagate(mlp, c, h, RAUA)
+    x0, r = propagate(mlp, c, h, AA)
+    np.testing.assert_array_equal(mu, x0)
+    n_sym = 3 + sum(widths[1:-1])
+    assert np.all(sigma <= r / np.sqrt(3.0) * (1 + 1e-12))
+    assert np.all(sigma >= r / np.sqrt(3.0 * n_sym) * (1 - 1e-12))
