@@ -231,7 +231,7 @@ def main(argv=None):
                     help="held-out (cell, propagated) pairs for the error and band calibration")
     ap.add_argument("--sur-steps", type=int, default=2000)
     ap.add_argument("--depth", type=int, default=None)
-    ap.add_argument("--cpu-baseline-seconds", type=float, default=25.0)
+    ap.add_argument("--cpu-baseline-seconds", type=float, default=30.0)
     ap.add_argument("--no-bf16-only", action="store_true",
                     help="skip the BF16 extraction without the surrogate (its recall is reported)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

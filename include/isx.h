@@ -110,7 +110,10 @@ isx_status isx_set_isovalues(isx_ctx* ctx, int32_t mlp_id, int32_t n_iso, const 
  * (x0, r) for ISX_AA, whose range is [x0 - r, x0 + r] (Eq. 2), and
  * (mu, sigma) for ISX_UP (Eq. 7).  With ISX_FP64 the same pair is also
  * written in float64 to d_out64 [n][2] if it is not NULL (it must be NULL
- * for the other precisions).  Asynchronous.  n_cells == 0 is a no-op.
+ * for the other precisions).  Asynchronous, except ISX_BF16 with ISX_UP in
+ * covariance form with ISX_CANCEL_CHECK on (the default), which synchronises
+ * the stream once to count the cells it re-propagates in float64.
+ * n_cells == 0 is a no-op.
  * Errors: ISX_EINVAL, ISX_ENOMEM, ISX_EHIP. */
 isx_status isx_propagate(isx_ctx* ctx, int32_t mlp_id, isx_method method, isx_precision precision,
                          int64_t n_cells, const float* d_centres, const float* d_halves, float* d_out,
@@ -189,6 +192,10 @@ isx_status isx_mesh_info(const isx_mesh* mesh, int64_t* n_tris, int64_t* n_leave
  * (all examined cells unless the surrogate decided some). */
 isx_status isx_mesh_level(const isx_mesh* mesh, int32_t level, int64_t* n_cells, int64_t* n_active,
                           int64_t* n_rechecked, int64_t* n_propagated);
+
+/* Cells of a level that the bf16 covariance form flagged for cancellation
+ * and propagated again in float64 (ISX_CANCEL_CHECK; 0 for other paths). */
+isx_status isx_mesh_level_cancelled(const isx_mesh* mesh, int32_t level, int64_t* n_cancelled);
 
 /* Phase times in milliseconds measured with HIP events on the context
  * stream: active-cell prediction (all levels), corner evaluation, marching
@@ -281,6 +288,25 @@ isx_status isx_surrogate_attach(isx_ctx* ctx, int32_t mlp_id, int32_t sur_id, in
                                 const float* h_z_accept, int32_t accept_leaves);
 isx_status isx_surrogate_free(isx_ctx* ctx, int32_t sur_id);
 
+/* isx_surrogate_partition: the band partition isx_extract applies at octree
+ * level `level` (bands of that level as attached to mlp_id by
+ * isx_surrogate_attach, its iso-values, bound multiplier k = t), on n caller
+ * cells.  d_pred [n][2] = (mu_hat, sigma_hat) as from isx_surrogate_predict,
+ * d_unit [n] the per-cell unit of err_mu (the base scale s_b for a surrogate
+ * with a base; NULL = 1), d_parent_mask [n] the iso bits each cell carries.
+ * Per carried iso-value c, with d = |mu_hat - c|: outside if
+ * d - z err_mu unit > t sigma_hat exp(z err_logsig), inside if
+ * d + z_accept err_mu unit < t sigma_hat exp(-z_accept err_logsig), else
+ * unsure.  d_fallback[i] = 1 (propagate; d_mask[i] = 0) if some carried
+ * iso-value is unsure or the prediction is not finite, or if leaf != 0, the
+ * surrogate may not accept leaves and some bit is inside; otherwise
+ * d_fallback[i] = 0 and d_mask[i] = the inside bits (0 = pruned).
+ * Float32 arithmetic.  Asynchronous.  Errors: ISX_EINVAL (also when no
+ * surrogate is attached), ISX_EHIP. */
+isx_status isx_surrogate_partition(isx_ctx* ctx, int32_t mlp_id, int64_t n, const float* d_pred,
+                                   const float* d_unit, float k, int32_t level, int32_t leaf,
+                                   const uint32_t* d_parent_mask, uint32_t* d_mask, uint32_t* d_fallback);
+
 /* isx_surrogate_save_file: write surrogate sur_id to `path` (binary, little
  * endian): "ISXSUR01", int32 n_linear, int32 widths[n_linear + 1], float32
  * mu_bar, S, a, b, s_floor, int32 has_base, then per layer the row-major
@@ -321,8 +347,13 @@ typedef enum {
                               accumulation 2^-24 float32 / 2^-53 float64), so that the returned range
                               contains the exact range of the network over the box; 0 (default) = the
                               paper's rule (exact arithmetic assumed) evaluated in floating point */
-  ISX_BATCH_WORKERS = 10   /* isx_extract_batch: worker contexts (streams) that run INRs at once, 1..16
+  ISX_BATCH_WORKERS = 10,  /* isx_extract_batch: worker contexts (streams) that run INRs at once, 1..16
                               (default 4) */
+  ISX_CANCEL_CHECK = 11    /* bf16 uncertainty propagation in covariance form: 1 (default) = a cell with a
+                              layer whose variance sum sum_i T_ji W_ji (signed, over bfloat16-rounded
+                              covariances) keeps at most 2^-9 of the magnitude sum_i |T_ji W_ji| of its
+                              terms is propagated again in float64 (Eq. 7 needs the variance; such a sum
+                              can lose every digit), and its float64 (mu, sigma) is returned; 0 = off */
 } isx_option;
 isx_status isx_set_option(isx_ctx* ctx, isx_option option, int64_t value);
 

@@ -84,3 +84,52 @@ def adam_step(params, grads, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
         mhat = mi / (1.0 - beta1 ** t)
         vhat = vi / (1.0 - beta2 ** t)
         p -= lr * mhat / (np.sqrt(vhat) + eps)
+
+
+def partition(pred, unit, k, isos, parent_mask, err_mu, err_ls, z, z_acc, leaf, accept_leaves):
+    """Band partition of cells by the surrogate's prediction (the learned
+    part's safety band around the soft-bound test of Alg. 1), float64.
+
+    pred [n, 2] = (mu_hat, sigma_hat); unit [n] scales err_mu per cell (None =
+    1, field units); err_mu / err_ls are the standard deviations of the
+    surrogate's error in mu (times unit) and in ln sigma; z / z_acc the prune
+    and accept bands in those units.  For every iso-value c_j the cell
+    carries (bit j of parent_mask), with d = |mu_hat - c_j|:
+      outside  if d - z err_mu unit > t sigma_hat e^{+z err_ls}      (bit dropped)
+      inside   if d + z_acc err_mu unit < t sigma_hat e^{-z_acc err_ls}  (bit kept)
+      unsure   otherwise.
+    A cell with no unsure iso-value is decided without propagation (its mask
+    is the set of inside bits); one with an unsure iso-value, a non-finite
+    prediction, or -- at the leaf level unless accept_leaves -- any inside
+    bit, falls back to propagation (mask 0, fallback 1).
+
+    Returns (mask uint32 [n], fallback bool [n], slack [n]): slack is the
+    smallest distance of a decision quantity to its threshold, relative to the
+    larger side, over the carried iso-values (a cell whose slack is within
+    float32 rounding may be decided either way in float32 arithmetic)."""
+    pred = np.asarray(pred, np.float64)
+    n = pred.shape[0]
+    mu, sg = pred[:, 0], pred[:, 1]
+    u = np.ones(n) if unit is None else np.asarray(unit, np.float64)
+    pm = np.asarray(parent_mask, np.uint32)
+    hi_s = k * sg * np.exp(z * err_ls)
+    lo_s = k * sg * np.exp(-z_acc * err_ls)
+    e, ea = z * err_mu * u, z_acc * err_mu * u
+    inside = np.zeros(n, np.uint32)
+    unsure = np.zeros(n, bool)
+    slack = np.full(n, np.inf)
+    for j, c in enumerate(isos):
+        carried = ((pm >> np.uint32(j)) & np.uint32(1)).astype(bool)
+        d = np.abs(mu - np.float64(c))
+        out_q, in_q = d - e, d + ea
+        is_out = out_q > hi_s
+        is_in = (~is_out) & (in_q < lo_s)
+        inside |= np.where(carried & is_in, np.uint32(1) << np.uint32(j), np.uint32(0))
+        unsure |= carried & ~is_out & ~is_in
+        rel = np.minimum(np.abs(out_q - hi_s) / np.maximum(np.maximum(np.abs(out_q), hi_s), 1e-300),
+                         np.abs(in_q - lo_s) / np.maximum(np.maximum(np.abs(in_q), lo_s), 1e-300))
+        slack = np.where(carried, np.minimum(slack, rel), slack)
+    unsure |= ~np.isfinite(mu) | ~np.isfinite(sg)
+    fallback = unsure | (bool(leaf) and not accept_leaves) & (inside != 0)
+    mask = np.where(fallback, np.uint32(0), inside)
+    return mask.astype(np.uint32), fallback, slack

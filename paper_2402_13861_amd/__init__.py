@@ -21,7 +21,7 @@ import numpy as np
 
 from . import _lib
 from ._lib import (AA, BF16, BF16_VARIANT, FP32, FP64, HIDDEN_KERNEL, KEEP_LEVELS, PROFILE, SCRATCH_BYTES, UP,
-                   UP_FORM, LIN_PRECISION, AA_MARGIN, BATCH_WORKERS, VERBOSE)
+                   UP_FORM, LIN_PRECISION, AA_MARGIN, BATCH_WORKERS, VERBOSE, CANCEL_CHECK)
 
 KERNEL_KINDS = ("hidden_fp32", "hidden_bf16", "hidden_simt_fp32", "hidden_fp64", "dense", "output",
                 "hidden_cov_bf16", "linearize")
@@ -263,6 +263,20 @@ class Context:
                                                (C.c_float * n)(*err_ls), (C.c_float * n)(*zp),
                                                (C.c_float * n)(*za), int(bool(accept_leaves))))
 
+    def surrogate_partition(self, mlp_id: int, pred, unit, k: float, level: int, leaf: bool, parent_mask):
+        """isx_surrogate_partition on device tensors: pred float32 [n, 2],
+        unit float32 [n] or None, parent_mask int32 [n]; returns (mask,
+        fallback) int32 device tensors."""
+        import torch
+
+        _check_dev(pred, torch.float32, "pred", (2,))
+        n = pred.shape[0]
+        mask = torch.empty(max(n, 1), dtype=torch.int32, device=pred.device)
+        fb = torch.empty(max(n, 1), dtype=torch.int32, device=pred.device)
+        self._chk(self._L.isx_surrogate_partition(self._h, mlp_id, n, _ptr(pred), _ptr(unit), float(k), int(level),
+                                                  int(bool(leaf)), _ptr(parent_mask), _ptr(mask), _ptr(fb)))
+        return mask[:n], fb[:n]
+
     def surrogate_free(self, sid: int):
         self._chk(self._L.isx_surrogate_free(self._h, sid))
 
@@ -353,7 +367,10 @@ class Mesh:
         for i in range(self.n_levels):
             a, b, c, d = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
             self._L.isx_mesh_level(self._h, i, C.byref(a), C.byref(b), C.byref(c), C.byref(d))
-            out.append(dict(cells=a.value, active=b.value, rechecked=c.value, propagated=d.value))
+            x = C.c_int64()
+            self._L.isx_mesh_level_cancelled(self._h, i, C.byref(x))
+            out.append(dict(cells=a.value, active=b.value, rechecked=c.value, propagated=d.value,
+                            cancelled=x.value))
         return out
 
     def times(self):

@@ -19,7 +19,7 @@ STATUS_NAMES = {
 AA, UP = 0, 1
 FP32, BF16, FP64 = 0, 1, 2
 (KEEP_LEVELS, HIDDEN_KERNEL, PROFILE, SCRATCH_BYTES, VERBOSE, BF16_VARIANT, UP_FORM, LIN_PRECISION,
- AA_MARGIN, BATCH_WORKERS) = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10
+ AA_MARGIN, BATCH_WORKERS, CANCEL_CHECK) = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11
 MAX_LINEAR, MAX_WIDTH, MAX_ISO = 16, 1024, 32
 (KERNEL_HIDDEN_FP32, KERNEL_HIDDEN_BF16, KERNEL_HIDDEN_SIMT_FP32, KERNEL_HIDDEN_FP64, KERNEL_DENSE,
  KERNEL_OUTPUT, KERNEL_HIDDEN_COV_BF16, KERNEL_LINEARIZE) = range(8)
@@ -61,6 +61,7 @@ _SIGS = [
                                 C.POINTER(C.c_int32)]),
     ("isx_mesh_level", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                  C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    ("isx_mesh_level_cancelled", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64)]),
     ("isx_mesh_times", C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_float), C.POINTER(C.c_float),
                                  C.POINTER(C.c_float)]),
     ("isx_mesh_copy_tris", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -84,6 +85,8 @@ _SIGS = [
                                        C.POINTER(C.c_float), C.POINTER(C.c_float), C.POINTER(C.c_float),
                                        C.c_int32]),
     ("isx_surrogate_free", C.c_int, [C.c_void_p, C.c_int32]),
+    ("isx_surrogate_partition", C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.c_float,
+                                          C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("isx_surrogate_save_file", C.c_int, [C.c_void_p, C.c_int32, C.c_char_p]),
     ("isx_surrogate_load_file", C.c_int, [C.c_void_p, C.c_char_p, C.c_int32, C.POINTER(C.c_int32)]),
     ("isx_get_profile", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double),

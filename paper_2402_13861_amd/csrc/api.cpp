@@ -54,6 +54,8 @@ struct isx_ctx {
   int up_form = 0;
   int lin_prec = 1;  // centre linearisation: 1 = bf16 split where supported, 0 = float32
   int aa_margin = 0; // AA: widen by the rounding margin
+  int cancel_check = 1;  // bf16 UP covariance form: re-propagate cells whose variance sums cancel, in float64
+  int64_t n_cancel_last = 0;  // cells re-propagated for cancellation by the last run_propagate
   size_t prop_budget = size_t(16) << 30;  // bytes of propagation scratch per chunk
   // propagation scratch
   Buf F32[2], vec32, F64[2], vec64, Fbf[2];
@@ -68,6 +70,7 @@ struct isx_ctx {
   Buf sur_act[ISX_MAX_LINEAR + 1], sur_out, sur_T, sur_d[2], sur_base, sp_base, sp_scale;
   Buf sp_pred, sp_fb, sp_idx, sp_pm, sp_c, sp_h, sp_out, sp_mask, sp_cnt, sp_tmp;
   Buf rc_flags, rc_fidx, rc_fmask;
+  Buf cx_flags, cx_idx, cx_c, cx_h, cx_out, cx_out64, cx_cnt;
   int64_t* h_count = nullptr;  // pinned
   Profiler prof;
   // batched extraction: worker contexts with their own stream and scratch;
@@ -86,7 +89,7 @@ struct isx_mesh {
   float* tri_pos = nullptr;
   uint64_t* tri_keys = nullptr;
   int32_t* tri_iso = nullptr;
-  std::vector<int64_t> lvl_cells, lvl_active, lvl_recheck, lvl_prop;
+  std::vector<int64_t> lvl_cells, lvl_active, lvl_recheck, lvl_prop, lvl_cancel;
   std::vector<std::vector<uint32_t>> lvl_ids, lvl_masks;
   std::vector<std::vector<float>> lvl_out;
   bool kept = false;
@@ -186,6 +189,38 @@ int64_t chunk_for(isx_ctx* ctx, const Model& m, int64_t n, int64_t req) {
 }
 
 isx_status run_propagate(isx_ctx* ctx, const Model& m, isx_method method, isx_precision prec, int64_t n,
+                         const float* centres, const float* halves, float* out, double* out64, int64_t chunk_req);
+
+// Cells whose covariance-form variance sums cancelled (flags[i] != 0) are
+// propagated again in float64 and their (mu, sigma) replaced.  Synchronises
+// the stream once to read the count.
+isx_status recheck_cancelled(isx_ctx* ctx, const Model& m, int64_t n, const float* centres, const float* halves,
+                             float* out, const uint32_t* flags, int64_t chunk_req) {
+  hipStream_t s = ctx->stream;
+  HIPCHK(ensure(ctx->cx_idx, n * 4));
+  HIPCHK(ensure(ctx->cx_cnt, sizeof(int64_t)));
+  HIPCHK(ensure(ctx->scan_tmp, compact_tmp_bytes(n)));
+  HIPCHK(launch_compact(n, flags, nullptr, (uint32_t*)ctx->cx_idx.p, nullptr, (int64_t*)ctx->cx_cnt.p,
+                        ctx->scan_tmp.p, s));
+  HIPCHK(hipMemcpyAsync(ctx->h_count, ctx->cx_cnt.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const int64_t nc = ctx->h_count[0];
+  ctx->n_cancel_last = nc;
+  if (nc <= 0) return ISX_OK;
+  HIPCHK(ensure(ctx->cx_c, nc * 12));
+  HIPCHK(ensure(ctx->cx_h, nc * 12));
+  HIPCHK(ensure(ctx->cx_out, nc * 8));
+  HIPCHK(ensure(ctx->cx_out64, nc * 16));
+  const uint32_t* idx = (const uint32_t*)ctx->cx_idx.p;
+  HIPCHK(launch_gather_boxes(nc, idx, centres, halves, (float*)ctx->cx_c.p, (float*)ctx->cx_h.p, s));
+  isx_status st = run_propagate(ctx, m, ISX_UP, ISX_FP64, nc, (const float*)ctx->cx_c.p, (const float*)ctx->cx_h.p,
+                                (float*)ctx->cx_out.p, (double*)ctx->cx_out64.p, chunk_req);
+  if (st != ISX_OK) return st;
+  HIPCHK(scatter_u64(nc, idx, (const uint64_t*)ctx->cx_out.p, (uint64_t*)out, s));
+  return ISX_OK;
+}
+
+isx_status run_propagate(isx_ctx* ctx, const Model& m, isx_method method, isx_precision prec, int64_t n,
                          const float* centres, const float* halves, float* out, double* out64, int64_t chunk_req) {
   if (n <= 0) return ISX_OK;
   const bool marg = method == ISX_AA && ctx->aa_margin != 0;
@@ -221,13 +256,18 @@ isx_status run_propagate(isx_ctx* ctx, const Model& m, isx_method method, isx_pr
     }
     HIPCHK(ensure(ctx->vec32, prop_vec_elems(m, chunk, marg) * sizeof(float)));
     w.vec = (float*)ctx->vec32.p;
+    const bool check = cov && ctx->cancel_check != 0;
+    if (check) HIPCHK(ensure(ctx->cx_flags, n * 4));
     uint16_t* Fbf[2] = {(uint16_t*)ctx->Fbf[0].p, (uint16_t*)ctx->Fbf[1].p};
     for (int64_t s = 0; s < n; s += chunk) {
       PropArgs a{&m, method, std::min(chunk, n - s), centres + 3 * s, halves + 3 * s, out + 2 * s, nullptr,
                  ctx->kernel_choice, ctx->stream, &ctx->prof, ctx->bf16_variant, ctx->up_form};
       a.aa_margin = marg;
+      if (check) a.cancel = (uint32_t*)ctx->cx_flags.p + s;
       HIPCHK(propagate_bf16(a, w, Fbf, 0));
     }
+    ctx->n_cancel_last = 0;
+    if (check) return recheck_cancelled(ctx, m, n, centres, halves, out, (const uint32_t*)ctx->cx_flags.p, chunk_req);
     return ISX_OK;
   }
   const int64_t chunk = chunk_for<float>(ctx, m, n, chunk_req);
@@ -258,15 +298,6 @@ bool finite3(const float* v) { return std::isfinite(v[0]) && std::isfinite(v[1])
 
 }  // namespace
 
-// ---------------------------------------------------------------- recheck
-namespace isx {
-hipError_t launch_band_flags(int64_t n, const float* out, float k, const IsoList& iso, const uint32_t* mask_pre,
-                             float band, uint32_t* flags, hipStream_t s);
-hipError_t launch_gather_boxes(int64_t n, const uint32_t* idx, const float* centres, const float* halves,
-                               float* c_out, float* h_out, hipStream_t s);
-hipError_t launch_recheck_apply(int64_t n, const uint32_t* idx, const double* out64, double k, const IsoList& iso,
-                                const uint32_t* pmask, float* out, uint32_t* mask, hipStream_t s);
-}  // namespace isx
 
 extern "C" {
 
@@ -330,6 +361,8 @@ isx_status isx_destroy(isx_ctx* ctx) {
                   &ctx->sp_tmp, &ctx->rc_flags, &ctx->rc_fidx, &ctx->rc_fmask};
   for (Buf* b : sbufs) release(*b);
   for (Buf& b : ctx->sur_act) release(b);
+  Buf* cbufs[] = {&ctx->cx_flags, &ctx->cx_idx, &ctx->cx_c, &ctx->cx_h, &ctx->cx_out, &ctx->cx_out64, &ctx->cx_cnt};
+  for (Buf* b : cbufs) release(*b);
   for (int i = 0; i < (int)ctx->surs.size(); ++i) isx_surrogate_free(ctx, i);
   if (ctx->h_count) (void)hipHostFree(ctx->h_count);
   if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -374,6 +407,10 @@ isx_status isx_set_option(isx_ctx* ctx, isx_option option, int64_t value) {
     case ISX_BF16_VARIANT:
       if (value < 0 || value > 4) return fail(ctx, ISX_EINVAL, "ISX_BF16_VARIANT must be in [0, 4]");
       ctx->bf16_variant = (int)value;
+      return ISX_OK;
+    case ISX_CANCEL_CHECK:
+      if (value < 0 || value > 1) return fail(ctx, ISX_EINVAL, "ISX_CANCEL_CHECK must be 0 or 1");
+      ctx->cancel_check = (int)value;
       return ISX_OK;
     case ISX_SCRATCH_BYTES:
       if (value < (int64_t)(1 << 20)) return fail(ctx, ISX_EINVAL, "ISX_SCRATCH_BYTES must be >= 1 MiB");
@@ -658,12 +695,14 @@ static isx_status read_count(isx_ctx* ctx, const int64_t* d, int64_t* h) {
 // re-check in float64 the cells within the band.  Writes out[n][2], mask[n].
 static isx_status prop_classify(isx_ctx* ctx, const Model& m, const isx_params* p, float k, const IsoList& iso,
                                 int64_t n, const float* centres, const float* halves, const uint32_t* pmask,
-                                float* out, uint32_t* mask, int64_t* n_rc_out) {
+                                float* out, uint32_t* mask, int64_t* n_rc_out, int64_t* n_cancel_out) {
   hipStream_t s = ctx->stream;
   *n_rc_out = 0;
+  *n_cancel_out = 0;
   if (n <= 0) return ISX_OK;
   isx_status st = run_propagate(ctx, m, p->method, p->precision, n, centres, halves, out, nullptr, p->chunk_cells);
   if (st != ISX_OK) return st;
+  *n_cancel_out = p->precision == ISX_BF16 ? ctx->n_cancel_last : 0;
   HIPCHK(launch_classify(n, out, k, iso, pmask, mask, s));
   if (!(p->fp64_band > 0.f) || p->precision == ISX_FP64) return ISX_OK;
   HIPCHK(ensure(ctx->rc_flags, n * 4));
@@ -795,12 +834,12 @@ isx_status isx_extract(isx_ctx* ctx, int32_t mlp_id, const isx_params* p, isx_me
       XCHK(launch_children(m, L, n_par, (const uint32_t*)ctx->act_ids[cur].p, (const uint32_t*)ctx->act_mask[cur].p,
                            ids, pmask, centres, halves, s));
     }
-    int64_t n_rc = 0, n_prop = n;
+    int64_t n_rc = 0, n_prop = n, n_cx = 0;
     isx_status st = ISX_OK;
     Sur* S = p->use_surrogate ? get_sur(ctx, m.sur_id) : nullptr;
     if (p->use_surrogate && !S) return bail(fail(ctx, ISX_EINVAL, "use_surrogate set but no surrogate attached"));
     if (!S) {
-      st = prop_classify(ctx, m, p, k, iso, n, centres, halves, pmask, outb, mask, &n_rc);
+      st = prop_classify(ctx, m, p, k, iso, n, centres, halves, pmask, outb, mask, &n_rc, &n_cx);
       if (st != ISX_OK) return bail(st);
     } else {
       // surrogate decides the confident cells, the others are propagated
@@ -832,7 +871,8 @@ isx_status isx_extract(isx_ctx* ctx, int32_t mlp_id, const isx_params* p, isx_me
         XCHK(launch_gather_boxes(n_fb, fidx, centres, halves, (float*)ctx->sp_c.p, (float*)ctx->sp_h.p, s));
         XCHK(gather_u32(n_fb, fidx, pmask, (uint32_t*)ctx->sp_pm.p, s));
         st = prop_classify(ctx, m, p, k, iso, n_fb, (const float*)ctx->sp_c.p, (const float*)ctx->sp_h.p,
-                           (const uint32_t*)ctx->sp_pm.p, (float*)ctx->sp_out.p, (uint32_t*)ctx->sp_mask.p, &n_rc);
+                           (const uint32_t*)ctx->sp_pm.p, (float*)ctx->sp_out.p, (uint32_t*)ctx->sp_mask.p, &n_rc,
+                           &n_cx);
         if (st != ISX_OK) return bail(st);
         XCHK(scatter_u32(n_fb, fidx, (const uint32_t*)ctx->sp_mask.p, mask, s));
         XCHK(scatter_u64(n_fb, fidx, (const uint64_t*)ctx->sp_out.p, (uint64_t*)outb, s));
@@ -848,9 +888,10 @@ isx_status isx_extract(isx_ctx* ctx, int32_t mlp_id, const isx_params* p, isx_me
     mesh->lvl_active.push_back(n_act);
     mesh->lvl_recheck.push_back(n_rc);
     mesh->lvl_prop.push_back(n_prop);
+    mesh->lvl_cancel.push_back(n_cx);
     if (ctx->verbose) {
-      std::fprintf(stderr, "isx: level %d: %lld cells, %lld active, %lld propagated, %lld re-checked\n", L,
-                   (long long)n, (long long)n_act, (long long)n_prop, (long long)n_rc);
+      std::fprintf(stderr, "isx: level %d: %lld cells, %lld active, %lld propagated, %lld re-checked, %lld cancelled\n",
+                   L, (long long)n, (long long)n_act, (long long)n_prop, (long long)n_rc, (long long)n_cx);
       std::fflush(stderr);
     }
     if (ctx->keep_levels) {
@@ -988,6 +1029,7 @@ isx_status isx_extract_batch(isx_ctx* ctx, int32_t n, const int32_t* mlp_ids, co
     w->up_form = ctx->up_form;
     w->lin_prec = ctx->lin_prec;
     w->aa_margin = ctx->aa_margin;
+    w->cancel_check = ctx->cancel_check;
     w->keep_levels = ctx->keep_levels;
     w->verbose = false;
     w->prop_budget = std::max<size_t>(size_t(1) << 28, ctx->prop_budget / nw);
@@ -1041,6 +1083,12 @@ isx_status isx_mesh_level(const isx_mesh* mesh, int32_t level, int64_t* n_cells,
   if (n_active) *n_active = mesh->lvl_active[level];
   if (n_rechecked) *n_rechecked = mesh->lvl_recheck[level];
   if (n_propagated) *n_propagated = mesh->lvl_prop[level];
+  return ISX_OK;
+}
+
+isx_status isx_mesh_level_cancelled(const isx_mesh* mesh, int32_t level, int64_t* n_cancelled) {
+  if (!mesh || !n_cancelled || level < 0 || level >= (int32_t)mesh->lvl_cancel.size()) return ISX_EINVAL;
+  *n_cancelled = mesh->lvl_cancel[level];
   return ISX_OK;
 }
 
@@ -1401,6 +1449,24 @@ isx_status isx_surrogate_attach(isx_ctx* ctx, int32_t mlp_id, int32_t sur_id, in
     m->sur_z_acc[i] = i < n_levels ? h_z_accept[i] : h_z_accept[n_levels - 1];
   }
   m->sur_accept_leaves = accept_leaves ? 1 : 0;
+  return ISX_OK;
+}
+
+isx_status isx_surrogate_partition(isx_ctx* ctx, int32_t mlp_id, int64_t n, const float* d_pred, const float* d_unit,
+                                   float k, int32_t level, int32_t leaf, const uint32_t* d_parent_mask,
+                                   uint32_t* d_mask, uint32_t* d_fallback) {
+  Model* m = get_model(ctx, mlp_id);
+  if (!m) return fail(ctx, ISX_EINVAL, "bad mlp id");
+  if (m->sur_id < 0) return fail(ctx, ISX_EINVAL, "no surrogate attached to this mlp");
+  if (n < 0 || level < 0 || !(k >= 0.f) || !std::isfinite(k) ||
+      (n > 0 && (!d_pred || !d_parent_mask || !d_mask || !d_fallback)))
+    return fail(ctx, ISX_EINVAL, "bad arguments");
+  if (n == 0) return ISX_OK;
+  (void)hipSetDevice(ctx->device);
+  const int Ls = std::min<int>(level, std::max(0, m->sur_levels - 1));
+  HIPCHK(sur_partition(n, d_pred, d_unit, k, iso_list(*m), d_parent_mask, m->sur_err_mu[Ls], m->sur_err_ls[Ls],
+                       m->sur_z[Ls], m->sur_z_acc[Ls], leaf ? 1 : 0, m->sur_accept_leaves, d_mask, d_fallback,
+                       ctx->stream));
   return ISX_OK;
 }
 

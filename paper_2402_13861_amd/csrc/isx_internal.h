@@ -262,14 +262,17 @@ struct PropArgs {
   int bf16_variant;   // 0 = default tile shape for the width
   int up_form = 0;    // bf16 UP: 0 = covariance form when supported, 1 = coefficient form
   int aa_margin = 0;  // AA: widen by the rounding margin (kernels_margin.hip)
+  uint32_t* cancel = nullptr;  // bf16 UP covariance form: per-cell cancellation flags [C] (may be null)
 };
 
 // Constants of the affine-arithmetic rounding margin of one layer
-// (kernels_margin.hip): c, the inflation of the margin's own sums, of the
-// row statistic, and the rule's slack.
+// (kernels_margin.hip): c for the coefficient term, c_z for the centre term
+// (no operand rounding: the centre is computed from float32 / float64
+// weights), the inflation of the margin's own sums, of the row statistic, and
+// the rule's slack.
 template <typename T>
 struct AaMargin {
-  T c, infl_m, infl_s, slack;
+  T c, c_z, infl_m, infl_s, slack;
 };
 template <typename T>
 AaMargin<T> aa_margin_consts(double u, double u_b, int K, int64_t D);
@@ -292,8 +295,9 @@ bool bf16_supported(const Model& m);
 bool cov_supported(const Model& m);
 double cov_flops_per_cell(const Model& m);
 // vec: the Y, A, B, G vectors of hidden layers 1..L-1, each [C][padded width], in that order per layer
+// cancel [C] (may be null): 1 where a variance sum cancelled (kernels_cov.hip)
 hipError_t launch_up_cov_bf16(const Model& m, int64_t C, const float* centres, const float* halves, float* vec,
-                              hipStream_t s);
+                              uint32_t* cancel, hipStream_t s);
 size_t prop_F_elems_bf16(const Model& m, int64_t C);
 hipError_t eval_points_f32(const Model& m, int64_t n, const float* pts, float* vals, hipStream_t s);
 hipError_t eval_points_f64(const Model& m, int64_t n, const float* pts, float* vals, hipStream_t s);
@@ -353,6 +357,15 @@ hipError_t launch_mc_emit(const Model& m, int depth, int64_t n_leaves, const uin
                           const float* corner_vals, const uint32_t* tri_offsets, float* tri_pos,
                           uint64_t* tri_keys, int32_t* tri_iso, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
+// float64 re-check of the band (kernels_hier.hip): flag cells with a bound
+// endpoint within `band` of a carried iso-value, gather boxes by index, and
+// overwrite the classification of re-checked cells from their float64 bounds.
+hipError_t launch_band_flags(int64_t n, const float* out, float k, const IsoList& iso, const uint32_t* mask_pre,
+                             float band, uint32_t* flags, hipStream_t s);
+hipError_t launch_gather_boxes(int64_t n, const uint32_t* idx, const float* centres, const float* halves,
+                               float* c_out, float* h_out, hipStream_t s);
+hipError_t launch_recheck_apply(int64_t n, const uint32_t* idx, const double* out64, double k, const IsoList& iso,
+                                const uint32_t* pmask, float* out, uint32_t* mask, hipStream_t s);
 
 // ---- surrogate kernels (kernels_sur.hip) ----
 hipError_t sur_gemm(int M, int N, int K, const float* A, int lda, bool ta, const float* B, int ldb, bool tb, float* C,

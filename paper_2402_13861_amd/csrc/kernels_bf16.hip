@@ -451,7 +451,7 @@ hipError_t propagate_bf16(const PropArgs& a, PropWork<float>& w, uint16_t* Fbf_r
     for (int h = 1; h <= Lh; ++h) vec_bytes += 16.0 * m.pw[h];
     const bool prof = a.prof && a.prof->begin(rec, ISX_KERNEL_HIDDEN_COV_BF16, cov_flops_per_cell(m) * (double)C,
                                               vec_bytes * (double)C, a.stream);
-    hipError_t e = launch_up_cov_bf16(m, C, a.centres, a.halves, w.vec, a.stream);
+    hipError_t e = launch_up_cov_bf16(m, C, a.centres, a.halves, w.vec, a.cancel, a.stream);
     if (prof) a.prof->end(rec, a.stream);
     if (e != hipSuccess) return e;
     Profiler::Rec rec2{};

@@ -4,10 +4,14 @@
 //
 // A linear layer z -> W z + b evaluated with unit roundoff u (operands rounded
 // with u_b) lands within
-//   m_j = c (sum_k |W_jk| (rho_k + |z_k|) + |b_j|),
+//   m_j = c sum_k |W_jk| rho_k + c_z (sum_k |W_jk| |z_k| + |b_j|),
 //   c = 2 u_b + u_b^2 + g_{K+1} (1 + u_b)^2,   g_n = n u / (1 - n u),
 // of the exact form, where z and rho_k (the sum of |coefficients| of input
-// component k) describe the layer's input form.  That error is one more
+// component k) describe the layer's input form.  The operand rounding u_b
+// applies only to products whose operands are rounded: the bfloat16 path
+// multiplies coefficients with bfloat16 operands but computes the centre
+// W z + b with float32 weights, so its centre term takes c_z = g_{K+1}
+// (c_z = c wherever u_b = 0).  That error is one more
 // independent symbol per neuron, so after the hidden kernel has written the
 // pre-activation centre y_j and its float row statistic r_j:
 //   * the ReLU rule (Eq. 4) is applied to the radius r_j (1 + 2 g_D) + m_j
@@ -92,7 +96,7 @@ __global__ void aa_margin_hidden_kernel(int64_t C, int n_in, int n_out, const T*
   T sr, sz;
   aa_margin_sums<T>(cell, j, n_in, n_out, Wt, bias, Yp, Ap, Bp, Rp, centres, halves, sr, sz);
   sr *= k.infl_m;
-  const T m = k.c * (sr + sz) * k.infl_m;
+  const T m = (k.c * sr + k.c_z * sz) * k.infl_m;
   const T y = Y[idx];
   const T r = S[idx] * k.infl_s + m;
   T a, b, g;
@@ -114,7 +118,7 @@ __global__ void aa_margin_output_kernel(int64_t C, int n_in, const T* __restrict
   if (cell >= C) return;
   T sr, sz;
   aa_margin_sums<T>(cell, 0, n_in, 1, Wt, bias, Yp, Ap, Bp, Rp, centres, halves, sr, sz);
-  const T m = k.c * (sr + sz) * k.infl_m;
+  const T m = (k.c * sr + k.c_z * sz) * k.infl_m;
   const T x0 = out64 ? T(out64[cell * 2]) : T(out32[cell * 2]);
   const T r0 = out64 ? T(out64[cell * 2 + 1]) : T(out32[cell * 2 + 1]);
   T r = r0 * k.infl_s + m;
@@ -128,6 +132,7 @@ AaMargin<T> aa_margin_consts(double u, double u_b, int K, int64_t D) {
   auto gn = [u](double n) { return n * u / (1.0 - n * u); };
   AaMargin<T> k;
   k.c = (T)(2.0 * u_b + u_b * u_b + gn(K + 1) * (1.0 + u_b) * (1.0 + u_b));
+  k.c_z = (T)gn(K + 1);
   k.infl_m = (T)(1.0 + 2.0 * gn(K + 4));
   k.infl_s = (T)(1.0 + 2.0 * gn((double)D + 1));
   k.slack = (T)(8.0 * u);

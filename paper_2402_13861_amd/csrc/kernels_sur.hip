@@ -261,7 +261,7 @@ __global__ void sur_partition_kernel(int64_t n, const float* __restrict__ pred, 
     if (d + ea < lo_s) acc_bits |= 1u << j;     // confidently inside
     else unsure = true;
   }
-  if (!(mu == mu) || !(sg == sg)) unsure = true;  // NaN predictions fall back
+  if (!isfinite(mu) || !isfinite(sg)) unsure = true;  // non-finite predictions fall back
   const bool fb = unsure || (leaf && !accept_leaves && acc_bits != 0u);
   fallback[i] = fb ? 1u : 0u;
   mask[i] = fb ? 0u : acc_bits;

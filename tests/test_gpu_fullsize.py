@@ -63,7 +63,7 @@ def test_sampled_cells_match_oracle(run):
         cid = ids[pick].astype(np.uint64)
         c, h = cell_boxes(L, cid)
         mu, sg = propagate(mlp, c, h, UP)
-        # bounds: the bf16 parity tolerance (5e-2 of max(|o|, S))
+        # bounds: within 4e-3 of max(|o|, S) (about twice the largest BF16 error measured here)
         g = out[pick].astype(np.float64)
         for sgn in (-1.0, 1.0):
             o = mu + sgn * k * sg
@@ -81,7 +81,7 @@ def test_sampled_cells_match_oracle(run):
               f"({int(diff.sum())} unexcused)", flush=True)
         assert not diff.any(), (L, cid[diff][:5])
     print(f"max bound error over samples {worst:.3e}", flush=True)
-    assert worst <= 5e-2
+    assert worst <= 4e-3
 
 
 def test_sampled_leaf_triangles_match_oracle(run):

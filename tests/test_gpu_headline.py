@@ -28,10 +28,12 @@ pytestmark = pytest.mark.gpu
 METHODS = {"up": (UP, 1), "aa": (AA, 0)}
 INR = "relu256x5_fourier"
 
-# Largest BF16 endpoint error against the oracle, in units of S, over levels
-# 0..9 of the 3->256x5->1 INR (about twice the largest value measured on the
-# device, rounded up): UP covariance form, UP coefficient form, AA.
-BF16_ENDPOINT_TOL = {"up-cov": 2e-2, "up-coef": 2e-2, "aa": 2e-2}
+# Largest BF16 endpoint error against the oracle over levels 0..9 of the
+# 3->256x5->1 INR, about twice the largest value measured on the device:
+# UP in units of S (covariance form 4.2e-3, coefficient form 1.14e-2, both at
+# levels 0-2); AA relative to max(|endpoint|, S), since its ranges at the top
+# levels are hundreds of S wide.
+BF16_ENDPOINT_TOL = {"up-cov": 8e-3, "up-coef": 2.5e-2, "aa": 1e-2}
 BAND_REL = 1e-3  # the float64 re-check band of the benchmark, in units of S
 
 
@@ -94,16 +96,22 @@ def test_propagate_256x5_fp32_and_fp64_match_oracle(ctx, net, mname):
         ctx.unload_mlp(mid)
 
 
-def _endpoint_err(g, oc, os_, k, S):
+def _endpoint_err(g, oc, os_, k, S, relative=False):
+    """Largest endpoint error per cell, in units of S, or relative to
+    max(|endpoint|, S)."""
     g = np.asarray(g, np.float64)
-    lo = np.abs((g[:, 0] - k * g[:, 1]) - (oc - k * os_))
-    hi = np.abs((g[:, 0] + k * g[:, 1]) - (oc + k * os_))
+    lo_o, hi_o = oc - k * os_, oc + k * os_
+    lo = np.abs((g[:, 0] - k * g[:, 1]) - lo_o)
+    hi = np.abs((g[:, 0] + k * g[:, 1]) - hi_o)
+    if relative:
+        return np.maximum(lo / np.maximum(np.abs(lo_o), S), hi / np.maximum(np.abs(hi_o), S))
     return np.maximum(lo, hi) / S
 
 
 def test_bf16_error_per_level_on_the_benchmark_inr(ctx):
     """BF16 bound error against the oracle on 80 cells per octree level
-    0..9 (800 cells), per level max and 99.9th percentile in units of S.
+    0..9 (800 cells), per level max and 99.9th percentile in units of S
+    (AA: relative to max(|endpoint|, S)).
     Both UP forms and AA stay within BF16_ENDPOINT_TOL; for UP (the
     benchmark's method) the band 1e-3 S exceeds the largest error at every
     level from 6 on, so that a cell classified differently in BF16 and in
@@ -128,7 +136,7 @@ def test_bf16_error_per_level_on_the_benchmark_inr(ctx):
         results = {
             "up-cov": _endpoint_err(_gpu_prop(ctx, mid, isx.UP, isx.BF16, c, h, form=0)[0], mu, sg, 3.0, S),
             "up-coef": _endpoint_err(_gpu_prop(ctx, mid, isx.UP, isx.BF16, c, h, form=1)[0], mu, sg, 3.0, S),
-            "aa": _endpoint_err(_gpu_prop(ctx, mid, isx.AA, isx.BF16, c, h)[0], x0, r, 1.0, S),
+            "aa": _endpoint_err(_gpu_prop(ctx, mid, isx.AA, isx.BF16, c, h)[0], x0, r, 1.0, S, relative=True),
             "up-fp32": _endpoint_err(_gpu_prop(ctx, mid, isx.UP, isx.FP32, c, h)[0], mu, sg, 3.0, S),
         }
     finally:
@@ -136,7 +144,8 @@ def test_bf16_error_per_level_on_the_benchmark_inr(ctx):
     for name, e in results.items():
         per = [(L, float(e[rng_levels == L].max()), float(np.quantile(e[rng_levels == L], 0.999)))
                for L in range(10)]
-        print(f"bf16 error vs oracle [{name}] (units of S): max {e.max():.3e} p99.9 {np.quantile(e, 0.999):.3e}; "
+        unit = "relative" if name == "aa" else "units of S"
+        print(f"bf16 error vs oracle [{name}] ({unit}): max {e.max():.3e} p99.9 {np.quantile(e, 0.999):.3e}; "
               + ", ".join(f"L{L} {m:.2e}/{q:.2e}" for L, m, q in per), flush=True)
     for name, tol in BF16_ENDPOINT_TOL.items():
         assert results[name].max() <= tol, (name, float(results[name].max()))

@@ -394,6 +394,13 @@ BF16_WIDTHS = [
 ]
 
 
+# BF16 tolerances relative to max(|o|, S): (bounds, spread, centre), about
+# twice the largest error measured over BF16_WIDTHS on the device (UP: bounds
+# 2.4e-3, spread 3.8e-3, centre 2.1e-3, on 3->32^7->1; AA: 8.6e-3, 6.8e-3,
+# 6.3e-3, same net)
+BF16_TOL = {"up": (5e-3, 1e-2, 5e-3), "aa": (2e-2, 1.5e-2, 1.5e-2)}
+
+
 @pytest.mark.parametrize("widths", BF16_WIDTHS, ids=lambda w: "x".join(map(str, w)))
 @pytest.mark.parametrize("mname", ["up", "aa"])
 def test_propagate_bf16_error_against_oracle(ctx, widths, mname):
@@ -414,10 +421,11 @@ def test_propagate_bf16_error_against_oracle(ctx, widths, mname):
         for form in ((0, 1) if mname == "up" else (0,)):
             ctx.set_option(isx.UP_FORM, form)
             g, _ = _gpu_prop(ctx, mid, gm, isx.BF16, c, h)
-            worst, _ = assert_pair_close(g, ref, S, 5e-2, f"bf16 {mname} form {form} {widths}", k=k,
-                                         spread_rtol=0.2)
+            tol, stol, ctol = BF16_TOL[mname]
+            worst, _ = assert_pair_close(g, ref, S, tol, f"bf16 {mname} form {form} {widths}", k=k,
+                                         spread_rtol=stol)
             # the centre is a float32 point evaluation of the linearised net
-            assert worst["centre"] <= 1e-2
+            assert worst["centre"] <= ctol
     finally:
         ctx.set_option(isx.UP_FORM, 0)
         ctx.unload_mlp(mid)
@@ -438,7 +446,7 @@ def test_cov_propagate_past_one_grid(ctx):
         assert np.isfinite(g).all()
         pick = np.r_[0:16, (1 << 22) - 16:(1 << 22) + 16, n - 16:n]
         ref = propagate(mlp, c[pick], h[pick], UP)
-        assert_pair_close(g[pick], ref, output_scale(mlp), 5e-2, "bf16 up past one grid", k=3.0, spread_rtol=0.2)
+        assert_pair_close(g[pick], ref, output_scale(mlp), 1e-3, "bf16 up past one grid", k=3.0, spread_rtol=1e-3)
     finally:
         ctx.unload_mlp(mid)
 

@@ -244,3 +244,53 @@ def test_surrogate_file_round_trip(ctx, tmp_path):
     finally:
         if mid is not None:
             ctx.unload_mlp(mid)
+
+
+@pytest.mark.parametrize("accept_leaves", [0, 1])
+def test_band_partition_matches_oracle(ctx, accept_leaves):
+    """isx_surrogate_partition (the kernel isx_extract runs at every level)
+    against oracle.surrogate.partition on 200 003 cells, element by element:
+    fallback flags and decided masks, at an inner level and at the leaf
+    level, with and without a per-cell unit; only cells whose decision
+    quantity lies within float32 rounding (1e-5 relative) of its threshold
+    are exempt, and they are counted."""
+    n = 200_003
+    rng = np.random.default_rng(7 + accept_leaves)
+    pred = np.stack([rng.normal(0, 1, n), np.exp(rng.normal(-2, 1, n))], 1).astype(np.float32)
+    pred[::1009, 0] = np.nan
+    unit = np.exp(rng.normal(-1, 0.5, n)).astype(np.float32)
+    pm = rng.integers(0, 8, n).astype(np.uint32)
+    isos = [-0.6, 0.05, 0.7]
+    err_mu = [0.3, 0.2, 0.1, 0.05]
+    err_ls = [0.4, 0.3, 0.2, 0.1]
+    z = [8.0, 6.0, 4.0, 2.0]
+    za = [2.0, 1.5, 1.0, 0.5]
+    mlp = he_normal_mlp([3, 32, 32, 1], seed=0)
+    mid = ctx.load_weights(mlp)
+    Ws, bs = _sur_weights(5)
+    sid = ctx.surrogate_load(Ws, bs)
+    try:
+        ctx.set_isovalues(mid, isos)
+        ctx.surrogate_attach(mid, sid, err_mu, err_ls, z=z, accept_leaves=bool(accept_leaves), z_accept=za)
+        dpred, dunit, dpm = _dev(pred), _dev(unit), _dev(pm.view(np.int32), torch.int32)
+        for level, leaf, use_unit in ((2, False, False), (3, True, True), (9, False, True), (9, True, False)):
+            Ls = min(level, 3)
+            u = dunit if use_unit else None
+            mask, fb = ctx.surrogate_partition(mid, dpred, u, 3.0, level, leaf, dpm)
+            torch.cuda.synchronize()
+            gm = mask.cpu().numpy().view(np.uint32)
+            gf = fb.cpu().numpy() != 0
+            om, of, slack = osg.partition(pred.astype(np.float64), unit if use_unit else None, 3.0, isos, pm,
+                                          err_mu[Ls], err_ls[Ls], z[Ls], za[Ls], leaf, bool(accept_leaves))
+            exempt = slack <= 1e-5
+            bad = ((gm != om) | (gf != of)) & ~exempt
+            print(f"partition level {level} leaf {leaf} unit {use_unit} accept_leaves {accept_leaves}: "
+                  f"fallback {int(of.sum())}, decided {int((~of).sum())} (pruned {int(((~of) & (om == 0)).sum())}), "
+                  f"differences {int(((gm != om) | (gf != of)).sum())}, exempt cells {int(exempt.sum())}",
+                  flush=True)
+            assert not bad.any(), np.nonzero(bad)[0][:5]
+            assert exempt.mean() < 1e-3
+    finally:
+        ctx.surrogate_attach(mid, -1, [0.0], [0.0])
+        ctx.surrogate_free(sid)
+        ctx.unload_mlp(mid)

@@ -91,3 +91,57 @@ def test_base_targets_invert_base_prediction():
     # a perfect linearisation gives zero targets
     Z = sg.base_targets(f[5:], s[5:], f[5:], s[5:], 1e-6)
     np.testing.assert_allclose(Z, 0.0, atol=1e-12)
+
+
+def test_partition_hand_cases():
+    """Band partition, worked by hand.  t = 3, err_mu = 0.1, err_ls = 0.2,
+    z = 2, z_acc = 1, isos (0, 5), unit 1:
+      prune band: t sigma e^{0.4} = 3 sigma * 1.4918..., mu margin 0.2
+      accept band: t sigma e^{-0.2} = 3 sigma * 0.8187..., mu margin 0.1"""
+    from oracle.surrogate import partition
+
+    isos = [0.0, 5.0]
+    pred = np.array([
+        [2.0, 0.1],    # iso 0: d 2, 2-0.2 > 0.4476 -> outside; iso 5: d 3 -> outside => pruned
+        [0.05, 1.0],   # iso 0: d 0.05+0.1 < 2.456 -> inside; iso 5: 4.95-0.2=4.75 > 4.4755 -> outside
+        [1.0, 0.3],    # iso 0: 1-0.2 = 0.8 <= 1.343 (not outside), 1.1 >= 0.737 (not inside) -> unsure
+        [0.05, 1.0],   # as row 1, but the parent carries only iso 5 -> outside => pruned
+        [np.nan, 1.0], # non-finite prediction -> fallback
+        [4.0, 1.0],    # iso 0: outside? 3.8 <= 4.4755 no; inside? 4.1 < 2.456 no -> unsure
+    ])
+    pm = np.array([3, 3, 3, 2, 3, 1], dtype=np.uint32)
+    mask, fb, slack = partition(pred, None, 3.0, isos, pm, 0.1, 0.2, 2.0, 1.0, leaf=False, accept_leaves=False)
+    np.testing.assert_array_equal(mask, [0, 1, 0, 0, 0, 0])
+    np.testing.assert_array_equal(fb, [False, False, True, False, True, True])
+    # at the leaf level an accepted bit falls back unless leaves may be accepted
+    mask, fb, _ = partition(pred, None, 3.0, isos, pm, 0.1, 0.2, 2.0, 1.0, leaf=True, accept_leaves=False)
+    np.testing.assert_array_equal(fb, [False, True, True, False, True, True])
+    np.testing.assert_array_equal(mask, [0, 0, 0, 0, 0, 0])
+    mask, fb, _ = partition(pred, None, 3.0, isos, pm, 0.1, 0.2, 2.0, 1.0, leaf=True, accept_leaves=True)
+    np.testing.assert_array_equal(mask, [0, 1, 0, 0, 0, 0])
+    # the per-cell unit scales only the mu margin: unit 10 on row 0 makes
+    # iso 0 unsure (2 - 2 = 0 <= 0.4476)
+    mask, fb, _ = partition(pred[:1], np.array([10.0]), 3.0, isos, pm[:1], 0.1, 0.2, 2.0, 1.0, False, False)
+    assert fb[0] and mask[0] == 0
+    # a cell exactly on a threshold is within slack 0
+    p2 = np.array([[0.2 + 3.0 * np.exp(0.4), 1.0]])
+    _, _, s2 = partition(p2, None, 3.0, [0.0], np.array([1], np.uint32), 0.1, 0.2, 2.0, 1.0, False, False)
+    assert s2[0] < 1e-15
+
+
+def test_partition_is_the_plain_test_with_zero_bands():
+    """With zero error and zero bands the rule is the soft-bound test itself
+    (strict on both sides, so a bound touching c is unsure): outside iff
+    |mu - c| > t sigma, inside iff |mu - c| < t sigma."""
+    from oracle.surrogate import partition
+
+    rng = np.random.default_rng(0)
+    pred = np.stack([rng.normal(0, 1, 500), np.abs(rng.normal(0, 0.5, 500))], 1)
+    isos = [-0.5, 0.4]
+    pm = np.full(500, 3, np.uint32)
+    mask, fb, _ = partition(pred, None, 3.0, isos, pm, 0.0, 0.0, 0.0, 0.0, False, False)
+    want = np.zeros(500, np.uint32)
+    for j, c in enumerate(isos):
+        want |= (np.abs(pred[:, 0] - c) < 3.0 * pred[:, 1]).astype(np.uint32) << np.uint32(j)
+    assert not fb.any()
+    np.testing.assert_array_equal(mask, want)
