@@ -131,6 +131,24 @@ isx_status isx_classify_compact(isx_ctx* ctx, int32_t mlp_id, float k, int64_t n
                                 const uint32_t* d_parent_mask, uint32_t* d_active_idx,
                                 uint32_t* d_active_mask, int64_t* d_n_active);
 
+/* isx_classify_compact_noalloc: isx_classify_compact for callers that cannot
+ * allocate device memory -- code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation.  Same arguments, results and
+ * asynchrony as isx_classify_compact; it calls no allocating routine.  Its
+ * working memory (a uint32 mask per cell and the scan's block partials) is a
+ * fixed array of the library, one copy per device, sized for
+ * ISX_NOALLOC_MAX_CELLS cells (16 MiB + 16 KiB) and held until the process
+ * ends.  n_cells above ISX_NOALLOC_MAX_CELLS fails with ISX_ECAPACITY (split
+ * the batch).  Every call on a device uses that device's one array and leaves
+ * its contents behind; nothing in it needs to start at zero, but calls that
+ * overlap on one device (several streams or host threads) race and must be
+ * serialised by the caller.
+ * Errors: ISX_EINVAL, ISX_ECAPACITY, ISX_EHIP. */
+#define ISX_NOALLOC_MAX_CELLS (1 << 22)
+isx_status isx_classify_compact_noalloc(isx_ctx* ctx, int32_t mlp_id, float k, int64_t n_cells,
+                                        const float* d_out, const uint32_t* d_parent_mask,
+                                        uint32_t* d_active_idx, uint32_t* d_active_mask, int64_t* d_n_active);
+
 /* Plain MLP evaluation f(x) at n points (Sec. III-B; the reconstruction step
  * of Sec. IV-D).  d_points [n][3], d_values [n], float32 device arrays;
  * ISX_FP64 computes in float64 and rounds the result.  Asynchronous. */

@@ -180,6 +180,13 @@ class Context:
                                                _ptr(idx), _ptr(msk), _ptr(cnt)))
         return idx, msk, cnt
 
+    def classify_compact_noalloc(self, mlp_id: int, k: float, out, parent_mask, idx, msk, cnt):
+        """isx_classify_compact_noalloc into caller-allocated device tensors
+        idx, msk (int32 [>= n]) and cnt (int64 [1]); allocates nothing."""
+        n = out.shape[0]
+        self._chk(self._L.isx_classify_compact_noalloc(self._h, mlp_id, float(k), n, _ptr(out), _ptr(parent_mask),
+                                                       _ptr(idx), _ptr(msk), _ptr(cnt)))
+
     # -- learned surrogate
     def surrogate_load(self, Ws, bs) -> int:
         Ws = [np.ascontiguousarray(W, dtype=np.float32) for W in Ws]

@@ -21,6 +21,7 @@ FP32, BF16, FP64 = 0, 1, 2
 (KEEP_LEVELS, HIDDEN_KERNEL, PROFILE, SCRATCH_BYTES, VERBOSE, BF16_VARIANT, UP_FORM, LIN_PRECISION,
  AA_MARGIN, BATCH_WORKERS, CANCEL_CHECK) = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11
 MAX_LINEAR, MAX_WIDTH, MAX_ISO = 16, 1024, 32
+NOALLOC_MAX_CELLS = 1 << 22
 (KERNEL_HIDDEN_FP32, KERNEL_HIDDEN_BF16, KERNEL_HIDDEN_SIMT_FP32, KERNEL_HIDDEN_FP64, KERNEL_DENSE,
  KERNEL_OUTPUT, KERNEL_HIDDEN_COV_BF16, KERNEL_LINEARIZE) = range(8)
 
@@ -52,6 +53,8 @@ _SIGS = [
                                 C.c_void_p, C.c_void_p]),
     ("isx_classify_compact", C.c_int, [C.c_void_p, C.c_int32, C.c_float, C.c_int64, C.c_void_p, C.c_void_p,
                                        C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("isx_classify_compact_noalloc", C.c_int, [C.c_void_p, C.c_int32, C.c_float, C.c_int64, C.c_void_p,
+                                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("isx_eval_points", C.c_int, [C.c_void_p, C.c_int32, C.c_int, C.c_int64, C.c_void_p, C.c_void_p]),
     ("isx_linearize", C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("isx_extract", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Params), C.POINTER(C.c_void_p)]),

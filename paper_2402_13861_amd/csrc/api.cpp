@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <atomic>
+#include <mutex>
 #include <thread>
 #include <string>
 #include <vector>
@@ -24,6 +25,40 @@ struct Buf {
 };
 
 std::string g_create_error;
+
+// ---- fixed working memory of the allocation-free classify/compact entry
+// point: per-cell masks, then the scan's block partials (one uint64 per
+// 2048 cells, plus one).  Each device holds its own copy of this array; host
+// code never uses its name as an address, only the per-device pointer that
+// hipGetSymbolAddress returns at context creation.
+constexpr size_t kNoAllocMaskBytes = size_t(ISX_NOALLOC_MAX_CELLS) * sizeof(uint32_t);
+constexpr size_t kNoAllocBytes = kNoAllocMaskBytes + (size_t(ISX_NOALLOC_MAX_CELLS) / 2048 + 2) * sizeof(uint64_t);
+static __device__ __align__(256) uint8_t scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+
+// Looks up the device address of `scratch` on the current device `dev` once.
+hipError_t init_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_done[dev]) {
+    void* ptr = nullptr;
+    g_scratch_err[dev] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    g_scratch_ptr[dev] = g_scratch_err[dev] == hipSuccess ? ptr : nullptr;
+    g_scratch_done[dev] = true;
+  }
+  return g_scratch_err[dev];
+}
+
+void* scratch_ptr(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  return g_scratch_ptr[dev];
+}
 
 }  // namespace
 
@@ -318,6 +353,11 @@ isx_status isx_create(int device, void* hip_stream, isx_ctx** out) {
   e = upload_mc_table();
   if (e != hipSuccess) {
     g_create_error = std::string("upload_mc_table: ") + hipGetErrorString(e);
+    return ISX_EHIP;
+  }
+  e = init_scratch(device);
+  if (e != hipSuccess) {
+    g_create_error = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
     return ISX_EHIP;
   }
   isx_ctx* c = new isx_ctx();
@@ -625,6 +665,29 @@ isx_status isx_classify_compact(isx_ctx* ctx, int32_t mlp_id, float k, int64_t n
   HIPCHK(launch_classify(n_cells, d_out, k, iso_list(*m), d_parent_mask, (uint32_t*)ctx->cls_mask.p, ctx->stream));
   HIPCHK(launch_compact(n_cells, (const uint32_t*)ctx->cls_mask.p, nullptr, d_active_idx, d_active_mask, d_n_active,
                         ctx->scan_tmp.p, ctx->stream));
+  return ISX_OK;
+}
+
+isx_status isx_classify_compact_noalloc(isx_ctx* ctx, int32_t mlp_id, float k, int64_t n_cells, const float* d_out,
+                                        const uint32_t* d_parent_mask, uint32_t* d_active_idx,
+                                        uint32_t* d_active_mask, int64_t* d_n_active) {
+  Model* m = get_model(ctx, mlp_id);
+  if (!m) return fail(ctx, ISX_EINVAL, "bad mlp id");
+  if (!(k >= 0.f) || !std::isfinite(k)) return fail(ctx, ISX_EINVAL, "k must be finite and >= 0");
+  if (n_cells < 0 || !d_n_active || (n_cells > 0 && (!d_out || !d_active_idx || !d_active_mask)))
+    return fail(ctx, ISX_EINVAL, "bad arguments");
+  if (n_cells > (int64_t)ISX_NOALLOC_MAX_CELLS)
+    return fail(ctx, ISX_ECAPACITY, "n_cells " + std::to_string(n_cells) + " exceeds ISX_NOALLOC_MAX_CELLS (" +
+                                        std::to_string((int64_t)ISX_NOALLOC_MAX_CELLS) + ")");
+  (void)hipSetDevice(ctx->device);
+  uint8_t* base = static_cast<uint8_t*>(scratch_ptr(ctx->device));
+  if (!base) return fail(ctx, ISX_EHIP, "the fixed working memory of this device is not available");
+  // every mask entry is written by the classification and every scan
+  // partial by the scan before it is read: nothing needs clearing
+  uint32_t* cls = reinterpret_cast<uint32_t*>(base);
+  void* tmp = base + kNoAllocMaskBytes;
+  HIPCHK(launch_classify(n_cells, d_out, k, iso_list(*m), d_parent_mask, cls, ctx->stream));
+  HIPCHK(launch_compact(n_cells, cls, nullptr, d_active_idx, d_active_mask, d_n_active, tmp, ctx->stream));
   return ISX_OK;
 }
 
