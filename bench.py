@@ -194,6 +194,118 @@ def error_vs_oracle(ctx, mid, mlp, sample, S, k, n_aa, log):
 
 
 
+def dense_truth(ctx, mid, depth, isos):
+    """Iso-voxels of the dense (2^D)^3 grid: cells whose 8 corner values
+    (library float32 evaluation of the INR at every grid point) straddle an
+    iso-value (some < c, some >= c), as a bool tensor [iso, i, j, k] on the
+    device."""
+    import torch
+
+    import paper_2402_13861_amd as isx
+
+    R = (1 << depth) + 1
+    g = torch.linspace(-1.0, 1.0, R, device="cuda", dtype=torch.float64).float()
+    vals = torch.empty(R ** 3, dtype=torch.float32, device="cuda")
+    plane = torch.empty((R * R, 3), dtype=torch.float32, device="cuda")
+    jj, ii = torch.meshgrid(g, g, indexing="ij")
+    plane[:, 0] = ii.reshape(-1)
+    plane[:, 1] = jj.reshape(-1)
+    for kz in range(R):  # one z-plane of grid points per call (index i + R (j + R k))
+        plane[:, 2] = g[kz]
+        ctx.eval_points(mid, isx.FP32, plane, vals[kz * R * R:(kz + 1) * R * R])
+    v = vals.view(R, R, R)  # [k, j, i]
+    out = []
+    for c in isos:
+        below = v < c
+        any_b = torch.zeros((R - 1,) * 3, dtype=torch.bool, device="cuda")
+        all_b = torch.ones((R - 1,) * 3, dtype=torch.bool, device="cuda")
+        for dz in (0, 1):
+            for dy in (0, 1):
+                for dx in (0, 1):
+                    s_ = below[dz:dz + R - 1, dy:dy + R - 1, dx:dx + R - 1]
+                    any_b |= s_
+                    all_b &= s_
+        out.append((any_b & ~all_b).permute(2, 1, 0).contiguous())  # [i, j, k]
+    return torch.stack(out)
+
+
+def leaf_rates(ids, masks, truth, depth):
+    """FPR and FNR (Sec. V-A-3) of the active (leaf, iso) pairs against the
+    dense iso-voxels, over all (2^D)^3 x n_iso pairs."""
+    import numpy as np
+    import torch
+
+    code = torch.from_numpy(np.asarray(ids, dtype=np.int64)).cuda()
+    ijk = []
+    for axis in range(3):  # Morton ids, x bit lowest
+        v = torch.zeros_like(code)
+        for t_ in range(depth):
+            v |= ((code >> (3 * t_ + axis)) & 1) << t_
+        ijk.append(v)
+    ii, jj, kk = ijk
+    n_iso = truth.shape[0]
+    m = torch.from_numpy(np.asarray(masks, dtype=np.int64)).cuda()
+    tp = fp = 0
+    for q in range(n_iso):
+        pred = ((m >> q) & 1).bool()
+        t = truth[q, ii, jj, kk]
+        tp += int((pred & t).sum())
+        fp += int((pred & ~t).sum())
+    pos = int(truth.sum())
+    total = truth.numel()
+    fn = pos - tp
+    tn = total - pos - fp
+    return fp / max(fp + tn, 1), fn / max(fn + tp, 1)
+
+
+def t_sweep(a, log):
+    """Sec. V-B's sweep of t (time against missed iso-voxels) on the
+    benchmark INR at depth a.depth (default 8, 256^3): BF16 with the float64
+    band; UP on the octree and on Alg. 1's k-d tree, RA-UA on the octree, and
+    AA (the hard range) once.  Prints one JSON line."""
+    import numpy as np
+    import torch
+
+    import paper_2402_13861_amd as isx
+    from workloads.configs import WORKLOADS, isovalues, load_mlp
+
+    w = WORKLOADS[a.workload]
+    depth = a.depth if a.depth is not None else 8
+    mlp = load_mlp(a.workload)
+    isos, S = isovalues(a.workload)
+    ctx = isx.Context(0)
+    ctx.set_option(isx.SCRATCH_BYTES, 48 << 30)
+    mid = ctx.load_weights(mlp)
+    ctx.set_isovalues(mid, isos)
+    t0 = time.perf_counter()
+    truth = dense_truth(ctx, mid, depth, isos)
+    torch.cuda.synchronize()
+    dense_s = time.perf_counter() - t0
+    log(f"t-sweep: dense truth at {1 << depth}^3 in {dense_s:.2f} s, {int(truth.sum())} iso-voxel pairs")
+    band = w.get("band_rel", 0.0) * S
+    rows = []
+    runs = [("up", isx.UP, False, t) for t in (1, 2, 3, 4, 5, 6, 8, 10)]
+    runs += [("up-kd", isx.UP, True, t) for t in (2, 3, 5, 10)]
+    runs += [("raua", isx.RAUA, False, t) for t in (1, 2, 3, 5, 10)]
+    runs += [("aa", isx.AA, False, 1.0)]
+    for name, meth, kd, t in runs:
+        ctx.extract(mid, meth, isx.BF16, k=float(t), max_depth=depth, fp64_band=band, kd_tree=kd).free()  # warm
+        t1 = time.perf_counter()
+        m = ctx.extract(mid, meth, isx.BF16, k=float(t), max_depth=depth, fp64_band=band, kd_tree=kd)
+        ms = 1e3 * (time.perf_counter() - t1)
+        ids, masks = m.leaves()
+        fpr, fnr = leaf_rates(ids, masks, truth, depth)
+        prop = sum(l["propagated"] for l in m.levels())
+        rows.append(dict(method=name, t=t, ms=round(ms, 2), leaves=int(m.n_leaves), propagated=int(prop),
+                         fpr=fpr, fnr=fnr))
+        log(f"t-sweep {name} t={t}: {ms:.1f} ms, {m.n_leaves} leaves, FPR {fpr:.4f}, FNR {fnr:.2e}")
+        m.free()
+    print(json.dumps({"t_sweep": rows, "workload": a.workload, "depth": depth, "precision": "bf16",
+                      "fp64_band_S": w.get("band_rel", 0.0), "dense_truth_s": round(dense_s, 2)}), flush=True)
+    ctx.close()
+    return 0
+
+
 def copy_probe(nbytes: int, reps: int = 5):
     """A plain device-to-device copy of known size: the reference that scales
     the HBM byte counters (FETCH_SIZE, WRITE_SIZE) read for the kernels."""
@@ -235,6 +347,8 @@ def main(argv=None):
     ap.add_argument("--no-bf16-only", action="store_true",
                     help="skip the BF16 extraction without the surrogate (its recall is reported)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--t-sweep", action="store_true",
+                    help="only run the sweep of t (time against missed iso-voxels) and exit")
     ap.add_argument("--copy-probe-bytes", type=int, default=0,
                     help="only run a plain copy of this many bytes (counter calibration) and exit")
     a = ap.parse_args(argv)
@@ -244,6 +358,8 @@ def main(argv=None):
         return 2
     if a.copy_probe_bytes:
         return copy_probe(a.copy_probe_bytes)
+    if a.t_sweep:
+        return t_sweep(a, log)
 
     import numpy as np
     import torch
@@ -282,11 +398,13 @@ def main(argv=None):
         plain_s = time.perf_counter() - t0
         ctx.set_option(isx.KEEP_LEVELS, 0)
         plain_ids, _ = m.leaves()
-        visited = [m.level_cells(L)[0] for L in range(m.n_levels)] if use_sur else None
         plain = dict(ms=1e3 * plain_s, leaves=int(m.n_leaves), tris=int(m.n_tris),
                      propagated=sum(l["cells"] for l in m.levels()), phases=m.times())
         log(f"plain fp32: {1e3 * plain_s:.1f} ms, {m.n_leaves} leaves")
-        m.free()
+        if use_sur:
+            visited = m  # its kept levels seed the surrogate's training cells
+        else:
+            m.free()
 
     # 1b. BF16 without the surrogate: separates the BF16 error's share of the
     #     leaf differences from the surrogate's
@@ -308,17 +426,16 @@ def main(argv=None):
     if use_sur:
         t0 = time.perf_counter()
         info = train_surrogate(ctx, mid, depth, mu_bar, S, visited=visited, n_pairs=a.sur_pairs, steps=a.sur_steps,
-                               holdout=a.sur_holdout,
-                               isos=isos, k=w["k"], accept_leaves=bool(a.accept_leaves), base=bool(a.sur_base),
-                               log=log)
-        sur_info = dict(train_total_s=round(time.perf_counter() - t0, 2), train_kernel_s=round(info.train_seconds, 3),
+                               holdout=a.sur_holdout, k=w["k"], accept_leaves=bool(a.accept_leaves),
+                               base=bool(a.sur_base), log=log)
+        sur_info = dict(train_total_s=round(time.perf_counter() - t0, 2),
                         pairs=info.n_pairs, steps=info.steps, final_loss=info.final_loss, z=info.z,
                         z_accept=info.z_accept, z_levels=info.z_levels, z_accept_levels=info.z_accept_levels,
                         holdout_miss=info.holdout_miss,
                         holdout_false_accept=info.holdout_false_accept,
                         accept_leaves=bool(a.accept_leaves), base=bool(a.sur_base),
                         err_mu=[round(x, 5) for x in info.err_mu], err_logsig=[round(x, 4) for x in info.err_logsig])
-        del visited
+        visited.free()
 
     kw = dict(base, precision=prec, use_surrogate=use_sur)
     for i in range(a.warmup):

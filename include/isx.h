@@ -49,9 +49,13 @@ typedef enum {
   ISX_EUNSUPPORTED = -7  /* valid request that this build does not implement */
 } isx_status;
 
-/* Range analysis by affine arithmetic ("RA-Full", Sec. III) or uncertainty
- * propagation with probabilistic affine forms ("UP", Sec. IV-B). */
-typedef enum { ISX_AA = 0, ISX_UP = 1 } isx_method;
+/* Range analysis by affine arithmetic ("RA-Full", Sec. III), uncertainty
+ * propagation with probabilistic affine forms ("UP", Sec. IV-B), or range
+ * analysis read off under the uniform assumption ("RA-UA", Sec. IV-A,
+ * Eq. 5): the affine form of AA, its symbols taken as independent uniform
+ * variables on [-1, 1], gives N(x0, sum_i x_i^2 / 3), whose soft bound is
+ * [x0 - t sigma, x0 + t sigma] as for UP. */
+typedef enum { ISX_AA = 0, ISX_UP = 1, ISX_RAUA = 2 } isx_method;
 
 /* Arithmetic of the propagation and evaluation kernels.
  *   ISX_FP32: float32 everywhere; hidden-layer products on FP32 MFMA.
@@ -59,6 +63,11 @@ typedef enum { ISX_AA = 0, ISX_UP = 1 } isx_method;
  *             accumulation, statistics and epilogues (centre column float32).
  *   ISX_FP64: float64 everywhere (reference / re-check path). */
 typedef enum { ISX_FP32 = 0, ISX_BF16 = 1, ISX_FP64 = 2 } isx_precision;
+
+/* Activation after every hidden linear layer (App. D table rows): ReLU, sine
+ * (SIREN nets; any frequency factor omega_0 is folded into the weights), or
+ * ELU (x for x > 0, e^x - 1 otherwise). */
+typedef enum { ISX_RELU = 0, ISX_SINE = 1, ISX_ELU = 2 } isx_activation;
 
 typedef struct isx_ctx isx_ctx;
 typedef struct isx_mesh isx_mesh;
@@ -93,6 +102,15 @@ const char* isx_last_error(const isx_ctx* ctx);
 isx_status isx_load_mlp(isx_ctx* ctx, int32_t n_linear, const int32_t* widths,
                         const float* const* h_W, const float* const* h_b, int32_t* mlp_id);
 
+/* Hidden activation of a loaded MLP (default ISX_RELU).  The rules follow
+ * the App. D table (UP: Gaussian least-squares lines; AA: the minimax line for
+ * ReLU and the convex ELU, a chord with exact error extremes for sine).
+ * Sine and ELU nets run in float32 and float64 (vector-ALU and FP32/FP64 MFMA
+ * kernels); ISX_BF16 propagation, the AA rounding margin, isx_linearize and
+ * the surrogate's linearisation base need ReLU (ISX_EUNSUPPORTED otherwise).
+ * Errors: ISX_EINVAL. */
+isx_status isx_set_activation(isx_ctx* ctx, int32_t mlp_id, isx_activation act);
+
 /* Release an MLP's device memory. */
 isx_status isx_unload_mlp(isx_ctx* ctx, int32_t mlp_id);
 
@@ -107,8 +125,8 @@ isx_status isx_set_isovalues(isx_ctx* ctx, int32_t mlp_id, int32_t n_iso, const 
 /* Propagate n_cells boxes through the MLP (the bound computation of Alg. 1, without the
  * test).  d_centres [n][3] and d_halves [n][3] (per-axis half-widths, > 0)
  * are device arrays.  d_out [n][2] receives (centre, spread) as float32:
- * (x0, r) for ISX_AA, whose range is [x0 - r, x0 + r] (Eq. 2), and
- * (mu, sigma) for ISX_UP (Eq. 7).  With ISX_FP64 the same pair is also
+ * (x0, r) for ISX_AA, whose range is [x0 - r, x0 + r] (Eq. 2),
+ * (mu, sigma) for ISX_UP (Eq. 7) and (x0, sigma) for ISX_RAUA (Eq. 5).  With ISX_FP64 the same pair is also
  * written in float64 to d_out64 [n][2] if it is not NULL (it must be NULL
  * for the other precisions).  Asynchronous, except ISX_BF16 with ISX_UP in
  * covariance form with ISX_CANCEL_CHECK on (the default), which synchronises
@@ -169,7 +187,7 @@ isx_status isx_linearize(isx_ctx* ctx, int32_t mlp_id, int64_t n, const float* d
 typedef struct {
   isx_method method;       /* ISX_UP (soft bound) or ISX_AA (hard bound) */
   isx_precision precision; /* arithmetic of propagation and corner evaluation */
-  float k;                 /* t of Alg. 1 for UP (ignored for AA, which uses 1) */
+  float k;                 /* t of Alg. 1 for UP and RA-UA (ignored for AA, which uses 1) */
   int32_t max_depth;       /* octree depth D: leaves are the (2^D)^3 grid cells, D <= 10 */
   float fp64_band;         /* > 0: cells whose bound endpoint lies within
                               fp64_band of an iso-value are re-propagated in
@@ -180,6 +198,14 @@ typedef struct {
   int32_t use_surrogate;   /* 1: decide cells with the surrogate attached to
                               the MLP where it is confident (see
                               isx_surrogate_attach), propagate the rest */
+  int32_t tree;            /* 0: octree (every level splits a cell into 8 cubes);
+                              1: Alg. 1's binary k-d tree, each node split along
+                              its widest dimension (ties x, y, z) down to node
+                              depth 3 max_depth, so that nodes at half and quarter
+                              cells are tested too; needs a cube domain; meshes
+                              then record 3 max_depth + 1 levels (node ids: root 0,
+                              children 2p and 2p + 1), leaves as octree Morton
+                              ids in k-d order; not with use_surrogate */
 } isx_params;
 
 /* Full extraction (Alg. 1 followed by corner evaluation and marching cubes)
@@ -306,6 +332,81 @@ isx_status isx_surrogate_attach(isx_ctx* ctx, int32_t mlp_id, int32_t sur_id, in
                                 const float* h_z_accept, int32_t accept_leaves);
 isx_status isx_surrogate_free(isx_ctx* ctx, int32_t sur_id);
 
+/* Training set of the surrogate: n cells, each drawn (with probability 1/2
+ * when `visited` is given) uniformly from the cells a plain extraction
+ * examined -- a mesh made with ISX_KEEP_LEVELS, whose level lists are used --
+ * or else as a uniform random cell of a uniform random octree level in
+ * [level_lo, level_hi] (<= 10) of the MLP's domain.  Random numbers from
+ * SplitMix64 at counters derived from (seed, cell index).  d_centres,
+ * d_halves [n][3] float32 and d_levels [n] int32 device arrays receive the
+ * boxes and their levels.  Synchronous.  Errors: ISX_EINVAL, ISX_EHIP. */
+isx_status isx_surrogate_sample_cells(isx_ctx* ctx, int32_t mlp_id, const isx_mesh* visited, int64_t n,
+                                      int32_t level_lo, int32_t level_hi, uint64_t seed, float* d_centres,
+                                      float* d_halves, int32_t* d_levels);
+
+/* Calibration of the surrogate's safety bands on held-out cells. */
+typedef struct {
+  int32_t n_levels;          /* levels 0..n_levels-1 (<= 16) */
+  int64_t n_cells[16];       /* held-out cells per level */
+  int64_t kept[16];          /* of those, cells the plain soft-bound test keeps for some carried iso-value */
+  float err_mu[16];          /* RMS error of mu_hat (field units, or units of s_b with a base); a level with
+                                fewer than 50 cells takes the previous level's value (level 0: S, 1) */
+  float err_logsig[16];      /* RMS error of ln sigma_hat */
+  float z[16], z_accept[16]; /* prune / accept band per level, from the ladder
+                                {0, .5, 1, 1.5, 2, 2.5, 3, 3.5, 4, 5, 6, 8, 12} (prune bands >= 2) */
+  float z_global, z_accept_global;          /* the bands chosen over all levels together */
+  double holdout_miss, holdout_false_accept; /* rates at the chosen per-level bands */
+} isx_surrogate_calibration;
+
+/* isx_surrogate_calibrate: predict the n held-out cells (d_centres,
+ * d_halves [n][3], propagated d_targets [n][2] = (mu, sigma), octree levels
+ * d_levels [n]) with surrogate sur_id, measure its per-level error, and pick
+ * bands so that, with t = k and the MLP's iso-values, the prune rule of
+ * isx_surrogate_partition drops a kept iso-value of at most miss_target of
+ * the kept cells (misses / kept) and the accept rule accepts a rejected
+ * iso-value of at most accept_target of them: the smallest ladder value that
+ * meets the target over all levels, and per level where at least
+ * min_level_kept cells are kept (else the global band).  The surrogate is
+ * then attached to mlp_id with those bands (accept_leaves as in
+ * isx_surrogate_attach) and *cal receives them.  Error sums are reduced in a
+ * fixed order and the rates are integer counts, so the result is
+ * deterministic.  Synchronous.  Errors: ISX_EINVAL, ISX_ENOMEM, ISX_EHIP. */
+isx_status isx_surrogate_calibrate(isx_ctx* ctx, int32_t sur_id, int32_t mlp_id, int64_t n,
+                                   const float* d_centres, const float* d_halves, const float* d_targets,
+                                   const int32_t* d_levels, int32_t n_levels, float k, float miss_target,
+                                   float accept_target, int64_t min_level_kept, int32_t accept_leaves,
+                                   isx_surrogate_calibration* cal);
+
+/* One-call training of a surrogate for MLP mlp_id (the learned part as a
+ * whole): n_pairs + n_holdout cells from isx_surrogate_sample_cells (levels
+ * min(3, depth)..depth, `visited` optional), their float32 uncertainty
+ * propagation as targets, a 4 -> hidden_width^hidden_layers -> 2 network
+ * with He-normal weights from the seed, normalisation (mu_bar, scale) and
+ * the size feature 0.25 log2(cell size) + 1, optionally corrections to the
+ * centre linearisation (use_base, s_floor = 1e-6 scale), `steps` Adam steps
+ * of `batch` rows with learning rate lr on the n_pairs cells, and the bands
+ * of isx_surrogate_calibrate on the n_holdout cells (attached to mlp_id).
+ * *sur_id receives the surrogate, *cal its calibration and h_loss [steps]
+ * (host, may be NULL) the training losses.  Synchronous.
+ * Errors: ISX_EINVAL, ISX_ESHAPE, ISX_ENOMEM, ISX_EHIP. */
+typedef struct {
+  int64_t n_pairs, n_holdout;
+  int32_t steps, batch;
+  float lr;
+  uint64_t seed;
+  int32_t depth;                       /* octree depth of the extractions it serves */
+  int32_t hidden_width, hidden_layers; /* 128, 3 */
+  int32_t use_base;
+  float mu_bar, scale;                 /* mean and std of the INR output */
+  float k;                             /* t of the soft-bound test */
+  float miss_target, accept_target;    /* 1e-4, 1e-3 */
+  int64_t min_level_kept;              /* 20000 */
+  int32_t accept_leaves;
+} isx_surrogate_fit_params;
+isx_status isx_surrogate_fit(isx_ctx* ctx, int32_t mlp_id, const isx_mesh* visited,
+                             const isx_surrogate_fit_params* params, int32_t* sur_id,
+                             isx_surrogate_calibration* cal, float* h_loss);
+
 /* isx_surrogate_partition: the band partition isx_extract applies at octree
  * level `level` (bands of that level as attached to mlp_id by
  * isx_surrogate_attach, its iso-values, bound multiplier k = t), on n caller
@@ -368,10 +469,12 @@ typedef enum {
   ISX_BATCH_WORKERS = 10,  /* isx_extract_batch: worker contexts (streams) that run INRs at once, 1..16
                               (default 4) */
   ISX_CANCEL_CHECK = 11    /* bf16 uncertainty propagation in covariance form: 1 (default) = a cell with a
-                              layer whose variance sum sum_i T_ji W_ji (signed, over bfloat16-rounded
-                              covariances) keeps at most 2^-9 of the magnitude sum_i |T_ji W_ji| of its
-                              terms is propagated again in float64 (Eq. 7 needs the variance; such a sum
-                              can lose every digit), and its float64 (mu, sigma) is returned; 0 = off */
+                              neuron whose variance sum v = sum_i T_ji W_ji (signed, over bfloat16-rounded
+                              covariances) keeps at most 2^-9 of the magnitude a = sum_i |T_ji W_ji| of its
+                              terms (Eq. 7 needs the variance; such a sum can lose every digit) while its
+                              pre-activation y has |y| < 6 sqrt(max(v, 0) + 2^-7 a) (the ReLU rule of Eq. 9
+                              depends on sigma there) is propagated again in float64, and its float64
+                              (mu, sigma) is returned; 0 = off */
 } isx_option;
 isx_status isx_set_option(isx_ctx* ctx, isx_option option, int64_t value);
 

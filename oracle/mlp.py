@@ -1,5 +1,5 @@
 """Plain coordinate-MLP evaluation in float64 (Sec. III-B: a chain of linear
-layers, each but the last followed by the activation; here ReLU).
+layers, each but the last followed by the activation: ReLU, or sine / ELU).
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 """
@@ -16,8 +16,10 @@ def as_f64_layers(layers):
     return [(np.asarray(W, dtype=np.float64), np.asarray(b, dtype=np.float64)) for W, b in layers]
 
 
-def mlp_forward(layers, x, chunk: int = 1 << 16) -> np.ndarray:
+def mlp_forward(layers, x, chunk: int = 1 << 16, act: str = "relu") -> np.ndarray:
     """f(x) for points ``x [N, 3]``; returns ``[N]`` float64."""
+    from .rules import activation
+
     layers = as_f64_layers(layers)
     x = np.asarray(x, dtype=np.float64)
     out = np.empty(x.shape[0], dtype=np.float64)
@@ -26,6 +28,6 @@ def mlp_forward(layers, x, chunk: int = 1 << 16) -> np.ndarray:
         for li, (W, b) in enumerate(layers):
             h = h @ W.T + b
             if li + 1 < len(layers):
-                h = np.maximum(h, 0.0)
+                h = activation(act, h)
         out[s : s + chunk] = h[:, 0]
     return out

@@ -81,7 +81,7 @@ def bound_k(method, k):
 
 
 def extract_active(layers, method, isos, depth, k=3.0, lo=(-1.0,) * 3, hi=(1.0,) * 3,
-                   max_cells=None):
+                   max_cells=None, act="relu"):
     """Octree search of Alg. 1 from the root to ``depth``.
 
     Returns a list, one dict per level 0..depth, with the evaluated cells
@@ -105,7 +105,79 @@ def extract_active(layers, method, isos, depth, k=3.0, lo=(-1.0,) * 3, hi=(1.0,)
         if max_cells is not None and ids.size > max_cells:
             raise MemoryError(f"level {L}: {ids.size} cells exceed max_cells={max_cells}")
         c, h = cell_boxes(L, ids, lo, hi)
-        centre, spread = propagate(layers, c, h, method)
+        centre, spread = propagate(layers, c, h, method, act=act)
         mask = classify(centre, spread, kk, isos, pmask)
         levels.append(dict(level=L, ids=ids, centre=centre, spread=spread, mask=mask))
     return levels
+
+
+# ---------------------------------------------------------------- k-d tree
+def widest_axis(half):
+    """Split axis of Alg. 1: the widest dimension of the box, ties broken
+    towards the lower axis index (x, then y, then z)."""
+    half = np.asarray(half, dtype=np.float64)
+    return int(np.argmax(half))  # argmax returns the first of equal maxima
+
+
+def kd_split(centre, half, axis):
+    """The two halves of a box split at its centre along ``axis``: (lower,
+    upper), each as (centre, half-widths)."""
+    c0, c1 = np.array(centre, dtype=np.float64), np.array(centre, dtype=np.float64)
+    h = np.array(half, dtype=np.float64)
+    h[axis] *= 0.5
+    c0[axis] -= h[axis]
+    c1[axis] += h[axis]
+    return (c0, h), (c1, h.copy())
+
+
+def extract_active_kd(layers, method, isos, depth, k=3.0, lo=(-1.0,) * 3, hi=(1.0,) * 3, act="relu"):
+    """Alg. 1 with its binary k-d tree: every node is split along its widest
+    dimension (ties x, y, z) until depth ``depth`` (the paper takes a multiple
+    of 3, so that a cube domain ends in cubes), nodes of one depth handled
+    together (each node's decision depends only on its box).  Node ids:
+    the root is 0 and the children of node p are 2p (lower half) and 2p + 1
+    (upper half).  Returns one dict per depth 0..depth with ``ids``,
+    ``centre``, ``half`` (per-axis half-widths), ``spread`` and ``mask`` as in
+    ``extract_active``."""
+    isos = np.atleast_1d(np.asarray(isos, dtype=np.float64))
+    full = np.uint32((1 << isos.size) - 1)
+    kk = bound_k(method, k)
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    ids = np.zeros(1, dtype=np.uint64)
+    cen = ((lo + hi) / 2.0)[None, :]
+    hal = ((hi - lo) / 2.0)[None, :]
+    pmask = np.array([full], dtype=np.uint32)
+    levels = []
+    for d in range(depth + 1):
+        if d > 0:
+            prev = levels[-1]
+            keep = prev["mask"] != 0
+            par_ids, par_c, par_h, par_m = prev["ids"][keep], prev["centre_box"][keep], prev["half"][keep], prev["mask"][keep]
+            n = par_ids.size
+            ids = np.empty(2 * n, dtype=np.uint64)
+            cen = np.empty((2 * n, 3))
+            hal = np.empty((2 * n, 3))
+            for i in range(n):
+                lower, upper = kd_split(par_c[i], par_h[i], widest_axis(par_h[i]))
+                ids[2 * i], ids[2 * i + 1] = 2 * par_ids[i], 2 * par_ids[i] + np.uint64(1)
+                cen[2 * i], hal[2 * i] = lower
+                cen[2 * i + 1], hal[2 * i + 1] = upper
+            pmask = np.repeat(par_m, 2)
+        centre, spread = propagate(layers, cen, hal, method, act=act) if ids.size else (np.zeros(0), np.zeros(0))
+        mask = classify(centre, spread, kk, isos, pmask)
+        levels.append(dict(level=d, ids=ids, centre_box=cen, half=hal, centre=centre, spread=spread, mask=mask))
+    return levels
+
+
+def kd_to_morton(ids, depth3):
+    """Octree Morton id (x bit lowest) of the k-d node ``ids`` at depth
+    3 * depth3 of a cube domain, whose splits cycle x, y, z: each triple of
+    id bits, read from the top, is the (x, y, z) side of one octree level."""
+    ids = np.asarray(ids, dtype=np.uint64)
+    out = np.zeros(ids.shape, dtype=np.uint64)
+    for q in range(depth3):
+        t = (ids >> np.uint64(3 * (depth3 - 1 - q))) & np.uint64(7)
+        bx, by, bz = (t >> np.uint64(2)) & np.uint64(1), (t >> np.uint64(1)) & np.uint64(1), t & np.uint64(1)
+        out |= (bx | (by << np.uint64(1)) | (bz << np.uint64(2))) << np.uint64(3 * (depth3 - 1 - q))
+    return out

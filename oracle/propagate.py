@@ -11,8 +11,8 @@ Z_i zero-mean, unit-variance, independent).
   Sec. IV-C and Alg. 1 for UP): x0 = c, F = diag(h) for AA and
   F = diag(h / sqrt 3) for UP (a uniform variable on [-h, h] has std h/sqrt 3).
 * Linear layer y = W x + b (Eq. 3 / Eq. 8, exact): x0 <- W x0 + b, F <- W F.
-* ReLU, per neuron j (Eq. 4 / Eq. 9): take (alpha_j, beta_j, gamma_j) from the
-  rule, then x0_j <- alpha_j x0_j + beta_j, row j of F <- alpha_j * row j, and
+* Activation (ReLU; or sine / ELU, App. D rows), per neuron j (Eq. 4 /
+  Eq. 9): take (alpha_j, beta_j, gamma_j) from the rule, then x0_j <- alpha_j x0_j + beta_j, row j of F <- alpha_j * row j, and
   append one new symbol column whose only nonzero entry is gamma_j in row j.
   The rule's input is (x0_j, r_j = sum_i |F_ji|) for AA (Eq. 2 hard range)
   and (mu_j = x0_j, sigma_j = sqrt(sum_i F_ji^2)) for UP (Eq. 7, CLT).
@@ -45,7 +45,7 @@ from __future__ import annotations
 import numpy as np
 
 from .mlp import as_f64_layers
-from .rules import relu_aa_rule, relu_up_rule
+from .rules import aa_rule, relu_aa_rule, relu_up_rule, up_rule
 
 AA = "aa"
 UP = "up"
@@ -72,7 +72,7 @@ def margin_const(K, u, u_b=0.0):
     return 2.0 * u_b + u_b * u_b + gamma_n(K + 1, u) * (1.0 + u_b) ** 2
 
 
-def _track(layers, centres, halves, method, keep_hidden=False, margin=False):
+def _track(layers, centres, halves, method, keep_hidden=False, margin=False, act="relu"):
     """Coefficient tracking for one chunk of boxes; returns (centre, spread)
     and optionally per-hidden-layer (pre-activation centre, row statistic)."""
     C = centres.shape[0]
@@ -95,13 +95,13 @@ def _track(layers, centres, halves, method, keep_hidden=False, margin=False):
         n = W.shape[0]
         if method == UP:
             stat = np.sqrt(np.einsum("cnd,cnd->cn", F, F))
-            alpha, beta, gamma2 = relu_up_rule(x0, stat)
+            alpha, beta, gamma2 = up_rule(act, x0, stat)
             gamma = np.sqrt(gamma2)
         else:
             stat = np.abs(F).sum(axis=2)
             if margin:
                 stat = stat * (1.0 + 2.0 * gamma_n(F.shape[2], U64)) + m
-            alpha, beta, gamma = relu_aa_rule(x0, stat)
+            alpha, beta, gamma = aa_rule(act, x0, stat)
             if margin:
                 gamma = gamma + alpha * m + 8.0 * U64 * (alpha * (np.abs(x0) + stat) + np.abs(beta))
         if keep_hidden:
@@ -124,24 +124,26 @@ def _track(layers, centres, halves, method, keep_hidden=False, margin=False):
     return x0[:, 0], spread, hidden
 
 
-def propagate(layers, centres, halves, method: str, chunk: int | None = None, margin: bool = False):
+def propagate(layers, centres, halves, method: str, chunk: int | None = None, margin: bool = False,
+              act: str = "relu"):
     """Propagate boxes through the MLP.
 
     centres, halves: [C, 3] (box centre and per-axis half-widths).
     method: ``AA`` (range analysis), ``UP`` (uncertainty propagation) or
     ``RAUA`` (range analysis with the uniform assumption read-off).
     margin: AA only, apply the rounding margin (module docstring).
+    act: the hidden activation, ``relu``, ``sine`` or ``elu`` (App. D rows).
     Returns float64 (centre [C], spread [C]).
     """
-    if margin and method != AA:
-        raise ValueError("the rounding margin applies to AA")
+    if margin and (method != AA or act != "relu"):
+        raise ValueError("the rounding margin applies to AA on ReLU nets")
     layers = as_f64_layers(layers)
     centres = np.asarray(centres, dtype=np.float64).reshape(-1, 3)
     halves = np.asarray(halves, dtype=np.float64).reshape(-1, 3)
     chunk = chunk or _chunk_for(layers)
     cs, ss = [], []
     for a in range(0, centres.shape[0], chunk):
-        c, s, _ = _track(layers, centres[a : a + chunk], halves[a : a + chunk], method, margin=margin)
+        c, s, _ = _track(layers, centres[a : a + chunk], halves[a : a + chunk], method, margin=margin, act=act)
         cs.append(c)
         ss.append(s)
     if not cs:
@@ -149,16 +151,16 @@ def propagate(layers, centres, halves, method: str, chunk: int | None = None, ma
     return np.concatenate(cs), np.concatenate(ss)
 
 
-def propagate_hidden(layers, centres, halves, method: str):
+def propagate_hidden(layers, centres, halves, method: str, act: str = "relu"):
     """As ``propagate`` but also returns, per hidden layer, the pre-activation
     centre [C, n] and row statistic [C, n] (sigma for UP, r for AA)."""
     layers = as_f64_layers(layers)
     centres = np.asarray(centres, dtype=np.float64).reshape(-1, 3)
     halves = np.asarray(halves, dtype=np.float64).reshape(-1, 3)
-    return _track(layers, centres, halves, method, keep_hidden=True)
+    return _track(layers, centres, halves, method, keep_hidden=True, act=act)
 
 
-def propagate_up_covariance(layers, centres, halves):
+def propagate_up_covariance(layers, centres, halves, act: str = "relu"):
     """UP written with the covariance of the symbols instead of the symbols.
 
     Since the symbols are independent with unit variance, only
@@ -183,7 +185,7 @@ def propagate_up_covariance(layers, centres, halves):
             break
         n = W.shape[0]
         sigma = np.sqrt(np.maximum(S[:, np.arange(n), np.arange(n)], 0.0))
-        alpha, beta, gamma2 = relu_up_rule(x0, sigma)
+        alpha, beta, gamma2 = up_rule(act, x0, sigma)
         x0 = alpha * x0 + beta
         S = alpha[:, :, None] * S * alpha[:, None, :]
         S[:, np.arange(n), np.arange(n)] += gamma2

@@ -20,13 +20,13 @@ from typing import Optional, Sequence
 import numpy as np
 
 from . import _lib
-from ._lib import (AA, BF16, BF16_VARIANT, FP32, FP64, HIDDEN_KERNEL, KEEP_LEVELS, PROFILE, SCRATCH_BYTES, UP,
+from ._lib import (AA, RAUA, RELU, SINE, ELU, BF16, BF16_VARIANT, FP32, FP64, HIDDEN_KERNEL, KEEP_LEVELS, PROFILE, SCRATCH_BYTES, UP,
                    UP_FORM, LIN_PRECISION, AA_MARGIN, BATCH_WORKERS, VERBOSE, CANCEL_CHECK)
 
 KERNEL_KINDS = ("hidden_fp32", "hidden_bf16", "hidden_simt_fp32", "hidden_fp64", "dense", "output",
                 "hidden_cov_bf16", "linearize")
 
-__all__ = ["Context", "Mesh", "IsxError", "AA", "UP", "FP32", "BF16", "FP64", "KEEP_LEVELS", "HIDDEN_KERNEL",
+__all__ = ["Context", "Mesh", "IsxError", "AA", "UP", "RAUA", "RELU", "SINE", "ELU", "FP32", "BF16", "FP64", "KEEP_LEVELS", "HIDDEN_KERNEL",
            "PROFILE", "SCRATCH_BYTES", "VERBOSE", "BF16_VARIANT", "mc_case_table"]
 
 
@@ -124,6 +124,10 @@ class Context:
 
     def unload_mlp(self, mlp_id: int):
         self._chk(self._L.isx_unload_mlp(self._h, mlp_id))
+
+    def set_activation(self, mlp_id: int, act: int):
+        """Hidden activation of a loaded MLP: RELU (default), SINE or ELU."""
+        self._chk(self._L.isx_set_activation(self._h, mlp_id, int(act)))
 
     def set_domain(self, mlp_id: int, lo, hi):
         lo = (C.c_float * 3)(*map(float, lo))
@@ -284,6 +288,61 @@ class Context:
                                                   int(bool(leaf)), _ptr(parent_mask), _ptr(mask), _ptr(fb)))
         return mask[:n], fb[:n]
 
+    @staticmethod
+    def _calibration(cal):
+        n = cal.n_levels
+        return dict(n_levels=n, n_cells=list(cal.n_cells[:n]), kept=list(cal.kept[:n]), err_mu=list(cal.err_mu[:n]),
+                    err_logsig=list(cal.err_logsig[:n]), z=list(cal.z[:n]), z_accept=list(cal.z_accept[:n]),
+                    z_global=cal.z_global, z_accept_global=cal.z_accept_global, holdout_miss=cal.holdout_miss,
+                    holdout_false_accept=cal.holdout_false_accept)
+
+    def surrogate_sample_cells(self, mlp_id: int, visited, n: int, level_lo: int, level_hi: int, seed: int = 0):
+        """isx_surrogate_sample_cells: (centres, halves, levels) device
+        tensors of n training cells; visited is a Mesh made with KEEP_LEVELS
+        (or None)."""
+        import torch
+
+        dev = torch.device("cuda", self.device)
+        c = torch.empty((n, 3), dtype=torch.float32, device=dev)
+        h = torch.empty((n, 3), dtype=torch.float32, device=dev)
+        lv = torch.empty(n, dtype=torch.int32, device=dev)
+        self._chk(self._L.isx_surrogate_sample_cells(self._h, mlp_id, visited._h if visited is not None else None, n,
+                                                     level_lo, level_hi, int(seed), _ptr(c), _ptr(h), _ptr(lv)))
+        return c, h, lv
+
+    def surrogate_calibrate(self, sid: int, mlp_id: int, centres, halves, targets, levels, n_levels: int, k: float,
+                            miss_target: float = 1e-4, accept_target: float = 1e-3, min_level_kept: int = 20000,
+                            accept_leaves: bool = False):
+        """isx_surrogate_calibrate on held-out device tensors; attaches the
+        surrogate and returns its calibration as a dict."""
+        cal = _lib.SurrogateCalibration()
+        self._chk(self._L.isx_surrogate_calibrate(self._h, sid, mlp_id, centres.shape[0], _ptr(centres), _ptr(halves),
+                                                  _ptr(targets), _ptr(levels), n_levels, float(k), float(miss_target),
+                                                  float(accept_target), int(min_level_kept), int(bool(accept_leaves)),
+                                                  C.byref(cal)))
+        return self._calibration(cal)
+
+    def surrogate_fit(self, mlp_id: int, visited=None, *, n_pairs: int, n_holdout: int, steps: int, batch: int,
+                      lr: float, seed: int, depth: int, mu_bar: float, scale: float, k: float, use_base: bool,
+                      accept_leaves: bool, miss_target: float = 1e-4, accept_target: float = 1e-3,
+                      min_level_kept: int = 20000, hidden_width: int = 128, hidden_layers: int = 3):
+        """isx_surrogate_fit: returns (surrogate id, calibration dict, losses
+        per step as a numpy array)."""
+        p = _lib.SurrogateFitParams(n_pairs=n_pairs, n_holdout=n_holdout, steps=steps, batch=batch, lr=lr,
+                                    seed=seed, depth=depth, hidden_width=hidden_width, hidden_layers=hidden_layers,
+                                    use_base=int(bool(use_base)), mu_bar=mu_bar, scale=scale, k=k,
+                                    miss_target=miss_target, accept_target=accept_target,
+                                    min_level_kept=min_level_kept, accept_leaves=int(bool(accept_leaves)))
+        sid = C.c_int32()
+        cal = _lib.SurrogateCalibration()
+        losses = np.zeros(max(steps, 1), dtype=np.float32)
+        self._chk(self._L.isx_surrogate_fit(self._h, mlp_id, visited._h if visited is not None else None, C.byref(p),
+                                            C.byref(sid), C.byref(cal), losses.ctypes.data))
+        widths = [4] + [hidden_width] * hidden_layers + [2]
+        self._sur_shapes = getattr(self, "_sur_shapes", {})
+        self._sur_shapes[sid.value] = [(o, i) for i, o in zip(widths[:-1], widths[1:])]
+        return sid.value, self._calibration(cal), losses[:steps]
+
     def surrogate_free(self, sid: int):
         self._chk(self._L.isx_surrogate_free(self._h, sid))
 
@@ -328,9 +387,11 @@ class Context:
     # -- full extraction (synchronous)
     def extract(self, mlp_id: int, method: int = UP, precision: int = FP32, k: float = 3.0, max_depth: int = 6,
                 fp64_band: float = 0.0, max_cells: int = 0, chunk_cells: int = 0,
-                use_surrogate: bool = False) -> "Mesh":
+                use_surrogate: bool = False, kd_tree: bool = False) -> "Mesh":
+        """isx_extract; kd_tree selects Alg. 1's binary k-d tree (node depth
+        3 max_depth) instead of the octree."""
         p = _lib.Params(method, precision, float(k), int(max_depth), float(fp64_band), int(max_cells),
-                        int(chunk_cells), int(bool(use_surrogate)))
+                        int(chunk_cells), int(bool(use_surrogate)), int(bool(kd_tree)))
         h = C.c_void_p()
         self._chk(self._L.isx_extract(self._h, mlp_id, C.byref(p), C.byref(h)))
         return Mesh(self._L, h)
@@ -341,7 +402,7 @@ class Context:
         """isx_extract of several INRs with the same parameters, run on
         ISX_BATCH_WORKERS streams at once; returns one Mesh per INR."""
         p = _lib.Params(method, precision, float(k), int(max_depth), float(fp64_band), int(max_cells),
-                        int(chunk_cells), int(bool(use_surrogate)))
+                        int(chunk_cells), int(bool(use_surrogate)), 0)
         ids = (C.c_int32 * len(mlp_ids))(*[int(i) for i in mlp_ids])
         hs = (C.c_void_p * len(mlp_ids))()
         self._chk(self._L.isx_extract_batch(self._h, len(mlp_ids), ids, C.byref(p), hs))

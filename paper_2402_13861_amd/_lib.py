@@ -16,7 +16,8 @@ STATUS_NAMES = {
     0: "ISX_OK", -1: "ISX_EINVAL", -2: "ISX_ESHAPE", -3: "ISX_ENOMEM", -4: "ISX_ECAPACITY",
     -5: "ISX_EHIP", -6: "ISX_ENAN", -7: "ISX_EUNSUPPORTED",
 }
-AA, UP = 0, 1
+AA, UP, RAUA = 0, 1, 2
+RELU, SINE, ELU = 0, 1, 2
 FP32, BF16, FP64 = 0, 1, 2
 (KEEP_LEVELS, HIDDEN_KERNEL, PROFILE, SCRATCH_BYTES, VERBOSE, BF16_VARIANT, UP_FORM, LIN_PRECISION,
  AA_MARGIN, BATCH_WORKERS, CANCEL_CHECK) = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11
@@ -24,6 +25,44 @@ MAX_LINEAR, MAX_WIDTH, MAX_ISO = 16, 1024, 32
 NOALLOC_MAX_CELLS = 1 << 22
 (KERNEL_HIDDEN_FP32, KERNEL_HIDDEN_BF16, KERNEL_HIDDEN_SIMT_FP32, KERNEL_HIDDEN_FP64, KERNEL_DENSE,
  KERNEL_OUTPUT, KERNEL_HIDDEN_COV_BF16, KERNEL_LINEARIZE) = range(8)
+
+
+class SurrogateCalibration(C.Structure):
+    _fields_ = [
+        ("n_levels", C.c_int32),
+        ("n_cells", C.c_int64 * 16),
+        ("kept", C.c_int64 * 16),
+        ("err_mu", C.c_float * 16),
+        ("err_logsig", C.c_float * 16),
+        ("z", C.c_float * 16),
+        ("z_accept", C.c_float * 16),
+        ("z_global", C.c_float),
+        ("z_accept_global", C.c_float),
+        ("holdout_miss", C.c_double),
+        ("holdout_false_accept", C.c_double),
+    ]
+
+
+class SurrogateFitParams(C.Structure):
+    _fields_ = [
+        ("n_pairs", C.c_int64),
+        ("n_holdout", C.c_int64),
+        ("steps", C.c_int32),
+        ("batch", C.c_int32),
+        ("lr", C.c_float),
+        ("seed", C.c_uint64),
+        ("depth", C.c_int32),
+        ("hidden_width", C.c_int32),
+        ("hidden_layers", C.c_int32),
+        ("use_base", C.c_int32),
+        ("mu_bar", C.c_float),
+        ("scale", C.c_float),
+        ("k", C.c_float),
+        ("miss_target", C.c_float),
+        ("accept_target", C.c_float),
+        ("min_level_kept", C.c_int64),
+        ("accept_leaves", C.c_int32),
+    ]
 
 
 class Params(C.Structure):
@@ -36,6 +75,7 @@ class Params(C.Structure):
         ("max_cells", C.c_int64),
         ("chunk_cells", C.c_int64),
         ("use_surrogate", C.c_int32),
+        ("tree", C.c_int32),
     ]
 
 
@@ -47,6 +87,7 @@ _SIGS = [
     ("isx_load_mlp", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_void_p),
                                C.POINTER(C.c_void_p), C.POINTER(C.c_int32)]),
     ("isx_unload_mlp", C.c_int, [C.c_void_p, C.c_int32]),
+    ("isx_set_activation", C.c_int, [C.c_void_p, C.c_int32, C.c_int]),
     ("isx_set_domain", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
     ("isx_set_isovalues", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_float)]),
     ("isx_propagate", C.c_int, [C.c_void_p, C.c_int32, C.c_int, C.c_int, C.c_int64, C.c_void_p, C.c_void_p,
@@ -90,6 +131,13 @@ _SIGS = [
     ("isx_surrogate_free", C.c_int, [C.c_void_p, C.c_int32]),
     ("isx_surrogate_partition", C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.c_float,
                                           C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("isx_surrogate_sample_cells", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_int32, C.c_int32,
+                                             C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("isx_surrogate_calibrate", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p,
+                                          C.c_void_p, C.c_void_p, C.c_int32, C.c_float, C.c_float, C.c_float,
+                                          C.c_int64, C.c_int32, C.POINTER(SurrogateCalibration)]),
+    ("isx_surrogate_fit", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(SurrogateFitParams),
+                                    C.POINTER(C.c_int32), C.POINTER(SurrogateCalibration), C.c_void_p]),
     ("isx_surrogate_save_file", C.c_int, [C.c_void_p, C.c_int32, C.c_char_p]),
     ("isx_surrogate_load_file", C.c_int, [C.c_void_p, C.c_char_p, C.c_int32, C.POINTER(C.c_int32)]),
     ("isx_get_profile", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double),

@@ -106,6 +106,8 @@ struct isx_ctx {
   Buf sp_pred, sp_fb, sp_idx, sp_pm, sp_c, sp_h, sp_out, sp_mask, sp_cnt, sp_tmp;
   Buf rc_flags, rc_fidx, rc_fmask;
   Buf cx_flags, cx_idx, cx_c, cx_h, cx_out, cx_out64, cx_cnt;
+  // surrogate training set and band calibration
+  Buf sp_vis, sp_vis_off, cal_pred, cal_unit, cal_part, cal_cnt, cal_vec, fit_c, fit_h, fit_t, fit_l, fit_loss;
   int64_t* h_count = nullptr;  // pinned
   Profiler prof;
   // batched extraction: worker contexts with their own stream and scratch;
@@ -259,6 +261,7 @@ isx_status run_propagate(isx_ctx* ctx, const Model& m, isx_method method, isx_pr
                          const float* centres, const float* halves, float* out, double* out64, int64_t chunk_req) {
   if (n <= 0) return ISX_OK;
   const bool marg = method == ISX_AA && ctx->aa_margin != 0;
+  if (marg && m.act != ISX_RELU) return fail(ctx, ISX_EUNSUPPORTED, "the AA rounding margin needs a ReLU net");
   if (prec == ISX_FP64) {
     const int64_t chunk = chunk_for<double>(ctx, m, n, chunk_req);
     PropWork<double> w;
@@ -277,6 +280,7 @@ isx_status run_propagate(isx_ctx* ctx, const Model& m, isx_method method, isx_pr
     return ISX_OK;
   }
   if (prec == ISX_BF16) {
+    if (m.act != ISX_RELU) return fail(ctx, ISX_EUNSUPPORTED, "bf16 propagation needs a ReLU net");
     if (!bf16_supported(m))
       return fail(ctx, ISX_EUNSUPPORTED, "bf16 propagation needs every hidden layer's input width <= 256");
     // the covariance form (UP) keeps each cell on chip: no coefficient blocks
@@ -401,7 +405,10 @@ isx_status isx_destroy(isx_ctx* ctx) {
                   &ctx->sp_tmp, &ctx->rc_flags, &ctx->rc_fidx, &ctx->rc_fmask};
   for (Buf* b : sbufs) release(*b);
   for (Buf& b : ctx->sur_act) release(b);
-  Buf* cbufs[] = {&ctx->cx_flags, &ctx->cx_idx, &ctx->cx_c, &ctx->cx_h, &ctx->cx_out, &ctx->cx_out64, &ctx->cx_cnt};
+  Buf* cbufs[] = {&ctx->cx_flags, &ctx->cx_idx, &ctx->cx_c,     &ctx->cx_h,     &ctx->cx_out,   &ctx->cx_out64,
+                  &ctx->cx_cnt,   &ctx->sp_vis, &ctx->sp_vis_off, &ctx->cal_pred, &ctx->cal_unit, &ctx->cal_part,
+                  &ctx->cal_cnt,  &ctx->cal_vec, &ctx->fit_c,     &ctx->fit_h,    &ctx->fit_t,    &ctx->fit_l,
+                  &ctx->fit_loss};
   for (Buf* b : cbufs) release(*b);
   for (int i = 0; i < (int)ctx->surs.size(); ++i) isx_surrogate_free(ctx, i);
   if (ctx->h_count) (void)hipHostFree(ctx->h_count);
@@ -610,6 +617,18 @@ isx_status isx_unload_mlp(isx_ctx* ctx, int32_t mlp_id) {
   return ISX_OK;
 }
 
+isx_status isx_set_activation(isx_ctx* ctx, int32_t mlp_id, isx_activation act) {
+  Model* m = get_model(ctx, mlp_id);
+  if (!m) return fail(ctx, ISX_EINVAL, "bad mlp id");
+  if (act != ISX_RELU && act != ISX_SINE && act != ISX_ELU) return fail(ctx, ISX_EINVAL, "unknown activation");
+  if (act != ISX_RELU)
+    for (const Sur& S : ctx->surs)
+      if (S.live && S.base_mlp == mlp_id)
+        return fail(ctx, ISX_EUNSUPPORTED, "a surrogate uses this MLP's centre linearisation, which needs ReLU");
+  m->act = act;
+  return ISX_OK;
+}
+
 isx_status isx_set_domain(isx_ctx* ctx, int32_t mlp_id, const float h_lo[3], const float h_hi[3]) {
   Model* m = get_model(ctx, mlp_id);
   if (!m || !h_lo || !h_hi) return fail(ctx, ISX_EINVAL, "bad mlp id or null domain");
@@ -639,7 +658,7 @@ isx_status isx_propagate(isx_ctx* ctx, int32_t mlp_id, isx_method method, isx_pr
                          const float* d_centres, const float* d_halves, float* d_out, double* d_out64) {
   Model* m = get_model(ctx, mlp_id);
   if (!m) return fail(ctx, ISX_EINVAL, "bad mlp id");
-  if (method != ISX_AA && method != ISX_UP) return fail(ctx, ISX_EINVAL, "unknown method");
+  if (method != ISX_AA && method != ISX_UP && method != ISX_RAUA) return fail(ctx, ISX_EINVAL, "unknown method");
   if (precision != ISX_FP32 && precision != ISX_BF16 && precision != ISX_FP64)
     return fail(ctx, ISX_EINVAL, "unknown precision");
   if (n_cells < 0) return fail(ctx, ISX_EINVAL, "n_cells < 0");
@@ -693,7 +712,8 @@ isx_status isx_classify_compact_noalloc(isx_ctx* ctx, int32_t mlp_id, float k, i
 
 // float32 point evaluation: FP32 MFMA, or the SIMT kernel when forced
 static hipError_t eval_f32(isx_ctx* ctx, const Model& m, int64_t n, const float* pts, float* vals, hipStream_t s) {
-  if (ctx->kernel_choice == 1) return eval_points_f32(m, n, pts, vals, s);
+  // (the MFMA forward pass is written for ReLU; other activations take the vector-ALU kernel)
+  if (ctx->kernel_choice == 1 || m.act != ISX_RELU) return eval_points_f32(m, n, pts, vals, s);
   double flops = 6.0 * m.widths[1] + 2.0 * m.widths[m.n_linear - 1];
   for (int h = 2; h < m.n_linear; ++h) flops += 2.0 * m.widths[h] * m.widths[h - 1];
   Profiler::Rec rec{};
@@ -739,6 +759,7 @@ isx_status isx_linearize(isx_ctx* ctx, int32_t mlp_id, int64_t n, const float* d
                          float* d_out) {
   Model* m = get_model(ctx, mlp_id);
   if (!m) return fail(ctx, ISX_EINVAL, "bad mlp id");
+  if (m->act != ISX_RELU) return fail(ctx, ISX_EUNSUPPORTED, "the centre linearisation needs a ReLU net");
   if (n < 0 || (n > 0 && (!d_centres || !d_halves || !d_out))) return fail(ctx, ISX_EINVAL, "bad arguments");
   if (n == 0) return ISX_OK;
   (void)hipSetDevice(ctx->device);
@@ -836,13 +857,22 @@ isx_status isx_extract(isx_ctx* ctx, int32_t mlp_id, const isx_params* p, isx_me
   if (!mp || !p || !out) return fail(ctx, ISX_EINVAL, "bad arguments");
   *out = nullptr;
   const Model& m = *mp;
-  if (p->method != ISX_AA && p->method != ISX_UP) return fail(ctx, ISX_EINVAL, "unknown method");
+  if (p->method != ISX_AA && p->method != ISX_UP && p->method != ISX_RAUA)
+    return fail(ctx, ISX_EINVAL, "unknown method");
   if (p->precision != ISX_FP32 && p->precision != ISX_BF16 && p->precision != ISX_FP64)
     return fail(ctx, ISX_EINVAL, "unknown precision");
   if (p->max_depth < 0 || p->max_depth > 10) return fail(ctx, ISX_EINVAL, "max_depth must be in [0, 10]");
   if (!(p->k >= 0.f) || !std::isfinite(p->k)) return fail(ctx, ISX_EINVAL, "k must be finite and >= 0");
   if (!(p->fp64_band >= 0.f)) return fail(ctx, ISX_EINVAL, "fp64_band must be >= 0");
   if (m.n_iso < 1) return fail(ctx, ISX_EINVAL, "no iso-values set");
+  if (p->tree != 0 && p->tree != 1) return fail(ctx, ISX_EINVAL, "tree must be 0 (octree) or 1 (k-d tree)");
+  const bool kd = p->tree == 1;
+  if (kd) {
+    if (p->use_surrogate) return fail(ctx, ISX_EUNSUPPORTED, "the k-d tree does not take the surrogate");
+    const double e0 = (double)m.hi[0] - m.lo[0];
+    if ((double)m.hi[1] - m.lo[1] != e0 || (double)m.hi[2] - m.lo[2] != e0)
+      return fail(ctx, ISX_EUNSUPPORTED, "the k-d tree needs a cube domain");
+  }
   (void)hipSetDevice(ctx->device);
   hipStream_t s = ctx->stream;
   const float k = p->method == ISX_AA ? 1.f : p->k;
@@ -870,8 +900,9 @@ isx_status isx_extract(isx_ctx* ctx, int32_t mlp_id, const isx_params* p, isx_me
 
   int64_t n_par = 0;
   int cur = 0;  // parents in act_*[cur]
-  for (int L = 0; L <= p->max_depth; ++L) {
-    const int64_t n = L == 0 ? 1 : 8 * n_par;
+  const int last_level = kd ? 3 * p->max_depth : p->max_depth;
+  for (int L = 0; L <= last_level; ++L) {
+    const int64_t n = L == 0 ? 1 : (kd ? 2 : 8) * n_par;
     if (n > cap)
       return bail(fail(ctx, ISX_ECAPACITY, "level " + std::to_string(L) + " has " + std::to_string(n) +
                                                " cells, above max_cells=" + std::to_string(cap)));
@@ -893,6 +924,9 @@ isx_status isx_extract(isx_ctx* ctx, int32_t mlp_id, const isx_params* p, isx_me
     uint32_t* mask = (uint32_t*)ctx->mask.p;
     if (L == 0) {
       XCHK(launch_root(m, full, ids, pmask, centres, halves, s));
+    } else if (kd) {
+      XCHK(launch_children_kd(m, L, n_par, (const uint32_t*)ctx->act_ids[cur].p,
+                              (const uint32_t*)ctx->act_mask[cur].p, ids, pmask, centres, halves, s));
     } else {
       XCHK(launch_children(m, L, n_par, (const uint32_t*)ctx->act_ids[cur].p, (const uint32_t*)ctx->act_mask[cur].p,
                            ids, pmask, centres, halves, s));
@@ -971,6 +1005,8 @@ isx_status isx_extract(isx_ctx* ctx, int32_t mlp_id, const isx_params* p, isx_me
     cur ^= 1;
     n_par = n_act;
   }
+  // k-d leaves (node depth 3 D) are octree cells of level D: Morton ids
+  if (kd) XCHK(launch_kd_to_morton(n_par, p->max_depth, (uint32_t*)ctx->act_ids[cur].p, s));
   XCHK(hipEventRecord(ev[1], s));
 
   // active leaves
@@ -1480,6 +1516,7 @@ isx_status isx_surrogate_set_base(isx_ctx* ctx, int32_t sur_id, int32_t mlp_id, 
   }
   const Model* m = get_model(ctx, mlp_id);
   if (!m) return fail(ctx, ISX_EINVAL, "bad mlp id");
+  if (m->act != ISX_RELU) return fail(ctx, ISX_EUNSUPPORTED, "the centre linearisation needs a ReLU net");
   if (!(s_floor > 0.f) || !std::isfinite(s_floor)) return fail(ctx, ISX_EINVAL, "s_floor must be finite and > 0");
   S->base_mlp = mlp_id;
   S->s_floor = s_floor;
@@ -1530,6 +1567,249 @@ isx_status isx_surrogate_partition(isx_ctx* ctx, int32_t mlp_id, int64_t n, cons
   HIPCHK(sur_partition(n, d_pred, d_unit, k, iso_list(*m), d_parent_mask, m->sur_err_mu[Ls], m->sur_err_ls[Ls],
                        m->sur_z[Ls], m->sur_z_acc[Ls], leaf ? 1 : 0, m->sur_accept_leaves, d_mask, d_fallback,
                        ctx->stream));
+  return ISX_OK;
+}
+
+
+// ------------------------------------------------ surrogate training set and bands
+isx_status isx_surrogate_sample_cells(isx_ctx* ctx, int32_t mlp_id, const isx_mesh* visited, int64_t n,
+                                      int32_t level_lo, int32_t level_hi, uint64_t seed, float* d_centres,
+                                      float* d_halves, int32_t* d_levels) {
+  Model* m = get_model(ctx, mlp_id);
+  if (!m) return fail(ctx, ISX_EINVAL, "bad mlp id");
+  if (n < 0 || level_lo < 0 || level_hi < level_lo || level_hi > 10 ||
+      (n > 0 && (!d_centres || !d_halves || !d_levels)))
+    return fail(ctx, ISX_EINVAL, "bad arguments");
+  if (visited && !visited->kept) return fail(ctx, ISX_EINVAL, "the visited mesh keeps no level cells (ISX_KEEP_LEVELS)");
+  if (n == 0) return ISX_OK;
+  (void)hipSetDevice(ctx->device);
+  std::vector<int64_t> off(1, 0);
+  int64_t total = 0;
+  if (visited) {
+    for (const auto& v : visited->lvl_ids) {
+      total += (int64_t)v.size();
+      off.push_back(total);
+    }
+  }
+  const int vis_levels = (int)off.size() - 1;
+  if (total > 0) {
+    HIPCHK(ensure(ctx->sp_vis, (size_t)total * 4));
+    HIPCHK(ensure(ctx->sp_vis_off, off.size() * sizeof(int64_t)));
+    for (int L = 0; L < vis_levels; ++L)
+      HIPCHK(hipMemcpyAsync((uint32_t*)ctx->sp_vis.p + off[L], visited->lvl_ids[L].data(),
+                            visited->lvl_ids[L].size() * 4, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->sp_vis_off.p, off.data(), off.size() * sizeof(int64_t), hipMemcpyHostToDevice,
+                          ctx->stream));
+  }
+  HIPCHK(launch_sample_cells(n, seed, m->lo, m->hi, level_lo, level_hi, total > 0 ? (const uint32_t*)ctx->sp_vis.p : nullptr,
+                             total > 0 ? (const int64_t*)ctx->sp_vis_off.p : nullptr, vis_levels, total, d_centres,
+                             d_halves, d_levels, ctx->stream));
+  // the host copies of the level ids must outlive the transfers
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return ISX_OK;
+}
+
+static const float kBandLadder[] = {0.f, 0.5f, 1.f, 1.5f, 2.f, 2.5f, 3.f, 3.5f, 4.f, 5.f, 6.f, 8.f, 12.f};
+static constexpr int kLadder = 13;
+static constexpr int kPruneFrom = 4;  // prune bands start at 2
+
+isx_status isx_surrogate_calibrate(isx_ctx* ctx, int32_t sur_id, int32_t mlp_id, int64_t n, const float* d_centres,
+                                   const float* d_halves, const float* d_targets, const int32_t* d_levels,
+                                   int32_t n_levels, float k, float miss_target, float accept_target,
+                                   int64_t min_level_kept, int32_t accept_leaves, isx_surrogate_calibration* cal) {
+  Sur* Sp = get_sur(ctx, sur_id);
+  Model* m = get_model(ctx, mlp_id);
+  if (!Sp || !m) return fail(ctx, ISX_EINVAL, "bad surrogate or mlp id");
+  if (n <= 0 || !d_centres || !d_halves || !d_targets || !d_levels || !cal || n_levels < 1 || n_levels > 16 ||
+      !(k >= 0.f) || !(miss_target >= 0.f) || !(accept_target >= 0.f) || min_level_kept < 0)
+    return fail(ctx, ISX_EINVAL, "bad calibration arguments");
+  if (m->n_iso < 1) return fail(ctx, ISX_EINVAL, "no iso-values set");
+  (void)hipSetDevice(ctx->device);
+  hipStream_t s = ctx->stream;
+  Sur& S = *Sp;
+  const bool based = S.base_mlp >= 0;
+  HIPCHK(ensure(ctx->cal_pred, (size_t)n * 8));
+  if (based) HIPCHK(ensure(ctx->cal_unit, (size_t)n * 4));
+  float* pred = (float*)ctx->cal_pred.p;
+  float* unit = based ? (float*)ctx->cal_unit.p : nullptr;
+  isx_status st = sur_predict_n(ctx, S, n, d_centres, d_halves, pred, unit);
+  if (st != ISX_OK) return st;
+  // 1. per-level RMS errors (block partials added in order on the host)
+  const int64_t nb = std::min<int64_t>(1024, (n + 255) / 256);
+  HIPCHK(ensure(ctx->cal_part, (size_t)nb * n_levels * 3 * sizeof(double)));
+  HIPCHK(launch_calib_err(n, pred, d_targets, unit, d_levels, n_levels, (double*)ctx->cal_part.p, nb, s));
+  std::vector<double> part((size_t)nb * n_levels * 3);
+  HIPCHK(hipMemcpyAsync(part.data(), ctx->cal_part.p, part.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::memset(cal, 0, sizeof(*cal));
+  cal->n_levels = n_levels;
+  for (int L = 0; L < n_levels; ++L) {
+    double sm = 0.0, sl = 0.0, cnt = 0.0;
+    for (int64_t b = 0; b < nb; ++b) {
+      const double* q = &part[((size_t)b * n_levels + L) * 3];
+      sm += q[0];
+      sl += q[1];
+      cnt += q[2];
+    }
+    cal->n_cells[L] = (int64_t)cnt;
+    if (cnt < 50.0) {  // too few held-out cells: the previous level's error
+      cal->err_mu[L] = L > 0 ? cal->err_mu[L - 1] : S.scale;
+      cal->err_logsig[L] = L > 0 ? cal->err_logsig[L - 1] : 1.f;
+    } else {
+      cal->err_mu[L] = (float)std::sqrt(sm / cnt);
+      cal->err_logsig[L] = (float)std::sqrt(sl / cnt);
+    }
+  }
+  // 2. counts per (level, band) of misses and false accepts, and of kept cells
+  const size_t ncnt = (size_t)n_levels * kLadder * 2;
+  HIPCHK(ensure(ctx->cal_cnt, (ncnt + 16) * sizeof(unsigned long long)));
+  HIPCHK(ensure(ctx->cal_vec, 3 * 16 * sizeof(float)));
+  float hv[48];
+  for (int i = 0; i < 16; ++i) {
+    hv[i] = i < n_levels ? cal->err_mu[i] : 0.f;
+    hv[16 + i] = i < n_levels ? cal->err_logsig[i] : 0.f;
+    hv[32 + i] = i < kLadder ? kBandLadder[i] : 0.f;
+  }
+  unsigned long long* dcnt = (unsigned long long*)ctx->cal_cnt.p;
+  HIPCHK(hipMemcpyAsync(ctx->cal_vec.p, hv, sizeof(hv), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemsetAsync(dcnt, 0, (ncnt + 16) * sizeof(unsigned long long), s));
+  const float* dv = (const float*)ctx->cal_vec.p;
+  HIPCHK(launch_calib_count(n, pred, d_targets, unit, d_levels, n_levels, k, iso_list(*m), dv, dv + 16, dv + 32,
+                            kLadder, dcnt, dcnt + ncnt, s));
+  std::vector<unsigned long long> cnt(ncnt + 16);
+  HIPCHK(hipMemcpyAsync(cnt.data(), dcnt, cnt.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  auto miss = [&](int L, int zi) { return (double)cnt[((size_t)L * kLadder + zi) * 2 + 0]; };
+  auto fals = [&](int L, int zi) { return (double)cnt[((size_t)L * kLadder + zi) * 2 + 1]; };
+  double kept_all = 0.0;
+  for (int L = 0; L < n_levels; ++L) {
+    cal->kept[L] = (int64_t)cnt[ncnt + L];
+    kept_all += (double)cal->kept[L];
+  }
+  const double den = std::max(kept_all, 1.0);
+  // 3. the smallest band of the ladder whose rate meets the target, over all
+  //    levels, then per level where enough held-out cells are kept
+  int zg = kLadder - 1, zag = kLadder - 1;
+  for (int zi = kPruneFrom; zi < kLadder; ++zi) {
+    double mm = 0.0;
+    for (int L = 0; L < n_levels; ++L) mm += miss(L, zi);
+    if (mm / den <= miss_target) {
+      zg = zi;
+      break;
+    }
+  }
+  for (int zi = 0; zi < kLadder; ++zi) {
+    double ff = 0.0;
+    for (int L = 0; L < n_levels; ++L) ff += fals(L, zi);
+    if (ff / den <= accept_target) {
+      zag = zi;
+      break;
+    }
+  }
+  cal->z_global = kBandLadder[zg];
+  cal->z_accept_global = kBandLadder[zag];
+  int zl[16], zal[16];
+  double hm = 0.0, hf = 0.0;
+  for (int L = 0; L < n_levels; ++L) {
+    zl[L] = zg;
+    zal[L] = zag;
+    if (cal->n_cells[L] > 0 && cal->kept[L] >= std::max<int64_t>(min_level_kept, 1)) {
+      const double kl = (double)cal->kept[L];
+      zl[L] = kLadder - 1;
+      for (int zi = kPruneFrom; zi < kLadder; ++zi)
+        if (miss(L, zi) / kl <= miss_target) {
+          zl[L] = zi;
+          break;
+        }
+      zal[L] = kLadder - 1;
+      for (int zi = 0; zi < kLadder; ++zi)
+        if (fals(L, zi) / kl <= accept_target) {
+          zal[L] = zi;
+          break;
+        }
+    }
+    cal->z[L] = kBandLadder[zl[L]];
+    cal->z_accept[L] = kBandLadder[zal[L]];
+    hm += miss(L, zl[L]);
+    hf += fals(L, zal[L]);
+  }
+  cal->holdout_miss = hm / den;
+  cal->holdout_false_accept = hf / den;
+  return isx_surrogate_attach(ctx, mlp_id, sur_id, n_levels, cal->err_mu, cal->err_logsig, cal->z, cal->z_accept,
+                              accept_leaves);
+}
+
+isx_status isx_surrogate_fit(isx_ctx* ctx, int32_t mlp_id, const isx_mesh* visited, const isx_surrogate_fit_params* p,
+                             int32_t* sur_id, isx_surrogate_calibration* cal, float* h_loss) {
+  Model* m = get_model(ctx, mlp_id);
+  if (!m || !p || !sur_id || !cal) return fail(ctx, ISX_EINVAL, "bad arguments");
+  if (p->n_pairs < 1 || p->n_holdout < 1 || p->steps < 0 || p->batch < 1 || !(p->lr > 0.f) || p->depth < 0 ||
+      p->depth > 10 || p->hidden_width < 1 || p->hidden_width > ISX_MAX_WIDTH || p->hidden_layers < 1 ||
+      p->hidden_layers + 1 > ISX_MAX_LINEAR || !(p->scale > 0.f) || !std::isfinite(p->mu_bar))
+    return fail(ctx, ISX_EINVAL, "bad surrogate fit parameters");
+  (void)hipSetDevice(ctx->device);
+  *sur_id = -1;
+  const int64_t n = p->n_pairs + p->n_holdout;
+  HIPCHK(ensure(ctx->fit_c, (size_t)n * 12));
+  HIPCHK(ensure(ctx->fit_h, (size_t)n * 12));
+  HIPCHK(ensure(ctx->fit_t, (size_t)n * 8));
+  HIPCHK(ensure(ctx->fit_l, (size_t)n * 4));
+  float* C = (float*)ctx->fit_c.p;
+  float* H = (float*)ctx->fit_h.p;
+  float* T = (float*)ctx->fit_t.p;
+  int32_t* Lv = (int32_t*)ctx->fit_l.p;
+  // 1. cells: visited cells and uniform random cells of levels min(3, D)..D
+  isx_status st = isx_surrogate_sample_cells(ctx, mlp_id, visited, n, std::min(3, p->depth), p->depth, p->seed, C, H, Lv);
+  if (st != ISX_OK) return st;
+  // 2. targets: float32 uncertainty propagation of every cell
+  st = run_propagate(ctx, *m, ISX_UP, ISX_FP32, n, C, H, T, nullptr, 0);
+  if (st != ISX_OK) return st;
+  // 3. network 4 -> hidden^layers -> 2, He-normal weights N(0, 2/fan_in),
+  //    biases N(0, (0.1 std)^2), from SplitMix64 streams of the seed
+  std::vector<int32_t> widths(p->hidden_layers + 2, p->hidden_width);
+  widths.front() = 4;
+  widths.back() = 2;
+  const int nl = (int)widths.size() - 1;
+  std::vector<std::vector<float>> Ws(nl), bs(nl);
+  std::vector<const float*> Wp(nl), bp(nl);
+  for (int l = 0; l < nl; ++l) {
+    const float sd = std::sqrt(2.f / (float)widths[l]);
+    Ws[l].resize((size_t)widths[l] * widths[l + 1]);
+    bs[l].resize(widths[l + 1]);
+    host_normal_fill(p->seed ^ (0xA5A5A5A5ull * (uint64_t)(2 * l + 1)), sd, Ws[l].data(), (int64_t)Ws[l].size());
+    host_normal_fill(p->seed ^ (0xA5A5A5A5ull * (uint64_t)(2 * l + 2)), 0.1f * sd, bs[l].data(), (int64_t)bs[l].size());
+    Wp[l] = Ws[l].data();
+    bp[l] = bs[l].data();
+  }
+  int32_t sid = -1;
+  st = isx_surrogate_load(ctx, nl, widths.data(), Wp.data(), bp.data(), &sid);
+  if (st != ISX_OK) return st;
+  auto undo = [&](isx_status e) {
+    isx_surrogate_free(ctx, sid);
+    return e;
+  };
+  st = isx_surrogate_set_norm(ctx, sid, p->mu_bar, p->scale, 0.25f, 1.f);
+  if (st == ISX_OK && p->use_base) st = isx_surrogate_set_base(ctx, sid, mlp_id, 1e-6f * p->scale);
+  if (st != ISX_OK) return undo(st);
+  // 4. training on the first n_pairs cells
+  float* dloss = nullptr;
+  if (h_loss && p->steps > 0) {
+    HIPCHK(ensure(ctx->fit_loss, (size_t)p->steps * 4));
+    dloss = (float*)ctx->fit_loss.p;
+  }
+  st = isx_surrogate_train(ctx, sid, p->n_pairs, C, H, T, 0, p->steps, p->batch, p->lr, dloss);
+  if (st != ISX_OK) return undo(st);
+  if (dloss) {
+    hipError_t e = hipMemcpyAsync(h_loss, dloss, (size_t)p->steps * 4, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return undo(hip_fail(ctx, e, "surrogate loss copy"));
+  }
+  // 5. bands calibrated on the held-out cells, then attached to the MLP
+  const int64_t o = p->n_pairs;
+  st = isx_surrogate_calibrate(ctx, sid, mlp_id, p->n_holdout, C + 3 * o, H + 3 * o, T + 2 * o, Lv + o, p->depth + 1,
+                               p->k, p->miss_target, p->accept_target, p->min_level_kept, p->accept_leaves, cal);
+  if (st != ISX_OK) return undo(st);
+  *sur_id = sid;
   return ISX_OK;
 }
 

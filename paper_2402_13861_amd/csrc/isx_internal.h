@@ -124,6 +124,7 @@ struct Model {
   float lo[3] = {-1.f, -1.f, -1.f}, hi[3] = {1.f, 1.f, 1.f};
   int n_iso = 0;
   float iso[ISX_MAX_ISO] = {};
+  int act = ISX_RELU;  // hidden activation (isx_activation)
   // surrogate attached for extraction (-1 = none)
   int sur_id = -1;
   int sur_levels = 0;
@@ -160,6 +161,7 @@ struct PropWork {
 template <typename T>
 struct NetView {
   int n_linear;
+  int act;  // hidden activation (isx_activation)
   int n[ISX_MAX_LINEAR + 1];  // padded widths
   const T* W[ISX_MAX_LINEAR];
   const T* b[ISX_MAX_LINEAR];
@@ -327,6 +329,13 @@ hipError_t launch_root(const Model& m, uint32_t full_mask, uint32_t* ids, uint32
 hipError_t launch_children(const Model& m, int level, int64_t n_par, const uint32_t* par_ids,
                            const uint32_t* par_masks, uint32_t* ids, uint32_t* pmask, float* centres,
                            float* halves, hipStream_t s);
+// k-d tree of Alg. 1 on a cube domain (split axes x, y, z in turn): the 2
+// children of each parent at node depth `depth`, and the conversion of depth
+// 3 D node ids to octree Morton ids of level D
+hipError_t launch_children_kd(const Model& m, int depth, int64_t n_par, const uint32_t* par_ids,
+                              const uint32_t* par_masks, uint32_t* ids, uint32_t* pmask, float* centres,
+                              float* halves, hipStream_t s);
+hipError_t launch_kd_to_morton(int64_t n, int levels, uint32_t* ids, hipStream_t s);
 hipError_t launch_classify(int64_t n, const float* out, float k, const IsoList& iso, const uint32_t* pmask,
                            uint32_t* mask, hipStream_t s);
 // Stable compaction of the entries with mask != 0: writes (ids ? ids[i] : i)
@@ -385,6 +394,18 @@ hipError_t sur_partition(int64_t n, const float* pred, const float* mu_unit, flo
 hipError_t gather_u32(int64_t n, const uint32_t* idx, const uint32_t* src, uint32_t* dst, hipStream_t s);
 hipError_t scatter_u32(int64_t n, const uint32_t* idx, const uint32_t* src, uint32_t* dst, hipStream_t s);
 hipError_t scatter_u64(int64_t n, const uint32_t* idx, const uint64_t* src, uint64_t* dst, hipStream_t s);
+
+// ---- surrogate training set and band calibration (kernels_calib.hip) ----
+hipError_t launch_sample_cells(int64_t n, uint64_t seed, const float lo[3], const float hi[3], int level_lo,
+                               int level_hi, const uint32_t* vis_ids, const int64_t* vis_off, int vis_levels,
+                               int64_t vis_total, float* centres, float* halves, int32_t* levels, hipStream_t s);
+hipError_t launch_calib_err(int64_t n, const float* pred, const float* targ, const float* unit, const int32_t* levels,
+                            int n_levels, double* partial, int64_t n_blocks, hipStream_t s);
+hipError_t launch_calib_count(int64_t n, const float* pred, const float* targ, const float* unit, const int32_t* levels,
+                              int n_levels, float k, const IsoList& iso, const float* err_mu, const float* err_ls,
+                              const float* ladder, int n_z, unsigned long long* counts, unsigned long long* kept,
+                              hipStream_t s);
+void host_normal_fill(uint64_t seed, float stddev, float* out, int64_t n);
 
 // ---- marching-cubes case table (mc_table.cpp) ----
 struct McTable {

@@ -26,6 +26,7 @@
 // 8*(l/32)+e), B elements (k 8*(l/32)+e, column l%32), e = 0..7; accumulator
 // register r holds (row 8*(r/4) + 4*(l/32) + r%4, column l%32).
 #include "isx_internal.h"
+#include "rules.h"
 
 #include <algorithm>
 
@@ -39,42 +40,6 @@ __device__ __forceinline__ float bstat(float v) {
   return METHOD == ISX_UP ? v * v : fabsf(v);
 }
 
-template <int METHOD>
-__device__ __forceinline__ void relu_rule_bf(float y, float stat, float& a, float& b, float& g) {
-  if (METHOD == ISX_UP) {
-    const float sigma = sqrtf(stat);
-    const float ay = fabsf(y);
-    if (!(sigma > 1e-30f * (ay > 1.f ? ay : 1.f))) {
-      a = y > 0.f ? 1.f : (y < 0.f ? 0.f : 0.5f);
-      b = 0.f;
-      g = 0.f;
-      return;
-    }
-    const float r = y / sigma;
-    const float Phi = 0.5f * erfcf(-r * 0.70710678118654752440f);
-    const float Q = 0.5f * erfcf(r * 0.70710678118654752440f);
-    const float phi = 0.39894228040143267794f * expf(-0.5f * r * r);
-    a = Phi;
-    b = sigma * phi;
-    const float g2 = sigma * sigma * ((r * r + 1.f) * Phi * Q + r * phi * (Q - Phi) - phi * phi);
-    g = g2 > 0.f ? sqrtf(g2) : 0.f;
-  } else {
-    const float l = y - stat, u = y + stat;
-    if (u <= 0.f) {
-      a = 0.f;
-      b = 0.f;
-      g = 0.f;
-    } else if (l >= 0.f) {
-      a = 1.f;
-      b = 0.f;
-      g = 0.f;
-    } else {
-      a = u / (u - l);
-      b = -a * l * 0.5f;
-      g = b;
-    }
-  }
-}
 
 // ------------------------------------------------------------- layer 1
 template <int METHOD>
@@ -98,7 +63,7 @@ __global__ void layer1_bf16_kernel(int64_t C, int n, const float* __restrict__ c
     stat += bstat<METHOD>(f[i]);
   }
   float a, b, g;
-  relu_rule_bf<METHOD>(y, stat, a, b, g);
+  apply_rule<float, METHOD>(ISX_RELU, y, stat, a, b, g);
   Y[idx] = y;
   A[idx] = a;
   B[idx] = b;
@@ -348,7 +313,7 @@ __global__ __launch_bounds__(64 * NW) void hidden_mfma_bf16_kernel(
   for (int m = t; m < BM; m += THREADS) {
     const float tot = s_row[m] + s_gen[m];
     float a, b, gg;
-    relu_rule_bf<METHOD>(s_y[m], tot, a, b, gg);
+    apply_rule<float, METHOD>(ISX_RELU, s_y[m], tot, a, b, gg);
     const int64_t o = cell * n_out + m0 + m;
     Y[o] = s_y[m];
     A[o] = a;
@@ -466,6 +431,7 @@ hipError_t propagate_bf16(const PropArgs& a, PropWork<float>& w, uint16_t* Fbf_r
   // AA rounding margin (kernels_margin.hip): bfloat16 operands from layer 2
   // on (u_b = 2^-8), float32 accumulation; the row statistics S and radii R
   // follow the four vectors of every layer in the vector buffer
+  // (RA-UA runs the AA layers below and reads off with the uniform assumption)
   const bool marg = a.method == ISX_AA && a.aa_margin;
   float *S[ISX_MAX_LINEAR] = {}, *R[ISX_MAX_LINEAR] = {};
   if (marg) {
@@ -540,7 +506,8 @@ hipError_t propagate_bf16(const PropArgs& a, PropWork<float>& w, uint16_t* Fbf_r
                                             4.0 * C * 4.0 * (double)m.pw[1] * Lh, a.stream);
   // (UP: the read-off on BF16 MFMA with hi/lo splits where the widths allow;
   // AA keeps the float32 read-off, which the rounding margin assumes)
-  hipError_t e = a.kernel_choice == 1 ? launch_output_f32(m, a.method, C, w.vec, a.halves, a.out32, a.stream)
+  hipError_t e = (a.kernel_choice == 1 || a.method == ISX_RAUA)
+                     ? launch_output_f32(m, a.method, C, w.vec, a.halves, a.out32, a.stream)
                  : (a.method == ISX_UP && output_bf16_supported(m))
                      ? launch_output_bf16(m, C, Y, A, B, G, a.halves, a.out32, a.stream)
                      : launch_output_mfma(m, a.method, C, Y, A, B, G, a.halves, a.out32, a.stream);

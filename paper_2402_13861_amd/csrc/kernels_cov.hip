@@ -46,13 +46,15 @@
 // bfloat16 rounding of about 2^-8 per entry, so a sum that keeps only a
 // small part of its terms' magnitude can lose every digit or turn negative).
 // Step 3 also sums |T[j][i] W[j][i]|; a neuron whose variance is not above
-// kCancelRatio times that magnitude marks its cell, and the host
-// re-propagates marked cells in float64.  Layers 1 and 2 sum squares and
-// cannot cancel.
+// kCancelRatio times that magnitude, and whose pre-activation lies within 6
+// of its largest plausible sigma (so that its rule depends on sigma), marks
+// its cell, and the host re-propagates marked cells in float64.  Layers 1
+// and 2 sum squares and cannot cancel.
 // MFMA 32x32x16 bf16 layout (lane l): A (row l%32, k 8(l/32)+e), B (k
 // 8(l/32)+e, column l%32), e = 0..7; accumulator register r holds (row
 // 8(r/4) + 4(l/32) + r%4, column l%32).
 #include "isx_internal.h"
+#include "rules.h"
 
 #include <algorithm>
 
@@ -145,28 +147,6 @@ __device__ __forceinline__ void cov_store_vec(float* v, int64_t C, int n, int64_
   v[3 * NC + o] = g;
 }
 
-// Gaussian least-squares ReLU rule (App. D ReLU row, erfc form, clamped).
-__device__ __forceinline__ void cov_relu_rule(float y, float var, float& a, float& b, float& g) {
-  const float sigma = sqrtf(fmaxf(var, 0.f));
-  const float ay = fabsf(y);
-  if (!(sigma > 1e-30f * (ay > 1.f ? ay : 1.f))) {
-    a = y > 0.f ? 1.f : (y < 0.f ? 0.f : 0.5f);
-    b = 0.f;
-    g = 0.f;
-    return;
-  }
-  const float r = y / sigma;
-  // one tail: the smaller of Phi(r) and Q(r) = 1 - Phi(r) from erfc, the
-  // larger as its complement
-  const float tail = 0.5f * erfcf(fabsf(r) * 0.70710678118654752440f);
-  const float Phi = r >= 0.f ? 1.f - tail : tail;
-  const float Q = r >= 0.f ? tail : 1.f - tail;
-  const float phi = 0.39894228040143267794f * expf(-0.5f * r * r);
-  a = Phi;
-  b = sigma * phi;
-  const float g2 = sigma * sigma * ((r * r + 1.f) * Phi * Q + r * phi * (Q - Phi) - phi * phi);
-  g = g2 > 0.f ? sqrtf(g2) : 0.f;
-}
 
 // Sum over the 4 lanes of a quad (all four active), via DPP quad permutes.
 __device__ __forceinline__ float quad_sum(float x) {
@@ -227,7 +207,7 @@ __global__ __launch_bounds__(kCovThreads) void up_cov_bf16_kernel(int64_t C, int
       const float y = b1[j] + w0 * centres[cell * 3 + 0] + w1 * centres[cell * 3 + 1] + w2 * centres[cell * 3 + 2];
       const float f0 = w0 * hx, f1 = w1 * hy, f2 = w2 * hz;
       float a, b, g;
-      cov_relu_rule(y, f0 * f0 + f1 * f1 + f2 * f2, a, b, g);
+      up_rule<float>(ISX_RELU, y, f0 * f0 + f1 * f1 + f2 * f2, a, b, g);
       s_alpha[j] = a;
       s_z[j] = a * y + b;
       s_gamma[j] = g;
@@ -330,7 +310,7 @@ __global__ __launch_bounds__(kCovThreads) void up_cov_bf16_kernel(int64_t C, int
           float a, b, g;
           const float y = sel[0] + ((gfloat*)Lw.b)[j];
           const float v = sel[1] * sel[1] + sel[2] * sel[2] + sel[3] * sel[3] + sel[4];
-          cov_relu_rule(y, v, a, b, g);
+          up_rule<float>(ISX_RELU, y, v, a, b, g);
           s_var[j] = v;
           s_alpha[j] = a;
           s_zout[j] = a * y + b;
@@ -431,10 +411,15 @@ __global__ __launch_bounds__(kCovThreads) void up_cov_bf16_kernel(int64_t C, int
             yc += p.y;
             av += p.z;
           }
-          if (av > 0.f && !(v > kCancelRatio * av)) s_cancel = 1u;
           float a, b, g;
           const float y = yc + ((gfloat*)Lw.b)[j];
-          cov_relu_rule(y, v, a, b, g);
+          // a cancelled sum matters only where the rule depends on sigma:
+          // beyond 6 sigma (taken at its largest with the terms' rounding,
+          // sqrt(v + 2^-7 sum |terms|)) alpha is 0 or 1 and beta, gamma vanish
+          // to float32 accuracy whatever sigma is
+          if (av > 0.f && !(v > kCancelRatio * av) && fabsf(y) < 6.f * sqrtf(fmaxf(v, 0.f) + 0x1p-7f * av))
+            s_cancel = 1u;
+          up_rule<float>(ISX_RELU, y, v, a, b, g);
           s_var[j] = v;
           s_alpha[j] = a;
           s_zout[j] = a * y + b;

@@ -91,6 +91,91 @@ hipError_t launch_children(const Model& m, int level, int64_t n_par, const uint3
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------ k-d tree
+// Alg. 1's own tree: every node is split in two along its widest dimension,
+// ties broken x, then y, then z.  On a cube domain all nodes of a depth have
+// the same shape and the split axes cycle x, y, z, so node (depth l, id) --
+// children 2 id (lower half) and 2 id + 1 (upper half) -- has, read from the
+// top of its l bits, one side bit per split, split s along axis s mod 3.
+struct KdDomain {
+  double lo[3];
+  double ext[3];  // hi - lo
+};
+
+__device__ __forceinline__ void kd_box(uint32_t id, int depth, const KdDomain& d, float* c, float* h) {
+  uint32_t ijk[3] = {0u, 0u, 0u};
+  int cnt[3] = {0, 0, 0};
+  for (int s = 0; s < depth; ++s) {
+    const int a = s % 3;
+    ijk[a] = (ijk[a] << 1) | ((id >> (depth - 1 - s)) & 1u);
+    ++cnt[a];
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double step = d.ext[a] / (double)(2ull << cnt[a]);  // half the node size along a
+    c[a] = (float)(d.lo[a] + (double)(2 * ijk[a] + 1) * step);
+    h[a] = (float)step;
+  }
+}
+
+__global__ void children_kd_kernel(int64_t n_par, const uint32_t* __restrict__ par_ids,
+                                   const uint32_t* __restrict__ par_masks, int depth, KdDomain d,
+                                   uint32_t* __restrict__ ids, uint32_t* __restrict__ pmask,
+                                   float* __restrict__ centres, float* __restrict__ halves) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * n_par) return;
+  const int64_t p = i >> 1;
+  const uint32_t id = (par_ids[p] << 1) | (uint32_t)(i & 1);
+  ids[i] = id;
+  pmask[i] = par_masks[p];
+  float c[3], h[3];
+  kd_box(id, depth, d, c, h);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    centres[i * 3 + a] = c[a];
+    halves[i * 3 + a] = h[a];
+  }
+}
+
+static KdDomain make_kd_domain(const Model& m) {
+  KdDomain d;
+  for (int a = 0; a < 3; ++a) {
+    d.lo[a] = m.lo[a];
+    d.ext[a] = (double)m.hi[a] - (double)m.lo[a];
+  }
+  return d;
+}
+
+hipError_t launch_children_kd(const Model& m, int depth, int64_t n_par, const uint32_t* par_ids,
+                              const uint32_t* par_masks, uint32_t* ids, uint32_t* pmask, float* centres,
+                              float* halves, hipStream_t s) {
+  if (n_par <= 0) return hipSuccess;
+  const int64_t n = 2 * n_par;
+  hipLaunchKernelGGL(children_kd_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n_par, par_ids,
+                     par_masks, depth, make_kd_domain(m), ids, pmask, centres, halves);
+  return hipGetLastError();
+}
+
+// k-d node ids of depth 3 D -> octree Morton ids of level D (x bit lowest):
+// each triple of k-d bits holds the (x, y, z) sides from the top.
+__global__ void kd_to_morton_kernel(int64_t n, int levels, uint32_t* __restrict__ ids) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t v = ids[i];
+  uint32_t out = 0;
+  for (int q = 0; q < levels; ++q) {
+    const uint32_t t = (v >> (3 * q)) & 7u;
+    out |= (((t >> 2) & 1u) | (((t >> 1) & 1u) << 1) | ((t & 1u) << 2)) << (3 * q);
+  }
+  ids[i] = out;
+}
+
+hipError_t launch_kd_to_morton(int64_t n, int levels, uint32_t* ids, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kd_to_morton_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, levels, ids);
+  return hipGetLastError();
+}
+
 // Soft/hard bound test of Alg. 1 for every iso-value; the interval is
 // closed (a bound touching c keeps the cell).
 __global__ void classify_kernel(int64_t n, const float* __restrict__ out, float k, IsoList iso,

@@ -35,24 +35,10 @@
 // c_out = (n_linear + 1) g_{Kmax+1}, plus 4 u_32 (|x0| + r) so that a float32
 // read-off x0 -/+ r still contains the range.
 #include "isx_internal.h"
+#include "rules.h"
 
 namespace isx {
 
-// Chebyshev rule of affine arithmetic for ReLU on [y - r, y + r] (Eq. 4).
-template <typename T>
-__device__ __forceinline__ void aa_rule(T y, T r, T& a, T& b, T& g) {
-  const T l = y - r, u = y + r;
-  if (u <= T(0)) {
-    a = b = g = T(0);
-  } else if (l >= T(0)) {
-    a = T(1);
-    b = g = T(0);
-  } else {
-    a = u / (u - l);
-    b = -a * l * T(0.5);
-    g = b;
-  }
-}
 
 // (sum_k |W_jk| R_k, sum_k |W_jk| |z_k| + |b_j|) for the input form of a
 // layer: the previous hidden layer's post-rule vectors, or for layer 1 the
@@ -100,7 +86,7 @@ __global__ void aa_margin_hidden_kernel(int64_t C, int n_in, int n_out, const T*
   const T y = Y[idx];
   const T r = S[idx] * k.infl_s + m;
   T a, b, g;
-  aa_rule<T>(y, r, a, b, g);
+  aa_rule_act<T>(ISX_RELU, y, r, a, b, g);
   g = g + a * m + k.slack * (a * (fabs(y) + r) + fabs(b));
   A[idx] = a;
   B[idx] = b;

@@ -20,6 +20,7 @@
 // consecutive on the same XCD (blocks are dealt to the 8 XCDs round-robin),
 // letting the second row block find the cell's coefficients in that XCD's L2.
 #include "isx_internal.h"
+#include "rules.h"
 
 namespace isx {
 
@@ -30,43 +31,6 @@ __device__ __forceinline__ float mstat(float v) {
   return METHOD == ISX_UP ? v * v : fabsf(v);
 }
 
-// same rule as the SIMT path (kept local to this translation unit)
-template <int METHOD>
-__device__ __forceinline__ void relu_rule_f32(float y, float stat, float& a, float& b, float& g) {
-  if (METHOD == ISX_UP) {
-    const float sigma = sqrtf(stat);
-    const float ay = fabsf(y);
-    if (!(sigma > 1e-30f * (ay > 1.f ? ay : 1.f))) {
-      a = y > 0.f ? 1.f : (y < 0.f ? 0.f : 0.5f);
-      b = 0.f;
-      g = 0.f;
-      return;
-    }
-    const float r = y / sigma;
-    const float Phi = 0.5f * erfcf(-r * 0.70710678118654752440f);
-    const float Q = 0.5f * erfcf(r * 0.70710678118654752440f);
-    const float phi = 0.39894228040143267794f * expf(-0.5f * r * r);
-    a = Phi;
-    b = sigma * phi;
-    const float g2 = sigma * sigma * ((r * r + 1.f) * Phi * Q + r * phi * (Q - Phi) - phi * phi);
-    g = g2 > 0.f ? sqrtf(g2) : 0.f;
-  } else {
-    const float l = y - stat, u = y + stat;
-    if (u <= 0.f) {
-      a = 0.f;
-      b = 0.f;
-      g = 0.f;
-    } else if (l >= 0.f) {
-      a = 1.f;
-      b = 0.f;
-      g = 0.f;
-    } else {
-      a = u / (u - l);
-      b = -a * l * 0.5f;
-      g = b;
-    }
-  }
-}
 
 template <int BM>
 struct Cfg {
@@ -87,7 +51,7 @@ __global__ __launch_bounds__(512) void hidden_mfma_f32_kernel(
     int64_t C, int n_in, int n_out, int64_t cols_in, int rb_count, const float* __restrict__ Wt,
     const float* __restrict__ bias, const float* __restrict__ Fin, const float* __restrict__ Ain,
     const float* __restrict__ Bin, const float* __restrict__ Gin, float* __restrict__ Fout, float* __restrict__ Y,
-    float* __restrict__ A, float* __restrict__ B, float* __restrict__ G, float* __restrict__ S) {
+    float* __restrict__ A, float* __restrict__ B, float* __restrict__ G, float* __restrict__ S, int act) {
   using K = Cfg<BM>;
   __shared__ float As[K::KT * K::ASTR];
   __shared__ float Bs[K::KT * K::BSTR];
@@ -304,7 +268,7 @@ __global__ __launch_bounds__(512) void hidden_mfma_f32_kernel(
 #pragma unroll
     for (int g = 0; g < K::G; ++g) tot += s_gen[g][t];
     float a, b, gg;
-    relu_rule_f32<METHOD>(s_y[t], tot, a, b, gg);
+    apply_rule<float, METHOD>(act, s_y[t], tot, a, b, gg);
     const int64_t o = cell * n_out + m0 + t;
     Y[o] = s_y[t];
     A[o] = a;
@@ -323,11 +287,11 @@ bool mfma_supported(const Model& m) {
 template <int METHOD, int BM>
 static void launch_bm(int64_t C, int n_in, int n_out, int64_t cols_in, const float* Wt, const float* bias,
                       const float* Fin, const float* Ain, const float* Bin, const float* Gin, float* Fout, float* Y,
-                      float* A, float* B, float* G, float* S, hipStream_t s) {
+                      float* A, float* B, float* G, float* S, int act, hipStream_t s) {
   const int rb_count = n_out / BM;
   const int64_t blocks = ((C + 7) / 8) * 8 * rb_count;
   hipLaunchKernelGGL((hidden_mfma_f32_kernel<METHOD, BM>), dim3((unsigned)blocks), dim3(Cfg<BM>::THREADS), 0, s, C,
-                     n_in, n_out, cols_in, rb_count, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S);
+                     n_in, n_out, cols_in, rb_count, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, act);
 }
 
 hipError_t launch_hidden_mfma_f32(int method, int64_t C, int n_in, int n_out, int64_t cols_in, const float* Wt,
@@ -336,15 +300,18 @@ hipError_t launch_hidden_mfma_f32(int method, int64_t C, int n_in, int n_out, in
                                   hipStream_t s) {
   if (C <= 0) return hipSuccess;
   if (n_out % 32 != 0 || n_in % 32 != 0 || n_in > ISX_MAX_WIDTH) return hipErrorInvalidValue;
+  // method: the propagation method in the low 4 bits, the activation above
+  const int act = method >> 4;
+  method &= 15;
   const int bm = n_out % 128 == 0 ? 128 : (n_out % 64 == 0 ? 64 : 32);
   if (method == ISX_UP) {
-    if (bm == 128) launch_bm<ISX_UP, 128>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, s);
-    else if (bm == 64) launch_bm<ISX_UP, 64>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, s);
-    else launch_bm<ISX_UP, 32>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, s);
+    if (bm == 128) launch_bm<ISX_UP, 128>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, act, s);
+    else if (bm == 64) launch_bm<ISX_UP, 64>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, act, s);
+    else launch_bm<ISX_UP, 32>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, act, s);
   } else {
-    if (bm == 128) launch_bm<ISX_AA, 128>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, s);
-    else if (bm == 64) launch_bm<ISX_AA, 64>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, s);
-    else launch_bm<ISX_AA, 32>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, s);
+    if (bm == 128) launch_bm<ISX_AA, 128>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, act, s);
+    else if (bm == 64) launch_bm<ISX_AA, 64>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, act, s);
+    else launch_bm<ISX_AA, 32>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, act, s);
   }
   return hipGetLastError();
 }

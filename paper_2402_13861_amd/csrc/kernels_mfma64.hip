@@ -17,6 +17,7 @@
 // (row l/16 + 4i, column l%16).  Each wave owns 32 rows x 32*NB columns as
 // 2 x 2NB tiles of 16 x 16.
 #include "isx_internal.h"
+#include "rules.h"
 
 #include <algorithm>
 
@@ -29,44 +30,6 @@ __device__ __forceinline__ double dstat(double v) {
   return METHOD == ISX_UP ? v * v : fabs(v);
 }
 
-// Gaussian least-squares ReLU rule (App. D ReLU row, erfc form, clamped) and
-// the Chebyshev rule of affine arithmetic, in float64.
-template <int METHOD>
-__device__ __forceinline__ void relu_rule_f64(double y, double stat, double& a, double& b, double& g) {
-  if (METHOD == ISX_UP) {
-    const double sigma = sqrt(stat);
-    const double ay = fabs(y);
-    if (!(sigma > 1e-30 * (ay > 1.0 ? ay : 1.0))) {
-      a = y > 0.0 ? 1.0 : (y < 0.0 ? 0.0 : 0.5);
-      b = 0.0;
-      g = 0.0;
-      return;
-    }
-    const double r = y / sigma;
-    const double Phi = 0.5 * erfc(-r * 0.70710678118654752440);
-    const double Q = 0.5 * erfc(r * 0.70710678118654752440);
-    const double phi = 0.39894228040143267794 * exp(-0.5 * r * r);
-    a = Phi;
-    b = sigma * phi;
-    const double g2 = sigma * sigma * ((r * r + 1.0) * Phi * Q + r * phi * (Q - Phi) - phi * phi);
-    g = g2 > 0.0 ? sqrt(g2) : 0.0;
-  } else {
-    const double l = y - stat, u = y + stat;
-    if (u <= 0.0) {
-      a = 0.0;
-      b = 0.0;
-      g = 0.0;
-    } else if (l >= 0.0) {
-      a = 1.0;
-      b = 0.0;
-      g = 0.0;
-    } else {
-      a = u / (u - l);
-      b = -a * l * 0.5;
-      g = b;
-    }
-  }
-}
 
 template <int BM>
 struct Cfg64 {
@@ -88,7 +51,7 @@ __global__ __launch_bounds__(512) void hidden_mfma_f64_kernel(
     const double* __restrict__ bias, const double* __restrict__ Fin, const double* __restrict__ Ain,
     const double* __restrict__ Bin, const double* __restrict__ Gin, double* __restrict__ Fout,
     double* __restrict__ Y, double* __restrict__ A, double* __restrict__ B, double* __restrict__ G,
-    double* __restrict__ S) {
+    double* __restrict__ S, int act) {
   using K = Cfg64<BM>;
   __shared__ double As[K::KT * K::ASTR];
   __shared__ double Bs[K::KT * K::BSTR];
@@ -314,7 +277,7 @@ __global__ __launch_bounds__(512) void hidden_mfma_f64_kernel(
 #pragma unroll
     for (int g = 0; g < K::G; ++g) tot += s_gen[g][t];
     double a, b, gg;
-    relu_rule_f64<METHOD>(s_y[t], tot, a, b, gg);
+    apply_rule<double, METHOD>(act, s_y[t], tot, a, b, gg);
     const int64_t o = cell * n_out + m0 + t;
     Y[o] = s_y[t];
     A[o] = a;
@@ -327,11 +290,11 @@ __global__ __launch_bounds__(512) void hidden_mfma_f64_kernel(
 template <int METHOD, int BM>
 static void launch64_bm(int64_t C, int n_in, int n_out, int64_t cols_in, const double* Wt, const double* bias,
                         const double* Fin, const double* Ain, const double* Bin, const double* Gin, double* Fout,
-                        double* Y, double* A, double* B, double* G, double* S, hipStream_t s) {
+                        double* Y, double* A, double* B, double* G, double* S, int act, hipStream_t s) {
   const int rb_count = n_out / BM;
   const int64_t blocks = ((C + 7) / 8) * 8 * rb_count;
   hipLaunchKernelGGL((hidden_mfma_f64_kernel<METHOD, BM>), dim3((unsigned)blocks), dim3(Cfg64<BM>::THREADS), 0, s,
-                     C, n_in, n_out, cols_in, rb_count, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S);
+                     C, n_in, n_out, cols_in, rb_count, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, act);
 }
 
 hipError_t launch_hidden_mfma_f64(int method, int64_t C, int n_in, int n_out, int64_t cols_in, const double* Wt,
@@ -340,11 +303,14 @@ hipError_t launch_hidden_mfma_f64(int method, int64_t C, int n_in, int n_out, in
                                   double* S, hipStream_t s) {
   if (C <= 0) return hipSuccess;
   if (n_out % 32 != 0 || n_in % 32 != 0 || n_in > ISX_MAX_WIDTH) return hipErrorInvalidValue;
+  // method: the propagation method in the low 4 bits, the activation above
+  const int act = method >> 4;
+  method &= 15;
   // 64-row blocks run two workgroups per CU (the 128-row tile needs more
   // registers than that allows); wider layers keep 128 so that each cell's
   // coefficient block is streamed fewer times
   const int bm = (n_out % 64 == 0 && n_out <= 256) ? 64 : (n_out % 128 == 0 ? 128 : (n_out % 64 == 0 ? 64 : 32));
-#define ISX_F64_ARGS C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, s
+#define ISX_F64_ARGS C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, act, s
   if (method == ISX_UP) {
     if (bm == 128) launch64_bm<ISX_UP, 128>(ISX_F64_ARGS);
     else if (bm == 64) launch64_bm<ISX_UP, 64>(ISX_F64_ARGS);

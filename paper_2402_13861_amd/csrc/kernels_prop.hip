@@ -22,6 +22,7 @@
 //     another wide product.  Each symbol's output coefficient is the same
 //     number the forward tracking would give, so this is exact.
 #include "isx_internal.h"
+#include "rules.h"
 
 #include <algorithm>
 
@@ -53,46 +54,11 @@ struct M<double> {
 //    a zero-width input takes the exact limit (alpha = step(y), 1/2 at 0).
 //  AA (Eq. 4), hard range [l, u] = [y - r, y + r]: minimax line; for l < 0 < u
 //    alpha = u/(u-l), beta = gamma = -alpha l / 2; identity if l >= 0; 0 if u <= 0.
-template <typename T, int METHOD>
-__device__ __forceinline__ void relu_rule(T y, T stat, T& a, T& b, T& g) {
-  if (METHOD == ISX_UP) {
-    const T sigma = M<T>::sqrt_(stat);
-    const T ay = M<T>::abs_(y);
-    if (!(sigma > T(1e-30) * (ay > T(1) ? ay : T(1)))) {
-      a = y > T(0) ? T(1) : (y < T(0) ? T(0) : T(0.5));
-      b = T(0);
-      g = T(0);
-      return;
-    }
-    const T r = y / sigma;
-    const T Phi = T(0.5) * M<T>::erfc_(-r * T(0.70710678118654752440));
-    const T Q = T(0.5) * M<T>::erfc_(r * T(0.70710678118654752440));
-    const T phi = T(0.39894228040143267794) * M<T>::exp_(T(-0.5) * r * r);
-    a = Phi;
-    b = sigma * phi;
-    const T g2 = sigma * sigma * ((r * r + T(1)) * Phi * Q + r * phi * (Q - Phi) - phi * phi);
-    g = g2 > T(0) ? M<T>::sqrt_(g2) : T(0);
-  } else {
-    const T l = y - stat, u = y + stat;
-    if (u <= T(0)) {
-      a = T(0);
-      b = T(0);
-      g = T(0);
-    } else if (l >= T(0)) {
-      a = T(1);
-      b = T(0);
-      g = T(0);
-    } else {
-      a = u / (u - l);
-      b = -a * l * T(0.5);
-      g = b;
-    }
-  }
-}
 
+// row statistic terms: squares for UP and for the RA-UA read-off, magnitudes for AA
 template <typename T, int METHOD>
 __device__ __forceinline__ T stat_term(T v) {
-  return METHOD == ISX_UP ? v * v : M<T>::abs_(v);
+  return METHOD != ISX_AA ? v * v : M<T>::abs_(v);
 }
 
 // ---------------------------------------------------------------- layer 1
@@ -104,7 +70,7 @@ template <typename T, int METHOD>
 __global__ void layer1_kernel(int64_t C, int n, const float* __restrict__ centres,
                               const float* __restrict__ halves, const T* __restrict__ W1,
                               const T* __restrict__ b1, T* __restrict__ Fout, T* __restrict__ Y,
-                              T* __restrict__ A, T* __restrict__ B, T* __restrict__ G, T* __restrict__ S) {
+                              T* __restrict__ A, T* __restrict__ B, T* __restrict__ G, T* __restrict__ S, int act) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= C * n) return;
   const int64_t cell = idx / n;
@@ -121,7 +87,7 @@ __global__ void layer1_kernel(int64_t C, int n, const float* __restrict__ centre
     stat += stat_term<T, METHOD>(f[i]);
   }
   T a, b, g;
-  relu_rule<T, METHOD>(y, stat, a, b, g);
+  apply_rule<T, METHOD>(act, y, stat, a, b, g);
   Y[idx] = y;
   A[idx] = a;
   B[idx] = b;
@@ -150,7 +116,7 @@ __global__ void hidden_simt_kernel(int64_t C, int n_in, int n_out, int64_t cols_
                                    const T* __restrict__ Fin, const T* __restrict__ Ain,
                                    const T* __restrict__ Bin, const T* __restrict__ Gin,
                                    T* __restrict__ Fout, T* __restrict__ Y, T* __restrict__ A,
-                                   T* __restrict__ B, T* __restrict__ G, T* __restrict__ S) {
+                                   T* __restrict__ B, T* __restrict__ G, T* __restrict__ S, int act_fn) {
   extern __shared__ unsigned char smem_raw[];
   T* Bs = reinterpret_cast<T*>(smem_raw);  // [n_in][CT]
   const int64_t cell = blockIdx.x;
@@ -210,7 +176,7 @@ __global__ void hidden_simt_kernel(int64_t C, int n_in, int n_out, int64_t cols_
       if (fout) fout[(cols_in + j) * n_out + m] = v;
     }
     T a, b, g;
-    relu_rule<T, METHOD>(y, stat, a, b, g);
+    apply_rule<T, METHOD>(act_fn, y, stat, a, b, g);
     const int64_t o = cell * n_out + m;
     Y[o] = y;
     A[o] = a;
@@ -328,7 +294,9 @@ __global__ __launch_bounds__(256) void output_kernel(int64_t C, NetView<T> net, 
       acc += red[1][c][w];
     }
     mu += net.b[L - 1][0];
-    const T spread = METHOD == ISX_UP ? M<T>::sqrt_(acc) : acc;
+    // RA-UA (Eq. 5): the AA coefficients read as uniform variables, variance x_i^2 / 3
+    const T spread = METHOD == ISX_UP ? M<T>::sqrt_(acc)
+                                      : (METHOD == ISX_RAUA ? M<T>::sqrt_(acc) * T(0.57735026918962576451) : acc);
     const int64_t cell = cell0 + c;
     out32[cell * 2 + 0] = (float)mu;
     out32[cell * 2 + 1] = (float)spread;
@@ -386,9 +354,9 @@ __global__ void mlp_eval_kernel(int64_t n, NetView<T> net, int n_max, const floa
 #pragma unroll
         for (int p = 0; p < PT; ++p) acc[p] += w * hin[k * PT + p];
       }
-      const bool relu = l + 1 < net.n_linear;
+      const bool hidden = l + 1 < net.n_linear;
 #pragma unroll
-      for (int p = 0; p < PT; ++p) hout[m * PT + p] = relu ? (acc[p] > T(0) ? acc[p] : T(0)) : acc[p];
+      for (int p = 0; p < PT; ++p) hout[m * PT + p] = hidden ? activate<T>(net.act, acc[p]) : acc[p];
     }
     __syncthreads();
     T* tmp = hin;
@@ -475,6 +443,7 @@ template <typename T>
 static NetView<T> make_view(const Model& m) {
   NetView<T> v{};
   v.n_linear = m.n_linear;
+  v.act = m.act;
   for (int i = 0; i <= m.n_linear; ++i) v.n[i] = m.pw[i];
   for (int l = 0; l < m.n_linear; ++l) {
     v.W[l] = wptr<T>(m.L[l]);
@@ -523,7 +492,7 @@ static hipError_t propagate_impl(const PropArgs& a, PropWork<T>& w, bool use_mfm
   layer_ptrs<T>(m, C, w.vec, Y, A, B, G);
   // AA rounding margin: the kernels also write their row statistics, and a
   // pass after each layer re-applies the rule to the widened radius
-  const bool marg = METHOD == ISX_AA && a.aa_margin;
+  const bool marg = METHOD == ISX_AA && a.aa_margin && a.method == ISX_AA;
   const double u = sizeof(T) == 8 ? 0x1p-53 : 0x1p-24;
   if (marg) margin_ptrs<T>(m, C, w.vec, S, R);
   int64_t D = 3;  // symbol columns summed by the row statistic of the layer
@@ -534,7 +503,7 @@ static hipError_t propagate_impl(const PropArgs& a, PropWork<T>& w, bool use_mfm
     const int bs = 256;
     hipLaunchKernelGGL((layer1_kernel<T, METHOD>), dim3((unsigned)((threads + bs - 1) / bs)), dim3(bs), 0,
                        a.stream, C, n1, a.centres, a.halves, wptr<T>(m.L[0]), bptr<T>(m.L[0]),
-                       Lh >= 2 ? w.F[cur] : (T*)nullptr, Y[1], A[1], B[1], G[1], S[1]);
+                       Lh >= 2 ? w.F[cur] : (T*)nullptr, Y[1], A[1], B[1], G[1], S[1], m.act);
     if (marg) {
       hipError_t e = launch_aa_margin_hidden<T>(C, 3, n1, wtptr<T>(m.L[0]), bptr<T>(m.L[0]), nullptr, nullptr, nullptr,
                                                 nullptr, a.centres, a.halves, Y[1], S[1], A[1], B[1], G[1], R[1],
@@ -560,7 +529,7 @@ static hipError_t propagate_impl(const PropArgs& a, PropWork<T>& w, bool use_mfm
       prof = a.prof->begin(rec, kind, flops, bytes, a.stream);
     }
     if (use_mfma) {
-      hipError_t e = hidden_mfma<T>(METHOD, C, n_in, n_out, cols_in, wtptr<T>(m.L[h - 1]), bptr<T>(m.L[h - 1]),
+      hipError_t e = hidden_mfma<T>(METHOD | (m.act << 4), C, n_in, n_out, cols_in, wtptr<T>(m.L[h - 1]), bptr<T>(m.L[h - 1]),
                                     w.F[cur], A[h - 1], B[h - 1], G[h - 1], Fout, Y[h], A[h], B[h], G[h], S[h],
                                     a.stream);
       if (e != hipSuccess) return e;
@@ -570,7 +539,7 @@ static hipError_t propagate_impl(const PropArgs& a, PropWork<T>& w, bool use_mfm
       const size_t lds = (size_t)CT * n_in * sizeof(T);
       hipLaunchKernelGGL((hidden_simt_kernel<T, METHOD, CT>), dim3((unsigned)C), dim3(bs), lds, a.stream, C, n_in,
                          n_out, cols_in, wtptr<T>(m.L[h - 1]), bptr<T>(m.L[h - 1]), w.F[cur], A[h - 1], B[h - 1],
-                         G[h - 1], Fout, Y[h], A[h], B[h], G[h], S[h]);
+                         G[h - 1], Fout, Y[h], A[h], B[h], G[h], S[h], m.act);
     }
     if (prof) a.prof->end(rec, a.stream);
     D += n_in;
@@ -585,7 +554,19 @@ static hipError_t propagate_impl(const PropArgs& a, PropWork<T>& w, bool use_mfm
   Profiler::Rec rec{};
   const bool prof = a.prof && a.prof->begin(rec, ISX_KERNEL_OUTPUT, output_flops_per_cell(m) * (double)C,
                                             (double)sizeof(T) * C * 4.0 * (double)m.pw[1] * Lh, a.stream);
-  if (use_mfma && sizeof(T) == 4 && a.out64 == nullptr) {
+  if (a.method == ISX_RAUA) {
+    // RA-UA: the AA vectors with the uniform-assumption read-off
+    NetView<T> view = make_view<T>(m);
+    for (int h = 1; h <= Lh; ++h) {
+      view.Y[h] = Y[h];
+      view.A[h] = A[h];
+      view.B[h] = B[h];
+      view.G[h] = G[h];
+    }
+    hipError_t e = sizeof(T) == 8 ? launch_output_simt<T, ISX_RAUA, 4>(m, C, view, a.halves, a.out32, a.out64, a.stream)
+                                  : launch_output_simt<T, ISX_RAUA, 1>(m, C, view, a.halves, a.out32, a.out64, a.stream);
+    if (e != hipSuccess) return e;
+  } else if (use_mfma && sizeof(T) == 4 && a.out64 == nullptr) {
     hipError_t e = launch_output_mfma(m, (isx_method)METHOD, C, reinterpret_cast<float* const*>(Y),
                                       reinterpret_cast<float* const*>(A), reinterpret_cast<float* const*>(B),
                                       reinterpret_cast<float* const*>(G), a.halves, a.out32, a.stream);
@@ -629,8 +610,9 @@ hipError_t launch_output_f32(const Model& m, isx_method method, int64_t C, float
     view.B[h] = B[h];
     view.G[h] = G[h];
   }
-  return method == ISX_UP ? launch_output_simt<float, ISX_UP, 1>(m, C, view, halves, out32, nullptr, s)
-                          : launch_output_simt<float, ISX_AA, 1>(m, C, view, halves, out32, nullptr, s);
+  return method == ISX_UP     ? launch_output_simt<float, ISX_UP, 1>(m, C, view, halves, out32, nullptr, s)
+         : method == ISX_RAUA ? launch_output_simt<float, ISX_RAUA, 1>(m, C, view, halves, out32, nullptr, s)
+                              : launch_output_simt<float, ISX_AA, 1>(m, C, view, halves, out32, nullptr, s);
 }
 
 hipError_t propagate_f32(const PropArgs& a, PropWork<float>& w) {

@@ -89,7 +89,9 @@ def test_cancelling_net_is_rerouted_to_fp64(ctx):
     err_off = np.abs(off[:, 1].astype(np.float64) - sg) / sg
     print(f"without the check: spread relative error median {np.median(err_off):.3e} max {err_off.max():.3e}",
           flush=True)
-    assert np.median(err_off) > 1e-2
+    # without it almost every cell is outside float32 parity and some are off by more than 100 %
+    assert (err_off > 1e-5).mean() >= 0.9
+    assert err_off.max() > 1.0
 
 
 @pytest.mark.parametrize("net", ["he-normal-256x5", "fourier-inr"])

@@ -96,9 +96,9 @@ def test_extraction_with_surrogate_recall(ctx):
         ctx.set_option(isx.KEEP_LEVELS, 1)
         plain = ctx.extract(mid, isx.UP, isx.FP32, k=3.0, max_depth=6)
         ctx.set_option(isx.KEEP_LEVELS, 0)
-        visited = [plain.level_cells(L)[0] for L in range(plain.n_levels)]
-        info = train_surrogate(ctx, mid, 6, float(vals.mean()), S, visited=visited, n_pairs=200_000, steps=800,
-                               batch=2048, holdout=20_000, seed=0, isos=isos, k=3.0, log=print)
+        # (a held-out set large enough to resolve the 1e-4 miss target per level)
+        info = train_surrogate(ctx, mid, 6, float(vals.mean()), S, visited=plain, n_pairs=200_000, steps=800,
+                               batch=2048, holdout=400_000, seed=0, k=3.0, min_level_kept=20_000, log=print)
         assert info.losses[-50:].mean() < 0.3 * info.losses[:10].mean()
         sur = ctx.extract(mid, isx.UP, isx.FP32, k=3.0, max_depth=6, use_surrogate=True)
         p_ids, _ = plain.leaves()
@@ -186,10 +186,9 @@ def test_surrogate_with_base_gains_over_plain_extraction(ctx):
         ctx.set_option(isx.KEEP_LEVELS, 1)
         plain = ctx.extract(mid, isx.UP, isx.FP32, k=3.0, max_depth=6)
         ctx.set_option(isx.KEEP_LEVELS, 0)
-        visited = [plain.level_cells(L)[0] for L in range(plain.n_levels)]
-        info = train_surrogate(ctx, mid, 6, float(vals.mean()), S, visited=visited, n_pairs=200_000, steps=800,
-                               batch=2048, holdout=20_000, seed=0, isos=isos, k=3.0, base=True,
-                               accept_leaves=True, log=print)
+        info = train_surrogate(ctx, mid, 6, float(vals.mean()), S, visited=plain, n_pairs=200_000, steps=800,
+                               batch=2048, holdout=400_000, seed=0, k=3.0, base=True, accept_leaves=True,
+                               min_level_kept=20_000, log=print)
         sur = ctx.extract(mid, isx.UP, isx.FP32, k=3.0, max_depth=6, use_surrogate=True)
         p_ids, _ = plain.leaves()
         s_ids, _ = sur.leaves()
@@ -290,6 +289,87 @@ def test_band_partition_matches_oracle(ctx, accept_leaves):
                   flush=True)
             assert not bad.any(), np.nonzero(bad)[0][:5]
             assert exempt.mean() < 1e-3
+    finally:
+        ctx.surrogate_attach(mid, -1, [0.0], [0.0])
+        ctx.surrogate_free(sid)
+        ctx.unload_mlp(mid)
+
+
+def _rates_reference(pred, targ, unit, levels, err_mu, err_ls, isos, k, z_prune, z_acc):
+    """Held-out miss and false-accept counts per cell, float64 (the band
+    rules of the safety band at given per-cell bands)."""
+    mu_h, sg_h = pred[:, 0], pred[:, 1]
+    mu, sg = targ[:, 0], targ[:, 1]
+    em = np.asarray(err_mu)[levels] * (1.0 if unit is None else unit)
+    el = np.asarray(err_ls)[levels]
+    kept = np.zeros(len(mu), bool)
+    miss = np.zeros(len(mu), bool)
+    fa = np.zeros(len(mu), bool)
+    for c in isos:
+        pk = np.abs(mu - c) <= k * sg
+        kept |= pk
+        miss |= pk & (np.abs(mu_h - c) - z_prune * em > k * sg_h * np.exp(z_prune * el))
+        fa |= ~pk & (np.abs(mu_h - c) + z_acc * em < k * sg_h * np.exp(-z_acc * el))
+    return kept, miss, fa
+
+
+def test_calibration_matches_a_reference_of_its_bookkeeping(ctx):
+    """isx_surrogate_calibrate against the same bookkeeping in float64 here:
+    per-level RMS errors of the predictions, and at the chosen bands the
+    held-out miss and false-accept counts; each chosen band is the smallest
+    ladder value meeting its target (where the reference rates are not within
+    float32 rounding of the target)."""
+    import paper_2402_13861_amd as isx
+
+    mlp = he_normal_mlp([3, 64, 64, 64, 1], seed=0)
+    vals = mlp_forward(mlp, uniform_points(10_000, seed=1))
+    isos = [float(np.float32(np.quantile(vals, q))) for q in (0.25, 0.5, 0.75)]
+    S = float(vals.std())
+    mid = ctx.load_weights(mlp)
+    Ws, bs = _sur_weights(11)
+    sid = ctx.surrogate_load(Ws, bs)
+    try:
+        ctx.set_isovalues(mid, isos)
+        ctx.surrogate_set_norm(sid, float(vals.mean()), S, 0.25, 1.0)
+        c, h, lv = ctx.surrogate_sample_cells(mid, None, 60_000, 0, 6, seed=3)
+        T = torch.empty((60_000, 2), dtype=torch.float32, device="cuda")
+        ctx.propagate(mid, isx.UP, isx.FP32, c, h, T)
+        cal = ctx.surrogate_calibrate(sid, mid, c, h, T, lv, 7, 3.0, miss_target=1e-2, accept_target=5e-2,
+                                      min_level_kept=3000)
+        P = torch.empty((60_000, 2), dtype=torch.float32, device="cuda")
+        ctx.surrogate_predict(sid, c, h, P)
+        torch.cuda.synchronize()
+        pred = P.cpu().numpy().astype(np.float64)
+        targ = T.cpu().numpy().astype(np.float64)
+        L = lv.cpu().numpy().astype(np.int64)
+        assert L.min() >= 0 and L.max() <= 6 and len(np.unique(L)) == 7
+        for l in range(7):
+            sel = L == l
+            dmu = np.sqrt(np.mean((pred[sel, 0] - targ[sel, 0]) ** 2))
+            dls = np.sqrt(np.mean((np.log(pred[sel, 1]) - np.log(targ[sel, 1])) ** 2))
+            assert cal["n_cells"][l] == int(sel.sum())
+            assert cal["err_mu"][l] == pytest.approx(dmu, rel=1e-4)
+            assert cal["err_logsig"][l] == pytest.approx(dls, rel=1e-4)
+        ladder = [0.0, 0.5, 1.0, 1.5, 2.0, 2.5, 3.0, 3.5, 4.0, 5.0, 6.0, 8.0, 12.0]
+        zl = np.asarray(cal["z"])[L]
+        zal = np.asarray(cal["z_accept"])[L]
+        kept, miss, fa = _rates_reference(pred, targ, None, L, cal["err_mu"], cal["err_logsig"], isos, 3.0, zl, zal)
+        n_kept = kept.sum()
+        print(f"calibration: bands {cal['z']} / {cal['z_accept']}; miss {cal['holdout_miss']:.3e} "
+              f"(reference {miss.sum() / n_kept:.3e}), false accept {cal['holdout_false_accept']:.3e} "
+              f"(reference {fa.sum() / n_kept:.3e})", flush=True)
+        assert sum(cal["kept"]) == pytest.approx(n_kept, abs=3)
+        assert cal["holdout_miss"] * n_kept == pytest.approx(miss.sum(), abs=3)
+        assert cal["holdout_false_accept"] * n_kept == pytest.approx(fa.sum(), abs=3)
+        for l in range(7):
+            sel = L == l
+            kl = kept[sel].sum()
+            if kl < 3000:
+                continue
+            z_ok = [z for z in ladder[4:]
+                    if _rates_reference(pred[sel], targ[sel], None, L[sel], cal["err_mu"], cal["err_logsig"], isos,
+                                        3.0, z, 0.0)[1].sum() / kl <= 1e-2]
+            assert cal["z"][l] == (z_ok[0] if z_ok else 12.0), (l, cal["z"][l], z_ok[:2])
     finally:
         ctx.surrogate_attach(mid, -1, [0.0], [0.0])
         ctx.surrogate_free(sid)

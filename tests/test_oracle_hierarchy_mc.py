@@ -21,7 +21,8 @@ from oracle.mlp import mlp_forward
 from oracle.metrics import fpr_fnr, set_recall
 from oracle.octree import cell_boxes, classify, extract_active, morton_decode, morton_encode
 from oracle.propagate import AA, UP
-from workloads import he_normal_mlp
+from oracle.propagate import propagate
+from workloads import he_normal_mlp, uniform_points
 
 
 def test_morton_roundtrip_and_children():
@@ -177,3 +178,75 @@ def test_fpr_fnr_hand_counted():
     fpr, fnr = fpr_fnr(pred, true)
     assert fpr == pytest.approx(2 / 4)
     assert fnr == pytest.approx(1 / 3)
+
+
+def _kd_recursive(layers, method, iso, depth, k, c, h, node, d, out):
+    """Alg. 1 as printed: depth-first recursion on one node."""
+    from oracle.octree import kd_split, widest_axis
+
+    cen, spr = propagate(layers, c[None, :], h[None, :], method)
+    kk = 1.0 if method == AA else k
+    if not (cen[0] - kk * spr[0] <= iso <= cen[0] + kk * spr[0]):
+        return
+    if d == depth:
+        out.add(int(node))
+        return
+    lower, upper = kd_split(c, h, widest_axis(h))
+    _kd_recursive(layers, method, iso, depth, k, *lower, 2 * node, d + 1, out)
+    _kd_recursive(layers, method, iso, depth, k, *upper, 2 * node + 1, d + 1, out)
+
+
+@pytest.mark.parametrize("method", [AA, UP])
+def test_kd_tree_breadth_first_equals_recursion(method):
+    """The level-by-level k-d search equals the depth-first recursion of
+    Alg. 1 on a tiny net (every node's decision depends on its box only)."""
+    from oracle.octree import extract_active_kd
+
+    mlp = he_normal_mlp([3, 16, 16, 1], seed=2)
+    iso = float(np.median(mlp_forward(mlp, uniform_points(2000, seed=1))))
+    lv = extract_active_kd(mlp, method, [iso], 6, k=3.0)
+    bfs = set(lv[-1]["ids"][lv[-1]["mask"] != 0].tolist())
+    rec = set()
+    _kd_recursive(mlp, method, iso, 6, 3.0, np.zeros(3), np.ones(3), 0, 0, rec)
+    assert bfs == rec and len(bfs) > 0
+
+
+def test_kd_tree_splits_cycle_and_leaves_are_octree_cells():
+    """On a cube the widest-dimension rule with ties x, y, z splits x, y, z in
+    turn; depth 3D nodes are the octree cells of level D (k-d id -> Morton)."""
+    from oracle.octree import cell_boxes, extract_active_kd, kd_to_morton, widest_axis
+
+    assert widest_axis([1.0, 1.0, 1.0]) == 0
+    assert widest_axis([0.5, 1.0, 1.0]) == 1
+    assert widest_axis([0.5, 0.5, 1.0]) == 2
+    layers = [(np.eye(3)[:1] * 0.0, np.array([0.0])), (np.array([[1.0]]), np.array([0.0]))]  # constant 0: all active
+    lv = extract_active_kd(layers, AA, [0.0], 6)
+    ids = lv[6]["ids"]
+    assert ids.size == 64
+    c_oct, h_oct = cell_boxes(2, kd_to_morton(ids, 2))
+    np.testing.assert_allclose(lv[6]["centre_box"], c_oct)
+    np.testing.assert_allclose(lv[6]["half"], h_oct)
+
+
+@pytest.mark.parametrize("method", [AA, UP])
+def test_kd_leaves_within_octree_leaves_and_aa_covers_dense(method):
+    """Cube nodes of the k-d tree have the octree cells' boxes, so they get
+    the same test; a k-d leaf also needs its half and quarter ancestors, so
+    the k-d leaves at depth 3D are a subset of the octree leaves at D.  For
+    AA (sound), both contain the dense grid's iso-voxels."""
+    from oracle.octree import extract_active_kd, kd_to_morton
+
+    mlp = he_normal_mlp([3, 32, 32, 1], seed=3)
+    iso = float(np.median(mlp_forward(mlp, uniform_points(4000, seed=1))))
+    D = 4
+    kd = extract_active_kd(mlp, method, [iso], 3 * D, k=3.0)
+    oc = extract_active(mlp, method, [iso], D, k=3.0)
+    kd_leaves = set(kd_to_morton(kd[-1]["ids"][kd[-1]["mask"] != 0], D).tolist())
+    oc_leaves = set(oc[-1]["ids"][oc[-1]["mask"] != 0].tolist())
+    assert kd_leaves <= oc_leaves
+    if method == AA:
+        grid = mc.dense_grid(lambda p: mlp_forward(mlp, p), D)
+        ijk, cv = mc.dense_cells(grid)
+        act = mc.iso_voxels(cv, iso)
+        dense = set(morton_encode(ijk[act, 0], ijk[act, 1], ijk[act, 2]).tolist())
+        assert dense <= kd_leaves
