@@ -15,6 +15,8 @@ Two rules replace ReLU(x) on a form with centre ``mu`` by
 
 from __future__ import annotations
 
+from math import factorial
+
 import numpy as np
 from scipy.special import erf, erfc
 
@@ -117,9 +119,25 @@ def sine_up_rule(mu, sigma):
     alpha = np.cos(mu) * e1
     mean = np.sin(mu) * e1
     beta = mean - alpha * mu
-    var = 0.5 * (1.0 - np.cos(2.0 * mu) * np.exp(-2.0 * s * s)) - mean * mean
-    gamma2 = np.maximum(var - alpha * alpha * s * s, 0.0)
-    return alpha, beta, gamma2
+    # gamma^2 = Var sin X - alpha^2 t, t = s^2.  With Var sin X =
+    # (1 - e^{-2t} cos 2 mu)/2 - e^{-t} sin^2 mu and cos 2 mu = 1 - 2 sin^2 mu it
+    # equals e^{-t} (sinh t - t) + sin^2(mu) e^{-t} (e^{-t} - 1 + t): two
+    # non-negative terms, so no digits are lost to cancellation for small t.
+    t = s * s
+    S = np.sin(mu) ** 2
+    et = np.exp(-t)
+    ts = np.minimum(t, 1.0)
+    sh = np.zeros_like(ts)  # sinh t - t = sum_{k >= 1} t^(2k+1) / (2k+1)!
+    for k in range(1, 13):
+        sh = sh + ts ** (2 * k + 1) / factorial(2 * k + 1)
+    em = np.zeros_like(ts)  # e^{-t} - 1 + t = sum_{k >= 2} (-t)^k / k!
+    for k in range(2, 26):
+        em = em + (-ts) ** k / factorial(k)
+    small = t < 1.0
+    q = np.where(small, et * sh, 0.5 * (1.0 - np.exp(-2.0 * t)) - t * et)  # e^{-t} (sinh t - t)
+    bt = np.where(small, em, et - 1.0 + t)
+    gamma2 = q + S * et * bt
+    return alpha, beta, np.maximum(gamma2, 0.0)
 
 
 def _phi_cdf(x):

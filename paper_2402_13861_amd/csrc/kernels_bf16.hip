@@ -81,7 +81,7 @@ __global__ void layer1_bf16_kernel(int64_t C, int n, const float* __restrict__ c
 }
 
 // -------------------------------------------------------- hidden layer
-constexpr int kKMax = 256;  // largest n_in held in registers
+constexpr int kKMax = 512;  // largest n_in held in registers
 
 // Hidden layer h.  Logical input block of the cell: F_{h-1} = [stored part
 // (s_in columns, read from Fin) | W_{h-1} diag(gamma_{h-2}) (g_in columns)].
@@ -111,10 +111,10 @@ __global__ __launch_bounds__(64 * NW) void hidden_mfma_bf16_kernel(
   // (addresses are formed from the __shared__ base so they stay LDS accesses)
   constexpr int LSTR = KMAXT + 8;  // bf16 per staged input column (padded against bank conflicts)
   __bf16* const lds = reinterpret_cast<__bf16*>(lds4);
-  __shared__ float s_z[kKMax];
-  __shared__ float s_alpha[kKMax];
-  __shared__ float s_gamma[kKMax];
-  __shared__ float s_gp[kKMax];
+  __shared__ float s_z[KMAXT];
+  __shared__ float s_alpha[KMAXT];
+  __shared__ float s_gamma[KMAXT];
+  __shared__ float s_gp[kKMax];  // indexed by the width of layer h-2, which may exceed KMAXT
   __shared__ float s_y[BM];
   __shared__ float s_row[BM];
   __shared__ float s_gen[BM];
@@ -360,7 +360,11 @@ static hipError_t launch_bf16_v(int64_t C, int n_in, int n_out, int64_t s_in, in
 #define ISX_BF16_KARGS C, n_in, n_out, s_in, g_in, W, bias, WtPrev, Gprev2, Fin, Yin, Ain, Bin, Gin, Fout, Y, A, B, G, S, s
   if (n_in <= 64) return launch_bf16_k<METHOD, NW, RB, NB, 64>(ISX_BF16_KARGS);
   if (n_in <= 128) return launch_bf16_k<METHOD, NW, RB, NB, 128>(ISX_BF16_KARGS);
-  return launch_bf16_k<METHOD, NW, RB, NB, 256>(ISX_BF16_KARGS);
+  if (n_in <= 256) return launch_bf16_k<METHOD, NW, RB, NB, 256>(ISX_BF16_KARGS);
+  // K = 512: the operand rows fill 128 registers per lane, and one 32-column
+  // block per tile keeps the staged tiles within LDS (2 x 32 x 520 bf16 in,
+  // 2 x 32 x (BM + 8) out)
+  return launch_bf16_k<METHOD, NW, RB, 1, 512>(ISX_BF16_KARGS);
 #undef ISX_BF16_KARGS
 }
 

@@ -25,9 +25,9 @@
 //    sine  the chord slope, with beta and gamma from the exact extremes of
 //          sin x - alpha x over [l, u] (end points and the points where
 //          cos x = alpha); a range wider than 2 pi gives 0 +/- 1.
-// The sine and ELU quantities are evaluated in forms free of differences of
-// nearly equal terms (series for small widths, product forms of chord
-// slopes), so that float32 keeps the accuracy of float64's direct forms.
+// The sine and ELU rules run in float64 (also inside float32 kernels), with
+// the sine residual as a sum of non-negative terms and chord slopes in
+// product forms, which avoid differences of nearly equal terms.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -47,6 +47,7 @@ struct RM<float> {
   __device__ static float abs_(float x) { return fabsf(x); }
   __device__ static float sin_(float x) { return sinf(x); }
   __device__ static float cos_(float x) { return cosf(x); }
+  __device__ static float sinh_(float x) { return sinhf(x); }
   __device__ static float acos_(float x) { return acosf(x); }
   __device__ static float log_(float x) { return logf(x); }
   __device__ static float ceil_(float x) { return ceilf(x); }
@@ -60,6 +61,7 @@ struct RM<double> {
   __device__ static double abs_(double x) { return fabs(x); }
   __device__ static double sin_(double x) { return sin(x); }
   __device__ static double cos_(double x) { return cos(x); }
+  __device__ static double sinh_(double x) { return sinh(x); }
   __device__ static double acos_(double x) { return acos(x); }
   __device__ static double log_(double x) { return log(x); }
   __device__ static double ceil_(double x) { return ceil(x); }
@@ -104,17 +106,30 @@ __device__ __forceinline__ void up_rule(int act, T y, T var, T& a, T& b, T& g) {
     a = cs * e1;
     const T mean = sn * e1;
     b = mean - a * y;
-    T g2;
-    if (var < T(0.01)) {
-      // Var f - alpha^2 t, t = sigma^2, cancels to O(t^2): its expansion
-      // S t^2 / 2 + (1/6 - 2S/3) t^3 + (11S/24 - 1/6) t^4, S = sin^2 y
-      // (relative truncation below 3e-5 for t < 0.01)
-      const T S = sn * sn, t = var;
-      g2 = t * t * (T(0.5) * S + t * ((T(1) / T(6) - T(2) / T(3) * S) + t * (T(11) / T(24) * S - T(1) / T(6))));
+    // Var f - alpha^2 t (t = sigma^2) rewritten as a sum of non-negative
+    // terms, e^{-t} [(sinh t - t) + S (e^{-t} - 1 + t)], S = sin^2 y, so that
+    // small cells keep every digit
+    const T t = var, S = sn * sn, et = M::exp_(-t);
+    T q, bt;  // e^{-t} (sinh t - t) and e^{-t} - 1 + t
+    if (t < T(1)) {
+      const T t2 = t * t;
+      // sinh t - t by its series (the first dropped term is below 1e-19 of the sum)
+      const T sh = t * t2 / T(6) *
+                   (T(1) + t2 / T(20) *
+                               (T(1) + t2 / T(42) *
+                                           (T(1) + t2 / T(72) *
+                                                       (T(1) + t2 / T(110) *
+                                                                   (T(1) + t2 / T(156) *
+                                                                               (T(1) + t2 / T(210) *
+                                                                                           (T(1) + t2 / T(272) * (T(1) + t2 / T(342)))))))));
+      const T h = M::sinh_(T(0.5) * t);
+      q = et * sh;
+      bt = T(2) * h * h - sh;  // cosh t - 1 - (sinh t - t)
     } else {
-      const T v = T(0.5) * (T(1) - M::cos_(T(2) * y) * M::exp_(T(-2) * var)) - mean * mean;
-      g2 = v - a * a * var;
+      q = T(-0.5) * M::expm1_(T(-2) * t) - t * et;
+      bt = M::expm1_(-t) + t;
     }
+    const T g2 = q + S * et * bt;
     g = g2 > T(0) ? M::sqrt_(g2) : T(0);
     return;
   }
@@ -259,8 +274,23 @@ __device__ __forceinline__ void aa_rule_act(int act, T y, T rad, T& a, T& b, T& 
 }
 
 // Rule of METHOD (ISX_UP: stat = variance; otherwise AA: stat = radius).
+// The sine and ELU rules are evaluated in float64 also for float32 kernels:
+// their moments are differences of O(1) terms whose float32 rounding would
+// dominate the O(sigma^2) results (one evaluation per neuron, beside the
+// layer's products).
 template <typename T, int METHOD>
 __device__ __forceinline__ void apply_rule(int act, T y, T stat, T& a, T& b, T& g) {
+  if (act != ISX_RELU && sizeof(T) == 4) {
+    double ad, bd, gd;
+    if (METHOD == ISX_UP)
+      up_rule<double>(act, (double)y, (double)stat, ad, bd, gd);
+    else
+      aa_rule_act<double>(act, (double)y, (double)stat, ad, bd, gd);
+    a = (T)ad;
+    b = (T)bd;
+    g = (T)gd;
+    return;
+  }
   if (METHOD == ISX_UP)
     up_rule<T>(act, y, stat, a, b, g);
   else

@@ -451,10 +451,34 @@ def test_cov_propagate_past_one_grid(ctx):
         ctx.unload_mlp(mid)
 
 
+@pytest.mark.parametrize("mname", ["up", "aa"])
+def test_bf16_width_512_against_oracle(ctx, mname):
+    """Hidden width 512 (the coefficient kernel's K = 512 tiles, 3->512x3->1):
+    BF16 bounds within the BF16 tolerance of max(|o|, S); the float32 path
+    within 1e-5."""
+    import paper_2402_13861_amd as isx
+
+    method, gm = METHODS[mname]
+    k = 3.0 if mname == "up" else 1.0
+    mlp = he_normal_mlp([3, 512, 512, 512, 1], seed=2)
+    S = output_scale(mlp)
+    c, h, _ = random_boxes(96, range(0, 10), seed=13)
+    ref = propagate(mlp, c, h, method)
+    mid = ctx.load_weights(mlp)
+    try:
+        tol, stol, _ = BF16_TOL[mname]
+        g, _ = _gpu_prop(ctx, mid, gm, isx.BF16, c, h)
+        assert_pair_close(g, ref, S, tol, f"bf16 {mname} 512", k=k, spread_rtol=stol)
+        g32, _ = _gpu_prop(ctx, mid, gm, isx.FP32, c, h)
+        assert_pair_close(g32, ref, S, 1e-5, f"fp32 {mname} 512", k=k)
+    finally:
+        ctx.unload_mlp(mid)
+
+
 def test_bf16_unsupported_width_reports_error(ctx):
     import paper_2402_13861_amd as isx
 
-    mlp = he_normal_mlp([3, 512, 512, 1], seed=0)
+    mlp = he_normal_mlp([3, 1024, 1024, 1], seed=0)
     mid = ctx.load_weights(mlp)
     try:
         c, h, _ = random_boxes(4, [3], seed=1)

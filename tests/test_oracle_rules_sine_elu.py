@@ -45,6 +45,25 @@ def test_sine_up_rule_matches_quadrature(mu, sigma):
     assert abs(g2 - qg2) < 1e-9
 
 
+@pytest.mark.parametrize("sigma", [1e-7, 1e-5, 3e-4, 1e-2, 0.3, 0.999, 1.0, 1.7, 6.0])
+def test_sine_residual_keeps_its_digits_for_small_cells(sigma):
+    """gamma^2 = Var sin X - alpha^2 sigma^2 is O(sigma^4) (O(sigma^6) where
+    sin mu = 0) while its two terms are O(sigma^2): the definition evaluated
+    with 60-digit arithmetic, from E sin X = sin(mu) e^{-t/2} and
+    E sin^2 X = (1 - cos(2 mu) e^{-2t})/2, t = sigma^2, pins the oracle's
+    cancellation-free form to 1e-13 relative, at the series/closed-form switch
+    (t = 1) too."""
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 60
+    for mu in (0.0, 0.37, 1.0, np.pi / 2, -2.5, 7.0):
+        _, _, g2 = sine_up_rule(mu, sigma)
+        m, t = mp.mpf(mu), mp.mpf(sigma) ** 2
+        mean = mp.sin(m) * mp.exp(-t / 2)
+        var = (1 - mp.cos(2 * m) * mp.exp(-2 * t)) / 2 - mean ** 2
+        ref = var - (mp.cos(m) * mp.exp(-t / 2)) ** 2 * t
+        assert abs(g2 - float(ref)) <= 1e-13 * float(ref), (mu, sigma, g2, float(ref))
+
+
 @pytest.mark.parametrize("mu,sigma", [(0.0, 1.0), (0.3, 0.2), (-2.0, 0.7), (5.0, 2.0), (-0.1, 0.05), (-4.0, 3.0)])
 def test_elu_up_rule_matches_quadrature(mu, sigma):
     a, b, g2 = elu_up_rule(mu, sigma)

@@ -10,6 +10,13 @@ octree depth.  Inputs only; no method arithmetic here.
   256^3 points (field seed 2); octree depth 9 (512^3 effective resolution);
   iso-values at the 25/50/75 % output quantiles; t = 3; float64 re-check band
   1e-3 S.
+* ``relu512x8_blobs``: ReLU MLP 3->512x8->1 fitted (4000 Adam steps, batch
+  65536, lr 1e-3, He-normal init seed 0; ``workloads.fit_gpu``) to a field
+  of 4096 random anisotropic Gaussian blobs (seed 5) plus a 0.25-weighted
+  unit-std Fourier background (512 modes, k^(-5/3), seed 6), standardised,
+  sampled at random points of the 512^3 grid; octree depth 10 (1024^3
+  effective resolution); 8 iso-values at the 1/9 .. 8/9 output quantiles;
+  t = 3; float64 re-check band 1e-3 S.
 """
 
 from __future__ import annotations
@@ -29,6 +36,10 @@ WORKLOADS = {
     "relu256x5_fourier": dict(
         widths=[3, 256, 256, 256, 256, 256, 1], weight_seed=0, weights="relu_256x5_fourier.isxw", depth=9, k=3.0,
         iso_quantiles=[0.25, 0.5, 0.75], band_rel=1e-3,
+    ),
+    "relu512x8_blobs": dict(
+        widths=[3] + [512] * 8 + [1], weight_seed=0, weights="relu_512x8_blobs.isxw", depth=10, k=3.0,
+        iso_quantiles=[i / 9 for i in range(1, 9)], band_rel=1e-3,
     ),
 }
 

@@ -39,3 +39,39 @@ def fourier_field_grid(res: int, n_modes: int = 512, kmax: int = 16, seed: int =
         out[i] = (T.T @ Z).real  # [j, k]
     mean, std = out.mean(), out.std()
     return ((out - mean) / std).astype(np.float32), (mean, std)
+
+
+def blob_params(n_blobs: int = 4096, seed: int = 5):
+    """Anisotropic Gaussian blobs: centres U[-1,1]^3, a random rotation (QR
+    of a Gaussian matrix, signs fixed so that the factor is unique), axis
+    scales log-uniform in [0.01, 0.1], amplitudes U[0.5, 1.5] with a random
+    sign, all from default_rng(seed) in that order."""
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(-1.0, 1.0, (n_blobs, 3))
+    rots = np.empty((n_blobs, 3, 3))
+    for b in range(n_blobs):
+        q, r = np.linalg.qr(rng.standard_normal((3, 3)))
+        rots[b] = q * np.sign(np.diag(r))[None, :]
+    scales = np.exp(rng.uniform(np.log(0.01), np.log(0.1), (n_blobs, 3)))
+    amps = rng.uniform(0.5, 1.5, n_blobs) * rng.choice([-1.0, 1.0], n_blobs)
+    return centres, rots, scales, amps
+
+
+def blob_field_points(x, params, chunk: int = 4096):
+    """sum_b a_b exp(-|diag(1/s_b) R_b^T (x - c_b)|^2 / 2) at points x [N, 3]
+    (float64, numpy)."""
+    centres, rots, scales, amps = params
+    x = np.asarray(x, dtype=np.float64)
+    out = np.zeros(x.shape[0])
+    for s0 in range(0, x.shape[0], chunk):
+        d = x[s0:s0 + chunk, None, :] - centres[None, :, :]          # [n, B, 3]
+        u = np.einsum("nbi,bij->nbj", d, rots) / scales[None, :, :]  # local axes
+        out[s0:s0 + chunk] = (amps[None, :] * np.exp(-0.5 * (u * u).sum(-1))).sum(1)
+    return out
+
+
+def fourier_field_points(x, n_modes: int = 512, kmax: int = 16, seed: int = 6):
+    """sum_m A_m cos(pi k_m . x + phi_m) at points x [N, 3] (unstandardised)."""
+    k, amp, phase = fourier_modes(n_modes, kmax, seed)
+    x = np.asarray(x, dtype=np.float64)
+    return np.cos(np.pi * x @ k.T + phase[None, :]) @ amp
