@@ -150,7 +150,8 @@ def error_vs_oracle(ctx, mid, mlp, sample, S, k, n_aa, log):
     """Error of the GPU's BF16 bounds (UP covariance form, UP coefficient form,
     AA) and FP32 UP bounds against the float64 oracle, per octree level: max
     and 99.9th percentile of |endpoint_gpu - endpoint_oracle| / S over both
-    endpoints centre -/+ k spread (AA: k = 1).  AA is measured on the first
+    endpoints centre -/+ k spread (AA: k = 1), and the max of the same error
+    over the oracle's spread of the cell.  AA is measured on the first
     n_aa cells of the sample (the oracle's AA is run here, untimed)."""
     import numpy as np
     import torch
@@ -167,14 +168,17 @@ def error_vs_oracle(ctx, mid, mlp, sample, S, k, n_aa, log):
         return out.cpu().numpy().astype(np.float64)
 
     def stats(g, oc, os_, kk, lv):
-        e = np.maximum(np.abs((g[:, 0] - kk * g[:, 1]) - (oc - kk * os_)),
-                       np.abs((g[:, 0] + kk * g[:, 1]) - (oc + kk * os_))) / S
+        ea = np.maximum(np.abs((g[:, 0] - kk * g[:, 1]) - (oc - kk * os_)),
+                        np.abs((g[:, 0] + kk * g[:, 1]) - (oc + kk * os_)))
+        e = ea / S
+        er = ea / np.maximum(os_, 1e-30)  # in units of the cell's own spread
         per = {}
         for L in np.unique(lv):
             sel = lv == L
             per[int(L)] = {"n": int(sel.sum()), "max": float(e[sel].max()),
-                           "p999": float(np.quantile(e[sel], 0.999))}
-        return {"max": float(e.max()), "p999": float(np.quantile(e, 0.999)), "levels": per}
+                           "p999": float(np.quantile(e[sel], 0.999)), "max_over_spread": float(er[sel].max())}
+        return {"max": float(e.max()), "p999": float(np.quantile(e, 0.999)), "max_over_spread": float(er.max()),
+                "levels": per}
 
     c, h, lv = sample["centres"], sample["halves"], sample["levels"]
     mu, sg = sample["mu"], sample["sigma"]
@@ -188,8 +192,9 @@ def error_vs_oracle(ctx, mid, mlp, sample, S, k, n_aa, log):
     out["aa_fp32"] = stats(gpu(isx.AA, isx.FP32, c[:na], h[:na]), x0, r, 1.0, lv[:na])
     for key in ("up_bf16_cov", "up_bf16_coef", "up_fp32", "aa_bf16", "aa_fp32"):
         v = out[key]
-        log(f"error vs oracle {key}: max {v['max']:.3e} S, p99.9 {v['p999']:.3e} S; per level max " +
-            ", ".join(f"L{L} {d['max']:.2e}" for L, d in v["levels"].items()))
+        log(f"error vs oracle {key}: max {v['max']:.3e} S, p99.9 {v['p999']:.3e} S, max {v['max_over_spread']:.3e} "
+            f"of the spread; per level max " +
+            ", ".join(f"L{L} {d['max']:.2e} ({d['max_over_spread']:.1e})" for L, d in v["levels"].items()))
     return out
 
 
@@ -306,6 +311,112 @@ def t_sweep(a, log):
     return 0
 
 
+def kl_report(a, log):
+    """Sec. V-E's evaluation of the estimated distribution on the benchmark
+    INR: a.kl_blocks random octree blocks of level a.kl_level (default 100 of
+    level 5, seed a.kl_seed), 10^6 Monte Carlo samples each, a 100-bin
+    histogram, and the KL divergence of Eq. 11 from UP's Gaussian, RA-UA's
+    and the Gaussian fitted to 100 samples (the SAMPLE baseline).  Prints one
+    JSON line."""
+    import numpy as np
+    import torch
+
+    import paper_2402_13861_amd as isx
+    from workloads.configs import load_mlp
+
+    mlp = load_mlp(a.workload)
+    rng = np.random.default_rng(a.kl_seed)
+    L = a.kl_level
+    idx = rng.integers(0, 1 << L, (a.kl_blocks, 3))
+    h = 1.0 / (1 << L)
+    centres = (-1.0 + (2 * idx + 1) * h).astype(np.float32)
+    halves = np.full((a.kl_blocks, 3), h, np.float32)
+    ctx = isx.Context(0)
+    mid = ctx.load_weights(mlp)
+    args = dict(n_samples=a.kl_samples, n_bins=100, n_fit=100, seed=a.kl_seed)
+    c, hh = torch.from_numpy(centres).cuda(), torch.from_numpy(halves).cuda()
+    ctx.distribution_kl(mid, c[:1], hh[:1], **args)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = ctx.distribution_kl(mid, c, hh, **args)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    r = out.cpu().numpy()
+    cols = {f: i for i, f in enumerate(isx.DIST_FIELDS)}
+    res = {}
+    for name in ("up", "raua", "fit"):
+        kl = r[:, cols[f"kl_{name}"]]
+        ok = np.isfinite(kl)
+        res[name] = dict(mean=float(kl[ok].mean()), median=float(np.median(kl[ok])), max=float(kl[ok].max()),
+                         finite=int(ok.sum()))
+    log(f"kl report: {a.kl_blocks} blocks of level {L}, {a.kl_samples} samples each, {dt:.2f} s; mean KL "
+        + ", ".join(f"{k} {v['mean']:.4f}" for k, v in res.items()))
+    print(json.dumps({"kl_report": res, "workload": a.workload, "blocks": a.kl_blocks, "level": L,
+                      "samples_per_block": a.kl_samples, "bins": 100, "fit_samples": 100, "seconds": round(dt, 3),
+                      "samples_per_s": a.kl_blocks * a.kl_samples / dt}), flush=True)
+    ctx.close()
+    return 0
+
+
+def batch_bench(a, log):
+    """The batched workload (64 INRs of uneven width and depth, 4 iso-values
+    each, octree depth 8, BF16 UP, t = 3): isx_extract_batch on
+    a.batch_workers worker streams against the INRs extracted one after
+    another.  Prints one JSON line."""
+    import numpy as np
+    import torch
+
+    import paper_2402_13861_amd as isx
+    from workloads.batch import DEPTH, batch_mlps, batch_shapes
+
+    table = json.loads((ROOT / "workloads" / "isovalues.json").read_text())["batch64"]
+    n = a.batch_inrs
+    mlps = batch_mlps(n)
+    ctx = isx.Context(0)
+    ctx.set_option(isx.SCRATCH_BYTES, 48 << 30)
+    ids = []
+    for mlp, t in zip(mlps, table[:n]):
+        mid = ctx.load_weights(mlp)
+        ctx.set_isovalues(mid, t["iso"])
+        ids.append(mid)
+    depth = a.depth if a.depth is not None else DEPTH
+    prec = {"fp32": isx.FP32, "bf16": isx.BF16}[a.precision]
+    kw = dict(method=isx.UP, precision=prec, k=3.0, max_depth=depth)
+    # warm-up (code objects, scratch)
+    for m in ctx.extract_batch(ids[:4], **kw):
+        m.free()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    singles = []
+    for mid in ids:
+        m = ctx.extract(mid, **kw)
+        singles.append(dict(leaves=int(m.n_leaves), tris=int(m.n_tris),
+                            propagated=int(sum(l["propagated"] for l in m.levels())), ms=m.times()["total_ms"]))
+        m.free()
+    t_seq = time.perf_counter() - t0
+    propagated = sum(x["propagated"] for x in singles)
+    log(f"batch: {n} INRs one after another in {t_seq * 1e3:.1f} ms, {propagated} propagated cells")
+    res = {}
+    for workers in a.batch_workers:
+        ctx.set_option(isx.BATCH_WORKERS, workers)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ms = ctx.extract_batch(ids, **kw)
+        dt = time.perf_counter() - t0
+        same = all(m.n_leaves == x["leaves"] and m.n_tris == x["tris"] for m, x in zip(ms, singles))
+        for m in ms:
+            m.free()
+        res[workers] = dict(ms=round(dt * 1e3, 2), cells_per_s=propagated / dt, same_meshes_as_single=same)
+        log(f"batch: {workers} workers {dt * 1e3:.1f} ms, same meshes {same}")
+    shapes = [w for w, _ in batch_shapes(n)]
+    print(json.dumps({"batch": res, "sequential_ms": round(t_seq * 1e3, 2), "inrs": n, "depth": depth,
+                      "precision": a.precision, "propagated_cells": propagated,
+                      "per_inr": [dict(widths=f"{w[1]}x{len(w) - 2}", **x) for w, x in zip(shapes, singles)]}),
+          flush=True)
+    ctx.close()
+    return 0
+
+
 def copy_probe(nbytes: int, reps: int = 5):
     """A plain device-to-device copy of known size: the reference that scales
     the HBM byte counters (FETCH_SIZE, WRITE_SIZE) read for the kernels."""
@@ -349,6 +460,21 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--t-sweep", action="store_true",
                     help="only run the sweep of t (time against missed iso-voxels) and exit")
+    ap.add_argument("--batch", action="store_true",
+                    help="only run the batched 64-INR workload (isx_extract_batch) and exit")
+    ap.add_argument("--batch-inrs", type=int, default=64)
+    ap.add_argument("--batch-workers", type=int, nargs="+", default=[1, 4, 8])
+    ap.add_argument("--kl-report", action="store_true",
+                    help="only run the distribution-quality report (KL of Eq. 11 over random blocks) and exit")
+    ap.add_argument("--kl-blocks", type=int, default=100)
+    ap.add_argument("--kl-level", type=int, default=5)
+    ap.add_argument("--kl-samples", type=int, default=1_000_000)
+    ap.add_argument("--kl-seed", type=int, default=0)
+    ap.add_argument("--band-rel", type=float, default=0.0,
+                    help="BF16: widen each cell's float64 re-check band by this multiple of its spread")
+    ap.add_argument("--subtree", type=int, default=0,
+                    help="extract only inside the level-L octree cell [0, 2/2^L]^3 of the domain, to the same "
+                         "leaf size (depth - L levels below it)")
     ap.add_argument("--copy-probe-bytes", type=int, default=0,
                     help="only run a plain copy of this many bytes (counter calibration) and exit")
     a = ap.parse_args(argv)
@@ -360,6 +486,10 @@ def main(argv=None):
         return copy_probe(a.copy_probe_bytes)
     if a.t_sweep:
         return t_sweep(a, log)
+    if a.kl_report:
+        return kl_report(a, log)
+    if a.batch:
+        return batch_bench(a, log)
 
     import numpy as np
     import torch
@@ -369,7 +499,8 @@ def main(argv=None):
     from workloads.configs import WORKLOADS, isovalues, load_mlp
 
     w = WORKLOADS[a.workload]
-    depth = a.depth if a.depth is not None else w["depth"]
+    full_depth = a.depth if a.depth is not None else w["depth"]
+    depth = full_depth - a.subtree
     mlp = load_mlp(a.workload)
     isos, S = isovalues(a.workload)
     import json as _json
@@ -386,7 +517,11 @@ def main(argv=None):
     ctx.set_option(isx.VERBOSE, 1)
     mid = ctx.load_weights(mlp)
     ctx.set_isovalues(mid, isos)
-    base = dict(method=isx.UP, k=w["k"], max_depth=depth, fp64_band=band)
+    sub_hi = 2.0 / (1 << a.subtree) if a.subtree else None
+    if a.subtree:
+        ctx.set_domain(mid, (0.0, 0.0, 0.0), (sub_hi, sub_hi, sub_hi))
+    base = dict(method=isx.UP, k=w["k"], max_depth=depth, fp64_band=band,
+                fp64_band_rel=a.band_rel if a.precision == "bf16" else 0.0)
 
     # 1. plain FP32 reference: the speedup baseline, the recall reference and
     #    the source of visited cells for the surrogate's training set
@@ -467,7 +602,7 @@ def main(argv=None):
     ctx.set_option(isx.PROFILE, 0)
 
     K = a.steps
-    eff_cells = float((1 << depth) ** 3)
+    eff_cells = float((1 << depth) ** 3)  # leaves of the extracted domain at full resolution
     ms_per_step = 1e3 * elapsed / K
     value = eff_cells * K / elapsed
     levels = runs[-1]["levels"]
@@ -587,7 +722,9 @@ def main(argv=None):
         "config": {
             "workload": f"{a.workload}: ReLU MLP {'x'.join(map(str, mlp.widths))}, octree depth {depth} "
                         f"({1 << depth}^3 effective cells), {len(isos)} iso-values, UP t={w['k']}, "
-                        f"fp64 band {w.get('band_rel', 0)} S",
+                        f"fp64 band {w.get('band_rel', 0)} S"
+                        + (f"; domain [0, {sub_hi:g}]^3, the level-{a.subtree} subtree of [-1, 1]^3 at "
+                           f"{1 << full_depth}^3 effective resolution" if a.subtree else ""),
             "path": name,
         },
         "value_definition": "effective cells (2^depth)^3 per second of full extraction",

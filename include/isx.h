@@ -191,7 +191,8 @@ typedef struct {
   int32_t max_depth;       /* octree depth D: leaves are the (2^D)^3 grid cells, D <= 10 */
   float fp64_band;         /* > 0: cells whose bound endpoint lies within
                               fp64_band of an iso-value are re-propagated in
-                              float64 and that result decides (not with ISX_FP64) */
+                              float64 and that result decides (not with ISX_FP64;
+                              see also fp64_band_rel) */
   int64_t max_cells;       /* capacity of one level (0 = library default); a
                               level above it fails with ISX_ECAPACITY */
   int64_t chunk_cells;     /* cells propagated per batch (0 = automatic; at most 2^22) */
@@ -206,6 +207,13 @@ typedef struct {
                               then record 3 max_depth + 1 levels (node ids: root 0,
                               children 2p and 2p + 1), leaves as octree Morton
                               ids in k-d order; not with use_surrogate */
+  float fp64_band_rel;     /* >= 0: widens the re-check band of each cell by this
+                              multiple of its own spread (sigma for UP, r for AA):
+                              a cell is re-propagated in float64 when a bound
+                              endpoint lies within fp64_band + fp64_band_rel *
+                              spread of a carried iso-value (the bfloat16 error
+                              of the endpoints grows with the spread, so coarse
+                              cells need the relative term) */
 } isx_params;
 
 /* Full extraction (Alg. 1 followed by corner evaluation and marching cubes)
@@ -425,6 +433,35 @@ isx_status isx_surrogate_fit(isx_ctx* ctx, int32_t mlp_id, const isx_mesh* visit
 isx_status isx_surrogate_partition(isx_ctx* ctx, int32_t mlp_id, int64_t n, const float* d_pred,
                                    const float* d_unit, float k, int32_t level, int32_t leaf,
                                    const uint32_t* d_parent_mask, uint32_t* d_mask, uint32_t* d_fallback);
+
+/* isx_distribution_kl: quality of the predicted output distribution over
+ * blocks (Sec. V-E and Eq. 11).  For block b with centre d_centres[b][3] and
+ * half-sizes d_halves[b][3] (device, float32), the INR is evaluated (float32)
+ * at n_samples Monte Carlo points drawn uniformly in the block: point i,
+ * axis a, takes u = (SplitMix64 output number (b n_samples + i) 3 + a of the
+ * stream with this seed) >> 40, times 2^-24, and the coordinate
+ * c_a + h_a (2u - 1) (float64 product and sum, rounded to float32).  The
+ * values' histogram has n_bins equal bins on their [min, max] (bin of v:
+ * floor((v - min) / (max - min) n_bins), clamped).  Three Gaussians are
+ * scored by the KL divergence of Eq. 11 of the histogram density p from
+ * their density q, integrated bin by bin in closed form (ln q is a
+ * quadratic): UP's (mu, sigma) and RA-UA's (Eq. 5), both from float64
+ * propagation of the block, and the maximum-likelihood Gaussian of the first
+ * n_fit samples (the few-sample baseline).  d_out [n_blocks][ISX_DIST_FIELDS]
+ * float64, columns in isx_dist_field order; KL is NaN when all samples are
+ * equal or a sigma is 0.  d_hist [n_blocks][n_bins] (optional, NULL) gets the
+ * counts.  Limits: n_samples in [1, 2^31), n_bins in [1, 8192], n_fit in
+ * [1, n_samples].  Asynchronous on the context stream; scratch grows to
+ * 16 bytes per sample of up to 2^26 samples at once.  Errors: ISX_EINVAL,
+ * ISX_ENOMEM, ISX_EHIP. */
+typedef enum {
+  ISX_DIST_MC_MEAN = 0, ISX_DIST_MC_STD, ISX_DIST_LO, ISX_DIST_HI, ISX_DIST_UP_MU, ISX_DIST_UP_SIGMA,
+  ISX_DIST_RAUA_MU, ISX_DIST_RAUA_SIGMA, ISX_DIST_FIT_MU, ISX_DIST_FIT_SIGMA, ISX_DIST_KL_UP, ISX_DIST_KL_RAUA,
+  ISX_DIST_KL_FIT, ISX_DIST_FIELDS
+} isx_dist_field;
+isx_status isx_distribution_kl(isx_ctx* ctx, int32_t mlp_id, int64_t n_blocks, const float* d_centres,
+                               const float* d_halves, int64_t n_samples, int32_t n_bins, int32_t n_fit,
+                               uint64_t seed, double* d_out, uint32_t* d_hist);
 
 /* isx_surrogate_save_file: write surrogate sur_id to `path` (binary, little
  * endian): "ISXSUR01", int32 n_linear, int32 widths[n_linear + 1], float32

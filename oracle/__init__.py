@@ -16,13 +16,17 @@ it follows.
 Modules
 -------
 mlp        plain MLP evaluation (Sec. III-B)
-rules      ReLU linearisations: Chebyshev/minimax for affine arithmetic
-           (Eq. 4) and Gaussian least squares for uncertainty propagation
-           (Eq. 9-10, App. D ReLU row)
-propagate  layer-by-layer range analysis (Eq. 1-4) and uncertainty
-           propagation (Eq. 6-9), plus a covariance-form cross-check
-octree     hierarchical active-cell search (Alg. 1, octree form)
+rules      activation linearisations: Chebyshev/minimax for affine
+           arithmetic (Eq. 4) and Gaussian least squares for uncertainty
+           propagation (Eq. 9-10, App. D ReLU, Sine and ELU rows)
+propagate  layer-by-layer range analysis (Eq. 1-4), its RA-UA read-off
+           (Eq. 5) and uncertainty propagation (Eq. 6-9), plus a
+           covariance-form cross-check
+octree     hierarchical active-cell search (Alg. 1, octree and k-d tree)
 mc         marching-cubes case table (generated) and triangle emission
 metrics    FPR/FNR (Sec. V-A-3) and parity helpers
-surrogate  float64 forward/backward/Adam of the surrogate MLP
+surrogate  float64 forward/backward/Adam of the surrogate MLP and its
+           band partition
+distribution  Monte Carlo histogram of a block and the KL divergence of
+           Eq. 11 from the UP, RA-UA and few-sample Gaussians (Sec. V-E)
 """

@@ -23,6 +23,9 @@ from . import _lib
 from ._lib import (AA, RAUA, RELU, SINE, ELU, BF16, BF16_VARIANT, FP32, FP64, HIDDEN_KERNEL, KEEP_LEVELS, PROFILE, SCRATCH_BYTES, UP,
                    UP_FORM, LIN_PRECISION, AA_MARGIN, BATCH_WORKERS, VERBOSE, CANCEL_CHECK)
 
+# columns of isx_distribution_kl's report (isx_dist_field order)
+DIST_FIELDS = ("mc_mean", "mc_std", "lo", "hi", "up_mu", "up_sigma", "raua_mu", "raua_sigma", "fit_mu", "fit_sigma",
+               "kl_up", "kl_raua", "kl_fit")
 KERNEL_KINDS = ("hidden_fp32", "hidden_bf16", "hidden_simt_fp32", "hidden_fp64", "dense", "output",
                 "hidden_cov_bf16", "linearize")
 
@@ -288,6 +291,25 @@ class Context:
                                                   int(bool(leaf)), _ptr(parent_mask), _ptr(mask), _ptr(fb)))
         return mask[:n], fb[:n]
 
+    def distribution_kl(self, mlp_id: int, centres, halves, n_samples: int = 1_000_000, n_bins: int = 100,
+                        n_fit: int = 100, seed: int = 0, with_hist: bool = False):
+        """isx_distribution_kl on device tensors centres/halves float32 [n, 3]:
+        returns a float64 [n, 13] tensor (columns DIST_FIELDS) and, with
+        with_hist, the int32 [n, n_bins] bin counts."""
+        import torch
+
+        _check_dev(centres, torch.float32, "centres", (3,))
+        _check_dev(halves, torch.float32, "halves", (3,))
+        n = centres.shape[0]
+        if halves.shape[0] != n:
+            raise ValueError("centres and halves must have the same length")
+        out = torch.full((max(n, 1), len(DIST_FIELDS)), float("nan"), dtype=torch.float64, device=centres.device)
+        hist = torch.zeros((max(n, 1), n_bins), dtype=torch.int32, device=centres.device) if with_hist else None
+        self._chk(self._L.isx_distribution_kl(self._h, mlp_id, n, _ptr(centres), _ptr(halves), int(n_samples),
+                                              int(n_bins), int(n_fit), int(seed) & ((1 << 64) - 1), _ptr(out),
+                                              _ptr(hist)))
+        return (out[:n], hist[:n]) if with_hist else out[:n]
+
     @staticmethod
     def _calibration(cal):
         n = cal.n_levels
@@ -387,22 +409,22 @@ class Context:
     # -- full extraction (synchronous)
     def extract(self, mlp_id: int, method: int = UP, precision: int = FP32, k: float = 3.0, max_depth: int = 6,
                 fp64_band: float = 0.0, max_cells: int = 0, chunk_cells: int = 0,
-                use_surrogate: bool = False, kd_tree: bool = False) -> "Mesh":
+                use_surrogate: bool = False, kd_tree: bool = False, fp64_band_rel: float = 0.0) -> "Mesh":
         """isx_extract; kd_tree selects Alg. 1's binary k-d tree (node depth
         3 max_depth) instead of the octree."""
         p = _lib.Params(method, precision, float(k), int(max_depth), float(fp64_band), int(max_cells),
-                        int(chunk_cells), int(bool(use_surrogate)), int(bool(kd_tree)))
+                        int(chunk_cells), int(bool(use_surrogate)), int(bool(kd_tree)), float(fp64_band_rel))
         h = C.c_void_p()
         self._chk(self._L.isx_extract(self._h, mlp_id, C.byref(p), C.byref(h)))
         return Mesh(self._L, h)
 
     def extract_batch(self, mlp_ids, method: int = UP, precision: int = FP32, k: float = 3.0, max_depth: int = 6,
                       fp64_band: float = 0.0, max_cells: int = 0, chunk_cells: int = 0,
-                      use_surrogate: bool = False) -> list:
+                      use_surrogate: bool = False, fp64_band_rel: float = 0.0) -> list:
         """isx_extract of several INRs with the same parameters, run on
         ISX_BATCH_WORKERS streams at once; returns one Mesh per INR."""
         p = _lib.Params(method, precision, float(k), int(max_depth), float(fp64_band), int(max_cells),
-                        int(chunk_cells), int(bool(use_surrogate)), 0)
+                        int(chunk_cells), int(bool(use_surrogate)), 0, float(fp64_band_rel))
         ids = (C.c_int32 * len(mlp_ids))(*[int(i) for i in mlp_ids])
         hs = (C.c_void_p * len(mlp_ids))()
         self._chk(self._L.isx_extract_batch(self._h, len(mlp_ids), ids, C.byref(p), hs))

@@ -76,6 +76,7 @@ class Params(C.Structure):
         ("chunk_cells", C.c_int64),
         ("use_surrogate", C.c_int32),
         ("tree", C.c_int32),
+        ("fp64_band_rel", C.c_float),
     ]
 
 
@@ -98,6 +99,8 @@ _SIGS = [
                                                C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("isx_eval_points", C.c_int, [C.c_void_p, C.c_int32, C.c_int, C.c_int64, C.c_void_p, C.c_void_p]),
     ("isx_linearize", C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("isx_distribution_kl", C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.c_int64,
+                                      C.c_int32, C.c_int32, C.c_uint64, C.c_void_p, C.c_void_p]),
     ("isx_extract", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Params), C.POINTER(C.c_void_p)]),
     ("isx_extract_batch", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(Params),
                                     C.POINTER(C.c_void_p)]),

@@ -108,6 +108,8 @@ struct isx_ctx {
   Buf cx_flags, cx_idx, cx_c, cx_h, cx_out, cx_out64, cx_cnt;
   // surrogate training set and band calibration
   Buf sp_vis, sp_vis_off, cal_pred, cal_unit, cal_part, cal_cnt, cal_vec, fit_c, fit_h, fit_t, fit_l, fit_loss;
+  // distribution-quality report
+  Buf ds_pts, ds_vals, ds_stats, ds_o32, ds_up64, ds_ra64;
   int64_t* h_count = nullptr;  // pinned
   Profiler prof;
   // batched extraction: worker contexts with their own stream and scratch;
@@ -408,7 +410,8 @@ isx_status isx_destroy(isx_ctx* ctx) {
   Buf* cbufs[] = {&ctx->cx_flags, &ctx->cx_idx, &ctx->cx_c,     &ctx->cx_h,     &ctx->cx_out,   &ctx->cx_out64,
                   &ctx->cx_cnt,   &ctx->sp_vis, &ctx->sp_vis_off, &ctx->cal_pred, &ctx->cal_unit, &ctx->cal_part,
                   &ctx->cal_cnt,  &ctx->cal_vec, &ctx->fit_c,     &ctx->fit_h,    &ctx->fit_t,    &ctx->fit_l,
-                  &ctx->fit_loss};
+                  &ctx->fit_loss, &ctx->ds_pts,  &ctx->ds_vals, &ctx->ds_stats, &ctx->ds_o32, &ctx->ds_up64,
+                  &ctx->ds_ra64};
   for (Buf* b : cbufs) release(*b);
   for (int i = 0; i < (int)ctx->surs.size(); ++i) isx_surrogate_free(ctx, i);
   if (ctx->h_count) (void)hipHostFree(ctx->h_count);
@@ -739,6 +742,48 @@ isx_status isx_eval_points(isx_ctx* ctx, int32_t mlp_id, isx_precision precision
   return ISX_OK;
 }
 
+// Distribution-quality report (Sec. V-E, Eq. 11): float64 UP and RA-UA of
+// the blocks, then per chunk of blocks the sample points, their float32
+// evaluation, statistics, histogram and KL divergences.
+isx_status isx_distribution_kl(isx_ctx* ctx, int32_t mlp_id, int64_t n_blocks, const float* d_centres,
+                               const float* d_halves, int64_t n_samples, int32_t n_bins, int32_t n_fit,
+                               uint64_t seed, double* d_out, uint32_t* d_hist) {
+  Model* m = get_model(ctx, mlp_id);
+  if (!m) return fail(ctx, ISX_EINVAL, "bad mlp id");
+  if (n_blocks < 0 || n_samples < 1 || n_samples >= ((int64_t)1 << 31) || n_bins < 1 || n_bins > 8192 ||
+      n_fit < 1 || n_fit > n_samples)
+    return fail(ctx, ISX_EINVAL, "distribution report: bad sizes");
+  if (n_blocks == 0) return ISX_OK;
+  if (!d_centres || !d_halves || !d_out) return fail(ctx, ISX_EINVAL, "distribution report: null buffer");
+  (void)hipSetDevice(ctx->device);
+  hipStream_t s = ctx->stream;
+  HIPCHK(ensure(ctx->ds_o32, (size_t)n_blocks * 8));
+  HIPCHK(ensure(ctx->ds_up64, (size_t)n_blocks * 16));
+  HIPCHK(ensure(ctx->ds_ra64, (size_t)n_blocks * 16));
+  HIPCHK(ensure(ctx->ds_stats, (size_t)n_blocks * 48));
+  isx_status st = run_propagate(ctx, *m, ISX_UP, ISX_FP64, n_blocks, d_centres, d_halves, (float*)ctx->ds_o32.p,
+                                (double*)ctx->ds_up64.p, 0);
+  if (st != ISX_OK) return st;
+  st = run_propagate(ctx, *m, ISX_RAUA, ISX_FP64, n_blocks, d_centres, d_halves, (float*)ctx->ds_o32.p,
+                     (double*)ctx->ds_ra64.p, 0);
+  if (st != ISX_OK) return st;
+  const int64_t max_samples = (int64_t)1 << 26;
+  const int64_t per = std::max<int64_t>(1, std::min<int64_t>(n_blocks, max_samples / n_samples));
+  HIPCHK(ensure(ctx->ds_pts, (size_t)per * n_samples * 12));
+  HIPCHK(ensure(ctx->ds_vals, (size_t)per * n_samples * 4));
+  for (int64_t b0 = 0; b0 < n_blocks; b0 += per) {
+    const int64_t nb = std::min(per, n_blocks - b0);
+    HIPCHK(launch_dist_points(nb, b0, n_samples, seed, d_centres, d_halves, (float*)ctx->ds_pts.p, s));
+    HIPCHK(eval_f32(ctx, *m, nb * n_samples, (const float*)ctx->ds_pts.p, (float*)ctx->ds_vals.p, s));
+    double* stats = (double*)ctx->ds_stats.p + b0 * 6;
+    HIPCHK(launch_dist_stats(nb, n_samples, n_fit, (const float*)ctx->ds_vals.p, stats, s));
+    HIPCHK(launch_dist_hist_kl(nb, n_samples, n_bins, (const float*)ctx->ds_vals.p, stats,
+                               (const double*)ctx->ds_up64.p + b0 * 2, (const double*)ctx->ds_ra64.p + b0 * 2,
+                               d_out + b0 * ISX_DIST_FIELDS, d_hist ? d_hist + b0 * n_bins : nullptr, s));
+  }
+  return ISX_OK;
+}
+
 // Centre linearisation of n cells: bf16 split where the option and the
 // widths allow, else float32; timed as ISX_KERNEL_LINEARIZE.
 static hipError_t linearize_cells(isx_ctx* ctx, const Model& m, int64_t n, const float* centres,
@@ -788,12 +833,12 @@ static isx_status prop_classify(isx_ctx* ctx, const Model& m, const isx_params* 
   if (st != ISX_OK) return st;
   *n_cancel_out = p->precision == ISX_BF16 ? ctx->n_cancel_last : 0;
   HIPCHK(launch_classify(n, out, k, iso, pmask, mask, s));
-  if (!(p->fp64_band > 0.f) || p->precision == ISX_FP64) return ISX_OK;
+  if (!(p->fp64_band > 0.f || p->fp64_band_rel > 0.f) || p->precision == ISX_FP64) return ISX_OK;
   HIPCHK(ensure(ctx->rc_flags, n * 4));
   HIPCHK(ensure(ctx->rc_fidx, n * 4));
   HIPCHK(ensure(ctx->rc_count, sizeof(int64_t)));
   HIPCHK(ensure(ctx->scan_tmp, compact_tmp_bytes(n)));
-  HIPCHK(launch_band_flags(n, out, k, iso, pmask, p->fp64_band, (uint32_t*)ctx->rc_flags.p, s));
+  HIPCHK(launch_band_flags(n, out, k, iso, pmask, p->fp64_band, p->fp64_band_rel, (uint32_t*)ctx->rc_flags.p, s));
   HIPCHK(launch_compact(n, (const uint32_t*)ctx->rc_flags.p, nullptr, (uint32_t*)ctx->rc_fidx.p, nullptr,
                         (int64_t*)ctx->rc_count.p, ctx->scan_tmp.p, s));
   int64_t n_rc = 0;
@@ -863,7 +908,8 @@ isx_status isx_extract(isx_ctx* ctx, int32_t mlp_id, const isx_params* p, isx_me
     return fail(ctx, ISX_EINVAL, "unknown precision");
   if (p->max_depth < 0 || p->max_depth > 10) return fail(ctx, ISX_EINVAL, "max_depth must be in [0, 10]");
   if (!(p->k >= 0.f) || !std::isfinite(p->k)) return fail(ctx, ISX_EINVAL, "k must be finite and >= 0");
-  if (!(p->fp64_band >= 0.f)) return fail(ctx, ISX_EINVAL, "fp64_band must be >= 0");
+  if (!(p->fp64_band >= 0.f) || !(p->fp64_band_rel >= 0.f) || !std::isfinite(p->fp64_band_rel))
+    return fail(ctx, ISX_EINVAL, "fp64_band and fp64_band_rel must be >= 0");
   if (m.n_iso < 1) return fail(ctx, ISX_EINVAL, "no iso-values set");
   if (p->tree != 0 && p->tree != 1) return fail(ctx, ISX_EINVAL, "tree must be 0 (octree) or 1 (k-d tree)");
   const bool kd = p->tree == 1;

@@ -370,7 +370,7 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
 // endpoint within `band` of a carried iso-value, gather boxes by index, and
 // overwrite the classification of re-checked cells from their float64 bounds.
 hipError_t launch_band_flags(int64_t n, const float* out, float k, const IsoList& iso, const uint32_t* mask_pre,
-                             float band, uint32_t* flags, hipStream_t s);
+                             float band, float band_rel, uint32_t* flags, hipStream_t s);
 hipError_t launch_gather_boxes(int64_t n, const uint32_t* idx, const float* centres, const float* halves,
                                float* c_out, float* h_out, hipStream_t s);
 hipError_t launch_recheck_apply(int64_t n, const uint32_t* idx, const double* out64, double k, const IsoList& iso,
@@ -395,6 +395,15 @@ hipError_t gather_u32(int64_t n, const uint32_t* idx, const uint32_t* src, uint3
 hipError_t scatter_u32(int64_t n, const uint32_t* idx, const uint32_t* src, uint32_t* dst, hipStream_t s);
 hipError_t scatter_u64(int64_t n, const uint32_t* idx, const uint64_t* src, uint64_t* dst, hipStream_t s);
 
+// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): the output for state x,
+// so that output n of the stream with seed s is splitmix64(s + n * golden).
+__host__ __device__ inline uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
 // ---- surrogate training set and band calibration (kernels_calib.hip) ----
 hipError_t launch_sample_cells(int64_t n, uint64_t seed, const float lo[3], const float hi[3], int level_lo,
                                int level_hi, const uint32_t* vis_ids, const int64_t* vis_off, int vis_levels,
@@ -406,6 +415,15 @@ hipError_t launch_calib_count(int64_t n, const float* pred, const float* targ, c
                               const float* ladder, int n_z, unsigned long long* counts, unsigned long long* kept,
                               hipStream_t s);
 void host_normal_fill(uint64_t seed, float stddev, float* out, int64_t n);
+
+// ---- distribution-quality report (kernels_dist.hip) ----
+// Sample points of blocks b0 .. b0 + nb - 1 (SplitMix64 counters), their
+// statistics, and the histogram with the KL divergences of Eq. 11.
+hipError_t launch_dist_points(int64_t nb, int64_t b0, int64_t ns, uint64_t seed, const float* centres,
+                              const float* halves, float* pts, hipStream_t s);
+hipError_t launch_dist_stats(int64_t nb, int64_t ns, int n_fit, const float* vals, double* stats, hipStream_t s);
+hipError_t launch_dist_hist_kl(int64_t nb, int64_t ns, int n_bins, const float* vals, const double* stats,
+                               const double* up64, const double* raua64, double* out, uint32_t* hist, hipStream_t s);
 
 // ---- marching-cubes case table (mc_table.cpp) ----
 struct McTable {

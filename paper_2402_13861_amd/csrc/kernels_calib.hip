@@ -23,13 +23,6 @@
 
 namespace isx {
 
-__host__ __device__ inline uint64_t splitmix64(uint64_t x) {
-  x += 0x9E3779B97F4A7C15ull;
-  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
-  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
-  return x ^ (x >> 31);
-}
-
 // uniform double in [0, 1) from draw `stream` of cell i
 __device__ inline double unit_draw(uint64_t seed, int64_t i, int stream) {
   const uint64_t r = splitmix64(seed + (uint64_t)(4 * i + stream) * 0x9E3779B97F4A7C15ull);

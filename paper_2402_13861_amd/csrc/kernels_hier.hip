@@ -596,27 +596,29 @@ namespace isx {
 // iso-value they still carry are re-propagated in float64, and the float64
 // bound decides their mask.
 __global__ void band_flags_kernel(int64_t n, const float* __restrict__ out, float k, IsoList iso,
-                                  const uint32_t* __restrict__ pmask, float band, uint32_t* __restrict__ flags) {
+                                  const uint32_t* __restrict__ pmask, float band, float band_rel,
+                                  uint32_t* __restrict__ flags) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float c = out[2 * i], s = out[2 * i + 1];
   const float ks = __fmul_rn(k, s);
   const float lo = __fsub_rn(c, ks), hi = __fadd_rn(c, ks);
   const uint32_t pm = pmask ? pmask[i] : 0xffffffffu;
+  const float bw = band + band_rel * s;  // this cell's band
   uint32_t f = 0;
   for (int j = 0; j < iso.n; ++j) {
     if (!((pm >> j) & 1u)) continue;
     const float d = fminf(fabsf(lo - iso.c[j]), fabsf(hi - iso.c[j]));
-    if (!(d > band)) f = 1;  // also catches NaN
+    if (!(d > bw)) f = 1;  // also catches NaN
   }
   flags[i] = f;
 }
 
 hipError_t launch_band_flags(int64_t n, const float* out, float k, const IsoList& iso, const uint32_t* pmask,
-                             float band, uint32_t* flags, hipStream_t s) {
+                             float band, float band_rel, uint32_t* flags, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(band_flags_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, out, k, iso, pmask,
-                     band, flags);
+                     band, band_rel, flags);
   return hipGetLastError();
 }
 

@@ -18,6 +18,7 @@ import numpy as np
 
 from oracle.mlp import mlp_forward
 
+from .batch import batch_mlps, batch_shapes
 from .cells import uniform_points
 from .configs import WORKLOADS, load_mlp
 
@@ -42,6 +43,15 @@ def main():
             mean=float(np.mean(vals)),
         )
         print(name, table[name])
+    # the batched workload: per INR, iso-values at its own quantile levels
+    # over the points of seed 3 + i + 1
+    batch = []
+    for i, (mlp, (_, qs)) in enumerate(zip(batch_mlps(), batch_shapes())):
+        vals = mlp_forward(mlp, uniform_points(10_000, 3 + i + 1))
+        isos = [float(np.float32(v)) for v in np.quantile(vals, qs, method="linear")]
+        batch.append(dict(iso=isos, scale=float(np.std(vals)), mean=float(np.mean(vals))))
+    table["batch64"] = batch
+    print("batch64:", len(batch), "INRs")
     OUT.write_text(json.dumps(table, indent=1) + "\n")
     print("wrote", OUT)
 
