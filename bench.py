@@ -417,6 +417,87 @@ def batch_bench(a, log):
     return 0
 
 
+def camera_rays(res: int, eye=(1.3, 0.8, 2.3), fov_deg: float = 42.0):
+    """Pinhole camera looking at the origin (up = +y), one ray per pixel
+    centre, clipped to the domain [-1, 1]^3 by the slab test; float32 arrays
+    (origins, unit directions, t_near, t_far)."""
+    import numpy as np
+
+    eye = np.array(eye, np.float64)
+    fwd = -eye / np.linalg.norm(eye)
+    right = np.cross(fwd, [0.0, 1.0, 0.0])
+    right /= np.linalg.norm(right)
+    up = np.cross(right, fwd)
+    half = np.tan(np.radians(fov_deg) / 2)
+    u = ((np.arange(res) + 0.5) / res * 2 - 1) * half
+    X, Y = np.meshgrid(u, -u, indexing="xy")
+    d = fwd[None, :] + X.reshape(-1, 1) * right[None, :] + Y.reshape(-1, 1) * up[None, :]
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        inv = 1.0 / d
+        t0 = (-1.0 - eye) * inv
+        t1 = (1.0 - eye) * inv
+    tn = np.maximum(np.nanmax(np.minimum(t0, t1), axis=1), 0.0)
+    tf = np.nanmin(np.maximum(t0, t1), axis=1)
+    tf = np.maximum(tf, tn)
+    org = np.tile(eye, (res * res, 1))
+    return org.astype(np.float32), d.astype(np.float32), tn.astype(np.float32), tf.astype(np.float32)
+
+
+def raycast_bench(a, log):
+    """App. A's ray casting on the two SDF INRs (ReLU 3->64->64->48->1 at
+    512^2, ELU 3->128->128->96->1 at 400^2): frame time, segments bounded and
+    agreement with RA-Full's image, for UP at several t, RA-Full (AA) and
+    RA-Fixed, float32.  Prints one JSON line."""
+    import numpy as np
+    import torch
+
+    import paper_2402_13861_amd as isx
+    from workloads.configs import WORKLOADS, load_mlp
+
+    ctx = isx.Context(0)
+    res_all = {}
+    for name, res in (("relu_sdf_7k", 512), ("elu_sdf_29k", 400)):
+        w = WORKLOADS[name]
+        mlp = load_mlp(name, a.sdf_weights_dir)
+        mid = ctx.load_weights(mlp)
+        if w.get("act") == "elu":
+            ctx.set_activation(mid, isx.ELU)
+        org, d, tn, tf = (torch.from_numpy(x).cuda() for x in camera_rays(res))
+        runs = [("ra-full", isx.AA, 1.0), ("ra-fixed", isx.RAFIXED, 1.0)]
+        runs += [(f"up-t{t}", isx.UP, float(t)) for t in (2, 3, 4, 5)]
+        ref = None
+        rows = []
+        for label, meth, t in runs:
+            kw = dict(method=meth, precision=isx.FP32, k=t, iso=0.0, step0=1 / 16, step_min=1 / 2048, step_max=0.5,
+                      max_iter=2000)
+            ctx.raycast(mid, org, d, tn, tf, **kw)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            thit, steps, nseg, nsteps = ctx.raycast(mid, org, d, tn, tf, **kw)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0)
+            th = thit.cpu().numpy()
+            hit = np.isfinite(th)
+            row = dict(method=label, t=t, ms=round(ms, 2), segments=nseg, max_steps=nsteps, hits=int(hit.sum()))
+            if ref is None:
+                ref = th
+            else:
+                rh = np.isfinite(ref)
+                row["missing_vs_ra_full"] = int((rh & ~hit).sum())
+                row["extra_vs_ra_full"] = int((~rh & hit).sum())
+                both = rh & hit
+                row["mean_abs_dt_vs_ra_full"] = float(np.abs(th[both] - ref[both]).mean()) if both.any() else None
+            rows.append(row)
+            log(f"raycast {name} {res}^2 {label}: {ms:.1f} ms, {nseg} segments, {int(hit.sum())} hits")
+        res_all[name] = dict(resolution=res, widths=mlp.widths, act=w.get("act", "relu"), runs=rows)
+        ctx.unload_mlp(mid)
+    print(json.dumps({"raycast": res_all, "precision": "fp32", "step0": 1 / 16, "step_min": 1 / 2048,
+                      "step_max": 0.5}), flush=True)
+    ctx.close()
+    return 0
+
+
 def copy_probe(nbytes: int, reps: int = 5):
     """A plain device-to-device copy of known size: the reference that scales
     the HBM byte counters (FETCH_SIZE, WRITE_SIZE) read for the kernels."""
@@ -460,6 +541,9 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--t-sweep", action="store_true",
                     help="only run the sweep of t (time against missed iso-voxels) and exit")
+    ap.add_argument("--raycast", action="store_true",
+                    help="only run ray casting of the two SDF INRs (UP, RA-Full, RA-Fixed) and exit")
+    ap.add_argument("--sdf-weights-dir", default=None, help="directory of the SDF weight files (default: workloads/data)")
     ap.add_argument("--batch", action="store_true",
                     help="only run the batched 64-INR workload (isx_extract_batch) and exit")
     ap.add_argument("--batch-inrs", type=int, default=64)
@@ -490,6 +574,8 @@ def main(argv=None):
         return kl_report(a, log)
     if a.batch:
         return batch_bench(a, log)
+    if a.raycast:
+        return raycast_bench(a, log)
 
     import numpy as np
     import torch
@@ -736,6 +822,7 @@ def main(argv=None):
         "surrogate": sur_info,
         "examined_cells": examined,
         "propagated_cells": propagated,
+        "rechecked_cells": int(rechecked),
         "propagated_cells_per_s": propagated / acp_s if acp_s > 0 else None,
         "active_leaves": runs[-1]["leaves"],
         "triangles": runs[-1]["tris"],

@@ -54,8 +54,13 @@ typedef enum {
  * analysis read off under the uniform assumption ("RA-UA", Sec. IV-A,
  * Eq. 5): the affine form of AA, its symbols taken as independent uniform
  * variables on [-1, 1], gives N(x0, sum_i x_i^2 / 3), whose soft bound is
- * [x0 - t sigma, x0 + t sigma] as for UP. */
-typedef enum { ISX_AA = 0, ISX_UP = 1, ISX_RAUA = 2 } isx_method;
+ * [x0 - t sigma, x0 + t sigma] as for UP.  "RA-Fixed" (the reduced affine form
+ * App. A compares against): affine arithmetic that keeps the input symbols
+ * and folds every symbol an activation creates into one error magnitude per
+ * neuron (a linear layer maps it by |W|); its hard range is
+ * [x0 - r, x0 + r].  The affine rule of every activation is that of
+ * ISX_AA (Eq. 4). */
+typedef enum { ISX_AA = 0, ISX_UP = 1, ISX_RAUA = 2, ISX_RAFIXED = 3 } isx_method;
 
 /* Arithmetic of the propagation and evaluation kernels.
  *   ISX_FP32: float32 everywhere; hidden-layer products on FP32 MFMA.
@@ -182,6 +187,47 @@ isx_status isx_eval_points(isx_ctx* ctx, int32_t mlp_id, isx_precision precision
  * Errors: ISX_EINVAL, ISX_EHIP. */
 isx_status isx_linearize(isx_ctx* ctx, int32_t mlp_id, int64_t n, const float* d_centres,
                          const float* d_halves, float* d_out);
+
+/* isx_propagate_segments: isx_propagate for line segments instead of boxes
+ * (App. A's ray casting): segment i is {c_i + e v_i : e in [-1, 1]}, d_centres
+ * [n][3] its centre and d_halfvec [n][3] its half-vector v_i (float32,
+ * device).  It has one input symbol e, with coefficient v (AA, RA-UA,
+ * RA-Fixed; range analysis) or v / sqrt 3 (UP: uniform on [-1, 1]).  Methods
+ * ISX_AA, ISX_UP, ISX_RAUA, ISX_RAFIXED; precisions ISX_FP32 and ISX_FP64
+ * (ISX_BF16 and the AA rounding margin: ISX_EUNSUPPORTED).  Output as
+ * isx_propagate.  Asynchronous.  Errors: ISX_EINVAL, ISX_EUNSUPPORTED,
+ * ISX_EHIP. */
+isx_status isx_propagate_segments(isx_ctx* ctx, int32_t mlp_id, isx_method method, isx_precision precision,
+                                  int64_t n, const float* d_centres, const float* d_halfvec, float* d_out,
+                                  double* d_out64);
+
+/* Ray casting of the level set f = iso (App. A, following the range-analysis
+ * ray caster it compares with).  Ray i starts at t = d_tnear[i] with step
+ * step0 and marches along o_i + t d_i (d_origins, d_dirs [n][3], float32;
+ * unit directions expected) until t_far = d_tfar[i]: the segment
+ * [t, t + de], de = min(step, t_far - t), is bounded by `method` at
+ * `precision` (isx_propagate_segments; UP and RA-UA: centre -/+ k spread, AA
+ * and RA-Fixed: the hard range).  If the bound excludes iso, t += de and the
+ * step doubles (at most step_max), the ray missing once t >= t_far;
+ * otherwise the ray hits at t + de / 2 if de <= step_min, else the step
+ * becomes de / 2.  Ray state (t, step) is float64; segment centres and
+ * half-vectors are formed in float64 and rounded to float32; with ISX_FP64
+ * the float64 bounds decide.  d_thit [n] (float32) gets the hit distance or
+ * NaN (miss, empty ray, or not finished after max_iter steps), d_iters [n]
+ * the steps each ray took; h_stats[2] (host, optional) the segments bounded
+ * and the steps taken by the slowest ray.  Synchronises once per step.
+ * Errors: ISX_EINVAL, ISX_EUNSUPPORTED (ISX_BF16), ISX_EHIP. */
+typedef struct {
+  isx_method method;
+  isx_precision precision;  /* ISX_FP32 or ISX_FP64 */
+  float k;                  /* t of the soft bound (UP, RA-UA) */
+  float iso;                /* the level (0 for a signed distance function) */
+  float step0, step_min, step_max;
+  int32_t max_iter;
+} isx_ray_params;
+isx_status isx_raycast(isx_ctx* ctx, int32_t mlp_id, const isx_ray_params* params, int64_t n_rays,
+                       const float* d_origins, const float* d_dirs, const float* d_tnear, const float* d_tfar,
+                       float* d_thit, int32_t* d_iters, int64_t* h_stats);
 
 /* Parameters of a full extraction. */
 typedef struct {
@@ -505,13 +551,17 @@ typedef enum {
                               paper's rule (exact arithmetic assumed) evaluated in floating point */
   ISX_BATCH_WORKERS = 10,  /* isx_extract_batch: worker contexts (streams) that run INRs at once, 1..16
                               (default 4) */
-  ISX_CANCEL_CHECK = 11    /* bf16 uncertainty propagation in covariance form: 1 (default) = a cell with a
+  ISX_CANCEL_CHECK = 11,   /* bf16 uncertainty propagation in covariance form: 1 (default) = a cell with a
                               neuron whose variance sum v = sum_i T_ji W_ji (signed, over bfloat16-rounded
                               covariances) keeps at most 2^-9 of the magnitude a = sum_i |T_ji W_ji| of its
                               terms (Eq. 7 needs the variance; such a sum can lose every digit) while its
                               pre-activation y has |y| < 6 sqrt(max(v, 0) + 2^-7 a) (the ReLU rule of Eq. 9
                               depends on sigma there) is propagated again in float64, and its float64
                               (mu, sigma) is returned; 0 = off */
+  ISX_AUTOTUNE = 12        /* bf16 coefficient-form propagation: 1 = pick the hidden-layer tile shape of
+                              each MLP by timing the shapes (1, 3, 4 and the default) on 4096 sample
+                              cells at its first such propagation (the shapes give identical results);
+                              0 (default) = the default shape for the width, or ISX_BF16_VARIANT */
 } isx_option;
 isx_status isx_set_option(isx_ctx* ctx, isx_option option, int64_t value);
 

@@ -50,6 +50,7 @@ from .rules import aa_rule, relu_aa_rule, relu_up_rule, up_rule
 AA = "aa"
 UP = "up"
 RAUA = "raua"  # AA propagation, uniform-assumption read-off (Sec. IV-A)
+RAFIXED = "rafixed"  # input symbols kept, created symbols folded into one error term (App. A)
 
 
 def _chunk_for(layers, budget_bytes=2.0e8):
@@ -72,15 +73,20 @@ def margin_const(K, u, u_b=0.0):
     return 2.0 * u_b + u_b * u_b + gamma_n(K + 1, u) * (1.0 + u_b) ** 2
 
 
-def _track(layers, centres, halves, method, keep_hidden=False, margin=False, act="relu"):
+def _track(layers, centres, halves, method, keep_hidden=False, margin=False, act="relu", F0=None):
     """Coefficient tracking for one chunk of boxes; returns (centre, spread)
-    and optionally per-hidden-layer (pre-activation centre, row statistic)."""
+    and optionally per-hidden-layer (pre-activation centre, row statistic).
+    F0: an input coefficient block [C, 3, N0] in place of the box's
+    diag(halves) (UP's 1/sqrt 3 included by the caller)."""
     C = centres.shape[0]
     s = 1.0 if method in (AA, RAUA) else 1.0 / np.sqrt(3.0)
     x0 = centres.copy()
-    F = np.zeros((C, 3, 3))
-    for i in range(3):
-        F[:, i, i] = halves[:, i] * s
+    if F0 is not None:
+        F = np.array(F0, dtype=np.float64)
+    else:
+        F = np.zeros((C, 3, 3))
+        for i in range(3):
+            F[:, i, i] = halves[:, i] * s
     hidden = []
     last = len(layers) - 1
     for li, (W, b) in enumerate(layers):
@@ -149,6 +155,50 @@ def propagate(layers, centres, halves, method: str, chunk: int | None = None, ma
     if not cs:
         return np.zeros(0), np.zeros(0)
     return np.concatenate(cs), np.concatenate(ss)
+
+
+def propagate_segments(layers, centres, halfvecs, method: str, act: str = "relu"):
+    """Propagate line segments {c + e v : e in [-1, 1]} (App. A's ray
+    casting): one input symbol e, coefficient v (range analysis) or v/sqrt 3
+    (UP: e uniform on [-1, 1]).  ``method``: AA, UP, RAUA or RAFIXED.
+    Returns float64 (centre [C], spread [C])."""
+    layers = as_f64_layers(layers)
+    centres = np.asarray(centres, dtype=np.float64).reshape(-1, 3)
+    v = np.asarray(halfvecs, dtype=np.float64).reshape(-1, 3)
+    if method == RAFIXED:
+        return propagate_rafixed(layers, centres, v[:, :, None], act=act)
+    s = 1.0 if method in (AA, RAUA) else 1.0 / np.sqrt(3.0)
+    if centres.shape[0] == 0:
+        return np.zeros(0), np.zeros(0)
+    c, sp, _ = _track(layers, centres, None, method, act=act, F0=v[:, :, None] * s)
+    return c, sp
+
+
+def propagate_rafixed(layers, centres, F0, act: str = "relu"):
+    """RA-Fixed (the reduced affine form App. A compares with): the input
+    symbols' coefficients A [C, n, N0] are tracked exactly, every symbol an
+    activation creates is folded into one error magnitude e [C, n] per
+    neuron.  Linear: x0 <- W x0 + b, A <- W A, e <- |W| e.  Activation: the
+    affine rule of Eq. 4 on the range x0 -/+ (sum |A| + e), then
+    x0 <- alpha x0 + beta, A <- alpha A, e <- |alpha| e + |gamma|.  Output:
+    (x0, sum |A| + e), the hard range's centre and radius."""
+    layers = as_f64_layers(layers)
+    x0 = np.asarray(centres, dtype=np.float64).reshape(-1, 3).copy()
+    A = np.array(F0, dtype=np.float64)
+    e = np.zeros(x0.shape)
+    last = len(layers) - 1
+    for li, (W, b) in enumerate(layers):
+        x0 = x0 @ W.T + b
+        A = np.matmul(W, A)
+        e = e @ np.abs(W).T
+        r = np.abs(A).sum(axis=2) + e
+        if li == last:
+            return x0[:, 0], r[:, 0]
+        alpha, beta, gamma = aa_rule(act, x0, r)
+        x0 = alpha * x0 + beta
+        A = alpha[:, :, None] * A
+        e = np.abs(alpha) * e + np.abs(gamma)
+    raise AssertionError("unreachable")
 
 
 def propagate_hidden(layers, centres, halves, method: str, act: str = "relu"):

@@ -20,8 +20,8 @@ from typing import Optional, Sequence
 import numpy as np
 
 from . import _lib
-from ._lib import (AA, RAUA, RELU, SINE, ELU, BF16, BF16_VARIANT, FP32, FP64, HIDDEN_KERNEL, KEEP_LEVELS, PROFILE, SCRATCH_BYTES, UP,
-                   UP_FORM, LIN_PRECISION, AA_MARGIN, BATCH_WORKERS, VERBOSE, CANCEL_CHECK)
+from ._lib import (AA, RAUA, RAFIXED, RELU, SINE, ELU, BF16, BF16_VARIANT, FP32, FP64, HIDDEN_KERNEL, KEEP_LEVELS, PROFILE, SCRATCH_BYTES, UP,
+                   UP_FORM, LIN_PRECISION, AA_MARGIN, BATCH_WORKERS, VERBOSE, CANCEL_CHECK, AUTOTUNE)
 
 # columns of isx_distribution_kl's report (isx_dist_field order)
 DIST_FIELDS = ("mc_mean", "mc_std", "lo", "hi", "up_mu", "up_sigma", "raua_mu", "raua_sigma", "fit_mu", "fit_sigma",
@@ -29,7 +29,7 @@ DIST_FIELDS = ("mc_mean", "mc_std", "lo", "hi", "up_mu", "up_sigma", "raua_mu", 
 KERNEL_KINDS = ("hidden_fp32", "hidden_bf16", "hidden_simt_fp32", "hidden_fp64", "dense", "output",
                 "hidden_cov_bf16", "linearize")
 
-__all__ = ["Context", "Mesh", "IsxError", "AA", "UP", "RAUA", "RELU", "SINE", "ELU", "FP32", "BF16", "FP64", "KEEP_LEVELS", "HIDDEN_KERNEL",
+__all__ = ["Context", "Mesh", "IsxError", "AA", "UP", "RAUA", "RAFIXED", "RELU", "SINE", "ELU", "FP32", "BF16", "FP64", "KEEP_LEVELS", "HIDDEN_KERNEL",
            "PROFILE", "SCRATCH_BYTES", "VERBOSE", "BF16_VARIANT", "mc_case_table"]
 
 
@@ -290,6 +290,44 @@ class Context:
         self._chk(self._L.isx_surrogate_partition(self._h, mlp_id, n, _ptr(pred), _ptr(unit), float(k), int(level),
                                                   int(bool(leaf)), _ptr(parent_mask), _ptr(mask), _ptr(fb)))
         return mask[:n], fb[:n]
+
+    def propagate_segments(self, mlp_id: int, method: int, precision: int, centres, halfvec, out, out64=None):
+        """isx_propagate_segments on device tensors: centres and half-vectors
+        float32 [n, 3], out float32 [n, 2] (and float64 out64 with FP64)."""
+        import torch
+
+        _check_dev(centres, torch.float32, "centres", (3,))
+        _check_dev(halfvec, torch.float32, "halfvec", (3,))
+        _check_dev(out, torch.float32, "out", (2,))
+        _check_dev(out64, torch.float64, "out64", (2,))
+        n = centres.shape[0]
+        if halfvec.shape[0] != n or out.shape[0] != n or (out64 is not None and out64.shape[0] != n):
+            raise ValueError("centres, halfvec and out must have the same length")
+        self._chk(self._L.isx_propagate_segments(self._h, mlp_id, method, precision, n, _ptr(centres), _ptr(halfvec),
+                                                 _ptr(out), _ptr(out64)))
+
+    def raycast(self, mlp_id: int, origins, dirs, tnear, tfar, method: int = UP, precision: int = FP32,
+                k: float = 3.0, iso: float = 0.0, step0: float = 1.0 / 16, step_min: float = 1.0 / 1024,
+                step_max: float = 0.5, max_iter: int = 1000):
+        """isx_raycast on device tensors origins/dirs float32 [n, 3], tnear/tfar
+        float32 [n]; returns (t_hit float32 [n] with NaN for no hit, steps
+        int32 [n], segments bounded, steps of the slowest ray)."""
+        import torch
+
+        _check_dev(origins, torch.float32, "origins", (3,))
+        _check_dev(dirs, torch.float32, "dirs", (3,))
+        n = origins.shape[0]
+        for name, t in (("dirs", dirs), ("tnear", tnear), ("tfar", tfar)):
+            if t.shape[0] != n:
+                raise ValueError(f"{name} must have one row per ray")
+        thit = torch.empty(max(n, 1), dtype=torch.float32, device=origins.device)
+        iters = torch.empty(max(n, 1), dtype=torch.int32, device=origins.device)
+        p = _lib.RayParams(method, precision, float(k), float(iso), float(step0), float(step_min), float(step_max),
+                           int(max_iter))
+        stats = (C.c_int64 * 2)()
+        self._chk(self._L.isx_raycast(self._h, mlp_id, C.byref(p), n, _ptr(origins), _ptr(dirs), _ptr(tnear),
+                                      _ptr(tfar), _ptr(thit), _ptr(iters), stats))
+        return thit[:n], iters[:n], int(stats[0]), int(stats[1])
 
     def distribution_kl(self, mlp_id: int, centres, halves, n_samples: int = 1_000_000, n_bins: int = 100,
                         n_fit: int = 100, seed: int = 0, with_hist: bool = False):

@@ -16,11 +16,11 @@ STATUS_NAMES = {
     0: "ISX_OK", -1: "ISX_EINVAL", -2: "ISX_ESHAPE", -3: "ISX_ENOMEM", -4: "ISX_ECAPACITY",
     -5: "ISX_EHIP", -6: "ISX_ENAN", -7: "ISX_EUNSUPPORTED",
 }
-AA, UP, RAUA = 0, 1, 2
+AA, UP, RAUA, RAFIXED = 0, 1, 2, 3
 RELU, SINE, ELU = 0, 1, 2
 FP32, BF16, FP64 = 0, 1, 2
 (KEEP_LEVELS, HIDDEN_KERNEL, PROFILE, SCRATCH_BYTES, VERBOSE, BF16_VARIANT, UP_FORM, LIN_PRECISION,
- AA_MARGIN, BATCH_WORKERS, CANCEL_CHECK) = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11
+ AA_MARGIN, BATCH_WORKERS, CANCEL_CHECK, AUTOTUNE) = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12
 MAX_LINEAR, MAX_WIDTH, MAX_ISO = 16, 1024, 32
 NOALLOC_MAX_CELLS = 1 << 22
 (KERNEL_HIDDEN_FP32, KERNEL_HIDDEN_BF16, KERNEL_HIDDEN_SIMT_FP32, KERNEL_HIDDEN_FP64, KERNEL_DENSE,
@@ -65,6 +65,19 @@ class SurrogateFitParams(C.Structure):
     ]
 
 
+class RayParams(C.Structure):
+    _fields_ = [
+        ("method", C.c_int),
+        ("precision", C.c_int),
+        ("k", C.c_float),
+        ("iso", C.c_float),
+        ("step0", C.c_float),
+        ("step_min", C.c_float),
+        ("step_max", C.c_float),
+        ("max_iter", C.c_int32),
+    ]
+
+
 class Params(C.Structure):
     _fields_ = [
         ("method", C.c_int),
@@ -99,6 +112,10 @@ _SIGS = [
                                                C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("isx_eval_points", C.c_int, [C.c_void_p, C.c_int32, C.c_int, C.c_int64, C.c_void_p, C.c_void_p]),
     ("isx_linearize", C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("isx_propagate_segments", C.c_int, [C.c_void_p, C.c_int32, C.c_int, C.c_int, C.c_int64, C.c_void_p, C.c_void_p,
+                                         C.c_void_p, C.c_void_p]),
+    ("isx_raycast", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(RayParams), C.c_int64, C.c_void_p, C.c_void_p,
+                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int64)]),
     ("isx_distribution_kl", C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.c_int64,
                                       C.c_int32, C.c_int32, C.c_uint64, C.c_void_p, C.c_void_p]),
     ("isx_extract", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Params), C.POINTER(C.c_void_p)]),

@@ -86,6 +86,9 @@ struct isx_ctx {
   bool verbose = false;
   int kernel_choice = 0;
   int bf16_variant = 0;
+  int autotune = 0;   // ISX_AUTOTUNE
+  bool tuning = false;
+  Buf tune_c, tune_h, tune_out;
   int up_form = 0;
   int lin_prec = 1;  // centre linearisation: 1 = bf16 split where supported, 0 = float32
   int aa_margin = 0; // AA: widen by the rounding margin
@@ -110,6 +113,8 @@ struct isx_ctx {
   Buf sp_vis, sp_vis_off, cal_pred, cal_unit, cal_part, cal_cnt, cal_vec, fit_c, fit_h, fit_t, fit_l, fit_loss;
   // distribution-quality report
   Buf ds_pts, ds_vals, ds_stats, ds_o32, ds_up64, ds_ra64;
+  // ray casting
+  Buf ray_t, ray_dt, ray_act, ray_idx, ray_c, ray_v, ray_o32, ray_o64, ray_cnt;
   int64_t* h_count = nullptr;  // pinned
   Profiler prof;
   // batched extraction: worker contexts with their own stream and scratch;
@@ -228,7 +233,8 @@ int64_t chunk_for(isx_ctx* ctx, const Model& m, int64_t n, int64_t req) {
 }
 
 isx_status run_propagate(isx_ctx* ctx, const Model& m, isx_method method, isx_precision prec, int64_t n,
-                         const float* centres, const float* halves, float* out, double* out64, int64_t chunk_req);
+                         const float* centres, const float* halves, float* out, double* out64, int64_t chunk_req,
+                         int seg = 0);
 
 // Cells whose covariance-form variance sums cancelled (flags[i] != 0) are
 // propagated again in float64 and their (mu, sigma) replaced.  Synchronises
@@ -259,11 +265,91 @@ isx_status recheck_cancelled(isx_ctx* ctx, const Model& m, int64_t n, const floa
   return ISX_OK;
 }
 
+// Tile shape of the bf16 coefficient-form hidden-layer kernel for this MLP:
+// each candidate propagates the same 4096 cells (octree levels 3..6 of the
+// domain, SplitMix64 positions) once untimed and twice timed with HIP
+// events; the fastest is kept in the model.  The shapes only split the same
+// products differently, so they give identical results.
+static isx_status tune_bf16(isx_ctx* ctx, const Model& m) {
+  if (m.bf16_tuned >= 0) return ISX_OK;
+  constexpr int kN = 4096;
+  std::vector<float> hc(3 * kN), hh(3 * kN);
+  for (int i = 0; i < kN; ++i) {
+    const int L = 3 + (int)(splitmix64(0x5eedull + 4ull * i) % 4ull);
+    const int64_t res = (int64_t)1 << L;
+    for (int a = 0; a < 3; ++a) {
+      const int64_t q = (int64_t)(splitmix64(0x5eedull + 4ull * i + 1ull + (uint64_t)a) % (uint64_t)res);
+      const double ext = (double)m.hi[a] - m.lo[a];
+      hh[3 * i + a] = (float)(0.5 * ext / (double)res);
+      hc[3 * i + a] = (float)((double)m.lo[a] + ext * ((double)q + 0.5) / (double)res);
+    }
+  }
+  HIPCHK(ensure(ctx->tune_c, sizeof(float) * 3 * kN));
+  HIPCHK(ensure(ctx->tune_h, sizeof(float) * 3 * kN));
+  HIPCHK(ensure(ctx->tune_out, sizeof(float) * 2 * kN));
+  hipStream_t s = ctx->stream;
+  HIPCHK(hipMemcpyAsync(ctx->tune_c.p, hc.data(), sizeof(float) * 3 * kN, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ctx->tune_h.p, hh.data(), sizeof(float) * 3 * kN, hipMemcpyHostToDevice, s));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const int saved = ctx->bf16_variant, saved_form = ctx->up_form;
+  const bool saved_prof = ctx->prof.on;
+  ctx->tuning = true;
+  ctx->prof.on = false;
+  ctx->up_form = 1;  // the coefficient form, whose kernel the shapes belong to
+  int best = 0;
+  float best_ms = 0.f;
+  isx_status st = ISX_OK;
+  for (int v : {0, 1, 3, 4}) {
+    ctx->bf16_variant = v;
+    float ms = 0.f;
+    for (int rep = 0; rep < 3 && st == ISX_OK; ++rep) {
+      if (rep == 1) (void)hipEventRecord(e0, s);
+      st = run_propagate(ctx, m, ISX_UP, ISX_BF16, kN, (const float*)ctx->tune_c.p, (const float*)ctx->tune_h.p,
+                         (float*)ctx->tune_out.p, nullptr, 0);
+    }
+    if (st != ISX_OK) break;
+    (void)hipEventRecord(e1, s);
+    (void)hipEventSynchronize(e1);
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    m.bf16_tune_ms[v] = ms / 2.f;
+    if (v == 0 || ms < best_ms) {
+      best = v;
+      best_ms = ms;
+    }
+  }
+  ctx->bf16_variant = saved;
+  ctx->up_form = saved_form;
+  ctx->tuning = false;
+  ctx->prof.on = saved_prof;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != ISX_OK) return st;
+  m.bf16_tuned = best;
+  if (ctx->verbose) {
+    std::fprintf(stderr, "isx: bf16 tile shape %d picked (ms per 4096 cells: default %.3f, 1 %.3f, 3 %.3f, 4 %.3f)\n",
+                 best, m.bf16_tune_ms[0], m.bf16_tune_ms[1], m.bf16_tune_ms[3], m.bf16_tune_ms[4]);
+    std::fflush(stderr);
+  }
+  return ISX_OK;
+}
+
 isx_status run_propagate(isx_ctx* ctx, const Model& m, isx_method method, isx_precision prec, int64_t n,
-                         const float* centres, const float* halves, float* out, double* out64, int64_t chunk_req) {
+                         const float* centres, const float* halves, float* out, double* out64, int64_t chunk_req,
+                         int seg) {
   if (n <= 0) return ISX_OK;
   const bool marg = method == ISX_AA && ctx->aa_margin != 0;
   if (marg && m.act != ISX_RELU) return fail(ctx, ISX_EUNSUPPORTED, "the AA rounding margin needs a ReLU net");
+  if (seg && (marg || prec == ISX_BF16))
+    return fail(ctx, ISX_EUNSUPPORTED, "segments take float32 or float64 without the AA rounding margin");
+  if (method == ISX_RAFIXED) {
+    // one SIMT pass per cell: the form is the input symbols and one error term
+    if (prec == ISX_BF16) return fail(ctx, ISX_EUNSUPPORTED, "RA-Fixed runs in float32 or float64");
+    HIPCHK(launch_rafixed(m, prec == ISX_FP64, n, centres, halves, seg, out, prec == ISX_FP64 ? out64 : nullptr,
+                          ctx->stream));
+    return ISX_OK;
+  }
   if (prec == ISX_FP64) {
     const int64_t chunk = chunk_for<double>(ctx, m, n, chunk_req);
     PropWork<double> w;
@@ -277,6 +363,7 @@ isx_status run_propagate(isx_ctx* ctx, const Model& m, isx_method method, isx_pr
       PropArgs a{&m, method, std::min(chunk, n - s), centres + 3 * s, halves + 3 * s, out + 2 * s,
                  out64 ? out64 + 2 * s : nullptr, ctx->kernel_choice, ctx->stream, &ctx->prof, ctx->bf16_variant};
       a.aa_margin = marg;
+      a.seg = seg;
       HIPCHK(propagate_f64(a, w));
     }
     return ISX_OK;
@@ -299,10 +386,16 @@ isx_status run_propagate(isx_ctx* ctx, const Model& m, isx_method method, isx_pr
     w.vec = (float*)ctx->vec32.p;
     const bool check = cov && ctx->cancel_check != 0;
     if (check) HIPCHK(ensure(ctx->cx_flags, n * 4));
+    int variant = ctx->bf16_variant;
+    if (variant == 0 && !cov && ctx->autotune && !ctx->tuning) {
+      const isx_status st = tune_bf16(ctx, m);
+      if (st != ISX_OK) return st;
+      variant = m.bf16_tuned;
+    }
     uint16_t* Fbf[2] = {(uint16_t*)ctx->Fbf[0].p, (uint16_t*)ctx->Fbf[1].p};
     for (int64_t s = 0; s < n; s += chunk) {
       PropArgs a{&m, method, std::min(chunk, n - s), centres + 3 * s, halves + 3 * s, out + 2 * s, nullptr,
-                 ctx->kernel_choice, ctx->stream, &ctx->prof, ctx->bf16_variant, ctx->up_form};
+                 ctx->kernel_choice, ctx->stream, &ctx->prof, variant, ctx->up_form};
       a.aa_margin = marg;
       if (check) a.cancel = (uint32_t*)ctx->cx_flags.p + s;
       HIPCHK(propagate_bf16(a, w, Fbf, 0));
@@ -323,6 +416,7 @@ isx_status run_propagate(isx_ctx* ctx, const Model& m, isx_method method, isx_pr
     PropArgs a{&m, method, std::min(chunk, n - s), centres + 3 * s, halves + 3 * s, out + 2 * s, nullptr,
                ctx->kernel_choice, ctx->stream, &ctx->prof, ctx->bf16_variant};
     a.aa_margin = marg;
+    a.seg = seg;
     HIPCHK(propagate_f32(a, w));
   }
   return ISX_OK;
@@ -411,7 +505,8 @@ isx_status isx_destroy(isx_ctx* ctx) {
                   &ctx->cx_cnt,   &ctx->sp_vis, &ctx->sp_vis_off, &ctx->cal_pred, &ctx->cal_unit, &ctx->cal_part,
                   &ctx->cal_cnt,  &ctx->cal_vec, &ctx->fit_c,     &ctx->fit_h,    &ctx->fit_t,    &ctx->fit_l,
                   &ctx->fit_loss, &ctx->ds_pts,  &ctx->ds_vals, &ctx->ds_stats, &ctx->ds_o32, &ctx->ds_up64,
-                  &ctx->ds_ra64};
+                  &ctx->ds_ra64,  &ctx->ray_t,   &ctx->ray_dt,  &ctx->ray_act,  &ctx->ray_idx, &ctx->ray_c,
+                  &ctx->ray_v,    &ctx->ray_o32, &ctx->ray_o64, &ctx->ray_cnt};
   for (Buf* b : cbufs) release(*b);
   for (int i = 0; i < (int)ctx->surs.size(); ++i) isx_surrogate_free(ctx, i);
   if (ctx->h_count) (void)hipHostFree(ctx->h_count);
@@ -461,6 +556,10 @@ isx_status isx_set_option(isx_ctx* ctx, isx_option option, int64_t value) {
     case ISX_CANCEL_CHECK:
       if (value < 0 || value > 1) return fail(ctx, ISX_EINVAL, "ISX_CANCEL_CHECK must be 0 or 1");
       ctx->cancel_check = (int)value;
+      return ISX_OK;
+    case ISX_AUTOTUNE:
+      if (value < 0 || value > 1) return fail(ctx, ISX_EINVAL, "ISX_AUTOTUNE must be 0 or 1");
+      ctx->autotune = (int)value;
       return ISX_OK;
     case ISX_SCRATCH_BYTES:
       if (value < (int64_t)(1 << 20)) return fail(ctx, ISX_EINVAL, "ISX_SCRATCH_BYTES must be >= 1 MiB");
@@ -661,7 +760,8 @@ isx_status isx_propagate(isx_ctx* ctx, int32_t mlp_id, isx_method method, isx_pr
                          const float* d_centres, const float* d_halves, float* d_out, double* d_out64) {
   Model* m = get_model(ctx, mlp_id);
   if (!m) return fail(ctx, ISX_EINVAL, "bad mlp id");
-  if (method != ISX_AA && method != ISX_UP && method != ISX_RAUA) return fail(ctx, ISX_EINVAL, "unknown method");
+  if (method != ISX_AA && method != ISX_UP && method != ISX_RAUA && method != ISX_RAFIXED)
+    return fail(ctx, ISX_EINVAL, "unknown method");
   if (precision != ISX_FP32 && precision != ISX_BF16 && precision != ISX_FP64)
     return fail(ctx, ISX_EINVAL, "unknown precision");
   if (n_cells < 0) return fail(ctx, ISX_EINVAL, "n_cells < 0");
@@ -670,6 +770,87 @@ isx_status isx_propagate(isx_ctx* ctx, int32_t mlp_id, isx_method method, isx_pr
   if (d_out64 && precision != ISX_FP64) return fail(ctx, ISX_EINVAL, "d_out64 is only written with ISX_FP64");
   (void)hipSetDevice(ctx->device);
   return run_propagate(ctx, *m, method, precision, n_cells, d_centres, d_halves, d_out, d_out64, 0);
+}
+
+static isx_status read_count(isx_ctx* ctx, const int64_t* d, int64_t* h);
+
+isx_status isx_propagate_segments(isx_ctx* ctx, int32_t mlp_id, isx_method method, isx_precision precision,
+                                  int64_t n, const float* d_centres, const float* d_halfvec, float* d_out,
+                                  double* d_out64) {
+  Model* m = get_model(ctx, mlp_id);
+  if (!m) return fail(ctx, ISX_EINVAL, "bad mlp id");
+  if (method != ISX_AA && method != ISX_UP && method != ISX_RAUA && method != ISX_RAFIXED)
+    return fail(ctx, ISX_EINVAL, "unknown method");
+  if (precision != ISX_FP32 && precision != ISX_BF16 && precision != ISX_FP64)
+    return fail(ctx, ISX_EINVAL, "unknown precision");
+  if (n < 0) return fail(ctx, ISX_EINVAL, "n < 0");
+  if (n == 0) return ISX_OK;
+  if (!d_centres || !d_halfvec || !d_out) return fail(ctx, ISX_EINVAL, "null buffer");
+  if (d_out64 && precision != ISX_FP64) return fail(ctx, ISX_EINVAL, "d_out64 is only written with ISX_FP64");
+  (void)hipSetDevice(ctx->device);
+  return run_propagate(ctx, *m, method, precision, n, d_centres, d_halfvec, d_out, d_out64, 0, 1);
+}
+
+// Ray casting (App. A): per step, the active rays are compacted, their
+// segments formed and bounded, and the rays advanced, refined or finished.
+isx_status isx_raycast(isx_ctx* ctx, int32_t mlp_id, const isx_ray_params* p, int64_t n, const float* d_org,
+                       const float* d_dir, const float* d_tnear, const float* d_tfar, float* d_thit,
+                       int32_t* d_iters, int64_t* h_stats) {
+  Model* m = get_model(ctx, mlp_id);
+  if (!m || !p) return fail(ctx, ISX_EINVAL, "bad arguments");
+  if (p->method != ISX_AA && p->method != ISX_UP && p->method != ISX_RAUA && p->method != ISX_RAFIXED)
+    return fail(ctx, ISX_EINVAL, "unknown method");
+  if (p->precision == ISX_BF16) return fail(ctx, ISX_EUNSUPPORTED, "ray casting runs in float32 or float64");
+  if (p->precision != ISX_FP32 && p->precision != ISX_FP64) return fail(ctx, ISX_EINVAL, "unknown precision");
+  if (!(p->step0 > 0.f) || !(p->step_min > 0.f) || !(p->step_max >= p->step0) || !(p->k >= 0.f) ||
+      !std::isfinite(p->k) || !std::isfinite(p->iso) || !std::isfinite(p->step_max) || p->max_iter < 1)
+    return fail(ctx, ISX_EINVAL, "ray parameters: need step0, step_min > 0, step_max >= step0, k >= 0, max_iter >= 1");
+  if (n < 0) return fail(ctx, ISX_EINVAL, "n_rays < 0");
+  if (h_stats) h_stats[0] = h_stats[1] = 0;
+  if (n == 0) return ISX_OK;
+  if (!d_org || !d_dir || !d_tnear || !d_tfar || !d_thit || !d_iters) return fail(ctx, ISX_EINVAL, "null buffer");
+  (void)hipSetDevice(ctx->device);
+  hipStream_t s = ctx->stream;
+  const bool f64 = p->precision == ISX_FP64;
+  const double k = (p->method == ISX_AA || p->method == ISX_RAFIXED) ? 1.0 : (double)p->k;
+  HIPCHK(ensure(ctx->ray_t, n * 8));
+  HIPCHK(ensure(ctx->ray_dt, n * 8));
+  HIPCHK(ensure(ctx->ray_act, n * 4));
+  HIPCHK(ensure(ctx->ray_idx, n * 4));
+  HIPCHK(ensure(ctx->ray_c, n * 12));
+  HIPCHK(ensure(ctx->ray_v, n * 12));
+  HIPCHK(ensure(ctx->ray_o32, n * 8));
+  if (f64) HIPCHK(ensure(ctx->ray_o64, n * 16));
+  HIPCHK(ensure(ctx->ray_cnt, sizeof(int64_t)));
+  HIPCHK(ensure(ctx->scan_tmp, compact_tmp_bytes(n)));
+  double* t = (double*)ctx->ray_t.p;
+  double* dt = (double*)ctx->ray_dt.p;
+  uint32_t* act = (uint32_t*)ctx->ray_act.p;
+  uint32_t* idx = (uint32_t*)ctx->ray_idx.p;
+  HIPCHK(launch_ray_init(n, d_tnear, d_tfar, (double)p->step0, t, dt, d_thit, d_iters, act, s));
+  int64_t segments = 0, steps = 0;
+  for (int it = 0; it < p->max_iter; ++it) {
+    HIPCHK(launch_compact(n, act, nullptr, idx, nullptr, (int64_t*)ctx->ray_cnt.p, ctx->scan_tmp.p, s));
+    int64_t n_act = 0;
+    isx_status st = read_count(ctx, (const int64_t*)ctx->ray_cnt.p, &n_act);
+    if (st != ISX_OK) return st;
+    if (n_act == 0) break;
+    HIPCHK(launch_ray_segments(n_act, idx, d_org, d_dir, d_tfar, t, dt, (float*)ctx->ray_c.p, (float*)ctx->ray_v.p, s));
+    st = run_propagate(ctx, *m, p->method, p->precision, n_act, (const float*)ctx->ray_c.p,
+                       (const float*)ctx->ray_v.p, (float*)ctx->ray_o32.p, f64 ? (double*)ctx->ray_o64.p : nullptr,
+                       0, 1);
+    if (st != ISX_OK) return st;
+    HIPCHK(launch_ray_step(n_act, idx, (const float*)ctx->ray_o32.p, f64 ? (const double*)ctx->ray_o64.p : nullptr,
+                           k, (double)p->iso, (double)p->step_min, (double)p->step_max, d_tfar, t, dt, d_thit,
+                           d_iters, act, s));
+    segments += n_act;
+    steps = it + 1;
+  }
+  if (h_stats) {
+    h_stats[0] = segments;
+    h_stats[1] = steps;
+  }
+  return ISX_OK;
 }
 
 isx_status isx_classify_compact(isx_ctx* ctx, int32_t mlp_id, float k, int64_t n_cells, const float* d_out,
@@ -902,7 +1083,7 @@ isx_status isx_extract(isx_ctx* ctx, int32_t mlp_id, const isx_params* p, isx_me
   if (!mp || !p || !out) return fail(ctx, ISX_EINVAL, "bad arguments");
   *out = nullptr;
   const Model& m = *mp;
-  if (p->method != ISX_AA && p->method != ISX_UP && p->method != ISX_RAUA)
+  if (p->method != ISX_AA && p->method != ISX_UP && p->method != ISX_RAUA && p->method != ISX_RAFIXED)
     return fail(ctx, ISX_EINVAL, "unknown method");
   if (p->precision != ISX_FP32 && p->precision != ISX_BF16 && p->precision != ISX_FP64)
     return fail(ctx, ISX_EINVAL, "unknown precision");
@@ -921,7 +1102,7 @@ isx_status isx_extract(isx_ctx* ctx, int32_t mlp_id, const isx_params* p, isx_me
   }
   (void)hipSetDevice(ctx->device);
   hipStream_t s = ctx->stream;
-  const float k = p->method == ISX_AA ? 1.f : p->k;
+  const float k = (p->method == ISX_AA || p->method == ISX_RAFIXED) ? 1.f : p->k;
   const int64_t cap = p->max_cells > 0 ? p->max_cells : (int64_t)1 << 28;
   const IsoList iso = iso_list(m);
   const uint32_t full = m.n_iso >= 32 ? 0xffffffffu : ((1u << m.n_iso) - 1u);
@@ -1158,6 +1339,18 @@ isx_status isx_extract_batch(isx_ctx* ctx, int32_t n, const int32_t* mlp_ids, co
   (void)hipSetDevice(ctx->device);
   // the caller's stream may hold work the INRs depend on
   HIPCHK(hipStreamSynchronize(ctx->stream));
+  // tile shapes are timed here, one model at a time, so that the timing
+  // runs alone on the device
+  if (ctx->autotune && p->precision == ISX_BF16 && ctx->bf16_variant == 0) {
+    for (int32_t i = 0; i < n; ++i) {
+      const Model& mi = *get_model(ctx, mlp_ids[i]);
+      if (mi.act != ISX_RELU || !bf16_supported(mi)) continue;
+      if ((p->method == ISX_UP && ctx->up_form == 0 && cov_supported(mi))) continue;
+      const isx_status st = tune_bf16(ctx, mi);
+      if (st != ISX_OK) return st;
+    }
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  }
   const int nw = std::min<int>(ctx->batch_workers, n);
   while ((int)ctx->workers.size() < nw) {
     isx_ctx* w = nullptr;
@@ -1171,6 +1364,7 @@ isx_status isx_extract_batch(isx_ctx* ctx, int32_t n, const int32_t* mlp_ids, co
     w->surs = ctx->surs;
     w->kernel_choice = ctx->kernel_choice;
     w->bf16_variant = ctx->bf16_variant;
+    w->autotune = ctx->autotune;
     w->up_form = ctx->up_form;
     w->lin_prec = ctx->lin_prec;
     w->aa_margin = ctx->aa_margin;

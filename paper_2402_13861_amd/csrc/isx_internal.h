@@ -131,6 +131,9 @@ struct Model {
   float sur_err_mu[16] = {}, sur_err_ls[16] = {};
   float sur_z[16] = {}, sur_z_acc[16] = {};  // per-level prune / accept bands
   int sur_accept_leaves = 0;
+  // bf16 coefficient-form tile shape picked by timing (-1 = not yet timed)
+  mutable int bf16_tuned = -1;
+  mutable float bf16_tune_ms[5] = {};
   int hidden() const { return n_linear - 1; }
   // columns of hidden layer h's coefficient block (h = 1..hidden())
   int64_t cols(int h) const {
@@ -265,6 +268,7 @@ struct PropArgs {
   int up_form = 0;    // bf16 UP: 0 = covariance form when supported, 1 = coefficient form
   int aa_margin = 0;  // AA: widen by the rounding margin (kernels_margin.hip)
   uint32_t* cancel = nullptr;  // bf16 UP covariance form: per-cell cancellation flags [C] (may be null)
+  int seg = 0;                 // 1: inputs are segments (centre, half-vector) with one input symbol
 };
 
 // Constants of the affine-arithmetic rounding margin of one layer
@@ -424,6 +428,23 @@ hipError_t launch_dist_points(int64_t nb, int64_t b0, int64_t ns, uint64_t seed,
 hipError_t launch_dist_stats(int64_t nb, int64_t ns, int n_fit, const float* vals, double* stats, hipStream_t s);
 hipError_t launch_dist_hist_kl(int64_t nb, int64_t ns, int n_bins, const float* vals, const double* stats,
                                const double* up64, const double* raua64, double* out, uint32_t* hist, hipStream_t s);
+
+// The row-major weights and biases of a model as kernels read them
+// (kernels_prop.hip; float and double).
+template <typename T>
+NetView<T> net_view(const Model& m);
+
+// ---- ray casting and RA-Fixed (kernels_ray.hip) ----
+hipError_t launch_rafixed(const Model& m, bool f64, int64_t n, const float* centres, const float* halves, int seg,
+                          float* out32, double* out64, hipStream_t s);
+hipError_t launch_ray_init(int64_t n, const float* tnear, const float* tfar, double step0, double* t, double* dt,
+                           float* thit, int32_t* iters, uint32_t* active, hipStream_t s);
+hipError_t launch_ray_segments(int64_t n_act, const uint32_t* idx, const float* org, const float* dir,
+                               const float* tfar, const double* t, const double* dt, float* centres, float* halfvec,
+                               hipStream_t s);
+hipError_t launch_ray_step(int64_t n_act, const uint32_t* idx, const float* out32, const double* out64, double k,
+                           double iso, double step_min, double step_max, const float* tfar, double* t, double* dt,
+                           float* thit, int32_t* iters, uint32_t* active, hipStream_t s);
 
 // ---- marching-cubes case table (mc_table.cpp) ----
 struct McTable {

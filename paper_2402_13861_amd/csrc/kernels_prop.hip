@@ -66,11 +66,16 @@ __device__ __forceinline__ T stat_term(T v) {
 // one symbol per axis with coefficient h_i (AA) or h_i/sqrt(3) (UP: a uniform
 // variable on [-h, h] has standard deviation h/sqrt 3).  One thread per
 // (cell, neuron).
+// A segment (seg != 0; App. A's ray casting) {c + v e : e in [-1, 1]} has one
+// input symbol, e (uniform on [-1, 1] for UP, coefficient v/sqrt 3): its
+// column holds W1 v s and the other two input columns are 0; `halves` then
+// holds the half-vectors v.
 template <typename T, int METHOD>
 __global__ void layer1_kernel(int64_t C, int n, const float* __restrict__ centres,
                               const float* __restrict__ halves, const T* __restrict__ W1,
                               const T* __restrict__ b1, T* __restrict__ Fout, T* __restrict__ Y,
-                              T* __restrict__ A, T* __restrict__ B, T* __restrict__ G, T* __restrict__ S, int act) {
+                              T* __restrict__ A, T* __restrict__ B, T* __restrict__ G, T* __restrict__ S, int act,
+                              int seg) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= C * n) return;
   const int64_t cell = idx / n;
@@ -79,12 +84,25 @@ __global__ void layer1_kernel(int64_t C, int n, const float* __restrict__ centre
   T f[3];
   T y = b1[m];
   T stat = T(0);
+  if (seg) {
+    T wv = T(0);
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const T w = W1[m * 3 + i];
-    y += w * T(centres[cell * 3 + i]);
-    f[i] = w * (T(halves[cell * 3 + i]) * s);
-    stat += stat_term<T, METHOD>(f[i]);
+    for (int i = 0; i < 3; ++i) {
+      const T w = W1[m * 3 + i];
+      y += w * T(centres[cell * 3 + i]);
+      wv += w * T(halves[cell * 3 + i]);
+    }
+    f[0] = wv * s;
+    f[1] = f[2] = T(0);
+    stat = stat_term<T, METHOD>(f[0]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const T w = W1[m * 3 + i];
+      y += w * T(centres[cell * 3 + i]);
+      f[i] = w * (T(halves[cell * 3 + i]) * s);
+      stat += stat_term<T, METHOD>(f[i]);
+    }
   }
   T a, b, g;
   apply_rule<T, METHOD>(act, y, stat, a, b, g);
@@ -196,7 +214,7 @@ __global__ void hidden_simt_kernel(int64_t C, int n_in, int n_out, int64_t cols_
 template <typename T, int METHOD, int CPB>
 __global__ __launch_bounds__(256) void output_kernel(int64_t C, NetView<T> net, int nmax,
                                                      const float* __restrict__ halves, float* __restrict__ out32,
-                                                     double* __restrict__ out64) {
+                                                     double* __restrict__ out64, int seg) {
   extern __shared__ float4 outk_smem4[];
   T* v = reinterpret_cast<T*>(outk_smem4);  // [CPB][nmax]
   T* u = v + CPB * nmax;                    // [CPB][nmax]
@@ -261,14 +279,26 @@ __global__ __launch_bounds__(256) void output_kernel(int64_t C, NetView<T> net, 
       for (int j = t; j < n1; j += blockDim.x) u[c * nmax + j] = v[c * nmax + j] * A1[j];
     }
     __syncthreads();
-    if (t < 3) {
-      const T* W0 = net.W[0];  // [n1][3]
-      const T sc = METHOD == ISX_UP ? T(0.57735026918962576451) : T(1);
+    const T* W0 = net.W[0];  // [n1][3]
+    const T sc = METHOD == ISX_UP ? T(0.57735026918962576451) : T(1);
+    if (!seg && t < 3) {
 #pragma unroll
       for (int c = 0; c < CPB; ++c) {
         T s = T(0);
         for (int j = 0; j < n1; ++j) s += u[c * nmax + j] * W0[j * 3 + t];
         acc_p[c] += stat_term<T, METHOD>(s * (T(halves[cl[c] * 3 + t]) * sc));
+      }
+    } else if (seg && t == 0) {
+      // the segment's one input symbol: coefficient (u^T W0) . v
+#pragma unroll
+      for (int c = 0; c < CPB; ++c) {
+        T sv = T(0);
+        for (int a = 0; a < 3; ++a) {
+          T s = T(0);
+          for (int j = 0; j < n1; ++j) s += u[c * nmax + j] * W0[j * 3 + a];
+          sv += s * T(halves[cl[c] * 3 + a]);
+        }
+        acc_p[c] += stat_term<T, METHOD>(sv * sc);
       }
     }
   }
@@ -310,7 +340,7 @@ __global__ __launch_bounds__(256) void output_kernel(int64_t C, NetView<T> net, 
 // Launch of the read-off with CPB cells per workgroup.
 template <typename T, int METHOD, int CPB>
 static hipError_t launch_output_simt(const Model& m, int64_t C, const NetView<T>& view, const float* halves,
-                                     float* out32, double* out64, hipStream_t s) {
+                                     float* out32, double* out64, hipStream_t s, int seg = 0) {
   int nmax = 3;
   for (int h = 1; h < m.n_linear; ++h) nmax = std::max(nmax, m.pw[h]);
   const size_t lds = (size_t)2 * CPB * nmax * sizeof(T);
@@ -319,7 +349,7 @@ static hipError_t launch_output_simt(const Model& m, int64_t C, const NetView<T>
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL((output_kernel<T, METHOD, CPB>), dim3((unsigned)((C + CPB - 1) / CPB)), dim3(256), lds, s, C,
-                     view, nmax, halves, out32, out64);
+                     view, nmax, halves, out32, out64, seg);
   return hipGetLastError();
 }
 
@@ -452,6 +482,16 @@ static NetView<T> make_view(const Model& m) {
   return v;
 }
 
+template <>
+NetView<float> net_view<float>(const Model& m) {
+  return make_view<float>(m);
+}
+template <>
+NetView<double> net_view<double>(const Model& m) {
+  return make_view<double>(m);
+}
+
+
 hipError_t launch_hidden_mfma_f32(int method, int64_t C, int n_in, int n_out, int64_t cols_in, const float* Wt,
                                   const float* bias, const float* Fin, const float* Ain, const float* Bin,
                                   const float* Gin, float* Fout, float* Y, float* A, float* B, float* G, float* S,
@@ -503,7 +543,7 @@ static hipError_t propagate_impl(const PropArgs& a, PropWork<T>& w, bool use_mfm
     const int bs = 256;
     hipLaunchKernelGGL((layer1_kernel<T, METHOD>), dim3((unsigned)((threads + bs - 1) / bs)), dim3(bs), 0,
                        a.stream, C, n1, a.centres, a.halves, wptr<T>(m.L[0]), bptr<T>(m.L[0]),
-                       Lh >= 2 ? w.F[cur] : (T*)nullptr, Y[1], A[1], B[1], G[1], S[1], m.act);
+                       Lh >= 2 ? w.F[cur] : (T*)nullptr, Y[1], A[1], B[1], G[1], S[1], m.act, a.seg);
     if (marg) {
       hipError_t e = launch_aa_margin_hidden<T>(C, 3, n1, wtptr<T>(m.L[0]), bptr<T>(m.L[0]), nullptr, nullptr, nullptr,
                                                 nullptr, a.centres, a.halves, Y[1], S[1], A[1], B[1], G[1], R[1],
@@ -563,10 +603,11 @@ static hipError_t propagate_impl(const PropArgs& a, PropWork<T>& w, bool use_mfm
       view.B[h] = B[h];
       view.G[h] = G[h];
     }
-    hipError_t e = sizeof(T) == 8 ? launch_output_simt<T, ISX_RAUA, 4>(m, C, view, a.halves, a.out32, a.out64, a.stream)
-                                  : launch_output_simt<T, ISX_RAUA, 1>(m, C, view, a.halves, a.out32, a.out64, a.stream);
+    hipError_t e = sizeof(T) == 8
+                       ? launch_output_simt<T, ISX_RAUA, 4>(m, C, view, a.halves, a.out32, a.out64, a.stream, a.seg)
+                       : launch_output_simt<T, ISX_RAUA, 1>(m, C, view, a.halves, a.out32, a.out64, a.stream, a.seg);
     if (e != hipSuccess) return e;
-  } else if (use_mfma && sizeof(T) == 4 && a.out64 == nullptr) {
+  } else if (use_mfma && sizeof(T) == 4 && a.out64 == nullptr && !a.seg) {
     hipError_t e = launch_output_mfma(m, (isx_method)METHOD, C, reinterpret_cast<float* const*>(Y),
                                       reinterpret_cast<float* const*>(A), reinterpret_cast<float* const*>(B),
                                       reinterpret_cast<float* const*>(G), a.halves, a.out32, a.stream);
@@ -580,8 +621,9 @@ static hipError_t propagate_impl(const PropArgs& a, PropWork<T>& w, bool use_mfm
       view.G[h] = G[h];
     }
     // float64 (the re-check band) batches 4 cells per workgroup
-    hipError_t e = sizeof(T) == 8 ? launch_output_simt<T, METHOD, 4>(m, C, view, a.halves, a.out32, a.out64, a.stream)
-                                  : launch_output_simt<T, METHOD, 1>(m, C, view, a.halves, a.out32, a.out64, a.stream);
+    hipError_t e = sizeof(T) == 8
+                       ? launch_output_simt<T, METHOD, 4>(m, C, view, a.halves, a.out32, a.out64, a.stream, a.seg)
+                       : launch_output_simt<T, METHOD, 1>(m, C, view, a.halves, a.out32, a.out64, a.stream, a.seg);
     if (e != hipSuccess) return e;
   }
   if (prof) a.prof->end(rec, a.stream);

@@ -17,6 +17,12 @@ octree depth.  Inputs only; no method arithmetic here.
   sampled at random points of the 512^3 grid; octree depth 10 (1024^3
   effective resolution); 8 iso-values at the 1/9 .. 8/9 output quantiles;
   t = 3; float64 re-check band 1e-3 S.
+* ``relu_sdf_7k`` / ``elu_sdf_29k``: signed distance functions of a small
+  analytic scene (a sphere, a torus and a box; ``workloads.fit_gpu --target
+  sdf``) fitted by a ReLU 3->64->64->48->1 (7.6k parameters) and an ELU
+  3->128->128->96->1 (29.5k parameters) net (3000 Adam steps, batch 65536,
+  lr 1e-3, He-normal init seed 0); the level set f = 0 is ray cast (App. A's
+  experiment, whose networks have 7.6k and 29k parameters).
 """
 
 from __future__ import annotations
@@ -37,6 +43,14 @@ WORKLOADS = {
         widths=[3, 256, 256, 256, 256, 256, 1], weight_seed=0, weights="relu_256x5_fourier.isxw", depth=9, k=3.0,
         iso_quantiles=[0.25, 0.5, 0.75], band_rel=1e-3,
     ),
+    "relu_sdf_7k": dict(
+        widths=[3, 64, 64, 48, 1], weight_seed=0, weights="relu_sdf_7k.isxw", depth=8, k=3.0, iso_quantiles=None,
+        act="relu",
+    ),
+    "elu_sdf_29k": dict(
+        widths=[3, 128, 128, 96, 1], weight_seed=0, weights="elu_sdf_29k.isxw", depth=8, k=3.0, iso_quantiles=None,
+        act="elu",
+    ),
     "relu512x8_blobs": dict(
         widths=[3] + [512] * 8 + [1], weight_seed=0, weights="relu_512x8_blobs.isxw", depth=10, k=3.0,
         iso_quantiles=[i / 9 for i in range(1, 9)], band_rel=1e-3,
@@ -44,11 +58,11 @@ WORKLOADS = {
 }
 
 
-def load_mlp(name: str):
+def load_mlp(name: str, data_dir=None):
     w = WORKLOADS[name]
     if w["weights"] is None:
         return he_normal_mlp(w["widths"], w["weight_seed"])
-    mlp = read_weights(DATA / w["weights"])
+    mlp = read_weights(Path(data_dir or DATA) / w["weights"])
     assert mlp.widths == w["widths"], (mlp.widths, w["widths"])
     return mlp
 
