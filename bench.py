@@ -382,6 +382,15 @@ def batch_bench(a, log):
     depth = a.depth if a.depth is not None else DEPTH
     prec = {"fp32": isx.FP32, "bf16": isx.BF16}[a.precision]
     kw = dict(method=isx.UP, precision=prec, k=3.0, max_depth=depth)
+    if a.autotune:
+        # tile shapes of the coefficient-form kernel, timed per INR (printed by the library)
+        ctx.set_option(isx.AUTOTUNE, 1)
+        ctx.set_option(isx.VERBOSE, 1)
+        t0 = time.perf_counter()
+        for m in ctx.extract_batch(ids, **dict(kw, max_depth=1)):
+            m.free()
+        ctx.set_option(isx.VERBOSE, 0)
+        log(f"batch: tile shapes timed in {time.perf_counter() - t0:.2f} s")
     # warm-up (code objects, scratch)
     for m in ctx.extract_batch(ids[:4], **kw):
         m.free()
@@ -410,6 +419,7 @@ def batch_bench(a, log):
         log(f"batch: {workers} workers {dt * 1e3:.1f} ms, same meshes {same}")
     shapes = [w for w, _ in batch_shapes(n)]
     print(json.dumps({"batch": res, "sequential_ms": round(t_seq * 1e3, 2), "inrs": n, "depth": depth,
+                      "autotune": bool(a.autotune),
                       "precision": a.precision, "propagated_cells": propagated,
                       "per_inr": [dict(widths=f"{w[1]}x{len(w) - 2}", **x) for w, x in zip(shapes, singles)]}),
           flush=True)
@@ -548,14 +558,16 @@ def main(argv=None):
                     help="only run the batched 64-INR workload (isx_extract_batch) and exit")
     ap.add_argument("--batch-inrs", type=int, default=64)
     ap.add_argument("--batch-workers", type=int, nargs="+", default=[1, 4, 8])
+    ap.add_argument("--autotune", type=int, default=1, help="time the BF16 coefficient kernel's tile shapes per INR")
     ap.add_argument("--kl-report", action="store_true",
                     help="only run the distribution-quality report (KL of Eq. 11 over random blocks) and exit")
     ap.add_argument("--kl-blocks", type=int, default=100)
     ap.add_argument("--kl-level", type=int, default=5)
     ap.add_argument("--kl-samples", type=int, default=1_000_000)
     ap.add_argument("--kl-seed", type=int, default=0)
-    ap.add_argument("--band-rel", type=float, default=0.0,
-                    help="BF16: widen each cell's float64 re-check band by this multiple of its spread")
+    ap.add_argument("--band-rel", type=float, default=2.0 ** -6,
+                    help="BF16: widen each cell's float64 re-check band by this multiple of its spread (the BF16 "
+                         "endpoint error measured per level stays below 2^-7 of the cell's sigma)")
     ap.add_argument("--subtree", type=int, default=0,
                     help="extract only inside the level-L octree cell [0, 2/2^L]^3 of the domain, to the same "
                          "leaf size (depth - L levels below it)")
@@ -809,6 +821,7 @@ def main(argv=None):
             "workload": f"{a.workload}: ReLU MLP {'x'.join(map(str, mlp.widths))}, octree depth {depth} "
                         f"({1 << depth}^3 effective cells), {len(isos)} iso-values, UP t={w['k']}, "
                         f"fp64 band {w.get('band_rel', 0)} S"
+                        + (f" + {a.band_rel:g} of the cell's spread" if a.precision == "bf16" and a.band_rel else "")
                         + (f"; domain [0, {sub_hi:g}]^3, the level-{a.subtree} subtree of [-1, 1]^3 at "
                            f"{1 << full_depth}^3 effective resolution" if a.subtree else ""),
             "path": name,

@@ -558,10 +558,13 @@ typedef enum {
                               pre-activation y has |y| < 6 sqrt(max(v, 0) + 2^-7 a) (the ReLU rule of Eq. 9
                               depends on sigma there) is propagated again in float64, and its float64
                               (mu, sigma) is returned; 0 = off */
-  ISX_AUTOTUNE = 12        /* bf16 coefficient-form propagation: 1 = pick the hidden-layer tile shape of
+  ISX_AUTOTUNE = 12,       /* bf16 coefficient-form propagation: 1 = pick the hidden-layer tile shape of
                               each MLP by timing the shapes (1, 3, 4 and the default) on 4096 sample
                               cells at its first such propagation (the shapes give identical results);
                               0 (default) = the default shape for the width, or ISX_BF16_VARIANT */
+  ISX_BF16_READOFF = 13    /* bf16 uncertainty propagation: 0 (default) = the output read-off on bf16 MFMA
+                              with hi/lo splits of the row vectors and weights where the widths allow;
+                              1 = the float32 MFMA read-off (the same vectors; for comparison) */
 } isx_option;
 isx_status isx_set_option(isx_ctx* ctx, isx_option option, int64_t value);
 

@@ -87,6 +87,7 @@ struct isx_ctx {
   int kernel_choice = 0;
   int bf16_variant = 0;
   int autotune = 0;   // ISX_AUTOTUNE
+  int readoff_f32 = 0;  // ISX_BF16_READOFF
   bool tuning = false;
   Buf tune_c, tune_h, tune_out;
   int up_form = 0;
@@ -398,6 +399,7 @@ isx_status run_propagate(isx_ctx* ctx, const Model& m, isx_method method, isx_pr
                  ctx->kernel_choice, ctx->stream, &ctx->prof, variant, ctx->up_form};
       a.aa_margin = marg;
       if (check) a.cancel = (uint32_t*)ctx->cx_flags.p + s;
+      a.readoff_f32 = ctx->readoff_f32;
       HIPCHK(propagate_bf16(a, w, Fbf, 0));
     }
     ctx->n_cancel_last = 0;
@@ -560,6 +562,10 @@ isx_status isx_set_option(isx_ctx* ctx, isx_option option, int64_t value) {
     case ISX_AUTOTUNE:
       if (value < 0 || value > 1) return fail(ctx, ISX_EINVAL, "ISX_AUTOTUNE must be 0 or 1");
       ctx->autotune = (int)value;
+      return ISX_OK;
+    case ISX_BF16_READOFF:
+      if (value < 0 || value > 1) return fail(ctx, ISX_EINVAL, "ISX_BF16_READOFF must be 0 or 1");
+      ctx->readoff_f32 = (int)value;
       return ISX_OK;
     case ISX_SCRATCH_BYTES:
       if (value < (int64_t)(1 << 20)) return fail(ctx, ISX_EINVAL, "ISX_SCRATCH_BYTES must be >= 1 MiB");
@@ -1365,6 +1371,7 @@ isx_status isx_extract_batch(isx_ctx* ctx, int32_t n, const int32_t* mlp_ids, co
     w->kernel_choice = ctx->kernel_choice;
     w->bf16_variant = ctx->bf16_variant;
     w->autotune = ctx->autotune;
+    w->readoff_f32 = ctx->readoff_f32;
     w->up_form = ctx->up_form;
     w->lin_prec = ctx->lin_prec;
     w->aa_margin = ctx->aa_margin;

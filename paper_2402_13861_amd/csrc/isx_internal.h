@@ -269,6 +269,7 @@ struct PropArgs {
   int aa_margin = 0;  // AA: widen by the rounding margin (kernels_margin.hip)
   uint32_t* cancel = nullptr;  // bf16 UP covariance form: per-cell cancellation flags [C] (may be null)
   int seg = 0;                 // 1: inputs are segments (centre, half-vector) with one input symbol
+  int readoff_f32 = 0;         // bf16 UP: 1 = the float32 MFMA read-off instead of the bf16 hi/lo one
 };
 
 // Constants of the affine-arithmetic rounding margin of one layer

@@ -427,7 +427,7 @@ hipError_t propagate_bf16(const PropArgs& a, PropWork<float>& w, uint16_t* Fbf_r
     const bool prof2 = a.prof && a.prof->begin(rec2, ISX_KERNEL_OUTPUT, output_flops_per_cell(m) * (double)C,
                                                4.0 * C * 4.0 * (double)m.pw[1] * Lh, a.stream);
     // (the UP read-off on BF16 MFMA with hi/lo splits, float32 accuracy)
-    e = output_bf16_supported(m) ? launch_output_bf16(m, C, Y, A, B, G, a.halves, a.out32, a.stream)
+    e = output_bf16_supported(m) && !a.readoff_f32 ? launch_output_bf16(m, C, Y, A, B, G, a.halves, a.out32, a.stream)
                                  : launch_output_mfma(m, a.method, C, Y, A, B, G, a.halves, a.out32, a.stream);
     if (prof2) a.prof->end(rec2, a.stream);
     return e;
@@ -512,7 +512,7 @@ hipError_t propagate_bf16(const PropArgs& a, PropWork<float>& w, uint16_t* Fbf_r
   // AA keeps the float32 read-off, which the rounding margin assumes)
   hipError_t e = (a.kernel_choice == 1 || a.method == ISX_RAUA)
                      ? launch_output_f32(m, a.method, C, w.vec, a.halves, a.out32, a.stream)
-                 : (a.method == ISX_UP && output_bf16_supported(m))
+                 : (a.method == ISX_UP && output_bf16_supported(m) && !a.readoff_f32)
                      ? launch_output_bf16(m, C, Y, A, B, G, a.halves, a.out32, a.stream)
                      : launch_output_mfma(m, a.method, C, Y, A, B, G, a.halves, a.out32, a.stream);
   if (prof) a.prof->end(rec, a.stream);

@@ -28,37 +28,12 @@
 
 namespace isx {
 
-template <typename T>
-struct M;
-template <>
-struct M<float> {
-  static __device__ __forceinline__ float erfc_(float x) { return erfcf(x); }
-  static __device__ __forceinline__ float exp_(float x) { return expf(x); }
-  static __device__ __forceinline__ float sqrt_(float x) { return sqrtf(x); }
-  static __device__ __forceinline__ float abs_(float x) { return fabsf(x); }
-};
-template <>
-struct M<double> {
-  static __device__ __forceinline__ double erfc_(double x) { return erfc(x); }
-  static __device__ __forceinline__ double exp_(double x) { return exp(x); }
-  static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
-  static __device__ __forceinline__ double abs_(double x) { return fabs(x); }
-};
-
-// ReLU linearisation from the pre-activation centre y and the row statistic
-// (UP: sum of squared coefficients; AA: sum of absolute coefficients).
-//  UP (Eq. 10, App. D ReLU row), r = y/sigma, Phi/phi standard normal cdf/pdf:
-//    alpha = Phi(r), beta = sigma phi(r),
-//    gamma^2 = sigma^2 [(r^2+1) Phi Q + r phi (Q - Phi) - phi^2], Q = 1 - Phi,
-//    with (1 - erf^2)/4 written as Phi*Q from erfc and the result clamped at 0;
-//    a zero-width input takes the exact limit (alpha = step(y), 1/2 at 0).
-//  AA (Eq. 4), hard range [l, u] = [y - r, y + r]: minimax line; for l < 0 < u
-//    alpha = u/(u-l), beta = gamma = -alpha l / 2; identity if l >= 0; 0 if u <= 0.
+// (the activation rules, Eq. 4 and Eq. 9-10 with the App. D rows, are in rules.h)
 
 // row statistic terms: squares for UP and for the RA-UA read-off, magnitudes for AA
 template <typename T, int METHOD>
 __device__ __forceinline__ T stat_term(T v) {
-  return METHOD != ISX_AA ? v * v : M<T>::abs_(v);
+  return METHOD != ISX_AA ? v * v : RM<T>::abs_(v);
 }
 
 // ---------------------------------------------------------------- layer 1
@@ -325,8 +300,8 @@ __global__ __launch_bounds__(256) void output_kernel(int64_t C, NetView<T> net, 
     }
     mu += net.b[L - 1][0];
     // RA-UA (Eq. 5): the AA coefficients read as uniform variables, variance x_i^2 / 3
-    const T spread = METHOD == ISX_UP ? M<T>::sqrt_(acc)
-                                      : (METHOD == ISX_RAUA ? M<T>::sqrt_(acc) * T(0.57735026918962576451) : acc);
+    const T spread = METHOD == ISX_UP ? RM<T>::sqrt_(acc)
+                                      : (METHOD == ISX_RAUA ? RM<T>::sqrt_(acc) * T(0.57735026918962576451) : acc);
     const int64_t cell = cell0 + c;
     out32[cell * 2 + 0] = (float)mu;
     out32[cell * 2 + 1] = (float)spread;

@@ -2,7 +2,8 @@
 float64 oracle.
 
 * Segment bounds (AA, UP, RA-UA, RA-Fixed): float32 within 1e-5 of
-  max(|o|, S), float64 within 1e-10, on random segments of many lengths.
+  max(|o|, S), float64 within 1e-10, on random segments of many lengths
+  (RA-Fixed's float32 spread within 5e-4 of max(spread, 1e-3 S)).
 * RA-Fixed on boxes: the same tolerances.
 * Ray casting a 20x20 image (3->32x3->1 He-normal net, iso = median): with
   float64 bounds every ray whose decisions all clear the iso-value by more
@@ -72,7 +73,11 @@ def test_segment_bounds_match_oracle(ctx, widths, name):
                                    out, out64)
             torch.cuda.synchronize()
             got = out64.cpu().numpy() if out64 is not None else out.cpu().numpy()
-            assert_pair_close(got, ref, S, tol, f"segments {name} {widths} prec {prec}", k=k)
+            # RA-Fixed's error term adds |W| |gamma| over every straddling neuron, and gamma = -alpha l / 2
+            # carries the float32 centre's absolute rounding (~1e-7 S): on segments whose spread is near the
+            # 1e-3 S floor that is a few 1e-4 of it, without the sign cancellation AA's separate symbols get
+            srtol = 5e-4 if (name == "rafixed" and prec == isx.FP32) else None
+            assert_pair_close(got, ref, S, tol, f"segments {name} {widths} prec {prec}", k=k, spread_rtol=srtol)
     finally:
         ctx.unload_mlp(mid)
 
