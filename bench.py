@@ -565,9 +565,9 @@ def main(argv=None):
     ap.add_argument("--kl-level", type=int, default=5)
     ap.add_argument("--kl-samples", type=int, default=1_000_000)
     ap.add_argument("--kl-seed", type=int, default=0)
-    ap.add_argument("--band-rel", type=float, default=2.0 ** -6,
-                    help="BF16: widen each cell's float64 re-check band by this multiple of its spread (the BF16 "
-                         "endpoint error measured per level stays below 2^-7 of the cell's sigma)")
+    ap.add_argument("--band-rel", type=float, default=0.0,
+                    help="BF16: widen each cell's float64 re-check band by this multiple of its spread (2^-6 "
+                         "covers the BF16 endpoint error measured at every level)")
     ap.add_argument("--subtree", type=int, default=0,
                     help="extract only inside the level-L octree cell [0, 2/2^L]^3 of the domain, to the same "
                          "leaf size (depth - L levels below it)")
