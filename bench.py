@@ -565,6 +565,8 @@ def main(argv=None):
     ap.add_argument("--kl-level", type=int, default=5)
     ap.add_argument("--kl-samples", type=int, default=1_000_000)
     ap.add_argument("--kl-seed", type=int, default=0)
+    ap.add_argument("--recheck-cascade", type=int, default=1,
+                    help="BF16: re-check band cells in float32 first and in float64 only within 1/8 of the band")
     ap.add_argument("--band-rel", type=float, default=0.0,
                     help="BF16: widen each cell's float64 re-check band by this multiple of its spread (2^-6 "
                          "covers the BF16 endpoint error measured at every level)")
@@ -613,6 +615,7 @@ def main(argv=None):
     ctx = isx.Context(0)
     ctx.set_option(isx.SCRATCH_BYTES, 48 << 30)
     ctx.set_option(isx.VERBOSE, 1)
+    ctx.set_option(isx.RECHECK_CASCADE, a.recheck_cascade)
     mid = ctx.load_weights(mlp)
     ctx.set_isovalues(mid, isos)
     sub_hi = 2.0 / (1 << a.subtree) if a.subtree else None
@@ -723,6 +726,7 @@ def main(argv=None):
     # covariance form: the cheapest exact formulation, alg_flops_cov_hybrid),
     # and at the flops the kernel executes (the library's own count)
     rechecked = sum(l["rechecked"] for l in levels)
+    rechecked64 = sum(l["rechecked_fp64"] for l in levels)
     per_kernel = {}
     for kname, (kern, src, dt, form) in HIDDEN_KINDS.items():
         v = prof[kname]
@@ -731,7 +735,7 @@ def main(argv=None):
         if kname == "hidden_cov_bf16":
             alg = propagated * K * alg_flops_cov_hybrid(mlp.widths)
         elif kname == "hidden_fp64":
-            alg = rechecked * K * alg_flops_coefficient(mlp.widths)
+            alg = rechecked64 * K * alg_flops_coefficient(mlp.widths)
         else:
             alg = v["flops"]
         sec = v["ms"] * 1e-3
@@ -750,7 +754,7 @@ def main(argv=None):
     launches = max(kp["launches"], 1)
     avg_ms = kp["ms"] / launches
     alg_per_launch = pk["alg_flops_per_step"] * K / launches
-    cells_kind = rechecked if kind == "hidden_fp64" else propagated
+    cells_kind = rechecked64 if kind == "hidden_fp64" else propagated
     cells_per_launch = cells_kind / (kp["launches"] / K) if kp["launches"] else 0.0
     traffic = traffic_from_profiles(kind, cells_per_launch)
     roofline = {
@@ -822,6 +826,8 @@ def main(argv=None):
                         f"({1 << depth}^3 effective cells), {len(isos)} iso-values, UP t={w['k']}, "
                         f"fp64 band {w.get('band_rel', 0)} S"
                         + (f" + {a.band_rel:g} of the cell's spread" if a.precision == "bf16" and a.band_rel else "")
+                        + (" (float32 re-check, float64 within 1/8 of the band)" if a.precision == "bf16"
+                           and a.recheck_cascade else "")
                         + (f"; domain [0, {sub_hi:g}]^3, the level-{a.subtree} subtree of [-1, 1]^3 at "
                            f"{1 << full_depth}^3 effective resolution" if a.subtree else ""),
             "path": name,
@@ -836,6 +842,7 @@ def main(argv=None):
         "examined_cells": examined,
         "propagated_cells": propagated,
         "rechecked_cells": int(rechecked),
+        "rechecked_fp64_cells": int(rechecked64),
         "propagated_cells_per_s": propagated / acp_s if acp_s > 0 else None,
         "active_leaves": runs[-1]["leaves"],
         "triangles": runs[-1]["tris"],

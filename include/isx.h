@@ -295,6 +295,11 @@ isx_status isx_mesh_level(const isx_mesh* mesh, int32_t level, int64_t* n_cells,
  * and propagated again in float64 (ISX_CANCEL_CHECK; 0 for other paths). */
 isx_status isx_mesh_level_cancelled(const isx_mesh* mesh, int32_t level, int64_t* n_cancelled);
 
+/* Cells of `level` propagated in float64 by the re-check band (all band
+ * cells, or with ISX_RECHECK_CASCADE the inner band's).  ISX_EINVAL on a bad
+ * level. */
+isx_status isx_mesh_level_rechecked_fp64(const isx_mesh* mesh, int32_t level, int64_t* n_fp64);
+
 /* Phase times in milliseconds measured with HIP events on the context
  * stream: active-cell prediction (all levels), corner evaluation, marching
  * cubes, total. */
@@ -562,9 +567,16 @@ typedef enum {
                               each MLP by timing the shapes (1, 3, 4 and the default) on 4096 sample
                               cells at its first such propagation (the shapes give identical results);
                               0 (default) = the default shape for the width, or ISX_BF16_VARIANT */
-  ISX_BF16_READOFF = 13    /* bf16 uncertainty propagation: 0 (default) = the output read-off on bf16 MFMA
+  ISX_BF16_READOFF = 13,   /* bf16 uncertainty propagation: 0 (default) = the output read-off on bf16 MFMA
                               with hi/lo splits of the row vectors and weights where the widths allow;
                               1 = the float32 MFMA read-off (the same vectors; for comparison) */
+  ISX_RECHECK_CASCADE = 14 /* isx_extract with ISX_BF16 and a re-check band: 0 (default) = band cells are
+                              propagated again in float64 and that result decides; 1 = they are propagated
+                              in float32 first, and only those whose float32 bound endpoint lies within
+                              1/8 of the band (fp64_band / 8 + fp64_band_rel / 8 * spread) of a carried
+                              iso-value go on to float64; the others keep the float32 decision (float32
+                              endpoint errors are far below that eighth: <= 1e-5 of max(|o|, S) in the
+                              parity tests); isx_mesh_level_rechecked_fp64 counts the float64 cells */
 } isx_option;
 isx_status isx_set_option(isx_ctx* ctx, isx_option option, int64_t value);
 

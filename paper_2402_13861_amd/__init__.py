@@ -22,7 +22,7 @@ import numpy as np
 from . import _lib
 from ._lib import (AA, RAUA, RAFIXED, RELU, SINE, ELU, BF16, BF16_VARIANT, FP32, FP64, HIDDEN_KERNEL, KEEP_LEVELS, PROFILE, SCRATCH_BYTES, UP,
                    UP_FORM, LIN_PRECISION, AA_MARGIN, BATCH_WORKERS, VERBOSE, CANCEL_CHECK, AUTOTUNE,
-                   BF16_READOFF)
+                   BF16_READOFF, RECHECK_CASCADE)
 
 # columns of isx_distribution_kl's report (isx_dist_field order)
 DIST_FIELDS = ("mc_mean", "mc_std", "lo", "hi", "up_mu", "up_sigma", "raua_mu", "raua_sigma", "fit_mu", "fit_sigma",
@@ -496,10 +496,11 @@ class Mesh:
         for i in range(self.n_levels):
             a, b, c, d = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
             self._L.isx_mesh_level(self._h, i, C.byref(a), C.byref(b), C.byref(c), C.byref(d))
-            x = C.c_int64()
+            x, y = C.c_int64(), C.c_int64()
             self._L.isx_mesh_level_cancelled(self._h, i, C.byref(x))
+            self._L.isx_mesh_level_rechecked_fp64(self._h, i, C.byref(y))
             out.append(dict(cells=a.value, active=b.value, rechecked=c.value, propagated=d.value,
-                            cancelled=x.value))
+                            cancelled=x.value, rechecked_fp64=y.value))
         return out
 
     def times(self):

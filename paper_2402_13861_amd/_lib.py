@@ -20,7 +20,8 @@ AA, UP, RAUA, RAFIXED = 0, 1, 2, 3
 RELU, SINE, ELU = 0, 1, 2
 FP32, BF16, FP64 = 0, 1, 2
 (KEEP_LEVELS, HIDDEN_KERNEL, PROFILE, SCRATCH_BYTES, VERBOSE, BF16_VARIANT, UP_FORM, LIN_PRECISION,
- AA_MARGIN, BATCH_WORKERS, CANCEL_CHECK, AUTOTUNE, BF16_READOFF) = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13
+ AA_MARGIN, BATCH_WORKERS, CANCEL_CHECK, AUTOTUNE, BF16_READOFF, RECHECK_CASCADE) = (
+    1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14)
 MAX_LINEAR, MAX_WIDTH, MAX_ISO = 16, 1024, 32
 NOALLOC_MAX_CELLS = 1 << 22
 (KERNEL_HIDDEN_FP32, KERNEL_HIDDEN_BF16, KERNEL_HIDDEN_SIMT_FP32, KERNEL_HIDDEN_FP64, KERNEL_DENSE,
@@ -126,6 +127,7 @@ _SIGS = [
     ("isx_mesh_level", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                  C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     ("isx_mesh_level_cancelled", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64)]),
+    ("isx_mesh_level_rechecked_fp64", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64)]),
     ("isx_mesh_times", C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_float), C.POINTER(C.c_float),
                                  C.POINTER(C.c_float)]),
     ("isx_mesh_copy_tris", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),

@@ -109,6 +109,9 @@ struct isx_ctx {
   Buf sur_act[ISX_MAX_LINEAR + 1], sur_out, sur_T, sur_d[2], sur_base, sp_base, sp_scale;
   Buf sp_pred, sp_fb, sp_idx, sp_pm, sp_c, sp_h, sp_out, sp_mask, sp_cnt, sp_tmp;
   Buf rc_flags, rc_fidx, rc_fmask;
+  Buf rc_pm, rc_flags2, rc_idx2, rc2_c, rc2_h, rc2_out32, rc2_out64;  // two-stage re-check
+  int recheck_cascade = 0;                                          // ISX_RECHECK_CASCADE
+  int64_t n_rc64_last = 0;  // cells propagated in float64 by the re-checks since the level began
   Buf cx_flags, cx_idx, cx_c, cx_h, cx_out, cx_out64, cx_cnt;
   // surrogate training set and band calibration
   Buf sp_vis, sp_vis_off, cal_pred, cal_unit, cal_part, cal_cnt, cal_vec, fit_c, fit_h, fit_t, fit_l, fit_loss;
@@ -134,7 +137,7 @@ struct isx_mesh {
   float* tri_pos = nullptr;
   uint64_t* tri_keys = nullptr;
   int32_t* tri_iso = nullptr;
-  std::vector<int64_t> lvl_cells, lvl_active, lvl_recheck, lvl_prop, lvl_cancel;
+  std::vector<int64_t> lvl_cells, lvl_active, lvl_recheck, lvl_prop, lvl_cancel, lvl_recheck64;
   std::vector<std::vector<uint32_t>> lvl_ids, lvl_masks;
   std::vector<std::vector<float>> lvl_out;
   bool kept = false;
@@ -508,7 +511,8 @@ isx_status isx_destroy(isx_ctx* ctx) {
                   &ctx->cal_cnt,  &ctx->cal_vec, &ctx->fit_c,     &ctx->fit_h,    &ctx->fit_t,    &ctx->fit_l,
                   &ctx->fit_loss, &ctx->ds_pts,  &ctx->ds_vals, &ctx->ds_stats, &ctx->ds_o32, &ctx->ds_up64,
                   &ctx->ds_ra64,  &ctx->ray_t,   &ctx->ray_dt,  &ctx->ray_act,  &ctx->ray_idx, &ctx->ray_c,
-                  &ctx->ray_v,    &ctx->ray_o32, &ctx->ray_o64, &ctx->ray_cnt};
+                  &ctx->ray_v,    &ctx->ray_o32, &ctx->ray_o64, &ctx->ray_cnt, &ctx->rc_pm,   &ctx->rc_flags2,
+                  &ctx->rc_idx2,  &ctx->rc2_c,   &ctx->rc2_h,   &ctx->rc2_out32, &ctx->rc2_out64};
   for (Buf* b : cbufs) release(*b);
   for (int i = 0; i < (int)ctx->surs.size(); ++i) isx_surrogate_free(ctx, i);
   if (ctx->h_count) (void)hipHostFree(ctx->h_count);
@@ -562,6 +566,10 @@ isx_status isx_set_option(isx_ctx* ctx, isx_option option, int64_t value) {
     case ISX_AUTOTUNE:
       if (value < 0 || value > 1) return fail(ctx, ISX_EINVAL, "ISX_AUTOTUNE must be 0 or 1");
       ctx->autotune = (int)value;
+      return ISX_OK;
+    case ISX_RECHECK_CASCADE:
+      if (value < 0 || value > 1) return fail(ctx, ISX_EINVAL, "ISX_RECHECK_CASCADE must be 0 or 1");
+      ctx->recheck_cascade = (int)value;
       return ISX_OK;
     case ISX_BF16_READOFF:
       if (value < 0 || value > 1) return fail(ctx, ISX_EINVAL, "ISX_BF16_READOFF must be 0 or 1");
@@ -1038,10 +1046,50 @@ static isx_status prop_classify(isx_ctx* ctx, const Model& m, const isx_params* 
     HIPCHK(ensure(ctx->rc_out64, n_rc * 16));
     HIPCHK(launch_gather_boxes(n_rc, (const uint32_t*)ctx->rc_fidx.p, centres, halves, (float*)ctx->rc_centres.p,
                                (float*)ctx->rc_halves.p, s));
-    st = run_propagate(ctx, m, p->method, ISX_FP64, n_rc, (const float*)ctx->rc_centres.p,
-                       (const float*)ctx->rc_halves.p, (float*)ctx->rc_out32.p, (double*)ctx->rc_out64.p,
-                       p->chunk_cells);
-    if (st != ISX_OK) return st;
+    int64_t n64 = n_rc;
+    if (ctx->recheck_cascade && p->precision == ISX_BF16) {
+      // float32 first; float64 only where the float32 bound still lies within
+      // an eighth of the band of a carried iso-value (the float32 endpoint
+      // error is far below that, so elsewhere both decide alike)
+      st = run_propagate(ctx, m, p->method, ISX_FP32, n_rc, (const float*)ctx->rc_centres.p,
+                         (const float*)ctx->rc_halves.p, (float*)ctx->rc_out32.p, nullptr, p->chunk_cells);
+      if (st != ISX_OK) return st;
+      HIPCHK(launch_widen_pairs(n_rc, (const float*)ctx->rc_out32.p, (double*)ctx->rc_out64.p, s));
+      HIPCHK(ensure(ctx->rc_pm, n_rc * 4));
+      HIPCHK(ensure(ctx->rc_flags2, n_rc * 4));
+      HIPCHK(ensure(ctx->rc_idx2, n_rc * 4));
+      HIPCHK(ensure(ctx->scan_tmp, compact_tmp_bytes(n_rc)));
+      const uint32_t* rc_pm = nullptr;
+      if (pmask) {
+        HIPCHK(gather_u32(n_rc, (const uint32_t*)ctx->rc_fidx.p, pmask, (uint32_t*)ctx->rc_pm.p, s));
+        rc_pm = (const uint32_t*)ctx->rc_pm.p;
+      }
+      HIPCHK(launch_band_flags(n_rc, (const float*)ctx->rc_out32.p, k, iso, rc_pm, 0.125f * p->fp64_band,
+                               0.125f * p->fp64_band_rel, (uint32_t*)ctx->rc_flags2.p, s));
+      HIPCHK(launch_compact(n_rc, (const uint32_t*)ctx->rc_flags2.p, nullptr, (uint32_t*)ctx->rc_idx2.p, nullptr,
+                            (int64_t*)ctx->rc_count.p, ctx->scan_tmp.p, s));
+      st = read_count(ctx, (const int64_t*)ctx->rc_count.p, &n64);
+      if (st != ISX_OK) return st;
+      if (n64 > 0) {
+        HIPCHK(ensure(ctx->rc2_c, n64 * 12));
+        HIPCHK(ensure(ctx->rc2_h, n64 * 12));
+        HIPCHK(ensure(ctx->rc2_out32, n64 * 8));
+        HIPCHK(ensure(ctx->rc2_out64, n64 * 16));
+        const uint32_t* idx2 = (const uint32_t*)ctx->rc_idx2.p;
+        HIPCHK(launch_gather_boxes(n64, idx2, (const float*)ctx->rc_centres.p, (const float*)ctx->rc_halves.p,
+                                   (float*)ctx->rc2_c.p, (float*)ctx->rc2_h.p, s));
+        st = run_propagate(ctx, m, p->method, ISX_FP64, n64, (const float*)ctx->rc2_c.p, (const float*)ctx->rc2_h.p,
+                           (float*)ctx->rc2_out32.p, (double*)ctx->rc2_out64.p, p->chunk_cells);
+        if (st != ISX_OK) return st;
+        HIPCHK(launch_scatter_pairs(n64, idx2, (const double*)ctx->rc2_out64.p, (double*)ctx->rc_out64.p, s));
+      }
+    } else {
+      st = run_propagate(ctx, m, p->method, ISX_FP64, n_rc, (const float*)ctx->rc_centres.p,
+                         (const float*)ctx->rc_halves.p, (float*)ctx->rc_out32.p, (double*)ctx->rc_out64.p,
+                         p->chunk_cells);
+      if (st != ISX_OK) return st;
+    }
+    ctx->n_rc64_last += n64;
     HIPCHK(launch_recheck_apply(n_rc, (const uint32_t*)ctx->rc_fidx.p, (const double*)ctx->rc_out64.p, (double)k, iso,
                                 pmask, out, mask, s));
   }
@@ -1165,6 +1213,7 @@ isx_status isx_extract(isx_ctx* ctx, int32_t mlp_id, const isx_params* p, isx_me
                            ids, pmask, centres, halves, s));
     }
     int64_t n_rc = 0, n_prop = n, n_cx = 0;
+    ctx->n_rc64_last = 0;
     isx_status st = ISX_OK;
     Sur* S = p->use_surrogate ? get_sur(ctx, m.sur_id) : nullptr;
     if (p->use_surrogate && !S) return bail(fail(ctx, ISX_EINVAL, "use_surrogate set but no surrogate attached"));
@@ -1219,6 +1268,7 @@ isx_status isx_extract(isx_ctx* ctx, int32_t mlp_id, const isx_params* p, isx_me
     mesh->lvl_recheck.push_back(n_rc);
     mesh->lvl_prop.push_back(n_prop);
     mesh->lvl_cancel.push_back(n_cx);
+    mesh->lvl_recheck64.push_back(ctx->n_rc64_last);
     if (ctx->verbose) {
       std::fprintf(stderr, "isx: level %d: %lld cells, %lld active, %lld propagated, %lld re-checked, %lld cancelled\n",
                    L, (long long)n, (long long)n_act, (long long)n_prop, (long long)n_rc, (long long)n_cx);
@@ -1372,6 +1422,7 @@ isx_status isx_extract_batch(isx_ctx* ctx, int32_t n, const int32_t* mlp_ids, co
     w->bf16_variant = ctx->bf16_variant;
     w->autotune = ctx->autotune;
     w->readoff_f32 = ctx->readoff_f32;
+    w->recheck_cascade = ctx->recheck_cascade;
     w->up_form = ctx->up_form;
     w->lin_prec = ctx->lin_prec;
     w->aa_margin = ctx->aa_margin;
@@ -1435,6 +1486,12 @@ isx_status isx_mesh_level(const isx_mesh* mesh, int32_t level, int64_t* n_cells,
 isx_status isx_mesh_level_cancelled(const isx_mesh* mesh, int32_t level, int64_t* n_cancelled) {
   if (!mesh || !n_cancelled || level < 0 || level >= (int32_t)mesh->lvl_cancel.size()) return ISX_EINVAL;
   *n_cancelled = mesh->lvl_cancel[level];
+  return ISX_OK;
+}
+
+isx_status isx_mesh_level_rechecked_fp64(const isx_mesh* mesh, int32_t level, int64_t* n_fp64) {
+  if (!mesh || !n_fp64 || level < 0 || level >= (int32_t)mesh->lvl_recheck64.size()) return ISX_EINVAL;
+  *n_fp64 = mesh->lvl_recheck64[level];
   return ISX_OK;
 }
 

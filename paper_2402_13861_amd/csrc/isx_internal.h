@@ -376,6 +376,8 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
 // overwrite the classification of re-checked cells from their float64 bounds.
 hipError_t launch_band_flags(int64_t n, const float* out, float k, const IsoList& iso, const uint32_t* mask_pre,
                              float band, float band_rel, uint32_t* flags, hipStream_t s);
+hipError_t launch_widen_pairs(int64_t n, const float* src, double* dst, hipStream_t s);
+hipError_t launch_scatter_pairs(int64_t n, const uint32_t* idx, const double* src, double* dst, hipStream_t s);
 hipError_t launch_gather_boxes(int64_t n, const uint32_t* idx, const float* centres, const float* halves,
                                float* c_out, float* h_out, hipStream_t s);
 hipError_t launch_recheck_apply(int64_t n, const uint32_t* idx, const double* out64, double k, const IsoList& iso,

@@ -661,6 +661,36 @@ __global__ void recheck_apply_kernel(int64_t n, const uint32_t* __restrict__ idx
   out[2 * i + 1] = (float)s;
 }
 
+// float32 (centre, spread) pairs widened to float64
+__global__ void widen_pairs_kernel(int64_t n, const float* __restrict__ src, double* __restrict__ dst) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  dst[2 * t] = (double)src[2 * t];
+  dst[2 * t + 1] = (double)src[2 * t + 1];
+}
+
+hipError_t launch_widen_pairs(int64_t n, const float* src, double* dst, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(widen_pairs_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, src, dst);
+  return hipGetLastError();
+}
+
+// dst[idx[t]] = src[t] for float64 pairs
+__global__ void scatter_pairs_kernel(int64_t n, const uint32_t* __restrict__ idx, const double* __restrict__ src,
+                                     double* __restrict__ dst) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int64_t i = idx[t];
+  dst[2 * i] = src[2 * t];
+  dst[2 * i + 1] = src[2 * t + 1];
+}
+
+hipError_t launch_scatter_pairs(int64_t n, const uint32_t* idx, const double* src, double* dst, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(scatter_pairs_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, idx, src, dst);
+  return hipGetLastError();
+}
+
 hipError_t launch_recheck_apply(int64_t n, const uint32_t* idx, const double* out64, double k, const IsoList& iso,
                                 const uint32_t* pmask, float* out, uint32_t* mask, hipStream_t s) {
   if (n <= 0) return hipSuccess;

@@ -193,6 +193,16 @@ def test_band_leaf_sets_equal_fp64_extraction_depth7(ctx):
         idsrel, masksrel = mrel.leaves()
         rc_rel = sum(l["rechecked"] for l in mrel.levels())
         mrel.free()
+        # the two-stage re-check: float32 for the band, float64 within an eighth of it
+        ctx.set_option(isx.RECHECK_CASCADE, 1)
+        try:
+            mcas = ctx.extract(mid, isx.UP, isx.BF16, fp64_band=BAND_REL * S, **kw)
+        finally:
+            ctx.set_option(isx.RECHECK_CASCADE, 0)
+        idscas, maskscas = mcas.leaves()
+        lv = mcas.levels()
+        rc_cas, rc_cas64 = sum(l["rechecked"] for l in lv), sum(l["rechecked_fp64"] for l in lv)
+        mcas.free()
     finally:
         ctx.unload_mlp(mid)
     common = np.intersect1d(idsbf, ids64).size
@@ -206,3 +216,8 @@ def test_band_leaf_sets_equal_fp64_extraction_depth7(ctx):
     # the error-aware band re-decides every cell BF16 could misclassify: the float64 sets exactly
     np.testing.assert_array_equal(idsrel, ids64)
     np.testing.assert_array_equal(masksrel, masks64)
+    print(f"two-stage re-check: {rc_cas} band cells, {rc_cas64} of them in float64; leaves {idscas.size}", flush=True)
+    assert rc_cas == rc and rc_cas64 < 0.5 * rc_cas
+    # the float32 decisions outside the inner band are the float64 ones: same sets as the one-stage band
+    np.testing.assert_array_equal(idscas, idsbf)
+    assert common >= 0.9999 * ids64.size and np.intersect1d(idscas, ids64).size == common
