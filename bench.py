@@ -544,6 +544,10 @@ def main(argv=None):
     ap.add_argument("--sur-holdout", type=int, default=1_000_000,
                     help="held-out (cell, propagated) pairs for the error and band calibration")
     ap.add_argument("--sur-steps", type=int, default=2000)
+    ap.add_argument("--sur-miss-target", type=float, default=1e-4,
+                    help="held-out rate of cells the prune band may drop that the plain test keeps, per level")
+    ap.add_argument("--sur-accept-target", type=float, default=1e-3,
+                    help="held-out rate of cells the accept band may accept that the plain test rejects")
     ap.add_argument("--depth", type=int, default=None)
     ap.add_argument("--cpu-baseline-seconds", type=float, default=30.0)
     ap.add_argument("--no-bf16-only", action="store_true",
@@ -558,7 +562,8 @@ def main(argv=None):
                     help="only run the batched 64-INR workload (isx_extract_batch) and exit")
     ap.add_argument("--batch-inrs", type=int, default=64)
     ap.add_argument("--batch-workers", type=int, nargs="+", default=[1, 4, 8])
-    ap.add_argument("--autotune", type=int, default=1, help="time the BF16 coefficient kernel's tile shapes per INR")
+    ap.add_argument("--autotune", type=int, default=0,
+                    help="time the BF16 coefficient kernel's tile shapes per INR (switched off in the library)")
     ap.add_argument("--kl-report", action="store_true",
                     help="only run the distribution-quality report (KL of Eq. 11 over random blocks) and exit")
     ap.add_argument("--kl-blocks", type=int, default=100)
@@ -663,11 +668,13 @@ def main(argv=None):
         t0 = time.perf_counter()
         info = train_surrogate(ctx, mid, depth, mu_bar, S, visited=visited, n_pairs=a.sur_pairs, steps=a.sur_steps,
                                holdout=a.sur_holdout, k=w["k"], accept_leaves=bool(a.accept_leaves),
-                               base=bool(a.sur_base), log=log)
+                               base=bool(a.sur_base), miss_target=a.sur_miss_target,
+                               accept_target=a.sur_accept_target, log=log)
         sur_info = dict(train_total_s=round(time.perf_counter() - t0, 2),
                         pairs=info.n_pairs, steps=info.steps, final_loss=info.final_loss, z=info.z,
                         z_accept=info.z_accept, z_levels=info.z_levels, z_accept_levels=info.z_accept_levels,
-                        holdout_miss=info.holdout_miss,
+                        holdout_miss=info.holdout_miss, miss_target=a.sur_miss_target,
+                        accept_target=a.sur_accept_target,
                         holdout_false_accept=info.holdout_false_accept,
                         accept_leaves=bool(a.accept_leaves), base=bool(a.sur_base),
                         err_mu=[round(x, 5) for x in info.err_mu], err_logsig=[round(x, 4) for x in info.err_logsig])

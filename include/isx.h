@@ -540,7 +540,8 @@ typedef enum {
   ISX_PROFILE = 3,         /* value 1: time every hidden-layer launch with HIP events */
   ISX_SCRATCH_BYTES = 4,   /* bytes of propagation scratch per batch (default 16 GiB) */
   ISX_VERBOSE = 5,         /* value 1: isx_extract prints one line per octree level to stderr */
-  ISX_BF16_VARIANT = 6,    /* bf16 hidden-layer tile shape: 0 = default for the width, 1..4 = forced */
+  ISX_BF16_VARIANT = 6,    /* bf16 hidden-layer tile shape: 0 = default for the width; 1..4 (forced shapes)
+                              currently return ISX_EUNSUPPORTED */
   ISX_UP_FORM = 7,         /* bf16 uncertainty propagation: 0 = covariance form (exact alternative to
                               coefficient tracking: C_h = W_h (D C_{h-1} D + diag(gamma^2)) W_h^T, one
                               fused launch per batch, hidden widths <= 256), 1 = coefficient form */
@@ -566,7 +567,8 @@ typedef enum {
   ISX_AUTOTUNE = 12,       /* bf16 coefficient-form propagation: 1 = pick the hidden-layer tile shape of
                               each MLP by timing the shapes (1, 3, 4 and the default) on 4096 sample
                               cells at its first such propagation (the shapes give identical results);
-                              0 (default) = the default shape for the width, or ISX_BF16_VARIANT */
+                              0 (default) = the default shape for the width, or ISX_BF16_VARIANT;
+                              1 currently returns ISX_EUNSUPPORTED (switched off with the forced shapes) */
   ISX_BF16_READOFF = 13,   /* bf16 uncertainty propagation: 0 (default) = the output read-off on bf16 MFMA
                               with hi/lo splits of the row vectors and weights where the widths allow;
                               1 = the float32 MFMA read-off (the same vectors; for comparison) */

@@ -557,6 +557,10 @@ isx_status isx_set_option(isx_ctx* ctx, isx_option option, int64_t value) {
       return ISX_OK;
     case ISX_BF16_VARIANT:
       if (value < 0 || value > 4) return fail(ctx, ISX_EINVAL, "ISX_BF16_VARIANT must be in [0, 4]");
+      if (value != 0)
+        return fail(ctx, ISX_EUNSUPPORTED,
+                    "tile shapes other than the default are switched off (a device fault surfaced while they ran; "
+                    "its cause is not established)");
       ctx->bf16_variant = (int)value;
       return ISX_OK;
     case ISX_CANCEL_CHECK:
@@ -565,6 +569,10 @@ isx_status isx_set_option(isx_ctx* ctx, isx_option option, int64_t value) {
       return ISX_OK;
     case ISX_AUTOTUNE:
       if (value < 0 || value > 1) return fail(ctx, ISX_EINVAL, "ISX_AUTOTUNE must be 0 or 1");
+      if (value != 0)
+        return fail(ctx, ISX_EUNSUPPORTED,
+                    "tile-shape timing is switched off with the non-default shapes (a device fault surfaced while "
+                    "they ran; its cause is not established)");
       ctx->autotune = (int)value;
       return ISX_OK;
     case ISX_RECHECK_CASCADE:
