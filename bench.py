@@ -544,9 +544,9 @@ def main(argv=None):
     ap.add_argument("--sur-holdout", type=int, default=1_000_000,
                     help="held-out (cell, propagated) pairs for the error and band calibration")
     ap.add_argument("--sur-steps", type=int, default=2000)
-    ap.add_argument("--sur-miss-target", type=float, default=1e-4,
+    ap.add_argument("--sur-miss-target", type=float, default=3e-4,
                     help="held-out rate of cells the prune band may drop that the plain test keeps, per level")
-    ap.add_argument("--sur-accept-target", type=float, default=1e-3,
+    ap.add_argument("--sur-accept-target", type=float, default=1e-2,
                     help="held-out rate of cells the accept band may accept that the plain test rejects")
     ap.add_argument("--depth", type=int, default=None)
     ap.add_argument("--cpu-baseline-seconds", type=float, default=30.0)
