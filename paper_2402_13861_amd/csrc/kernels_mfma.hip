@@ -46,8 +46,10 @@ struct Cfg {
   static constexpr int G = THREADS / BM;       // thread groups in the generated-block pass
 };
 
+// At most 128 VGPRs (four waves per SIMD): two workgroups share a CU, so one
+// workgroup's barriers and chunk stores overlap the other's products.
 template <int METHOD, int BM>
-__global__ __launch_bounds__(512) void hidden_mfma_f32_kernel(
+__global__ __launch_bounds__(512, 4) void hidden_mfma_f32_kernel(
     int64_t C, int n_in, int n_out, int64_t cols_in, int rb_count, const float* __restrict__ Wt,
     const float* __restrict__ bias, const float* __restrict__ Fin, const float* __restrict__ Ain,
     const float* __restrict__ Bin, const float* __restrict__ Gin, float* __restrict__ Fout, float* __restrict__ Y,
@@ -81,14 +83,18 @@ __global__ __launch_bounds__(512) void hidden_mfma_f32_kernel(
   }
   __syncthreads();
 
-  float stat[16];
-#pragma unroll
-  for (int r = 0; r < 16; ++r) stat[r] = 0.f;
+  // each row's statistic, summed over the tiles in order by the wave that
+  // owns the row block (s_stat[wc] is written by wave (wr, wc) only)
+  for (int i = t; i < K::WC * BM; i += K::THREADS) (&s_stat[0][0])[i] = 0.f;
 
   const int64_t ntiles = (cols_in + K::BN - 1) / K::BN;
   for (int64_t nt = 0; nt < ntiles; ++nt) {
     const int64_t c0 = nt * K::BN;
     const bool wave_active = c0 + wc * 32 * K::NB < cols_in;
+    // 32-column blocks of this wave that hold real columns (wave-uniform):
+    // the last tile of a layer is mostly padding (the centre and the three
+    // input symbols make every layer's column count 4 above a multiple of 32)
+    const int nb_real = (int)min((int64_t)K::NB, (cols_in - c0 - wc * 32 * K::NB + 31) / 32);
     v16f acc[K::NB];
 #pragma unroll
     for (int nb = 0; nb < K::NB; ++nb)
@@ -177,6 +183,7 @@ __global__ __launch_bounds__(512) void hidden_mfma_f32_kernel(
           const float a = As[kr * K::ASTR + wr * 32 + (lane & 31)];
 #pragma unroll
           for (int nb = 0; nb < K::NB; ++nb) {
+            if (nb > 0 && nb >= nb_real) break;
             const float bv = Bs[kr * K::BSTR + wc * 32 * K::NB + nb * 32 + (lane & 31)];
             acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bv, acc[nb], 0, 0, 0);
           }
@@ -190,6 +197,9 @@ __global__ __launch_bounds__(512) void hidden_mfma_f32_kernel(
 #undef ISX_F32_STORE_B
     __syncthreads();
     if (wave_active) {
+      float stat[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) stat[r] = 0.f;
 #pragma unroll
       for (int nb = 0; nb < K::NB; ++nb) {
         const int64_t col = c0 + wc * 32 * K::NB + nb * 32 + (lane & 31);
@@ -218,22 +228,23 @@ __global__ __launch_bounds__(512) void hidden_mfma_f32_kernel(
           }
         }
       }
+      // reduce each row's statistic over the 32 lanes holding the tile's
+      // columns and add it to the row's running sum
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        float v = stat[r];
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 8);
+        v += __shfl_xor(v, 4);
+        v += __shfl_xor(v, 2);
+        v += __shfl_xor(v, 1);
+        stat[r] = v;
+      }
+      if ((lane & 31) == 0) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) s_stat[wc][wr * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)] += stat[r];
+      }
     }
-  }
-  // reduce each row's statistic over the 32 lanes holding its columns
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    float v = stat[r];
-    v += __shfl_xor(v, 16);
-    v += __shfl_xor(v, 8);
-    v += __shfl_xor(v, 4);
-    v += __shfl_xor(v, 2);
-    v += __shfl_xor(v, 1);
-    stat[r] = v;
-  }
-  if ((lane & 31) == 0) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) s_stat[wc][wr * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)] = stat[r];
   }
   // new symbol block W diag(gamma_{h-1}) and its statistic
   {
