@@ -106,7 +106,7 @@ struct isx_ctx {
   Buf cls_mask;
   // surrogate: models, training/inference activations, extraction scratch
   std::vector<Sur> surs;
-  Buf sur_act[ISX_MAX_LINEAR + 1], sur_out, sur_T, sur_d[2], sur_base, sp_base, sp_scale;
+  Buf sur_act[ISX_MAX_LINEAR + 1], sur_out, sur_T, sur_d[2], sur_base, sp_base, sp_scale, sur_work;
   Buf sp_pred, sp_fb, sp_idx, sp_pm, sp_c, sp_h, sp_out, sp_mask, sp_cnt, sp_tmp;
   Buf rc_flags, rc_fidx, rc_fmask;
   Buf rc_pm, rc_flags2, rc_idx2, rc2_c, rc2_h, rc2_out32, rc2_out64;  // two-stage re-check
@@ -503,7 +503,7 @@ isx_status isx_destroy(isx_ctx* ctx) {
   Buf* sbufs[] = {&ctx->sur_out, &ctx->sur_T, &ctx->sur_d[0], &ctx->sur_d[1], &ctx->sur_base, &ctx->sp_base,
                   &ctx->sp_scale, &ctx->sp_pred, &ctx->sp_fb,
                   &ctx->sp_idx, &ctx->sp_pm, &ctx->sp_c, &ctx->sp_h, &ctx->sp_out, &ctx->sp_mask, &ctx->sp_cnt,
-                  &ctx->sp_tmp, &ctx->rc_flags, &ctx->rc_fidx, &ctx->rc_fmask};
+                  &ctx->sp_tmp, &ctx->rc_flags, &ctx->rc_fidx, &ctx->rc_fmask, &ctx->sur_work};
   for (Buf* b : sbufs) release(*b);
   for (Buf& b : ctx->sur_act) release(b);
   Buf* cbufs[] = {&ctx->cx_flags, &ctx->cx_idx, &ctx->cx_c,     &ctx->cx_h,     &ctx->cx_out,   &ctx->cx_out64,
@@ -1727,8 +1727,13 @@ static isx_status sur_fwd_bwd(isx_ctx* ctx, Sur& S, int64_t n, const float* d_ce
   for (int l = S.L - 1; l >= 0; --l) {
     const float* dY = (const float*)ctx->sur_d[cur].p;
     // dW = dY^T H_l,  db = column sums of dY,  dH_l = (dY W_l) . [H_l > 0]
-    HIPCHK(sur_gemm(S.w[l + 1], S.w[l], batch, dY, S.w[l + 1], true, (const float*)ctx->sur_act[l].p, S.w[l], false,
-                    S.gW[l], S.w[l], nullptr, false, nullptr, 0, s));
+    {
+      // (K = batch rows against a few output tiles: split K)
+      const size_t we = (size_t)sur_gemm_splits(S.w[l + 1], S.w[l], batch) * S.w[l + 1] * S.w[l];
+      HIPCHK(ensure(ctx->sur_work, we * 4));
+      HIPCHK(sur_gemm_splitk(S.w[l + 1], S.w[l], batch, dY, S.w[l + 1], true, (const float*)ctx->sur_act[l].p,
+                             S.w[l], false, S.gW[l], S.w[l], (float*)ctx->sur_work.p, we, s));
+    }
     HIPCHK(sur_colsum(batch, S.w[l + 1], dY, S.gb[l], s));
     if (l > 0) {
       HIPCHK(sur_gemm(batch, S.w[l], S.w[l + 1], dY, S.w[l + 1], false, S.W[l], S.w[l], false,

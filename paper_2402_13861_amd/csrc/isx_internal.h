@@ -386,6 +386,12 @@ hipError_t launch_recheck_apply(int64_t n, const uint32_t* idx, const double* ou
 // ---- surrogate kernels (kernels_sur.hip) ----
 hipError_t sur_gemm(int M, int N, int K, const float* A, int lda, bool ta, const float* B, int ldb, bool tb, float* C,
                     int ldc, const float* bias, bool relu, const float* mask, int ldm, hipStream_t s);
+// C = A B without epilogue, K split over workgroups when the M x N tiles are
+// too few to fill the chip (partials in `work`, which needs
+// sur_gemm_splits(M, N, K) * M * N floats, else no split)
+int sur_gemm_splits(int M, int N, int K);
+hipError_t sur_gemm_splitk(int M, int N, int K, const float* A, int lda, bool ta, const float* B, int ldb, bool tb,
+                           float* C, int ldc, float* work, size_t work_elems, hipStream_t s);
 hipError_t sur_features(int64_t n, int64_t r0, int B, const float* centres, const float* halves, float a, float b,
                         float* X, const float* mu_sigma, float mu_bar, float scale, const float* base,
                         float s_floor, float* T, hipStream_t s);

@@ -17,6 +17,9 @@ typedef float sv16f __attribute__((ext_vector_type(16)));
 // staged, float32 accumulation.  A(m,k) = ta ? A[k*lda+m] : A[m*lda+k];
 // B(k,n) = tb ? B[n*ldb+k] : B[k*ldb+n].  Epilogue: + bias[n], ReLU, times
 // (mask[m*ldm+n] > 0).  64x64 tiles, 4 waves of 32x32 (32x32x16 bf16 MFMA).
+// Split K: workgroup z sums k in [z kc, (z+1) kc) and writes its partial
+// tile, without the epilogue, to part[z][M][N]; a second kernel adds the
+// partials in z order (deterministic).
 constexpr int GT = 64;       // tile edge
 constexpr int GK = 32;       // K chunk
 constexpr int GKP = GK + 8;  // padded bf16 row in LDS
@@ -24,7 +27,8 @@ constexpr int GKP = GK + 8;  // padded bf16 row in LDS
 __global__ __launch_bounds__(256) void sur_gemm_kernel(int M, int N, int K, const float* __restrict__ A, int lda,
                                                        int ta, const float* __restrict__ B, int ldb, int tb,
                                                        float* __restrict__ Cm, int ldc, const float* __restrict__ bias,
-                                                       int relu, const float* __restrict__ mask, int ldm) {
+                                                       int relu, const float* __restrict__ mask, int ldm, int kc,
+                                                       float* __restrict__ part) {
   __shared__ __bf16 As[GT * GKP];
   __shared__ __bf16 Bs[GT * GKP];
   const int t = threadIdx.x, lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);  // wave-uniform
@@ -33,7 +37,8 @@ __global__ __launch_bounds__(256) void sur_gemm_kernel(int M, int N, int K, cons
   sv16f acc;
 #pragma unroll
   for (int i = 0; i < 16; ++i) acc[i] = 0.f;
-  for (int k0 = 0; k0 < K; k0 += GK) {
+  const int kbeg = blockIdx.z * kc, kend = min(K, kbeg + kc);
+  for (int k0 = kbeg; k0 < kend; k0 += GK) {
     for (int i = t; i < GT * GK; i += 256) {
       // consecutive threads walk the contiguous index of each operand
       int r, kk;
@@ -46,7 +51,7 @@ __global__ __launch_bounds__(256) void sur_gemm_kernel(int M, int N, int K, cons
       }
       const int m = m0 + r, k = k0 + kk;
       float v = 0.f;
-      if (m < M && k < K) v = ta ? A[(int64_t)k * lda + m] : A[(int64_t)m * lda + k];
+      if (m < M && k < kend) v = ta ? A[(int64_t)k * lda + m] : A[(int64_t)m * lda + k];
       As[r * GKP + kk] = (__bf16)v;
     }
     for (int i = t; i < GT * GK; i += 256) {
@@ -60,7 +65,7 @@ __global__ __launch_bounds__(256) void sur_gemm_kernel(int M, int N, int K, cons
       }
       const int n = n0 + c, k = k0 + kk;
       float v = 0.f;
-      if (n < N && k < K) v = tb ? B[(int64_t)n * ldb + k] : B[(int64_t)k * ldb + n];
+      if (n < N && k < kend) v = tb ? B[(int64_t)n * ldb + k] : B[(int64_t)k * ldb + n];
       Bs[c * GKP + kk] = (__bf16)v;
     }
     __syncthreads();
@@ -77,7 +82,9 @@ __global__ __launch_bounds__(256) void sur_gemm_kernel(int M, int N, int K, cons
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int m = m0 + wr * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-      if (m < M) {
+      if (m < M && part) {
+        part[((int64_t)blockIdx.z * M + m) * N + n] = acc[r];
+      } else if (m < M) {
         float v = acc[r];
         if (bias) v += bias[n];
         if (relu) v = v > 0.f ? v : 0.f;
@@ -88,12 +95,50 @@ __global__ __launch_bounds__(256) void sur_gemm_kernel(int M, int N, int K, cons
   }
 }
 
+// C[m][n] = sum_z part[z][m][n], z in order
+__global__ void sur_splitk_sum_kernel(int M, int N, int splits, const float* __restrict__ part, float* __restrict__ C,
+                                      int ldc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)M * N) return;
+  const int m = (int)(i / N), n = (int)(i - (int64_t)m * N);
+  float v = 0.f;
+  for (int z = 0; z < splits; ++z) v += part[(int64_t)z * M * N + i];
+  C[(int64_t)m * ldc + n] = v;
+}
+
 hipError_t sur_gemm(int M, int N, int K, const float* A, int lda, bool ta, const float* B, int ldb, bool tb, float* C,
                     int ldc, const float* bias, bool relu, const float* mask, int ldm, hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
   dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
   hipLaunchKernelGGL(sur_gemm_kernel, grid, dim3(256), 0, s, M, N, K, A, lda, (int)ta, B, ldb, (int)tb, C, ldc, bias,
-                     (int)relu, mask, ldm);
+                     (int)relu, mask, ldm, K, (float*)nullptr);
+  return hipGetLastError();
+}
+
+int sur_gemm_splits(int M, int N, int K) {
+  const int tiles = ((N + GT - 1) / GT) * ((M + GT - 1) / GT);
+  // at least two K chunks per workgroup, and about 256 workgroups in all
+  const int by_k = std::max(1, K / (2 * GK));
+  const int want = std::max(1, (256 + tiles - 1) / tiles);
+  const int splits = std::min(by_k, want);
+  if (splits <= 1) return 1;
+  const int kc = ((K + splits - 1) / splits + GK - 1) / GK * GK;
+  return (K + kc - 1) / kc;
+}
+
+hipError_t sur_gemm_splitk(int M, int N, int K, const float* A, int lda, bool ta, const float* B, int ldb, bool tb,
+                           float* C, int ldc, float* work, size_t work_elems, hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const int splits = sur_gemm_splits(M, N, K);
+  if (splits <= 1 || !work || work_elems < (size_t)splits * M * N)
+    return sur_gemm(M, N, K, A, lda, ta, B, ldb, tb, C, ldc, nullptr, false, nullptr, 0, s);
+  const int kc = ((K + splits - 1) / splits + GK - 1) / GK * GK;
+  dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT, splits);
+  hipLaunchKernelGGL(sur_gemm_kernel, grid, dim3(256), 0, s, M, N, K, A, lda, (int)ta, B, ldb, (int)tb, C, ldc,
+                     (const float*)nullptr, 0, (const float*)nullptr, 0, kc, work);
+  const int64_t mn = (int64_t)M * N;
+  hipLaunchKernelGGL(sur_splitk_sum_kernel, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, s, M, N, splits,
+                     (const float*)work, C, ldc);
   return hipGetLastError();
 }
 
