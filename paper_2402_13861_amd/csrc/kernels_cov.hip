@@ -378,10 +378,10 @@ __global__ __launch_bounds__(kCovThreads) void up_cov_bf16_kernel(int64_t C, int
               const float4 z4 = *reinterpret_cast<const float4*>(s_zin + i0);
               const float t0 = acc[r][c][4 * q4 + 0], t1 = acc[r][c][4 * q4 + 1];
               const float t2 = acc[r][c][4 * q4 + 2], t3 = acc[r][c][4 * q4 + 3];
-              const float e0 = w4.x * t0, e1 = w4.y * t1, e2 = w4.z * t2, e3 = w4.w * t3;
-              pv[r] += e0 + e1 + e2 + e3;
-              pa[r] += fabsf(e0) + fabsf(e1) + fabsf(e2) + fabsf(e3);
-              py[r] += w4.x * z4.x + w4.y * z4.y + w4.z * z4.z + w4.w * z4.w;
+              pv[r] = fmaf(w4.x, t0, fmaf(w4.y, t1, fmaf(w4.z, t2, fmaf(w4.w, t3, pv[r]))));
+              pa[r] = fmaf(fabsf(w4.x), fabsf(t0),
+                           fmaf(fabsf(w4.y), fabsf(t1), fmaf(fabsf(w4.z), fabsf(t2), fmaf(fabsf(w4.w), fabsf(t3), pa[r]))));
+              py[r] = fmaf(w4.x, z4.x, fmaf(w4.y, z4.y, fmaf(w4.z, z4.z, fmaf(w4.w, z4.w, py[r]))));
               if (!last) {
                 __bf16 v4[4] = {(__bf16)t0, (__bf16)t1, (__bf16)t2, (__bf16)t3};
                 *reinterpret_cast<uint2*>(X + (size_t)j * STR + i0) = *reinterpret_cast<const uint2*>(v4);
