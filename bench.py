@@ -535,6 +535,8 @@ def main(argv=None):
     ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16"])
     ap.add_argument("--no-surrogate", action="store_true", help="headline path without the learned surrogate")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 reference run")
+    ap.add_argument("--no-dense", action="store_true",
+                    help="skip the dense baseline (the INR at every grid corner and marching cubes on every cell)")
     ap.add_argument("--accept-leaves", type=int, default=1,
                     help="let the surrogate accept leaves it is confident about (recall is unaffected)")
     ap.add_argument("--sur-base", type=int, default=1,
@@ -728,6 +730,21 @@ def main(argv=None):
                        plain_leaves=int(plain_ids.size), leaves=int(last_ids.size))
         log("quality:", quality)
 
+    # dense baseline (context, outside the timed region): the INR at every
+    # corner of the (2^D)^3 grid and marching cubes on every cell, float32
+    dense = None
+    if not a.no_dense:
+        ctx.extract_dense(mid, depth, isx.FP32).free()  # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dm = ctx.extract_dense(mid, depth, isx.FP32)
+        dense_s = time.perf_counter() - t0
+        dense = dict(ms=round(1e3 * dense_s, 1), phases={k_: round(v_, 2) for k_, v_ in dm.times().items()},
+                     corners=dm.n_corners, tris=dm.n_tris,
+                     ratio_to_step=round(1e3 * dense_s / ms_per_step, 3))
+        dm.free()
+        log(f"dense baseline: {dense}")
+
     # per hidden-layer kernel kind: achieved rate at the algorithmic flop count
     # of its formulation (coefficient form: alg_flops_coefficient per cell;
     # covariance form: the cheapest exact formulation, alg_flops_cov_hybrid),
@@ -844,6 +861,7 @@ def main(argv=None):
         "speedup_vs_plain_fp32": (plain["ms"] / ms_per_step) if plain else None,
         "quality": quality,
         "bf16_only": bf16_only,
+        "dense_gpu": dense,
         "bf16_err_vs_oracle": err_oracle,
         "surrogate": sur_info,
         "examined_cells": examined,

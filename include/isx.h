@@ -269,6 +269,20 @@ typedef struct {
  * ISX_EHIP. */
 isx_status isx_extract(isx_ctx* ctx, int32_t mlp_id, const isx_params* params, isx_mesh** out);
 
+/* Dense baseline (the reference point for the range analysis): every cell
+ * of the (2^depth)^3 grid is a leaf for every iso-value, so the INR is
+ * evaluated at all (2^depth + 1)^3 grid corners (float64 for ISX_FP64, else
+ * float32) and marching cubes runs on every (cell, iso) pair (corner
+ * evaluation and marching cubes as in isx_extract, Sec. IV-C).  *out
+ * receives a library-owned mesh with the same triangle layout as
+ * isx_extract's; it records no octree levels, and its times are the leaf
+ * list (ms_acp), the corner values (ms_inr) and marching cubes (ms_mc).
+ * Synchronises the stream.  Errors: ISX_EINVAL (bad id, precision or depth
+ * outside [0, 10], no iso-values), ISX_ECAPACITY (more than 2^28 cells or
+ * 2^31 (cell, iso) pairs), ISX_ENOMEM, ISX_EHIP. */
+isx_status isx_extract_dense(isx_ctx* ctx, int32_t mlp_id, int32_t depth, isx_precision precision,
+                             isx_mesh** out);
+
 /* isx_extract_batch: isx_extract of n INRs (mlp_ids[i], each with its own
  * iso-values and attached surrogate) with the same params; out[i] receives
  * INR i's mesh.  The INRs are dealt to up to ISX_BATCH_WORKERS worker

@@ -457,6 +457,13 @@ class Context:
         self._chk(self._L.isx_extract(self._h, mlp_id, C.byref(p), C.byref(h)))
         return Mesh(self._L, h)
 
+    def extract_dense(self, mlp_id: int, max_depth: int, precision: int = FP32) -> "Mesh":
+        """isx_extract_dense: the INR at every corner of the (2^D)^3 grid and
+        marching cubes on every cell (the dense baseline)."""
+        h = C.c_void_p()
+        self._chk(self._L.isx_extract_dense(self._h, int(mlp_id), int(max_depth), int(precision), C.byref(h)))
+        return Mesh(self._L, h)
+
     def extract_batch(self, mlp_ids, method: int = UP, precision: int = FP32, k: float = 3.0, max_depth: int = 6,
                       fp64_band: float = 0.0, max_cells: int = 0, chunk_cells: int = 0,
                       use_surrogate: bool = False, fp64_band_rel: float = 0.0) -> list:

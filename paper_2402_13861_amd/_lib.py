@@ -120,6 +120,7 @@ _SIGS = [
     ("isx_distribution_kl", C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.c_int64,
                                       C.c_int32, C.c_int32, C.c_uint64, C.c_void_p, C.c_void_p]),
     ("isx_extract", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Params), C.POINTER(C.c_void_p)]),
+    ("isx_extract_dense", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int, C.POINTER(C.c_void_p)]),
     ("isx_extract_batch", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(Params),
                                     C.POINTER(C.c_void_p)]),
     ("isx_mesh_info", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),

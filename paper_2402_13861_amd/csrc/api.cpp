@@ -1140,6 +1140,71 @@ static isx_status sur_predict_n(isx_ctx* ctx, Sur& S, int64_t n, const float* ce
   return ISX_OK;
 }
 
+// Leaf phase shared by the extractions: the leaves (ids, masks on the
+// device) are copied into the mesh, their distinct corners evaluated (float64
+// for ISX_FP64, else float32) and marching cubes run on every (leaf, iso)
+// pair of the masks.  Records ev_inr after the corner values and ev_mc after
+// the triangles; on an error the caller frees the mesh.
+static isx_status leaf_phase(isx_ctx* ctx, const Model& m, int D, isx_precision prec, int64_t n_leaves,
+                             const uint32_t* ids, const uint32_t* masks, isx_mesh* mesh, hipEvent_t ev_inr,
+                             hipEvent_t ev_mc) {
+  hipStream_t s = ctx->stream;
+  mesh->n_leaves = n_leaves;
+  HIPCHK(hipMalloc((void**)&mesh->leaf_ids, std::max<int64_t>(1, n_leaves) * 4));
+  HIPCHK(hipMalloc((void**)&mesh->leaf_masks, std::max<int64_t>(1, n_leaves) * 4));
+  if (n_leaves > 0) {
+    HIPCHK(hipMemcpyAsync(mesh->leaf_ids, ids, n_leaves * 4, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(mesh->leaf_masks, masks, n_leaves * 4, hipMemcpyDeviceToDevice, s));
+  }
+  // corners: bitmap, prefix, list, points, values
+  const uint64_t words = corner_bitmap_words(D);
+  HIPCHK(ensure(ctx->bitmap, words * 4));
+  HIPCHK(ensure(ctx->word_prefix, words * 4));
+  HIPCHK(ensure(ctx->scan_tmp, std::max(scan_tmp_bytes((int64_t)words), scan_tmp_bytes(n_leaves * m.n_iso))));
+  HIPCHK(launch_corner_mark(D, n_leaves, mesh->leaf_ids, (uint32_t*)ctx->bitmap.p, words, s));
+  HIPCHK(launch_corner_list(D, words, (const uint32_t*)ctx->bitmap.p, (uint32_t*)ctx->word_prefix.p,
+                          (int64_t*)ctx->count.p, ctx->scan_tmp.p, ctx->scan_tmp.bytes, nullptr, s));
+  int64_t n_corners = 0;
+  {
+    isx_status st = read_count(ctx, (const int64_t*)ctx->count.p, &n_corners);
+    if (st != ISX_OK) return st;
+  }
+  mesh->n_corners = n_corners;
+  HIPCHK(ensure(ctx->corner_g, n_corners * 4));
+  HIPCHK(ensure(ctx->corner_pts, n_corners * 12));
+  HIPCHK(ensure(ctx->corner_vals, n_corners * 4));
+  HIPCHK(launch_corner_list(D, words, (const uint32_t*)ctx->bitmap.p, (uint32_t*)ctx->word_prefix.p,
+                          (int64_t*)ctx->count.p, ctx->scan_tmp.p, ctx->scan_tmp.bytes, (uint32_t*)ctx->corner_g.p,
+                          s));
+  HIPCHK(launch_corner_points(m, D, n_corners, (const uint32_t*)ctx->corner_g.p, (float*)ctx->corner_pts.p, s));
+  if (prec == ISX_FP64) {
+    HIPCHK(eval_points_f64(m, n_corners, (const float*)ctx->corner_pts.p, (float*)ctx->corner_vals.p, s));
+  } else {
+    HIPCHK(eval_f32(ctx, m, n_corners, (const float*)ctx->corner_pts.p, (float*)ctx->corner_vals.p, s));
+  }
+  HIPCHK(hipEventRecord(ev_inr, s));
+  // marching cubes
+  const int64_t pairs = n_leaves * m.n_iso;
+  HIPCHK(ensure(ctx->tri_off, std::max<int64_t>(1, pairs) * 4));
+  HIPCHK(launch_mc_count(m, D, n_leaves, mesh->leaf_ids, mesh->leaf_masks, (const uint32_t*)ctx->bitmap.p,
+                       (const uint32_t*)ctx->word_prefix.p, (const float*)ctx->corner_vals.p, (uint32_t*)ctx->tri_off.p,
+                       (int64_t*)ctx->count.p, ctx->scan_tmp.p, ctx->scan_tmp.bytes, s));
+  int64_t n_tris = 0;
+  {
+    isx_status st = read_count(ctx, (const int64_t*)ctx->count.p, &n_tris);
+    if (st != ISX_OK) return st;
+  }
+  mesh->n_tris = n_tris;
+  HIPCHK(hipMalloc((void**)&mesh->tri_pos, std::max<int64_t>(1, n_tris) * 36));
+  HIPCHK(hipMalloc((void**)&mesh->tri_keys, std::max<int64_t>(1, n_tris) * 24));
+  HIPCHK(hipMalloc((void**)&mesh->tri_iso, std::max<int64_t>(1, n_tris) * 4));
+  HIPCHK(launch_mc_emit(m, D, n_leaves, mesh->leaf_ids, mesh->leaf_masks, (const uint32_t*)ctx->bitmap.p,
+                      (const uint32_t*)ctx->word_prefix.p, (const float*)ctx->corner_vals.p,
+                      (const uint32_t*)ctx->tri_off.p, mesh->tri_pos, mesh->tri_keys, mesh->tri_iso, s));
+  HIPCHK(hipEventRecord(ev_mc, s));
+  return ISX_OK;
+}
+
 isx_status isx_extract(isx_ctx* ctx, int32_t mlp_id, const isx_params* p, isx_mesh** out) {
   Model* mp = get_model(ctx, mlp_id);
   if (!mp || !p || !out) return fail(ctx, ISX_EINVAL, "bad arguments");
@@ -1300,62 +1365,69 @@ isx_status isx_extract(isx_ctx* ctx, int32_t mlp_id, const isx_params* p, isx_me
   if (kd) XCHK(launch_kd_to_morton(n_par, p->max_depth, (uint32_t*)ctx->act_ids[cur].p, s));
   XCHK(hipEventRecord(ev[1], s));
 
-  // active leaves
-  const int D = p->max_depth;
-  const int64_t n_leaves = n_par;
-  mesh->n_leaves = n_leaves;
-  XCHK(hipMalloc((void**)&mesh->leaf_ids, std::max<int64_t>(1, n_leaves) * 4));
-  XCHK(hipMalloc((void**)&mesh->leaf_masks, std::max<int64_t>(1, n_leaves) * 4));
-  if (n_leaves > 0) {
-    XCHK(hipMemcpyAsync(mesh->leaf_ids, ctx->act_ids[cur].p, n_leaves * 4, hipMemcpyDeviceToDevice, s));
-    XCHK(hipMemcpyAsync(mesh->leaf_masks, ctx->act_mask[cur].p, n_leaves * 4, hipMemcpyDeviceToDevice, s));
-  }
-  // corners: bitmap, prefix, list, points, values
-  const uint64_t words = corner_bitmap_words(D);
-  XCHK(ensure(ctx->bitmap, words * 4));
-  XCHK(ensure(ctx->word_prefix, words * 4));
-  XCHK(ensure(ctx->scan_tmp, std::max(scan_tmp_bytes((int64_t)words), scan_tmp_bytes(n_leaves * m.n_iso))));
-  XCHK(launch_corner_mark(D, n_leaves, mesh->leaf_ids, (uint32_t*)ctx->bitmap.p, words, s));
-  XCHK(launch_corner_list(D, words, (const uint32_t*)ctx->bitmap.p, (uint32_t*)ctx->word_prefix.p,
-                          (int64_t*)ctx->count.p, ctx->scan_tmp.p, ctx->scan_tmp.bytes, nullptr, s));
-  int64_t n_corners = 0;
   {
-    isx_status st = read_count(ctx, (const int64_t*)ctx->count.p, &n_corners);
+    isx_status st = leaf_phase(ctx, m, p->max_depth, p->precision, n_par, (const uint32_t*)ctx->act_ids[cur].p,
+                               (const uint32_t*)ctx->act_mask[cur].p, mesh, ev[2], ev[3]);
     if (st != ISX_OK) return bail(st);
   }
-  mesh->n_corners = n_corners;
-  XCHK(ensure(ctx->corner_g, n_corners * 4));
-  XCHK(ensure(ctx->corner_pts, n_corners * 12));
-  XCHK(ensure(ctx->corner_vals, n_corners * 4));
-  XCHK(launch_corner_list(D, words, (const uint32_t*)ctx->bitmap.p, (uint32_t*)ctx->word_prefix.p,
-                          (int64_t*)ctx->count.p, ctx->scan_tmp.p, ctx->scan_tmp.bytes, (uint32_t*)ctx->corner_g.p,
-                          s));
-  XCHK(launch_corner_points(m, D, n_corners, (const uint32_t*)ctx->corner_g.p, (float*)ctx->corner_pts.p, s));
-  if (p->precision == ISX_FP64) {
-    XCHK(eval_points_f64(m, n_corners, (const float*)ctx->corner_pts.p, (float*)ctx->corner_vals.p, s));
-  } else {
-    XCHK(eval_f32(ctx, m, n_corners, (const float*)ctx->corner_pts.p, (float*)ctx->corner_vals.p, s));
-  }
-  XCHK(hipEventRecord(ev[2], s));
-  // marching cubes
-  const int64_t pairs = n_leaves * m.n_iso;
-  XCHK(ensure(ctx->tri_off, std::max<int64_t>(1, pairs) * 4));
-  XCHK(launch_mc_count(m, D, n_leaves, mesh->leaf_ids, mesh->leaf_masks, (const uint32_t*)ctx->bitmap.p,
-                       (const uint32_t*)ctx->word_prefix.p, (const float*)ctx->corner_vals.p, (uint32_t*)ctx->tri_off.p,
-                       (int64_t*)ctx->count.p, ctx->scan_tmp.p, ctx->scan_tmp.bytes, s));
-  int64_t n_tris = 0;
+  XCHK(hipEventSynchronize(ev[3]));
+  float t01 = 0, t12 = 0, t23 = 0, t03 = 0;
+  XCHK(hipEventElapsedTime(&t01, ev[0], ev[1]));
+  XCHK(hipEventElapsedTime(&t12, ev[1], ev[2]));
+  XCHK(hipEventElapsedTime(&t23, ev[2], ev[3]));
+  XCHK(hipEventElapsedTime(&t03, ev[0], ev[3]));
+  mesh->ms_acp = t01;
+  mesh->ms_inr = t12;
+  mesh->ms_mc = t23;
+  mesh->ms_total = t03;
+  for (auto& e : ev) (void)hipEventDestroy(e);
+#undef XCHK
+  *out = mesh;
+  return ISX_OK;
+}
+
+isx_status isx_extract_dense(isx_ctx* ctx, int32_t mlp_id, int32_t depth, isx_precision precision,
+                             isx_mesh** out) {
+  Model* mp = get_model(ctx, mlp_id);
+  if (!mp || !out) return fail(ctx, ISX_EINVAL, "bad arguments");
+  *out = nullptr;
+  const Model& m = *mp;
+  if (precision != ISX_FP32 && precision != ISX_BF16 && precision != ISX_FP64)
+    return fail(ctx, ISX_EINVAL, "unknown precision");
+  if (depth < 0 || depth > 10) return fail(ctx, ISX_EINVAL, "depth must be in [0, 10]");
+  if (m.n_iso < 1) return fail(ctx, ISX_EINVAL, "no iso-values set");
+  const int64_t n = (int64_t)1 << (3 * depth);
+  if (n > ((int64_t)1 << 28) || n * m.n_iso > ((int64_t)1 << 31))
+    return fail(ctx, ISX_ECAPACITY, "the dense grid of depth " + std::to_string(depth) + " with " +
+                                        std::to_string(m.n_iso) + " iso-values exceeds 2^28 cells or 2^31 pairs");
+  (void)hipSetDevice(ctx->device);
+  hipStream_t s = ctx->stream;
+  const uint32_t full = m.n_iso >= 32 ? 0xffffffffu : ((1u << m.n_iso) - 1u);
+  hipEvent_t ev[4];
+  for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+  isx_mesh* mesh = new isx_mesh();
+  mesh->depth = depth;
+  auto bail = [&](isx_status st) {
+    isx_mesh_free(mesh);
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    return st;
+  };
+#define XCHK(expr)                                               \
+  do {                                                           \
+    hipError_t _e = (expr);                                      \
+    if (_e != hipSuccess) return bail(hip_fail(ctx, _e, #expr)); \
+  } while (0)
+  XCHK(hipEventRecord(ev[0], s));
+  XCHK(ensure(ctx->act_ids[0], n * 4));
+  XCHK(ensure(ctx->act_mask[0], n * 4));
+  XCHK(ensure(ctx->count, 2 * sizeof(int64_t)));
+  XCHK(launch_dense_leaves(n, full, (uint32_t*)ctx->act_ids[0].p, (uint32_t*)ctx->act_mask[0].p, s));
+  XCHK(hipEventRecord(ev[1], s));
   {
-    isx_status st = read_count(ctx, (const int64_t*)ctx->count.p, &n_tris);
+    isx_status st = leaf_phase(ctx, m, depth, precision, n, (const uint32_t*)ctx->act_ids[0].p,
+                               (const uint32_t*)ctx->act_mask[0].p, mesh, ev[2], ev[3]);
     if (st != ISX_OK) return bail(st);
   }
-  mesh->n_tris = n_tris;
-  XCHK(hipMalloc((void**)&mesh->tri_pos, std::max<int64_t>(1, n_tris) * 36));
-  XCHK(hipMalloc((void**)&mesh->tri_keys, std::max<int64_t>(1, n_tris) * 24));
-  XCHK(hipMalloc((void**)&mesh->tri_iso, std::max<int64_t>(1, n_tris) * 4));
-  XCHK(launch_mc_emit(m, D, n_leaves, mesh->leaf_ids, mesh->leaf_masks, (const uint32_t*)ctx->bitmap.p,
-                      (const uint32_t*)ctx->word_prefix.p, (const float*)ctx->corner_vals.p,
-                      (const uint32_t*)ctx->tri_off.p, mesh->tri_pos, mesh->tri_keys, mesh->tri_iso, s));
-  XCHK(hipEventRecord(ev[3], s));
   XCHK(hipEventSynchronize(ev[3]));
   float t01 = 0, t12 = 0, t23 = 0, t03 = 0;
   XCHK(hipEventElapsedTime(&t01, ev[0], ev[1]));

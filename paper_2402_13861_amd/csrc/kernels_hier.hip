@@ -91,6 +91,22 @@ hipError_t launch_children(const Model& m, int level, int64_t n_par, const uint3
   return hipGetLastError();
 }
 
+// Every cell of one level as a leaf for every iso-value (the dense
+// baseline): ids 0 .. n-1 are the level's Morton codes in order.
+__global__ void dense_leaves_kernel(int64_t n, uint32_t full, uint32_t* __restrict__ ids,
+                                    uint32_t* __restrict__ masks) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  ids[i] = (uint32_t)i;
+  masks[i] = full;
+}
+
+hipError_t launch_dense_leaves(int64_t n, uint32_t full, uint32_t* ids, uint32_t* masks, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(dense_leaves_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, full, ids, masks);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------ k-d tree
 // Alg. 1's own tree: every node is split in two along its widest dimension,
 // ties broken x, then y, then z.  On a cube domain all nodes of a depth have

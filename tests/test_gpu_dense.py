@@ -1,0 +1,126 @@
+"""GPU: the dense baseline (isx_extract_dense) -- the INR at every grid corner
+and marching cubes on every cell -- against the oracle's brute-force dense
+surface, and against the hierarchical extraction with sound (margin-widened)
+affine arithmetic, which must keep every cell the surface crosses.
+
+Tolerances: triangle sets (grid-edge keys per iso-value) exact; with the
+same float32 corner evaluation on both sides, vertex positions bit-exact.
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import mc
+from oracle.mlp import mlp_forward
+from workloads import he_normal_mlp, uniform_points
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2402_13861_amd as isx
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    c = isx.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def _isos(mlp, qs, seed=1):
+    vals = mlp_forward(mlp, uniform_points(4000, seed=seed))
+    return [float(np.float32(np.quantile(vals, q))) for q in qs]
+
+
+def _tri_set(pos, keys, iso):
+    """{(iso, sorted edge keys): vertex positions in key order}"""
+    out = {}
+    for p, k, i in zip(pos, keys, iso):
+        order = np.argsort(k)
+        out[(int(i),) + tuple(int(x) for x in k[order])] = p[order].tobytes()
+    return out
+
+
+def test_dense_equals_dense_oracle_fp64(ctx):
+    """Float64 corner values: the same triangles (grid-edge keys) as the
+    oracle's dense marching cubes, for two iso-values."""
+    import paper_2402_13861_amd as isx
+
+    mlp = he_normal_mlp([3, 32, 32, 1], seed=3)
+    depth = 5
+    isos = _isos(mlp, [0.3, 0.7])
+    mid = ctx.load_weights(mlp)
+    try:
+        ctx.set_isovalues(mid, isos)
+        mesh = ctx.extract_dense(mid, depth, isx.FP64)
+        assert mesh.n_leaves == 8 ** depth
+        assert mesh.n_corners == (2 ** depth + 1) ** 3
+        assert mesh.n_levels == 0
+        _, keys, iso = mesh.triangles()
+        grid = mc.dense_grid(lambda p: mlp_forward(mlp, p), depth)
+        ijk, cv = mc.dense_cells(grid)
+        for q, c in enumerate(isos):
+            act = mc.iso_voxels(cv, c)
+            dense = mc.march(ijk[act], cv[act], c, depth)
+            gk = sorted(tuple(sorted(map(int, t))) for t in keys[iso == q])
+            dk = sorted(tuple(sorted(map(int, t))) for t in dense["keys"])
+            assert gk == dk, q
+    finally:
+        ctx.unload_mlp(mid)
+
+
+@pytest.mark.parametrize("widths,depth", [([3, 64, 64, 64, 1], 6), ([3, 256, 256, 1], 5)])
+def test_dense_equals_sound_hierarchy_fp32(ctx, widths, depth):
+    """Affine arithmetic with the rounding margin keeps every crossed cell,
+    so its surface is the dense surface: the same triangles with the same
+    float32 vertices (both evaluate the corners with the same kernel)."""
+    import paper_2402_13861_amd as isx
+
+    mlp = he_normal_mlp(widths, seed=5)
+    isos = _isos(mlp, [0.25, 0.5, 0.75], seed=2)
+    mid = ctx.load_weights(mlp)
+    try:
+        ctx.set_isovalues(mid, isos)
+        ctx.set_option(isx.AA_MARGIN, 1)
+        h = ctx.extract(mid, isx.AA, isx.FP32, k=1.0, max_depth=depth)
+        ctx.set_option(isx.AA_MARGIN, 0)
+        d = ctx.extract_dense(mid, depth, isx.FP32)
+        assert d.n_tris == h.n_tris > 0
+        assert _tri_set(*d.triangles()) == _tri_set(*h.triangles())
+        # the hierarchy's leaves are a subset of the dense grid's cells
+        hid, _ = h.leaves()
+        did, dm = d.leaves()
+        assert np.array_equal(did, np.arange(8 ** depth, dtype=np.uint32))
+        assert np.all(dm == 7)
+        assert np.all(np.diff(hid.astype(np.int64)) > 0) and hid[-1] < 8 ** depth
+    finally:
+        ctx.set_option(isx.AA_MARGIN, 0)
+        ctx.unload_mlp(mid)
+
+
+def test_dense_errors(ctx):
+    import paper_2402_13861_amd as isx
+
+    mlp = he_normal_mlp([3, 32, 32, 1], seed=3)
+    mid = ctx.load_weights(mlp)
+    try:
+        with pytest.raises(isx.IsxError) as e:
+            ctx.extract_dense(mid, 4, isx.FP32)  # no iso-values yet
+        assert e.value.status == -1
+        ctx.set_isovalues(mid, [0.0])
+        with pytest.raises(isx.IsxError) as e:
+            ctx.extract_dense(mid, 10, isx.FP32)  # 2^30 cells
+        assert e.value.status == -4
+        with pytest.raises(isx.IsxError) as e:
+            ctx.extract_dense(mid, 11, isx.FP32)
+        assert e.value.status == -1
+        with pytest.raises(isx.IsxError) as e:
+            ctx.extract_dense(mid, 4, 7)
+        assert e.value.status == -1
+        m0 = ctx.extract_dense(mid, 0, isx.FP32)
+        assert m0.n_leaves == 1 and m0.n_corners == 8
+    finally:
+        ctx.unload_mlp(mid)
