@@ -535,6 +535,8 @@ def main(argv=None):
     ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16"])
     ap.add_argument("--no-surrogate", action="store_true", help="headline path without the learned surrogate")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 reference run")
+    ap.add_argument("--dense-from-level", type=int, default=0,
+                    help="range analysis down to this level only, dense subtrees below (0: the full refinement)")
     ap.add_argument("--no-dense", action="store_true",
                     help="skip the dense baseline (the INR at every grid corner and marching cubes on every cell)")
     ap.add_argument("--accept-leaves", type=int, default=1,
@@ -623,6 +625,7 @@ def main(argv=None):
     ctx.set_option(isx.SCRATCH_BYTES, 48 << 30)
     ctx.set_option(isx.VERBOSE, 1)
     ctx.set_option(isx.RECHECK_CASCADE, a.recheck_cascade)
+    ctx.set_option(isx.DENSE_FROM_LEVEL, a.dense_from_level)
     mid = ctx.load_weights(mlp)
     ctx.set_isovalues(mid, isos)
     sub_hi = 2.0 / (1 << a.subtree) if a.subtree else None
@@ -744,6 +747,23 @@ def main(argv=None):
                      ratio_to_step=round(1e3 * dense_s / ms_per_step, 3))
         dm.free()
         log(f"dense baseline: {dense}")
+    # dense subtrees below level depth - 2 (the same extraction otherwise;
+    # context, outside the timed region)
+    hybrid = None
+    if not a.no_dense and a.dense_from_level == 0 and depth >= 3:
+        hl = depth - 2
+        ctx.set_option(isx.DENSE_FROM_LEVEL, hl)
+        ctx.extract(mid, **kw).free()  # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hm = ctx.extract(mid, **kw)
+        hyb_s = time.perf_counter() - t0
+        ctx.set_option(isx.DENSE_FROM_LEVEL, 0)
+        hybrid = dict(dense_from_level=hl, ms=round(1e3 * hyb_s, 1),
+                      phases={k_: round(v_, 2) for k_, v_ in hm.times().items()}, leaves=hm.n_leaves,
+                      corners=hm.n_corners, tris=hm.n_tris, ratio_to_step=round(1e3 * hyb_s / ms_per_step, 3))
+        hm.free()
+        log(f"dense subtrees below level {hl}: {hybrid}")
 
     # per hidden-layer kernel kind: achieved rate at the algorithmic flop count
     # of its formulation (coefficient form: alg_flops_coefficient per cell;
@@ -862,6 +882,7 @@ def main(argv=None):
         "quality": quality,
         "bf16_only": bf16_only,
         "dense_gpu": dense,
+        "dense_subtrees_gpu": hybrid,
         "bf16_err_vs_oracle": err_oracle,
         "surrogate": sur_info,
         "examined_cells": examined,

@@ -586,13 +586,24 @@ typedef enum {
   ISX_BF16_READOFF = 13,   /* bf16 uncertainty propagation: 0 (default) = the output read-off on bf16 MFMA
                               with hi/lo splits of the row vectors and weights where the widths allow;
                               1 = the float32 MFMA read-off (the same vectors; for comparison) */
-  ISX_RECHECK_CASCADE = 14 /* isx_extract with ISX_BF16 and a re-check band: 0 (default) = band cells are
+  ISX_RECHECK_CASCADE = 14, /* isx_extract with ISX_BF16 and a re-check band: 0 (default) = band cells are
                               propagated again in float64 and that result decides; 1 = they are propagated
                               in float32 first, and only those whose float32 bound endpoint lies within
                               1/8 of the band (fp64_band / 8 + fp64_band_rel / 8 * spread) of a carried
                               iso-value go on to float64; the others keep the float32 decision (float32
                               endpoint errors are far below that eighth: <= 1e-5 of max(|o|, S) in the
                               parity tests); isx_mesh_level_rechecked_fp64 counts the float64 cells */
+  ISX_DENSE_FROM_LEVEL = 15 /* isx_extract on the octree: 0 (default) = range analysis down to max_depth
+                              (Alg. 1); L in [1, max_depth) = range analysis down to level L only, then
+                              every level-max_depth cell below an active level-L cell is a leaf for that
+                              cell's iso-values (its corners evaluated and marching cubes run on it, as in
+                              isx_extract_dense).  A cost choice beyond the paper: refining a busy level
+                              by range analysis can cost more than evaluating its subtrees densely.  The
+                              surface contains the one of the full refinement (same computation down to
+                              level L, and every leaf the refinement keeps lies below an active level-L
+                              cell); the mesh records levels 0..L; isx_extract fails with
+                              ISX_ECAPACITY above 2^28 leaves or 2^31 (leaf, iso) pairs, and with
+                              ISX_EUNSUPPORTED for the k-d tree */
 } isx_option;
 isx_status isx_set_option(isx_ctx* ctx, isx_option option, int64_t value);
 

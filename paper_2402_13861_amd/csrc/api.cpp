@@ -111,6 +111,7 @@ struct isx_ctx {
   Buf rc_flags, rc_fidx, rc_fmask;
   Buf rc_pm, rc_flags2, rc_idx2, rc2_c, rc2_h, rc2_out32, rc2_out64;  // two-stage re-check
   int recheck_cascade = 0;                                          // ISX_RECHECK_CASCADE
+  int dense_from = 0;                                               // ISX_DENSE_FROM_LEVEL
   int64_t n_rc64_last = 0;  // cells propagated in float64 by the re-checks since the level began
   Buf cx_flags, cx_idx, cx_c, cx_h, cx_out, cx_out64, cx_cnt;
   // surrogate training set and band calibration
@@ -578,6 +579,10 @@ isx_status isx_set_option(isx_ctx* ctx, isx_option option, int64_t value) {
     case ISX_RECHECK_CASCADE:
       if (value < 0 || value > 1) return fail(ctx, ISX_EINVAL, "ISX_RECHECK_CASCADE must be 0 or 1");
       ctx->recheck_cascade = (int)value;
+      return ISX_OK;
+    case ISX_DENSE_FROM_LEVEL:
+      if (value < 0 || value > 10) return fail(ctx, ISX_EINVAL, "ISX_DENSE_FROM_LEVEL must be in [0, 10]");
+      ctx->dense_from = (int)value;
       return ISX_OK;
     case ISX_BF16_READOFF:
       if (value < 0 || value > 1) return fail(ctx, ISX_EINVAL, "ISX_BF16_READOFF must be 0 or 1");
@@ -1221,6 +1226,9 @@ isx_status isx_extract(isx_ctx* ctx, int32_t mlp_id, const isx_params* p, isx_me
   if (m.n_iso < 1) return fail(ctx, ISX_EINVAL, "no iso-values set");
   if (p->tree != 0 && p->tree != 1) return fail(ctx, ISX_EINVAL, "tree must be 0 (octree) or 1 (k-d tree)");
   const bool kd = p->tree == 1;
+  // dense subtrees below level dense_from (0: the full refinement)
+  const int dense_from = ctx->dense_from > 0 && ctx->dense_from < p->max_depth ? ctx->dense_from : 0;
+  if (kd && dense_from) return fail(ctx, ISX_EUNSUPPORTED, "ISX_DENSE_FROM_LEVEL takes the octree");
   if (kd) {
     if (p->use_surrogate) return fail(ctx, ISX_EUNSUPPORTED, "the k-d tree does not take the surrogate");
     const double e0 = (double)m.hi[0] - m.lo[0];
@@ -1254,7 +1262,7 @@ isx_status isx_extract(isx_ctx* ctx, int32_t mlp_id, const isx_params* p, isx_me
 
   int64_t n_par = 0;
   int cur = 0;  // parents in act_*[cur]
-  const int last_level = kd ? 3 * p->max_depth : p->max_depth;
+  const int last_level = kd ? 3 * p->max_depth : (dense_from ? dense_from : p->max_depth);
   for (int L = 0; L <= last_level; ++L) {
     const int64_t n = L == 0 ? 1 : (kd ? 2 : 8) * n_par;
     if (n > cap)
@@ -1365,7 +1373,21 @@ isx_status isx_extract(isx_ctx* ctx, int32_t mlp_id, const isx_params* p, isx_me
   if (kd) XCHK(launch_kd_to_morton(n_par, p->max_depth, (uint32_t*)ctx->act_ids[cur].p, s));
   XCHK(hipEventRecord(ev[1], s));
 
-  {
+  if (dense_from) {
+    // every max_depth cell below an active level-dense_from cell is a leaf
+    const int sub = p->max_depth - dense_from;
+    const int64_t n_leaves = n_par << (3 * sub);
+    if (n_leaves > ((int64_t)1 << 28) || n_leaves * m.n_iso > ((int64_t)1 << 31))
+      return bail(fail(ctx, ISX_ECAPACITY, "the subtrees below level " + std::to_string(dense_from) + " hold " +
+                                               std::to_string(n_leaves) + " leaves, above 2^28 (or 2^31 pairs)"));
+    XCHK(ensure(ctx->ids, n_leaves * 4));
+    XCHK(ensure(ctx->mask, n_leaves * 4));
+    XCHK(launch_subtree_leaves(n_par, sub, (const uint32_t*)ctx->act_ids[cur].p, (const uint32_t*)ctx->act_mask[cur].p,
+                               (uint32_t*)ctx->ids.p, (uint32_t*)ctx->mask.p, s));
+    isx_status st = leaf_phase(ctx, m, p->max_depth, p->precision, n_leaves, (const uint32_t*)ctx->ids.p,
+                               (const uint32_t*)ctx->mask.p, mesh, ev[2], ev[3]);
+    if (st != ISX_OK) return bail(st);
+  } else {
     isx_status st = leaf_phase(ctx, m, p->max_depth, p->precision, n_par, (const uint32_t*)ctx->act_ids[cur].p,
                                (const uint32_t*)ctx->act_mask[cur].p, mesh, ev[2], ev[3]);
     if (st != ISX_OK) return bail(st);
@@ -1503,6 +1525,7 @@ isx_status isx_extract_batch(isx_ctx* ctx, int32_t n, const int32_t* mlp_ids, co
     w->autotune = ctx->autotune;
     w->readoff_f32 = ctx->readoff_f32;
     w->recheck_cascade = ctx->recheck_cascade;
+    w->dense_from = ctx->dense_from;
     w->up_form = ctx->up_form;
     w->lin_prec = ctx->lin_prec;
     w->aa_margin = ctx->aa_margin;

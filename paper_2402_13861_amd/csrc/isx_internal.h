@@ -343,6 +343,10 @@ hipError_t launch_children_kd(const Model& m, int depth, int64_t n_par, const ui
 hipError_t launch_kd_to_morton(int64_t n, int levels, uint32_t* ids, hipStream_t s);
 // ids[i] = i, masks[i] = full for i < n (every cell of a level)
 hipError_t launch_dense_leaves(int64_t n, uint32_t full, uint32_t* ids, uint32_t* masks, hipStream_t s);
+// the 8^levels descendants of each of n_par cells, levels further down, in
+// Morton order (parents in order): ids (par << 3 levels) | j, the parent's mask
+hipError_t launch_subtree_leaves(int64_t n_par, int levels, const uint32_t* par_ids, const uint32_t* par_masks,
+                                 uint32_t* ids, uint32_t* masks, hipStream_t s);
 hipError_t launch_classify(int64_t n, const float* out, float k, const IsoList& iso, const uint32_t* pmask,
                            uint32_t* mask, hipStream_t s);
 // Stable compaction of the entries with mask != 0: writes (ids ? ids[i] : i)

@@ -107,6 +107,25 @@ hipError_t launch_dense_leaves(int64_t n, uint32_t full, uint32_t* ids, uint32_t
   return hipGetLastError();
 }
 
+__global__ void subtree_leaves_kernel(int64_t n, int shift, const uint32_t* __restrict__ par_ids,
+                                      const uint32_t* __restrict__ par_masks, uint32_t* __restrict__ ids,
+                                      uint32_t* __restrict__ masks) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t p = i >> shift;
+  ids[i] = (par_ids[p] << shift) | (uint32_t)(i & (((int64_t)1 << shift) - 1));
+  masks[i] = par_masks[p];
+}
+
+hipError_t launch_subtree_leaves(int64_t n_par, int levels, const uint32_t* par_ids, const uint32_t* par_masks,
+                                 uint32_t* ids, uint32_t* masks, hipStream_t s) {
+  const int64_t n = n_par << (3 * levels);
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(subtree_leaves_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, 3 * levels,
+                     par_ids, par_masks, ids, masks);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------ k-d tree
 // Alg. 1's own tree: every node is split in two along its widest dimension,
 // ties broken x, then y, then z.  On a cube domain all nodes of a depth have

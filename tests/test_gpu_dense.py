@@ -124,3 +124,105 @@ def test_dense_errors(ctx):
         assert m0.n_leaves == 1 and m0.n_corners == 8
     finally:
         ctx.unload_mlp(mid)
+
+
+@pytest.mark.parametrize("level", [3, 4])
+def test_dense_from_level_contains_full_refinement(ctx, level):
+    """Range analysis down to `level`, dense subtrees below: the levels down
+    to `level` are those of the full refinement, the leaves are every cell
+    below its active level-`level` cells, and the surface contains the full
+    refinement's surface, vertex for vertex."""
+    import paper_2402_13861_amd as isx
+
+    mlp = he_normal_mlp([3, 64, 64, 64, 1], seed=7)
+    depth = 6
+    isos = _isos(mlp, [0.3, 0.6], seed=4)
+    mid = ctx.load_weights(mlp)
+    try:
+        ctx.set_isovalues(mid, isos)
+        full = ctx.extract(mid, isx.UP, isx.FP32, k=3.0, max_depth=depth)
+        ctx.set_option(isx.DENSE_FROM_LEVEL, level)
+        hyb = ctx.extract(mid, isx.UP, isx.FP32, k=3.0, max_depth=depth)
+        ctx.set_option(isx.DENSE_FROM_LEVEL, 0)
+        fl, hl = full.levels(), hyb.levels()
+        assert len(hl) == level + 1
+        assert [(x["cells"], x["active"]) for x in hl] == [(x["cells"], x["active"]) for x in fl[:level + 1]]
+        assert hyb.n_leaves == hl[level]["active"] * 8 ** (depth - level)
+        ids, masks = hyb.leaves()
+        assert np.all(np.diff(ids.astype(np.int64)) > 0)
+        fids, fmasks = full.leaves()
+        pos = np.minimum(np.searchsorted(ids, fids), ids.size - 1)
+        assert np.array_equal(ids[pos], fids)
+        assert np.all((fmasks & ~masks[pos]) == 0)  # a leaf's isos are its ancestor's
+        ht, ft = _tri_set(*hyb.triangles()), _tri_set(*full.triangles())
+        assert ft.items() <= ht.items()
+        assert hyb.n_tris >= full.n_tris > 0
+    finally:
+        ctx.set_option(isx.DENSE_FROM_LEVEL, 0)
+        ctx.unload_mlp(mid)
+
+
+def test_dense_from_level_sound_aa_is_dense(ctx):
+    """With sound affine arithmetic above the dense level, the surface is the
+    dense baseline's."""
+    import paper_2402_13861_amd as isx
+
+    mlp = he_normal_mlp([3, 64, 64, 64, 1], seed=5)
+    depth = 6
+    isos = _isos(mlp, [0.25, 0.5, 0.75], seed=2)
+    mid = ctx.load_weights(mlp)
+    try:
+        ctx.set_isovalues(mid, isos)
+        ctx.set_option(isx.AA_MARGIN, 1)
+        ctx.set_option(isx.DENSE_FROM_LEVEL, 3)
+        h = ctx.extract(mid, isx.AA, isx.FP32, k=1.0, max_depth=depth)
+        ctx.set_option(isx.DENSE_FROM_LEVEL, 0)
+        ctx.set_option(isx.AA_MARGIN, 0)
+        d = ctx.extract_dense(mid, depth, isx.FP32)
+        assert _tri_set(*h.triangles()) == _tri_set(*d.triangles())
+    finally:
+        ctx.set_option(isx.DENSE_FROM_LEVEL, 0)
+        ctx.set_option(isx.AA_MARGIN, 0)
+        ctx.unload_mlp(mid)
+
+
+def test_dense_from_level_edges(ctx):
+    import paper_2402_13861_amd as isx
+
+    mlp = he_normal_mlp([3, 32, 32, 1], seed=3)
+    mid = ctx.load_weights(mlp)
+    try:
+        ctx.set_isovalues(mid, [0.0])
+        with pytest.raises(isx.IsxError) as e:
+            ctx.set_option(isx.DENSE_FROM_LEVEL, 11)
+        assert e.value.status == -1
+        full = ctx.extract(mid, isx.UP, isx.FP32, k=3.0, max_depth=4)
+        ctx.set_option(isx.DENSE_FROM_LEVEL, 4)  # not above max_depth: the full refinement
+        same = ctx.extract(mid, isx.UP, isx.FP32, k=3.0, max_depth=4)
+        assert same.n_levels == full.n_levels and same.n_leaves == full.n_leaves
+        assert _tri_set(*same.triangles()) == _tri_set(*full.triangles())
+        ctx.set_option(isx.DENSE_FROM_LEVEL, 2)
+        with pytest.raises(isx.IsxError) as e:
+            ctx.extract(mid, isx.UP, isx.FP32, k=3.0, max_depth=4, kd_tree=True)
+        assert e.value.status == -7
+    finally:
+        ctx.set_option(isx.DENSE_FROM_LEVEL, 0)
+        ctx.unload_mlp(mid)
+
+
+def test_every_option_takes_its_default(ctx):
+    """isx_set_option accepts every documented option at its default value."""
+    import paper_2402_13861_amd as isx
+
+    defaults = [(isx.KEEP_LEVELS, 0), (isx.HIDDEN_KERNEL, 0), (isx.PROFILE, 0), (isx.SCRATCH_BYTES, 16 << 30),
+                (isx.VERBOSE, 0), (isx.BF16_VARIANT, 0), (isx.UP_FORM, 0), (isx.LIN_PRECISION, 1),
+                (isx.AA_MARGIN, 0), (isx.BATCH_WORKERS, 4), (isx.CANCEL_CHECK, 1), (isx.AUTOTUNE, 0),
+                (isx.BF16_READOFF, 0), (isx.RECHECK_CASCADE, 0), (isx.DENSE_FROM_LEVEL, 0)]
+    assert sorted(o for o, _ in defaults) == list(range(1, 16))
+    for opt, val in defaults:
+        ctx.set_option(opt, val)
+    ctx.set_option(isx.RECHECK_CASCADE, 1)
+    ctx.set_option(isx.RECHECK_CASCADE, 0)
+    with pytest.raises(isx.IsxError) as e:
+        ctx.set_option(99, 0)
+    assert e.value.status == -1
