@@ -374,6 +374,7 @@ def batch_bench(a, log):
     mlps = batch_mlps(n)
     ctx = isx.Context(0)
     ctx.set_option(isx.SCRATCH_BYTES, 48 << 30)
+    ctx.set_option(isx.DENSE_FROM_LEVEL, a.dense_from_level)
     ids = []
     for mlp, t in zip(mlps, table[:n]):
         mid = ctx.load_weights(mlp)
@@ -419,7 +420,7 @@ def batch_bench(a, log):
         log(f"batch: {workers} workers {dt * 1e3:.1f} ms, same meshes {same}")
     shapes = [w for w, _ in batch_shapes(n)]
     print(json.dumps({"batch": res, "sequential_ms": round(t_seq * 1e3, 2), "inrs": n, "depth": depth,
-                      "autotune": bool(a.autotune),
+                      "autotune": bool(a.autotune), "dense_from_level": a.dense_from_level,
                       "precision": a.precision, "propagated_cells": propagated,
                       "per_inr": [dict(widths=f"{w[1]}x{len(w) - 2}", **x) for w, x in zip(shapes, singles)]}),
           flush=True)
