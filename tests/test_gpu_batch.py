@@ -8,7 +8,10 @@ import numpy as np
 import pytest
 import torch
 
+from _parity import close_sets, unexcused_level_diffs
 from oracle.mlp import mlp_forward
+from oracle.octree import extract_active
+from oracle.propagate import UP
 from workloads import he_normal_mlp, uniform_points
 
 pytestmark = pytest.mark.gpu
@@ -77,6 +80,40 @@ def test_extract_batch_equals_single_extractions(ctx, prec_name, widths):
         for m in singles:
             m.free()
     finally:
+        ctx.set_option(isx.BATCH_WORKERS, 4)
+        for mid in ids:
+            ctx.unload_mlp(mid)
+
+
+def test_extract_batch_matches_oracle(ctx):
+    """Every INR of a batch (uneven widths and depths, own iso-values, four
+    worker streams) against the oracle's octree search: per-level active
+    sets equal except cells that are, or descend from, cells whose oracle
+    bound endpoint lies within 1e-4 S of an iso-value."""
+    import paper_2402_13861_amd as isx
+
+    inrs = _uneven_inrs(6, seed=11, widths=(32, 64, 96), depths=(2, 3))
+    depth = 4
+    ids = []
+    try:
+        for mlp, isos in inrs:
+            mid = ctx.load_weights(mlp)
+            ctx.set_isovalues(mid, [float(np.float32(c)) for c in isos])
+            ids.append(mid)
+        ctx.set_option(isx.KEEP_LEVELS, 1)
+        ctx.set_option(isx.BATCH_WORKERS, 4)
+        meshes = ctx.extract_batch(ids, method=isx.UP, precision=isx.FP32, k=3.0, max_depth=depth)
+        ctx.set_option(isx.KEEP_LEVELS, 0)
+        for i, ((mlp, isos), m) in enumerate(zip(inrs, meshes)):
+            isos32 = [float(np.float32(c)) for c in isos]
+            S = float(mlp_forward(mlp, uniform_points(10_000, seed=1)).std())
+            gl = [m.level_cells(L) for L in range(m.n_levels)]
+            ol = extract_active(mlp, UP, isos32, depth, k=3.0)
+            bad = unexcused_level_diffs(gl, ol, close_sets(ol, UP, 3.0, isos32, S))
+            assert not bad, (i, bad)
+            m.free()
+    finally:
+        ctx.set_option(isx.KEEP_LEVELS, 0)
         ctx.set_option(isx.BATCH_WORKERS, 4)
         for mid in ids:
             ctx.unload_mlp(mid)
