@@ -110,9 +110,10 @@ isx_status isx_load_mlp(isx_ctx* ctx, int32_t n_linear, const int32_t* widths,
 /* Hidden activation of a loaded MLP (default ISX_RELU).  The rules follow
  * the App. D table (UP: Gaussian least-squares lines; AA: the minimax line for
  * ReLU and the convex ELU, a chord with exact error extremes for sine).
- * Sine and ELU nets run in float32 and float64 (vector-ALU and FP32/FP64 MFMA
- * kernels); ISX_BF16 propagation, the AA rounding margin, isx_linearize and
- * the surrogate's linearisation base need ReLU (ISX_EUNSUPPORTED otherwise).
+ * Sine and ELU nets run in float32, float64 and bfloat16 (the rules
+ * themselves in float64 inside the float32 and bfloat16 kernels); the AA
+ * rounding margin, isx_linearize and the surrogate's linearisation base need
+ * ReLU (ISX_EUNSUPPORTED otherwise).
  * Errors: ISX_EINVAL. */
 isx_status isx_set_activation(isx_ctx* ctx, int32_t mlp_id, isx_activation act);
 
@@ -575,9 +576,10 @@ typedef enum {
                               neuron whose variance sum v = sum_i T_ji W_ji (signed, over bfloat16-rounded
                               covariances) keeps at most 2^-9 of the magnitude a = sum_i |T_ji W_ji| of its
                               terms (Eq. 7 needs the variance; such a sum can lose every digit) while its
-                              pre-activation y has |y| < 6 sqrt(max(v, 0) + 2^-7 a) (the ReLU rule of Eq. 9
-                              depends on sigma there) is propagated again in float64, and its float64
-                              (mu, sigma) is returned; 0 = off */
+                              pre-activation y lies where the rule depends on sigma (ReLU, Eq. 9:
+                              |y| < 6 sqrt(max(v, 0) + 2^-7 a); ELU: y below that bound; sine: always)
+                              is propagated again in float64, and its float64 (mu, sigma) is returned;
+                              0 = off */
   ISX_AUTOTUNE = 12,       /* bf16 coefficient-form propagation: 1 = pick the hidden-layer tile shape of
                               each MLP by timing the shapes (1, 3, 4 and the default) on 4096 sample
                               cells at its first such propagation (the shapes give identical results);

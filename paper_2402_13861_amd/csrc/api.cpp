@@ -374,7 +374,6 @@ isx_status run_propagate(isx_ctx* ctx, const Model& m, isx_method method, isx_pr
     return ISX_OK;
   }
   if (prec == ISX_BF16) {
-    if (m.act != ISX_RELU) return fail(ctx, ISX_EUNSUPPORTED, "bf16 propagation needs a ReLU net");
     if (!bf16_supported(m))
       return fail(ctx, ISX_EUNSUPPORTED, "bf16 propagation needs every hidden layer's input width <= 256");
     // the covariance form (UP) keeps each cell on chip: no coefficient blocks

@@ -47,7 +47,7 @@ __global__ void layer1_bf16_kernel(int64_t C, int n, const float* __restrict__ c
                                    const float* __restrict__ halves, const float* __restrict__ W1,
                                    const float* __restrict__ b1, __bf16* __restrict__ Fout, float* __restrict__ Y,
                                    float* __restrict__ A, float* __restrict__ B, float* __restrict__ G,
-                                   float* __restrict__ S) {
+                                   float* __restrict__ S, int act) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= C * n) return;
   const int64_t cell = idx / n;
@@ -63,7 +63,7 @@ __global__ void layer1_bf16_kernel(int64_t C, int n, const float* __restrict__ c
     stat += bstat<METHOD>(f[i]);
   }
   float a, b, g;
-  apply_rule<float, METHOD>(ISX_RELU, y, stat, a, b, g);
+  apply_rule<float, METHOD>(act, y, stat, a, b, g);
   Y[idx] = y;
   A[idx] = a;
   B[idx] = b;
@@ -96,7 +96,7 @@ __global__ __launch_bounds__(64 * NW) void hidden_mfma_bf16_kernel(
     const float* __restrict__ bias, const __bf16* __restrict__ WtPrev, const float* __restrict__ Gprev2,
     const __bf16* __restrict__ Fin, const float* __restrict__ Yin, const float* __restrict__ Ain,
     const float* __restrict__ Bin, const float* __restrict__ Gin, __bf16* __restrict__ Fout, float* __restrict__ Y,
-    float* __restrict__ A, float* __restrict__ B, float* __restrict__ G, float* __restrict__ S) {
+    float* __restrict__ A, float* __restrict__ B, float* __restrict__ G, float* __restrict__ S, int act) {
   constexpr int THREADS = 64 * NW;
   constexpr int BN = 32 * NB;                  // columns per tile
   constexpr int BM = 32 * RB * NW;             // output neurons per workgroup
@@ -313,7 +313,7 @@ __global__ __launch_bounds__(64 * NW) void hidden_mfma_bf16_kernel(
   for (int m = t; m < BM; m += THREADS) {
     const float tot = s_row[m] + s_gen[m];
     float a, b, gg;
-    apply_rule<float, METHOD>(ISX_RELU, s_y[m], tot, a, b, gg);
+    apply_rule<float, METHOD>(act, s_y[m], tot, a, b, gg);
     const int64_t o = cell * n_out + m0 + m;
     Y[o] = s_y[m];
     A[o] = a;
@@ -333,7 +333,7 @@ template <int METHOD, int NW, int RB, int NB, int KMAXT>
 static hipError_t launch_bf16_k(int64_t C, int n_in, int n_out, int64_t s_in, int g_in, const float* W,
                                 const float* bias, const __bf16* WtPrev, const float* Gprev2, const __bf16* Fin,
                                 const float* Yin, const float* Ain, const float* Bin, const float* Gin, __bf16* Fout,
-                                float* Y, float* A, float* B, float* G, float* S, hipStream_t s) {
+                                float* Y, float* A, float* B, float* G, float* S, int act, hipStream_t s) {
   constexpr int BM = 32 * RB * NW;
   constexpr int BN = 32 * NB;
   const int rb_count = n_out / BM;
@@ -345,7 +345,7 @@ static hipError_t launch_bf16_k(int64_t C, int n_in, int n_out, int64_t s_in, in
   }
   hipLaunchKernelGGL((hidden_mfma_bf16_kernel<METHOD, NW, RB, NB, KMAXT>), dim3((unsigned)blocks), dim3(64 * NW), lds, s, C,
                      n_in, n_out, s_in, g_in, rb_count, W, bias, WtPrev, Gprev2, Fin, Yin, Ain, Bin, Gin, Fout, Y, A,
-                     B, G, S);
+                     B, G, S, act);
   return hipGetLastError();
 }
 
@@ -356,8 +356,8 @@ template <int METHOD, int NW, int RB, int NB>
 static hipError_t launch_bf16_v(int64_t C, int n_in, int n_out, int64_t s_in, int g_in, const float* W,
                                 const float* bias, const __bf16* WtPrev, const float* Gprev2, const __bf16* Fin,
                                 const float* Yin, const float* Ain, const float* Bin, const float* Gin, __bf16* Fout,
-                                float* Y, float* A, float* B, float* G, float* S, hipStream_t s) {
-#define ISX_BF16_KARGS C, n_in, n_out, s_in, g_in, W, bias, WtPrev, Gprev2, Fin, Yin, Ain, Bin, Gin, Fout, Y, A, B, G, S, s
+                                float* Y, float* A, float* B, float* G, float* S, int act, hipStream_t s) {
+#define ISX_BF16_KARGS C, n_in, n_out, s_in, g_in, W, bias, WtPrev, Gprev2, Fin, Yin, Ain, Bin, Gin, Fout, Y, A, B, G, S, act, s
   if (n_in <= 64) return launch_bf16_k<METHOD, NW, RB, NB, 64>(ISX_BF16_KARGS);
   if (n_in <= 128) return launch_bf16_k<METHOD, NW, RB, NB, 128>(ISX_BF16_KARGS);
   if (n_in <= 256) return launch_bf16_k<METHOD, NW, RB, NB, 256>(ISX_BF16_KARGS);
@@ -372,8 +372,8 @@ template <int METHOD>
 static hipError_t launch_bf16_m(int variant, int64_t C, int n_in, int n_out, int64_t s_in, int g_in, const float* W,
                                 const float* bias, const __bf16* WtPrev, const float* Gprev2, const __bf16* Fin,
                                 const float* Yin, const float* Ain, const float* Bin, const float* Gin, __bf16* Fout,
-                                float* Y, float* A, float* B, float* G, float* S, hipStream_t s) {
-#define ISX_BF16_ARGS C, n_in, n_out, s_in, g_in, W, bias, WtPrev, Gprev2, Fin, Yin, Ain, Bin, Gin, Fout, Y, A, B, G, S, s
+                                float* Y, float* A, float* B, float* G, float* S, int act, hipStream_t s) {
+#define ISX_BF16_ARGS C, n_in, n_out, s_in, g_in, W, bias, WtPrev, Gprev2, Fin, Yin, Ain, Bin, Gin, Fout, Y, A, B, G, S, act, s
   if (variant == 1 && n_out % 256 == 0) return launch_bf16_v<METHOD, 4, 2, 2>(ISX_BF16_ARGS);
   if (variant == 3 && n_out % 128 == 0) return launch_bf16_v<METHOD, 4, 1, 2>(ISX_BF16_ARGS);
   if (variant == 4 && n_out % 64 == 0) return launch_bf16_v<METHOD, 2, 1, 2>(ISX_BF16_ARGS);
@@ -456,11 +456,11 @@ hipError_t propagate_bf16(const PropArgs& a, PropWork<float>& w, uint16_t* Fbf_r
     if (a.method == ISX_UP)
       hipLaunchKernelGGL(layer1_bf16_kernel<ISX_UP>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, a.stream,
                          C, n1, a.centres, a.halves, m.L[0].W, m.L[0].b, Lh >= 2 ? Fbf[cur] : nullptr, Y[1], A[1], B[1],
-                         G[1], (float*)nullptr);
+                         G[1], (float*)nullptr, m.act);
     else
       hipLaunchKernelGGL(layer1_bf16_kernel<ISX_AA>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, a.stream,
                          C, n1, a.centres, a.halves, m.L[0].W, m.L[0].b, Lh >= 2 ? Fbf[cur] : nullptr, Y[1], A[1], B[1],
-                         G[1], S[1]);
+                         G[1], S[1], m.act);
     if (marg) {
       hipError_t e = launch_aa_margin_hidden<float>(C, 3, n1, m.L[0].Wt, m.L[0].b, nullptr, nullptr, nullptr, nullptr,
                                                     a.centres, a.halves, Y[1], S[1], A[1], B[1], G[1], R[1],
@@ -490,10 +490,10 @@ hipError_t propagate_bf16(const PropArgs& a, PropWork<float>& w, uint16_t* Fbf_r
     hipError_t e = a.method == ISX_UP
                        ? launch_bf16_m<ISX_UP>(a.bf16_variant, C, n_in, n_out, s_in, g_in, L.W, L.b, WtPrev, Gp2,
                                                Fbf[cur], Y[h - 1], A[h - 1], B[h - 1], G[h - 1], Fout, Y[h], A[h], B[h],
-                                               G[h], (float*)nullptr, a.stream)
+                                               G[h], (float*)nullptr, m.act, a.stream)
                        : launch_bf16_m<ISX_AA>(a.bf16_variant, C, n_in, n_out, s_in, g_in, L.W, L.b, WtPrev, Gp2,
                                                Fbf[cur], Y[h - 1], A[h - 1], B[h - 1], G[h - 1], Fout, Y[h], A[h], B[h],
-                                               G[h], S[h], a.stream);
+                                               G[h], S[h], m.act, a.stream);
     if (e != hipSuccess) return e;
     if (prof) a.prof->end(rec, a.stream);
     D += n_in;

@@ -36,7 +36,7 @@
 //      alpha . y_{h-1} + beta, from a float32 copy of W in the accumulators'
 //      order (one 1 KiB run per wave and register quad).
 //   4. Per neuron, the column groups' partial sums, y = W z + b, and the
-//      ReLU rule, which gives (alpha, beta, gamma).
+//      activation's rule (ReLU, sine or ELU), which gives (alpha, beta, gamma).
 //   5. C_h = T W_h^T on the wave's tile (A = rows of T from LDS, B = weight
 //      fragments, whose lane layout is the B layout of the transposed
 //      product).  The last hidden layer stops after step 4 (and keeps no T).
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kCovThreads) void up_cov_bf16_kernel(int64_t C, int
                                                                   float* __restrict__ vec,
                                                                   const float* __restrict__ centres,
                                                                   const float* __restrict__ halves,
-                                                                  uint32_t* __restrict__ cancel) {
+                                                                  uint32_t* __restrict__ cancel, int act) {
   using S = CovShape<N>;
   constexpr int STR = S::STR, KS = S::KS, NB = S::NB;
   extern __shared__ float4 cov_smem4[];
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(kCovThreads) void up_cov_bf16_kernel(int64_t C, int
       const float y = b1[j] + w0 * centres[cell * 3 + 0] + w1 * centres[cell * 3 + 1] + w2 * centres[cell * 3 + 2];
       const float f0 = w0 * hx, f1 = w1 * hy, f2 = w2 * hz;
       float a, b, g;
-      up_rule<float>(ISX_RELU, y, f0 * f0 + f1 * f1 + f2 * f2, a, b, g);
+      apply_rule<float, ISX_UP>(act, y, f0 * f0 + f1 * f1 + f2 * f2, a, b, g);
       s_alpha[j] = a;
       s_z[j] = a * y + b;
       s_gamma[j] = g;
@@ -245,7 +245,7 @@ __global__ __launch_bounds__(kCovThreads) void up_cov_bf16_kernel(int64_t C, int
       // 3./4. per neuron j (a lane quad), one pass over the row-pass copy of
       //    its weight row, both row groups of the wave together (G and z
       //    are read once for both): y_j = W[j] z + b_j, P_j = W[j] G, the
-      //    variance |P_j|^2 + sum_k W[j][k]^2 gamma_1k^2 and the ReLU rule,
+      //    variance |P_j|^2 + sum_k W[j][k]^2 gamma_1k^2 and the rule,
       //    and row j of T' = W diag(gamma_1^2) into LDS
       {
         float r5[GPW][5];
@@ -310,7 +310,7 @@ __global__ __launch_bounds__(kCovThreads) void up_cov_bf16_kernel(int64_t C, int
           float a, b, g;
           const float y = sel[0] + ((gfloat*)Lw.b)[j];
           const float v = sel[1] * sel[1] + sel[2] * sel[2] + sel[3] * sel[3] + sel[4];
-          up_rule<float>(ISX_RELU, y, v, a, b, g);
+          apply_rule<float, ISX_UP>(act, y, v, a, b, g);
           s_var[j] = v;
           s_alpha[j] = a;
           s_zout[j] = a * y + b;
@@ -399,7 +399,7 @@ __global__ __launch_bounds__(kCovThreads) void up_cov_bf16_kernel(int64_t C, int
       }
       __syncthreads();
       // 4. per neuron: the column groups' sums in a fixed order, the centre
-      //    y = W z + b with z = alpha . y_{h-1} + beta, and the ReLU rule
+      //    y = W z + b with z = alpha . y_{h-1} + beta, and the rule
       {
         const float4* s_part = s_G;
         for (int j = t; j < N; j += kCovThreads) {
@@ -414,12 +414,15 @@ __global__ __launch_bounds__(kCovThreads) void up_cov_bf16_kernel(int64_t C, int
           float a, b, g;
           const float y = yc + ((gfloat*)Lw.b)[j];
           // a cancelled sum matters only where the rule depends on sigma:
-          // beyond 6 sigma (taken at its largest with the terms' rounding,
-          // sqrt(v + 2^-7 sum |terms|)) alpha is 0 or 1 and beta, gamma vanish
-          // to float32 accuracy whatever sigma is
-          if (av > 0.f && !(v > kCancelRatio * av) && fabsf(y) < 6.f * sqrtf(fmaxf(v, 0.f) + 0x1p-7f * av))
-            s_cancel = 1u;
-          up_rule<float>(ISX_RELU, y, v, a, b, g);
+          // for ReLU, beyond 6 sigma (taken at its largest with the terms'
+          // rounding, sqrt(v + 2^-7 sum |terms|)) alpha is 0 or 1 and beta,
+          // gamma vanish to float32 accuracy whatever sigma is; for ELU that
+          // holds 6 sigma above 0 only; the sine rule always depends on sigma
+          if (av > 0.f && !(v > kCancelRatio * av)) {
+            const float s6 = 6.f * sqrtf(fmaxf(v, 0.f) + 0x1p-7f * av);
+            if (act == ISX_SINE || (act == ISX_ELU ? y < s6 : fabsf(y) < s6)) s_cancel = 1u;
+          }
+          apply_rule<float, ISX_UP>(act, y, v, a, b, g);
           s_var[j] = v;
           s_alpha[j] = a;
           s_zout[j] = a * y + b;
@@ -533,7 +536,7 @@ static hipError_t launch_cov_n(const Model& m, int64_t C, const float* centres, 
   // one workgroup per cell: a launch's work-items must stay below 2^32
   if (C > (int64_t(1) << 22)) return hipErrorInvalidValue;
   hipLaunchKernelGGL((up_cov_bf16_kernel<N>), dim3((unsigned)C), dim3(kCovThreads), CovShape<N>::LDS, s, C,
-                     m.n_linear, m.dev_layers, vec, centres, halves, cancel);
+                     m.n_linear, m.dev_layers, vec, centres, halves, cancel, m.act);
   return hipGetLastError();
 }
 
