@@ -111,7 +111,7 @@ def host_cpu():
     return os.cpu_count() or 1, model
 
 
-def cpu_baseline(mlp, depth: int, budget_s: float, seed: int = 0):
+def cpu_baseline(mlp, depth: int, budget_s: float, seed: int = 0, act: str = "relu"):
     """The float64 oracle on a bounded sample: random cells drawn uniformly
     over octree levels 3..depth (the oracle's cost per cell does not depend on
     the level), timed on the host's BLAS threads.  Returns the rate and the
@@ -131,7 +131,7 @@ def cpu_baseline(mlp, depth: int, budget_s: float, seed: int = 0):
     while t_used < budget_s:
         c, h, L = random_boxes(batch, levels, seed=int(rng.integers(1 << 30)))
         t0 = time.perf_counter()
-        mu, sg = propagate(mlp, c, h, UP)
+        mu, sg = propagate(mlp, c, h, UP, act=act)
         t_used += time.perf_counter() - t0
         done += batch
         cs.append(c)
@@ -146,7 +146,7 @@ def cpu_baseline(mlp, depth: int, budget_s: float, seed: int = 0):
     return rate, done, t_used, threads, sample
 
 
-def error_vs_oracle(ctx, mid, mlp, sample, S, k, n_aa, log):
+def error_vs_oracle(ctx, mid, mlp, sample, S, k, n_aa, log, act="relu"):
     """Error of the GPU's BF16 bounds (UP covariance form, UP coefficient form,
     AA) and FP32 UP bounds against the float64 oracle, per octree level: max
     and 99.9th percentile of |endpoint_gpu - endpoint_oracle| / S over both
@@ -187,7 +187,7 @@ def error_vs_oracle(ctx, mid, mlp, sample, S, k, n_aa, log):
     out["up_bf16_coef"] = stats(gpu(isx.UP, isx.BF16, c, h, 1), mu, sg, k, lv)
     out["up_fp32"] = stats(gpu(isx.UP, isx.FP32, c, h), mu, sg, k, lv)
     na = min(n_aa, c.shape[0])
-    x0, r = propagate(mlp, c[:na], h[:na], AA)
+    x0, r = propagate(mlp, c[:na], h[:na], AA, act=act)
     out["aa_bf16"] = stats(gpu(isx.AA, isx.BF16, c[:na], h[:na]), x0, r, 1.0, lv[:na])
     out["aa_fp32"] = stats(gpu(isx.AA, isx.FP32, c[:na], h[:na]), x0, r, 1.0, lv[:na])
     for key in ("up_bf16_cov", "up_bf16_coef", "up_fp32", "aa_bf16", "aa_fp32"):
@@ -628,6 +628,12 @@ def main(argv=None):
     ctx.set_option(isx.RECHECK_CASCADE, a.recheck_cascade)
     ctx.set_option(isx.DENSE_FROM_LEVEL, a.dense_from_level)
     mid = ctx.load_weights(mlp)
+    act = w.get("act", "relu")
+    if act != "relu":
+        ctx.set_activation(mid, {"sine": isx.SINE, "elu": isx.ELU}[act])
+        if use_sur and a.sur_base:
+            raise SystemExit(f"bench: the surrogate's linearisation base needs a ReLU net ({a.workload} is {act}); "
+                             "pass --no-surrogate or --sur-base 0")
     ctx.set_isovalues(mid, isos)
     sub_hi = 2.0 / (1 << a.subtree) if a.subtree else None
     if a.subtree:
@@ -830,7 +836,7 @@ def main(argv=None):
     cpu = None
     err_oracle = None
     if not a.no_cpu_baseline:
-        rate, done, t_used, threads, sample = cpu_baseline(mlp, depth, a.cpu_baseline_seconds)
+        rate, done, t_used, threads, sample = cpu_baseline(mlp, depth, a.cpu_baseline_seconds, act=act)
         total_plain = plain["propagated"] if plain is not None else examined
         est_s = total_plain / rate
         n_cores, cpu_model = host_cpu()
@@ -846,7 +852,7 @@ def main(argv=None):
                        f"cost per cell does not depend on the level); plain-method extraction time extrapolated "
                        f"from propagation of its {int(total_plain)} cells alone ({est_s:.0f} s)"),
         }
-        err_oracle = error_vs_oracle(ctx, mid, mlp, sample, S, w["k"], 2000, log)
+        err_oracle = error_vs_oracle(ctx, mid, mlp, sample, S, w["k"], 2000, log, act=act)
         err_oracle["band_S"] = w.get("band_rel", 0.0)
         err_oracle["levels_where_band_exceeds_bf16_max"] = [
             L for L, d in err_oracle["up_bf16_cov"]["levels"].items() if d["max"] < w.get("band_rel", 0.0)]
@@ -867,7 +873,8 @@ def main(argv=None):
         "dtype": a.precision,
         "data": "synthetic",
         "config": {
-            "workload": f"{a.workload}: ReLU MLP {'x'.join(map(str, mlp.widths))}, octree depth {depth} "
+            "workload": f"{a.workload}: {dict(relu='ReLU', sine='sine', elu='ELU')[act]} MLP "
+                        f"{'x'.join(map(str, mlp.widths))}, octree depth {depth} "
                         f"({1 << depth}^3 effective cells), {len(isos)} iso-values, UP t={w['k']}, "
                         f"fp64 band {w.get('band_rel', 0)} S"
                         + (f" + {a.band_rel:g} of the cell's spread" if a.precision == "bf16" and a.band_rel else "")

@@ -922,8 +922,7 @@ isx_status isx_classify_compact_noalloc(isx_ctx* ctx, int32_t mlp_id, float k, i
 
 // float32 point evaluation: FP32 MFMA, or the SIMT kernel when forced
 static hipError_t eval_f32(isx_ctx* ctx, const Model& m, int64_t n, const float* pts, float* vals, hipStream_t s) {
-  // (the MFMA forward pass is written for ReLU; other activations take the vector-ALU kernel)
-  if (ctx->kernel_choice == 1 || m.act != ISX_RELU) return eval_points_f32(m, n, pts, vals, s);
+  if (ctx->kernel_choice == 1) return eval_points_f32(m, n, pts, vals, s);
   double flops = 6.0 * m.widths[1] + 2.0 * m.widths[m.n_linear - 1];
   for (int h = 2; h < m.n_linear; ++h) flops += 2.0 * m.widths[h] * m.widths[h - 1];
   Profiler::Rec rec{};

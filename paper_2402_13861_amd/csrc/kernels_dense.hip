@@ -24,6 +24,7 @@
 // registers are four consecutive neurons of one column, written back to LDS
 // as one 16-byte store after every wave has finished reading the layer input.
 #include "isx_internal.h"
+#include "rules.h"
 
 #include <algorithm>
 
@@ -38,6 +39,7 @@ enum { DENSE_EVAL = 0, DENSE_LIN = 1 };
 
 struct DenseNet {
   int n_linear;
+  int act;  // hidden activation (evaluation mode; the linearisation is ReLU only)
   int n[ISX_MAX_LINEAR + 1];
   const float* W[ISX_MAX_LINEAR];
   const float* b[ISX_MAX_LINEAR];
@@ -131,7 +133,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_mfma_kernel(int64_t n_ite
         const float* x = in0 + item * 3;
         const float pre = b1[j] + w0 * x[0] + w1 * x[1] + w2 * x[2];
         if (MODE == DENSE_EVAL) {
-          v = pre > 0.f ? pre : 0.f;
+          v = activate<float>(net.act, pre);
         } else {
           const int a = col % 4;  // 0: centre, 1..3: tangent along axis a-1
           if (a == 0) {
@@ -178,8 +180,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_mfma_kernel(int64_t n_ite
           for (int i = 0; i < 4; ++i) {
             const float y = acc[j][4 * qq + i];
             if (MODE == DENSE_EVAL) {
-              const float pre = y + bias[row + i];
-              v[i] = pre > 0.f ? pre : 0.f;
+              v[i] = activate<float>(net.act, y + bias[row + i]);
             } else {
               // the centre column of this lane's cell is lane (l & ~3): its
               // pre-activation decides the sign for the whole quad
@@ -233,6 +234,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_mfma_kernel(int64_t n_ite
 static DenseNet dense_net(const Model& m) {
   DenseNet d{};
   d.n_linear = m.n_linear;
+  d.act = m.act;
   for (int i = 0; i <= m.n_linear; ++i) d.n[i] = m.pw[i];
   for (int l = 0; l < m.n_linear; ++l) {
     d.W[l] = m.L[l].W;
@@ -253,14 +255,22 @@ static hipError_t launch_dense_k(const Model& m, int64_t n, const float* in0, co
   using Sh = DenseShape<KMAX>;
   constexpr int per = MODE == DENSE_LIN ? 4 : 1;
   constexpr int items = Sh::BN / per;
-  const int64_t blocks = (n + items - 1) / items;
   {
     hipError_t e = ensure_lds_limit(reinterpret_cast<const void*>(&dense_mfma_kernel<MODE, KMAX>), (int)Sh::LDS);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((dense_mfma_kernel<MODE, KMAX>), dim3((unsigned)blocks), dim3(kDenseThreads), Sh::LDS, s, n,
-                     dense_net(m), in0, in1, out);
-  return hipGetLastError();
+  // a launch's work-items must stay below 2^32: at most 2^31 / kDenseThreads
+  // blocks per launch (in0 holds 3 floats per item, in1 3 or none, out 1 or 2)
+  const int64_t per_launch = ((int64_t(1) << 31) / kDenseThreads) * items;
+  constexpr int outw = MODE == DENSE_LIN ? 2 : 1;
+  for (int64_t o = 0; o < n; o += per_launch) {
+    const int64_t c = std::min(per_launch, n - o);
+    hipLaunchKernelGGL((dense_mfma_kernel<MODE, KMAX>), dim3((unsigned)((c + items - 1) / items)), dim3(kDenseThreads),
+                       Sh::LDS, s, c, dense_net(m), in0 + 3 * o, in1 ? in1 + 3 * o : nullptr, out + outw * o);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 template <int MODE>
@@ -649,10 +659,16 @@ static hipError_t launch_lin_n(const Model& m, int64_t n, const float* centres, 
     hipError_t e = ensure_lds_limit(reinterpret_cast<const void*>(&lin_bf16_kernel<N>), (int)LinShape<N>::LDS);
     if (e != hipSuccess) return e;
   }
-  const int64_t blocks = (n + kLinCells - 1) / kLinCells;
-  hipLaunchKernelGGL((lin_bf16_kernel<N>), dim3((unsigned)blocks), dim3(kDenseThreads), LinShape<N>::LDS, s, n,
-                     m.n_linear, m.dev_layers, centres, halves, out);
-  return hipGetLastError();
+  // a launch's work-items must stay below 2^32
+  const int64_t per_launch = ((int64_t(1) << 31) / kDenseThreads) * kLinCells;
+  for (int64_t o = 0; o < n; o += per_launch) {
+    const int64_t c = std::min(per_launch, n - o);
+    hipLaunchKernelGGL((lin_bf16_kernel<N>), dim3((unsigned)((c + kLinCells - 1) / kLinCells)), dim3(kDenseThreads),
+                       LinShape<N>::LDS, s, c, m.n_linear, m.dev_layers, centres + 3 * o, halves + 3 * o, out + 2 * o);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 bool lin_bf16_supported(const Model& m) {

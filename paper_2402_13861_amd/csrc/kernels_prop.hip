@@ -654,9 +654,17 @@ static hipError_t eval_points_t(const Model& m, int64_t n, const float* pts, flo
   const int bs = std::min(1024, std::max(64, (n_max + 63) / 64 * 64));
   const size_t lds = 2 * (size_t)n_max * PT * sizeof(T);
   NetView<T> view = make_view<T>(m);
-  hipLaunchKernelGGL((mlp_eval_kernel<T, PT>), dim3((unsigned)((n + PT - 1) / PT)), dim3(bs), lds, s, n, view,
-                     n_max, pts, vals);
-  return hipGetLastError();
+  // a launch's work-items (blocks x bs) must stay below 2^32: at most 2^31 / bs
+  // blocks of PT points each per launch
+  const int64_t per_launch = ((int64_t(1) << 31) / bs) * PT;
+  for (int64_t o = 0; o < n; o += per_launch) {
+    const int64_t c = std::min(per_launch, n - o);
+    hipLaunchKernelGGL((mlp_eval_kernel<T, PT>), dim3((unsigned)((c + PT - 1) / PT)), dim3(bs), lds, s, c, view,
+                       n_max, pts + 3 * o, vals + o);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t eval_points_f32(const Model& m, int64_t n, const float* pts, float* vals, hipStream_t s) {

@@ -182,9 +182,16 @@ static hipError_t launch_rafixed_t(const Model& m, int64_t n, const float* centr
     if (e != hipSuccess) return e;
   }
   NetView<T> view = net_view<T>(m);
-  hipLaunchKernelGGL((rafixed_kernel<T, PT>), dim3((unsigned)((n + PT - 1) / PT)), dim3(bs), lds, s, n, view, n_max,
-                     centres, halves, seg, out32, out64);
-  return hipGetLastError();
+  // a launch's work-items (blocks x bs) must stay below 2^32
+  const int64_t per_launch = ((int64_t(1) << 31) / bs) * PT;
+  for (int64_t o = 0; o < n; o += per_launch) {
+    const int64_t c = std::min(per_launch, n - o);
+    hipLaunchKernelGGL((rafixed_kernel<T, PT>), dim3((unsigned)((c + PT - 1) / PT)), dim3(bs), lds, s, c, view, n_max,
+                       centres + 3 * o, halves + 3 * o, seg, out32 + 2 * o, out64 ? out64 + 2 * o : nullptr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // LDS per workgroup 2 * 5 * n_max * PT values: float64 takes 2 cells (1 above

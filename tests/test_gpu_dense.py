@@ -226,3 +226,34 @@ def test_every_option_takes_its_default(ctx):
     with pytest.raises(isx.IsxError) as e:
         ctx.set_option(99, 0)
     assert e.value.status == -1
+
+
+@pytest.mark.parametrize("prec_name,n", [("fp32", (1 << 26) + 1000), ("fp64", (1 << 25) + 1000)])
+def test_eval_points_past_one_launch(ctx, prec_name, n):
+    """More points than one launch of the vector-ALU evaluation takes (a
+    launch stays below 2^32 work-items: 2^26 points in float32, 2^25 in
+    float64 for a 256-wide net): points on both sides of every split and at
+    the ends match the oracle (a sine net takes the vector-ALU kernel)."""
+    import paper_2402_13861_amd as isx
+    from workloads.weights import siren_mlp
+
+    mlp = siren_mlp([3, 256, 256, 1], 5, 6.0)
+    prec = {"fp32": isx.FP32, "fp64": isx.FP64}[prec_name]
+    per = 1 << (26 if prec_name == "fp32" else 25)
+    mid = ctx.load_weights(mlp)
+    try:
+        ctx.set_activation(mid, isx.SINE)
+        g = torch.Generator(device="cuda").manual_seed(3)
+        pts = torch.rand((n, 3), device="cuda", generator=g) * 2 - 1
+        vals = torch.full((n,), float("nan"), device="cuda")
+        ctx.eval_points(mid, prec, pts, vals)
+        torch.cuda.synchronize()
+        pick = np.concatenate([np.arange(0, 300), np.arange(per - 300, per + 300), np.arange(n - 300, n)])
+        p = pts[torch.from_numpy(pick).cuda()].double().cpu().numpy()
+        ref = mlp_forward(mlp, p, act="sine")
+        got = vals[torch.from_numpy(pick).cuda()].double().cpu().numpy()
+        S = float(np.std(mlp_forward(mlp, uniform_points(4000, seed=1), act="sine")))
+        err = np.abs(got - ref) / np.maximum(np.abs(ref), S)
+        assert np.all(np.isfinite(got)) and err.max() <= (1e-5 if prec_name == "fp32" else 1e-7), err.max()
+    finally:
+        ctx.unload_mlp(mid)

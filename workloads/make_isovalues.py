@@ -31,7 +31,7 @@ def main():
         if w.get("iso_quantiles") is None:
             continue
         mlp = load_mlp(name)
-        vals = mlp_forward(mlp, uniform_points(10_000, w["weight_seed"] + 1))
+        vals = mlp_forward(mlp, uniform_points(10_000, w["weight_seed"] + 1), act=w.get("act", "relu"))
         qs = w["iso_quantiles"]
         if qs == "median":
             isos = [float(np.median(vals))]

@@ -61,6 +61,20 @@ def he_normal_mlp(widths: Sequence[int], seed: int) -> MLPWeights:
     return MLPWeights(Ws, bs)
 
 
+def siren_mlp(widths: Sequence[int], seed: int, w0: float) -> MLPWeights:
+    """Sine network in the SIREN initialisation (Sitzmann et al. 2020): first
+    layer U(-w0/fan_in, w0/fan_in) (the frequency w0 folded into it), later
+    layers U(-sqrt(6/fan_in), sqrt(6/fan_in)), biases from the same ranges,
+    drawn in the order W1, b1, W2, b2, ... from ``default_rng(seed)``."""
+    rng = np.random.default_rng(seed)
+    Ws, bs = [], []
+    for li, (fan_in, fan_out) in enumerate(zip(widths[:-1], widths[1:])):
+        lim = w0 / fan_in if li == 0 else np.sqrt(6.0 / fan_in)
+        Ws.append(rng.uniform(-lim, lim, (fan_out, fan_in)).astype(np.float32))
+        bs.append(rng.uniform(-lim, lim, fan_out).astype(np.float32))
+    return MLPWeights(Ws, bs)
+
+
 def write_weights(path, mlp: MLPWeights) -> None:
     widths = mlp.widths
     with open(path, "wb") as f:
