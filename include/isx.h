@@ -577,7 +577,9 @@ typedef enum {
                               covariances) keeps at most 2^-9 of the magnitude a = sum_i |T_ji W_ji| of its
                               terms (Eq. 7 needs the variance; such a sum can lose every digit) while its
                               pre-activation y lies where the rule depends on sigma (ReLU, Eq. 9:
-                              |y| < 6 sqrt(max(v, 0) + 2^-7 a); ELU: y below that bound; sine: always)
+                              |y| < 6 sqrt(max(v, 0) + 2^-7 a); ELU: y below that bound; sine, whose rule
+                              depends on v smoothly: (1 + 2|y|) 2^-9 a > 2^-20, the largest shift of the
+                              centre that the variance error can cause)
                               is propagated again in float64, and its float64 (mu, sigma) is returned;
                               0 = off */
   ISX_AUTOTUNE = 12,       /* bf16 coefficient-form propagation: 1 = pick the hidden-layer tile shape of

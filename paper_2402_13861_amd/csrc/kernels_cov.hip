@@ -417,10 +417,17 @@ __global__ __launch_bounds__(kCovThreads) void up_cov_bf16_kernel(int64_t C, int
           // for ReLU, beyond 6 sigma (taken at its largest with the terms'
           // rounding, sqrt(v + 2^-7 sum |terms|)) alpha is 0 or 1 and beta,
           // gamma vanish to float32 accuracy whatever sigma is; for ELU that
-          // holds 6 sigma above 0 only; the sine rule always depends on sigma
+          // holds 6 sigma above 0 only.  The sine rule depends on the
+          // variance smoothly (alpha = cos(y) e^{-v/2}, |d beta / dv| <=
+          // (1 + |y|) / 2, gamma^2 of order v^2), so a variance error of at
+          // most 2^-8 sum |terms| moves the centre by at most
+          // (1 + 2|y|) 2^-9 sum |terms|: flagged only above 2^-20, below
+          // which it stays under the float32 rounding of the centre's sums
           if (av > 0.f && !(v > kCancelRatio * av)) {
             const float s6 = 6.f * sqrtf(fmaxf(v, 0.f) + 0x1p-7f * av);
-            if (act == ISX_SINE || (act == ISX_ELU ? y < s6 : fabsf(y) < s6)) s_cancel = 1u;
+            const bool dep = act == ISX_SINE ? (1.f + 2.f * fabsf(y)) * 0x1p-9f * av > 0x1p-20f
+                                             : (act == ISX_ELU ? y < s6 : fabsf(y) < s6);
+            if (dep) s_cancel = 1u;
           }
           apply_rule<float, ISX_UP>(act, y, v, a, b, g);
           s_var[j] = v;
