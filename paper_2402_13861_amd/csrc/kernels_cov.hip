@@ -155,14 +155,17 @@ __device__ __forceinline__ float quad_sum(float x) {
   return x;
 }
 
-// All hidden layers have padded width N (the input layer is 3 wide).
-template <int N>
+// All hidden layers have padded width N (the input layer is 3 wide).  The
+// activation is a compile-time constant: its rule is inlined, and ReLU keeps
+// the register budget of a kernel without the float64 sine and ELU rules.
+template <int N, int ACT>
 __global__ __launch_bounds__(kCovThreads) void up_cov_bf16_kernel(int64_t C, int n_linear,
                                                                   const DevLayer* __restrict__ layers,
                                                                   float* __restrict__ vec,
                                                                   const float* __restrict__ centres,
                                                                   const float* __restrict__ halves,
-                                                                  uint32_t* __restrict__ cancel, int act) {
+                                                                  uint32_t* __restrict__ cancel) {
+  constexpr int act = ACT;
   using S = CovShape<N>;
   constexpr int STR = S::STR, KS = S::KS, NB = S::NB;
   extern __shared__ float4 cov_smem4[];
@@ -533,18 +536,28 @@ static int cov_width(const Model& m) {
 
 bool cov_supported(const Model& m) { return cov_width(m) != 0; }
 
-template <int N>
-static hipError_t launch_cov_n(const Model& m, int64_t C, const float* centres, const float* halves, float* vec,
+template <int N, int ACT>
+static hipError_t launch_cov_na(const Model& m, int64_t C, const float* centres, const float* halves, float* vec,
                                uint32_t* cancel, hipStream_t s) {
   {
-    hipError_t e = ensure_lds_limit(reinterpret_cast<const void*>(&up_cov_bf16_kernel<N>), (int)CovShape<N>::LDS);
+    hipError_t e = ensure_lds_limit(reinterpret_cast<const void*>(&up_cov_bf16_kernel<N, ACT>), (int)CovShape<N>::LDS);
     if (e != hipSuccess) return e;
   }
   // one workgroup per cell: a launch's work-items must stay below 2^32
   if (C > (int64_t(1) << 22)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((up_cov_bf16_kernel<N>), dim3((unsigned)C), dim3(kCovThreads), CovShape<N>::LDS, s, C,
-                     m.n_linear, m.dev_layers, vec, centres, halves, cancel, m.act);
+  hipLaunchKernelGGL((up_cov_bf16_kernel<N, ACT>), dim3((unsigned)C), dim3(kCovThreads), CovShape<N>::LDS, s, C,
+                     m.n_linear, m.dev_layers, vec, centres, halves, cancel);
   return hipGetLastError();
+}
+
+template <int N>
+static hipError_t launch_cov_n(const Model& m, int64_t C, const float* centres, const float* halves, float* vec,
+                               uint32_t* cancel, hipStream_t s) {
+  switch (m.act) {
+    case ISX_SINE: return launch_cov_na<N, ISX_SINE>(m, C, centres, halves, vec, cancel, s);
+    case ISX_ELU: return launch_cov_na<N, ISX_ELU>(m, C, centres, halves, vec, cancel, s);
+    default: return launch_cov_na<N, ISX_RELU>(m, C, centres, halves, vec, cancel, s);
+  }
 }
 
 hipError_t launch_up_cov_bf16(const Model& m, int64_t C, const float* centres, const float* halves, float* vec,

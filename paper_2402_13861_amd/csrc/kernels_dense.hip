@@ -39,7 +39,6 @@ enum { DENSE_EVAL = 0, DENSE_LIN = 1 };
 
 struct DenseNet {
   int n_linear;
-  int act;  // hidden activation (evaluation mode; the linearisation is ReLU only)
   int n[ISX_MAX_LINEAR + 1];
   const float* W[ISX_MAX_LINEAR];
   const float* b[ISX_MAX_LINEAR];
@@ -100,7 +99,9 @@ __device__ __forceinline__ void dense_tile_gemm(const float* __restrict__ A, int
   }
 }
 
-template <int MODE, int KMAX>
+// The activation (evaluation mode) is a compile-time constant, so ReLU keeps
+// the register budget of a kernel without the sine and ELU branches.
+template <int MODE, int KMAX, int ACT>
 __global__ __launch_bounds__(kDenseThreads) void dense_mfma_kernel(int64_t n_items, DenseNet net,
                                                                    const float* __restrict__ in0,
                                                                    const float* __restrict__ in1,
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_mfma_kernel(int64_t n_ite
         const float* x = in0 + item * 3;
         const float pre = b1[j] + w0 * x[0] + w1 * x[1] + w2 * x[2];
         if (MODE == DENSE_EVAL) {
-          v = activate<float>(net.act, pre);
+          v = activate<float>(ACT, pre);
         } else {
           const int a = col % 4;  // 0: centre, 1..3: tangent along axis a-1
           if (a == 0) {
@@ -180,7 +181,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_mfma_kernel(int64_t n_ite
           for (int i = 0; i < 4; ++i) {
             const float y = acc[j][4 * qq + i];
             if (MODE == DENSE_EVAL) {
-              v[i] = activate<float>(net.act, y + bias[row + i]);
+              v[i] = activate<float>(ACT, y + bias[row + i]);
             } else {
               // the centre column of this lane's cell is lane (l & ~3): its
               // pre-activation decides the sign for the whole quad
@@ -234,7 +235,6 @@ __global__ __launch_bounds__(kDenseThreads) void dense_mfma_kernel(int64_t n_ite
 static DenseNet dense_net(const Model& m) {
   DenseNet d{};
   d.n_linear = m.n_linear;
-  d.act = m.act;
   for (int i = 0; i <= m.n_linear; ++i) d.n[i] = m.pw[i];
   for (int l = 0; l < m.n_linear; ++l) {
     d.W[l] = m.L[l].W;
@@ -249,14 +249,14 @@ static int dense_kmax(const Model& m) {
   return w;
 }
 
-template <int MODE, int KMAX>
+template <int MODE, int KMAX, int ACT>
 static hipError_t launch_dense_k(const Model& m, int64_t n, const float* in0, const float* in1, float* out,
                                  hipStream_t s) {
   using Sh = DenseShape<KMAX>;
   constexpr int per = MODE == DENSE_LIN ? 4 : 1;
   constexpr int items = Sh::BN / per;
   {
-    hipError_t e = ensure_lds_limit(reinterpret_cast<const void*>(&dense_mfma_kernel<MODE, KMAX>), (int)Sh::LDS);
+    hipError_t e = ensure_lds_limit(reinterpret_cast<const void*>(&dense_mfma_kernel<MODE, KMAX, ACT>), (int)Sh::LDS);
     if (e != hipSuccess) return e;
   }
   // a launch's work-items must stay below 2^32: at most 2^31 / kDenseThreads
@@ -265,7 +265,7 @@ static hipError_t launch_dense_k(const Model& m, int64_t n, const float* in0, co
   constexpr int outw = MODE == DENSE_LIN ? 2 : 1;
   for (int64_t o = 0; o < n; o += per_launch) {
     const int64_t c = std::min(per_launch, n - o);
-    hipLaunchKernelGGL((dense_mfma_kernel<MODE, KMAX>), dim3((unsigned)((c + items - 1) / items)), dim3(kDenseThreads),
+    hipLaunchKernelGGL((dense_mfma_kernel<MODE, KMAX, ACT>), dim3((unsigned)((c + items - 1) / items)), dim3(kDenseThreads),
                        Sh::LDS, s, c, dense_net(m), in0 + 3 * o, in1 ? in1 + 3 * o : nullptr, out + outw * o);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -273,24 +273,30 @@ static hipError_t launch_dense_k(const Model& m, int64_t n, const float* in0, co
   return hipSuccess;
 }
 
-template <int MODE>
+template <int MODE, int ACT>
 static hipError_t launch_dense(const Model& m, int64_t n, const float* in0, const float* in1, float* out,
                                hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int kmax = dense_kmax(m);
   if (m.n_linear < 2 || kmax < 32) return hipErrorNotSupported;
-  if (kmax <= 256) return launch_dense_k<MODE, 256>(m, n, in0, in1, out, s);
-  if (kmax <= 512) return launch_dense_k<MODE, 512>(m, n, in0, in1, out, s);
-  return launch_dense_k<MODE, 1024>(m, n, in0, in1, out, s);
+  if (kmax <= 256) return launch_dense_k<MODE, 256, ACT>(m, n, in0, in1, out, s);
+  if (kmax <= 512) return launch_dense_k<MODE, 512, ACT>(m, n, in0, in1, out, s);
+  return launch_dense_k<MODE, 1024, ACT>(m, n, in0, in1, out, s);
 }
 
 hipError_t eval_points_mfma(const Model& m, int64_t n, const float* pts, float* vals, hipStream_t s) {
-  return launch_dense<DENSE_EVAL>(m, n, pts, nullptr, vals, s);
+  switch (m.act) {
+    case ISX_SINE: return launch_dense<DENSE_EVAL, ISX_SINE>(m, n, pts, nullptr, vals, s);
+    case ISX_ELU: return launch_dense<DENSE_EVAL, ISX_ELU>(m, n, pts, nullptr, vals, s);
+    default: return launch_dense<DENSE_EVAL, ISX_RELU>(m, n, pts, nullptr, vals, s);
+  }
 }
 
+// (ReLU only: the tangent columns take the centre's ReLU mask)
 hipError_t linearize_mfma(const Model& m, int64_t n, const float* centres, const float* halves, float* out,
                           hipStream_t s) {
-  return launch_dense<DENSE_LIN>(m, n, centres, halves, out, s);
+  if (m.act != ISX_RELU) return hipErrorNotSupported;
+  return launch_dense<DENSE_LIN, ISX_RELU>(m, n, centres, halves, out, s);
 }
 
 // ------------------------------------------------------- output read-off
