@@ -374,24 +374,34 @@ isx_status run_propagate(isx_ctx* ctx, const Model& m, isx_method method, isx_pr
     return ISX_OK;
   }
   if (prec == ISX_BF16) {
-    if (!bf16_supported(m))
-      return fail(ctx, ISX_EUNSUPPORTED, "bf16 propagation needs every hidden layer's input width <= 256");
-    // the covariance form (UP) keeps each cell on chip: no coefficient blocks
+    // UP in covariance form: on chip (hidden widths <= 256), or with the
+    // per-cell matrices in global memory (ISX_UP_FORM = 2; uniform widths
+    // that are multiples of 256)
     const bool cov = method == ISX_UP && ctx->up_form == 0 && cov_supported(m);
-    const size_t per_cell = (cov ? 0 : 2 * prop_F_elems_bf16(m, 1) * 2) + prop_vec_elems(m, 1, marg) * 4;
+    const bool covg = method == ISX_UP && !marg && ctx->up_form == 2 && covg_width(m);
+    if (method == ISX_UP && ctx->up_form == 2 && !covg)
+      return fail(ctx, ISX_EUNSUPPORTED,
+                  "ISX_UP_FORM 2 needs hidden layers of one width, a multiple of 256 up to 1024");
+    if (!bf16_supported(m) && !covg)
+      return fail(ctx, ISX_EUNSUPPORTED, "bf16 propagation needs every hidden layer's input width <= 512");
+    const size_t per_cell = (cov ? 0 : (covg ? covg_scratch_bytes(m, 1) : 2 * prop_F_elems_bf16(m, 1) * 2)) +
+                            prop_vec_elems(m, 1, marg) * 4;
     int64_t chunk = chunk_req > 0 ? chunk_req : (int64_t)(ctx->prop_budget / per_cell);
     chunk = std::max<int64_t>(1, std::min<int64_t>({chunk, n, kMaxPropChunk}));
+    if (covg) chunk = std::min(chunk, covg_max_chunk(m));
     PropWork<float> w;
-    if (!cov) {
+    if (covg) {
+      HIPCHK(ensure(ctx->Fbf[0], covg_scratch_bytes(m, chunk)));
+    } else if (!cov) {
       HIPCHK(ensure(ctx->Fbf[0], prop_F_elems_bf16(m, chunk) * 2));
       HIPCHK(ensure(ctx->Fbf[1], prop_F_elems_bf16(m, chunk) * 2));
     }
     HIPCHK(ensure(ctx->vec32, prop_vec_elems(m, chunk, marg) * sizeof(float)));
     w.vec = (float*)ctx->vec32.p;
-    const bool check = cov && ctx->cancel_check != 0;
+    const bool check = (cov || covg) && ctx->cancel_check != 0;
     if (check) HIPCHK(ensure(ctx->cx_flags, n * 4));
     int variant = ctx->bf16_variant;
-    if (variant == 0 && !cov && ctx->autotune && !ctx->tuning) {
+    if (variant == 0 && !cov && !covg && ctx->autotune && !ctx->tuning) {
       const isx_status st = tune_bf16(ctx, m);
       if (st != ISX_OK) return st;
       variant = m.bf16_tuned;
@@ -403,6 +413,7 @@ isx_status run_propagate(isx_ctx* ctx, const Model& m, isx_method method, isx_pr
       a.aa_margin = marg;
       if (check) a.cancel = (uint32_t*)ctx->cx_flags.p + s;
       a.readoff_f32 = ctx->readoff_f32;
+      a.covg = covg;
       HIPCHK(propagate_bf16(a, w, Fbf, 0));
     }
     ctx->n_cancel_last = 0;
@@ -540,7 +551,7 @@ isx_status isx_set_option(isx_ctx* ctx, isx_option option, int64_t value) {
       ctx->verbose = value != 0;
       return ISX_OK;
     case ISX_UP_FORM:
-      if (value < 0 || value > 1) return fail(ctx, ISX_EINVAL, "ISX_UP_FORM must be 0 or 1");
+      if (value < 0 || value > 2) return fail(ctx, ISX_EINVAL, "ISX_UP_FORM must be 0, 1 or 2");
       ctx->up_form = (int)value;
       return ISX_OK;
     case ISX_BATCH_WORKERS:
@@ -673,6 +684,14 @@ isx_status isx_load_mlp(isx_ctx* ctx, int32_t n_linear, const int32_t* widths, c
     if (e == hipSuccess) e = upload(&L.bd, bd);
     if (e == hipSuccess) e = upload(&L.Wtbf, Wtbf);
     if (e == hipSuccess) e = upload(&L.Wbf, Wbf);
+    if (e == hipSuccess && l >= 1 && l + 1 < n_linear && ni == no && no > kCovNMax) {
+      // the fragment-order copy that the global-memory covariance form reads
+      const int N = no;
+      std::vector<uint16_t> Wfr((size_t)N * N);
+      for (int r = 0; r < N; ++r)
+        for (int k = 0; k < N; ++k) Wfr[cov_frag_index(N, r, k)] = Wbf[(size_t)r * N + k];
+      e = upload(&L.Wfr, Wfr);
+    }
     if (e == hipSuccess && l >= 1 && l + 1 < n_linear && ni == no && no <= kCovNMax) {
       // copies in the covariance kernel's access orders
       const int N = no;

@@ -270,6 +270,7 @@ struct PropArgs {
   uint32_t* cancel = nullptr;  // bf16 UP covariance form: per-cell cancellation flags [C] (may be null)
   int seg = 0;                 // 1: inputs are segments (centre, half-vector) with one input symbol
   int readoff_f32 = 0;         // bf16 UP: 1 = the float32 MFMA read-off instead of the bf16 hi/lo one
+  bool covg = false;           // bf16 UP: the covariance form with the matrices in global memory (scratch: Fbf[0])
 };
 
 // Constants of the affine-arithmetic rounding margin of one layer
@@ -301,6 +302,16 @@ bool bf16_supported(const Model& m);
 // covariance-form UP on BF16 MFMA (kernels_cov.hip)
 bool cov_supported(const Model& m);
 double cov_flops_per_cell(const Model& m);
+// Covariance form with the per-cell matrices in global memory
+// (kernels_covg.hip): uniform padded hidden width N, a multiple of 256 up to
+// ISX_MAX_WIDTH, with fragment-order weight copies (0 if not supported);
+// scratch bytes for C cells; executed flops per cell.
+int covg_width(const Model& m);
+size_t covg_scratch_bytes(const Model& m, int64_t C);
+int64_t covg_max_chunk(const Model& m);  // cells per launch (the gemm grid stays below 2^31 work-items)
+double covg_flops_per_cell(const Model& m);
+hipError_t launch_up_cov_global(const Model& m, int64_t C, const float* centres, const float* halves, float* vec,
+                                uint32_t* cancel, void* scratch, hipStream_t s);
 // vec: the Y, A, B, G vectors of hidden layers 1..L-1, each [C][padded width], in that order per layer
 // cancel [C] (may be null): 1 where a variance sum cancelled (kernels_cov.hip)
 hipError_t launch_up_cov_bf16(const Model& m, int64_t C, const float* centres, const float* halves, float* vec,

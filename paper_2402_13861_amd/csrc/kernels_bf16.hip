@@ -398,7 +398,7 @@ hipError_t propagate_bf16(const PropArgs& a, PropWork<float>& w, uint16_t* Fbf_r
   const Model& m = *a.m;
   const int64_t C = a.C;
   if (C <= 0) return hipSuccess;
-  if (!bf16_supported(m)) return hipErrorNotSupported;
+  if (!bf16_supported(m) && !a.covg) return hipErrorNotSupported;
   __bf16* Fbf[2] = {reinterpret_cast<__bf16*>(Fbf_raw[0]), reinterpret_cast<__bf16*>(Fbf_raw[1])};
   const int Lh = m.hidden();
   float *Y[ISX_MAX_LINEAR] = {}, *A[ISX_MAX_LINEAR] = {}, *B[ISX_MAX_LINEAR] = {}, *G[ISX_MAX_LINEAR] = {};
@@ -412,6 +412,23 @@ hipError_t propagate_bf16(const PropArgs& a, PropWork<float>& w, uint16_t* Fbf_r
       G[h] = w.vec + off + 3 * n;
       off += 4 * n;
     }
+  }
+  if (a.method == ISX_UP && a.covg) {
+    // covariance form with the per-cell matrices in global memory
+    Profiler::Rec rec{};
+    double vec_bytes = 24.0;
+    for (int h = 1; h <= Lh; ++h) vec_bytes += 16.0 * m.pw[h];
+    const bool prof = a.prof && a.prof->begin(rec, ISX_KERNEL_HIDDEN_COV_BF16, covg_flops_per_cell(m) * (double)C,
+                                              vec_bytes * (double)C, a.stream);
+    hipError_t e = launch_up_cov_global(m, C, a.centres, a.halves, w.vec, a.cancel, Fbf_raw[0], a.stream);
+    if (prof) a.prof->end(rec, a.stream);
+    if (e != hipSuccess) return e;
+    Profiler::Rec rec2{};
+    const bool prof2 = a.prof && a.prof->begin(rec2, ISX_KERNEL_OUTPUT, output_flops_per_cell(m) * (double)C,
+                                               4.0 * C * 4.0 * (double)m.pw[1] * Lh, a.stream);
+    e = launch_output_mfma(m, a.method, C, Y, A, B, G, a.halves, a.out32, a.stream);
+    if (prof2) a.prof->end(rec2, a.stream);
+    return e;
   }
   if (a.method == ISX_UP && a.up_form == 0 && cov_supported(m)) {
     // covariance form: one fused launch for every hidden layer
