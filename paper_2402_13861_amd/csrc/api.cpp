@@ -685,12 +685,18 @@ isx_status isx_load_mlp(isx_ctx* ctx, int32_t n_linear, const int32_t* widths, c
     if (e == hipSuccess) e = upload(&L.Wtbf, Wtbf);
     if (e == hipSuccess) e = upload(&L.Wbf, Wbf);
     if (e == hipSuccess && l >= 1 && l + 1 < n_linear && ni == no && no > kCovNMax) {
-      // the fragment-order copy that the global-memory covariance form reads
+      // the fragment-order and accumulator-quad copies that the device-memory
+      // covariance form reads
       const int N = no;
       std::vector<uint16_t> Wfr((size_t)N * N);
+      std::vector<float> Wq((size_t)N * N);
       for (int r = 0; r < N; ++r)
-        for (int k = 0; k < N; ++k) Wfr[cov_frag_index(N, r, k)] = Wbf[(size_t)r * N + k];
+        for (int k = 0; k < N; ++k) {
+          Wfr[cov_frag_index(N, r, k)] = Wbf[(size_t)r * N + k];
+          Wq[cov_quad_pos(N, r, k)] = W[(size_t)r * N + k];
+        }
       e = upload(&L.Wfr, Wfr);
+      if (e == hipSuccess) e = upload(&L.Wq, Wq);
     }
     if (e == hipSuccess && l >= 1 && l + 1 < n_linear && ni == no && no <= kCovNMax) {
       // copies in the covariance kernel's access orders

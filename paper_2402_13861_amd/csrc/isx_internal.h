@@ -51,7 +51,8 @@ struct Layer {
   double* bd = nullptr;
   uint16_t* Wtbf = nullptr; // bfloat16 bits of W^T, [n_in][n_out]
   uint16_t* Wbf = nullptr;  // bfloat16 bits of W, [n_out][n_in]
-  // square hidden layers of width <= kCovNMax only (else null):
+  // square hidden layers only (Wfr and Wq at every width, the others at
+  // widths <= kCovNMax; else null):
   uint16_t* Wfr = nullptr;  // bfloat16 bits of W in MFMA fragment order (cov_frag_index)
   uint16_t* Wfrl = nullptr; // bfloat16 bits of W - bf16(W), same order
   float* Wv = nullptr;      // W with each row's chunks in row-pass order (cov_row_pos)

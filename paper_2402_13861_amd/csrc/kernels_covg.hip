@@ -1,27 +1,41 @@
 // Uncertainty propagation in covariance form on BF16 MFMA for hidden widths
-// whose N x N covariance does not fit one CU's LDS: the per-cell matrices
-// live in global memory (HBM, L2) between the steps of a layer.
+// whose N x N covariance does not fit one CU's LDS: between layers the
+// per-cell matrices live in device memory, and each layer is one launch.
 //
 // The form is the one of kernels_cov.hip (Eq. 8-9 through covariances):
-//   X_1 = G G^T + diag(gamma_1^2),  G = D_1 W_1 diag(h / sqrt 3)  (N x 3),
-//   per hidden layer h >= 2:
-//     T = W_h X_{h-1}                      (computed as T^T = X W_h^T),
-//     v_j = C_h[j][j] = sum_i T[j][i] W_h[j][i],  y = W_h z + b,
+//   C_1 = F F^T,  F = W_1 diag(h / sqrt 3)  (N x 3),
+//   per hidden layer h >= 2, with X_{h-1} = D C_{h-1} D + diag(gamma^2)
+//   (D = diag(alpha) and gamma of layer h-1):
+//     T = W_h X_{h-1},  v_j = C_h[j][j] = sum_i T[j][i] W_h[j][i],
+//     y = W_h z + b (z = alpha . y_{h-1} + beta),
 //     the rule gives (alpha, beta, gamma) from (y, v),
-//     C_h = T W_h^T,  X_h = D C_h D + diag(gamma^2)  (not after the last).
-// Steps per layer, each a launch over the cells of a chunk:
-//   1. covg_gemm (T mode): per cell, 256 x 256 tiles of X W^T on
-//      v_mfma_f32_32x32x16_bf16 (rows of X staged in LDS in K chunks, weight
-//      fragments streamed from the L2-resident fragment-order copy, as in
-//      the LDS kernel); the epilogue stores T (bfloat16, row-major) and each
-//      row's partial variance sums and magnitude sums over the tile's rows
-//      (fixed slots, no atomics);
-//   2. covg_rule: per cell, the partial sums in a fixed order, the float32
-//      centre y = W z + b, the rule, the layer's (y, alpha, beta, gamma);
-//   3. covg_gemm (X mode): T W^T, the epilogue stores D C D + diag(gamma^2)
-//      (bfloat16; C is symmetric, so the tile's columns are written as rows).
-// The cancellation check is the LDS kernel's (variance <= 2^-9 of the
-// magnitude sum where the rule depends on sigma marks the cell).
+//     C_h = T W_h^T  (not after the last hidden layer).
+// Stored between layers: Chat[i][k] = alpha_k C[i][k] (bfloat16, one factor
+// of D applied along the second index), with the diagonal alpha_i v_i from
+// the variance the rule used.  Then X[i][k] = alpha_i Chat[i][k] + [i = k]
+// gamma_i^2, so that
+//   T[j][i] = alpha_i (Chat W_h^T)[i][j] + gamma_i^2 W_h[j][i]
+// needs no per-element scaling of an MFMA operand: a workgroup that owns
+// neurons R can store its block of the next Chat (columns R, scaled by its
+// own alpha_R) without the other workgroups' alphas.
+// One launch per layer h >= 2; a workgroup owns RB = 65536 / N neurons j of
+// one cell (N / RB workgroups per cell, 8 blocks apart so that they run on
+// the same XCD and share the cell's Chat through its L2):
+//   1. Out = Chat W_R^T (N x RB) on v_mfma_f32_32x32x16_bf16, rows of Chat
+//      staged through LDS in K chunks (double buffer), weight fragments of
+//      rows R streamed from the L2-resident fragment-order copy of W_h; the
+//      epilogue forms T[j][i] (float32), sums each neuron's variance, its
+//      magnitude and its centre W z over the lane's rows, and keeps T_R in
+//      LDS as bfloat16 (row-major, rows R);
+//   2. per neuron j in R: the partial sums in a fixed order, the rule, the
+//      layer's (y, alpha, beta, gamma);
+//   3. C_R = T_R W_h^T (RB x N), A = rows of T_R from LDS, B = weight
+//      fragments; the epilogue stores Chat[m][j] = alpha_j C[j][m] (C is
+//      symmetric), the diagonal alpha_j v_j.  The last hidden layer stops
+//      after step 2.
+// The cancellation check is the LDS kernel's (a variance sum that keeps at
+// most 2^-9 of its terms' magnitude, where the rule depends on sigma, marks
+// the cell for the host's float64 re-propagation).
 //
 // MFMA 32x32x16 bf16 layout (lane l): A (row l%32, k 8(l/32)+e), B (k
 // 8(l/32)+e, column l%32), e = 0..7; accumulator register r holds (row
@@ -39,15 +53,37 @@ typedef __bf16 gbf16x8 __attribute__((ext_vector_type(8)));
 typedef __attribute__((address_space(1))) const gbf16x8 ggbf16x8;  // in global memory
 typedef float gv16f __attribute__((ext_vector_type(16)));
 
-constexpr int kGThreads = 512;  // 8 waves: 2 row groups x 4 column groups
-constexpr int kGTile = 256;     // output tile edge per workgroup
-constexpr int kGK = 64;         // K chunk staged in LDS (4 k-steps)
-constexpr int kGStr = kGK + 8;  // LDS row stride in bfloat16 (rows 144 bytes apart)
-constexpr int kGRows = 128;     // rows of a wave (4 blocks of 32)
-constexpr int kGCols = 64;      // columns of a wave (2 blocks of 32)
-constexpr size_t kGLds = (size_t)2 * kGTile * kGStr * 2;  // two staged buffers
+constexpr int kGThreads = 512;  // 8 waves
 
-enum { COVG_T = 0, COVG_V = 1, COVG_X = 2 };
+template <int N>
+struct CovgShape {
+  static constexpr int RB = 65536 / N;  // neurons per workgroup (256, 128, 64)
+  static constexpr int NR = N / RB;     // workgroups per cell (1, 4, 16)
+  static constexpr int KC = N <= 512 ? 32 : 16;  // K chunk of the staged Chat rows
+  static constexpr int SSTR = KC + 8;            // staged row stride (bfloat16; 16-byte multiple)
+  static constexpr int SPT = N * KC / 8 / 512;   // 16-byte pieces per thread and chunk (2, 4, 4)
+  static constexpr int D = 2;                    // chunks in flight (register sets)
+  static constexpr int TSTR = N + 8;    // row stride of T_R in LDS
+  // step 1: Out (N x RB) on WI1 x WJ1 waves of PI x PJ blocks of 32 x 32
+  static constexpr int PI = 4, PJ = 2;
+  static constexpr int WI1 = N / 32 / PI;  // 2, 4, 8
+  static constexpr int WJ1 = 8 / WI1;      // 4, 2, 1
+  // step 3: C_R (RB x N) on WJ3 x WM3 waves of QJ x QM blocks
+  static constexpr int WJ3 = N == 256 ? 2 : 1;
+  static constexpr int WM3 = 8 / WJ3;
+  static constexpr int QJ = RB / 32 / WJ3;  // 4, 4, 2
+  static constexpr int QM = N / 32 / WM3;   // 2, 2, 4
+  static constexpr size_t STAGE = (size_t)2 * N * SSTR * 2;
+  static constexpr size_t TBYTES = (size_t)RB * TSTR * 2;
+  static constexpr size_t REGION = STAGE > TBYTES ? STAGE : TBYTES;  // staging, then T_R
+  static constexpr size_t PART = (size_t)3 * WI1 * RB * 4;          // partial sums
+  static constexpr size_t VECS = (size_t)(3 * N + 2 * RB) * 4;
+  static constexpr size_t LDS = REGION + PART + VECS;
+  static_assert(PI * WI1 * 32 == N && PJ * WJ1 * 32 == RB, "step-1 tiling");
+  static_assert(QJ * WJ3 * 32 == RB && QM * WM3 * 32 == N, "step-3 tiling");
+  static_assert(LDS <= 160 * 1024, "LDS");
+  static_assert((size_t)N * RB * 2 <= REGION, "the step-3 output tile fits where T_R was");
+};
 
 // four floats rounded to bfloat16, packed low to high
 __device__ __forceinline__ uint2 pack_bf16x4(float a, float b, float c, float d) {
@@ -62,180 +98,328 @@ __device__ __forceinline__ uint2 pack_bf16x4(float a, float b, float c, float d)
   return p.u;
 }
 
-// Out[r][c] = sum_k A[r][k] W[c][k] on the workgroup's 256 x 256 tile of one
-// cell (A: the cell's N x N bfloat16 matrix, row-major; W: fragment order).
-// MODE T: store T[c][r] = Out[r][c] to Tout and the partial sums
-// sum_r Out[r][c] W[c][r] (and of magnitudes) over the wave's 128 rows into
-// part[(cell * NP + p) * N + c], p = row tile * 2 + row group; V: only the
-// partial sums; X: store X[c][r] = alpha_r alpha_c Out[r][c] (+ the rule's
-// alpha_c^2 v_c + gamma_c^2 on the diagonal) to Xout.
-template <int MODE>
-__global__ __launch_bounds__(kGThreads) void covg_gemm_kernel(int64_t C, int N, const __bf16* __restrict__ Ain,
-                                                               const __bf16* __restrict__ Wfr,
-                                                               const float* __restrict__ Wf, __bf16* __restrict__ Out,
-                                                               float* __restrict__ part, float* __restrict__ partm,
-                                                               const float* __restrict__ alpha,
-                                                               const float* __restrict__ gamma,
-                                                               const float* __restrict__ var) {
+// A variance sum is flagged when it keeps at most this fraction of the
+// summed magnitude of its terms (as in the LDS kernel).
+constexpr float kGCancelRatio = 0x1p-9f;
+
+// Layer h >= 2: steps 1-3 above for the RB neurons of one workgroup.
+// vprev / vcur: the (y, alpha, beta, gamma) blocks of layers h-1 and h
+// ([4][C][N] floats each); Cin / Cout: Chat of layers h-1 and h ([C][N][N]).
+template <int N, int ACT, bool LAST>
+__global__ __launch_bounds__(kGThreads) void covg_layer_kernel(int64_t C, const __bf16* __restrict__ Cin,
+                                                                __bf16* __restrict__ Cout,
+                                                                const __bf16* __restrict__ Wfr,
+                                                                const float4* __restrict__ Wq,
+                                                                const float* __restrict__ bias,
+                                                                const float* __restrict__ vprev,
+                                                                float* __restrict__ vcur,
+                                                                uint32_t* __restrict__ cancel) {
+  using S = CovgShape<N>;
+  constexpr int RB = S::RB, NR = S::NR, KC = S::KC, SSTR = S::SSTR, TSTR = S::TSTR;
+  constexpr int PI = S::PI, PJ = S::PJ, WI1 = S::WI1, QJ = S::QJ, QM = S::QM, WM3 = S::WM3;
+  constexpr int KS = N / 16;
   extern __shared__ uint4 covg_smem[];
-  __bf16* lds = reinterpret_cast<__bf16*>(covg_smem);  // [2][kGTile][kGStr]
-  const int tiles = N / kGTile;
+  unsigned char* base = reinterpret_cast<unsigned char*>(covg_smem);
+  __bf16* stage = reinterpret_cast<__bf16*>(base);  // [2][N][SSTR] (step 1)
+  __bf16* Tl = reinterpret_cast<__bf16*>(base);     // [RB][TSTR] (steps 1-3)
+  float* pv = reinterpret_cast<float*>(base + S::REGION);  // [WI1][RB] variance
+  float* pm = pv + WI1 * RB;                               // [WI1][RB] magnitude
+  float* py = pm + WI1 * RB;                               // [WI1][RB] centre
+  float* s_alpha = py + WI1 * RB;  // [N] alpha of layer h-1
+  float* s_g2 = s_alpha + N;       // [N] gamma^2 of layer h-1
+  float* s_z = s_g2 + N;           // [N] mean of layer h-1's output
+  float* s_ac = s_z + N;           // [RB] alpha of the workgroup's neurons
+  float* s_vc = s_ac + RB;         // [RB] their variances
+
+  // block -> (cell, neuron block): the NR blocks of a cell lie 8 apart
   const int64_t blk = blockIdx.x;
-  const int64_t cell = blk / (tiles * tiles);
+  const int64_t grp = blk / (8 * NR);
+  const int w8 = (int)(blk - grp * 8 * NR);
+  const int64_t cell = grp * 8 + (w8 & 7);
   if (cell >= C) return;
-  const int tt = (int)(blk - cell * tiles * tiles);
-  const int tr = tt / tiles, tc = tt - tr * tiles;  // row tile (A rows), column tile (W rows)
+  const int R0 = (w8 >> 3) * RB;
   const int t = threadIdx.x, lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
   const int l32 = lane & 31, hi = lane >> 5;
-  const int wr = wave & 1, wc = wave >> 1;
-  const int row0 = tr * kGTile + wr * kGRows;  // the wave's first A row
-  const int col0 = tc * kGTile + wc * kGCols;  // the wave's first W row
+  const int64_t NC = (int64_t)N * C;
   const int64_t NN = (int64_t)N * N;
-  const __bf16* A = Ain + cell * NN + (int64_t)tr * kGTile * N;  // the tile's first row
-  const int KS = N / 16;
 
-  // staging: 256 rows x 64 k = 2048 chunks of 8 bf16, 4 per thread (rows
-  // t / 8 + 64 u, chunk t % 8), held in named registers between load and store
-  const int sr = t >> 3, sc8 = t & 7;
-  const __bf16* ag = A + (int64_t)sr * N + 8 * sc8;
-  const int64_t astep = (int64_t)64 * N;  // 64 rows further
-  __bf16* ls = lds + (size_t)sr * kGStr + 8 * sc8;
-  constexpr int lstep = 64 * kGStr;
-  uint4 s0, s1, s2, s3;
-#define COVG_LOAD(K0)                                                      \
-  {                                                                        \
-    s0 = *reinterpret_cast<const uint4*>(ag + (K0));                       \
-    s1 = *reinterpret_cast<const uint4*>(ag + astep + (K0));               \
-    s2 = *reinterpret_cast<const uint4*>(ag + 2 * astep + (K0));           \
-    s3 = *reinterpret_cast<const uint4*>(ag + 3 * astep + (K0));           \
-  }
-#define COVG_STORE(BUF)                                                    \
-  {                                                                        \
-    __bf16* d_ = ls + (size_t)(BUF) * kGTile * kGStr;                      \
-    *reinterpret_cast<uint4*>(d_) = s0;                                    \
-    *reinterpret_cast<uint4*>(d_ + lstep) = s1;                            \
-    *reinterpret_cast<uint4*>(d_ + 2 * lstep) = s2;                        \
-    *reinterpret_cast<uint4*>(d_ + 3 * lstep) = s3;                        \
+  for (int k = t; k < N; k += kGThreads) {
+    const int64_t o = cell * N + k;
+    const float a = vprev[NC + o], g = vprev[3 * NC + o];
+    s_alpha[k] = a;
+    s_g2[k] = g * g;
+    s_z[k] = a * vprev[o] + vprev[2 * NC + o];
   }
 
-  gv16f acc[2][4];
+  // ---- step 1: Out[i][j] = sum_k Chat[i][k] W[j][k], i < N, j in R
+  const int wi = wave % WI1, wj = wave / WI1;
+  const int i0w = wi * (PI * 32);        // the wave's first row i
+  const int j0w = R0 + wj * (PJ * 32);   // the wave's first neuron j
+  gv16f acc[PI][PJ];
 #pragma unroll
-  for (int r = 0; r < 2; ++r)
+  for (int c = 0; c < PI; ++c)
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
+    for (int p = 0; p < PJ; ++p)
 #pragma unroll
-      for (int e = 0; e < 16; ++e) acc[r][c][e] = 0.f;
+      for (int e = 0; e < 16; ++e) acc[c][p][e] = 0.f;
+  ggbf16x8* wfrag[PJ];
+#pragma unroll
+  for (int p = 0; p < PJ; ++p) wfrag[p] = (ggbf16x8*)(Wfr + ((int64_t)((j0w >> 5) + p) * KS * 64 + lane) * 8);
 
-  // the wave's two weight blocks, this lane's fragment of k-step 0
-  ggbf16x8* wfrag[2];
-#pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    const int wb = (col0 >> 5) + r;
-    wfrag[r] = (ggbf16x8*)(Wfr + ((int64_t)wb * KS * 64 + lane) * 8);
+  // staging: N rows x KC in pieces of 8 bfloat16, SPT per thread (rows
+  // t / P8 + u RSTEP, piece t % P8).  A chunk's pieces are loaded D chunks
+  // before the end of the chunk that stores them to LDS (one register set
+  // per chunk in flight), so that a load has D chunks of products to arrive.
+  constexpr int P8 = KC / 8, RSTEP = kGThreads / P8, SPT = S::SPT, D = S::D;
+  constexpr int NCH = N / KC, KK = KC / 16;
+  static_assert(NCH % D == 0 && D % 2 == 0, "staging ring");
+  const __bf16* ag = Cin + cell * NN + (int64_t)(t / P8) * N + 8 * (t % P8);
+  __bf16* ls = stage + (t / P8) * SSTR + 8 * (t % P8);
+  static_assert(SPT == 2 || SPT == 4, "pieces per thread");
+  uint4 a0, a1, a2, a3, b0, b1, b2, b3;  // register sets 0 (a) and 1 (b)
+#define COVG_LD1(R, U, K0) R = *reinterpret_cast<const uint4*>(ag + (int64_t)(U) * RSTEP * N + (K0));
+#define COVG_ST1(R, U, BUF) *reinterpret_cast<uint4*>(ls + (BUF) * N * SSTR + (U) * RSTEP * SSTR) = R;
+#define COVG_LOAD(R, K0)              \
+  {                                   \
+    COVG_LD1(R##0, 0, K0)             \
+    COVG_LD1(R##1, 1, K0)             \
+    if constexpr (SPT > 2) {          \
+      COVG_LD1(R##2, 2, K0)           \
+      COVG_LD1(R##3, 3, K0)           \
+    }                                 \
   }
-
-  COVG_LOAD(0);
-  COVG_STORE(0);
+#define COVG_STORE(R, BUF)            \
+  {                                   \
+    COVG_ST1(R##0, 0, BUF)            \
+    COVG_ST1(R##1, 1, BUF)            \
+    if constexpr (SPT > 2) {          \
+      COVG_ST1(R##2, 2, BUF)          \
+      COVG_ST1(R##3, 3, BUF)          \
+    }                                 \
+  }
+  // weight fragments of the chunk being multiplied (set u & 1); the next
+  // chunk's are loaded one chunk ahead
+  gbf16x8 wf[2][KK][PJ];
+#pragma unroll
+  for (int kk = 0; kk < KK; ++kk)
+#pragma unroll
+    for (int p = 0; p < PJ; ++p) wf[0][kk][p] = wfrag[p][64 * kk];
+  // chunk 0 to buffer 0; chunks 1 and 2 in flight in sets b and a
+  COVG_LOAD(a, 0);
+  COVG_STORE(a, 0);
+  COVG_LOAD(b, KC);
+  COVG_LOAD(a, 2 * KC);
   __syncthreads();
-  const int nch = N / kGK;
-  for (int ch = 0; ch < nch; ++ch) {
-    const int buf = ch & 1;
-    if (ch + 1 < nch) COVG_LOAD((ch + 1) * kGK);
-    gbf16x8 wf[4][2];
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-      for (int r = 0; r < 2; ++r) wf[kk][r] = wfrag[r][64 * (ch * 4 + kk)];
-    const __bf16* lb = lds + ((size_t)buf * kGTile + wr * kGRows + l32) * kGStr + 8 * hi;
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      gbf16x8 lf[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) lf[c] = *reinterpret_cast<const gbf16x8*>(lb + (size_t)c * 32 * kGStr + 16 * kk);
-#pragma unroll
-      for (int r = 0; r < 2; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lf[c], wf[kk][r], acc[r][c], 0, 0, 0);
-    }
-    // the other buffer was last read before the previous barrier
-    if (ch + 1 < nch) COVG_STORE(buf ^ 1);
-    __syncthreads();
+  // one chunk: ch = ch0 + U is in LDS buffer U & 1; NXT is the register
+  // set that holds chunk ch + 1 (D = 2: the two instances cover a period)
+#define COVG_CHUNK(U, NXT)                                                                            \
+  {                                                                                              \
+    const int ch = ch0 + (U);                                                                    \
+    if (ch + 1 < NCH) {                                                                          \
+      _Pragma("unroll") for (int kk = 0; kk < KK; ++kk)                                          \
+          _Pragma("unroll") for (int p = 0; p < PJ; ++p) wf[((U) + 1) & 1][kk][p] =              \
+              wfrag[p][64 * ((ch + 1) * KK + kk)];                                               \
+    }                                                                                            \
+    __builtin_amdgcn_sched_barrier(0); /* the loads stay ahead of this chunk's products */       \
+    const __bf16* lb = stage + ((size_t)((U) & 1) * N + i0w + l32) * SSTR + 8 * hi;              \
+    _Pragma("unroll") for (int kk = 0; kk < KK; ++kk) {                                          \
+      gbf16x8 lf[PI];                                                                            \
+      _Pragma("unroll") for (int c = 0; c < PI; ++c) lf[c] =                                     \
+          *reinterpret_cast<const gbf16x8*>(lb + (size_t)c * 32 * SSTR + 16 * kk);               \
+      _Pragma("unroll") for (int p = 0; p < PJ; ++p) _Pragma("unroll") for (int c = 0; c < PI; ++c) \
+          acc[c][p] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lf[c], wf[(U) & 1][kk][p], acc[c][p], 0, 0, 0); \
+    }                                                                                            \
+    /* chunk ch + 1 to the other buffer (last read before the previous                           \
+       barrier), then its register set takes chunk ch + 1 + D */                                 \
+    if (ch + 1 < NCH) {                                                                          \
+      COVG_STORE(NXT, ((U) + 1) & 1);                                                            \
+    }                                                                                            \
+    if (ch + 1 + D < NCH) {                                                                      \
+      COVG_LOAD(NXT, (ch + 1 + D) * KC);                                                         \
+    }                                                                                            \
+    __builtin_amdgcn_sched_barrier(0);                                                           \
+    __syncthreads();                                                                             \
   }
+  static_assert(D == 2, "two chunk instances per period");
+  for (int ch0 = 0; ch0 < NCH; ch0 += D) {
+    COVG_CHUNK(0, b);
+    COVG_CHUNK(1, a);
+  }
+#undef COVG_CHUNK
+#undef COVG_LD1
+#undef COVG_ST1
 #undef COVG_LOAD
 #undef COVG_STORE
 
-  // epilogue: block (r, c) holds Out[i][j], j = col0 + 32 r + l32 (the lane's
-  // column), i = row0 + 32 c + 8 q4 + 4 hi + (0..3) (register quad q4)
-  if (MODE == COVG_T || MODE == COVG_V) {
-    const int NP = 2 * tiles;
-    const int p = tr * 2 + wr;
+  // step-1 epilogue: block (c, p) holds Out[i][j], j = j0w + 32 p + l32 (the
+  // lane's neuron), i = i0w + 32 c + 8 q + 4 hi + (0..3) (register quad q);
+  // T[j][i] = alpha_i Out[i][j] + gamma_i^2 W[j][i] replaces the staging
+  // buffers (every wave passed the loop's last barrier)
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int j = col0 + 32 * r + l32;
-      const float* wrow = Wf + (int64_t)j * N;
-      float pv = 0.f, pa = 0.f;
+  for (int p = 0; p < PJ; ++p) {
+    const int j = j0w + 32 * p + l32;
+    // W[j][i..i+3] from the accumulator-quad copy: one 1 KiB run per wave
+    const float4* wq = Wq + ((int64_t)((j0w >> 5) + p) * (N / 32) + (i0w >> 5)) * 4 * 64 + lane;
+    float v = 0.f, mg = 0.f, y = 0.f;
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
+    for (int c = 0; c < PI; ++c)
 #pragma unroll
-        for (int q4 = 0; q4 < 4; ++q4) {
-          const int i0 = row0 + 32 * c + 8 * q4 + 4 * hi;
-          const float4 w4 = *reinterpret_cast<const float4*>(wrow + i0);
-          const float t0 = acc[r][c][4 * q4 + 0], t1 = acc[r][c][4 * q4 + 1];
-          const float t2 = acc[r][c][4 * q4 + 2], t3 = acc[r][c][4 * q4 + 3];
-          pv = fmaf(w4.x, t0, fmaf(w4.y, t1, fmaf(w4.z, t2, fmaf(w4.w, t3, pv))));
-          pa = fmaf(fabsf(w4.x), fabsf(t0),
-                    fmaf(fabsf(w4.y), fabsf(t1), fmaf(fabsf(w4.z), fabsf(t2), fmaf(fabsf(w4.w), fabsf(t3), pa))));
-          if (MODE == COVG_T)
-            *reinterpret_cast<uint2*>(Out + cell * NN + (int64_t)j * N + i0) = pack_bf16x4(t0, t1, t2, t3);
+      for (int q = 0; q < 4; ++q) {
+        const int i = i0w + 32 * c + 8 * q + 4 * hi;
+        const float4 w4 = wq[(c * 4 + q) * 64];
+        const float4 a4 = *reinterpret_cast<const float4*>(s_alpha + i);
+        const float4 g4 = *reinterpret_cast<const float4*>(s_g2 + i);
+        const float4 z4 = *reinterpret_cast<const float4*>(s_z + i);
+        const float t0 = fmaf(a4.x, acc[c][p][4 * q + 0], g4.x * w4.x);
+        const float t1 = fmaf(a4.y, acc[c][p][4 * q + 1], g4.y * w4.y);
+        const float t2 = fmaf(a4.z, acc[c][p][4 * q + 2], g4.z * w4.z);
+        const float t3 = fmaf(a4.w, acc[c][p][4 * q + 3], g4.w * w4.w);
+        v = fmaf(w4.x, t0, fmaf(w4.y, t1, fmaf(w4.z, t2, fmaf(w4.w, t3, v))));
+        mg = fmaf(fabsf(w4.x), fabsf(t0),
+                  fmaf(fabsf(w4.y), fabsf(t1), fmaf(fabsf(w4.z), fabsf(t2), fmaf(fabsf(w4.w), fabsf(t3), mg))));
+        y = fmaf(w4.x, z4.x, fmaf(w4.y, z4.y, fmaf(w4.z, z4.z, fmaf(w4.w, z4.w, y))));
+        if (!LAST) *reinterpret_cast<uint2*>(Tl + (size_t)(j - R0) * TSTR + i) = pack_bf16x4(t0, t1, t2, t3);
+      }
+    v += __shfl_xor(v, 32);
+    mg += __shfl_xor(mg, 32);
+    y += __shfl_xor(y, 32);
+    if (hi == 0) {
+      pv[wi * RB + (j - R0)] = v;
+      pm[wi * RB + (j - R0)] = mg;
+      py[wi * RB + (j - R0)] = y;
+    }
+  }
+  __syncthreads();
+
+  // ---- step 2: the rule for the workgroup's neurons
+  if (t < RB) {
+    const int j = R0 + t;
+    float v = 0.f, av = 0.f, y = 0.f;
+#pragma unroll
+    for (int w = 0; w < WI1; ++w) {
+      v += pv[w * RB + t];
+      av += pm[w * RB + t];
+      y += py[w * RB + t];
+    }
+    y += bias[j];
+    if (cancel && av > 0.f && !(v > kGCancelRatio * av)) {
+      const float s6 = 6.f * sqrtf(fmaxf(v, 0.f) + 0x1p-7f * av);
+      const bool dep = ACT == ISX_SINE ? (1.f + 2.f * fabsf(y)) * 0x1p-9f * av > 0x1p-20f
+                                       : (ACT == ISX_ELU ? y < s6 : fabsf(y) < s6);
+      if (dep) cancel[cell] = 1u;
+    }
+    float a, b, g;
+    apply_rule<float, ISX_UP>(ACT, y, v, a, b, g);
+    const int64_t o = cell * N + j;
+    vcur[o] = y;
+    vcur[NC + o] = a;
+    vcur[2 * NC + o] = b;
+    vcur[3 * NC + o] = g;
+    s_ac[t] = a;
+    s_vc[t] = v;
+  }
+  if (LAST) return;
+  __syncthreads();
+
+  // ---- step 3: C[j][m] = sum_i T[j][i] W[m][i], j in R, m < N
+  const int wj3 = wave / WM3, wm = wave % WM3;
+  const int jl0 = wj3 * (QJ * 32);  // the wave's first local neuron
+  const int m0 = wm * (QM * 32);    // its first column m
+  gv16f acc3[QJ][QM];
+#pragma unroll
+  for (int c = 0; c < QJ; ++c)
+#pragma unroll
+    for (int q = 0; q < QM; ++q)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc3[c][q][e] = 0.f;
+  ggbf16x8* bfr[QM];
+#pragma unroll
+  for (int q = 0; q < QM; ++q) bfr[q] = (ggbf16x8*)(Wfr + ((int64_t)((m0 >> 5) + q) * KS * 64 + lane) * 8);
+  const __bf16* ta = Tl + (size_t)(jl0 + l32) * TSTR + 8 * hi;
+  // weight fragments in a ring of PD k-steps, each slot reloaded PD k-steps
+  // ahead of its use
+  constexpr int PD = QM > 2 ? 2 : 4;
+  static_assert(KS % PD == 0, "ring");
+  gbf16x8 ring[PD][QM];
+#pragma unroll
+  for (int d = 0; d < PD; ++d)
+#pragma unroll
+    for (int q = 0; q < QM; ++q) ring[d][q] = bfr[q][64 * d];
+  for (int k0 = 0; k0 < KS; k0 += PD) {
+#pragma unroll
+    for (int d = 0; d < PD; ++d) {
+      const int ks = k0 + d;
+      gbf16x8 af[QJ], bq[QM];
+#pragma unroll
+      for (int c = 0; c < QJ; ++c) af[c] = *reinterpret_cast<const gbf16x8*>(ta + (size_t)c * 32 * TSTR + 16 * ks);
+#pragma unroll
+      for (int q = 0; q < QM; ++q) bq[q] = ring[d][q];
+      if (ks + PD < KS) {
+#pragma unroll
+        for (int q = 0; q < QM; ++q) ring[d][q] = bfr[q][64 * (ks + PD)];
+      }
+      // keep the reloads here: the scheduler would otherwise sink them to
+      // their use PD k-steps later and expose the L2 latency
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int q = 0; q < QM; ++q)
+#pragma unroll
+        for (int c = 0; c < QJ; ++c) acc3[c][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[c], bq[q], acc3[c][q], 0, 0, 0);
+    }
+  }
+
+  // step-3 epilogue: block (c, q) holds C[j][m], m = m0 + 32 q + l32, local
+  // j = jl0 + 32 c + 8 r + 4 hi + (0..3) (quad r).  Chat[m][j] = alpha_j C[j][m]
+  // (C is symmetric; the diagonal alpha_j v_j) goes through LDS, where T_R
+  // was, as the tile Ct[m][jl] (N x RB, 16-byte slots of each row XOR-swizzled
+  // by the row), and leaves as contiguous 16-byte pieces of the rows of Chat.
+  constexpr int SLOTS = RB / 8;
+  __bf16* Ct = reinterpret_cast<__bf16*>(base);
+  __syncthreads();  // every wave has finished reading T_R
+#pragma unroll
+  for (int c = 0; c < QJ; ++c)
+#pragma unroll
+    for (int q = 0; q < QM; ++q) {
+      const int m = m0 + 32 * q + l32;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int jl = jl0 + 32 * c + 8 * r + 4 * hi;
+        const float4 a4 = *reinterpret_cast<const float4*>(s_ac + jl);
+        float x0 = a4.x * acc3[c][q][4 * r + 0], x1 = a4.y * acc3[c][q][4 * r + 1];
+        float x2 = a4.z * acc3[c][q][4 * r + 2], x3 = a4.w * acc3[c][q][4 * r + 3];
+        const int d = m - (R0 + jl);
+        if (d >= 0 && d < 4) {
+          const float dv = s_ac[jl + d] * s_vc[jl + d];
+          x0 = d == 0 ? dv : x0;
+          x1 = d == 1 ? dv : x1;
+          x2 = d == 2 ? dv : x2;
+          x3 = d == 3 ? dv : x3;
         }
-      pv += __shfl_xor(pv, 32);
-      pa += __shfl_xor(pa, 32);
-      if (hi == 0) {
-        part[(cell * NP + p) * N + j] = pv;
-        partm[(cell * NP + p) * N + j] = pa;
+        const int slot = (jl >> 3) ^ (m & (SLOTS - 1));
+        *reinterpret_cast<uint2*>(Ct + (size_t)m * RB + slot * 8 + (jl & 7)) = pack_bf16x4(x0, x1, x2, x3);
       }
     }
-  } else {
-    const float* al = alpha + cell * N;
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int j = col0 + 32 * r + l32;
-      const float aj = al[j];
-#pragma unroll
-      for (int c = 0; c < 4; ++c)
-#pragma unroll
-        for (int q4 = 0; q4 < 4; ++q4) {
-          const int i0 = row0 + 32 * c + 8 * q4 + 4 * hi;
-          const float4 ai = *reinterpret_cast<const float4*>(al + i0);
-          float x0 = ai.x * aj * acc[r][c][4 * q4 + 0], x1 = ai.y * aj * acc[r][c][4 * q4 + 1];
-          float x2 = ai.z * aj * acc[r][c][4 * q4 + 2], x3 = ai.w * aj * acc[r][c][4 * q4 + 3];
-          if (j >= i0 && j < i0 + 4) {
-            // the diagonal from the variance the rule used
-            const float g = gamma[cell * N + j];
-            const float d = aj * aj * var[cell * N + j] + g * g;
-            const int e = j - i0;
-            x0 = e == 0 ? d : x0;
-            x1 = e == 1 ? d : x1;
-            x2 = e == 2 ? d : x2;
-            x3 = e == 3 ? d : x3;
-          }
-          *reinterpret_cast<uint2*>(Out + cell * NN + (int64_t)j * N + i0) = pack_bf16x4(x0, x1, x2, x3);
-        }
-    }
+  __syncthreads();
+  __bf16* Co = Cout + cell * NN + R0;
+#pragma unroll 4
+  for (int pidx = t; pidx < N * SLOTS; pidx += kGThreads) {
+    const int m = pidx / SLOTS, sl = pidx - m * SLOTS;
+    const uint4 v = *reinterpret_cast<const uint4*>(Ct + (size_t)m * RB + ((sl ^ (m & (SLOTS - 1))) * 8));
+    *reinterpret_cast<uint4*>(Co + (int64_t)m * N + sl * 8) = v;
   }
 }
 
-// Layer 1 of each cell: the rule per neuron (y = W_1 c + b_1, variance
-// |W_1[j] diag(h / sqrt 3)|^2), the layer's (y, alpha, beta, gamma), and
-// X_1 = G G^T + diag(gamma^2) with G = D_1 W_1 diag(h / sqrt 3), bfloat16.
+// Layer 1 of each cell: the rule per neuron (y = W_1 c + b_1, v = |F_j|^2
+// with F = W_1 diag(h / sqrt 3)), the layer's (y, alpha, beta, gamma), and
+// Chat_1[i][k] = alpha_k F_i . F_k (bfloat16).
 template <int ACT>
 __global__ __launch_bounds__(kGThreads) void covg_layer1_kernel(int64_t C, int N, const float* __restrict__ W1,
                                                                  const float* __restrict__ b1,
                                                                  const float* __restrict__ centres,
                                                                  const float* __restrict__ halves,
-                                                                 float* __restrict__ vec, __bf16* __restrict__ X,
+                                                                 float* __restrict__ vec, __bf16* __restrict__ Cout,
                                                                  uint32_t* __restrict__ cancel) {
-  extern __shared__ float4 covg_l1[];  // [N]: (G_j, gamma_j^2)
+  extern __shared__ float4 covg_l1[];  // [N]: (F_j, alpha_j)
   const int64_t cell = blockIdx.x;
   if (cell >= C) return;
   const int t = threadIdx.x;
@@ -248,7 +432,7 @@ __global__ __launch_bounds__(kGThreads) void covg_layer1_kernel(int64_t C, int N
     const float f0 = w0 * hx, f1 = w1 * hy, f2 = w2 * hz;
     float a, b, g;
     apply_rule<float, ISX_UP>(ACT, y, f0 * f0 + f1 * f1 + f2 * f2, a, b, g);
-    covg_l1[j] = make_float4(a * f0, a * f1, a * f2, g * g);
+    covg_l1[j] = make_float4(f0, f1, f2, a);
     const int64_t o = cell * N + j;
     vec[o] = y;
     vec[NC + o] = a;
@@ -257,78 +441,19 @@ __global__ __launch_bounds__(kGThreads) void covg_layer1_kernel(int64_t C, int N
   }
   if (t == 0 && cancel) cancel[cell] = 0u;
   __syncthreads();
-  // X_1 rows: 8 consecutive entries per thread and step (one 16-byte store)
+  // rows of Chat_1: 8 consecutive entries per thread and step (one 16-byte store)
   const int per_row = N / 8;
-  __bf16* Xc = X + cell * (int64_t)N * N;
+  __bf16* Cc = Cout + cell * (int64_t)N * N;
   for (int idx = t; idx < N * per_row; idx += kGThreads) {
     const int i = idx / per_row, k0 = 8 * (idx - i * per_row);
-    const float4 gi = covg_l1[i];
+    const float4 fi = covg_l1[i];
     gbf16x8 v;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      const float4 gk = covg_l1[k0 + e];
-      float x = gi.x * gk.x + gi.y * gk.y + gi.z * gk.z;
-      if (k0 + e == i) x += gi.w;
-      v[e] = (__bf16)x;
+      const float4 fk = covg_l1[k0 + e];
+      v[e] = (__bf16)(fk.w * (fi.x * fk.x + fi.y * fk.y + fi.z * fk.z));
     }
-    *reinterpret_cast<gbf16x8*>(Xc + (int64_t)i * N + k0) = v;
-  }
-}
-
-// A variance sum is flagged when it keeps at most this fraction of the
-// summed magnitude of its terms (as in the LDS kernel).
-constexpr float kGCancelRatio = 0x1p-9f;
-
-// Layer h >= 2 of each cell: the variance from the partial sums (fixed
-// order), the float32 centre y = W z + b with z = alpha . y_{h-1} + beta
-// (one wave per row, lanes across k, a butterfly sum), the rule, and the
-// layer's (y, alpha, beta, gamma) and variance.
-template <int ACT>
-__global__ __launch_bounds__(kGThreads) void covg_rule_kernel(int64_t C, int N, int NP, const float* __restrict__ W,
-                                                               const float* __restrict__ bias,
-                                                               const float* __restrict__ vprev,
-                                                               float* __restrict__ vcur,
-                                                               const float* __restrict__ part,
-                                                               const float* __restrict__ partm,
-                                                               float* __restrict__ var, uint32_t* __restrict__ cancel) {
-  extern __shared__ float covg_z[];  // [N]
-  const int64_t cell = blockIdx.x;
-  if (cell >= C) return;
-  const int t = threadIdx.x, lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
-  const int64_t NC = (int64_t)N * C;
-  for (int k = t; k < N; k += kGThreads) {
-    const int64_t o = cell * N + k;
-    covg_z[k] = vprev[NC + o] * vprev[o] + vprev[2 * NC + o];
-  }
-  __syncthreads();
-  for (int j = wave; j < N; j += kGThreads / 64) {
-    const float* wrow = W + (int64_t)j * N;
-    float s = 0.f;
-    for (int k = lane; k < N; k += 64) s = fmaf(wrow[k], covg_z[k], s);
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if (lane == 0) {
-      float v = 0.f, av = 0.f;
-      for (int p = 0; p < NP; ++p) {
-        v += part[(cell * NP + p) * N + j];
-        av += partm[(cell * NP + p) * N + j];
-      }
-      const float y = s + bias[j];
-      if (cancel && av > 0.f && !(v > kGCancelRatio * av)) {
-        const float s6 = 6.f * sqrtf(fmaxf(v, 0.f) + 0x1p-7f * av);
-        const bool dep = ACT == ISX_SINE ? (1.f + 2.f * fabsf(y)) * 0x1p-9f * av > 0x1p-20f
-                                         : (ACT == ISX_ELU ? y < s6 : fabsf(y) < s6);
-        if (dep) cancel[cell] = 1u;
-      }
-      float a, b, g;
-      apply_rule<float, ISX_UP>(ACT, y, v, a, b, g);
-      const int64_t o = cell * N + j;
-      vcur[o] = y;
-      vcur[NC + o] = a;
-      vcur[2 * NC + o] = b;
-      vcur[3 * NC + o] = g;
-      var[o] = v;
-    }
+    *reinterpret_cast<gbf16x8*>(Cc + (int64_t)i * N + k0) = v;
   }
 }
 
@@ -340,23 +465,23 @@ int covg_width(const Model& m) {
   for (int h = 1; h < m.n_linear; ++h)
     if (m.pw[h] != n) return 0;
   for (int l = 1; l + 1 < m.n_linear; ++l)
-    if (!m.L[l].Wfr) return 0;
-  return (n % kGTile == 0 && n <= ISX_MAX_WIDTH) ? n : 0;
+    if (!m.L[l].Wfr || !m.L[l].Wq) return 0;
+  return (n == 256 || n == 512 || n == 1024) ? n : 0;
 }
 
 size_t covg_scratch_bytes(const Model& m, int64_t C) {
   const int N = covg_width(m);
   if (!N) return 0;
-  const int NP = 2 * (N / kGTile);
-  // X and T (bfloat16), the partial sums and magnitudes, the variances
-  return (size_t)C * ((size_t)2 * N * N * 2 + (size_t)2 * NP * N * 4 + (size_t)N * 4);
+  // Chat of two consecutive layers (bfloat16)
+  return (size_t)C * 2 * N * N * 2;
 }
 
 int64_t covg_max_chunk(const Model& m) {
   const int N = covg_width(m);
   if (!N) return 0;
-  const int64_t tiles = N / kGTile;
-  return ((int64_t)1 << 22) / (tiles * tiles);
+  // (C + 7) N / RB blocks of 512 threads stay below 2^22 blocks
+  const int64_t nr = (int64_t)N * N / 65536;
+  return (((int64_t)1 << 22) / nr) - 8;
 }
 
 double covg_flops_per_cell(const Model& m) {
@@ -368,67 +493,63 @@ double covg_flops_per_cell(const Model& m) {
   return 2.0 * n3 * (Lh - 1) + 2.0 * n3 * std::max(0, Lh - 2) + 2.0 * (double)N * N * Lh;
 }
 
-template <int ACT>
+template <int N, int ACT>
 static hipError_t covg_run(const Model& m, int64_t C, const float* centres, const float* halves, float* vec,
                            uint32_t* cancel, void* scratch, hipStream_t s) {
-  const int N = covg_width(m);
-  const int tiles = N / kGTile, NP = 2 * tiles;
+  using S = CovgShape<N>;
   const int64_t NN = (int64_t)N * N;
   const int Lh = m.n_linear - 1;
-  __bf16* X = reinterpret_cast<__bf16*>(scratch);
-  __bf16* T = X + C * NN;
-  float* part = reinterpret_cast<float*>(T + C * NN);
-  float* partm = part + C * NP * N;
-  float* var = partm + C * NP * N;
-  // the gemm's grid: C tiles^2 blocks of 512 threads, at most 2^31 work-items
   if (C > covg_max_chunk(m)) return hipErrorInvalidValue;
+  __bf16* Cb[2] = {reinterpret_cast<__bf16*>(scratch), reinterpret_cast<__bf16*>(scratch) + C * NN};
   {
-    hipError_t e = ensure_lds_limit(reinterpret_cast<const void*>(&covg_gemm_kernel<COVG_T>), (int)kGLds);
-    if (e == hipSuccess) e = ensure_lds_limit(reinterpret_cast<const void*>(&covg_gemm_kernel<COVG_V>), (int)kGLds);
-    if (e == hipSuccess) e = ensure_lds_limit(reinterpret_cast<const void*>(&covg_gemm_kernel<COVG_X>), (int)kGLds);
+    hipError_t e = ensure_lds_limit(reinterpret_cast<const void*>(&covg_layer_kernel<N, ACT, false>), (int)S::LDS);
+    if (e == hipSuccess)
+      e = ensure_lds_limit(reinterpret_cast<const void*>(&covg_layer_kernel<N, ACT, true>), (int)S::LDS);
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL((covg_layer1_kernel<ACT>), dim3((unsigned)C), dim3(kGThreads), (size_t)N * sizeof(float4), s, C,
-                     N, m.L[0].W, m.L[0].b, centres, halves, vec, X, cancel);
+                     N, m.L[0].W, m.L[0].b, centres, halves, vec, Cb[0], cancel);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const float* vprev = vec;
-  float* vcur = vec + 4 * NN / N * C;  // 4 N C floats per layer
-  const dim3 grid((unsigned)(C * tiles * tiles));
+  const dim3 grid((unsigned)(((C + 7) / 8) * 8 * S::NR));
+  const int64_t layer = 4 * (int64_t)N * C;  // floats of one layer's vectors
   for (int h = 2; h <= Lh; ++h) {
     const Layer& L = m.L[h - 1];
     const __bf16* Wfr = reinterpret_cast<const __bf16*>(L.Wfr);
-    const bool last = h == Lh;
-    if (last)
-      hipLaunchKernelGGL(covg_gemm_kernel<COVG_V>, grid, dim3(kGThreads), kGLds, s, C, N, X, Wfr, L.W, (__bf16*)nullptr,
-                         part, partm, (const float*)nullptr, (const float*)nullptr, (const float*)nullptr);
+    const __bf16* cin = Cb[(h - 2) & 1];
+    __bf16* cout = Cb[(h - 1) & 1];
+    const float* vprev = vec + (h - 2) * layer;
+    float* vcur = vec + (h - 1) * layer;
+    if (h == Lh)
+      hipLaunchKernelGGL((covg_layer_kernel<N, ACT, true>), grid, dim3(kGThreads), S::LDS, s, C, cin, cout, Wfr,
+                         reinterpret_cast<const float4*>(L.Wq), L.b, vprev, vcur, cancel);
     else
-      hipLaunchKernelGGL(covg_gemm_kernel<COVG_T>, grid, dim3(kGThreads), kGLds, s, C, N, X, Wfr, L.W, T, part, partm,
-                         (const float*)nullptr, (const float*)nullptr, (const float*)nullptr);
+      hipLaunchKernelGGL((covg_layer_kernel<N, ACT, false>), grid, dim3(kGThreads), S::LDS, s, C, cin, cout, Wfr,
+                         reinterpret_cast<const float4*>(L.Wq), L.b, vprev, vcur, cancel);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL((covg_rule_kernel<ACT>), dim3((unsigned)C), dim3(kGThreads), (size_t)N * sizeof(float), s, C, N,
-                       NP, L.W, L.b, vprev, vcur, part, partm, var, cancel);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (!last) {
-      const int64_t NC = (int64_t)N * C;
-      hipLaunchKernelGGL(covg_gemm_kernel<COVG_X>, grid, dim3(kGThreads), kGLds, s, C, N, T, Wfr, L.W, X,
-                         (float*)nullptr, (float*)nullptr, vcur + NC, vcur + 3 * NC, var);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    vprev = vcur;
-    vcur += 4 * (int64_t)N * C;
   }
   return hipSuccess;
+}
+
+template <int N>
+static hipError_t covg_run_n(const Model& m, int64_t C, const float* centres, const float* halves, float* vec,
+                             uint32_t* cancel, void* scratch, hipStream_t s) {
+  switch (m.act) {
+    case ISX_SINE: return covg_run<N, ISX_SINE>(m, C, centres, halves, vec, cancel, scratch, s);
+    case ISX_ELU: return covg_run<N, ISX_ELU>(m, C, centres, halves, vec, cancel, scratch, s);
+    default: return covg_run<N, ISX_RELU>(m, C, centres, halves, vec, cancel, scratch, s);
+  }
 }
 
 hipError_t launch_up_cov_global(const Model& m, int64_t C, const float* centres, const float* halves, float* vec,
                                 uint32_t* cancel, void* scratch, hipStream_t s) {
   if (C <= 0) return hipSuccess;
-  if (!covg_width(m) || !scratch) return hipErrorInvalidValue;
-  switch (m.act) {
-    case ISX_SINE: return covg_run<ISX_SINE>(m, C, centres, halves, vec, cancel, scratch, s);
-    case ISX_ELU: return covg_run<ISX_ELU>(m, C, centres, halves, vec, cancel, scratch, s);
-    default: return covg_run<ISX_RELU>(m, C, centres, halves, vec, cancel, scratch, s);
+  if (!scratch) return hipErrorInvalidValue;
+  switch (covg_width(m)) {
+    case 256: return covg_run_n<256>(m, C, centres, halves, vec, cancel, scratch, s);
+    case 512: return covg_run_n<512>(m, C, centres, halves, vec, cancel, scratch, s);
+    case 1024: return covg_run_n<1024>(m, C, centres, halves, vec, cancel, scratch, s);
+    default: return hipErrorInvalidValue;
   }
 }
 
