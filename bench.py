@@ -43,6 +43,17 @@ HIDDEN_KINDS = {
     "hidden_cov_bf16": ("up_cov_bf16_kernel", "kernels_cov.hip", "bf16", "covariance"),
     "hidden_fp64": ("hidden_mfma_f64_kernel", "kernels_mfma64.hip", "fp64", "coefficient"),
 }
+# the covariance form with the per-cell matrices in device memory (hidden
+# widths 512 and 1024) reports under the same kind
+COV_GLOBAL = ("covg_layer_kernel", "kernels_covg.hip", "bf16", "covariance (device memory)")
+
+
+def kind_info(kind: str, widths) -> tuple:
+    """(kernel, source file, dtype, formulation) of a hidden-layer kind for a
+    net: the covariance kind runs in device memory above width 256."""
+    if kind == "hidden_cov_bf16" and max(widths[1:-1]) > 256:
+        return COV_GLOBAL
+    return HIDDEN_KINDS[kind]
 
 
 def alg_flops_coefficient(widths):
@@ -79,18 +90,18 @@ def alg_flops_cov_hybrid(widths):
     return f
 
 
-def kernel_source_hash(kind: str) -> str:
-    src = ROOT / "paper_2402_13861_amd" / "csrc" / HIDDEN_KINDS[kind][1]
+def kernel_source_hash(kind: str, src_name: str = None) -> str:
+    src = ROOT / "paper_2402_13861_amd" / "csrc" / (src_name or HIDDEN_KINDS[kind][1])
     return hashlib.sha256(src.read_bytes()).hexdigest()[:16]
 
 
-def traffic_from_profiles(kind: str, cells_per_launch: float):
+def traffic_from_profiles(kind: str, cells_per_launch: float, src_name: str = None):
     """HBM bytes per launch of the dominant kernel: the committed rocprofv3
     counter summary's bytes per propagated cell (all hidden-layer launches of
     a cell; taken on the current kernel source, else None) times the
     propagated cells per launch of this run (propagated cells / launches)."""
     f = ROOT / "profiles" / f"{kind}_traffic.json"
-    if not f.exists():
+    if not f.exists() or (src_name and src_name != HIDDEN_KINDS[kind][1]):
         return None
     t = json.loads(f.read_text())
     if t.get("kernel_source_sha256_16") != kernel_source_hash(kind):
@@ -779,7 +790,8 @@ def main(argv=None):
     rechecked = sum(l["rechecked"] for l in levels)
     rechecked64 = sum(l["rechecked_fp64"] for l in levels)
     per_kernel = {}
-    for kname, (kern, src, dt, form) in HIDDEN_KINDS.items():
+    for kname in HIDDEN_KINDS:
+        kern, src, dt, form = kind_info(kname, mlp.widths)
         v = prof[kname]
         if not v["launches"] or v["ms"] <= 0:
             continue
@@ -807,12 +819,13 @@ def main(argv=None):
     alg_per_launch = pk["alg_flops_per_step"] * K / launches
     cells_kind = rechecked64 if kind == "hidden_fp64" else propagated
     cells_per_launch = cells_kind / (kp["launches"] / K) if kp["launches"] else 0.0
-    traffic = traffic_from_profiles(kind, cells_per_launch)
+    kinfo = kind_info(kind, mlp.widths)
+    traffic = traffic_from_profiles(kind, cells_per_launch, kinfo[1])
     roofline = {
         "bound": "mfma",
-        "kernel": HIDDEN_KINDS[kind][0],
+        "kernel": kinfo[0],
         "achieved": round(alg_per_launch / (avg_ms * 1e-3) / 1e12, 3),
-        "peak": PEAK_TFLOPS[HIDDEN_KINDS[kind][2]],
+        "peak": PEAK_TFLOPS[kinfo[2]],
         "unit": "TFLOP/s",
         "frac": pk["frac"],
         "traffic": traffic,

@@ -559,11 +559,12 @@ typedef enum {
                               currently return ISX_EUNSUPPORTED */
   ISX_UP_FORM = 7,         /* bf16 uncertainty propagation: 0 (default) = covariance form (exact
                               alternative to coefficient tracking: C_h = W_h (D C_{h-1} D + diag(gamma^2))
-                              W_h^T) on chip, one fused launch per batch, for hidden widths <= 256, else
-                              the coefficient form; 1 = coefficient form; 2 = covariance form with the
-                              per-cell N x N matrices in device memory (three launches per layer) for nets
-                              whose hidden layers share one width that is a multiple of 256 up to 1024
-                              (ISX_EUNSUPPORTED for other nets) */
+                              W_h^T): on chip, one fused launch per batch, for hidden widths <= 256; with
+                              the per-cell N x N matrices in device memory, one launch per layer, for nets
+                              whose hidden layers all have width 512 or 1024; else the coefficient form.
+                              1 = coefficient form; 2 = the device-memory covariance form for nets whose
+                              hidden layers share one width of 256, 512 or 1024 (ISX_EUNSUPPORTED for
+                              other nets) */
   ISX_LIN_PRECISION = 8,   /* centre linearisation (isx_linearize and the surrogate's base): 1 (default)
                               = bfloat16 MFMA with every column carried as two bfloat16 parts and three
                               bfloat16 products per layer (f within ~3e-4 of max(|f|, output scale), s
@@ -624,8 +625,8 @@ typedef enum {
   ISX_KERNEL_DENSE = 4,            /* dense forward passes (corner evaluation, linearisation) */
   ISX_KERNEL_OUTPUT = 5,           /* output read-off (spread of the last layer) */
   ISX_KERNEL_HIDDEN_COV_BF16 = 6,  /* every hidden layer of uncertainty propagation in covariance form,
-                                      BF16 MFMA (ISX_UP_FORM 0 or 2; the device-memory form's launches
-                                      of one chunk count as one) */
+                                      BF16 MFMA (on chip or in device memory; the device-memory form's
+                                      launches of one chunk count as one) */
   ISX_KERNEL_LINEARIZE = 7         /* centre linearisation (isx_linearize, the surrogate's base) */
 } isx_kernel_kind;
 

@@ -375,10 +375,11 @@ isx_status run_propagate(isx_ctx* ctx, const Model& m, isx_method method, isx_pr
   }
   if (prec == ISX_BF16) {
     // UP in covariance form: on chip (hidden widths <= 256), or with the
-    // per-cell matrices in global memory (ISX_UP_FORM = 2; uniform widths
-    // that are multiples of 256)
+    // per-cell matrices in device memory (one hidden width of 512 or 1024 by
+    // default; ISX_UP_FORM = 2 also at 256)
     const bool cov = method == ISX_UP && ctx->up_form == 0 && cov_supported(m);
-    const bool covg = method == ISX_UP && !marg && ctx->up_form == 2 && covg_width(m);
+    const bool covg = method == ISX_UP && !marg && covg_width(m) &&
+                      ((ctx->up_form == 0 && !cov_supported(m)) || ctx->up_form == 2);
     if (method == ISX_UP && ctx->up_form == 2 && !covg)
       return fail(ctx, ISX_EUNSUPPORTED,
                   "ISX_UP_FORM 2 needs hidden layers of one width, a multiple of 256 up to 1024");

@@ -453,9 +453,9 @@ def test_cov_propagate_past_one_grid(ctx):
 
 @pytest.mark.parametrize("mname", ["up", "aa"])
 def test_bf16_width_512_against_oracle(ctx, mname):
-    """Hidden width 512 (the coefficient kernel's K = 512 tiles, 3->512x3->1):
-    BF16 bounds within the BF16 tolerance of max(|o|, S); the float32 path
-    within 1e-5."""
+    """Hidden width 512 (3->512x3->1; UP in the device-memory covariance
+    form, AA on the coefficient kernel's K = 512 tiles): BF16 bounds within
+    the BF16 tolerance of max(|o|, S); the float32 path within 1e-5."""
     import paper_2402_13861_amd as isx
 
     method, gm = METHODS[mname]
@@ -476,17 +476,22 @@ def test_bf16_width_512_against_oracle(ctx, mname):
 
 
 def test_bf16_unsupported_width_reports_error(ctx):
+    """BF16 needs every hidden layer's input width <= 512 (coefficient
+    kernels) or, for UP, one hidden width of 512 or 1024 (device-memory
+    covariance form): AA at width 1024 and UP on 3->1024->512->1 report
+    ISX_EUNSUPPORTED."""
     import paper_2402_13861_amd as isx
 
-    mlp = he_normal_mlp([3, 1024, 1024, 1], seed=0)
-    mid = ctx.load_weights(mlp)
-    try:
-        c, h, _ = random_boxes(4, [3], seed=1)
-        with pytest.raises(isx.IsxError) as e:
-            _gpu_prop(ctx, mid, isx.UP, isx.BF16, c, h)
-        assert e.value.status == -7
-    finally:
-        ctx.unload_mlp(mid)
+    c, h, _ = random_boxes(4, [3], seed=1)
+    for widths, method in (([3, 1024, 1024, 1], isx.AA), ([3, 1024, 512, 1], isx.UP)):
+        mlp = he_normal_mlp(widths, seed=0)
+        mid = ctx.load_weights(mlp)
+        try:
+            with pytest.raises(isx.IsxError) as e:
+                _gpu_prop(ctx, mid, method, isx.BF16, c, h)
+            assert e.value.status == -7
+        finally:
+            ctx.unload_mlp(mid)
 
 
 @pytest.mark.parametrize("prec_name", ["fp32", "bf16"])
