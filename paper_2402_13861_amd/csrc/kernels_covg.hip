@@ -79,6 +79,9 @@ struct CovgShape {
   static constexpr size_t PART = (size_t)3 * WI1 * RB * 4;          // partial sums
   static constexpr size_t VECS = (size_t)(3 * N + 2 * RB) * 4;
   static constexpr size_t LDS = REGION + PART + VECS;
+  // layer 2 in rank-3 form: F and alpha of layer 1 and P after the vectors
+  static constexpr size_t LDS_FIRST = LDS + (size_t)(N + RB) * 16;
+  static constexpr bool RANK3 = LDS_FIRST <= 160 * 1024;  // widths 256 and 512
   static_assert(PI * WI1 * 32 == N && PJ * WJ1 * 32 == RB, "step-1 tiling");
   static_assert(QJ * WJ3 * 32 == RB && QM * WM3 * 32 == N, "step-3 tiling");
   static_assert(LDS <= 160 * 1024, "LDS");
@@ -105,11 +108,18 @@ constexpr float kGCancelRatio = 0x1p-9f;
 // Layer h >= 2: steps 1-3 above for the RB neurons of one workgroup.
 // vprev / vcur: the (y, alpha, beta, gamma) blocks of layers h-1 and h
 // ([4][C][N] floats each); Cin / Cout: Chat of layers h-1 and h ([C][N][N]).
-template <int N, int ACT, bool LAST>
+// FIRST (layer 2, where X_1 = D_1 F F^T D_1 + diag(gamma_1^2) has rank 3
+// plus a diagonal): step 1's product is Out[i][j] = F_i . P_j with
+// P_j = sum_k W[j][k] alpha_k F_k, formed on the vector ALUs from the cell's
+// box and W_1 (Chat_1 is never stored); W is W_h row-major.
+template <int N, int ACT, bool LAST, bool FIRST>
 __global__ __launch_bounds__(kGThreads) void covg_layer_kernel(int64_t C, const __bf16* __restrict__ Cin,
                                                                 __bf16* __restrict__ Cout,
                                                                 const __bf16* __restrict__ Wfr,
                                                                 const float4* __restrict__ Wq,
+                                                                const float* __restrict__ W,
+                                                                const float* __restrict__ W1,
+                                                                const float* __restrict__ halves,
                                                                 const float* __restrict__ bias,
                                                                 const float* __restrict__ vprev,
                                                                 float* __restrict__ vcur,
@@ -162,6 +172,44 @@ __global__ __launch_bounds__(kGThreads) void covg_layer_kernel(int64_t C, const 
     for (int p = 0; p < PJ; ++p)
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc[c][p][e] = 0.f;
+  if constexpr (FIRST) {
+    // F_k (three arrays) and alpha_k of layer 1 and P_j for the workgroup's
+    // neurons, after the vectors (the staging region becomes T_R)
+    float* s_Fx = s_vc + RB;  // [N] each
+    float* s_Fy = s_Fx + N;
+    float* s_Fz = s_Fy + N;
+    float* s_Fa = s_Fz + N;
+    float4* s_P = reinterpret_cast<float4*>(s_Fa + N);  // [RB]
+    const float sc = 0.57735026918962576451f;
+    const float hx = halves[cell * 3 + 0] * sc, hy = halves[cell * 3 + 1] * sc, hz = halves[cell * 3 + 2] * sc;
+    for (int k = t; k < N; k += kGThreads) {
+      s_Fx[k] = W1[k * 3 + 0] * hx;
+      s_Fy[k] = W1[k * 3 + 1] * hy;
+      s_Fz[k] = W1[k * 3 + 2] * hz;
+      s_Fa[k] = vprev[NC + cell * N + k];
+    }
+    __syncthreads();
+    for (int jl = wave; jl < RB; jl += kGThreads / 64) {
+      const float* wrow = W + (int64_t)(R0 + jl) * N;
+      float px = 0.f, py2 = 0.f, pz = 0.f;
+      for (int k = lane; k < N; k += 64) {
+        const float wa = wrow[k] * s_Fa[k];
+        px = fmaf(wa, s_Fx[k], px);
+        py2 = fmaf(wa, s_Fy[k], py2);
+        pz = fmaf(wa, s_Fz[k], pz);
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        px += __shfl_xor(px, off);
+        py2 += __shfl_xor(py2, off);
+        pz += __shfl_xor(pz, off);
+      }
+      if (lane == 0) s_P[jl] = make_float4(px, py2, pz, 0.f);
+    }
+    __syncthreads();
+    // the epilogue forms Out[i][j] = F_i . P_j itself, and its T_R stores
+    // overwrite the region no wave reads any more
+  } else {
   ggbf16x8* wfrag[PJ];
 #pragma unroll
   for (int p = 0; p < PJ; ++p) wfrag[p] = (ggbf16x8*)(Wfr + ((int64_t)((j0w >> 5) + p) * KS * 64 + lane) * 8);
@@ -250,6 +298,7 @@ __global__ __launch_bounds__(kGThreads) void covg_layer_kernel(int64_t C, const 
 #undef COVG_ST1
 #undef COVG_LOAD
 #undef COVG_STORE
+  }
 
   // step-1 epilogue: block (c, p) holds Out[i][j], j = j0w + 32 p + l32 (the
   // lane's neuron), i = i0w + 32 c + 8 q + 4 hi + (0..3) (register quad q);
@@ -260,6 +309,8 @@ __global__ __launch_bounds__(kGThreads) void covg_layer_kernel(int64_t C, const 
     const int j = j0w + 32 * p + l32;
     // W[j][i..i+3] from the accumulator-quad copy: one 1 KiB run per wave
     const float4* wq = Wq + ((int64_t)((j0w >> 5) + p) * (N / 32) + (i0w >> 5)) * 4 * 64 + lane;
+    float4 pj = make_float4(0.f, 0.f, 0.f, 0.f);
+    if constexpr (FIRST) pj = reinterpret_cast<const float4*>(s_vc + RB + 4 * N)[j - R0];
     float v = 0.f, mg = 0.f, y = 0.f;
 #pragma unroll
     for (int c = 0; c < PI; ++c)
@@ -270,10 +321,27 @@ __global__ __launch_bounds__(kGThreads) void covg_layer_kernel(int64_t C, const 
         const float4 a4 = *reinterpret_cast<const float4*>(s_alpha + i);
         const float4 g4 = *reinterpret_cast<const float4*>(s_g2 + i);
         const float4 z4 = *reinterpret_cast<const float4*>(s_z + i);
-        const float t0 = fmaf(a4.x, acc[c][p][4 * q + 0], g4.x * w4.x);
-        const float t1 = fmaf(a4.y, acc[c][p][4 * q + 1], g4.y * w4.y);
-        const float t2 = fmaf(a4.z, acc[c][p][4 * q + 2], g4.z * w4.z);
-        const float t3 = fmaf(a4.w, acc[c][p][4 * q + 3], g4.w * w4.w);
+        float o0, o1, o2, o3;
+        if constexpr (FIRST) {
+          // Out[i][j] = F_i . P_j (F in three arrays after the vectors)
+          const float* fb = s_vc + RB;
+          const float4 fx = *reinterpret_cast<const float4*>(fb + i);
+          const float4 fy = *reinterpret_cast<const float4*>(fb + N + i);
+          const float4 fz = *reinterpret_cast<const float4*>(fb + 2 * N + i);
+          o0 = fmaf(pj.x, fx.x, fmaf(pj.y, fy.x, pj.z * fz.x));
+          o1 = fmaf(pj.x, fx.y, fmaf(pj.y, fy.y, pj.z * fz.y));
+          o2 = fmaf(pj.x, fx.z, fmaf(pj.y, fy.z, pj.z * fz.z));
+          o3 = fmaf(pj.x, fx.w, fmaf(pj.y, fy.w, pj.z * fz.w));
+        } else {
+          o0 = acc[c][p][4 * q + 0];
+          o1 = acc[c][p][4 * q + 1];
+          o2 = acc[c][p][4 * q + 2];
+          o3 = acc[c][p][4 * q + 3];
+        }
+        const float t0 = fmaf(a4.x, o0, g4.x * w4.x);
+        const float t1 = fmaf(a4.y, o1, g4.y * w4.y);
+        const float t2 = fmaf(a4.z, o2, g4.z * w4.z);
+        const float t3 = fmaf(a4.w, o3, g4.w * w4.w);
         v = fmaf(w4.x, t0, fmaf(w4.y, t1, fmaf(w4.z, t2, fmaf(w4.w, t3, v))));
         mg = fmaf(fabsf(w4.x), fabsf(t0),
                   fmaf(fabsf(w4.y), fabsf(t1), fmaf(fabsf(w4.z), fabsf(t2), fmaf(fabsf(w4.w), fabsf(t3), mg))));
@@ -410,8 +478,9 @@ __global__ __launch_bounds__(kGThreads) void covg_layer_kernel(int64_t C, const 
 }
 
 // Layer 1 of each cell: the rule per neuron (y = W_1 c + b_1, v = |F_j|^2
-// with F = W_1 diag(h / sqrt 3)), the layer's (y, alpha, beta, gamma), and
-// Chat_1[i][k] = alpha_k F_i . F_k (bfloat16).
+// with F = W_1 diag(h / sqrt 3)), the layer's (y, alpha, beta, gamma), and,
+// unless layer 2 runs in rank-3 form (Cout null), Chat_1[i][k] =
+// alpha_k F_i . F_k (bfloat16).
 template <int ACT>
 __global__ __launch_bounds__(kGThreads) void covg_layer1_kernel(int64_t C, int N, const float* __restrict__ W1,
                                                                  const float* __restrict__ b1,
@@ -440,6 +509,7 @@ __global__ __launch_bounds__(kGThreads) void covg_layer1_kernel(int64_t C, int N
     vec[3 * NC + o] = g;
   }
   if (t == 0 && cancel) cancel[cell] = 0u;
+  if (!Cout) return;
   __syncthreads();
   // rows of Chat_1: 8 consecutive entries per thread and step (one 16-byte store)
   const int per_row = N / 8;
@@ -487,10 +557,12 @@ int64_t covg_max_chunk(const Model& m) {
 double covg_flops_per_cell(const Model& m) {
   const int N = covg_width(m);
   const int Lh = m.n_linear - 1;
-  const double n3 = (double)N * N * N;
-  // the T product of every layer >= 2, the C product of every layer but the
-  // last, the centre (2 N^2 per layer)
-  return 2.0 * n3 * (Lh - 1) + 2.0 * n3 * std::max(0, Lh - 2) + 2.0 * (double)N * N * Lh;
+  const double n3 = (double)N * N * N, n2 = (double)N * N;
+  // the T product of every layer >= 2 (layer 2 at widths <= 512 in rank-3
+  // form: 6 N^2 for P and for F_i . P_j), the C product of every layer but
+  // the last, the centre (2 N^2 per layer)
+  const double t2 = N <= 512 ? 12.0 * n2 : 2.0 * n3;
+  return t2 + 2.0 * n3 * (Lh - 2) + 2.0 * n3 * std::max(0, Lh - 2) + 2.0 * n2 * Lh;
 }
 
 template <int N, int ACT>
@@ -501,14 +573,19 @@ static hipError_t covg_run(const Model& m, int64_t C, const float* centres, cons
   const int Lh = m.n_linear - 1;
   if (C > covg_max_chunk(m)) return hipErrorInvalidValue;
   __bf16* Cb[2] = {reinterpret_cast<__bf16*>(scratch), reinterpret_cast<__bf16*>(scratch) + C * NN};
+  constexpr bool R3 = S::RANK3;
   {
-    hipError_t e = ensure_lds_limit(reinterpret_cast<const void*>(&covg_layer_kernel<N, ACT, false>), (int)S::LDS);
+    hipError_t e = ensure_lds_limit(reinterpret_cast<const void*>(&covg_layer_kernel<N, ACT, false, false>), (int)S::LDS);
     if (e == hipSuccess)
-      e = ensure_lds_limit(reinterpret_cast<const void*>(&covg_layer_kernel<N, ACT, true>), (int)S::LDS);
+      e = ensure_lds_limit(reinterpret_cast<const void*>(&covg_layer_kernel<N, ACT, true, false>), (int)S::LDS);
+    if (R3 && e == hipSuccess)
+      e = ensure_lds_limit(reinterpret_cast<const void*>(&covg_layer_kernel<N, ACT, false, R3>), (int)S::LDS_FIRST);
+    if (R3 && e == hipSuccess)
+      e = ensure_lds_limit(reinterpret_cast<const void*>(&covg_layer_kernel<N, ACT, true, R3>), (int)S::LDS_FIRST);
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL((covg_layer1_kernel<ACT>), dim3((unsigned)C), dim3(kGThreads), (size_t)N * sizeof(float4), s, C,
-                     N, m.L[0].W, m.L[0].b, centres, halves, vec, Cb[0], cancel);
+                     N, m.L[0].W, m.L[0].b, centres, halves, vec, R3 ? (__bf16*)nullptr : Cb[0], cancel);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const dim3 grid((unsigned)(((C + 7) / 8) * 8 * S::NR));
@@ -516,16 +593,28 @@ static hipError_t covg_run(const Model& m, int64_t C, const float* centres, cons
   for (int h = 2; h <= Lh; ++h) {
     const Layer& L = m.L[h - 1];
     const __bf16* Wfr = reinterpret_cast<const __bf16*>(L.Wfr);
+    const float4* Wq = reinterpret_cast<const float4*>(L.Wq);
     const __bf16* cin = Cb[(h - 2) & 1];
     __bf16* cout = Cb[(h - 1) & 1];
     const float* vprev = vec + (h - 2) * layer;
     float* vcur = vec + (h - 1) * layer;
-    if (h == Lh)
-      hipLaunchKernelGGL((covg_layer_kernel<N, ACT, true>), grid, dim3(kGThreads), S::LDS, s, C, cin, cout, Wfr,
-                         reinterpret_cast<const float4*>(L.Wq), L.b, vprev, vcur, cancel);
-    else
-      hipLaunchKernelGGL((covg_layer_kernel<N, ACT, false>), grid, dim3(kGThreads), S::LDS, s, C, cin, cout, Wfr,
-                         reinterpret_cast<const float4*>(L.Wq), L.b, vprev, vcur, cancel);
+    const bool last = h == Lh, first = R3 && h == 2;
+#define COVG_LAUNCH(LASTV, FIRSTV)                                                                             \
+  hipLaunchKernelGGL((covg_layer_kernel<N, ACT, LASTV, FIRSTV>), grid, dim3(kGThreads),                        \
+                     (FIRSTV) ? S::LDS_FIRST : S::LDS, s, C, cin, cout, Wfr, Wq, L.W, m.L[0].W, halves, L.b, vprev, \
+                     vcur, cancel)
+    if (first) {
+      if (last)
+        COVG_LAUNCH(true, R3);
+      else
+        COVG_LAUNCH(false, R3);
+    } else {
+      if (last)
+        COVG_LAUNCH(true, false);
+      else
+        COVG_LAUNCH(false, false);
+    }
+#undef COVG_LAUNCH
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
