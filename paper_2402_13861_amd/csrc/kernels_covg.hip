@@ -111,13 +111,12 @@ constexpr float kGCancelRatio = 0x1p-9f;
 // FIRST (layer 2, where X_1 = D_1 F F^T D_1 + diag(gamma_1^2) has rank 3
 // plus a diagonal): step 1's product is Out[i][j] = F_i . P_j with
 // P_j = sum_k W[j][k] alpha_k F_k, formed on the vector ALUs from the cell's
-// box and W_1 (Chat_1 is never stored); W is W_h row-major.
+// box and W_1 (Chat_1 is never stored).
 template <int N, int ACT, bool LAST, bool FIRST>
 __global__ __launch_bounds__(kGThreads) void covg_layer_kernel(int64_t C, const __bf16* __restrict__ Cin,
                                                                 __bf16* __restrict__ Cout,
                                                                 const __bf16* __restrict__ Wfr,
                                                                 const float4* __restrict__ Wq,
-                                                                const float* __restrict__ W,
                                                                 const float* __restrict__ W1,
                                                                 const float* __restrict__ halves,
                                                                 const float* __restrict__ bias,
@@ -189,22 +188,49 @@ __global__ __launch_bounds__(kGThreads) void covg_layer_kernel(int64_t C, const 
       s_Fa[k] = vprev[NC + cell * N + k];
     }
     __syncthreads();
-    for (int jl = wave; jl < RB; jl += kGThreads / 64) {
-      const float* wrow = W + (int64_t)(R0 + jl) * N;
-      float px = 0.f, py2 = 0.f, pz = 0.f;
-      for (int k = lane; k < N; k += 64) {
-        const float wa = wrow[k] * s_Fa[k];
-        px = fmaf(wa, s_Fx[k], px);
-        py2 = fmaf(wa, s_Fy[k], py2);
-        pz = fmaf(wa, s_Fz[k], pz);
-      }
+    // P_j over the epilogue's lane layout (W[j][i..i+3] from the
+    // accumulator-quad copy, all loads of a lane in flight at once): partial
+    // sums over the lane's rows i, then over hi and the i-waves in a fixed
+    // order through the partial-sum area
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        px += __shfl_xor(px, off);
-        py2 += __shfl_xor(py2, off);
-        pz += __shfl_xor(pz, off);
+    for (int p = 0; p < PJ; ++p) {
+      const int j = j0w + 32 * p + l32;
+      const float4* wq = Wq + ((int64_t)((j0w >> 5) + p) * (N / 32) + (i0w >> 5)) * 4 * 64 + lane;
+      float px = 0.f, py2 = 0.f, pz = 0.f;
+#pragma unroll
+      for (int c = 0; c < PI; ++c)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = i0w + 32 * c + 8 * q + 4 * hi;
+          const float4 w4 = wq[(c * 4 + q) * 64];
+          const float4 a4 = *reinterpret_cast<const float4*>(s_Fa + i);
+          const float4 fx = *reinterpret_cast<const float4*>(s_Fx + i);
+          const float4 fy = *reinterpret_cast<const float4*>(s_Fy + i);
+          const float4 fz = *reinterpret_cast<const float4*>(s_Fz + i);
+          const float w0 = w4.x * a4.x, w1 = w4.y * a4.y, w2 = w4.z * a4.z, w3 = w4.w * a4.w;
+          px = fmaf(w0, fx.x, fmaf(w1, fx.y, fmaf(w2, fx.z, fmaf(w3, fx.w, px))));
+          py2 = fmaf(w0, fy.x, fmaf(w1, fy.y, fmaf(w2, fy.z, fmaf(w3, fy.w, py2))));
+          pz = fmaf(w0, fz.x, fmaf(w1, fz.y, fmaf(w2, fz.z, fmaf(w3, fz.w, pz))));
+        }
+      px += __shfl_xor(px, 32);
+      py2 += __shfl_xor(py2, 32);
+      pz += __shfl_xor(pz, 32);
+      if (hi == 0) {
+        pv[wi * RB + (j - R0)] = px;
+        pm[wi * RB + (j - R0)] = py2;
+        py[wi * RB + (j - R0)] = pz;
       }
-      if (lane == 0) s_P[jl] = make_float4(px, py2, pz, 0.f);
+    }
+    __syncthreads();
+    if (t < RB) {
+      float px = 0.f, py2 = 0.f, pz = 0.f;
+#pragma unroll
+      for (int w = 0; w < WI1; ++w) {
+        px += pv[w * RB + t];
+        py2 += pm[w * RB + t];
+        pz += py[w * RB + t];
+      }
+      s_P[t] = make_float4(px, py2, pz, 0.f);
     }
     __syncthreads();
     // the epilogue forms Out[i][j] = F_i . P_j itself, and its T_R stores
@@ -601,7 +627,7 @@ static hipError_t covg_run(const Model& m, int64_t C, const float* centres, cons
     const bool last = h == Lh, first = R3 && h == 2;
 #define COVG_LAUNCH(LASTV, FIRSTV)                                                                             \
   hipLaunchKernelGGL((covg_layer_kernel<N, ACT, LASTV, FIRSTV>), grid, dim3(kGThreads),                        \
-                     (FIRSTV) ? S::LDS_FIRST : S::LDS, s, C, cin, cout, Wfr, Wq, L.W, m.L[0].W, halves, L.b, vprev, \
+                     (FIRSTV) ? S::LDS_FIRST : S::LDS, s, C, cin, cout, Wfr, Wq, m.L[0].W, halves, L.b, vprev,      \
                      vcur, cancel)
     if (first) {
       if (last)
