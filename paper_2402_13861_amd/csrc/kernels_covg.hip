@@ -12,7 +12,8 @@
 //     C_h = T W_h^T  (not after the last hidden layer).
 // Stored between layers: Chat[i][k] = alpha_k C[i][k] (bfloat16, one factor
 // of D applied along the second index), with the diagonal alpha_i v_i from
-// the variance the rule used.  Then X[i][k] = alpha_i Chat[i][k] + [i = k]
+// the variance the rule used, in 32 x 8 blocks (chat_index): the 16 bytes of
+// 8 consecutive k of a row, for 32 consecutive rows, are one 512-byte run.  Then X[i][k] = alpha_i Chat[i][k] + [i = k]
 // gamma_i^2, so that
 //   T[j][i] = alpha_i (Chat W_h^T)[i][j] + gamma_i^2 W_h[j][i]
 // needs no per-element scaling of an MFMA operand: a workgroup that owns
@@ -85,8 +86,14 @@ struct CovgShape {
   static_assert(PI * WI1 * 32 == N && PJ * WJ1 * 32 == RB, "step-1 tiling");
   static_assert(QJ * WJ3 * 32 == RB && QM * WM3 * 32 == N, "step-3 tiling");
   static_assert(LDS <= 160 * 1024, "LDS");
-  static_assert((size_t)N * RB * 2 <= REGION, "the step-3 output tile fits where T_R was");
 };
+
+// Element offset of Chat[i][k] within a cell's N x N matrix: blocks of 32
+// rows x 8 columns (512 bytes), row blocks outermost, then column groups.
+template <int N>
+__device__ __forceinline__ int64_t chat_index(int i, int k) {
+  return ((int64_t)(i >> 5) * (N / 8) + (k >> 3)) * 256 + (i & 31) * 8 + (k & 7);
+}
 
 // four floats rounded to bfloat16, packed low to high
 __device__ __forceinline__ uint2 pack_bf16x4(float a, float b, float c, float d) {
@@ -240,18 +247,24 @@ __global__ __launch_bounds__(kGThreads) void covg_layer_kernel(int64_t C, const 
 #pragma unroll
   for (int p = 0; p < PJ; ++p) wfrag[p] = (ggbf16x8*)(Wfr + ((int64_t)((j0w >> 5) + p) * KS * 64 + lane) * 8);
 
-  // staging: N rows x KC in pieces of 8 bfloat16, SPT per thread (rows
-  // t / P8 + u RSTEP, piece t % P8).  A chunk's pieces are loaded D chunks
-  // before the end of the chunk that stores them to LDS (one register set
-  // per chunk in flight), so that a load has D chunks of products to arrive.
+  // staging: N rows x KC in pieces of 8 bfloat16 (a row and 8 columns), SPT
+  // per thread: lanes run over the 32 rows of a block, then the chunk's P8
+  // column groups, so that a wave reads whole 512-byte runs of the blocked
+  // layout (rows 32 (t / (32 P8)) + t % 32 + u RSTEP, group (t / 32) % P8).
+  // A chunk's pieces are loaded D chunks before the end of the chunk that
+  // stores them to LDS (one register set per chunk in flight), so that a load
+  // has D chunks of products to arrive.
   constexpr int P8 = KC / 8, RSTEP = kGThreads / P8, SPT = S::SPT, D = S::D;
   constexpr int NCH = N / KC, KK = KC / 16;
   static_assert(NCH % D == 0 && D % 2 == 0, "staging ring");
-  const __bf16* ag = Cin + cell * NN + (int64_t)(t / P8) * N + 8 * (t % P8);
-  __bf16* ls = stage + (t / P8) * SSTR + 8 * (t % P8);
+  const int srow = 32 * (t / (32 * P8)) + (t & 31), sgrp = (t >> 5) % P8;
+  const __bf16* ag = Cin + cell * NN + chat_index<N>(srow, 8 * sgrp);
+  __bf16* ls = stage + srow * SSTR + 8 * sgrp;
   static_assert(SPT == 2 || SPT == 4, "pieces per thread");
   uint4 a0, a1, a2, a3, b0, b1, b2, b3;  // register sets 0 (a) and 1 (b)
-#define COVG_LD1(R, U, K0) R = *reinterpret_cast<const uint4*>(ag + (int64_t)(U) * RSTEP * N + (K0));
+  // (RSTEP rows further: RSTEP / 32 row blocks of 32 N elements; K0 columns
+  // further: K0 / 8 groups of 256 elements)
+#define COVG_LD1(R, U, K0) R = *reinterpret_cast<const uint4*>(ag + (int64_t)(U) * RSTEP * N + (int64_t)(K0) * 32);
 #define COVG_ST1(R, U, BUF) *reinterpret_cast<uint4*>(ls + (BUF) * N * SSTR + (U) * RSTEP * SSTR) = R;
 #define COVG_LOAD(R, K0)              \
   {                                   \
@@ -463,13 +476,10 @@ __global__ __launch_bounds__(kGThreads) void covg_layer_kernel(int64_t C, const 
   }
 
   // step-3 epilogue: block (c, q) holds C[j][m], m = m0 + 32 q + l32, local
-  // j = jl0 + 32 c + 8 r + 4 hi + (0..3) (quad r).  Chat[m][j] = alpha_j C[j][m]
-  // (C is symmetric; the diagonal alpha_j v_j) goes through LDS, where T_R
-  // was, as the tile Ct[m][jl] (N x RB, 16-byte slots of each row XOR-swizzled
-  // by the row), and leaves as contiguous 16-byte pieces of the rows of Chat.
-  constexpr int SLOTS = RB / 8;
-  __bf16* Ct = reinterpret_cast<__bf16*>(base);
-  __syncthreads();  // every wave has finished reading T_R
+  // j = jl0 + 32 c + 8 r + 4 hi + (0..3) (quad r); stored as row m of Chat
+  // (C is symmetric), scaled by alpha_j, the diagonal alpha_j v_j.  In the
+  // blocked layout a wave's store of (c, q, r) is one 512-byte run.
+  __bf16* Co = Cout + cell * NN;
 #pragma unroll
   for (int c = 0; c < QJ; ++c)
 #pragma unroll
@@ -489,18 +499,9 @@ __global__ __launch_bounds__(kGThreads) void covg_layer_kernel(int64_t C, const 
           x2 = d == 2 ? dv : x2;
           x3 = d == 3 ? dv : x3;
         }
-        const int slot = (jl >> 3) ^ (m & (SLOTS - 1));
-        *reinterpret_cast<uint2*>(Ct + (size_t)m * RB + slot * 8 + (jl & 7)) = pack_bf16x4(x0, x1, x2, x3);
+        *reinterpret_cast<uint2*>(Co + chat_index<N>(m, R0 + jl)) = pack_bf16x4(x0, x1, x2, x3);
       }
     }
-  __syncthreads();
-  __bf16* Co = Cout + cell * NN + R0;
-#pragma unroll 4
-  for (int pidx = t; pidx < N * SLOTS; pidx += kGThreads) {
-    const int m = pidx / SLOTS, sl = pidx - m * SLOTS;
-    const uint4 v = *reinterpret_cast<const uint4*>(Ct + (size_t)m * RB + ((sl ^ (m & (SLOTS - 1))) * 8));
-    *reinterpret_cast<uint4*>(Co + (int64_t)m * N + sl * 8) = v;
-  }
 }
 
 // Layer 1 of each cell: the rule per neuron (y = W_1 c + b_1, v = |F_j|^2
@@ -537,11 +538,13 @@ __global__ __launch_bounds__(kGThreads) void covg_layer1_kernel(int64_t C, int N
   if (t == 0 && cancel) cancel[cell] = 0u;
   if (!Cout) return;
   __syncthreads();
-  // rows of Chat_1: 8 consecutive entries per thread and step (one 16-byte store)
-  const int per_row = N / 8;
+  // Chat_1 in the blocked layout: 8 consecutive entries of a row per thread
+  // and step (one 16-byte store), lanes over the 32 rows of a block
+  const int per_blk = 32 * (N / 8);
   __bf16* Cc = Cout + cell * (int64_t)N * N;
-  for (int idx = t; idx < N * per_row; idx += kGThreads) {
-    const int i = idx / per_row, k0 = 8 * (idx - i * per_row);
+  for (int idx = t; idx < N * (N / 8); idx += kGThreads) {
+    const int blk = idx / per_blk, rem = idx - blk * per_blk;
+    const int i = 32 * blk + (rem & 31), k0 = 8 * (rem >> 5);
     const float4 fi = covg_l1[i];
     gbf16x8 v;
 #pragma unroll
@@ -549,7 +552,7 @@ __global__ __launch_bounds__(kGThreads) void covg_layer1_kernel(int64_t C, int N
       const float4 fk = covg_l1[k0 + e];
       v[e] = (__bf16)(fk.w * (fi.x * fk.x + fi.y * fk.y + fi.z * fk.z));
     }
-    *reinterpret_cast<gbf16x8*>(Cc + (int64_t)i * N + k0) = v;
+    *reinterpret_cast<gbf16x8*>(Cc + ((int64_t)blk * (N / 8) + (rem >> 5)) * 256 + (rem & 31) * 8) = v;
   }
 }
 
