@@ -99,12 +99,16 @@ def traffic_from_profiles(kind: str, cells_per_launch: float, src_name: str = No
     """HBM bytes per launch of the dominant kernel: the committed rocprofv3
     counter summary's bytes per propagated cell (all hidden-layer launches of
     a cell; taken on the current kernel source, else None) times the
-    propagated cells per launch of this run (propagated cells / launches)."""
-    f = ROOT / "profiles" / f"{kind}_traffic.json"
-    if not f.exists() or (src_name and src_name != HIDDEN_KINDS[kind][1]):
+    propagated cells per launch of this run (propagated cells / launches).
+    A kind's kernel in another source file (the device-memory covariance
+    form) has its own summary, named after that file."""
+    default = not src_name or src_name == HIDDEN_KINDS[kind][1]
+    name = f"{kind}_traffic.json" if default else f"{kind}_{Path(src_name).stem}_traffic.json"
+    f = ROOT / "profiles" / name
+    if not f.exists():
         return None
     t = json.loads(f.read_text())
-    if t.get("kernel_source_sha256_16") != kernel_source_hash(kind):
+    if t.get("kernel_source_sha256_16") != kernel_source_hash(kind, None if default else src_name):
         return None
     return t["hbm_bytes_per_cell"] * cells_per_launch
 
