@@ -592,6 +592,9 @@ def main(argv=None):
     ap.add_argument("--kl-seed", type=int, default=0)
     ap.add_argument("--recheck-cascade", type=int, default=1,
                     help="BF16: re-check band cells in float32 first and in float64 only within 1/8 of the band")
+    ap.add_argument("--recheck-split", type=int, default=1,
+                    help="with --recheck-cascade: the float32 stage's products as split bf16 MFMAs (hi/lo parts; "
+                         "endpoint error <= 2.5e-5 S on the benchmark INR, against the inner band of 1.25e-4 S)")
     ap.add_argument("--band-rel", type=float, default=0.0,
                     help="BF16: widen each cell's float64 re-check band by this multiple of its spread (2^-6 "
                          "covers the BF16 endpoint error measured at every level)")
@@ -641,6 +644,7 @@ def main(argv=None):
     ctx.set_option(isx.SCRATCH_BYTES, 48 << 30)
     ctx.set_option(isx.VERBOSE, 1)
     ctx.set_option(isx.RECHECK_CASCADE, a.recheck_cascade)
+    ctx.set_option(isx.RECHECK_SPLIT, a.recheck_split)
     ctx.set_option(isx.DENSE_FROM_LEVEL, a.dense_from_level)
     mid = ctx.load_weights(mlp)
     act = w.get("act", "relu")
@@ -895,8 +899,9 @@ def main(argv=None):
                         f"({1 << depth}^3 effective cells), {len(isos)} iso-values, UP t={w['k']}, "
                         f"fp64 band {w.get('band_rel', 0)} S"
                         + (f" + {a.band_rel:g} of the cell's spread" if a.precision == "bf16" and a.band_rel else "")
-                        + (" (float32 re-check, float64 within 1/8 of the band)" if a.precision == "bf16"
-                           and a.recheck_cascade else "")
+                        + ((" (float32 re-check" + (" with split bf16 products" if a.recheck_split else "")
+                            + ", float64 within 1/8 of the band)") if a.precision == "bf16" and a.recheck_cascade
+                           else "")
                         + (f"; domain [0, {sub_hi:g}]^3, the level-{a.subtree} subtree of [-1, 1]^3 at "
                            f"{1 << full_depth}^3 effective resolution" if a.subtree else ""),
             "path": name,

@@ -551,7 +551,9 @@ isx_status isx_mc_case_table(uint8_t* h_count, int8_t* h_edges);
 /* Context options. */
 typedef enum {
   ISX_KEEP_LEVELS = 1,     /* value 1: meshes keep every level's cells (for testing) */
-  ISX_HIDDEN_KERNEL = 2,   /* 0 = automatic, 1 = force the SIMT kernels, 2 = force MFMA */
+  ISX_HIDDEN_KERNEL = 2,   /* 0 = automatic, 1 = force the SIMT kernels, 2 = force MFMA, 3 = MFMA with
+                              ISX_FP32 UP products as split bfloat16 MFMAs (as ISX_RECHECK_SPLIT gives the
+                              re-check cascade's float32 stage; for measuring that stage directly) */
   ISX_PROFILE = 3,         /* value 1: time every hidden-layer launch with HIP events */
   ISX_SCRATCH_BYTES = 4,   /* bytes of propagation scratch per batch (default 16 GiB) */
   ISX_VERBOSE = 5,         /* value 1: isx_extract prints one line per octree level to stderr */
@@ -602,7 +604,7 @@ typedef enum {
                               iso-value go on to float64; the others keep the float32 decision (float32
                               endpoint errors are far below that eighth: <= 1e-5 of max(|o|, S) in the
                               parity tests); isx_mesh_level_rechecked_fp64 counts the float64 cells */
-  ISX_DENSE_FROM_LEVEL = 15 /* isx_extract on the octree: 0 (default) = range analysis down to max_depth
+  ISX_DENSE_FROM_LEVEL = 15, /* isx_extract on the octree: 0 (default) = range analysis down to max_depth
                               (Alg. 1); L in [1, max_depth) = range analysis down to level L only, then
                               every level-max_depth cell below an active level-L cell is a leaf for that
                               cell's iso-values (its corners evaluated and marching cubes run on it, as in
@@ -613,6 +615,12 @@ typedef enum {
                               cell); the mesh records levels 0..L; isx_extract fails with
                               ISX_ECAPACITY above 2^28 leaves or 2^31 (leaf, iso) pairs, and with
                               ISX_EUNSUPPORTED for the k-d tree */
+  ISX_RECHECK_SPLIT = 16    /* with ISX_RECHECK_CASCADE 1: 0 (default) = the float32 stage multiplies on
+                              float32 MFMA; 1 = its products are three bfloat16 MFMAs of hi/lo splits of
+                              the float32 operands (a b ~ a_hi b_hi + a_hi b_lo + a_lo b_hi, float32
+                              accumulation; about 3 2^-18 of |a b| per term instead of 2^-24), with the
+                              same storage, rule and read-off as the float32 stage; UP only (AA keeps
+                              float32 products, which its rounding margin assumes) */
 } isx_option;
 isx_status isx_set_option(isx_ctx* ctx, isx_option option, int64_t value);
 

@@ -22,7 +22,7 @@ import numpy as np
 from . import _lib
 from ._lib import (AA, RAUA, RAFIXED, RELU, SINE, ELU, BF16, BF16_VARIANT, FP32, FP64, HIDDEN_KERNEL, KEEP_LEVELS, PROFILE, SCRATCH_BYTES, UP,
                    UP_FORM, LIN_PRECISION, AA_MARGIN, BATCH_WORKERS, VERBOSE, CANCEL_CHECK, AUTOTUNE,
-                   BF16_READOFF, RECHECK_CASCADE, DENSE_FROM_LEVEL)
+                   BF16_READOFF, RECHECK_CASCADE, DENSE_FROM_LEVEL, RECHECK_SPLIT)
 
 # columns of isx_distribution_kl's report (isx_dist_field order)
 DIST_FIELDS = ("mc_mean", "mc_std", "lo", "hi", "up_mu", "up_sigma", "raua_mu", "raua_sigma", "fit_mu", "fit_sigma",

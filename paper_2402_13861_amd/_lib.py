@@ -20,8 +20,8 @@ AA, UP, RAUA, RAFIXED = 0, 1, 2, 3
 RELU, SINE, ELU = 0, 1, 2
 FP32, BF16, FP64 = 0, 1, 2
 (KEEP_LEVELS, HIDDEN_KERNEL, PROFILE, SCRATCH_BYTES, VERBOSE, BF16_VARIANT, UP_FORM, LIN_PRECISION,
- AA_MARGIN, BATCH_WORKERS, CANCEL_CHECK, AUTOTUNE, BF16_READOFF, RECHECK_CASCADE, DENSE_FROM_LEVEL) = (
-    1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15)
+ AA_MARGIN, BATCH_WORKERS, CANCEL_CHECK, AUTOTUNE, BF16_READOFF, RECHECK_CASCADE, DENSE_FROM_LEVEL,
+ RECHECK_SPLIT) = (1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16)
 MAX_LINEAR, MAX_WIDTH, MAX_ISO = 16, 1024, 32
 NOALLOC_MAX_CELLS = 1 << 22
 (KERNEL_HIDDEN_FP32, KERNEL_HIDDEN_BF16, KERNEL_HIDDEN_SIMT_FP32, KERNEL_HIDDEN_FP64, KERNEL_DENSE,

@@ -112,6 +112,8 @@ struct isx_ctx {
   Buf rc_pm, rc_flags2, rc_idx2, rc2_c, rc2_h, rc2_out32, rc2_out64;  // two-stage re-check
   int recheck_cascade = 0;                                          // ISX_RECHECK_CASCADE
   int dense_from = 0;                                               // ISX_DENSE_FROM_LEVEL
+  int recheck_split = 0;                                            // ISX_RECHECK_SPLIT
+  bool f32_split_now = false;  // the float32 propagation running is the cascade's first stage (split products)
   int64_t n_rc64_last = 0;  // cells propagated in float64 by the re-checks since the level began
   Buf cx_flags, cx_idx, cx_c, cx_h, cx_out, cx_out64, cx_cnt;
   // surrogate training set and band calibration
@@ -434,6 +436,8 @@ isx_status run_propagate(isx_ctx* ctx, const Model& m, isx_method method, isx_pr
                ctx->kernel_choice, ctx->stream, &ctx->prof, ctx->bf16_variant};
     a.aa_margin = marg;
     a.seg = seg;
+    // (UP only: AA's rounding margin assumes float32 products)
+    a.f32_split = (ctx->f32_split_now || ctx->kernel_choice == 3) && method == ISX_UP;
     HIPCHK(propagate_f32(a, w));
   }
   return ISX_OK;
@@ -542,7 +546,7 @@ isx_status isx_set_option(isx_ctx* ctx, isx_option option, int64_t value) {
       ctx->keep_levels = value != 0;
       return ISX_OK;
     case ISX_HIDDEN_KERNEL:
-      if (value < 0 || value > 2) return fail(ctx, ISX_EINVAL, "ISX_HIDDEN_KERNEL must be 0, 1 or 2");
+      if (value < 0 || value > 3) return fail(ctx, ISX_EINVAL, "ISX_HIDDEN_KERNEL must be 0, 1, 2 or 3");
       ctx->kernel_choice = (int)value;
       return ISX_OK;
     case ISX_PROFILE:
@@ -590,6 +594,10 @@ isx_status isx_set_option(isx_ctx* ctx, isx_option option, int64_t value) {
     case ISX_RECHECK_CASCADE:
       if (value < 0 || value > 1) return fail(ctx, ISX_EINVAL, "ISX_RECHECK_CASCADE must be 0 or 1");
       ctx->recheck_cascade = (int)value;
+      return ISX_OK;
+    case ISX_RECHECK_SPLIT:
+      if (value < 0 || value > 1) return fail(ctx, ISX_EINVAL, "ISX_RECHECK_SPLIT must be 0 or 1");
+      ctx->recheck_split = (int)value;
       return ISX_OK;
     case ISX_DENSE_FROM_LEVEL:
       if (value < 0 || value > 10) return fail(ctx, ISX_EINVAL, "ISX_DENSE_FROM_LEVEL must be in [0, 10]");
@@ -1088,8 +1096,10 @@ static isx_status prop_classify(isx_ctx* ctx, const Model& m, const isx_params* 
       // float32 first; float64 only where the float32 bound still lies within
       // an eighth of the band of a carried iso-value (the float32 endpoint
       // error is far below that, so elsewhere both decide alike)
+      ctx->f32_split_now = ctx->recheck_split != 0;
       st = run_propagate(ctx, m, p->method, ISX_FP32, n_rc, (const float*)ctx->rc_centres.p,
                          (const float*)ctx->rc_halves.p, (float*)ctx->rc_out32.p, nullptr, p->chunk_cells);
+      ctx->f32_split_now = false;
       if (st != ISX_OK) return st;
       HIPCHK(launch_widen_pairs(n_rc, (const float*)ctx->rc_out32.p, (double*)ctx->rc_out64.p, s));
       HIPCHK(ensure(ctx->rc_pm, n_rc * 4));
@@ -1549,6 +1559,7 @@ isx_status isx_extract_batch(isx_ctx* ctx, int32_t n, const int32_t* mlp_ids, co
     w->autotune = ctx->autotune;
     w->readoff_f32 = ctx->readoff_f32;
     w->recheck_cascade = ctx->recheck_cascade;
+    w->recheck_split = ctx->recheck_split;
     w->dense_from = ctx->dense_from;
     w->up_form = ctx->up_form;
     w->lin_prec = ctx->lin_prec;

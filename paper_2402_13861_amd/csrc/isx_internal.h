@@ -272,6 +272,7 @@ struct PropArgs {
   int seg = 0;                 // 1: inputs are segments (centre, half-vector) with one input symbol
   int readoff_f32 = 0;         // bf16 UP: 1 = the float32 MFMA read-off instead of the bf16 hi/lo one
   bool covg = false;           // bf16 UP: the covariance form with the matrices in global memory (scratch: Fbf[0])
+  bool f32_split = false;      // float32 MFMA path: products as three bf16 MFMAs of hi/lo splits
 };
 
 // Constants of the affine-arithmetic rounding margin of one layer

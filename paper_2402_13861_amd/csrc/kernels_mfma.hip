@@ -32,6 +32,34 @@ __device__ __forceinline__ float mstat(float v) {
 }
 
 
+// SPLIT: the products as three BF16 MFMAs of float32 operands split into
+// bfloat16 parts, x = hi + lo (hi = bf16(x), lo = bf16(x - hi)):
+//   a b ~ a_hi b_hi + a_hi b_lo + a_lo b_hi,
+// each of v_mfma_f32_32x32x16_bf16, accumulated in float32.  The dropped
+// a_lo b_lo and the rounding of the lo parts leave about 3 2^-18 of |a b| per
+// term, against 2^-24 for float32 products; one k-step of 16 costs three
+// 32-cycle products instead of eight 64-cycle float32 ones.  Operands are
+// staged in LDS as [row][k] bfloat16 (hi block, then lo block), 8 + 32
+// elements per row.  The accumulator layout is the float32 product's.
+typedef __bf16 sbf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ void split_bf16x4(float4 v, uint2& hi, uint2& lo) {
+  union {
+    __bf16 h[4];
+    uint2 u;
+  } ph, pl;
+  ph.h[0] = (__bf16)v.x;
+  ph.h[1] = (__bf16)v.y;
+  ph.h[2] = (__bf16)v.z;
+  ph.h[3] = (__bf16)v.w;
+  pl.h[0] = (__bf16)(v.x - (float)ph.h[0]);
+  pl.h[1] = (__bf16)(v.y - (float)ph.h[1]);
+  pl.h[2] = (__bf16)(v.z - (float)ph.h[2]);
+  pl.h[3] = (__bf16)(v.w - (float)ph.h[3]);
+  hi = ph.u;
+  lo = pl.u;
+}
+
 template <int BM>
 struct Cfg {
   static constexpr int NWAVES = 8;
@@ -44,19 +72,23 @@ struct Cfg {
   static constexpr int ASTR = BM;
   static constexpr int BSTR = BN + 1;
   static constexpr int G = THREADS / BM;       // thread groups in the generated-block pass
+  static constexpr int SSTR = KT + 8;          // SPLIT: bfloat16 row stride of the staged operands
 };
 
 // At most 128 VGPRs (four waves per SIMD): two workgroups share a CU, so one
 // workgroup's barriers and chunk stores overlap the other's products.
-template <int METHOD, int BM>
+template <int METHOD, int BM, bool SPLIT>
 __global__ __launch_bounds__(512, 4) void hidden_mfma_f32_kernel(
     int64_t C, int n_in, int n_out, int64_t cols_in, int rb_count, const float* __restrict__ Wt,
-    const float* __restrict__ bias, const float* __restrict__ Fin, const float* __restrict__ Ain,
-    const float* __restrict__ Bin, const float* __restrict__ Gin, float* __restrict__ Fout, float* __restrict__ Y,
-    float* __restrict__ A, float* __restrict__ B, float* __restrict__ G, float* __restrict__ S, int act) {
+    const float* __restrict__ Wrow, const float* __restrict__ bias, const float* __restrict__ Fin,
+    const float* __restrict__ Ain, const float* __restrict__ Bin, const float* __restrict__ Gin,
+    float* __restrict__ Fout, float* __restrict__ Y, float* __restrict__ A, float* __restrict__ B,
+    float* __restrict__ G, float* __restrict__ S, int act) {
   using K = Cfg<BM>;
-  __shared__ float As[K::KT * K::ASTR];
-  __shared__ float Bs[K::KT * K::BSTR];
+  // float32 tiles [k][row] / [k][column], or (SPLIT) bfloat16 hi | lo blocks
+  // of [row][k] / [column][k]
+  __shared__ float As[SPLIT ? BM * K::SSTR : K::KT * K::ASTR];
+  __shared__ float Bs[SPLIT ? K::BN * K::SSTR : K::KT * K::BSTR];
   __shared__ float s_alpha[ISX_MAX_WIDTH];
   __shared__ float s_beta[ISX_MAX_WIDTH];
   __shared__ float s_gamma[ISX_MAX_WIDTH];
@@ -87,6 +119,22 @@ __global__ __launch_bounds__(512, 4) void hidden_mfma_f32_kernel(
   // owns the row block (s_stat[wc] is written by wave (wr, wc) only)
   for (int i = t; i < K::WC * BM; i += K::THREADS) (&s_stat[0][0])[i] = 0.f;
 
+  // SPLIT: the centre column (a point evaluation of the linearised net,
+  // y_j = sum_k W[j][k] (alpha_k y_k + beta_k) + b_j) in float32 on the vector
+  // ALUs: its dot products cancel, and the split products' error relative to
+  // the summed magnitudes would show in the classification margin
+  __shared__ float s_yx[SPLIT ? BM : 1];
+  if constexpr (SPLIT) {
+    constexpr int TPR = K::THREADS / BM;  // threads per row (consecutive lanes)
+    const int row = t / TPR, part = t % TPR;
+    const float* wrow = Wrow + (int64_t)(m0 + row) * n_in;
+    float yv = 0.f;
+    for (int k = part; k < n_in; k += TPR) yv = fmaf(wrow[k], fmaf(s_alpha[k], fin[k], s_beta[k]), yv);
+#pragma unroll
+    for (int off = TPR / 2; off > 0; off >>= 1) yv += __shfl_xor(yv, off);
+    if (part == 0) s_yx[row] = yv + bias[m0 + row];
+  }
+
   const int64_t ntiles = (cols_in + K::BN - 1) / K::BN;
   for (int64_t nt = 0; nt < ntiles; ++nt) {
     const int64_t c0 = nt * K::BN;
@@ -114,8 +162,13 @@ __global__ __launch_bounds__(512, 4) void hidden_mfma_f32_kernel(
 #define ISX_F32_LOAD_A(U, DST, K0)                                                                 \
   {                                                                                                \
     const int idx = min(t + (U) * K::THREADS, TA - 1);                                             \
-    const int kk = idx / (BM / 4), mq = idx - kk * (BM / 4);                                       \
-    DST = *reinterpret_cast<const float4*>(Wt + (int64_t)((K0) + kk) * n_out + m0 + 4 * mq);       \
+    if constexpr (SPLIT) {                                                                         \
+      const int mm = idx / (K::KT / 4), kq = idx - mm * (K::KT / 4);                               \
+      DST = *reinterpret_cast<const float4*>(Wrow + (int64_t)(m0 + mm) * n_in + (K0) + 4 * kq);    \
+    } else {                                                                                       \
+      const int kk = idx / (BM / 4), mq = idx - kk * (BM / 4);                                     \
+      DST = *reinterpret_cast<const float4*>(Wt + (int64_t)((K0) + kk) * n_out + m0 + 4 * mq);     \
+    }                                                                                              \
   }
 #define ISX_F32_LOAD_B(U, DST, K0)                                                                 \
   {                                                                                                \
@@ -135,11 +188,22 @@ __global__ __launch_bounds__(512, 4) void hidden_mfma_f32_kernel(
     if constexpr (NBL > 2) ISX_F32_LOAD_B(2, rb2, K0); \
     if constexpr (NBL > 3) ISX_F32_LOAD_B(3, rb3, K0); \
   }
-#define ISX_F32_STORE_A(U, SRC)                                                  \
-  {                                                                              \
-    const int idx = t + (U) * K::THREADS;                                        \
-    const int kk = idx / (BM / 4), mq = idx - kk * (BM / 4);                     \
-    if (idx < TA) *reinterpret_cast<float4*>(As + kk * K::ASTR + 4 * mq) = SRC;  \
+#define ISX_F32_STORE_A(U, SRC)                                                              \
+  {                                                                                          \
+    const int idx = t + (U) * K::THREADS;                                                    \
+    if constexpr (SPLIT) {                                                                   \
+      const int mm = idx / (K::KT / 4), kq = idx - mm * (K::KT / 4);                         \
+      if (idx < TA) {                                                                        \
+        __bf16* ah = reinterpret_cast<__bf16*>(As) + mm * K::SSTR + 4 * kq;                  \
+        uint2 h_, l_;                                                                        \
+        split_bf16x4(SRC, h_, l_);                                                           \
+        *reinterpret_cast<uint2*>(ah) = h_;                                                  \
+        *reinterpret_cast<uint2*>(ah + BM * K::SSTR) = l_;                                   \
+      }                                                                                      \
+    } else {                                                                                 \
+      const int kk = idx / (BM / 4), mq = idx - kk * (BM / 4);                               \
+      if (idx < TA) *reinterpret_cast<float4*>(As + kk * K::ASTR + 4 * mq) = SRC;            \
+    }                                                                                        \
   }
 #define ISX_F32_STORE_B(U, SRC)                                    \
   {                                                                \
@@ -158,10 +222,18 @@ __global__ __launch_bounds__(512, 4) void hidden_mfma_f32_kernel(
         v.z += s_beta[k + 2];                                      \
         v.w += s_beta[k + 3];                                      \
       }                                                            \
-      Bs[(4 * kq + 0) * K::BSTR + col] = v.x;                      \
-      Bs[(4 * kq + 1) * K::BSTR + col] = v.y;                      \
-      Bs[(4 * kq + 2) * K::BSTR + col] = v.z;                      \
-      Bs[(4 * kq + 3) * K::BSTR + col] = v.w;                      \
+      if constexpr (SPLIT) {                                       \
+        __bf16* bh = reinterpret_cast<__bf16*>(Bs) + col * K::SSTR + 4 * kq; \
+        uint2 h_, l_;                                              \
+        split_bf16x4(v, h_, l_);                                   \
+        *reinterpret_cast<uint2*>(bh) = h_;                        \
+        *reinterpret_cast<uint2*>(bh + K::BN * K::SSTR) = l_;      \
+      } else {                                                     \
+        Bs[(4 * kq + 0) * K::BSTR + col] = v.x;                    \
+        Bs[(4 * kq + 1) * K::BSTR + col] = v.y;                    \
+        Bs[(4 * kq + 2) * K::BSTR + col] = v.z;                    \
+        Bs[(4 * kq + 3) * K::BSTR + col] = v.w;                    \
+      }                                                            \
     }                                                              \
   }
     ISX_F32_LOAD_CHUNK(0);
@@ -177,15 +249,36 @@ __global__ __launch_bounds__(512, 4) void hidden_mfma_f32_kernel(
       __syncthreads();
       if (k0 + K::KT < n_in) ISX_F32_LOAD_CHUNK(k0 + K::KT);
       if (wave_active) {
+        if constexpr (SPLIT) {
+          const __bf16* a0 = reinterpret_cast<const __bf16*>(As) + (wr * 32 + (lane & 31)) * K::SSTR + 8 * (lane >> 5);
+          const __bf16* b0 = reinterpret_cast<const __bf16*>(Bs) + (wc * 32 * K::NB + (lane & 31)) * K::SSTR +
+                             8 * (lane >> 5);
 #pragma unroll
-        for (int ks = 0; ks < K::KT / 2; ++ks) {
-          const int kr = 2 * ks + (lane >> 5);
-          const float a = As[kr * K::ASTR + wr * 32 + (lane & 31)];
+          for (int kk = 0; kk < K::KT / 16; ++kk) {
+            const sbf16x8 ah = *reinterpret_cast<const sbf16x8*>(a0 + 16 * kk);
+            const sbf16x8 al = *reinterpret_cast<const sbf16x8*>(a0 + BM * K::SSTR + 16 * kk);
 #pragma unroll
-          for (int nb = 0; nb < K::NB; ++nb) {
-            if (nb > 0 && nb >= nb_real) break;
-            const float bv = Bs[kr * K::BSTR + wc * 32 * K::NB + nb * 32 + (lane & 31)];
-            acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bv, acc[nb], 0, 0, 0);
+            for (int nb = 0; nb < K::NB; ++nb) {
+              if (nb > 0 && nb >= nb_real) break;
+              const __bf16* bp = b0 + nb * 32 * K::SSTR + 16 * kk;
+              const sbf16x8 bh = *reinterpret_cast<const sbf16x8*>(bp);
+              const sbf16x8 bl = *reinterpret_cast<const sbf16x8*>(bp + K::BN * K::SSTR);
+              acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[nb], 0, 0, 0);
+              acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[nb], 0, 0, 0);
+              acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[nb], 0, 0, 0);
+            }
+          }
+        } else {
+#pragma unroll
+          for (int ks = 0; ks < K::KT / 2; ++ks) {
+            const int kr = 2 * ks + (lane >> 5);
+            const float a = As[kr * K::ASTR + wr * 32 + (lane & 31)];
+#pragma unroll
+            for (int nb = 0; nb < K::NB; ++nb) {
+              if (nb > 0 && nb >= nb_real) break;
+              const float bv = Bs[kr * K::BSTR + wc * 32 * K::NB + nb * 32 + (lane & 31)];
+              acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bv, acc[nb], 0, 0, 0);
+            }
           }
         }
       }
@@ -210,10 +303,17 @@ __global__ __launch_bounds__(512, 4) void hidden_mfma_f32_kernel(
             float v0 = acc[nb][4 * q4 + 0], v1 = acc[nb][4 * q4 + 1];
             float v2 = acc[nb][4 * q4 + 2], v3 = acc[nb][4 * q4 + 3];
             if (col == 0) {
-              v0 += bias[m0 + rl + 0];
-              v1 += bias[m0 + rl + 1];
-              v2 += bias[m0 + rl + 2];
-              v3 += bias[m0 + rl + 3];
+              if constexpr (SPLIT) {
+                v0 = s_yx[rl + 0];
+                v1 = s_yx[rl + 1];
+                v2 = s_yx[rl + 2];
+                v3 = s_yx[rl + 3];
+              } else {
+                v0 += bias[m0 + rl + 0];
+                v1 += bias[m0 + rl + 1];
+                v2 += bias[m0 + rl + 2];
+                v3 += bias[m0 + rl + 3];
+              }
               s_y[rl + 0] = v0;
               s_y[rl + 1] = v1;
               s_y[rl + 2] = v2;
@@ -295,34 +395,55 @@ bool mfma_supported(const Model& m) {
   return true;
 }
 
-template <int METHOD, int BM>
-static void launch_bm(int64_t C, int n_in, int n_out, int64_t cols_in, const float* Wt, const float* bias,
-                      const float* Fin, const float* Ain, const float* Bin, const float* Gin, float* Fout, float* Y,
-                      float* A, float* B, float* G, float* S, int act, hipStream_t s) {
+template <int METHOD, int BM, bool SPLIT>
+static void launch_bm(int64_t C, int n_in, int n_out, int64_t cols_in, const float* Wt, const float* Wrow,
+                      const float* bias, const float* Fin, const float* Ain, const float* Bin, const float* Gin,
+                      float* Fout, float* Y, float* A, float* B, float* G, float* S, int act, hipStream_t s) {
   const int rb_count = n_out / BM;
   const int64_t blocks = ((C + 7) / 8) * 8 * rb_count;
-  hipLaunchKernelGGL((hidden_mfma_f32_kernel<METHOD, BM>), dim3((unsigned)blocks), dim3(Cfg<BM>::THREADS), 0, s, C,
-                     n_in, n_out, cols_in, rb_count, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, act);
+  hipLaunchKernelGGL((hidden_mfma_f32_kernel<METHOD, BM, SPLIT>), dim3((unsigned)blocks), dim3(Cfg<BM>::THREADS), 0,
+                     s, C, n_in, n_out, cols_in, rb_count, Wt, Wrow, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S,
+                     act);
+}
+
+template <int METHOD, bool SPLIT>
+static void launch_m(int bm, int64_t C, int n_in, int n_out, int64_t cols_in, const float* Wt, const float* Wrow,
+                     const float* bias, const float* Fin, const float* Ain, const float* Bin, const float* Gin,
+                     float* Fout, float* Y, float* A, float* B, float* G, float* S, int act, hipStream_t s) {
+  if (bm == 128)
+    launch_bm<METHOD, 128, SPLIT>(C, n_in, n_out, cols_in, Wt, Wrow, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S,
+                                  act, s);
+  else if (bm == 64)
+    launch_bm<METHOD, 64, SPLIT>(C, n_in, n_out, cols_in, Wt, Wrow, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S,
+                                 act, s);
+  else
+    launch_bm<METHOD, 32, SPLIT>(C, n_in, n_out, cols_in, Wt, Wrow, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S,
+                                 act, s);
 }
 
 hipError_t launch_hidden_mfma_f32(int method, int64_t C, int n_in, int n_out, int64_t cols_in, const float* Wt,
-                                  const float* bias, const float* Fin, const float* Ain, const float* Bin,
-                                  const float* Gin, float* Fout, float* Y, float* A, float* B, float* G, float* S,
-                                  hipStream_t s) {
+                                  const float* Wrow, const float* bias, const float* Fin, const float* Ain,
+                                  const float* Bin, const float* Gin, float* Fout, float* Y, float* A, float* B,
+                                  float* G, float* S, hipStream_t s) {
   if (C <= 0) return hipSuccess;
   if (n_out % 32 != 0 || n_in % 32 != 0 || n_in > ISX_MAX_WIDTH) return hipErrorInvalidValue;
-  // method: the propagation method in the low 4 bits, the activation above
-  const int act = method >> 4;
+  // method: the propagation method in bits 0-3, the activation in bits 4-7,
+  // bit 8 the split bf16 products (SPLIT)
+  const int act = (method >> 4) & 15;
+  const bool split = (method >> 8) & 1;
   method &= 15;
+  if (split && !Wrow) return hipErrorInvalidValue;
   const int bm = n_out % 128 == 0 ? 128 : (n_out % 64 == 0 ? 64 : 32);
   if (method == ISX_UP) {
-    if (bm == 128) launch_bm<ISX_UP, 128>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, act, s);
-    else if (bm == 64) launch_bm<ISX_UP, 64>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, act, s);
-    else launch_bm<ISX_UP, 32>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, act, s);
+    if (split)
+      launch_m<ISX_UP, true>(bm, C, n_in, n_out, cols_in, Wt, Wrow, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, act, s);
+    else
+      launch_m<ISX_UP, false>(bm, C, n_in, n_out, cols_in, Wt, Wrow, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, act, s);
   } else {
-    if (bm == 128) launch_bm<ISX_AA, 128>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, act, s);
-    else if (bm == 64) launch_bm<ISX_AA, 64>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, act, s);
-    else launch_bm<ISX_AA, 32>(C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, act, s);
+    if (split)
+      launch_m<ISX_AA, true>(bm, C, n_in, n_out, cols_in, Wt, Wrow, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, act, s);
+    else
+      launch_m<ISX_AA, false>(bm, C, n_in, n_out, cols_in, Wt, Wrow, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, act, s);
   }
   return hipGetLastError();
 }

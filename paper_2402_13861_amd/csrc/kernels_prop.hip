@@ -468,9 +468,9 @@ NetView<double> net_view<double>(const Model& m) {
 
 
 hipError_t launch_hidden_mfma_f32(int method, int64_t C, int n_in, int n_out, int64_t cols_in, const float* Wt,
-                                  const float* bias, const float* Fin, const float* Ain, const float* Bin,
-                                  const float* Gin, float* Fout, float* Y, float* A, float* B, float* G, float* S,
-                                  hipStream_t s);
+                                  const float* Wrow, const float* bias, const float* Fin, const float* Ain,
+                                  const float* Bin, const float* Gin, float* Fout, float* Y, float* A, float* B,
+                                  float* G, float* S, hipStream_t s);
 hipError_t launch_hidden_mfma_f64(int method, int64_t C, int n_in, int n_out, int64_t cols_in, const double* Wt,
                                   const double* bias, const double* Fin, const double* Ain, const double* Bin,
                                   const double* Gin, double* Fout, double* Y, double* A, double* B, double* G,
@@ -479,19 +479,20 @@ bool mfma_supported(const Model& m);
 
 template <typename T>
 static hipError_t hidden_mfma(int, int64_t, int, int, int64_t, const T*, const T*, const T*, const T*, const T*,
-                              const T*, T*, T*, T*, T*, T*, T*, hipStream_t) {
+                              const T*, const T*, T*, T*, T*, T*, T*, T*, hipStream_t) {
   return hipErrorNotSupported;
 }
 template <>
 hipError_t hidden_mfma<float>(int method, int64_t C, int n_in, int n_out, int64_t cols_in, const float* Wt,
-                              const float* bias, const float* Fin, const float* Ain, const float* Bin,
-                              const float* Gin, float* Fout, float* Y, float* A, float* B, float* G, float* S,
-                              hipStream_t s) {
-  return launch_hidden_mfma_f32(method, C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, s);
+                              const float* Wrow, const float* bias, const float* Fin, const float* Ain,
+                              const float* Bin, const float* Gin, float* Fout, float* Y, float* A, float* B,
+                              float* G, float* S, hipStream_t s) {
+  return launch_hidden_mfma_f32(method, C, n_in, n_out, cols_in, Wt, Wrow, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B,
+                                G, S, s);
 }
 template <>
 hipError_t hidden_mfma<double>(int method, int64_t C, int n_in, int n_out, int64_t cols_in, const double* Wt,
-                               const double* bias, const double* Fin, const double* Ain, const double* Bin,
+                               const double*, const double* bias, const double* Fin, const double* Ain, const double* Bin,
                                const double* Gin, double* Fout, double* Y, double* A, double* B, double* G,
                                double* S, hipStream_t s) {
   return launch_hidden_mfma_f64(method, C, n_in, n_out, cols_in, Wt, bias, Fin, Ain, Bin, Gin, Fout, Y, A, B, G, S, s);
@@ -544,9 +545,11 @@ static hipError_t propagate_impl(const PropArgs& a, PropWork<T>& w, bool use_mfm
       prof = a.prof->begin(rec, kind, flops, bytes, a.stream);
     }
     if (use_mfma) {
-      hipError_t e = hidden_mfma<T>(METHOD | (m.act << 4), C, n_in, n_out, cols_in, wtptr<T>(m.L[h - 1]), bptr<T>(m.L[h - 1]),
-                                    w.F[cur], A[h - 1], B[h - 1], G[h - 1], Fout, Y[h], A[h], B[h], G[h], S[h],
-                                    a.stream);
+      // (bit 8: float32 products as split bfloat16 MFMAs, where asked for)
+      const int word = METHOD | (m.act << 4) | (sizeof(T) == 4 && a.f32_split ? 256 : 0);
+      hipError_t e = hidden_mfma<T>(word, C, n_in, n_out, cols_in, wtptr<T>(m.L[h - 1]), wptr<T>(m.L[h - 1]),
+                                    bptr<T>(m.L[h - 1]), w.F[cur], A[h - 1], B[h - 1], G[h - 1], Fout, Y[h], A[h],
+                                    B[h], G[h], S[h], a.stream);
       if (e != hipSuccess) return e;
     } else {
       constexpr int CT = sizeof(T) == 8 ? 8 : 16;

@@ -217,8 +217,9 @@ def test_every_option_takes_its_default(ctx):
     defaults = [(isx.KEEP_LEVELS, 0), (isx.HIDDEN_KERNEL, 0), (isx.PROFILE, 0), (isx.SCRATCH_BYTES, 16 << 30),
                 (isx.VERBOSE, 0), (isx.BF16_VARIANT, 0), (isx.UP_FORM, 0), (isx.LIN_PRECISION, 1),
                 (isx.AA_MARGIN, 0), (isx.BATCH_WORKERS, 4), (isx.CANCEL_CHECK, 1), (isx.AUTOTUNE, 0),
-                (isx.BF16_READOFF, 0), (isx.RECHECK_CASCADE, 0), (isx.DENSE_FROM_LEVEL, 0)]
-    assert sorted(o for o, _ in defaults) == list(range(1, 16))
+                (isx.BF16_READOFF, 0), (isx.RECHECK_CASCADE, 0), (isx.DENSE_FROM_LEVEL, 0),
+                (isx.RECHECK_SPLIT, 0)]
+    assert sorted(o for o, _ in defaults) == list(range(1, 17))
     for opt, val in defaults:
         ctx.set_option(opt, val)
     ctx.set_option(isx.RECHECK_CASCADE, 1)

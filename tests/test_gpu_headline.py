@@ -203,6 +203,18 @@ def test_band_leaf_sets_equal_fp64_extraction_depth7(ctx):
         lv = mcas.levels()
         rc_cas, rc_cas64 = sum(l["rechecked"] for l in lv), sum(l["rechecked_fp64"] for l in lv)
         mcas.free()
+        # the same with the float32 stage's products as split bf16 MFMAs
+        ctx.set_option(isx.RECHECK_CASCADE, 1)
+        ctx.set_option(isx.RECHECK_SPLIT, 1)
+        try:
+            msp = ctx.extract(mid, isx.UP, isx.BF16, fp64_band=BAND_REL * S, **kw)
+        finally:
+            ctx.set_option(isx.RECHECK_CASCADE, 0)
+            ctx.set_option(isx.RECHECK_SPLIT, 0)
+        idssp, maskssp = msp.leaves()
+        lv = msp.levels()
+        rc_sp, rc_sp64 = sum(l["rechecked"] for l in lv), sum(l["rechecked_fp64"] for l in lv)
+        msp.free()
     finally:
         ctx.unload_mlp(mid)
     common = np.intersect1d(idsbf, ids64).size
@@ -221,3 +233,47 @@ def test_band_leaf_sets_equal_fp64_extraction_depth7(ctx):
     # the float32 decisions outside the inner band are the float64 ones: same sets as the one-stage band
     np.testing.assert_array_equal(idscas, idsbf)
     assert common >= 0.9999 * ids64.size and np.intersect1d(idscas, ids64).size == common
+    # split products in the first stage: the same band cells, and their decisions are the float64 ones too
+    print(f"two-stage re-check, split products: {rc_sp} band cells, {rc_sp64} in float64; leaves {idssp.size}",
+          flush=True)
+    assert rc_sp == rc
+    np.testing.assert_array_equal(idssp, idsbf)
+    np.testing.assert_array_equal(maskssp, maskscas)
+
+
+# the split products' endpoint error must stay well inside the cascade's inner
+# band (1/8 of the 1e-3 S band): allowed 2.5e-5 S, a fifth of it
+SPLIT_TOL = 2.5e-5
+
+
+def test_split_fp32_products_error_per_level(ctx):
+    """Float32 UP with its products as split bfloat16 MFMAs (ISX_HIDDEN_KERNEL
+    3, the cascade's first stage with ISX_RECHECK_SPLIT) on 80 cells per
+    octree level 0..9 of the benchmark INR: endpoint error against the oracle
+    in units of S, per level, below SPLIT_TOL; the float32 MFMA path for
+    comparison."""
+    import paper_2402_13861_amd as isx
+    from workloads.configs import isovalues
+
+    mlp = _net("fourier-inr")
+    _, S = isovalues(INR)
+    rng_levels = np.repeat(np.arange(10), 80)
+    cs, hs = [], []
+    for L in range(10):
+        c, h, _ = random_boxes(80, [L], seed=200 + L)
+        cs.append(c)
+        hs.append(h)
+    c, h = np.concatenate(cs), np.concatenate(hs)
+    print("oracle UP on 800 cells of the 3->256x5->1 INR", flush=True)
+    mu, sg = propagate(mlp, c, h, UP)
+    mid = ctx.load_weights(mlp)
+    try:
+        e_split = _endpoint_err(_gpu_prop(ctx, mid, isx.UP, isx.FP32, c, h, kernel=3)[0], mu, sg, 3.0, S)
+        e_f32 = _endpoint_err(_gpu_prop(ctx, mid, isx.UP, isx.FP32, c, h, kernel=2)[0], mu, sg, 3.0, S)
+    finally:
+        ctx.unload_mlp(mid)
+    for name, e in (("split", e_split), ("fp32", e_f32)):
+        per = ", ".join(f"L{L} {e[rng_levels == L].max():.2e}" for L in range(10))
+        print(f"endpoint error vs oracle [{name}] (units of S): max {e.max():.3e}; {per}", flush=True)
+    assert e_split.max() <= SPLIT_TOL, float(e_split.max())
+    assert e_f32.max() <= SPLIT_TOL
