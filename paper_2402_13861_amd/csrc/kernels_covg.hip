@@ -13,27 +13,34 @@
 // Stored between layers: Chat[i][k] = alpha_k C[i][k] (bfloat16, one factor
 // of D applied along the second index), with the diagonal alpha_i v_i from
 // the variance the rule used, in 32 x 8 blocks (chat_index): the 16 bytes of
-// 8 consecutive k of a row, for 32 consecutive rows, are one 512-byte run.  Then X[i][k] = alpha_i Chat[i][k] + [i = k]
-// gamma_i^2, so that
+// 8 consecutive k of a row, for 32 consecutive rows, are one 512-byte run.
+// Then X[i][k] = alpha_i Chat[i][k] + [i = k] gamma_i^2, so that
 //   T[j][i] = alpha_i (Chat W_h^T)[i][j] + gamma_i^2 W_h[j][i]
 // needs no per-element scaling of an MFMA operand: a workgroup that owns
 // neurons R can store its block of the next Chat (columns R, scaled by its
 // own alpha_R) without the other workgroups' alphas.
+// Layer 2 at widths 256 and 512 runs in rank-3 form: with X_1 = D_1 F F^T
+// D_1 + diag(gamma_1^2), step 1's product is F_i . P_j, P_j = sum_k
+// W_2[j][k] alpha_k F_k, formed on the vector ALUs, and Chat_1 is never
+// stored (at 1024 its extra LDS does not fit and layer 1 writes Chat_1).
 // One launch per layer h >= 2; a workgroup owns RB = 65536 / N neurons j of
 // one cell (N / RB workgroups per cell, 8 blocks apart so that they run on
 // the same XCD and share the cell's Chat through its L2):
 //   1. Out = Chat W_R^T (N x RB) on v_mfma_f32_32x32x16_bf16, rows of Chat
-//      staged through LDS in K chunks (double buffer), weight fragments of
-//      rows R streamed from the L2-resident fragment-order copy of W_h; the
-//      epilogue forms T[j][i] (float32), sums each neuron's variance, its
-//      magnitude and its centre W z over the lane's rows, and keeps T_R in
-//      LDS as bfloat16 (row-major, rows R);
+//      staged through LDS in K chunks (double buffer, each chunk's loads two
+//      chunks ahead), weight fragments of rows R streamed from the
+//      L2-resident fragment-order copy of W_h one chunk ahead; the epilogue
+//      forms T[j][i] (float32), sums each neuron's variance, its magnitude
+//      and its centre W z over the lane's rows (float32 weights from the
+//      accumulator-quad copy), and keeps T_R in LDS as bfloat16 (row-major,
+//      rows R);
 //   2. per neuron j in R: the partial sums in a fixed order, the rule, the
 //      layer's (y, alpha, beta, gamma);
 //   3. C_R = T_R W_h^T (RB x N), A = rows of T_R from LDS, B = weight
-//      fragments; the epilogue stores Chat[m][j] = alpha_j C[j][m] (C is
-//      symmetric), the diagonal alpha_j v_j.  The last hidden layer stops
-//      after step 2.
+//      fragments in a ring four k-steps ahead; the epilogue stores
+//      Chat[m][j] = alpha_j C[j][m] (C is symmetric), the diagonal
+//      alpha_j v_j, one 512-byte run per store instruction.  The last hidden
+//      layer stops after step 2.
 // The cancellation check is the LDS kernel's (a variance sum that keeps at
 // most 2^-9 of its terms' magnitude, where the rule depends on sigma, marks
 // the cell for the host's float64 re-propagation).
