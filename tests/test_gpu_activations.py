@@ -229,3 +229,22 @@ def test_relu_only_paths_report_unsupported(ctx):
     finally:
         ctx.set_option(isx.AA_MARGIN, 0)
         ctx.unload_mlp(mid)
+
+
+@pytest.mark.parametrize("name", ["sine-64x3", "sine-128x4", "elu-64x3"])
+def test_split_fp32_products_against_oracle(ctx, name):
+    """Float32 UP with its products as split bf16 MFMAs (ISX_HIDDEN_KERNEL 3,
+    the re-check cascade's first stage) on sine and ELU nets: bounds within
+    1e-5 of max(|o|, S) and spread within 1e-4 relative, the float32 MFMA
+    path's tolerances (measured: bounds 3.4e-6, spread 2.6e-6 at most)."""
+    import paper_2402_13861_amd as isx
+
+    act, mlp, mid = _load(ctx, name)
+    try:
+        S = _scale(mlp, act)
+        c, h, _ = random_boxes(257, range(0, 10), seed=17)
+        ref = propagate(mlp, c, h, UP, act=act)
+        g, _ = _prop(ctx, mid, isx.UP, isx.FP32, c, h, kernel=3)
+        assert_pair_close(g, ref, S, 1e-5, f"split fp32 {name}", k=3.0, spread_rtol=1e-4)
+    finally:
+        ctx.unload_mlp(mid)

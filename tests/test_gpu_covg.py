@@ -7,7 +7,8 @@ have width 512 or 1024, and with ISX_UP_FORM = 2 also at width 256.  Checked
 here:
 * bounds, spread and centre against the oracle on dyadic cells of octree
   levels 0..9, ReLU, sine (SIREN) and ELU nets of widths 256, 512 and 1024
-  (the largest hidden width), within the BF16 tolerances below;
+  (the largest hidden width), with two and more hidden layers (layer 2 in
+  rank-3 form, and as the last layer), within the BF16 tolerances below;
 * a batch split into many chunks gives the one-chunk result bit for bit;
 * extraction with the float64 re-check band against the float64 extraction.
 """
@@ -36,6 +37,8 @@ NETS = {
     "relu-256x5": ("relu", lambda: he_normal_mlp([3, 256, 256, 256, 256, 256, 1], seed=0), 2),
     "relu-512x3": ("relu", lambda: he_normal_mlp([3, 512, 512, 512, 1], seed=2), 2),
     "relu-1024x2": ("relu", lambda: he_normal_mlp([3, 1024, 1024, 1], seed=5), 0),
+    "relu-512x2": ("relu", lambda: he_normal_mlp([3, 512, 512, 1], seed=8), 0),  # layer 2 rank-3 and last
+    "sine-1024x2": ("sine", lambda: siren_mlp([3, 1024, 1024, 1], seed=9, w0=6.0), 0),
     "sine-512x3": ("sine", lambda: siren_mlp([3, 512, 512, 512, 1], seed=6, w0=6.0), 2),
     "elu-512x3": ("elu", lambda: he_normal_mlp([3, 512, 512, 512, 1], seed=7), 2),
 }
