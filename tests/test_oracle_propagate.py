@@ -5,7 +5,9 @@ closed forms for nets that are affine on the box, the exact range of a tiny
 net by linear programming over its activation patterns, dense sampling
 (soundness of AA), invariances of the function (neuron rescaling and
 permutation), a one-neuron net whose UP output equals the exact Gaussian
-moments of ReLU by quadrature, and Monte Carlo moments on tiny boxes.
+moments of ReLU by quadrature, Monte Carlo moments on tiny boxes, and the
+exact centre of one-hidden-layer nets under UP's Gaussian input model on
+boxes of any size.
 """
 
 import itertools
@@ -18,6 +20,7 @@ from scipy.optimize import linprog
 from oracle.mlp import mlp_forward
 from oracle.propagate import AA, UP, propagate, propagate_hidden, propagate_up_covariance
 from workloads import he_normal_mlp, random_boxes
+from workloads.weights import siren_mlp
 
 
 def _affine_on_domain_net(seed, widths=(3, 8, 8, 1)):
@@ -370,3 +373,44 @@ def test_raua_between_aa_radius_bounds(seed):
     n_sym = 3 + sum(widths[1:-1])
     assert np.all(sigma <= r / np.sqrt(3.0) * (1 + 1e-12))
     assert np.all(sigma >= r / np.sqrt(3.0 * n_sym) * (1 - 1e-12))
+
+
+@pytest.mark.parametrize("act", ["relu", "sine", "elu"])
+def test_up_mean_exact_for_one_hidden_layer_under_gaussian_input(act):
+    # UP models the box as a Gaussian with the uniform variable's mean and
+    # variance (Eq. 6 with the input scale h/sqrt(3)).  With one hidden layer
+    # every pre-activation is then exactly Gaussian, each per-neuron rule
+    # keeps the mean of the activation (App. D), and the output layer is
+    # linear, so UP's centre equals E[f(X)], X ~ N(c, diag(h^2/3)), on boxes
+    # of any size, kinks and sine periods inside included.  Checked against
+    # Monte Carlo at 6 standard errors on the whole domain and half of it.
+    if act == "sine":
+        mlp = siren_mlp([3, 64, 1], seed=4, w0=12.0)
+    else:
+        mlp = he_normal_mlp([3, 64, 1], seed=4)
+    c = np.array([[0.0, 0.0, 0.0], [0.5, -0.5, 0.5], [-0.3, 0.2, 0.1]])
+    h = np.array([[1.0, 1.0, 1.0], [0.5, 0.5, 0.5], [0.25, 0.5, 1.0]])
+    mu, sigma = propagate(mlp, c, h, UP, act=act)
+    rng = np.random.default_rng(31)
+    for i in range(c.shape[0]):
+        x = c[i] + rng.standard_normal((2_000_000, 3)) * (h[i] / np.sqrt(3.0))
+        v = mlp_forward(mlp, x, act=act)
+        se = v.std() / np.sqrt(v.size)
+        assert abs(mu[i] - v.mean()) < 6 * se, (act, i, mu[i], v.mean(), se)
+        # the spread is not exact (cross terms of the linearised neurons), but
+        # stays near the Gaussian-input standard deviation
+        assert 0.5 < sigma[i] / v.std() < 2.0
+
+
+def test_up_mean_misses_monte_carlo_with_two_hidden_layers():
+    # The exactness above rests on the single hidden layer: with two, layer 2
+    # sees a non-Gaussian input, and on the whole domain the centre differs
+    # from the Gaussian-input mean by many standard errors.  This keeps the
+    # test above from passing on a Monte Carlo tolerance that is too loose.
+    mlp = he_normal_mlp([3, 64, 64, 1], seed=4)
+    c = np.zeros((1, 3))
+    h = np.ones((1, 3))
+    mu, _ = propagate(mlp, c, h, UP)
+    x = np.random.default_rng(31).standard_normal((2_000_000, 3)) / np.sqrt(3.0)
+    v = mlp_forward(mlp, x)
+    assert abs(mu[0] - v.mean()) > 20 * v.std() / np.sqrt(v.size)
