@@ -606,7 +606,7 @@ def main(argv=None):
     a = ap.parse_args(argv)
 
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 (the library has no multi-GPU path)"}))
         return 2
     if a.copy_probe_bytes:
         return copy_probe(a.copy_probe_bytes)

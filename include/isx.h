@@ -46,7 +46,7 @@ typedef enum {
   ISX_ECAPACITY = -4,    /* a result exceeds a caller-set capacity (never truncated silently) */
   ISX_EHIP = -5,         /* a HIP runtime call or kernel launch failed */
   ISX_ENAN = -6,         /* NaN or Inf in weights, domain or iso-values */
-  ISX_EUNSUPPORTED = -7  /* valid request that this build does not implement */
+  ISX_EUNSUPPORTED = -7  /* valid request that the library does not implement */
 } isx_status;
 
 /* Range analysis by affine arithmetic ("RA-Full", Sec. III), uncertainty
